@@ -1,0 +1,420 @@
+"""FP64 reference renderer for 2D Gaussian surfels -- TEST INFRASTRUCTURE ONLY.
+
+Plain definition of what the renderer computes, per ray (Sec. III-A):
+
+1. Each surfel is the sensor-frame map M = [s_u R t_u, s_v R t_v, mu_s] of
+   Eq. 1 (W restricted to the rigid pose; intrinsics live in the planes).
+2. A ray is the intersection of two planes h_u, h_v (Eq. 2): pinhole planes
+   (Eq. 3) written in the sensor frame as h_u = (-1, 0, x_n), h_v = (0, -1, y_n)
+   with x_n = (p_x - c_x)/f_x; LiDAR planes (Eq. 5) with the azimuth/elevation
+   roles read so that both planes contain the beam direction:
+   h_u = (sin az, -cos az, 0), h_v = (sin el cos az, sin el sin az, -cos el).
+3. The hit (u, v) solves [h_u, h_v]^T M (u, v, 1)^T = 0, i.e. (u, v, 1) is
+   proportional to a x b with a = h_u^T M, b = h_v^T M.
+4. rho = u^2 + v^2, optionally low-pass filtered as min(rho, rho_lp) (the 2DGS
+   filter against degenerate line projections, Sec. II), with rho_lp the
+   squared distance to the projected centre in units of sigma (pinhole:
+   pixels; LiDAR: chord to the centre direction in azimuth steps).
+5. The candidate set of a ray is every visible surfel whose support contains
+   it: rho_hat <= cutoff^2, hit depth (camera z / LiDAR range) > z_near.
+   Candidates are ordered by the FP32 depth key, ties by surfel index.
+6. Front-to-back alpha compositing (Sec. II, splatting): alpha =
+   min(alpha_max, o exp(-rho_hat/2)); skip if alpha < alpha_min; stop before a
+   surfel that would take T (1 - alpha) below T_min; w = alpha T.
+   Camera outputs: RGB + T_final*bg, depth (sum w z), normal (sum w n, normal
+   turned to face the sensor), alpha (sum w).  LiDAR: range, intensity, alpha.
+
+Floating point is FP64 everywhere except the integer decisions (visibility,
+rectangles, key, normal sign), which follow the FP32 binning spec in
+spec32.py.  Gradients are the autograd derivative of this FP64 program;
+skip/stop decisions carry no gradient.  Two candidate modes: "brute" tests every
+ray against every visible surfel; "culled" tests only surfels whose FP32 pixel
+rectangle holds the ray.  Their equality on small scenes pins the rectangle's
+conservativeness.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import sh as shmod
+from . import spec32
+
+F32 = np.float32
+DT = torch.float64
+
+PRODUCTION = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, cutoff2=2.0 * math.log(255.0),
+                  lowpass=True, lp_inv_sigma2=2.0, tile_w=16, tile_h=16, bg=(0.0, 0.0, 0.0))
+STRICT = dict(PRODUCTION, alpha_min=0.0, T_min=0.0, cutoff2=25.0)
+
+
+def make_opts(base=PRODUCTION, **kw):
+    o = dict(base)
+    o.update(kw)
+    # the FP32 spec reads these as float32 values; the FP64 side uses the same values
+    o["cutoff2"] = float(F32(o["cutoff2"]))
+    o["lp_inv_sigma2"] = float(F32(o["lp_inv_sigma2"]))
+    o["alpha_min"] = float(F32(o["alpha_min"]))
+    o["alpha_max"] = float(F32(o["alpha_max"]))
+    o["T_min"] = float(F32(o["T_min"]))
+    return o
+
+
+# ----------------------------------------------------------------------------
+# FP32 spec side: poses, frames, bins
+# ----------------------------------------------------------------------------
+
+def _group_of(scene) -> np.ndarray:
+    go = np.asarray(scene["group_offsets"], np.int64)
+    n = int(go[-1])
+    g = np.zeros(n, np.int64)
+    for i in range(len(go) - 1):
+        g[go[i]:go[i + 1]] = i
+    return g
+
+
+def spec_frames(scene, sensor):
+    """Per-surfel FP32 frame (concatenated over groups) and per-group composed poses."""
+    go = np.asarray(scene["group_offsets"], np.int64)
+    poses = [spec32.compose_pose(sensor["pose"], gp) for gp in np.asarray(scene["group_poses"], F32)]
+    parts = []
+    for g in range(len(go) - 1):
+        sl = slice(int(go[g]), int(go[g + 1]))
+        parts.append(spec32.splat_frame(poses[g], scene["mean"][:, sl], scene["quat"][:, sl],
+                                        scene["scale"][:, sl]))
+    fr = {}
+    for key in ("mu_s", "tu_s", "tv_s", "n_s"):
+        fr[key] = np.concatenate([p[key] for p in parts], axis=1)
+    fr["M"] = np.concatenate([p["M"] for p in parts], axis=2)
+    fr["valid"] = np.concatenate([p["valid"] for p in parts])
+    return fr, np.stack(poses)
+
+
+def spec_bins(scene, sensor, opts):
+    fr, poses = spec_frames(scene, sensor)
+    if sensor["kind"] == "pinhole":
+        b = spec32.pinhole_bins(fr, sensor, opts)
+    else:
+        b = spec32.lidar_bins(fr, scene["scale"], sensor, opts)
+    b["normal_sign"] = spec32.normal_sign(fr["n_s"], fr["mu_s"])
+    b["poses"] = poses
+    b["frame"] = fr
+    return b
+
+
+# ----------------------------------------------------------------------------
+# FP64 side
+# ----------------------------------------------------------------------------
+
+def _leaf(x, grad):
+    t = torch.as_tensor(np.asarray(x, np.float64), dtype=DT)
+    return t.requires_grad_(grad)
+
+
+def _rays(sensor, ray_ids: np.ndarray):
+    """Per-ray plane coefficients h_u, h_v [R,3], FP64, plus pixel data."""
+    W = int(sensor["width"])
+    i = ray_ids % W
+    j = ray_ids // W
+    if sensor["kind"] == "pinhole":
+        px = i.astype(np.float64) + 0.5
+        py = j.astype(np.float64) + 0.5
+        xn = (px - sensor["cx"]) / sensor["fx"]
+        yn = (py - sensor["cy"]) / sensor["fy"]
+        hu = np.stack([-np.ones_like(xn), np.zeros_like(xn), xn], 1)
+        hv = np.stack([np.zeros_like(yn), -np.ones_like(yn), yn], 1)
+        return dict(hu=torch.as_tensor(hu), hv=torch.as_tensor(hv), px=torch.as_tensor(px),
+                    py=torch.as_tensor(py), i=i, j=j)
+    tabs = spec32.lidar_tables(sensor)
+    ca = tabs["cos_az"][i].astype(np.float64)
+    sa = tabs["sin_az"][i].astype(np.float64)
+    ce = tabs["cos_el"][j].astype(np.float64)
+    se = tabs["sin_el"][j].astype(np.float64)
+    hu = np.stack([sa, -ca, np.zeros_like(sa)], 1)
+    hv = np.stack([se * ca, se * sa, -ce], 1)
+    d = np.stack([ce * ca, ce * sa, se], 1)
+    return dict(hu=torch.as_tensor(hu), hv=torch.as_tensor(hv), d=torch.as_tensor(d), i=i, j=j)
+
+
+def splat_quantities(scene, sensor, bins, params):
+    """Differentiable FP64 per-surfel quantities in the sensor frame.
+
+    params: dict of FP64 torch tensors mean [3,N], quat [4,N], scale [2,N],
+    opacity [N], and rgb [3,N] | sh [nb*3,N] (camera) or intensity [N] (LiDAR).
+    """
+    g = _group_of(scene)
+    P = torch.as_tensor(bins["poses"].astype(np.float64))[torch.as_tensor(g)]  # [N,3,4]
+    Rm = P[:, :, :3]
+    t = P[:, :, 3]
+    mean, quat, scale = params["mean"], params["quat"], params["scale"]
+    w, x, y, z = quat[0], quat[1], quat[2], quat[3]
+    s = 2.0 / (w * w + x * x + y * y + z * z)
+    tu = torch.stack([1 - s * (y * y + z * z), s * (x * y + w * z), s * (x * z - w * y)], 1)  # [N,3]
+    tv = torch.stack([s * (x * y - w * z), 1 - s * (x * x + z * z), s * (y * z + w * x)], 1)
+    nn = torch.stack([s * (x * z + w * y), s * (y * z - w * x), 1 - s * (x * x + y * y)], 1)
+    mu_s = torch.einsum("nij,nj->ni", Rm, mean.T) + t
+    tu_s = torch.einsum("nij,nj->ni", Rm, tu)
+    tv_s = torch.einsum("nij,nj->ni", Rm, tv)
+    n_s = torch.einsum("nij,nj->ni", Rm, nn)
+    M = torch.stack([scale[0][:, None] * tu_s, scale[1][:, None] * tv_s, mu_s], 2)  # [N,3,3] (row, col)
+    out = dict(M=M, mu_s=mu_s, opacity=params["opacity"])
+    sign = torch.as_tensor(bins["normal_sign"].astype(np.float64))
+    out["normal"] = n_s * sign[:, None]
+    if sensor["kind"] == "pinhole":
+        if "sh" in params and params["sh"] is not None:
+            dirs = torch.einsum("nji,nj->ni", Rm, mu_s)  # R^T mu_s: object-frame ray direction
+            dirs = dirs / torch.linalg.norm(dirs, dim=1, keepdim=True)
+            out["colour"] = shmod.sh_colour(params["sh"], dirs.T, int(scene["sh_degree"])).T
+        else:
+            out["colour"] = params["rgb"].T
+    else:
+        out["intensity"] = params["intensity"]
+    return out
+
+
+def _candidate_pairs(bins, sensor, ray_ids, mode):
+    """(ray position, surfel) candidate pairs before the per-pair support test."""
+    W = int(sensor["width"])
+    vis = np.nonzero(bins["visible"])[0]
+    R = ray_ids.size
+    if mode == "brute":
+        rp = np.repeat(np.arange(R), vis.size)
+        sp = np.tile(vis, R)
+        return rp, sp
+    touch = np.nonzero(bins["touch"])[0]
+    full_image = R == int(sensor["width"]) * int(sensor["height"]) and np.array_equal(ray_ids, np.arange(R))
+    lidar = sensor["kind"] != "pinhole"
+    if full_image:
+        i_lo, i_hi = bins["i_lo"][touch], bins["i_hi"][touch]
+        j_lo, j_hi = bins["j_lo"][touch], bins["j_hi"][touch]
+        if lidar:
+            full = bins["full_cols"][touch]
+            ncol = np.where(full, W, np.mod(i_hi - i_lo, W) + 1)
+            i_lo = np.where(full, 0, i_lo)
+        else:
+            ncol = i_hi - i_lo + 1
+        nrow = j_hi - j_lo + 1
+        cnt = ncol * nrow
+        sp = np.repeat(touch, cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        local = np.arange(int(cnt.sum())) - start
+        nc = np.repeat(ncol, cnt)
+        col = (np.repeat(i_lo, cnt) + local % nc) % W
+        row = np.repeat(j_lo, cnt) + local // nc
+        return row * W + col, sp
+    ii = ray_ids % W
+    jj = ray_ids // W
+    rps, sps = [], []
+    il, ih = bins["i_lo"][touch], bins["i_hi"][touch]
+    jl, jh = bins["j_lo"][touch], bins["j_hi"][touch]
+    full = bins["full_cols"][touch] if lidar else None
+    for c0 in range(0, R, 32):
+        ci = ii[c0:c0 + 32, None]
+        cj = jj[c0:c0 + 32, None]
+        inr = (cj >= jl[None]) & (cj <= jh[None])
+        if lidar:
+            wrap = il > ih
+            inc = np.where(wrap[None], (ci >= il[None]) | (ci <= ih[None]), (ci >= il[None]) & (ci <= ih[None]))
+            inc |= full[None]
+        else:
+            inc = (ci >= il[None]) & (ci <= ih[None])
+        r, s = np.nonzero(inr & inc)
+        rps.append(r + c0)
+        sps.append(touch[s])
+    return np.concatenate(rps), np.concatenate(sps)
+
+
+def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None, margins=False,
+           params=None):
+    """Render one sensor in FP64.
+
+    scene: dict of numpy arrays (see gen.scenes layouts; 'sh_degree' if 'sh').
+    rays: None for the whole image, else flat ray ids (row * width + col).
+    grad_out: optional dict channel -> array shaped like the output; then the
+    result also holds 'grads' (d(sum grad_out * out)/d inputs).
+    params: optional dict of FP64 torch tensors to use as inputs (e.g. the
+    output of the decode oracle); gradients then flow into them.
+    Returns dict of numpy FP64 outputs shaped [C, H, W] (or [C, R] for rays).
+    """
+    opts = make_opts(**(opts or {})) if not isinstance(opts, dict) or "tile_w" not in opts else opts
+    W, H = int(sensor["width"]), int(sensor["height"])
+    lidar = sensor["kind"] != "pinhole"
+    full = rays is None
+    ray_ids = np.arange(W * H, dtype=np.int64) if full else np.asarray(rays, np.int64)
+    R = ray_ids.size
+    bins = spec_bins(scene, sensor, opts)
+    want_grad = grad_out is not None
+    if params is None:
+        params = dict(mean=_leaf(scene["mean"], want_grad), quat=_leaf(scene["quat"], want_grad),
+                      scale=_leaf(scene["scale"], want_grad), opacity=_leaf(scene["opacity"], want_grad))
+        if lidar:
+            params["intensity"] = _leaf(scene["intensity"], want_grad)
+        elif scene.get("sh") is not None:
+            params["sh"] = _leaf(scene["sh"], want_grad)
+        else:
+            params["rgb"] = _leaf(scene["rgb"], want_grad)
+    sq = splat_quantities(scene, sensor, bins, params)
+    rays_t = _rays(sensor, ray_ids)
+
+    rp, sp = _candidate_pairs(bins, sensor, ray_ids, mode)
+    if not full and mode == "brute":
+        pass
+    # ----- no-grad pass: support test on every candidate pair
+    with torch.no_grad():
+        sol = _solve(sq, rays_t, rp, sp, sensor, opts, scene)
+        keep = sol["support"].numpy()
+    rp, sp = rp[keep], sp[keep]
+    # ----- order: ray, then FP32 key bits, then surfel index
+    order = np.lexsort((sp, bins["key_bits"][sp], rp))
+    rp, sp = rp[order], sp[order]
+    # ----- differentiable pass on supported pairs only
+    sol = _solve(sq, rays_t, rp, sp, sensor, opts, scene)
+    counts = np.bincount(rp, minlength=R)
+    K = int(counts.max()) if counts.size and counts.max() > 0 else 1
+    seg_start = np.cumsum(counts) - counts
+    pos = np.arange(rp.size) - seg_start[rp]
+    rp_t, pos_t = torch.as_tensor(rp), torch.as_tensor(pos)
+
+    o = sq["opacity"][torch.as_tensor(sp)]
+    a_raw = o * torch.exp(-0.5 * sol["rho_hat"])
+    alpha_p = torch.clamp(a_raw, max=opts["alpha_max"])
+    alpha = torch.zeros((R, K), dtype=DT).index_put((rp_t, pos_t), alpha_p)
+    with torch.no_grad():
+        skip = alpha < opts["alpha_min"]
+        present = torch.zeros((R, K), dtype=torch.bool).index_put((rp_t, pos_t), torch.ones(rp.size, dtype=torch.bool))
+        skip |= ~present
+        a_eff = torch.where(skip, torch.zeros_like(alpha), alpha)
+        one_m = 1.0 - a_eff
+        T_ex = torch.cumprod(torch.cat([torch.ones((R, 1), dtype=DT), one_m[:, :-1]], 1), 1)
+        test = T_ex * one_m
+        stop_ev = (~skip) & (test < opts["T_min"])
+        stopped = torch.cumsum(stop_ev.to(torch.int64), 1) > 0
+        active = (~skip) & (~stopped)
+    a_fin = torch.where(active, alpha, torch.zeros_like(alpha))
+    om = 1.0 - a_fin
+    T = torch.cumprod(torch.cat([torch.ones((R, 1), dtype=DT), om[:, :-1]], 1), 1)
+    w = a_fin * T
+    T_final = T[:, -1] * om[:, -1]
+
+    def acc(feat_p):  # feat_p: [P] per pair -> [R]
+        f = torch.zeros((R, K), dtype=DT).index_put((rp_t, pos_t), feat_p)
+        return (w * f).sum(1)
+
+    outs = {}
+    if lidar:
+        outs["range"] = acc(sol["depth"])
+        outs["intensity"] = acc(sq["intensity"][torch.as_tensor(sp)])
+        outs["alpha"] = w.sum(1)
+    else:
+        col = sq["colour"][torch.as_tensor(sp)]
+        bg = opts["bg"]
+        outs["rgb"] = torch.stack([acc(col[:, c]) + T_final * bg[c] for c in range(3)])
+        outs["depth"] = acc(sol["depth"])
+        nrm = sq["normal"][torch.as_tensor(sp)]
+        outs["normal"] = torch.stack([acc(nrm[:, c]) for c in range(3)])
+        outs["alpha"] = w.sum(1)
+    outs["T_final"] = T_final
+
+    result = {}
+    shape = (H, W) if full else (R,)
+    for k_, v in outs.items():
+        vv = v.detach().numpy()
+        result[k_] = vv.reshape((vv.shape[0],) + shape) if vv.ndim == 2 else vv.reshape(shape)
+    result["n_contrib"] = active.sum(1).numpy().reshape(shape)
+    if margins:
+        result["margin"] = _margins(sol, alpha.detach(), T_ex, skip, stopped, rp, pos, R, opts, sensor).reshape(shape)
+    if want_grad:
+        total = 0.0
+        for k_, g in grad_out.items():
+            gt = torch.as_tensor(np.asarray(g, np.float64)).reshape(outs[k_].shape)
+            total = total + (outs[k_] * gt).sum()
+        leaves = {k_: v for k_, v in params.items() if isinstance(v, torch.Tensor) and v.requires_grad}
+        if isinstance(total, torch.Tensor) and total.requires_grad:
+            gs = torch.autograd.grad(total, list(leaves.values()), allow_unused=True)
+        else:
+            gs = [None] * len(leaves)
+        result["grads"] = {k_: (torch.zeros_like(v) if g is None else g).detach().numpy()
+                           for (k_, v), g in zip(leaves.items(), gs)}
+    result["bins"] = bins
+    return result
+
+
+def _solve(sq, rays_t, rp, sp, sensor, opts, scene):
+    """Per-pair ray-splat solve (Eq. 2): (u, v), rho_hat, hit depth, support mask."""
+    rp_t = torch.as_tensor(rp)
+    sp_t = torch.as_tensor(sp)
+    M = sq["M"][sp_t]  # [P,3,3]
+    hu = rays_t["hu"][rp_t]
+    hv = rays_t["hv"][rp_t]
+    a = torch.einsum("pi,pij->pj", hu, M)
+    b = torch.einsum("pi,pij->pj", hv, M)
+    h = torch.linalg.cross(a, b, dim=1)
+    h2 = h[:, 2]
+    ok = h2 != 0
+    h2s = torch.where(ok, h2, torch.ones_like(h2))
+    u = h[:, 0] / h2s
+    v = h[:, 1] / h2s
+    rho = u * u + v * v
+    uv1 = torch.stack([u, v, torch.ones_like(u)], 1)
+    X = torch.einsum("pij,pj->pi", M, uv1)
+    mu = sq["mu_s"][sp_t]
+    lp = opts["lp_inv_sigma2"]
+    if sensor["kind"] == "pinhole":
+        depth = X[:, 2]
+        if opts["lowpass"]:
+            pcx = sensor["fx"] * mu[:, 0] / mu[:, 2] + sensor["cx"]
+            pcy = sensor["fy"] * mu[:, 1] / mu[:, 2] + sensor["cy"]
+            dx = rays_t["px"][rp_t] - pcx
+            dy = rays_t["py"][rp_t] - pcy
+            rho_lp = lp * (dx * dx + dy * dy)
+    else:
+        d = rays_t["d"][rp_t]
+        depth = (d * X).sum(1)
+        if opts["lowpass"]:
+            step = 2.0 * math.pi / int(sensor["width"])
+            mh = mu / torch.linalg.norm(mu, dim=1, keepdim=True)
+            dd = d - mh
+            rho_lp = lp * (dd * dd).sum(1) / (step * step)
+    if opts["lowpass"]:
+        use_rho = rho <= rho_lp
+        rho_hat = torch.where(use_rho, rho, rho_lp)
+    else:
+        rho_hat = rho
+    support = ok & (rho_hat <= opts["cutoff2"]) & (depth > sensor["z_near"])
+    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support)
+
+
+def _margins(sol, alpha, T_ex, skip, stopped, rp, pos, R, opts, sensor):
+    """Per-ray smallest relative distance of any compositing decision to its threshold.
+
+    Considers the alpha_min skip test, the T_min stop test, the cutoff and the
+    z_near hit test of every pair up to and including the stopping surfel.
+    """
+    rh = sol["rho_hat"].detach().numpy()
+    dep = sol["depth"].detach().numpy()
+    a = alpha.numpy()[rp, pos]
+    Tx = T_ex.numpy()[rp, pos]
+    st = stopped.numpy()[rp, pos]
+    sk = skip.numpy()[rp, pos]
+    prev_stopped = np.zeros_like(st)
+    # a pair is "considered" if no earlier pair stopped the ray
+    first_stop = np.full(R, np.iinfo(np.int64).max)
+    np.minimum.at(first_stop, rp[st], pos[st])
+    considered = pos <= first_stop[rp]
+    del prev_stopped
+    m = np.full(rp.size, np.inf)
+    k = opts["cutoff2"]
+    m = np.minimum(m, np.abs(rh - k) / k)
+    m = np.minimum(m, np.abs(dep - sensor["z_near"]) / max(sensor["z_near"], 1e-12))
+    if opts["alpha_min"] > 0:
+        m = np.minimum(m, np.abs(a - opts["alpha_min"]) / opts["alpha_min"])
+    if opts["T_min"] > 0:
+        tt = Tx * (1.0 - a)
+        mt = np.where(sk, np.inf, np.abs(tt - opts["T_min"]) / opts["T_min"])
+        m = np.minimum(m, mt)
+    m = np.where(considered, m, np.inf)
+    out = np.full(R, np.inf)
+    np.minimum.at(out, rp, m)
+    return out
