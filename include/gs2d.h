@@ -1,0 +1,293 @@
+/*
+ * gs2d.h -- C-ABI of the MI355X 2D-Gaussian-surfel sensor renderer.
+ *
+ * The library renders 2D Gaussian surfels (2DGS) for pinhole cameras and
+ * spinning LiDARs and computes the adjoint of that rendering, following the
+ * unified projection scheme of Sec. III-A of "Industrial-Grade Sensor
+ * Simulation via Gaussian Splatting" (arXiv 2503.11731):
+ *
+ *   - a surfel is the tangent-plane map P(u,v) = W H (u,v,1)^T of Eq. 1,
+ *     H = [s_u t_u, s_v t_v, mu; 0 0 1];
+ *   - a ray is the intersection of two planes h_u, h_v and meets the surfel
+ *     where [h_u, h_v]^T P(u,v) = 0 (Eq. 2);
+ *   - pinhole planes follow Eq. 3, LiDAR planes Eq. 5;
+ *   - the surfels a ray meets are alpha-composited front to back (the
+ *     splatting of Sec. II), with the 2DGS low-pass filter.
+ *
+ * Problem statement (the boundary): render(surfels, sensor models, poses) ->
+ * image or range buffers, and its adjoint.  The neural-Gaussian decode of
+ * Sec. III-A (anchor feature -> MLP -> surfel attributes) is a separate pair
+ * of calls that writes/reads the same surfel layout.
+ *
+ * Conventions shared by every call
+ *   - All array arguments named "device" are HIP device pointers; everything
+ *     else is host memory that the call reads before it returns.
+ *   - Layout is structure-of-arrays, FP32, plane-major: an attribute with C
+ *     components over N surfels is C planes of N floats ([C][N]).
+ *   - Image outputs are planar FP32 [C][H][W] (row y, column x).  For a LiDAR,
+ *     W = azimuth steps (column i has azimuth 2*pi*i/W, counter-clockwise
+ *     about the sensor's +z, x forward, y left) and H = beams (row j is
+ *     elevations[j], ascending).
+ *   - Poses are row-major 3x4 FP32 rigid transforms: sensor poses map world
+ *     to sensor, group poses map a surfel group's own frame to world.
+ *     Camera frame: x right, y down, z forward.
+ *   - The caller owns every buffer (inputs, outputs, workspace, gradients),
+ *     allocated on the plan's device.  Calls enqueue work on the given stream
+ *     and never synchronise it, except gs_query_status.  No call allocates
+ *     device memory after gs_plan_create.
+ *   - Errors: every call returns gs_status; nothing throws or aborts across
+ *     the ABI.  Argument errors are detected on the host before any launch
+ *     (GS_ERR_INVALID_ARG).  Data-dependent overflow of the (tile, surfel)
+ *     pair capacity is detected on the device, recorded in the workspace's
+ *     status words and reported by gs_query_status (GS_ERR_CAPACITY); the
+ *     outputs of such a run are undefined but no memory outside the given
+ *     buffers is touched.  gs_last_error() returns a message for the calling
+ *     thread's last failure.
+ *   - A plan is not re-entrant: calls that share a plan and a workspace must
+ *     be ordered on one stream.
+ */
+#ifndef GS2D_H
+#define GS2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef __HIP_INCLUDE_HIP_HIP_RUNTIME_API_H__
+/* Same declaration as the HIP runtime's, so this header needs no HIP include. */
+typedef struct ihipStream_t* hipStream_t;
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = 1,   /* bad argument, detected before any launch        */
+  GS_ERR_CAPACITY = 2,      /* pair capacity exceeded (device-detected)         */
+  GS_ERR_HIP = 3,           /* a HIP runtime call failed                        */
+  GS_ERR_UNSUPPORTED = 4    /* valid but unsupported combination of options     */
+} gs_status;
+
+enum gs_sensor_kind { GS_SENSOR_PINHOLE = 0, GS_SENSOR_LIDAR = 1 };
+
+/* Maximum number of surfel groups (static scene + posed objects) per scene. */
+#define GS_MAX_GROUPS 64
+/* Maximum number of sensors per plan. */
+#define GS_MAX_SENSORS 16
+
+/* Sensor model (Eq. 3 pinhole, Eq. 5 spinning LiDAR). */
+typedef struct gs_sensor_desc {
+  int32_t kind;              /* gs_sensor_kind                                     */
+  int32_t width, height;     /* pinhole: pixels; LiDAR: azimuth steps x beams        */
+  float fx, fy, cx, cy;      /* pinhole intrinsics; pixel (i,j) centre = (i+.5,j+.5) */
+  const double* elevations;  /* LiDAR: host array of `height` ascending angles (rad) */
+  float z_near;              /* camera: min hit depth; LiDAR: min hit range          */
+  int32_t scene;             /* index of the scene this sensor renders              */
+  int32_t tile_w, tile_h;    /* screen tile; 0 = default (16x16 camera, 32x8 LiDAR) */
+} gs_sensor_desc;
+
+/* Compositing rules (front-to-back alpha blending with the 2DGS low-pass
+ * filter): alpha = min(alpha_max, o * exp(-rho_hat / 2)) with
+ * rho_hat = min(u^2 + v^2, rho_lp) when `lowpass` is set; a ray-surfel pair
+ * contributes iff rho_hat <= cutoff2, the hit depth (range) > z_near and
+ * alpha >= alpha_min; a ray stops before the surfel that would take its
+ * transmittance T (1 - alpha) below T_min.  rho_lp is lp_inv_sigma2 times
+ * the squared distance to the projected centre in pixels (camera) or the
+ * squared chord to the centre direction in azimuth steps (LiDAR). */
+typedef struct gs_render_opts {
+  float alpha_min;       /* e.g. 1/255; 0 disables the skip test          */
+  float alpha_max;       /* e.g. 0.99                                     */
+  float T_min;           /* e.g. 1e-4; 0 disables early stopping          */
+  float cutoff2;         /* squared support radius in sigma, e.g. 2 ln 255 */
+  float lp_inv_sigma2;   /* low-pass 1/sigma^2, e.g. 2 (sigma = sqrt(2)/2)  */
+  int32_t lowpass;       /* 1: apply the low-pass filter                  */
+  float bg[3];           /* camera background colour added as T_final*bg  */
+} gs_render_opts;
+
+/* Static shape of one scene. */
+typedef struct gs_scene_desc {
+  int32_t n_splats;             /* N >= 0                                      */
+  int32_t sh_degree;            /* 0..3: colour from SH; -1: plain RGB         */
+  int32_t has_intensity;        /* 1 if a LiDAR renders this scene             */
+  int32_t n_groups;             /* 1..GS_MAX_GROUPS                            */
+  const int32_t* group_offsets; /* host, n_groups+1 non-decreasing, [0]=0, [G]=N */
+} gs_scene_desc;
+
+/* Per-call surfel data (device pointers, FP32 SoA).  Unused channels may be NULL. */
+typedef struct gs_scene {
+  const float* mean;       /* [3][N] centre mu, in the group's frame              */
+  const float* quat;       /* [4][N] rotation (w,x,y,z), any non-zero norm        */
+  const float* scale;      /* [2][N] s_u, s_v > 0 (metres)                         */
+  const float* opacity;    /* [N] in (0,1]                                         */
+  const float* rgb;        /* [3][N] when sh_degree < 0                            */
+  const float* sh;         /* [(deg+1)^2*3][N], row k*3+channel, when sh_degree>=0 */
+  const float* intensity;  /* [N] when has_intensity                              */
+} gs_scene;
+
+/* Gradient buffers (device pointers), same layouts as gs_scene.  The adjoint
+ * ACCUMULATES into them (+=); the caller zeroes them.  NULL entries skip. */
+typedef struct gs_scene_grads {
+  float* mean;
+  float* quat;
+  float* scale;
+  float* opacity;
+  float* rgb;
+  float* sh;
+  float* intensity;
+} gs_scene_grads;
+
+typedef struct gs_plan_desc {
+  int32_t n_scenes;              /* 1..2 (e.g. camera scene and LiDAR scene)   */
+  const gs_scene_desc* scenes;   /* host array [n_scenes]                      */
+  int32_t n_sensors;             /* 1..GS_MAX_SENSORS                          */
+  const gs_sensor_desc* sensors; /* host array [n_sensors]                     */
+  gs_render_opts opts;
+  int64_t pair_capacity;         /* (tile, surfel) pairs per sensor; 0 = 16*N+4096 */
+  int32_t batched;               /* 1: all sensors share one sort and one
+                                    persistent blend launch (one step)         */
+} gs_plan_desc;
+
+typedef struct gs_plan gs_plan; /* opaque, owned by the library */
+
+/* Output channel counts: camera [8][H][W] = rgb(3), depth, normal(3), alpha;
+ * LiDAR [3][H][W] = range, intensity, alpha.  Depth/range and normal are
+ * unnormalised sums (divide by alpha for the expected value). */
+#define GS_CAMERA_CHANNELS 8
+#define GS_LIDAR_CHANNELS 3
+
+/* Status of the last run on a workspace (filled by gs_query_status). */
+typedef struct gs_run_status {
+  int64_t pairs[GS_MAX_SENSORS];  /* (tile, surfel) pairs emitted per sensor */
+  int32_t overflow;               /* 1 if any sensor exceeded pair_capacity  */
+  int32_t n_visible[GS_MAX_SENSORS];
+  int64_t fp64_pairs;             /* pairs re-solved in FP64 (grazing rays)  */
+} gs_run_status;
+
+/* Library version string and status text. */
+const char* gs_version(void);
+const char* gs_status_string(gs_status s);
+/* Copies the calling thread's last error message into buf (always
+ * NUL-terminated when n > 0) and returns the last status. */
+gs_status gs_last_error(char* buf, size_t n);
+
+/* Creates a plan on the current HIP device: validates the descriptor,
+ * uploads sensor tables and fixes the workspace layout.  Host-only
+ * descriptor memory may be freed after the call.  *out receives the plan. */
+gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out);
+void gs_plan_destroy(gs_plan* plan);
+
+/* Bytes of device workspace a forward+backward pair needs (256-B aligned
+ * base required).  The forward leaves in it the state the backward reads
+ * (per-surfel records, sorted pair lists, tile ranges, final transmittance),
+ * so one workspace must be passed unchanged from a forward to its backward. */
+gs_status gs_plan_workspace_size(const gs_plan* plan, size_t* bytes);
+
+/* Forward render of every sensor of the plan.
+ *   scenes        host array [n_scenes] of device surfel data
+ *   sensor_poses  device [n_sensors][12] world->sensor
+ *   group_poses   device [sum of n_groups over scenes][12] group->world,
+ *                 scene 0's groups first
+ *   outputs       host array [n_sensors] of device output planes (see above)
+ *   workspace     device, gs_plan_workspace_size bytes
+ * Integer work (visibility, tile lists, depth order) follows a fixed FP32
+ * specification; per-ray compositing is FP32 with an FP64 re-solve of
+ * near-degenerate (grazing) ray-surfel intersections. */
+gs_status gs_render_forward(gs_plan* plan, const gs_scene* scenes, const float* sensor_poses,
+                            const float* group_poses, float* const* outputs, void* workspace,
+                            hipStream_t stream);
+
+/* Adjoint of gs_render_forward: given the forward's outputs and dL/d(outputs)
+ * (same layout), accumulates dL/d(surfel attributes) into `grads` (host array
+ * [n_scenes]).  Uses the forward's workspace state; transmittance is
+ * recomputed front to back rather than stored per pixel list. */
+gs_status gs_render_backward(gs_plan* plan, const gs_scene* scenes, const float* sensor_poses,
+                             const float* group_poses, const float* const* outputs,
+                             const float* const* grad_outputs, void* workspace,
+                             const gs_scene_grads* grads, hipStream_t stream);
+
+/* Synchronises `stream`, then reads the workspace's status words. Returns
+ * GS_ERR_CAPACITY when a sensor overflowed its pair capacity. */
+gs_status gs_query_status(const gs_plan* plan, const void* workspace, hipStream_t stream,
+                          gs_run_status* out);
+
+/* Byte offsets of internal arrays inside the workspace, for inspection by
+ * tests: sorted pair surfel indices (uint32 [capacity]), sorted pair tile ids
+ * (uint32 [capacity]), tile ranges (uint32 [n_tiles][2]), per-surfel visible
+ * flag (uint32 [N]) and the device pair counter (uint32). */
+typedef struct gs_workspace_view {
+  size_t pair_surfel, pair_tile, tile_ranges, visible, pair_count;
+  int32_t n_tiles, tile_offset;
+} gs_workspace_view;
+gs_status gs_plan_inspect(const gs_plan* plan, int32_t sensor, gs_workspace_view* out);
+
+/* ---------------------------------------------------------------------
+ * Neural-Gaussian decode (Sec. III-A: attributes inferred from each
+ * anchor's feature by the scene's MLP).  Per anchor a: input
+ * x = [f_a (F, bf16); unit(x_a - sensor centre) in the group frame (3)],
+ * h = ReLU(W1 x + b1) (H wide), y = W2 h + b2 with K offsets x J attributes:
+ *   camera J = 10: opacity, r, g, b, s_u, s_v, q (4)
+ *   LiDAR  J = 8 : opacity, intensity, s_u, s_v, q (4)
+ * Heads: opacity/colour/intensity = sigmoid, scale = l_a * sigmoid,
+ * rotation = raw 4-vector, centre = x_a + l_a * O_k.  Surfel n = a*K + k.
+ * The contractions run on MFMA with bf16 weights and features and FP32
+ * accumulation; activations keep ~16 mantissa bits (hi+lo bf16 split).
+ * ------------------------------------------------------------------- */
+typedef struct gs_anchor_set {
+  int32_t n_anchors;            /* A                                       */
+  int32_t k;                    /* offsets per anchor (K <= 16)            */
+  int32_t lidar;                /* 0: camera heads (J=10), 1: LiDAR (J=8)  */
+  int32_t n_groups;             /* groups, each with its own MLP           */
+  const int32_t* group_offsets; /* host [n_groups+1] over anchors          */
+  const float* xyz;             /* device [3][A]                           */
+  const float* scaling;         /* device [A]                              */
+  const float* offsets;         /* device [3][K][A]                        */
+  const uint16_t* feat;         /* device [A][32] bf16                     */
+  const uint16_t* w1;           /* device [G][32][35] bf16 (out x in)      */
+  const float* b1;              /* device [G][32]                          */
+  const uint16_t* w2;           /* device [G][K*J][32] bf16                */
+  const float* b2;              /* device [G][K*J]                         */
+} gs_anchor_set;
+
+/* Decoded surfel buffers (device, [C][A*K]).  rgb for camera, intensity for
+ * LiDAR. */
+typedef struct gs_decoded {
+  float* mean;
+  float* quat;
+  float* scale;
+  float* opacity;
+  float* rgb;
+  float* intensity;
+} gs_decoded;
+
+/* Decodes every anchor for one sensor pose.  sensor_pose: device [12]
+ * world->sensor; group_poses: device [n_groups][12] group->world.  Writes
+ * A*K surfels; anchors of group g become surfels [K*off[g], K*off[g+1]). */
+gs_status gs_decode_forward(const gs_anchor_set* anchors, const float* sensor_pose,
+                            const float* group_poses, const gs_decoded* out, hipStream_t stream);
+
+/* Adjoint of gs_decode_forward.  grad_in holds dL/d(decoded surfels) (same
+ * layout as `out`, read only); accumulates (+=) into the FP32 gradient
+ * buffers (device, NULL to skip): xyz [3][A], scaling [A], offsets [3][K][A],
+ * feat [A][32], w1 [G][32][35], b1 [G][32], w2 [G][K*J][32], b2 [G][K*J].
+ * scratch: device, gs_decode_scratch_size bytes. */
+typedef struct gs_anchor_grads {
+  float* xyz;
+  float* scaling;
+  float* offsets;
+  float* feat;
+  float* w1;
+  float* b1;
+  float* w2;
+  float* b2;
+} gs_anchor_grads;
+gs_status gs_decode_scratch_size(const gs_anchor_set* anchors, size_t* bytes);
+gs_status gs_decode_backward(const gs_anchor_set* anchors, const float* sensor_pose,
+                             const float* group_poses, const gs_decoded* grad_in,
+                             const gs_anchor_grads* grads, void* scratch, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS2D_H */

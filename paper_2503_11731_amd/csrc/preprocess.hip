@@ -1,0 +1,245 @@
+// a0 + a2: pose composition and per-surfel preprocessing (pinhole and LiDAR).
+//
+// One thread per surfel.  Integer decisions (visibility, tile rectangle,
+// depth key, normal orientation) follow the FP32 binning specification in
+// gs_internal.h.  The blend record is built in FP64 from the FP32 inputs and
+// rounded once, in the form the per-ray solve wants:
+//   camera: h' = e3 + P (dx, dy) with (dx, dy) the pixel offset from the
+//           projected centre, u = h'_0/h'_2, v = h'_1/h'_2, z = mu_z / h'_2
+//   LiDAR : h' = e3 + Q (d - mu_hat), u, v as above, range = |mu| / h'_2
+// (h' is adj(M) d scaled so that its third entry is 1 at the surfel centre).
+#include "gs_internal.h"
+#include "kernels.h"
+
+namespace gs {
+
+__global__ void k_compose_poses(const float* __restrict__ sensor_pose, const float* __restrict__ group_poses,
+                                int pose_base, int n_groups, float* __restrict__ out) {
+#pragma clang fp contract(off)
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_groups) return;
+  const float* a = sensor_pose;
+  const float* b = group_poses + 12 * (pose_base + g);
+  float* o = out + 12 * g;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) o[4 * i + j] = (a[4 * i] * b[j] + a[4 * i + 1] * b[4 + j]) + a[4 * i + 2] * b[8 + j];
+    o[4 * i + 3] = ((a[4 * i] * b[3] + a[4 * i + 1] * b[7]) + a[4 * i + 2] * b[11]) + a[4 * i + 3];
+  }
+}
+
+struct Frame64 {
+  double R[9], t[3];
+  double tus[3], tvs[3], ns[3], mus[3];
+  double M[3][3];
+  double adj[3][3];  // adj[row][col]; columns are r1 x r2, r2 x r0, r0 x r1
+  double det;
+};
+
+__device__ inline void frame64(const float* P, float m0, float m1, float m2, float qw, float qx, float qy, float qz,
+                               float su, float sv, Frame64& F) {
+  for (int i = 0; i < 3; ++i) {
+    F.R[3 * i] = P[4 * i];
+    F.R[3 * i + 1] = P[4 * i + 1];
+    F.R[3 * i + 2] = P[4 * i + 2];
+    F.t[i] = P[4 * i + 3];
+  }
+  double w = qw, x = qx, y = qy, z = qz;
+  double s = 2.0 / (w * w + x * x + y * y + z * z);
+  double a[3] = {1.0 - s * (y * y + z * z), s * (x * y + w * z), s * (x * z - w * y)};
+  double b[3] = {s * (x * y - w * z), 1.0 - s * (x * x + z * z), s * (y * z + w * x)};
+  double c[3] = {s * (x * z + w * y), s * (y * z - w * x), 1.0 - s * (x * x + y * y)};
+  double m[3] = {m0, m1, m2};
+  for (int i = 0; i < 3; ++i) {
+    const double* r = F.R + 3 * i;
+    F.tus[i] = r[0] * a[0] + r[1] * a[1] + r[2] * a[2];
+    F.tvs[i] = r[0] * b[0] + r[1] * b[1] + r[2] * b[2];
+    F.ns[i] = r[0] * c[0] + r[1] * c[1] + r[2] * c[2];
+    F.mus[i] = r[0] * m[0] + r[1] * m[1] + r[2] * m[2] + F.t[i];
+    F.M[i][0] = (double)su * F.tus[i];
+    F.M[i][1] = (double)sv * F.tvs[i];
+    F.M[i][2] = F.mus[i];
+  }
+  const double* r0 = F.M[0];
+  const double* r1 = F.M[1];
+  const double* r2 = F.M[2];
+  double c0[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2], r1[0] * r2[1] - r1[1] * r2[0]};
+  double c1[3] = {r2[1] * r0[2] - r2[2] * r0[1], r2[2] * r0[0] - r2[0] * r0[2], r2[0] * r0[1] - r2[1] * r0[0]};
+  double c2[3] = {r0[1] * r1[2] - r0[2] * r1[1], r0[2] * r1[0] - r0[0] * r1[2], r0[0] * r1[1] - r0[1] * r1[0]};
+  for (int i = 0; i < 3; ++i) {
+    F.adj[i][0] = c0[i];
+    F.adj[i][1] = c1[i];
+    F.adj[i][2] = c2[i];
+  }
+  F.det = r0[0] * c0[0] + r0[1] * c0[1] + r0[2] * c0[2];
+}
+
+__device__ inline void load_surfel(const PrepArgs& a, int i, float* P, float& m0, float& m1, float& m2, float& qw,
+                                   float& qx, float& qy, float& qz, float& su, float& sv) {
+  const int N = a.n;
+  int g = group_of(a.groups, i);
+  const float* pp = a.ws.pose + 12 * g;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) P[k] = pp[k];
+  m0 = a.mean[i];
+  m1 = a.mean[N + i];
+  m2 = a.mean[2 * N + i];
+  qw = a.quat[i];
+  qx = a.quat[N + i];
+  qy = a.quat[2 * N + i];
+  qz = a.quat[3 * N + i];
+  su = a.scale[i];
+  sv = a.scale[N + i];
+}
+
+__global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const int N = a.n;
+  float P[12], m0, m1, m2, qw, qx, qy, qz, su, sv;
+  load_surfel(a, i, P, m0, m1, m2, qw, qx, qy, qz, su, sv);
+  Frame32 f;
+  spec_frame(P, m0, m1, m2, qw, qx, qy, qz, su, sv, f);
+  Bins b;
+  spec_pinhole_bins(f, a.S, a.O, b);
+  a.ws.key[0][i] = b.vis ? __float_as_uint(b.key) : kInvalidKey;
+  a.ws.val[0][i] = (uint32_t)i;
+  a.ws.ntiles[i] = b.n_tiles;
+  a.ws.visible[i] = b.vis ? 1u : 0u;
+  if (!b.touch) return;
+  a.ws.rect[i] = make_int4(b.tx_lo, b.tx_hi, b.ty_lo, b.ty_hi);
+  const float nsign = spec_normal_sign(f);
+
+  Frame64 F;
+  frame64(P, m0, m1, m2, qw, qx, qy, qz, su, sv, F);
+  const double muz = F.mus[2];
+  const double k0 = muz / ((double)a.S.fx * F.det);
+  const double k1 = muz / ((double)a.S.fy * F.det);
+  double Pm[6] = {F.adj[0][0] * k0, F.adj[0][1] * k1, F.adj[1][0] * k0,
+                  F.adj[1][1] * k1, F.adj[2][0] * k0, F.adj[2][1] * k1};
+  const double pcx = (double)a.S.fx * F.mus[0] / muz + (double)a.S.cx;
+  const double pcy = (double)a.S.fy * F.mus[1] / muz + (double)a.S.cy;
+
+  // colour
+  float col[3];
+  if (a.sh_degree >= 0) {
+    // view direction in the group frame: R^T mu_s
+    double dx = F.R[0] * F.mus[0] + F.R[3] * F.mus[1] + F.R[6] * F.mus[2];
+    double dy = F.R[1] * F.mus[0] + F.R[4] * F.mus[1] + F.R[7] * F.mus[2];
+    double dz = F.R[2] * F.mus[0] + F.R[5] * F.mus[1] + F.R[8] * F.mus[2];
+    double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    float Y[16];
+    sh_eval(a.sh_degree, (float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    for (int c = 0; c < 3; ++c) {
+      float acc = 0.5f;
+      for (int k = 0; k < nb; ++k) acc += a.sh[(size_t)(k * 3 + c) * N + i] * Y[k];
+      col[c] = acc > 0.0f ? acc : 0.0f;
+    }
+  } else {
+    col[0] = a.rgb[i];
+    col[1] = a.rgb[N + i];
+    col[2] = a.rgb[2 * N + i];
+  }
+  const float o = a.opacity[i];
+  const float log2o = log2f(o);
+
+  // grazing: can h'_2 = 1 + P20 dx + P21 dy drop below 1/8 inside the rectangle?
+  double mx = fmax(fabs(b.i_lo + 0.5 - pcx), fabs(b.i_hi + 0.5 - pcx));
+  double my = fmax(fabs(b.j_lo + 0.5 - pcy), fabs(b.j_hi + 0.5 - pcy));
+  bool graze = fabs(Pm[4]) * mx + fabs(Pm[5]) * my > 0.875;
+  uint32_t flags = graze ? kFlagGrazing : 0u;
+
+  float4* r = a.ws.rec + 4 * (size_t)i;
+  r[0] = make_float4((float)Pm[0], (float)Pm[1], (float)Pm[2], (float)Pm[3]);
+  r[1] = make_float4((float)Pm[4], (float)Pm[5], (float)muz, log2o);
+  r[2] = make_float4(col[0], col[1], col[2], (float)(nsign * F.ns[0]));
+  r[3] = make_float4((float)(nsign * F.ns[1]), (float)(nsign * F.ns[2]), __uint_as_float(flags), o);
+  double* r64 = a.ws.rec64 + kRec64 * (size_t)i;
+  r64[0] = pcx;
+  r64[1] = pcy;
+  r64[2] = muz;
+  r64[3] = 0.0;
+  if (graze) {
+    double* gz = a.ws.grz + kGrz * (size_t)i;
+    for (int k = 0; k < 6; ++k) gz[k] = Pm[k];
+    gz[6] = muz;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  float P[12], m0, m1, m2, qw, qx, qy, qz, su, sv;
+  load_surfel(a, i, P, m0, m1, m2, qw, qx, qy, qz, su, sv);
+  Frame32 f;
+  spec_frame(P, m0, m1, m2, qw, qx, qy, qz, su, sv, f);
+  Bins b;
+  spec_lidar_bins(f, su, sv, a.S, a.O, b);
+  a.ws.key[0][i] = b.vis ? __float_as_uint(b.key) : kInvalidKey;
+  a.ws.val[0][i] = (uint32_t)i;
+  a.ws.ntiles[i] = b.n_tiles;
+  a.ws.visible[i] = b.vis ? 1u : 0u;
+  if (!b.touch) return;
+  a.ws.rect[i] = make_int4(b.tx_lo, b.tx_hi, b.ty_lo, b.ty_hi | (b.wrap ? (1 << 30) : 0));
+
+  Frame64 F;
+  frame64(P, m0, m1, m2, qw, qx, qy, qz, su, sv, F);
+  const double rn = sqrt(F.mus[0] * F.mus[0] + F.mus[1] * F.mus[1] + F.mus[2] * F.mus[2]);
+  const double kq = rn / F.det;
+  double Q[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Q[3 * r + c] = F.adj[r][c] * kq;
+  const double mh[3] = {F.mus[0] / rn, F.mus[1] / rn, F.mus[2] / rn};
+  const float o = a.opacity[i];
+  const float log2o = log2f(o);
+  const float inten = a.intensity ? a.intensity[i] : 0.0f;
+
+  // grazing: bound the angle between any ray of the rectangle and the centre
+  float el_lo = a.S.el[b.j_lo], el_hi = a.S.el[b.j_hi];
+  double ang_el = fmax(fabs((double)el_lo - b.el_c), fabs((double)el_hi - b.el_c));
+  double ang_az;
+  if (b.full_cols) {
+    ang_az = 3.2;
+  } else {
+    const double two_pi = 6.283185307179586;
+    double step = two_pi / a.S.W;
+    double d1 = fabs(remainder(b.i_lo * step - b.az_c, two_pi));
+    double d2 = fabs(remainder((b.i_hi + 1) * step - b.az_c, two_pi));
+    ang_az = fmax(d1, d2) + step * (double)a.S.tw;
+  }
+  double bound = ang_el + ang_az + 0.01;
+  bool graze = (fabs(Q[6]) + fabs(Q[7]) + fabs(Q[8])) * bound > 0.875;
+  uint32_t flags = graze ? kFlagGrazing : 0u;
+
+  float4* r = a.ws.rec + 4 * (size_t)i;
+  r[0] = make_float4((float)Q[0], (float)Q[1], (float)Q[2], (float)Q[3]);
+  r[1] = make_float4((float)Q[4], (float)Q[5], (float)Q[6], (float)Q[7]);
+  r[2] = make_float4((float)Q[8], (float)rn, log2o, inten);
+  r[3] = make_float4(__uint_as_float(flags), o, 0.0f, 0.0f);
+  double* r64 = a.ws.rec64 + kRec64 * (size_t)i;
+  r64[0] = mh[0];
+  r64[1] = mh[1];
+  r64[2] = mh[2];
+  r64[3] = rn;
+  if (graze) {
+    double* gz = a.ws.grz + kGrz * (size_t)i;
+    for (int k = 0; k < 9; ++k) gz[k] = Q[k];
+    gz[9] = rn;
+  }
+}
+
+void launch_compose_poses(const float* sensor_pose, const float* group_poses, int pose_base, int n_groups, float* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_compose_poses, dim3(1), dim3(64), 0, st, sensor_pose, group_poses, pose_base, n_groups, out);
+}
+
+void launch_prep(const PrepArgs& a, hipStream_t st) {
+  if (a.n == 0) return;
+  dim3 grid((a.n + 255) / 256);
+  if (a.S.kind == GS_SENSOR_PINHOLE)
+    hipLaunchKernelGGL(k_prep_pinhole, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_prep_lidar, grid, dim3(256), 0, st, a);
+}
+
+}  // namespace gs

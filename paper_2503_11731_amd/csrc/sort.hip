@@ -1,0 +1,370 @@
+// a3-a5: tile-count scan, (tile, surfel) pair emission, stable LSD radix sort
+// and per-tile ranges.
+//
+// The depth order within a tile is obtained without sorting 64-bit
+// (tile, depth) keys over all pairs: all pairs of one surfel share its depth
+// key, so the low 32 key bits are sorted once over the N surfels (stable, so
+// ties keep the surfel index order), pairs are then emitted in that order,
+// and a stable sort on the tile id alone (ceil(log2 tiles) bits) yields
+// exactly the order of a stable sort of (tile << 32 | depth) keys.
+//
+// Radix passes use 8-bit digits over 4096-item blocks: per-block digit
+// histograms, one device-wide exclusive scan, then a stable scatter whose
+// in-block ranks come from wavefront ballots (match mask of equal digits)
+// and whose writes are staged through LDS so that each block writes
+// contiguous runs per digit.
+#include "gs_internal.h"
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over NT threads; *total receives the block sum.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    uint32_t x = s_w[k];
+    off += (k < w) ? x : 0u;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+struct RadixArgs {
+  const uint32_t* kin;
+  const uint32_t* vin;
+  uint32_t* kout;
+  uint32_t* vout;
+  const uint32_t* count;
+  uint32_t count_const;
+  uint32_t cap;
+  int shift;
+  uint32_t* hist;
+};
+
+__device__ inline uint32_t radix_n(const RadixArgs& a) {
+  uint32_t n = a.count ? *a.count : a.count_const;
+  return n < a.cap ? n : a.cap;
+}
+
+__global__ __launch_bounds__(256) void k_rs_hist(RadixArgs a) {
+  const uint32_t n = radix_n(a);
+  const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
+  __shared__ uint32_t h[4][256];
+  const int t = threadIdx.x, w = t >> 6;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) h[k][t] = 0;
+    __syncthreads();
+    const uint32_t base = b * kRadixItems;
+#pragma unroll 4
+    for (int r = 0; r < kRadixItems / 256; ++r) {
+      uint32_t idx = base + r * 256 + t;
+      if (idx < n) atomicAdd(&h[w][(a.kin[idx] >> a.shift) & 255u], 1u);
+    }
+    __syncthreads();
+    a.hist[(size_t)t * nb + b] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_rs_scan(RadixArgs a) {
+  const uint32_t n = radix_n(a);
+  const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
+  const uint32_t E = 256u * nb;
+  __shared__ uint32_t s_w[16];
+  const uint32_t per = (E + 1023) / 1024;
+  const uint32_t beg = threadIdx.x * per;
+  const uint32_t end = min(beg + per, E);
+  uint32_t sum = 0;
+  for (uint32_t i = beg; i < end; ++i) sum += a.hist[i];
+  uint32_t tot;
+  uint32_t off = block_excl_scan<1024>(sum, s_w, &tot);
+  for (uint32_t i = beg; i < end; ++i) {
+    uint32_t x = a.hist[i];
+    a.hist[i] = off;
+    off += x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(RadixArgs a) {
+  const uint32_t n = radix_n(a);
+  const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
+  __shared__ uint32_t s_key[kRadixItems];
+  __shared__ uint32_t s_val[kRadixItems];
+  __shared__ uint32_t s_wcnt[4][256];
+  __shared__ uint32_t s_run[256];
+  __shared__ uint32_t s_start[256];
+  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_w[4];
+  const int t = threadIdx.x, w = t >> 6;
+  const uint64_t lt = lanemask_lt();
+  constexpr int R = kRadixItems / 256;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    s_run[t] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_wcnt[k][t] = 0;
+    __syncthreads();
+    const uint32_t base = b * kRadixItems;
+    uint32_t my_key[R], my_val[R], my_rank[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t idx = base + r * 256 + t;
+      const bool valid = idx < n;
+      const uint32_t k = valid ? a.kin[idx] : 0u;
+      const uint32_t v = valid ? a.vin[idx] : 0u;
+      const uint32_t d = (k >> a.shift) & 255u;
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t bb = __ballot(on);
+        m &= on ? bb : ~bb;
+      }
+      const uint32_t rank_w = __popcll(m & lt);
+      if (valid && rank_w == 0) s_wcnt[w][d] = __popcll(m);
+      __syncthreads();
+      uint32_t pre = 0;
+      if (valid) {
+        pre = s_run[d];
+        for (int ww = 0; ww < w; ++ww) pre += s_wcnt[ww][d];
+      }
+      my_key[r] = k;
+      my_val[r] = v;
+      my_rank[r] = valid ? pre + rank_w : 0xFFFFFFFFu;
+      __syncthreads();
+      s_run[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) s_wcnt[k2][t] = 0;
+      __syncthreads();
+    }
+    uint32_t tot;
+    const uint32_t st = block_excl_scan<256>(s_run[t], s_w, &tot);
+    s_start[t] = st;
+    s_gbase[t] = a.hist[(size_t)t * nb + b];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (my_rank[r] != 0xFFFFFFFFu) {
+        const uint32_t d = (my_key[r] >> a.shift) & 255u;
+        const uint32_t pos = s_start[d] + my_rank[r];
+        s_key[pos] = my_key[r];
+        s_val[pos] = my_val[r];
+      }
+    }
+    __syncthreads();
+    const uint32_t cnt = min((uint32_t)kRadixItems, n - base);
+    for (uint32_t i = t; i < cnt; i += 256) {
+      const uint32_t k = s_key[i];
+      const uint32_t d = (k >> a.shift) & 255u;
+      const uint32_t g = s_gbase[d] + (i - s_start[d]);
+      a.kout[g] = k;
+      a.vout[g] = s_val[i];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------- gathered exclusive scan of tile counts ----------------
+
+constexpr int kScanItems = 4096;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ val,
+                                                     const uint32_t* __restrict__ ntiles, int n,
+                                                     uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t s_w[4];
+  const int base = blockIdx.x * kScanItems;
+  uint32_t s = 0;
+  for (int r = 0; r < kScanItems / 256; ++r) {
+    int j = base + r * 256 + threadIdx.x;
+    if (j < n) s += ntiles[val[j]];
+  }
+  uint32_t tot;
+  block_excl_scan<256>(s, s_w, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, int nblk, uint32_t* offs, int n,
+                                                   uint32_t* status, uint32_t cap) {
+  __shared__ uint32_t s_w[16];
+  const int per = (nblk + 1023) / 1024;
+  const int beg = threadIdx.x * per;
+  const int end = min(beg + per, nblk);
+  uint32_t sum = 0;
+  for (int i = beg; i < end; ++i) sum += bsum[i];
+  uint32_t tot;
+  uint32_t off = block_excl_scan<1024>(sum, s_w, &tot);
+  for (int i = beg; i < end; ++i) {
+    uint32_t x = bsum[i];
+    bsum[i] = off;
+    off += x;
+  }
+  if (threadIdx.x == 0) {
+    offs[n] = tot;
+    status[kStPairs] = tot;
+    if (tot > cap) status[kStOverflow] = 1u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ val,
+                                                   const uint32_t* __restrict__ ntiles, int n,
+                                                   const uint32_t* __restrict__ bsum, uint32_t* __restrict__ offs) {
+  __shared__ uint32_t s_w[4];
+  const int base = blockIdx.x * kScanItems;
+  // each thread owns 16 consecutive items so that the scan is in order
+  constexpr int PER = kScanItems / 256;
+  uint32_t v[PER];
+  uint32_t s = 0;
+  const int j0 = base + threadIdx.x * PER;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    int j = j0 + r;
+    v[r] = j < n ? ntiles[val[j]] : 0u;
+    s += v[r];
+  }
+  uint32_t tot;
+  uint32_t off = block_excl_scan<256>(s, s_w, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    int j = j0 + r;
+    if (j < n) offs[j] = off;
+    off += v[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, const uint32_t* __restrict__ ntiles,
+                                              const int4* __restrict__ rect, const uint32_t* __restrict__ offs,
+                                              int n, SensorK S, uint32_t cap, uint32_t* __restrict__ ptile,
+                                              uint32_t* __restrict__ pval) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t s = val[j];
+  const uint32_t cnt = ntiles[s];
+  if (cnt == 0) return;
+  uint32_t o = offs[j];
+  if (o >= cap) return;
+  const int4 r = rect[s];
+  const bool wrap = (r.w >> 30) & 1;
+  const int ty_hi = r.w & 0x3FFFFFFF;
+  const int ncol = wrap ? (S.n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1);
+  for (int ty = r.z; ty <= ty_hi; ++ty) {
+    for (int c = 0; c < ncol; ++c) {
+      int tx = r.x + c;
+      if (tx >= S.n_tx) tx -= S.n_tx;
+      if (o < cap) {
+        ptile[o] = (uint32_t)(S.tile_offset + ty * S.n_tx + tx);
+        pval[o] = s;
+      }
+      ++o;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ ptile, const uint32_t* __restrict__ count,
+                                                uint32_t cap, uint2* __restrict__ ranges) {
+  uint32_t n = *count;
+  n = n < cap ? n : cap;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint32_t t = ptile[i];
+    if (i == 0 || ptile[i - 1] != t) ranges[t].x = i;
+    if (i + 1 == n || ptile[i + 1] != t) ranges[t].y = i + 1;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restrict__ vis, int n, uint32_t* status) {
+  uint32_t c = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) c += vis[i];
+  __shared__ uint32_t s_w[4];
+  uint32_t tot;
+  block_excl_scan<256>(c, s_w, &tot);
+  if (threadIdx.x == 0 && tot) atomicAdd(&status[kStVisible], tot);
+}
+
+inline unsigned grid_for(size_t n, unsigned block, unsigned cap_blocks) {
+  size_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  return (unsigned)(g < cap_blocks ? g : cap_blocks);
+}
+
+}  // namespace
+
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, v, n);
+}
+void launch_fill_f32(float* p, float v, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, v, n);
+}
+
+size_t radix_hist_words(uint32_t cap) { return 256ull * ((cap + kRadixItems - 1) / kRadixItems) + 256; }
+
+int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32_t count_const, uint32_t cap,
+               int bits, uint32_t* hist, hipStream_t st) {
+  int cur = 0;
+  const unsigned nb_max = (cap + kRadixItems - 1) / kRadixItems;
+  const unsigned grid = nb_max < 1 ? 1 : (nb_max < 2048 ? nb_max : 2048);
+  for (int shift = 0; shift < bits; shift += 8) {
+    RadixArgs a{key[cur], val[cur], key[cur ^ 1], val[cur ^ 1], count, count_const, cap, shift, hist};
+    hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(256), 0, st, a);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+size_t scan_bsum_words(int n) { return (size_t)((n + kScanItems - 1) / kScanItems) + 1; }
+
+void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uint32_t* offs, uint32_t* bsum,
+                         uint32_t* status, uint32_t cap, hipStream_t st) {
+  const int nblk = (n + kScanItems - 1) / kScanItems;
+  if (nblk > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(256), 0, st, val, ntiles, n, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, bsum, nblk, offs, n, status, cap);
+  if (nblk > 0) hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(256), 0, st, val, ntiles, n, bsum, offs);
+}
+
+void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
+                 const SensorK& S, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, S, cap, ptile, pval);
+}
+
+void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
+                   hipStream_t st) {
+  launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2ull * n_tiles, st);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, st, ptile, count, cap, ranges);
+}
+
+void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_count_visible, dim3(grid_for(n, 256, 256)), dim3(256), 0, st, visible, n, status);
+}
+
+}  // namespace gs

@@ -1,0 +1,262 @@
+// a9: per-surfel adjoint.  Maps the accumulated gradients of each surfel's
+// blend record back to its parameters (centre, quaternion, scales, opacity,
+// colour or SH coefficients, intensity), in FP64, one thread per surfel.
+//
+// Camera record: P[:,j] = adj(M)[:,j] mu_z / (f_j det M) (j = 0, 1),
+//   pc = (fx mu_x / mu_z, fy mu_y / mu_z), mu_z, o, colour, normal.
+// LiDAR record: Q = |mu| adj(M) / det M, mu_hat = mu / |mu|, |mu|, o, intensity.
+// adj(M) columns are r1 x r2, r2 x r0, r0 x r1 (rows r_i of M), det = r0 . (r1 x r2),
+// M = [s_u R t_u, s_v R t_v, R mu + t], (t_u, t_v, n) the columns of the
+// rotation of q scaled by s = 2/|q|^2.
+#include "gs_internal.h"
+#include "kernels.h"
+
+namespace gs {
+
+namespace {
+
+__device__ inline void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ inline void acc_cross(const double* a, const double* b, double* acc) {
+  double c[3];
+  cross3(a, b, c);
+  acc[0] += c[0];
+  acc[1] += c[1];
+  acc[2] += c[2];
+}
+__device__ inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+__global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
+  const PrepArgs& a = A.p;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  if (a.ws.ntiles[i] == 0) return;
+  const int N = a.n;
+  float gf[kGradFields];
+  bool any = false;
+#pragma unroll
+  for (int f = 0; f < kGradFields; ++f) {
+    gf[f] = a.ws.gacc[(size_t)f * N + i];
+    any = any || gf[f] != 0.0f;
+  }
+  if (!any) return;
+
+  // reload and rebuild the surfel map (same arithmetic as the preprocess)
+  const int g = group_of(a.groups, i);
+  float P[12];
+  for (int k = 0; k < 12; ++k) P[k] = a.ws.pose[12 * g + k];
+  const float m0 = a.mean[i], m1 = a.mean[N + i], m2 = a.mean[2 * N + i];
+  const float qwf = a.quat[i], qxf = a.quat[N + i], qyf = a.quat[2 * N + i], qzf = a.quat[3 * N + i];
+  const float su = a.scale[i], sv = a.scale[N + i];
+  double R[9], t[3];
+  for (int r = 0; r < 3; ++r) {
+    R[3 * r] = P[4 * r];
+    R[3 * r + 1] = P[4 * r + 1];
+    R[3 * r + 2] = P[4 * r + 2];
+    t[r] = P[4 * r + 3];
+  }
+  const double w = qwf, x = qxf, y = qyf, z = qzf;
+  const double n2 = w * w + x * x + y * y + z * z;
+  const double s = 2.0 / n2;
+  const double B[9] = {-(y * y + z * z), x * y - w * z, x * z + w * y,   // rows of Rq - I, over s
+                       x * y + w * z,    -(x * x + z * z), y * z - w * x,
+                       x * z - w * y,    y * z + w * x,  -(x * x + y * y)};
+  double Rq[9];
+  for (int k = 0; k < 9; ++k) Rq[k] = s * B[k] + ((k % 4) == 0 ? 1.0 : 0.0);
+  // columns of Rq: t_u, t_v, n
+  double tu[3] = {Rq[0], Rq[3], Rq[6]}, tv[3] = {Rq[1], Rq[4], Rq[7]}, nn[3] = {Rq[2], Rq[5], Rq[8]};
+  double tus[3], tvs[3], ns[3], mus[3];
+  const double mo[3] = {m0, m1, m2};
+  for (int r = 0; r < 3; ++r) {
+    tus[r] = dot3(R + 3 * r, tu);
+    tvs[r] = dot3(R + 3 * r, tv);
+    ns[r] = dot3(R + 3 * r, nn);
+    mus[r] = dot3(R + 3 * r, mo) + t[r];
+  }
+  double Mr[3][3];
+  for (int r = 0; r < 3; ++r) {
+    Mr[r][0] = (double)su * tus[r];
+    Mr[r][1] = (double)sv * tvs[r];
+    Mr[r][2] = mus[r];
+  }
+  double c0[3], c1[3], c2[3];
+  cross3(Mr[1], Mr[2], c0);
+  cross3(Mr[2], Mr[0], c1);
+  cross3(Mr[0], Mr[1], c2);
+  const double det = dot3(Mr[0], c0);
+
+  double gr0[3] = {0, 0, 0}, gr1[3] = {0, 0, 0}, gr2[3] = {0, 0, 0};  // dL/d rows of M
+  double gmus_extra[3] = {0, 0, 0};                                     // direct mu_s terms
+  double gns[3] = {0, 0, 0};
+  double g_op = 0.0;
+  double gcol[3] = {0, 0, 0};
+  double g_int = 0.0;
+
+  if (a.S.kind == GS_SENSOR_PINHOLE) {
+    const double fx = a.S.fx, fy = a.S.fy;
+    const double muz = mus[2];
+    const double g0[3] = {gf[0], gf[2], gf[4]};  // dL/dP[:,0]
+    const double g1[3] = {gf[1], gf[3], gf[5]};  // dL/dP[:,1]
+    const double S0 = dot3(g0, c0) / fx, S1 = dot3(g1, c1) / fy;
+    const double Ssum = S0 + S1;
+    const double gdet = -Ssum * muz / (det * det);
+    double ga0[3], ga1[3];
+    for (int k = 0; k < 3; ++k) {
+      ga0[k] = g0[k] * muz / (fx * det);
+      ga1[k] = g1[k] * muz / (fy * det);
+    }
+    // adj col0 = r1 x r2 ; adj col1 = r2 x r0
+    acc_cross(Mr[2], ga0, gr1);
+    acc_cross(ga0, Mr[1], gr2);
+    acc_cross(Mr[0], ga1, gr2);
+    acc_cross(ga1, Mr[2], gr0);
+    for (int k = 0; k < 3; ++k) {
+      gr0[k] += gdet * c0[k];
+      gr1[k] += gdet * c1[k];
+      gr2[k] += gdet * c2[k];
+    }
+    // mu_z from P's scale, from the record's mu_z, and pc
+    const double gpcx = gf[6], gpcy = gf[7];
+    gmus_extra[0] += gpcx * fx / muz;
+    gmus_extra[1] += gpcy * fy / muz;
+    gmus_extra[2] += Ssum / det + (double)gf[8] - (gpcx * fx * mus[0] + gpcy * fy * mus[1]) / (muz * muz);
+    g_op = gf[9];
+    gcol[0] = gf[10];
+    gcol[1] = gf[11];
+    gcol[2] = gf[12];
+    // normal: output = sign * n_s
+    Frame32 f32;
+    spec_frame(P, m0, m1, m2, qwf, qxf, qyf, qzf, su, sv, f32);
+    const double sgn = spec_normal_sign(f32);
+    gns[0] = sgn * gf[13];
+    gns[1] = sgn * gf[14];
+    gns[2] = sgn * gf[15];
+  } else {
+    const double rn = sqrt(dot3(mus, mus));
+    const double mh[3] = {mus[0] / rn, mus[1] / rn, mus[2] / rn};
+    const double* adjc[3] = {c0, c1, c2};
+    // Q[r][c] = adj[r][c] rn / det, adj[r][c] = column c, entry r
+    double gsum = 0.0;
+    double gcolv[3][3];
+    for (int c = 0; c < 3; ++c)
+      for (int r = 0; r < 3; ++r) {
+        const double gq = gf[3 * r + c];
+        gcolv[c][r] = gq * rn / det;
+        gsum += gq * adjc[c][r];
+      }
+    const double g_rn = gsum / det + (double)gf[12];
+    const double gdet = -gsum * rn / (det * det);
+    acc_cross(Mr[2], gcolv[0], gr1);
+    acc_cross(gcolv[0], Mr[1], gr2);
+    acc_cross(Mr[0], gcolv[1], gr2);
+    acc_cross(gcolv[1], Mr[2], gr0);
+    acc_cross(Mr[1], gcolv[2], gr0);
+    acc_cross(gcolv[2], Mr[0], gr1);
+    for (int k = 0; k < 3; ++k) {
+      gr0[k] += gdet * c0[k];
+      gr1[k] += gdet * c1[k];
+      gr2[k] += gdet * c2[k];
+    }
+    const double gmh[3] = {gf[9], gf[10], gf[11]};
+    const double pr = dot3(mh, gmh);
+    for (int k = 0; k < 3; ++k) gmus_extra[k] += (gmh[k] - mh[k] * pr) / rn + g_rn * mh[k];
+    g_op = gf[13];
+    g_int = gf[14];
+  }
+
+  // rows of M -> columns: M[r][0] = su tus[r], M[r][1] = sv tvs[r], M[r][2] = mus[r]
+  const double* grow[3] = {gr0, gr1, gr2};
+  double gtus[3], gtvs[3], gmus[3];
+  double gsu = 0.0, gsv = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    gtus[r] = (double)su * grow[r][0];
+    gtvs[r] = (double)sv * grow[r][1];
+    gmus[r] = grow[r][2] + gmus_extra[r];
+    gsu += grow[r][0] * tus[r];
+    gsv += grow[r][1] * tvs[r];
+  }
+  // back to the group frame: x_s = R x  =>  g_x = R^T g_xs
+  double gtu[3], gtv[3], gn[3], gmu[3];
+  for (int c = 0; c < 3; ++c) {
+    gtu[c] = R[c] * gtus[0] + R[3 + c] * gtus[1] + R[6 + c] * gtus[2];
+    gtv[c] = R[c] * gtvs[0] + R[3 + c] * gtvs[1] + R[6 + c] * gtvs[2];
+    gn[c] = R[c] * gns[0] + R[3 + c] * gns[1] + R[6 + c] * gns[2];
+    gmu[c] = R[c] * gmus[0] + R[3 + c] * gmus[1] + R[6 + c] * gmus[2];
+  }
+
+  // colour from SH: view direction v = R^T mu_s (group frame), colour = max(0, sum c Y + 1/2)
+  if (a.S.kind == GS_SENSOR_PINHOLE && a.sh_degree >= 0) {
+    double v[3];
+    for (int c = 0; c < 3; ++c) v[c] = R[c] * mus[0] + R[3 + c] * mus[1] + R[6 + c] * mus[2];
+    const double vn = sqrt(dot3(v, v));
+    const float dxf = (float)(v[0] / vn), dyf = (float)(v[1] / vn), dzf = (float)(v[2] / vn);
+    float Y[16];
+    sh_eval(a.sh_degree, dxf, dyf, dzf, Y);
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    float gY[16];
+    for (int k = 0; k < 16; ++k) gY[k] = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+      if (gcol[c] == 0.0) continue;
+      float raw = 0.5f;
+      for (int k = 0; k < nb; ++k) raw += a.sh[(size_t)(k * 3 + c) * N + i] * Y[k];
+      if (!(raw > 0.0f)) continue;
+      for (int k = 0; k < nb; ++k) {
+        if (A.g_sh) A.g_sh[(size_t)(k * 3 + c) * N + i] += (float)(gcol[c] * Y[k]);
+        gY[k] += (float)gcol[c] * a.sh[(size_t)(k * 3 + c) * N + i];
+      }
+    }
+    float gxf, gyf, gzf;
+    sh_grad(a.sh_degree, dxf, dyf, dzf, gY, gxf, gyf, gzf);
+    const double gd[3] = {gxf, gyf, gzf};
+    const double dd[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+    const double pr = dot3(dd, gd);
+    // v = mu - c_group, so dL/dmu gains the projected direction gradient
+    for (int c = 0; c < 3; ++c) gmu[c] += (gd[c] - dd[c] * pr) / vn;
+  } else if (a.S.kind == GS_SENSOR_PINHOLE) {
+    if (A.g_rgb) {
+      A.g_rgb[i] += (float)gcol[0];
+      A.g_rgb[N + i] += (float)gcol[1];
+      A.g_rgb[2 * N + i] += (float)gcol[2];
+    }
+  } else if (A.g_intensity) {
+    A.g_intensity[i] += (float)g_int;
+  }
+
+  // quaternion: Rq = I + s B(q), s = 2/|q|^2; G = dL/dRq with columns gtu, gtv, gn
+  const double G[9] = {gtu[0], gtv[0], gn[0], gtu[1], gtv[1], gn[1], gtu[2], gtv[2], gn[2]};
+  double GB = 0.0;
+  for (int k = 0; k < 9; ++k) GB += G[k] * B[k];
+  const double gw = s * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+  const double gx = s * (y * G[1] + z * G[2] + y * G[3] - 2 * x * G[4] - w * G[5] + z * G[6] + w * G[7] - 2 * x * G[8]);
+  const double gy = s * (-2 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] - 2 * y * G[8]);
+  const double gz = s * (-2 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2 * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
+  const double ds = -s * s * GB;  // d s / d q_k = -s^2 q_k
+  if (A.g_quat) {
+    A.g_quat[i] += (float)(gw + ds * w);
+    A.g_quat[N + i] += (float)(gx + ds * x);
+    A.g_quat[2 * N + i] += (float)(gy + ds * y);
+    A.g_quat[3 * N + i] += (float)(gz + ds * z);
+  }
+  if (A.g_mean) {
+    A.g_mean[i] += (float)gmu[0];
+    A.g_mean[N + i] += (float)gmu[1];
+    A.g_mean[2 * N + i] += (float)gmu[2];
+  }
+  if (A.g_scale) {
+    A.g_scale[i] += (float)gsu;
+    A.g_scale[N + i] += (float)gsv;
+  }
+  if (A.g_opacity) A.g_opacity[i] += (float)g_op;
+}
+
+}  // namespace
+
+void launch_splat_backward(const SplatBwdArgs& a, hipStream_t st) {
+  if (a.p.n == 0) return;
+  hipLaunchKernelGGL(k_splat_backward, dim3((a.p.n + 255) / 256), dim3(256), 0, st, a);
+}
+
+}  // namespace gs

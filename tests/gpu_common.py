@@ -1,0 +1,96 @@
+"""Shared helpers for GPU parity tests: run the HIP path and the FP64 oracle on one input."""
+import numpy as np
+import torch
+
+import paper_2503_11731_amd as gs
+from oracle import raster, spec32
+
+DEV = torch.device("cuda:0")
+
+TOL = 1e-4           # absolute, colour / alpha / normal / intensity
+TOL_DEPTH = 1e-4     # relative to max(1, |reference|), depth / range
+
+
+def gpu_render(scene, sensors, opts, tiles=None, pair_capacity=0):
+    shapes = [gs.SceneShape(int(scene["mean"].shape[1]), int(scene.get("sh_degree", -1) if scene.get("sh") is not None else -1),
+                            scene.get("intensity") is not None,
+                            tuple(int(x) for x in scene["group_offsets"]))]
+    sens = []
+    for i, s in enumerate(sensors):
+        s = dict(s)
+        if tiles is not None:
+            s["tile"] = tiles[i] if isinstance(tiles, list) else tiles
+        sens.append(s)
+    r = gs.Renderer(shapes, sens, opts=opts, pair_capacity=pair_capacity, device=DEV)
+    st = gs.scene_tensors(scene, DEV)
+    sp = gs.poses_tensor([s["pose"] for s in sensors], DEV)
+    gp = gs.poses_tensor(scene["group_poses"], DEV)
+    outs = r.forward([st], sp, gp)
+    torch.cuda.synchronize()
+    return r, st, sp, gp, outs
+
+
+def oracle_opts(opts, tile):
+    o = raster.make_opts(opts)
+    o["tile_w"], o["tile_h"] = tile
+    return o
+
+
+def camera_errors(got, ref, mask=None):
+    """Max errors per channel group; got [8,H,W] (or [8,R]) numpy, ref oracle dict."""
+    g = got.astype(np.float64)
+    m = np.ones(ref["alpha"].shape, bool) if mask is None else mask
+    e = {}
+    e["rgb"] = np.abs(g[0:3] - ref["rgb"])[:, m].max(initial=0.0)
+    e["normal"] = np.abs(g[4:7] - ref["normal"])[:, m].max(initial=0.0)
+    e["alpha"] = np.abs(g[7] - ref["alpha"])[m].max(initial=0.0)
+    e["depth"] = (np.abs(g[3] - ref["depth"]) / np.maximum(1.0, np.abs(ref["depth"])))[m].max(initial=0.0)
+    return e
+
+
+def camera_bad_pixels(got, ref):
+    """Pixels where any channel is outside tolerance."""
+    g = got.astype(np.float64)
+    bad = (np.abs(g[0:3] - ref["rgb"]) > TOL).any(0)
+    bad |= (np.abs(g[4:7] - ref["normal"]) > TOL).any(0)
+    bad |= np.abs(g[7] - ref["alpha"]) > TOL
+    bad |= np.abs(g[3] - ref["depth"]) > TOL_DEPTH * np.maximum(1.0, np.abs(ref["depth"]))
+    return bad
+
+
+def lidar_errors(got, ref, mask=None):
+    g = got.astype(np.float64)
+    m = np.ones(ref["alpha"].shape, bool) if mask is None else mask
+    e = {}
+    e["range"] = (np.abs(g[0] - ref["range"]) / np.maximum(1.0, np.abs(ref["range"])))[m].max(initial=0.0)
+    e["intensity"] = np.abs(g[1] - ref["intensity"])[m].max(initial=0.0)
+    e["alpha"] = np.abs(g[2] - ref["alpha"])[m].max(initial=0.0)
+    return e
+
+
+def within(errs):
+    return all(v <= (TOL_DEPTH if k in ("depth", "range") else TOL) for k, v in errs.items())
+
+
+def gpu_pairs(r, i=0):
+    v = r.inspect(i)
+    return (v["pair_tile"].cpu().numpy().astype(np.int64), v["pair_surfel"].cpu().numpy().astype(np.int64),
+            v["ranges"].cpu().numpy().astype(np.int64), v["visible"].cpu().numpy().astype(bool), v["pairs"])
+
+
+def check_integer_parity(r, scene, sensor, o, i=0):
+    bins = raster.spec_bins(scene, sensor, o)
+    t_ref, s_ref = spec32.tile_pairs_fast(bins)
+    t_got, s_got, ranges, vis, count = gpu_pairs(r, i)
+    assert count == t_ref.size, (count, t_ref.size)
+    np.testing.assert_array_equal(vis, bins["visible"])
+    np.testing.assert_array_equal(t_got, t_ref)
+    np.testing.assert_array_equal(s_got, s_ref)
+    # ranges: [start, end) of each tile in the sorted list
+    n_tiles = ranges.shape[0]
+    starts = np.searchsorted(t_ref, np.arange(n_tiles), side="left")
+    ends = np.searchsorted(t_ref, np.arange(n_tiles), side="right")
+    nz = ends > starts
+    np.testing.assert_array_equal(ranges[nz, 0], starts[nz])
+    np.testing.assert_array_equal(ranges[nz, 1], ends[nz])
+    return t_ref.size

@@ -1,0 +1,177 @@
+"""GPU (HIP) path vs the FP64 oracle: integer outputs bit-exact, floats within tolerance.
+
+Tolerances: 1e-4 absolute per channel for colour, alpha, normal and
+intensity; depth and range 1e-4 relative to max(1 m, reference).  Strict mode
+(alpha_min = 0, T_min = 0) compares every pixel.  Production mode excludes the
+pixels where the oracle's FP64 margin of some compositing decision to its
+threshold is below 1e-3 relative (a float32 path may legitimately decide
+those the other way), and bounds how many such pixels there are.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+from gen import scenes as S  # noqa: E402
+from oracle import raster  # noqa: E402
+from tests.gpu_common import (camera_bad_pixels, camera_errors, check_integer_parity, gpu_render, lidar_errors, oracle_opts,  # noqa: E402
+                              within)
+from tests.helpers import from_gen  # noqa: E402
+
+import paper_2503_11731_amd as gs  # noqa: E402
+
+MARGIN = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cfg1():
+    sc, sens = S.config1()
+    return from_gen(sc), sens
+
+
+@pytest.mark.parametrize("mode", ["production", "strict"])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_config1_forward_parity(mode, tile):
+    _say(f"config1 forward {mode} tile {tile}")
+    scene, sens = _cfg1()
+    opts = gs.PRODUCTION if mode == "production" else gs.STRICT
+    r, st, sp, gp, outs = gpu_render(scene, sens, opts, tiles=tile)
+    o = oracle_opts(opts, tile)
+    n_pairs = check_integer_parity(r, scene, sens[0], o)
+    ref = raster.render(scene, sens[0], o, margins=True)
+    got = outs[0].cpu().numpy()
+    mask = ref["margin"] >= MARGIN if mode == "production" else None
+    errs = camera_errors(got, ref, mask)
+    excluded = 0 if mask is None else int((~mask).sum())
+    bad = camera_bad_pixels(got, ref)
+    _say(f"  pairs {n_pairs} near-threshold {excluded} out-of-tol {int(bad.sum())} errs {errs}")
+    assert within(errs), errs
+    if mask is not None:
+        # every pixel outside tolerance sits at a compositing threshold
+        assert not (bad & mask).any()
+        assert excluded <= 0.02 * mask.size
+
+
+@pytest.mark.parametrize("mode", ["production", "strict"])
+def test_lidar_forward_parity(mode):
+    _say(f"lidar forward {mode}")
+    L = S.lidar_spinning(n_beams=32, n_az=360, pose=np.concatenate([np.eye(3), np.zeros((3, 1))], 1))
+    sc = S.corridor_surfels(seed=7, n=20000, sh_degree=-1, z_lo=-30, z_hi=30, with_intensity=True)
+    scene = from_gen(sc)
+    # put the sensor in the middle of the corridor, 1.9 m above ground (LiDAR frame: z up)
+    L["pose"] = S.lidar_rig_pose()
+    opts = gs.PRODUCTION if mode == "production" else gs.STRICT
+    tile = (32, 8)
+    r, st, sp, gp, outs = gpu_render(scene, [L], opts, tiles=tile)
+    o = oracle_opts(opts, tile)
+    n_pairs = check_integer_parity(r, scene, L, o)
+    ref = raster.render(scene, L, o, margins=True)
+    got = outs[0].cpu().numpy()
+    mask = ref["margin"] >= MARGIN if mode == "production" else None
+    errs = lidar_errors(got, ref, mask)
+    excluded = 0 if mask is None else int((~mask).sum())
+    _say(f"  pairs {n_pairs} near-threshold {excluded} errs {errs}")
+    assert within(errs), errs
+    if mask is not None:
+        assert excluded <= 0.02 * mask.size
+
+
+def test_forward_is_deterministic_and_order_invariant():
+    _say("determinism / permutation")
+    scene, sens = _cfg1()
+    r, st, sp, gp, outs = gpu_render(scene, sens, gs.PRODUCTION)
+    a = outs[0].clone()
+    outs2 = r.forward([st], sp, gp)
+    torch.cuda.synchronize()
+    assert torch.equal(a, outs2[0])
+    perm = np.random.default_rng(0).permutation(scene["mean"].shape[1])
+    sp_scene = dict(scene)
+    for k in ("mean", "quat", "scale", "rgb"):
+        sp_scene[k] = np.ascontiguousarray(scene[k][:, perm])
+    sp_scene["opacity"] = np.ascontiguousarray(scene["opacity"][perm])
+    _, _, _, _, outs3 = gpu_render(sp_scene, sens, gs.PRODUCTION)
+    # keys are tie-free, so the composited order and every float op are the same
+    assert torch.equal(a, outs3[0])
+
+
+def _grad_check(scene, sensor, opts, tile, keys, channels_seed=0):
+    r, st, sp, gp, outs = gpu_render(scene, [sensor], opts, tiles=tile)
+    rng = np.random.default_rng(channels_seed)
+    go = rng.standard_normal(tuple(outs[0].shape)).astype(np.float32)
+    grads = r.backward([st], sp, gp, outs, [torch.from_numpy(go).to(outs[0].device)])[0]
+    torch.cuda.synchronize()
+    o = oracle_opts(opts, tile)
+    names = (["rgb", "depth", "normal", "alpha"] if sensor["kind"] == "pinhole" else ["range", "intensity", "alpha"])
+    gmap = {}
+    if sensor["kind"] == "pinhole":
+        gmap = {"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]}
+    else:
+        gmap = {"range": go[0], "intensity": go[1], "alpha": go[2]}
+    ref = raster.render(scene, sensor, o, grad_out={k: gmap[k].astype(np.float64) for k in names})
+    res = {}
+    for k in keys:
+        g = grads[k].cpu().numpy().astype(np.float64)
+        gr = ref["grads"][k]
+        scale = np.abs(gr).max()
+        err = np.abs(g - gr).max()
+        res[k] = (err, scale)
+    return res
+
+
+@pytest.mark.parametrize("kind", ["rgb", "sh"])
+def test_camera_backward_parity(kind):
+    _say(f"camera backward {kind}")
+    rng = np.random.default_rng(3)
+    n = 300
+    sc = S.random_cloud(seed=11, n=n, lo=(-1, -1, 3), hi=(1, 1, 6), log_scale=(-2.6, 0.4))
+    scene = from_gen(sc)
+    if kind == "sh":
+        scene.pop("rgb")
+        scene["sh"] = (0.3 * rng.standard_normal((48, n))).astype(np.float32)
+        scene["sh_degree"] = 3
+    cam = S.pinhole(96, 80, 96.0)
+    keys = ["mean", "quat", "scale", "opacity", "rgb" if kind == "rgb" else "sh"]
+    res = _grad_check(scene, cam, gs.PRODUCTION, (16, 16), keys)
+    _say(f"  {res}")
+    for k, (err, scale) in res.items():
+        assert err <= 1e-3 * scale + 1e-6, (k, err, scale)
+
+
+def test_lidar_backward_parity():
+    _say("lidar backward")
+    L = S.lidar_spinning(n_beams=16, n_az=180, pose=np.concatenate([np.eye(3), np.zeros((3, 1))], 1))
+    rng = np.random.default_rng(5)
+    n = 300
+    r_ = rng.uniform(4, 9, n)
+    az = rng.uniform(-np.pi, np.pi, n)
+    el = np.deg2rad(rng.uniform(-25, 15, n))
+    mean = np.stack([r_ * np.cos(el) * np.cos(az), r_ * np.cos(el) * np.sin(az), r_ * np.sin(el)]).astype(np.float32)
+    q = rng.standard_normal((4, n)).astype(np.float32)
+    scene = dict(mean=mean, quat=q, scale=np.exp(rng.normal(-1.6, 0.3, (2, n))).astype(np.float32),
+                 opacity=rng.uniform(0.2, 0.95, n).astype(np.float32), intensity=rng.uniform(0, 1, n).astype(np.float32),
+                 group_offsets=np.array([0, n], np.int32), group_poses=S._identity_poses(1))
+    res = _grad_check(scene, L, gs.PRODUCTION, (32, 8), ["mean", "quat", "scale", "opacity", "intensity"])
+    _say(f"  {res}")
+    for k, (err, scale) in res.items():
+        assert err <= 1e-3 * scale + 1e-6, (k, err, scale)
+
+
+def test_empty_and_offscreen_scenes():
+    _say("empty / offscreen")
+    cam = S.pinhole(40, 30, 40.0)
+    empty = dict(mean=np.zeros((3, 0), np.float32), quat=np.zeros((4, 0), np.float32), scale=np.zeros((2, 0), np.float32),
+                 opacity=np.zeros(0, np.float32), rgb=np.zeros((3, 0), np.float32),
+                 group_offsets=np.array([0, 0], np.int32), group_poses=S._identity_poses(1))
+    r, st, sp, gp, outs = gpu_render(empty, [cam], gs.PRODUCTION)
+    assert float(outs[0].abs().max()) == 0.0
+    behind = S.random_cloud(seed=2, n=500, lo=(-1, -1, -5), hi=(1, 1, -1))
+    r, st, sp, gp, outs = gpu_render(from_gen(behind), [cam], gs.PRODUCTION)
+    assert float(outs[0].abs().max()) == 0.0
+    assert r.status()["pairs"][0] == 0
