@@ -138,14 +138,19 @@ typedef struct gs_scene_grads {
 } gs_scene_grads;
 
 typedef struct gs_plan_desc {
-  int32_t n_scenes;              /* 1..2 (e.g. camera scene and LiDAR scene)   */
+  int32_t n_scenes;              /* 1..GS_MAX_SENSORS (e.g. one decoded scene
+                                    per sensor, or camera + LiDAR scenes)      */
   const gs_scene_desc* scenes;   /* host array [n_scenes]                      */
   int32_t n_sensors;             /* 1..GS_MAX_SENSORS                          */
   const gs_sensor_desc* sensors; /* host array [n_sensors]                     */
   gs_render_opts opts;
   int64_t pair_capacity;         /* (tile, surfel) pairs per sensor; 0 = 16*N+4096 */
-  int32_t batched;               /* 1: all sensors share one sort and one
-                                    persistent blend launch (one step)         */
+  int32_t batched;               /* 1: all sensors of the plan form one step:
+                                    one record space, one depth sort, one pair
+                                    list over a global tile space and one
+                                    persistent compositing launch over a
+                                    heaviest-first (sensor, tile) queue; every
+                                    tile shape must then hold 256 rays         */
 } gs_plan_desc;
 
 typedef struct gs_plan gs_plan; /* opaque, owned by the library */
@@ -162,7 +167,36 @@ typedef struct gs_run_status {
   int32_t overflow;               /* 1 if any sensor exceeded pair_capacity  */
   int32_t n_visible[GS_MAX_SENSORS];
   int64_t fp64_pairs;             /* pairs re-solved in FP64 (grazing rays)  */
+  int64_t evaluated;              /* ray-surfel pairs evaluated by the forward blend */
+  int64_t composited;             /* ray-surfel pairs that contributed             */
 } gs_run_status;
+
+/* Pipeline stages, for per-stage timing. */
+enum gs_stage {
+  GS_STAGE_PREPROCESS = 0, /* pose composition, projection, binning, records */
+  GS_STAGE_DEPTH_SORT,     /* radix sort of surfels by depth key             */
+  GS_STAGE_EMIT,           /* tile-count scan and pair emission              */
+  GS_STAGE_TILE_SORT,      /* stable radix sort of pairs by tile             */
+  GS_STAGE_RANGES,         /* per-tile ranges                                */
+  GS_STAGE_BLEND,          /* forward compositing (one kernel per sensor)    */
+  GS_STAGE_BLEND_BWD,      /* adjoint compositing                            */
+  GS_STAGE_SPLAT_BWD,      /* per-surfel adjoint                             */
+  GS_N_STAGES
+};
+
+typedef struct gs_stage_times {
+  int32_t records;                  /* stage intervals summed              */
+  int32_t launches[GS_N_STAGES];    /* intervals per stage                 */
+  double ms[GS_N_STAGES];           /* summed elapsed milliseconds         */
+} gs_stage_times;
+
+/* Enables (max_records > 0) or disables (0) HIP-event timing of every stage
+ * of subsequent forward/backward calls, keeping up to max_records stage
+ * intervals.  Creates the events now; the render calls then only record. */
+gs_status gs_plan_set_timing(gs_plan* plan, int32_t max_records);
+/* Synchronises `stream` and sums the recorded intervals per stage; clears
+ * them when `reset` is non-zero. */
+gs_status gs_plan_stage_times(gs_plan* plan, hipStream_t stream, int32_t reset, gs_stage_times* out);
 
 /* Library version string and status text. */
 const char* gs_version(void);
@@ -206,6 +240,15 @@ gs_status gs_render_backward(gs_plan* plan, const gs_scene* scenes, const float*
                              const float* const* grad_outputs, void* workspace,
                              const gs_scene_grads* grads, hipStream_t stream);
 
+/* Captures the forward of this plan with these exact arguments into a HIP
+ * graph on `stream` (which must not be the legacy default stream).  Later
+ * gs_render_forward calls with identical pointers and stream replay the
+ * graph (one graph launch per step); other calls run uncaptured.  Stage
+ * timing is not recorded inside the graph. */
+gs_status gs_plan_capture(gs_plan* plan, const gs_scene* scenes, const float* sensor_poses,
+                          const float* group_poses, float* const* outputs, void* workspace,
+                          hipStream_t stream);
+
 /* Synchronises `stream`, then reads the workspace's status words. Returns
  * GS_ERR_CAPACITY when a sensor overflowed its pair capacity. */
 gs_status gs_query_status(const gs_plan* plan, const void* workspace, hipStream_t stream,
@@ -247,7 +290,13 @@ typedef struct gs_anchor_set {
   const float* b1;              /* device [G][32]                          */
   const uint16_t* w2;           /* device [G][K*J][32] bf16                */
   const float* b2;              /* device [G][K*J]                         */
+  int32_t flags;                /* GS_DECODE_* bits                        */
 } gs_anchor_set;
+
+/* Decode the MLP with plain FP32 vector arithmetic (one thread per anchor,
+ * FP32 hidden activations) instead of bf16 MFMA: the reference "plain"
+ * decode the MFMA path is compared against. */
+#define GS_DECODE_VALU_FP32 1
 
 /* Decoded surfel buffers (device, [C][A*K]).  rgb for camera, intensity for
  * LiDAR. */

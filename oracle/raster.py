@@ -174,8 +174,38 @@ def splat_quantities(scene, sensor, bins, params):
     return out
 
 
-def _candidate_pairs(bins, sensor, ray_ids, mode):
+def grid_rays(sensor, stride: int) -> np.ndarray:
+    """Flat ray ids of every stride-th column of every stride-th row (a regular sample)."""
+    W, H = int(sensor["width"]), int(sensor["height"])
+    j, i = np.meshgrid(np.arange(0, H, stride), np.arange(0, W, stride), indexing="ij")
+    return (j * W + i).reshape(-1).astype(np.int64)
+
+
+def _grid_pairs(bins, sensor, stride):
+    """Candidate pairs for the grid_rays(sensor, stride) sample (pinhole rectangles)."""
+    W, H = int(sensor["width"]), int(sensor["height"])
+    nW = (W + stride - 1) // stride
+    touch = np.nonzero(bins["touch"])[0]
+    c_lo = -(-bins["i_lo"][touch] // stride)
+    c_hi = bins["i_hi"][touch] // stride
+    r_lo = -(-bins["j_lo"][touch] // stride)
+    r_hi = bins["j_hi"][touch] // stride
+    ncol = np.maximum(c_hi - c_lo + 1, 0)
+    nrow = np.maximum(r_hi - r_lo + 1, 0)
+    cnt = ncol * nrow
+    sp = np.repeat(touch, cnt)
+    start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    local = np.arange(int(cnt.sum())) - start
+    nc = np.repeat(np.maximum(ncol, 1), cnt)
+    col = np.repeat(c_lo, cnt) + local % nc
+    row = np.repeat(r_lo, cnt) + local // nc
+    return row * nW + col, sp
+
+
+def _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride=None):
     """(ray position, surfel) candidate pairs before the per-pair support test."""
+    if grid_stride is not None and mode != "brute" and sensor["kind"] == "pinhole":
+        return _grid_pairs(bins, sensor, grid_stride)
     W = int(sensor["width"])
     vis = np.nonzero(bins["visible"])[0]
     R = ray_ids.size
@@ -231,7 +261,8 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     """Render one sensor in FP64.
 
     scene: dict of numpy arrays (see gen.scenes layouts; 'sh_degree' if 'sh').
-    rays: None for the whole image, else flat ray ids (row * width + col).
+    rays: None for the whole image, flat ray ids (row * width + col), or
+    ("grid", stride) for the regular sample grid_rays(sensor, stride).
     grad_out: optional dict channel -> array shaped like the output; then the
     result also holds 'grads' (d(sum grad_out * out)/d inputs).
     params: optional dict of FP64 torch tensors to use as inputs (e.g. the
@@ -242,6 +273,10 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     W, H = int(sensor["width"]), int(sensor["height"])
     lidar = sensor["kind"] != "pinhole"
     full = rays is None
+    grid_stride = None
+    if isinstance(rays, tuple) and rays[0] == "grid":
+        grid_stride = int(rays[1])
+        rays = grid_rays(sensor, grid_stride)
     ray_ids = np.arange(W * H, dtype=np.int64) if full else np.asarray(rays, np.int64)
     R = ray_ids.size
     bins = spec_bins(scene, sensor, opts)
@@ -258,7 +293,7 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     sq = splat_quantities(scene, sensor, bins, params)
     rays_t = _rays(sensor, ray_ids)
 
-    rp, sp = _candidate_pairs(bins, sensor, ray_ids, mode)
+    rp, sp = _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride)
     if not full and mode == "brute":
         pass
     # ----- no-grad pass: support test on every candidate pair

@@ -125,7 +125,8 @@ def pinhole_bins(fr: dict, sensor: dict, opts: dict):
     centred pixels): with d = T3 D T3^T, f_i = T_i D T3^T, g_i = T_i D T_i^T,
     centre_i = f_i / d and half-extent_i = sqrt(f_i^2 - d g_i) / (-d).
     A surfel is visible iff mu_z >= z_near and d < 0 (its disc of radius
-    sqrt(k) lies wholly in front of the camera).
+    sqrt(k) lies wholly in front of the camera) and every bound is finite
+    (tested explicitly, so that no min/max ever sees a NaN).
     """
     M = _f(fr["M"])
     mu = _f(fr["mu_s"])
@@ -149,30 +150,32 @@ def pinhole_bins(fr: dict, sensor: dict, opts: dict):
         xc = f1 / d
         yc = f2 / d
         nd = -d
-        hx = np.sqrt(np.maximum(f1 * f1 - d * g1, F32(0.0))) / nd
-        hy = np.sqrt(np.maximum(f2 * f2 - d * g2, F32(0.0))) / nd
+        disc_x = f1 * f1 - d * g1
+        disc_y = f2 * f2 - d * g2
+        ok = np.isfinite(disc_x) & np.isfinite(disc_y)
+        hx = np.sqrt(np.maximum(np.where(ok, disc_x, F32(0.0)), F32(0.0))) / nd
+        hy = np.sqrt(np.maximum(np.where(ok, disc_y, F32(0.0)), F32(0.0))) / nd
         xlo, xhi = xc - hx, xc + hx
         ylo, yhi = yc - hy, yc + hy
+        ok &= np.isfinite(xlo) & np.isfinite(xhi) & np.isfinite(ylo) & np.isfinite(yhi)
         if use_lp:
             rl = np.sqrt(k / lp)
             pcx = (fx * mu[0]) / mu[2]
             pcy = (fy * mu[1]) / mu[2]
-            xlo = np.minimum(xlo, pcx - rl)
-            xhi = np.maximum(xhi, pcx + rl)
-            ylo = np.minimum(ylo, pcy - rl)
-            yhi = np.maximum(yhi, pcy + rl)
+            ok &= np.isfinite(pcx - rl) & np.isfinite(pcx + rl) & np.isfinite(pcy - rl) & np.isfinite(pcy + rl)
+            # both operands are finite wherever ok holds
+            xlo = np.where(ok, np.minimum(xlo, pcx - rl), F32(0.0))
+            xhi = np.where(ok, np.maximum(xhi, pcx + rl), F32(0.0))
+            ylo = np.where(ok, np.minimum(ylo, pcy - rl), F32(0.0))
+            yhi = np.where(ok, np.maximum(yhi, pcy + rl), F32(0.0))
         one = F32(1.0)
         half = F32(0.5)
         X_lo = ((xlo - one) + cx) - half
         X_hi = ((xhi + one) + cx) - half
         Y_lo = ((ylo - one) + cy) - half
         Y_hi = ((yhi + one) + cy) - half
-    vis = fr["valid"] & (mu[2] >= z_near) & (d < 0)
-    vis &= (X_lo <= X_hi) & (Y_lo <= Y_hi)  # false for NaN
-    X_lo = np.where(vis, X_lo, 0).astype(F32)
-    X_hi = np.where(vis, X_hi, 0).astype(F32)
-    Y_lo = np.where(vis, Y_lo, 0).astype(F32)
-    Y_hi = np.where(vis, Y_hi, 0).astype(F32)
+        ok &= np.isfinite(X_lo) & np.isfinite(X_hi) & np.isfinite(Y_lo) & np.isfinite(Y_hi)
+    vis = fr["valid"] & (mu[2] >= z_near) & (d < 0) & ok
     # clamp in float before converting (both bounds are finite after this)
     X_lo = np.minimum(np.maximum(X_lo, F32(-2.0)), F32(W + 2))
     X_hi = np.minimum(np.maximum(X_hi, F32(-2.0)), F32(W + 2))
@@ -229,9 +232,11 @@ def lidar_tables(sensor: dict):
     """
     n_az = int(sensor["width"])
     el = np.asarray(sensor["elevations"], np.float64)
-    az = (2.0 * math.pi) * np.arange(n_az, dtype=np.float64) / n_az
-    return dict(cos_az=np.cos(az).astype(F32), sin_az=np.sin(az).astype(F32),
-                cos_el=np.cos(el).astype(F32), sin_el=np.sin(el).astype(F32),
+    az = [((2.0 * math.pi) * float(i)) / n_az for i in range(n_az)]
+    # libm (math) rather than numpy's vectorised kernels: correctly rounded FP64
+    cosf = lambda v: np.array([math.cos(t) for t in v], np.float64).astype(F32)
+    sinf = lambda v: np.array([math.sin(t) for t in v], np.float64).astype(F32)
+    return dict(cos_az=cosf(az), sin_az=sinf(az), cos_el=cosf(el), sin_el=sinf(el),
                 el=el.astype(F32), inv_step=F32(n_az / (2.0 * math.pi)),
                 step=F32(2.0 * math.pi / n_az))
 
@@ -270,6 +275,7 @@ def lidar_bins(fr: dict, scale, sensor: dict, opts: dict):
             Reff = R + r * c_lp
         else:
             Reff = R
+        vis &= np.isfinite(r2) & np.isfinite(Reff)
         el_c = atan2_spec(mu[2], rxy)
         az_c = atan2_spec(mu[1], mu[0])
         sb = np.minimum(Reff / r, F32(1.0))

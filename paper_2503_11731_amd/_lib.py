@@ -54,7 +54,14 @@ class PlanDesc(ctypes.Structure):
 
 class RunStatus(ctypes.Structure):
     _fields_ = [("pairs", c_int64 * GS_MAX_SENSORS), ("overflow", c_int32), ("n_visible", c_int32 * GS_MAX_SENSORS),
-                ("fp64_pairs", c_int64)]
+                ("fp64_pairs", c_int64), ("evaluated", c_int64), ("composited", c_int64)]
+
+
+STAGES = ("preprocess", "depth_sort", "emit", "tile_sort", "ranges", "blend", "blend_bwd", "splat_bwd")
+
+
+class StageTimes(ctypes.Structure):
+    _fields_ = [("records", c_int32), ("launches", c_int32 * len(STAGES)), ("ms", c_double * len(STAGES))]
 
 
 class WorkspaceView(ctypes.Structure):
@@ -65,7 +72,11 @@ class WorkspaceView(ctypes.Structure):
 class AnchorSet(ctypes.Structure):
     _fields_ = [("n_anchors", c_int32), ("k", c_int32), ("lidar", c_int32), ("n_groups", c_int32),
                 ("group_offsets", POINTER(c_int32)), ("xyz", c_void_p), ("scaling", c_void_p), ("offsets", c_void_p),
-                ("feat", c_void_p), ("w1", c_void_p), ("b1", c_void_p), ("w2", c_void_p), ("b2", c_void_p)]
+                ("feat", c_void_p), ("w1", c_void_p), ("b1", c_void_p), ("w2", c_void_p), ("b2", c_void_p),
+                ("flags", c_int32)]
+
+
+GS_DECODE_VALU_FP32 = 1
 
 
 class Decoded(ctypes.Structure):
@@ -90,8 +101,12 @@ SIGNATURES = [
                                     c_void_p]),
     ("gs_render_backward", c_int32, [c_void_p, POINTER(Scene), c_void_p, c_void_p, POINTER(c_void_p),
                                      POINTER(c_void_p), c_void_p, POINTER(SceneGrads), c_void_p]),
+    ("gs_plan_capture", c_int32, [c_void_p, POINTER(Scene), c_void_p, c_void_p, POINTER(c_void_p), c_void_p,
+                                  c_void_p]),
     ("gs_query_status", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(RunStatus)]),
     ("gs_plan_inspect", c_int32, [c_void_p, c_int32, POINTER(WorkspaceView)]),
+    ("gs_plan_set_timing", c_int32, [c_void_p, c_int32]),
+    ("gs_plan_stage_times", c_int32, [c_void_p, c_void_p, c_int32, POINTER(StageTimes)]),
     ("gs_decode_forward", c_int32, [POINTER(AnchorSet), c_void_p, c_void_p, POINTER(Decoded), c_void_p]),
     ("gs_decode_scratch_size", c_int32, [POINTER(AnchorSet), POINTER(c_size_t)]),
     ("gs_decode_backward", c_int32, [POINTER(AnchorSet), c_void_p, c_void_p, POINTER(Decoded),

@@ -1,5 +1,16 @@
 // C-ABI of the gs2d library: plan creation, workspace layout and the
-// forward / adjoint render orchestration (see include/gs2d.h).
+// forward / adjoint render orchestration (declarations in include/gs2d.h).
+//
+// Two execution layouts:
+//  - per sensor: each sensor runs its own preprocess -> depth sort -> pair
+//    emission -> tile sort -> ranges -> compositing chain in its own
+//    workspace region;
+//  - batched (one simulation step): every sensor's surfel records live in one
+//    record space (record id = sensor's record base + surfel index), one depth
+//    sort orders all of them, one emission and one stable tile sort build the
+//    pair list over a global tile-id space (sensor tile offset + tile), and
+//    one persistent compositing launch drains a heaviest-first work queue of
+//    (sensor, tile) items.  A whole step can be captured into one HIP graph.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -9,11 +20,11 @@
 #include "gs_internal.h"
 #include "kernels.h"
 
-namespace gs {
-bool tile_shape_supported(int tw, int th);
-}
-
 using namespace gs;
+
+namespace gs {
+int persistent_blocks_per_cu(bool backward);
+}
 
 namespace {
 
@@ -31,9 +42,9 @@ gs_status ok() {
   return GS_OK;
 }
 
-#define GS_HIP_TRY(expr)                                                                      \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
+#define GS_HIP_TRY(expr)                                                                                \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
     if (e_ != hipSuccess) return fail(GS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
@@ -46,26 +57,67 @@ struct Layout {
   }
 };
 
+// Offsets of the per-surfel and pair arrays of one record space.
+struct RecordArrays {
+  size_t o_rec = 0, o_rec64 = 0, o_grz = 0, o_rect = 0, o_ntiles = 0, o_visible = 0, o_key0 = 0, o_key1 = 0,
+         o_val0 = 0, o_val1 = 0, o_offs = 0, o_bsum = 0, o_hist = 0, o_ptile0 = 0, o_ptile1 = 0, o_pval0 = 0,
+         o_pval1 = 0, o_ranges = 0, o_status = 0, o_gacc = 0;
+  uint32_t n_rec = 0, cap = 0;
+  int n_tiles = 0, tile_bits = 0;
+  int pair_buf = 0;  // buffer holding the sorted pairs
+
+  void layout(Layout& L, uint32_t n, uint32_t cap_, int tiles) {
+    n_rec = n;
+    cap = cap_;
+    n_tiles = tiles;
+    tile_bits = 0;
+    while ((1 << tile_bits) < tiles) ++tile_bits;
+    pair_buf = ((tile_bits + 7) / 8) % 2;
+    const size_t N = n;
+    o_status = L.take(16 * 4);
+    o_rec = L.take(N * 64);
+    o_rec64 = L.take(N * 8 * kRec64);
+    o_grz = L.take(N * 8 * kGrz);
+    o_rect = L.take(N * 16);
+    o_ntiles = L.take(N * 4);
+    o_visible = L.take(N * 4);
+    o_key0 = L.take(N * 4);
+    o_key1 = L.take(N * 4);
+    o_val0 = L.take(N * 4);
+    o_val1 = L.take(N * 4);
+    o_offs = L.take((N + 1) * 4);
+    o_bsum = L.take(scan_bsum_words((int)N) * 4);
+    size_t hw = radix_hist_words(cap);
+    const size_t hw2 = radix_hist_words(n);
+    const size_t hw3 = radix_hist_words((uint32_t)tiles);
+    hw = hw > hw2 ? hw : hw2;
+    hw = hw > hw3 ? hw : hw3;
+    o_hist = L.take(hw * 4);
+    o_ptile0 = L.take((size_t)cap * 4);
+    o_ptile1 = L.take((size_t)cap * 4);
+    o_pval0 = L.take((size_t)cap * 4);
+    o_pval1 = L.take((size_t)cap * 4);
+    o_ranges = L.take((size_t)tiles * 8);
+    o_gacc = L.take(N * 4 * kGradFields);
+  }
+};
+
 struct SensorPlan {
   gs_sensor_desc desc;
   SensorK K;
-  int scene;
-  uint32_t cap;
-  int n_tiles;
-  int tile_bits;
-  size_t base;  // workspace byte offset of this sensor's region
-  // region offsets (relative to base)
-  size_t o_pose, o_rec, o_rec64, o_grz, o_rect, o_ntiles, o_key0, o_key1, o_val0, o_val1, o_offs, o_bsum, o_hist,
-      o_ptile0, o_ptile1, o_pval0, o_pval1, o_ranges, o_Tfinal, o_nlast, o_status, o_gacc, o_visible;
-  int pair_buf;  // buffer holding the sorted pairs
-  // device tables (LiDAR)
-  float* d_tabs = nullptr;
+  int scene = 0;
+  int n_tiles = 0;
+  size_t base = 0;  // workspace byte offset of this sensor's region
+  size_t o_pose = 0, o_Tfinal = 0, o_nlast = 0, o_status = 0;
+  RecordArrays R;          // per-sensor layout only
+  uint32_t rec_base = 0;   // batched layout: first record id
+  float* d_tabs = nullptr; // LiDAR tables (device, owned by the plan)
 };
 
 struct ScenePlan {
   gs_scene_desc desc;
   std::vector<int32_t> offsets;
-  int pose_base;
+  int pose_base = 0;
 };
 
 }  // namespace
@@ -78,6 +130,30 @@ struct gs_plan {
   gs_render_opts opts;
   int batched = 0;
   size_t ws_bytes = 0;
+  // batched record space
+  size_t gbase = 0;
+  RecordArrays G;
+  size_t o_qkey0 = 0, o_qkey1 = 0, o_qval0 = 0, o_qval1 = 0, o_tiles = 0, o_counter = 0;
+  int queue_buf = 0;
+  int persistent_grid = 0;
+  int tile_off[GS_MAX_SENSORS + 1] = {0};
+  // stage timing
+  struct Interval {
+    int stage;
+    hipEvent_t e0, e1;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Interval> intervals;
+  size_t next_event = 0;
+  bool capturing = false;
+  // captured forward
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<gs_scene> g_scenes;
+  std::vector<float*> g_outputs;
+  const float* g_sensor_poses = nullptr;
+  const float* g_group_poses = nullptr;
+  void* g_workspace = nullptr;
+  hipStream_t g_stream = nullptr;
 };
 
 namespace {
@@ -91,42 +167,51 @@ GroupsK groups_of(const ScenePlan& sp) {
   return g;
 }
 
-SensorWS ws_of(const SensorPlan& s, void* workspace) {
-  char* b = static_cast<char*>(workspace) + s.base;
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// SensorWS view of a record space starting at byte `base`, shifted to records [rb, ...).
+SensorWS record_ws(const RecordArrays& R, void* ws, size_t base, uint32_t rb) {
+  char* b = static_cast<char*>(ws) + base;
   SensorWS w;
-  w.pose = reinterpret_cast<float*>(b + s.o_pose);
-  w.rec = reinterpret_cast<float4*>(b + s.o_rec);
-  w.rec64 = reinterpret_cast<double*>(b + s.o_rec64);
-  w.grz = reinterpret_cast<double*>(b + s.o_grz);
-  w.rect = reinterpret_cast<int4*>(b + s.o_rect);
-  w.ntiles = reinterpret_cast<uint32_t*>(b + s.o_ntiles);
-  w.key[0] = reinterpret_cast<uint32_t*>(b + s.o_key0);
-  w.key[1] = reinterpret_cast<uint32_t*>(b + s.o_key1);
-  w.val[0] = reinterpret_cast<uint32_t*>(b + s.o_val0);
-  w.val[1] = reinterpret_cast<uint32_t*>(b + s.o_val1);
-  w.offs = reinterpret_cast<uint32_t*>(b + s.o_offs);
-  w.bsum = reinterpret_cast<uint32_t*>(b + s.o_bsum);
-  w.hist = reinterpret_cast<uint32_t*>(b + s.o_hist);
-  w.ptile[0] = reinterpret_cast<uint32_t*>(b + s.o_ptile0);
-  w.ptile[1] = reinterpret_cast<uint32_t*>(b + s.o_ptile1);
-  w.pval[0] = reinterpret_cast<uint32_t*>(b + s.o_pval0);
-  w.pval[1] = reinterpret_cast<uint32_t*>(b + s.o_pval1);
-  w.ranges = reinterpret_cast<uint2*>(b + s.o_ranges);
-  w.T_final = reinterpret_cast<float*>(b + s.o_Tfinal);
-  w.n_last = reinterpret_cast<uint32_t*>(b + s.o_nlast);
-  w.status = reinterpret_cast<uint32_t*>(b + s.o_status);
-  w.gacc = reinterpret_cast<float*>(b + s.o_gacc);
-  w.visible = reinterpret_cast<uint32_t*>(b + s.o_visible);
+  memset(&w, 0, sizeof(w));
+  w.rec = reinterpret_cast<float4*>(b + R.o_rec) + 4 * (size_t)rb;
+  w.rec64 = reinterpret_cast<double*>(b + R.o_rec64) + kRec64 * (size_t)rb;
+  w.grz = reinterpret_cast<double*>(b + R.o_grz) + kGrz * (size_t)rb;
+  w.rect = reinterpret_cast<int4*>(b + R.o_rect) + rb;
+  w.ntiles = reinterpret_cast<uint32_t*>(b + R.o_ntiles) + rb;
+  w.visible = reinterpret_cast<uint32_t*>(b + R.o_visible) + rb;
+  w.key[0] = reinterpret_cast<uint32_t*>(b + R.o_key0) + rb;
+  w.key[1] = reinterpret_cast<uint32_t*>(b + R.o_key1) + rb;
+  w.val[0] = reinterpret_cast<uint32_t*>(b + R.o_val0) + rb;
+  w.val[1] = reinterpret_cast<uint32_t*>(b + R.o_val1) + rb;
+  w.offs = reinterpret_cast<uint32_t*>(b + R.o_offs);
+  w.bsum = reinterpret_cast<uint32_t*>(b + R.o_bsum);
+  w.hist = reinterpret_cast<uint32_t*>(b + R.o_hist);
+  w.ptile[0] = reinterpret_cast<uint32_t*>(b + R.o_ptile0);
+  w.ptile[1] = reinterpret_cast<uint32_t*>(b + R.o_ptile1);
+  w.pval[0] = reinterpret_cast<uint32_t*>(b + R.o_pval0);
+  w.pval[1] = reinterpret_cast<uint32_t*>(b + R.o_pval1);
+  w.ranges = reinterpret_cast<uint2*>(b + R.o_ranges);
+  w.status = reinterpret_cast<uint32_t*>(b + R.o_status);
+  w.gacc = reinterpret_cast<float*>(b + R.o_gacc) + rb;
   return w;
 }
 
-int ceil_log2(int n) {
-  int b = 0;
-  while ((1 << b) < n) ++b;
-  return b;
+const RecordArrays& records_of(const gs_plan* p, const SensorPlan& s) { return p->batched ? p->G : s.R; }
+size_t records_base(const gs_plan* p, const SensorPlan& s) { return p->batched ? p->gbase : s.base; }
+
+SensorWS sensor_ws(const gs_plan* p, const SensorPlan& s, void* ws) {
+  SensorWS w = record_ws(records_of(p, s), ws, records_base(p, s), p->batched ? s.rec_base : 0);
+  w.pose = at<float>(ws, s.base + s.o_pose);
+  w.T_final = at<float>(ws, s.base + s.o_Tfinal);
+  w.n_last = at<uint32_t>(ws, s.base + s.o_nlast);
+  return w;
 }
 
-PrepArgs prep_args(const gs_plan* p, const SensorPlan& s, const gs_scene& sc, SensorWS ws) {
+PrepArgs prep_args(const gs_plan* p, const SensorPlan& s, const gs_scene& sc, const SensorWS& ws) {
   const ScenePlan& sp = p->scenes[s.scene];
   PrepArgs a;
   memset(&a, 0, sizeof(a));
@@ -143,7 +228,43 @@ PrepArgs prep_args(const gs_plan* p, const SensorPlan& s, const gs_scene& sc, Se
   a.S = s.K;
   a.O = p->O;
   a.ws = ws;
+  a.rec_base = p->batched ? s.rec_base : 0;
+  a.gacc_stride = records_of(p, s).n_rec;
   return a;
+}
+
+TileArgs tile_args(const gs_plan* p, const SensorPlan& s, void* ws) {
+  const RecordArrays& R = records_of(p, s);
+  const SensorWS full = record_ws(R, ws, records_base(p, s), 0);
+  TileArgs t;
+  memset(&t, 0, sizeof(t));
+  t.S = s.K;
+  t.O = p->O;
+  t.rec = full.rec;
+  t.rec64 = full.rec64;
+  t.grz = full.grz;
+  t.ranges = full.ranges;
+  t.pval = full.pval[R.pair_buf];
+  t.T_final = at<float>(ws, s.base + s.o_Tfinal);
+  t.n_last = at<uint32_t>(ws, s.base + s.o_nlast);
+  t.status = full.status;
+  t.gacc = full.gacc;
+  t.gacc_stride = R.n_rec;
+  return t;
+}
+
+EmitTable emit_table(const gs_plan* p, const std::vector<int>& sensors) {
+  EmitTable E;
+  memset(&E, 0, sizeof(E));
+  E.n = (int)sensors.size();
+  for (int k = 0; k < E.n; ++k) {
+    const SensorPlan& s = p->sensors[sensors[k]];
+    E.rec_base[k] = p->batched ? s.rec_base : 0;
+    E.n_tx[k] = s.K.n_tx;
+    E.tile_off[k] = s.K.tile_offset;
+  }
+  E.rec_base[E.n] = 0xFFFFFFFFu;
+  return E;
 }
 
 gs_status check_scene(const gs_plan* p, int si, const gs_scene& sc, bool need_colour, bool need_intensity) {
@@ -159,6 +280,125 @@ gs_status check_scene(const gs_plan* p, int si, const gs_scene& sc, bool need_co
   return GS_OK;
 }
 
+// Marks the start of a stage: returns the start event or nullptr when timing
+// is off, the event pool is exhausted or a graph is being captured.
+hipEvent_t stage_begin(gs_plan* p, hipStream_t st) {
+  if (p->capturing || p->next_event + 2 > p->pool.size()) return nullptr;
+  hipEvent_t e = p->pool[p->next_event++];
+  (void)hipEventRecord(e, st);
+  return e;
+}
+
+void stage_end(gs_plan* p, hipStream_t st, int stage, hipEvent_t e0) {
+  if (!e0) return;
+  hipEvent_t e1 = p->pool[p->next_event++];
+  (void)hipEventRecord(e1, st);
+  p->intervals.push_back({stage, e0, e1});
+}
+
+gs_status validate_call(const gs_plan* p, const gs_scene* scenes, const float* sensor_poses,
+                        const float* group_poses, const void* outputs, void* workspace) {
+  if (!p || !scenes || !sensor_poses || !group_poses || !outputs || !workspace)
+    return fail(GS_ERR_INVALID_ARG, "null argument to the render call");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(GS_ERR_INVALID_ARG, "workspace must be 256-B aligned");
+  for (size_t si = 0; si < p->sensors.size(); ++si) {
+    const SensorPlan& s = p->sensors[si];
+    gs_status cs = check_scene(p, s.scene, scenes[s.scene], s.K.kind == GS_SENSOR_PINHOLE, s.K.kind == GS_SENSOR_LIDAR);
+    if (cs != GS_OK) return cs;
+  }
+  return GS_OK;
+}
+
+// Depth sort, emission, tile sort and ranges over one record space.
+void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::vector<int>& sensors, void* workspace,
+                  hipStream_t st) {
+  SensorWS w = record_ws(R, workspace, rbase, 0);
+  hipEvent_t ev = stage_begin(p, st);
+  const int kb = radix_sort(w.key, w.val, nullptr, R.n_rec, R.n_rec, 32, w.hist, st);
+  stage_end(p, st, GS_STAGE_DEPTH_SORT, ev);
+  ev = stage_begin(p, st);
+  launch_pair_offsets(w.val[kb], w.ntiles, (int)R.n_rec, w.offs, w.bsum, w.status, R.cap, st);
+  launch_emit(w.val[kb], w.ntiles, w.rect, w.offs, (int)R.n_rec, emit_table(p, sensors), R.cap, w.ptile[0],
+              w.pval[0], st);
+  stage_end(p, st, GS_STAGE_EMIT, ev);
+  ev = stage_begin(p, st);
+  (void)radix_sort(w.ptile, w.pval, w.status + kStPairs, 0, R.cap, R.tile_bits, w.hist, st);
+  stage_end(p, st, GS_STAGE_TILE_SORT, ev);
+  ev = stage_begin(p, st);
+  launch_ranges(w.ptile[R.pair_buf], w.status + kStPairs, R.cap, w.ranges, R.n_tiles, st);
+  stage_end(p, st, GS_STAGE_RANGES, ev);
+}
+
+BatchArgs batch_args(gs_plan* p, void* workspace) {
+  BatchArgs b;
+  memset(&b, 0, sizeof(b));
+  b.tiles = at<TileArgs>(workspace, p->o_tiles);
+  b.n_sensors = (int)p->sensors.size();
+  for (int i = 0; i <= b.n_sensors; ++i) b.tile_off[i] = p->tile_off[i];
+  b.queue = at<uint32_t>(workspace, p->queue_buf ? p->o_qval1 : p->o_qval0);
+  b.n_items = p->G.n_tiles;
+  b.counter = at<uint32_t>(workspace, p->o_counter);
+  return b;
+}
+
+void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_poses, const float* group_poses,
+                     float* const* outputs, void* workspace, hipStream_t st) {
+  if (!p->batched) {
+    for (size_t si = 0; si < p->sensors.size(); ++si) {
+      SensorPlan& s = p->sensors[si];
+      const ScenePlan& sp = p->scenes[s.scene];
+      SensorWS ws = sensor_ws(p, s, workspace);
+      hipEvent_t ev = stage_begin(p, st);
+      launch_fill_u32(ws.status, 0u, 16, st);
+      launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
+      launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
+      launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, st);
+      stage_end(p, st, GS_STAGE_PREPROCESS, ev);
+      sort_and_bin(p, s.R, s.base, std::vector<int>{(int)si}, workspace, st);
+      TileArgs t = tile_args(p, s, workspace);
+      t.out = outputs[si];
+      ev = stage_begin(p, st);
+      launch_blend_forward(t, s.n_tiles, st);
+      stage_end(p, st, GS_STAGE_BLEND, ev);
+    }
+    return;
+  }
+  // batched step
+  SensorWS g = record_ws(p->G, workspace, p->gbase, 0);
+  hipEvent_t ev = stage_begin(p, st);
+  launch_fill_u32(g.status, 0u, 16, st);
+  for (size_t si = 0; si < p->sensors.size(); ++si) {
+    SensorPlan& s = p->sensors[si];
+    const ScenePlan& sp = p->scenes[s.scene];
+    SensorWS ws = sensor_ws(p, s, workspace);
+    uint32_t* sst = at<uint32_t>(workspace, s.base + s.o_status);
+    launch_fill_u32(sst, 0u, 16, st);
+    launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
+    launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
+    launch_count_visible(ws.visible, sp.desc.n_splats, sst, st);
+  }
+  stage_end(p, st, GS_STAGE_PREPROCESS, ev);
+  std::vector<int> all(p->sensors.size());
+  for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
+  sort_and_bin(p, p->G, p->gbase, all, workspace, st);
+  ev = stage_begin(p, st);
+  uint32_t* qk[2] = {at<uint32_t>(workspace, p->o_qkey0), at<uint32_t>(workspace, p->o_qkey1)};
+  uint32_t* qv[2] = {at<uint32_t>(workspace, p->o_qval0), at<uint32_t>(workspace, p->o_qval1)};
+  launch_queue_keys(g.ranges, p->G.n_tiles, qk[0], qv[0], st);
+  p->queue_buf = radix_sort(qk, qv, nullptr, (uint32_t)p->G.n_tiles, (uint32_t)p->G.n_tiles, 24, g.hist, st);
+  TileArgs* table = at<TileArgs>(workspace, p->o_tiles);
+  for (size_t si = 0; si < p->sensors.size(); ++si) {
+    TileArgs t = tile_args(p, p->sensors[si], workspace);
+    t.out = outputs[si];
+    launch_store_tile_args(t, table + si, st);
+  }
+  BatchArgs b = batch_args(p, workspace);
+  launch_fill_u32(b.counter, 0u, 1, st);
+  launch_blend_persistent(b, p->persistent_grid, false, st);
+  stage_end(p, st, GS_STAGE_BLEND, ev);
+}
+
 }  // namespace
 
 namespace gs {
@@ -171,7 +411,7 @@ gs_status set_error(gs_status s, const std::string& msg) {
 
 extern "C" {
 
-const char* gs_version(void) { return "gs2d 0.1 (gfx950)"; }
+const char* gs_version(void) { return "gs2d 0.2 (gfx950)"; }
 
 const char* gs_status_string(gs_status s) {
   switch (s) {
@@ -193,22 +433,30 @@ gs_status gs_last_error(char* buf, size_t n) {
   return g_last_status;
 }
 
+void gs_plan_destroy(gs_plan* p) {
+  if (!p) return;
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  for (auto& s : p->sensors)
+    if (s.d_tabs) (void)hipFree(s.d_tabs);
+  delete p;
+}
+
 gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
   if (!desc || !out) return fail(GS_ERR_INVALID_ARG, "null descriptor or output");
   *out = nullptr;
-  if (desc->n_scenes < 1 || desc->n_scenes > 2 || !desc->scenes)
-    return fail(GS_ERR_INVALID_ARG, "n_scenes must be 1 or 2");
+  if (desc->n_scenes < 1 || desc->n_scenes > GS_MAX_SENSORS || !desc->scenes)
+    return fail(GS_ERR_INVALID_ARG, "n_scenes must be in [1, GS_MAX_SENSORS]");
   if (desc->n_sensors < 1 || desc->n_sensors > GS_MAX_SENSORS || !desc->sensors)
     return fail(GS_ERR_INVALID_ARG, "n_sensors must be in [1, GS_MAX_SENSORS]");
   const gs_render_opts& o = desc->opts;
   if (!(o.alpha_max > 0.0f && o.alpha_max < 1.0f) || !(o.alpha_min >= 0.0f) || !(o.T_min >= 0.0f) ||
       !(o.cutoff2 > 0.0f) || !(o.lp_inv_sigma2 > 0.0f) || !std::isfinite(o.cutoff2))
     return fail(GS_ERR_INVALID_ARG, "render options out of range");
-  if (desc->batched) return fail(GS_ERR_UNSUPPORTED, "batched plans are not available in this build");
   gs_plan* p = new gs_plan();
-  hipGetDevice(&p->device);
+  (void)hipGetDevice(&p->device);
   p->opts = o;
-  p->batched = desc->batched;
+  p->batched = desc->batched ? 1 : 0;
   p->O.alpha_min = o.alpha_min;
   p->O.alpha_max = o.alpha_max;
   p->O.T_min = o.T_min;
@@ -225,14 +473,14 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     ScenePlan sp;
     sp.desc = d;
     if (d.n_splats < 0 || d.n_groups < 1 || d.n_groups > GS_MAX_GROUPS || !d.group_offsets || d.sh_degree > 3) {
-      delete p;
+      gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "scene " + std::to_string(i) + ": bad shape");
     }
     sp.offsets.assign(d.group_offsets, d.group_offsets + d.n_groups + 1);
     bool okoff = sp.offsets[0] == 0 && sp.offsets[d.n_groups] == d.n_splats;
     for (int g = 0; g < d.n_groups; ++g) okoff = okoff && sp.offsets[g] <= sp.offsets[g + 1];
     if (!okoff) {
-      delete p;
+      gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "scene " + std::to_string(i) + ": group offsets must rise from 0 to N");
     }
     sp.desc.group_offsets = nullptr;
@@ -241,14 +489,15 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     p->scenes.push_back(sp);
   }
   Layout L;
+  uint64_t total_rec = 0, total_cap = 0;
+  int total_tiles = 0;
   for (int si = 0; si < desc->n_sensors; ++si) {
     const gs_sensor_desc& d = desc->sensors[si];
     SensorPlan s;
-    memset(&s, 0, sizeof(s));
     s.desc = d;
     s.desc.elevations = nullptr;
     if (d.scene < 0 || d.scene >= desc->n_scenes || d.width <= 0 || d.height <= 0 || !(d.z_near > 0.0f)) {
-      delete p;
+      gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": bad size, scene or z_near");
     }
     s.scene = d.scene;
@@ -262,7 +511,7 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     K.z_near = d.z_near;
     if (d.kind == GS_SENSOR_PINHOLE) {
       if (!(d.fx > 0.0f && d.fy > 0.0f)) {
-        delete p;
+        gs_plan_destroy(p);
         return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": focal lengths must be > 0");
       }
       K.tw = d.tile_w ? d.tile_w : 16;
@@ -273,16 +522,16 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
       K.cy = d.cy;
     } else if (d.kind == GS_SENSOR_LIDAR) {
       if (!d.elevations) {
-        delete p;
+        gs_plan_destroy(p);
         return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": LiDAR needs elevations");
       }
       for (int j = 0; j + 1 < d.height; ++j)
         if (!(d.elevations[j] < d.elevations[j + 1])) {
-          delete p;
+          gs_plan_destroy(p);
           return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": elevations must ascend");
         }
       if (!sp.desc.has_intensity) {
-        delete p;
+        gs_plan_destroy(p);
         return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": LiDAR scene needs intensity");
       }
       K.tw = d.tile_w ? d.tile_w : 32;
@@ -307,7 +556,8 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
       hipError_t e = hipMalloc(&s.d_tabs, tab.size() * sizeof(float));
       if (e == hipSuccess) e = hipMemcpy(s.d_tabs, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
       if (e != hipSuccess) {
-        delete p;
+        p->sensors.push_back(s);
+        gs_plan_destroy(p);
         return fail(GS_ERR_HIP, std::string("LiDAR tables: ") + hipGetErrorString(e));
       }
       K.el = s.d_tabs;
@@ -316,65 +566,104 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
       K.cos_az = s.d_tabs + 3 * d.height;
       K.sin_az = s.d_tabs + 3 * d.height + d.width;
     } else {
-      delete p;
+      gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": unknown kind");
     }
-    if (!tile_shape_supported(K.tw, K.th)) {
+    const bool shape_ok = tile_shape_supported(K.tw, K.th) && (!p->batched || K.tw * K.th == 256);
+    if (!shape_ok) {
       p->sensors.push_back(s);
       gs_plan_destroy(p);
       return fail(GS_ERR_UNSUPPORTED, "sensor " + std::to_string(si) + ": unsupported tile shape");
     }
     K.n_tx = (K.W + K.tw - 1) / K.tw;
     K.n_ty = (K.H + K.th - 1) / K.th;
-    K.tile_offset = 0;
     s.n_tiles = K.n_tx * K.n_ty;
-    s.tile_bits = ceil_log2(s.n_tiles);
     int64_t cap = desc->pair_capacity > 0 ? desc->pair_capacity : 16ll * N + 4096;
     if (cap > 0x7FFFFFFFll) cap = 0x7FFFFFFFll;
-    s.cap = (uint32_t)cap;
-    // workspace region
+    // per-sensor region
     Layout R;
-    const size_t n = (size_t)N;
     const size_t HW = (size_t)K.W * K.H;
     s.o_status = R.take(16 * 4);
     s.o_pose = R.take(12 * 4 * (size_t)sp.desc.n_groups);
-    s.o_rec = R.take(n * 64);
-    s.o_rec64 = R.take(n * 8 * kRec64);
-    s.o_grz = R.take(n * 8 * kGrz);
-    s.o_rect = R.take(n * 16);
-    s.o_ntiles = R.take(n * 4);
-    s.o_visible = R.take(n * 4);
-    s.o_key0 = R.take(n * 4);
-    s.o_key1 = R.take(n * 4);
-    s.o_val0 = R.take(n * 4);
-    s.o_val1 = R.take(n * 4);
-    s.o_offs = R.take((n + 1) * 4);
-    s.o_bsum = R.take(scan_bsum_words(N) * 4);
-    size_t hw = radix_hist_words(s.cap);
-    size_t hw2 = radix_hist_words((uint32_t)N);
-    s.o_hist = R.take((hw > hw2 ? hw : hw2) * 4);
-    s.o_ptile0 = R.take((size_t)s.cap * 4);
-    s.o_ptile1 = R.take((size_t)s.cap * 4);
-    s.o_pval0 = R.take((size_t)s.cap * 4);
-    s.o_pval1 = R.take((size_t)s.cap * 4);
-    s.o_ranges = R.take((size_t)s.n_tiles * 8);
     s.o_Tfinal = R.take(HW * 4);
     s.o_nlast = R.take(HW * 4);
-    s.o_gacc = R.take(n * 4 * kGradFields);
+    if (p->batched) {
+      K.tile_offset = total_tiles;
+      s.rec_base = (uint32_t)total_rec;
+      p->tile_off[si] = total_tiles;
+    } else {
+      K.tile_offset = 0;
+      s.R.layout(R, (uint32_t)N, (uint32_t)cap, s.n_tiles);
+    }
+    total_rec += (uint64_t)N;
+    total_cap += (uint64_t)cap;
+    total_tiles += s.n_tiles;
     s.base = L.take(R.off);
-    s.pair_buf = (s.tile_bits + 7) / 8 % 2;
     p->sensors.push_back(s);
+  }
+  if (p->batched) {
+    if (total_rec > 0x7FFFFFFFull) {
+      gs_plan_destroy(p);
+      return fail(GS_ERR_UNSUPPORTED, "batched plan exceeds 2^31 surfel records");
+    }
+    if (total_cap > 0x7FFFFFFFull) total_cap = 0x7FFFFFFFull;
+    p->tile_off[desc->n_sensors] = total_tiles;
+    Layout R;
+    p->G.layout(R, (uint32_t)total_rec, (uint32_t)total_cap, total_tiles);
+    p->o_qkey0 = R.take((size_t)total_tiles * 4);
+    p->o_qkey1 = R.take((size_t)total_tiles * 4);
+    p->o_qval0 = R.take((size_t)total_tiles * 4);
+    p->o_qval1 = R.take((size_t)total_tiles * 4);
+    p->o_tiles = R.take(sizeof(TileArgs) * GS_MAX_SENSORS);
+    p->o_counter = R.take(256);
+    p->gbase = L.take(R.off);
+    p->o_qkey0 += p->gbase;
+    p->o_qkey1 += p->gbase;
+    p->o_qval0 += p->gbase;
+    p->o_qval1 += p->gbase;
+    p->o_tiles += p->gbase;
+    p->o_counter += p->gbase;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    const int per = persistent_blocks_per_cu(false);
+    p->persistent_grid = cus * (per > 0 ? per : 4);
   }
   p->ws_bytes = L.off;
   *out = p;
   return ok();
 }
 
-void gs_plan_destroy(gs_plan* p) {
-  if (!p) return;
-  for (auto& s : p->sensors)
-    if (s.d_tabs) hipFree(s.d_tabs);
-  delete p;
+gs_status gs_plan_set_timing(gs_plan* p, int32_t max_records) {
+  if (!p || max_records < 0) return fail(GS_ERR_INVALID_ARG, "bad timing arguments");
+  for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
+  p->pool.clear();
+  p->intervals.clear();
+  p->next_event = 0;
+  for (int i = 0; i < 2 * max_records; ++i) {
+    hipEvent_t e;
+    GS_HIP_TRY(hipEventCreate(&e));
+    p->pool.push_back(e);
+  }
+  return ok();
+}
+
+gs_status gs_plan_stage_times(gs_plan* p, hipStream_t st, int32_t reset, gs_stage_times* out) {
+  if (!p || !out) return fail(GS_ERR_INVALID_ARG, "null argument to gs_plan_stage_times");
+  GS_HIP_TRY(hipStreamSynchronize(st));
+  memset(out, 0, sizeof(*out));
+  for (const auto& iv : p->intervals) {
+    float ms = 0.0f;
+    GS_HIP_TRY(hipEventElapsedTime(&ms, iv.e0, iv.e1));
+    out->ms[iv.stage] += ms;
+    out->launches[iv.stage] += 1;
+    out->records += 1;
+  }
+  if (reset) {
+    p->intervals.clear();
+    p->next_event = 0;
+  }
+  return ok();
 }
 
 gs_status gs_plan_workspace_size(const gs_plan* p, size_t* bytes) {
@@ -386,87 +675,109 @@ gs_status gs_plan_workspace_size(const gs_plan* p, size_t* bytes) {
 gs_status gs_plan_inspect(const gs_plan* p, int32_t sensor, gs_workspace_view* out) {
   if (!p || !out || sensor < 0 || sensor >= (int)p->sensors.size()) return fail(GS_ERR_INVALID_ARG, "bad inspect args");
   const SensorPlan& s = p->sensors[sensor];
-  out->pair_surfel = s.base + (s.pair_buf ? s.o_pval1 : s.o_pval0);
-  out->pair_tile = s.base + (s.pair_buf ? s.o_ptile1 : s.o_ptile0);
-  out->tile_ranges = s.base + s.o_ranges;
-  out->visible = s.base + s.o_visible;
-  out->pair_count = s.base + s.o_status + 4 * kStPairs;
-  out->n_tiles = s.n_tiles;
+  const RecordArrays& R = records_of(p, s);
+  const size_t b = records_base(p, s);
+  out->pair_surfel = b + (R.pair_buf ? R.o_pval1 : R.o_pval0);
+  out->pair_tile = b + (R.pair_buf ? R.o_ptile1 : R.o_ptile0);
+  out->tile_ranges = b + R.o_ranges;
+  out->visible = b + R.o_visible + 4ull * (p->batched ? s.rec_base : 0);
+  out->pair_count = b + R.o_status + 4 * kStPairs;
+  out->n_tiles = p->batched ? R.n_tiles : s.n_tiles;
   out->tile_offset = s.K.tile_offset;
   return ok();
 }
 
 gs_status gs_render_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_poses, const float* group_poses,
                             float* const* outputs, void* workspace, hipStream_t st) {
-  if (!p || !scenes || !sensor_poses || !group_poses || !outputs || !workspace)
-    return fail(GS_ERR_INVALID_ARG, "null argument to gs_render_forward");
-  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(GS_ERR_INVALID_ARG, "workspace must be 256-B aligned");
-  for (size_t si = 0; si < p->sensors.size(); ++si) {
-    const SensorPlan& s = p->sensors[si];
+  gs_status v = validate_call(p, scenes, sensor_poses, group_poses, outputs, workspace);
+  if (v != GS_OK) return v;
+  for (size_t si = 0; si < p->sensors.size(); ++si)
     if (!outputs[si]) return fail(GS_ERR_INVALID_ARG, "null output for sensor " + std::to_string(si));
-    gs_status cs = check_scene(p, s.scene, scenes[s.scene], s.K.kind == GS_SENSOR_PINHOLE, s.K.kind == GS_SENSOR_LIDAR);
-    if (cs != GS_OK) return cs;
+  bool replay = p->graph_exec && workspace == p->g_workspace && sensor_poses == p->g_sensor_poses &&
+                group_poses == p->g_group_poses && st == p->g_stream;
+  for (size_t i = 0; replay && i < p->scenes.size(); ++i)
+    replay = memcmp(&scenes[i], &p->g_scenes[i], sizeof(gs_scene)) == 0;
+  for (size_t i = 0; replay && i < p->sensors.size(); ++i) replay = outputs[i] == p->g_outputs[i];
+  if (replay) {
+    GS_HIP_TRY(hipGraphLaunch(p->graph_exec, st));
+    return ok();
   }
-  for (size_t si = 0; si < p->sensors.size(); ++si) {
-    const SensorPlan& s = p->sensors[si];
-    const ScenePlan& sp = p->scenes[s.scene];
-    const int N = sp.desc.n_splats;
-    SensorWS ws = ws_of(s, workspace);
-    launch_fill_u32(ws.status, 0u, 16, st);
-    launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
-    PrepArgs a = prep_args(p, s, scenes[s.scene], ws);
-    launch_prep(a, st);
-    launch_count_visible(ws.visible, N, ws.status, st);
-    int kb = radix_sort(ws.key, ws.val, nullptr, (uint32_t)N, (uint32_t)N, 32, ws.hist, st);
-    launch_pair_offsets(ws.val[kb], ws.ntiles, N, ws.offs, ws.bsum, ws.status, s.cap, st);
-    launch_emit(ws.val[kb], ws.ntiles, ws.rect, ws.offs, N, s.K, s.cap, ws.ptile[0], ws.pval[0], st);
-    int pb = radix_sort(ws.ptile, ws.pval, ws.status + kStPairs, 0, s.cap, s.tile_bits, ws.hist, st);
-    launch_ranges(ws.ptile[pb], ws.status + kStPairs, s.cap, ws.ranges, s.n_tiles, st);
-    BlendArgs b;
-    memset(&b, 0, sizeof(b));
-    b.S = s.K;
-    b.O = p->O;
-    b.ws = ws;
-    b.pval = ws.pval[pb];
-    b.n_tiles = s.n_tiles;
-    b.n_splats = N;
-    b.out = outputs[si];
-    launch_blend_forward(b, st);
-  }
+  enqueue_forward(p, scenes, sensor_poses, group_poses, outputs, workspace, st);
   GS_HIP_TRY(hipGetLastError());
+  return ok();
+}
+
+gs_status gs_plan_capture(gs_plan* p, const gs_scene* scenes, const float* sensor_poses, const float* group_poses,
+                          float* const* outputs, void* workspace, hipStream_t st) {
+  gs_status v = validate_call(p, scenes, sensor_poses, group_poses, outputs, workspace);
+  if (v != GS_OK) return v;
+  for (size_t si = 0; si < p->sensors.size(); ++si)
+    if (!outputs[si]) return fail(GS_ERR_INVALID_ARG, "null output for sensor " + std::to_string(si));
+  if (!st) return fail(GS_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+  if (p->graph_exec) {
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+  }
+  GS_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  p->capturing = true;
+  enqueue_forward(p, scenes, sensor_poses, group_poses, outputs, workspace, st);
+  p->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&p->graph_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    p->graph_exec = nullptr;
+    return fail(GS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  p->g_scenes.assign(scenes, scenes + p->scenes.size());
+  p->g_outputs.assign(outputs, outputs + p->sensors.size());
+  p->g_sensor_poses = sensor_poses;
+  p->g_group_poses = group_poses;
+  p->g_workspace = workspace;
+  p->g_stream = st;
   return ok();
 }
 
 gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* sensor_poses, const float* group_poses,
                              const float* const* outputs, const float* const* grad_outputs, void* workspace,
                              const gs_scene_grads* grads, hipStream_t st) {
-  (void)sensor_poses;
-  (void)group_poses;
-  if (!p || !scenes || !outputs || !grad_outputs || !workspace || !grads)
-    return fail(GS_ERR_INVALID_ARG, "null argument to gs_render_backward");
-  for (size_t si = 0; si < p->sensors.size(); ++si) {
-    if (!outputs[si] || !grad_outputs[si]) return fail(GS_ERR_INVALID_ARG, "null output/grad for sensor " + std::to_string(si));
-    const SensorPlan& s = p->sensors[si];
-    gs_status cs = check_scene(p, s.scene, scenes[s.scene], s.K.kind == GS_SENSOR_PINHOLE, s.K.kind == GS_SENSOR_LIDAR);
-    if (cs != GS_OK) return cs;
+  gs_status v = validate_call(p, scenes, sensor_poses, group_poses, outputs, workspace);
+  if (v != GS_OK) return v;
+  if (!grad_outputs || !grads) return fail(GS_ERR_INVALID_ARG, "null argument to gs_render_backward");
+  for (size_t si = 0; si < p->sensors.size(); ++si)
+    if (!outputs[si] || !grad_outputs[si])
+      return fail(GS_ERR_INVALID_ARG, "null output/grad for sensor " + std::to_string(si));
+  if (p->batched) {
+    SensorWS g = record_ws(p->G, workspace, p->gbase, 0);
+    hipEvent_t ev = stage_begin(p, st);
+    launch_fill_f32(g.gacc, 0.0f, (size_t)p->G.n_rec * kGradFields, st);
+    TileArgs* table = at<TileArgs>(workspace, p->o_tiles);
+    for (size_t si = 0; si < p->sensors.size(); ++si) {
+      TileArgs t = tile_args(p, p->sensors[si], workspace);
+      t.out_fwd = outputs[si];
+      t.gout = grad_outputs[si];
+      launch_store_tile_args(t, table + si, st);
+    }
+    BatchArgs b = batch_args(p, workspace);
+    launch_fill_u32(b.counter, 0u, 1, st);
+    launch_blend_persistent(b, p->persistent_grid, true, st);
+    stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
   }
   for (size_t si = 0; si < p->sensors.size(); ++si) {
-    const SensorPlan& s = p->sensors[si];
-    const ScenePlan& sp = p->scenes[s.scene];
-    const int N = sp.desc.n_splats;
-    SensorWS ws = ws_of(s, workspace);
-    launch_fill_f32(ws.gacc, 0.0f, (size_t)N * kGradFields, st);
-    BlendArgs b;
-    memset(&b, 0, sizeof(b));
-    b.S = s.K;
-    b.O = p->O;
-    b.ws = ws;
-    b.pval = s.pair_buf ? ws.pval[1] : ws.pval[0];
-    b.n_tiles = s.n_tiles;
-    b.n_splats = N;
-    b.out_fwd = outputs[si];
-    b.gout = grad_outputs[si];
-    launch_blend_backward(b, st);
+    SensorPlan& s = p->sensors[si];
+    SensorWS ws = sensor_ws(p, s, workspace);
+    if (!p->batched) {
+      const int N = p->scenes[s.scene].desc.n_splats;
+      hipEvent_t ev = stage_begin(p, st);
+      launch_fill_f32(ws.gacc, 0.0f, (size_t)N * kGradFields, st);
+      TileArgs t = tile_args(p, s, workspace);
+      t.out_fwd = outputs[si];
+      t.gout = grad_outputs[si];
+      launch_blend_backward(t, s.n_tiles, st);
+      stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
+    }
     SplatBwdArgs sb;
     memset(&sb, 0, sizeof(sb));
     sb.p = prep_args(p, s, scenes[s.scene], ws);
@@ -478,7 +789,9 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
     sb.g_rgb = g.rgb;
     sb.g_sh = g.sh;
     sb.g_intensity = g.intensity;
+    hipEvent_t ev = stage_begin(p, st);
     launch_splat_backward(sb, st);
+    stage_end(p, st, GS_STAGE_SPLAT_BWD, ev);
   }
   GS_HIP_TRY(hipGetLastError());
   return ok();
@@ -489,14 +802,34 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   GS_HIP_TRY(hipStreamSynchronize(st));
   memset(out, 0, sizeof(*out));
   bool over = false;
-  for (size_t si = 0; si < p->sensors.size(); ++si) {
-    const SensorPlan& s = p->sensors[si];
+  auto read = [&](size_t off, uint32_t* w) {
+    return hipMemcpy(w, static_cast<const char*>(workspace) + off, 16 * 4, hipMemcpyDeviceToHost);
+  };
+  if (p->batched) {
     uint32_t w[16];
-    GS_HIP_TRY(hipMemcpy(w, static_cast<const char*>(workspace) + s.base + s.o_status, sizeof(w), hipMemcpyDeviceToHost));
-    out->pairs[si] = w[kStPairs];
-    out->n_visible[si] = (int32_t)w[kStVisible];
-    out->fp64_pairs += w[kStFp64];
-    over = over || w[kStOverflow] != 0;
+    GS_HIP_TRY(read(p->gbase + p->G.o_status, w));
+    out->pairs[0] = w[kStPairs];
+    out->fp64_pairs = w[kStFp64];
+    out->evaluated = (int64_t)w[kStEvals] | ((int64_t)w[kStEvals + 1] << 32);
+    out->composited = (int64_t)w[kStContrib] | ((int64_t)w[kStContrib + 1] << 32);
+    over = w[kStOverflow] != 0;
+    for (size_t si = 0; si < p->sensors.size(); ++si) {
+      uint32_t ws[16];
+      GS_HIP_TRY(read(p->sensors[si].base + p->sensors[si].o_status, ws));
+      out->n_visible[si] = (int32_t)ws[kStVisible];
+    }
+  } else {
+    for (size_t si = 0; si < p->sensors.size(); ++si) {
+      const SensorPlan& s = p->sensors[si];
+      uint32_t w[16];
+      GS_HIP_TRY(read(s.base + s.R.o_status, w));
+      out->pairs[si] = w[kStPairs];
+      out->n_visible[si] = (int32_t)w[kStVisible];
+      out->fp64_pairs += w[kStFp64];
+      out->evaluated += (int64_t)w[kStEvals] | ((int64_t)w[kStEvals + 1] << 32);
+      out->composited += (int64_t)w[kStContrib] | ((int64_t)w[kStContrib + 1] << 32);
+      over = over || w[kStOverflow] != 0;
+    }
   }
   out->overflow = over ? 1 : 0;
   if (over) return fail(GS_ERR_CAPACITY, "pair capacity exceeded; re-plan with a larger pair_capacity");

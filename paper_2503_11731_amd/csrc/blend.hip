@@ -42,7 +42,7 @@ struct PairEval {
 //  [2] mu_z, log2 o, c0, c1          [3] c2, n0, n1, n2
 //  [4] flags, o, -, -
 __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint32_t s, float plx, float ply, int ox,
-                                             int oy, const BlendArgs& a, PairEval& e) {
+                                             int oy, const TileArgs& a, PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2];
   const uint32_t flags = __float_as_uint(R[4].x);
@@ -53,8 +53,9 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   const float h2 = fmaf(q1.z, dx, fmaf(q1.w, dy, 1.0f));
   float u, v, r, z;
   if ((flags & kFlagGrazing) && fabsf(h2) < 0.125f) {
-    const double* G = a.ws.grz + kGrz * (size_t)s;
-    const double* r64 = a.ws.rec64 + kRec64 * (size_t)s;
+    ++n64;
+    const double* G = a.grz + kGrz * (size_t)s;
+    const double* r64 = a.rec64 + kRec64 * (size_t)s;
     const double ddx = ((double)ox + (double)plx) - r64[0];
     const double ddy = ((double)oy + (double)ply) - r64[1];
     const double H0 = G[0] * ddx + G[1] * ddy;
@@ -100,10 +101,10 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   return true;
 }
 
-__device__ __forceinline__ void stage_pinhole(const BlendArgs& a, uint32_t s, int ox, int oy, float4* dst) {
-  const float4* r = a.ws.rec + 4 * (size_t)s;
+__device__ __forceinline__ void stage_pinhole(const TileArgs& a, uint32_t s, int ox, int oy, float4* dst) {
+  const float4* r = a.rec + 4 * (size_t)s;
   const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-  const double* r64 = a.ws.rec64 + kRec64 * (size_t)s;
+  const double* r64 = a.rec64 + kRec64 * (size_t)s;
   const float pcx = (float)(r64[0] - (double)ox);
   const float pcy = (float)(r64[1] - (double)oy);
   dst[0] = make_float4(pcx, pcy, r0.x, r0.y);
@@ -113,14 +114,10 @@ __device__ __forceinline__ void stage_pinhole(const BlendArgs& a, uint32_t s, in
   dst[4] = make_float4(r3.z, r3.w, 0.0f, 0.0f);
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_blend_pinhole(BlendArgs a) {
+template <int NT>
+__device__ void fwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id) {
 #pragma clang fp contract(off)
-  constexpr int NT = TW * TH;
-  constexpr int WX = TW / 8;
-  __shared__ float4 s_rec[NT][5];
-  __shared__ uint32_t s_id[NT];
-  const int tile = xcd_remap(blockIdx.x, a.n_tiles);
+  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
   const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
@@ -128,13 +125,13 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole(BlendArgs a) {
   const int px = ox + lx, py = oy + ly;
   const bool inside = px < a.S.W && py < a.S.H;
   const float plx = (float)lx + 0.5f, ply = (float)ly + 0.5f;
-  const uint2 rg = a.ws.ranges[a.S.tile_offset + tile];
+  const uint2 rg = a.ranges[a.S.tile_offset + tile];
   float T = 1.0f;
   float acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
   bool done = !inside;
-  uint32_t last = rg.x;
+  uint32_t last = rg.x, n_eval = 0, n_contrib = 0, n64 = 0;
   for (uint32_t base = rg.x; base < rg.y; base += NT) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t k = base + t;
@@ -149,12 +146,14 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole(BlendArgs a) {
       if (__ballot(!done) == 0) break;
       if (done) continue;
       PairEval e;
-      if (!eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e)) continue;
+      ++n_eval;
+      if (!eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e, n64)) continue;
       const float Tn = T * (1.0f - e.alpha);
       if (Tn < a.O.T_min) {
         done = true;
         continue;
       }
+      ++n_contrib;
       const float wgt = e.alpha * T;
       const float4 q2 = s_rec[j][2], q3 = s_rec[j][3];
       acc[0] = fmaf(wgt, q2.z, acc[0]);
@@ -169,6 +168,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole(BlendArgs a) {
       last = base + j + 1;
     }
   }
+  count_pairs(a.status, n_eval, n_contrib, n64);
   if (inside) {
     const size_t HW = (size_t)a.S.W * a.S.H;
     const size_t p = (size_t)py * a.S.W + px;
@@ -177,8 +177,8 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole(BlendArgs a) {
     a.out[2 * HW + p] = fmaf(T, a.O.bg2, acc[2]);
 #pragma unroll
     for (int c = 3; c < 8; ++c) a.out[c * HW + p] = acc[c];
-    a.ws.T_final[p] = T;
-    a.ws.n_last[p] = last;
+    a.T_final[p] = T;
+    a.n_last[p] = last;
   }
 }
 
@@ -190,15 +190,10 @@ __device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* g
   }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
+template <int NT>
+__device__ void bwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id, uint32_t& s_maxlast) {
 #pragma clang fp contract(off)
-  constexpr int NT = TW * TH;
-  constexpr int WX = TW / 8;
-  __shared__ float4 s_rec[NT][5];
-  __shared__ uint32_t s_id[NT];
-  __shared__ uint32_t s_maxlast;
-  const int tile = xcd_remap(blockIdx.x, a.n_tiles);
+  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
   const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
@@ -206,7 +201,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
   const int px = ox + lx, py = oy + ly;
   const bool inside = px < a.S.W && py < a.S.H;
   const float plx = (float)lx + 0.5f, ply = (float)ly + 0.5f;
-  const uint2 rg = a.ws.ranges[a.S.tile_offset + tile];
+  const uint2 rg = a.ranges[a.S.tile_offset + tile];
   const size_t HW = (size_t)a.S.W * a.S.H;
   const size_t p = inside ? (size_t)py * a.S.W + px : 0;
   float g[8], O[8];
@@ -215,7 +210,8 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
     g[c] = inside ? a.gout[c * HW + p] : 0.0f;
     O[c] = inside ? a.out_fwd[c * HW + p] : 0.0f;
   }
-  const uint32_t last = inside ? a.ws.n_last[p] : rg.x;
+  const uint32_t last = inside ? a.n_last[p] : rg.x;
+  __syncthreads();
   if (t == 0) s_maxlast = rg.x;
   __syncthreads();
   atomicMax(&s_maxlast, last);
@@ -225,11 +221,11 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
   uint32_t wlast = last;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+  uint32_t n64 = 0;
   float T = 1.0f;
   float A[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) A[c] = 0.0f;
-  const int N = a.n_splats;
   for (uint32_t base = rg.x; base < end; base += NT) {
     __syncthreads();
     const uint32_t k = base + t;
@@ -244,7 +240,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
       if (base + j >= wlast) break;
       const bool active = base + j < last;
       PairEval e;
-      const bool hit = active && eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e);
+      const bool hit = active && eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e, n64);
       float gr[kGradFields];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
@@ -294,7 +290,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
         gr[7] = -gdy;
         T = T * (1.0f - al);
       }
-      if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.ws.gacc, N, lane);
+      if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.gacc, a.gacc_stride, lane);
     }
   }
 }
@@ -304,10 +300,10 @@ __global__ __launch_bounds__(TW* TH) void k_blend_pinhole_bwd(BlendArgs a) {
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
 //  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, intensity, flags
 //  [4] o, -, -, -
-__device__ __forceinline__ void stage_lidar(const BlendArgs& a, uint32_t s, const double* dtile, float4* dst) {
-  const float4* r = a.ws.rec + 4 * (size_t)s;
+__device__ __forceinline__ void stage_lidar(const TileArgs& a, uint32_t s, const double* dtile, float4* dst) {
+  const float4* r = a.rec + 4 * (size_t)s;
   const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-  const double* r64 = a.ws.rec64 + kRec64 * (size_t)s;
+  const double* r64 = a.rec64 + kRec64 * (size_t)s;
   const float c0 = (float)(dtile[0] - r64[0]);
   const float c1 = (float)(dtile[1] - r64[1]);
   const float c2 = (float)(dtile[2] - r64[2]);
@@ -319,7 +315,7 @@ __device__ __forceinline__ void stage_lidar(const BlendArgs& a, uint32_t s, cons
 }
 
 __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix,
-                                           const double* d64, const BlendArgs& a, PairEval& e) {
+                                           const double* d64, const TileArgs& a, PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2], q3 = R[3];
   const uint32_t flags = __float_as_uint(q3.w);
@@ -331,8 +327,9 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   const float h2 = fmaf(q2.y, d0, fmaf(q2.z, d1, fmaf(q2.w, d2, 1.0f)));
   float u, v, r, z;
   if ((flags & kFlagGrazing) && fabsf(h2) < 0.125f) {
-    const double* G = a.ws.grz + kGrz * (size_t)s;
-    const double* r64 = a.ws.rec64 + kRec64 * (size_t)s;
+    ++n64;
+    const double* G = a.grz + kGrz * (size_t)s;
+    const double* r64 = a.rec64 + kRec64 * (size_t)s;
     const double e0 = d64[0] - r64[0], e1 = d64[1] - r64[1], e2 = d64[2] - r64[2];
     const double H0 = G[0] * e0 + G[1] * e1 + G[2] * e2;
     const double H1 = G[3] * e0 + G[4] * e1 + G[5] * e2;
@@ -386,14 +383,10 @@ __device__ inline void lidar_dir(const SensorK& S, int c, int j, double* d) {
   d[2] = se;
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_blend_lidar(BlendArgs a) {
+template <int NT>
+__device__ void fwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id) {
 #pragma clang fp contract(off)
-  constexpr int NT = TW * TH;
-  constexpr int WX = TW / 8;
-  __shared__ float4 s_rec[NT][5];
-  __shared__ uint32_t s_id[NT];
-  const int tile = xcd_remap(blockIdx.x, a.n_tiles);
+  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
   const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
@@ -404,10 +397,10 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar(BlendArgs a) {
   lidar_dir(a.S, ox, oy, dt);
   lidar_dir(a.S, inside ? pc : ox, inside ? pb : oy, d64);
   const float dpix[3] = {(float)(d64[0] - dt[0]), (float)(d64[1] - dt[1]), (float)(d64[2] - dt[2])};
-  const uint2 rg = a.ws.ranges[a.S.tile_offset + tile];
+  const uint2 rg = a.ranges[a.S.tile_offset + tile];
   float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
   bool done = !inside;
-  uint32_t last = rg.x;
+  uint32_t last = rg.x, n_eval = 0, n_contrib = 0, n64 = 0;
   for (uint32_t base = rg.x; base < rg.y; base += NT) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t k = base + t;
@@ -422,12 +415,14 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar(BlendArgs a) {
       if (__ballot(!done) == 0) break;
       if (done) continue;
       PairEval e;
-      if (!eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e)) continue;
+      ++n_eval;
+      if (!eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e, n64)) continue;
       const float Tn = T * (1.0f - e.alpha);
       if (Tn < a.O.T_min) {
         done = true;
         continue;
       }
+      ++n_contrib;
       const float wgt = e.alpha * T;
       acc0 = fmaf(wgt, e.z, acc0);
       acc1 = fmaf(wgt, s_rec[j][3].z, acc1);
@@ -436,26 +431,22 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar(BlendArgs a) {
       last = base + j + 1;
     }
   }
+  count_pairs(a.status, n_eval, n_contrib, n64);
   if (inside) {
     const size_t HW = (size_t)a.S.W * a.S.H;
     const size_t p = (size_t)pb * a.S.W + pc;
     a.out[p] = acc0;
     a.out[HW + p] = acc1;
     a.out[2 * HW + p] = acc2;
-    a.ws.T_final[p] = T;
-    a.ws.n_last[p] = last;
+    a.T_final[p] = T;
+    a.n_last[p] = last;
   }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
+template <int NT>
+__device__ void bwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id, uint32_t& s_maxlast) {
 #pragma clang fp contract(off)
-  constexpr int NT = TW * TH;
-  constexpr int WX = TW / 8;
-  __shared__ float4 s_rec[NT][5];
-  __shared__ uint32_t s_id[NT];
-  __shared__ uint32_t s_maxlast;
-  const int tile = xcd_remap(blockIdx.x, a.n_tiles);
+  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
   const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
@@ -466,7 +457,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
   lidar_dir(a.S, ox, oy, dt);
   lidar_dir(a.S, inside ? pc : ox, inside ? pb : oy, d64);
   const float dpix[3] = {(float)(d64[0] - dt[0]), (float)(d64[1] - dt[1]), (float)(d64[2] - dt[2])};
-  const uint2 rg = a.ws.ranges[a.S.tile_offset + tile];
+  const uint2 rg = a.ranges[a.S.tile_offset + tile];
   const size_t HW = (size_t)a.S.W * a.S.H;
   const size_t p = inside ? (size_t)pb * a.S.W + pc : 0;
   float g[3], O[3];
@@ -475,7 +466,8 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
     g[c] = inside ? a.gout[c * HW + p] : 0.0f;
     O[c] = inside ? a.out_fwd[c * HW + p] : 0.0f;
   }
-  const uint32_t last = inside ? a.ws.n_last[p] : rg.x;
+  const uint32_t last = inside ? a.n_last[p] : rg.x;
+  __syncthreads();
   if (t == 0) s_maxlast = rg.x;
   __syncthreads();
   atomicMax(&s_maxlast, last);
@@ -484,8 +476,8 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
   uint32_t wlast = last;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+  uint32_t n64 = 0;
   float T = 1.0f, A0 = 0.0f, A1 = 0.0f, A2 = 0.0f;
-  const int N = a.n_splats;
   for (uint32_t base = rg.x; base < end; base += NT) {
     __syncthreads();
     const uint32_t k = base + t;
@@ -500,7 +492,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
       if (base + j >= wlast) break;
       const bool active = base + j < last;
       PairEval e;
-      const bool hit = active && eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e);
+      const bool hit = active && eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e, n64);
       float gr[kGradFields];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
@@ -547,7 +539,66 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
         }
         T = T * (1.0f - al);
       }
-      if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.ws.gacc, N, lane);
+      if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.gacc, a.gacc_stride, lane);
+    }
+  }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_blend_fwd(TileArgs a, int n_tiles) {
+  __shared__ float4 s_rec[TW * TH][5];
+  __shared__ uint32_t s_id[TW * TH];
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  if (a.S.kind == GS_SENSOR_PINHOLE)
+    fwd_tile_pinhole<TW * TH>(a, tile, s_rec, s_id);
+  else
+    fwd_tile_lidar<TW * TH>(a, tile, s_rec, s_id);
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_blend_bwd(TileArgs a, int n_tiles) {
+  __shared__ float4 s_rec[TW * TH][5];
+  __shared__ uint32_t s_id[TW * TH];
+  __shared__ uint32_t s_maxlast;
+  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  if (a.S.kind == GS_SENSOR_PINHOLE)
+    bwd_tile_pinhole<TW * TH>(a, tile, s_rec, s_id, s_maxlast);
+  else
+    bwd_tile_lidar<TW * TH>(a, tile, s_rec, s_id, s_maxlast);
+}
+
+// Persistent compositing over every (sensor, tile) of a batched step: each
+// workgroup pops work items (global tile ids, heaviest first) from a queue
+// with one atomic per item until the queue is empty.  256 threads; every
+// sensor's tile shape has 256 rays.
+__device__ inline int sensor_of_tile(const BatchArgs& b, uint32_t gt) {
+  int s = 0;
+  while (s + 1 < b.n_sensors && b.tile_off[s + 1] <= (int)gt) ++s;
+  return s;
+}
+
+template <bool BWD>
+__global__ __launch_bounds__(256) void k_blend_persistent(BatchArgs b) {
+  __shared__ float4 s_rec[256][5];
+  __shared__ uint32_t s_id[256];
+  __shared__ uint32_t s_maxlast;
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= b.n_items) break;
+    const uint32_t gt = b.queue[it];
+    const int s = sensor_of_tile(b, gt);
+    const TileArgs a = b.tiles[s];
+    const int tile = (int)gt - b.tile_off[s];
+    if (a.S.kind == GS_SENSOR_PINHOLE) {
+      if (BWD) bwd_tile_pinhole<256>(a, tile, s_rec, s_id, s_maxlast);
+      else fwd_tile_pinhole<256>(a, tile, s_rec, s_id);
+    } else {
+      if (BWD) bwd_tile_lidar<256>(a, tile, s_rec, s_id, s_maxlast);
+      else fwd_tile_lidar<256>(a, tile, s_rec, s_id);
     }
   }
 }
@@ -556,36 +607,45 @@ __global__ __launch_bounds__(TW* TH) void k_blend_lidar_bwd(BlendArgs a) {
 
 #define GS_TILE_CASES(X) X(16, 16) X(32, 8) X(8, 32) X(16, 8) X(8, 16) X(8, 8) X(32, 16) X(16, 32)
 
-void launch_blend_forward(const BlendArgs& a, hipStream_t st) {
-  if (a.n_tiles == 0) return;
+void launch_blend_forward(const TileArgs& a, int n_tiles, hipStream_t st) {
+  if (n_tiles == 0) return;
   const int tw = a.S.tw, th = a.S.th;
-  const dim3 grid(a.n_tiles);
-#define CASE(W, H)                                                                                  \
-  if (tw == W && th == H) {                                                                         \
-    if (a.S.kind == GS_SENSOR_PINHOLE)                                                              \
-      hipLaunchKernelGGL((k_blend_pinhole<W, H>), grid, dim3(W * H), 0, st, a);                    \
-    else                                                                                            \
-      hipLaunchKernelGGL((k_blend_lidar<W, H>), grid, dim3(W * H), 0, st, a);                      \
-    return;                                                                                         \
+  const dim3 grid(n_tiles);
+#define CASE(W, H)                                                                 \
+  if (tw == W && th == H) {                                                        \
+    hipLaunchKernelGGL((k_blend_fwd<W, H>), grid, dim3(W * H), 0, st, a, n_tiles); \
+    return;                                                                        \
   }
   GS_TILE_CASES(CASE)
 #undef CASE
 }
 
-void launch_blend_backward(const BlendArgs& a, hipStream_t st) {
-  if (a.n_tiles == 0) return;
+void launch_blend_backward(const TileArgs& a, int n_tiles, hipStream_t st) {
+  if (n_tiles == 0) return;
   const int tw = a.S.tw, th = a.S.th;
-  const dim3 grid(a.n_tiles);
-#define CASE(W, H)                                                                                  \
-  if (tw == W && th == H) {                                                                         \
-    if (a.S.kind == GS_SENSOR_PINHOLE)                                                              \
-      hipLaunchKernelGGL((k_blend_pinhole_bwd<W, H>), grid, dim3(W * H), 0, st, a);                \
-    else                                                                                            \
-      hipLaunchKernelGGL((k_blend_lidar_bwd<W, H>), grid, dim3(W * H), 0, st, a);                  \
-    return;                                                                                         \
+  const dim3 grid(n_tiles);
+#define CASE(W, H)                                                                 \
+  if (tw == W && th == H) {                                                        \
+    hipLaunchKernelGGL((k_blend_bwd<W, H>), grid, dim3(W * H), 0, st, a, n_tiles); \
+    return;                                                                        \
   }
   GS_TILE_CASES(CASE)
 #undef CASE
+}
+
+void launch_blend_persistent(const BatchArgs& b, int grid, bool backward, hipStream_t st) {
+  if (b.n_items == 0) return;
+  if (backward)
+    hipLaunchKernelGGL((k_blend_persistent<true>), dim3(grid), dim3(256), 0, st, b);
+  else
+    hipLaunchKernelGGL((k_blend_persistent<false>), dim3(grid), dim3(256), 0, st, b);
+}
+
+int persistent_blocks_per_cu(bool backward) {
+  int n = 0;
+  hipError_t e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<true>, 256, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<false>, 256, 0);
+  return e == hipSuccess ? n : 0;
 }
 
 bool tile_shape_supported(int tw, int th) {

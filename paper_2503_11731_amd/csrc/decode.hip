@@ -239,6 +239,66 @@ __global__ __launch_bounds__(256) void k_decode_fwd(DecodeArgs a) {
   }
 }
 
+// Plain FP32 decode: one thread per anchor, weights widened from bf16, every
+// activation in FP32 (the comparison point for the MFMA decode).
+__global__ __launch_bounds__(128) void k_decode_fwd_valu(DecodeArgs a) {
+  __shared__ float sCam[kMaxGroups][3];
+  if (threadIdx.x < a.n_groups) group_camera(a, threadIdx.x, sCam[threadIdx.x]);
+  __syncthreads();
+  const int ai = blockIdx.x * 128 + threadIdx.x;
+  if (ai >= a.A) return;
+  int g = 0;
+  while (g + 1 < a.n_groups && a.goff[g + 1] <= ai) ++g;
+  float x[kIn];
+  for (int k = 0; k < kFeat; ++k) x[k] = bf2f(a.feat[(size_t)ai * kFeat + k]);
+  const double v0 = (double)a.xyz[ai] - sCam[g][0];
+  const double v1 = (double)a.xyz[a.A + ai] - sCam[g][1];
+  const double v2 = (double)a.xyz[2 * a.A + ai] - sCam[g][2];
+  const double nv = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+  x[kFeat] = (float)(v0 / nv);
+  x[kFeat + 1] = (float)(v1 / nv);
+  x[kFeat + 2] = (float)(v2 / nv);
+  const uint16_t* W1 = a.w1 + (size_t)g * kHidden * kIn;
+  const float* B1 = a.b1 + (size_t)g * kHidden;
+  float h[kHidden];
+  for (int j = 0; j < kHidden; ++j) {
+    float s = B1[j];
+    for (int k = 0; k < kIn; ++k) s = fmaf(bf2f(W1[j * kIn + k]), x[k], s);
+    h[j] = s > 0.f ? s : 0.f;
+  }
+  const int K = a.K, J = a.J, KJ = K * J;
+  const uint16_t* W2 = a.w2 + (size_t)g * KJ * kHidden;
+  const float* B2 = a.b2 + (size_t)g * KJ;
+  const size_t N = (size_t)a.A * K;
+  const float la = a.scaling[ai];
+  for (int k = 0; k < K; ++k) {
+    float y[10];
+    for (int j = 0; j < J; ++j) {
+      const int n = k * J + j;
+      float s = B2[n];
+      for (int q = 0; q < kHidden; ++q) s = fmaf(bf2f(W2[(size_t)n * kHidden + q]), h[q], s);
+      y[j] = s;
+    }
+    const size_t n = (size_t)ai * K + k;
+    a.opacity[n] = sigmoidf(y[0]);
+    int so;
+    if (!a.lidar) {
+      a.rgb[n] = sigmoidf(y[1]);
+      a.rgb[N + n] = sigmoidf(y[2]);
+      a.rgb[2 * N + n] = sigmoidf(y[3]);
+      so = 4;
+    } else {
+      a.intensity[n] = sigmoidf(y[1]);
+      so = 2;
+    }
+    a.scale[n] = la * sigmoidf(y[so]);
+    a.scale[N + n] = la * sigmoidf(y[so + 1]);
+    for (int e = 0; e < 4; ++e) a.quat[e * N + n] = y[so + 2 + e];
+    for (int e = 0; e < 3; ++e)
+      a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   __shared__ float sD[4][16][4];
   __shared__ float sH[4][16][kHidden + 1];
@@ -458,7 +518,11 @@ extern "C" gs_status gs_decode_forward(const gs_anchor_set* anchors, const float
   a.opacity = out->opacity;
   a.rgb = out->rgb;
   a.intensity = out->intensity;
-  if (nb > 0) hipLaunchKernelGGL(k_decode_fwd, dim3(nb), dim3(256), 0, stream, a);
+  if (anchors->flags & GS_DECODE_VALU_FP32) {
+    if (a.A > 0) hipLaunchKernelGGL(k_decode_fwd_valu, dim3((a.A + 127) / 128), dim3(128), 0, stream, a);
+  } else if (nb > 0) {
+    hipLaunchKernelGGL(k_decode_fwd, dim3(nb), dim3(256), 0, stream, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(GS_ERR_HIP, std::string("decode launch: ") + hipGetErrorString(e));
   return set_error(GS_OK, "");

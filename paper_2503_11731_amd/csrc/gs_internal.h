@@ -78,7 +78,7 @@ struct SensorWS {
 };
 
 // status word indices
-enum { kStPairs = 0, kStOverflow = 1, kStVisible = 2, kStFp64 = 3 };
+enum { kStPairs = 0, kStOverflow = 1, kStVisible = 2, kStFp64 = 3, kStEvals = 4 /* u64 */, kStContrib = 6 /* u64 */ };
 
 __device__ inline int group_of(const GroupsK& g, int i) {
   int lo = 0, hi = g.n - 1;
@@ -430,6 +430,24 @@ __device__ inline float wave_sum_last(float v) {
   v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
   v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
   return v;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+  return v;
+}
+
+// Adds the wave's evaluation / contribution counts to the status words.
+__device__ inline void count_pairs(uint32_t* status, uint32_t evals, uint32_t contribs, uint32_t fp64) {
+  evals = wave_sum_u32(evals);
+  contribs = wave_sum_u32(contribs);
+  fp64 = wave_sum_u32(fp64);
+  if (__lane_id() == 0) {
+    if (fp64) atomicAdd(status + kStFp64, fp64);
+    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStEvals), (unsigned long long)evals);
+    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStContrib), (unsigned long long)contribs);
+  }
 }
 
 __device__ inline uint64_t lanemask_lt() {

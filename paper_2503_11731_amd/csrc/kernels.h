@@ -18,19 +18,45 @@ struct PrepArgs {
   GroupsK groups;
   SensorK S;
   OptsK O;
-  SensorWS ws;
+  SensorWS ws;            // per-surfel arrays already offset to this sensor's records
+  uint32_t rec_base;      // record id of surfel 0 (pair values are rec_base + i)
+  size_t gacc_stride;     // plane stride of ws.gacc
 };
 
-struct BlendArgs {
-  SensorK S;
+// Per-sensor data the pair emission needs (record ranges and tile grids).
+struct EmitTable {
+  int n;
+  uint32_t rec_base[GS_MAX_SENSORS + 1];
+  int n_tx[GS_MAX_SENSORS];
+  int tile_off[GS_MAX_SENSORS];
+};
+
+// One sensor's view of the blend state (per-sensor or batched layout).
+struct TileArgs {
+  SensorK S;              // S.tile_offset indexes `ranges`
   OptsK O;
-  SensorWS ws;
-  const uint32_t* pval;   // sorted pair surfel ids
-  int n_tiles;            // tiles of this sensor
-  int n_splats;
-  float* out;             // forward: [C][H][W]
+  const float4* rec;      // records, indexed by the pair value
+  const double* rec64;
+  const double* grz;
+  const uint2* ranges;    // [global tiles]
+  const uint32_t* pval;   // sorted pair record ids
+  float* out;             // forward outputs [C][H][W]
   const float* out_fwd;   // backward: forward outputs
   const float* gout;      // backward: dL/d outputs
+  float* T_final;         // [H*W]
+  uint32_t* n_last;       // [H*W]
+  uint32_t* status;       // counters
+  float* gacc;            // [kGradFields][gacc_stride]
+  size_t gacc_stride;
+};
+
+struct BatchArgs {
+  const TileArgs* tiles;  // device table [n_sensors]
+  int n_sensors;
+  int tile_off[GS_MAX_SENSORS + 1];
+  const uint32_t* queue;  // global tile ids, heaviest first
+  int n_items;
+  uint32_t* counter;      // zeroed before the launch
 };
 
 struct SplatBwdArgs {
@@ -64,14 +90,19 @@ void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uin
                          uint32_t* status, uint32_t cap, hipStream_t st);
 size_t scan_bsum_words(int n);
 void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
-                 const SensorK& S, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st);
+                 const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st);
+// work queue keys: heaviest tiles first
+void launch_queue_keys(const uint2* ranges, int n_tiles, uint32_t* key, uint32_t* val, hipStream_t st);
+void launch_store_tile_args(const TileArgs& a, TileArgs* dst, hipStream_t st);
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st);
 void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipStream_t st);
 
 // blend.hip
-void launch_blend_forward(const BlendArgs& a, hipStream_t st);
-void launch_blend_backward(const BlendArgs& a, hipStream_t st);
+void launch_blend_forward(const TileArgs& a, int n_tiles, hipStream_t st);
+void launch_blend_backward(const TileArgs& a, int n_tiles, hipStream_t st);
+void launch_blend_persistent(const BatchArgs& b, int grid, bool backward, hipStream_t st);
+bool tile_shape_supported(int tw, int th);
 
 // splat_backward.hip
 void launch_splat_backward(const SplatBwdArgs& a, hipStream_t st);

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   Bins b;
   spec_pinhole_bins(f, a.S, a.O, b);
   a.ws.key[0][i] = b.vis ? __float_as_uint(b.key) : kInvalidKey;
-  a.ws.val[0][i] = (uint32_t)i;
+  a.ws.val[0][i] = a.rec_base + (uint32_t)i;
   a.ws.ntiles[i] = b.n_tiles;
   a.ws.visible[i] = b.vis ? 1u : 0u;
   if (!b.touch) return;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
   Bins b;
   spec_lidar_bins(f, su, sv, a.S, a.O, b);
   a.ws.key[0][i] = b.vis ? __float_as_uint(b.key) : kInvalidKey;
-  a.ws.val[0][i] = (uint32_t)i;
+  a.ws.val[0][i] = a.rec_base + (uint32_t)i;
   a.ws.ntiles[i] = b.n_tiles;
   a.ws.visible[i] = b.vis ? 1u : 0u;
   if (!b.touch) return;

@@ -253,31 +253,46 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, const uint32_t* __restrict__ ntiles,
                                               const int4* __restrict__ rect, const uint32_t* __restrict__ offs,
-                                              int n, SensorK S, uint32_t cap, uint32_t* __restrict__ ptile,
+                                              int n, EmitTable E, uint32_t cap, uint32_t* __restrict__ ptile,
                                               uint32_t* __restrict__ pval) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
-  const uint32_t s = val[j];
+  const uint32_t s = val[j];  // record id
   const uint32_t cnt = ntiles[s];
   if (cnt == 0) return;
   uint32_t o = offs[j];
   if (o >= cap) return;
+  int se = 0;
+  while (se + 1 < E.n && E.rec_base[se + 1] <= s) ++se;
+  const int n_tx = E.n_tx[se], toff = E.tile_off[se];
   const int4 r = rect[s];
   const bool wrap = (r.w >> 30) & 1;
   const int ty_hi = r.w & 0x3FFFFFFF;
-  const int ncol = wrap ? (S.n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1);
+  const int ncol = wrap ? (n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1);
   for (int ty = r.z; ty <= ty_hi; ++ty) {
     for (int c = 0; c < ncol; ++c) {
       int tx = r.x + c;
-      if (tx >= S.n_tx) tx -= S.n_tx;
+      if (tx >= n_tx) tx -= n_tx;
       if (o < cap) {
-        ptile[o] = (uint32_t)(S.tile_offset + ty * S.n_tx + tx);
+        ptile[o] = (uint32_t)(toff + ty * n_tx + tx);
         pval[o] = s;
       }
       ++o;
     }
   }
 }
+
+__global__ __launch_bounds__(256) void k_queue_keys(const uint2* __restrict__ ranges, int n_tiles,
+                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint2 r = ranges[t];
+  const uint32_t cost = r.y - r.x;
+  key[t] = 0xFFFFFFu - (cost < 0xFFFFFFu ? cost : 0xFFFFFFu);
+  val[t] = (uint32_t)t;
+}
+
+__global__ void k_store_tile_args(TileArgs a, TileArgs* dst) { *dst = a; }
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ ptile, const uint32_t* __restrict__ count,
                                                 uint32_t cap, uint2* __restrict__ ranges) {
@@ -351,9 +366,18 @@ void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uin
 }
 
 void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
-                 const SensorK& S, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st) {
+                 const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, S, cap, ptile, pval);
+  hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, E, cap, ptile, pval);
+}
+
+void launch_queue_keys(const uint2* ranges, int n_tiles, uint32_t* key, uint32_t* val, hipStream_t st) {
+  if (n_tiles == 0) return;
+  hipLaunchKernelGGL(k_queue_keys, dim3((n_tiles + 255) / 256), dim3(256), 0, st, ranges, n_tiles, key, val);
+}
+
+void launch_store_tile_args(const TileArgs& a, TileArgs* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_store_tile_args, dim3(1), dim3(1), 0, st, a, dst);
 }
 
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
   bool any = false;
 #pragma unroll
   for (int f = 0; f < kGradFields; ++f) {
-    gf[f] = a.ws.gacc[(size_t)f * N + i];
+    gf[f] = a.ws.gacc[(size_t)f * a.gacc_stride + i];
     any = any || gf[f] != 0.0f;
   }
   if (!any) return;

@@ -26,7 +26,7 @@ class Decoder:
     b2 [G,K*J] f32.
     """
 
-    def __init__(self, xyz, scaling, offsets, feat, w1, b1, w2, b2, group_offsets, lidar: bool):
+    def __init__(self, xyz, scaling, offsets, feat, w1, b1, w2, b2, group_offsets, lidar: bool, plain_fp32=False):
         self.lib = L.load()
         self.xyz, self.scaling, self.offsets, self.feat = xyz, scaling, offsets, feat
         self.w1, self.b1, self.w2, self.b2 = w1, b1, w2, b2
@@ -36,9 +36,10 @@ class Decoder:
         self.A = int(xyz.shape[1])
         self.J = 8 if lidar else 10
         self._off = (ctypes.c_int32 * len(self.group_offsets))(*self.group_offsets)
+        self.flags = L.GS_DECODE_VALU_FP32 if plain_fp32 else 0
 
     @classmethod
-    def from_gen(cls, sc, device="cuda", feat_bits=None):
+    def from_gen(cls, sc, device="cuda", feat_bits=None, plain_fp32=False):
         """Build from a gen.scenes.AnchorScene (bf16 features/weights as raw bits)."""
         def bf(bits):
             return torch.from_numpy(np.ascontiguousarray(bits).view(np.int16)).view(torch.bfloat16).to(device)
@@ -54,13 +55,13 @@ class Decoder:
         b2 = torch.stack([t(m["b2"]) for m in sc.mlps])
         fb = sc.feat_bf16 if feat_bits is None else feat_bits
         return cls(t(sc.xyz), t(sc.scaling), t(sc.offsets), bf(fb), w1.contiguous(), b1, w2.contiguous(), b2,
-                   sc.group_offsets, sc.sensor_kind != "pinhole")
+                   sc.group_offsets, sc.sensor_kind != "pinhole", plain_fp32=plain_fp32)
 
     def _struct(self):
         return L.AnchorSet(self.A, self.K, int(self.lidar), len(self.group_offsets) - 1, self._off,
                            self.xyz.data_ptr(), self.scaling.data_ptr(), self.offsets.data_ptr(),
                            self.feat.data_ptr(), self.w1.data_ptr(), self.b1.data_ptr(), self.w2.data_ptr(),
-                           self.b2.data_ptr())
+                           self.b2.data_ptr(), self.flags)
 
     def new_decoded(self):
         n = self.A * self.K

@@ -92,6 +92,7 @@ class Renderer:
         nb = ctypes.c_size_t()
         L.check(self.lib.gs_plan_workspace_size(self.plan, ctypes.byref(nb)))
         self.workspace = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        self.batched = bool(batched)
         assert self.workspace.data_ptr() % 256 == 0
         self.generation = 0
 
@@ -133,6 +134,16 @@ class Renderer:
         self.generation += 1
         return outs
 
+    def capture(self, scenes, sensor_poses, group_poses, outputs):
+        """Capture the forward into a HIP graph on the current (non-default) stream.
+
+        Later forward() calls with the same tensors replay the graph.
+        """
+        optr = (ctypes.c_void_p * len(outputs))(*[o.data_ptr() for o in outputs])
+        sc = self._scene_structs(scenes)
+        L.check(self.lib.gs_plan_capture(self.plan, sc, sensor_poses.data_ptr(), group_poses.data_ptr(), optr,
+                                         self.workspace.data_ptr(), _stream()))
+
     def backward(self, scenes, sensor_poses, group_poses, outputs, grad_outputs, grads=None):
         """Adjoint of forward (uses the workspace state of the last forward).
 
@@ -159,8 +170,18 @@ class Renderer:
         rc = self.lib.gs_query_status(self.plan, self.workspace.data_ptr(), _stream(), ctypes.byref(st))
         n = len(self.sensors)
         out = dict(pairs=list(st.pairs[:n]), overflow=bool(st.overflow), n_visible=list(st.n_visible[:n]),
-                   fp64_pairs=int(st.fp64_pairs), rc=rc)
+                   fp64_pairs=int(st.fp64_pairs), evaluated=int(st.evaluated), composited=int(st.composited), rc=rc)
         return out
+
+    def set_timing(self, max_records: int):
+        """Record HIP events around every stage of the next calls (0 disables)."""
+        L.check(self.lib.gs_plan_set_timing(self.plan, int(max_records)))
+
+    def stage_times(self, reset=True) -> dict:
+        """Summed milliseconds and interval counts per stage since the last reset (syncs)."""
+        t = L.StageTimes()
+        L.check(self.lib.gs_plan_stage_times(self.plan, _stream(), int(reset), ctypes.byref(t)))
+        return {name: (float(t.ms[i]), int(t.launches[i])) for i, name in enumerate(L.STAGES)}
 
     def inspect(self, i: int) -> dict:
         """Views of sensor i's sorted pair list, tile ranges and visibility (tests)."""

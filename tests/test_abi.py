@@ -104,9 +104,9 @@ def test_valid_plan_and_workspace_size_without_gpu():
 def test_decode_rejects_invalid_arguments():
     lib = L.load()
     off = (ctypes.c_int32 * 2)(0, 5)
-    an = L.AnchorSet(5, 0, 0, 1, off, 0, 0, 0, 0, 0, 0, 0, 0)  # k = 0
+    an = L.AnchorSet(5, 0, 0, 1, off, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # k = 0
     assert lib.gs_decode_forward(ctypes.byref(an), None, None, None, None) == L.GS_ERR_INVALID_ARG
-    an = L.AnchorSet(5, 10, 0, 1, off, 0, 0, 0, 0, 0, 0, 0, 0)
+    an = L.AnchorSet(5, 10, 0, 1, off, 0, 0, 0, 0, 0, 0, 0, 0, 0)
     one = ctypes.c_float(0)
     assert lib.gs_decode_forward(ctypes.byref(an), ctypes.addressof(one), ctypes.addressof(one), None,
                                  None) == L.GS_ERR_INVALID_ARG

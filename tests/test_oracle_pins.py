@@ -344,3 +344,15 @@ def test_tile_pairs_vectorised_matches_loop():
     t2, s2 = spec32.tile_pairs_fast(b)
     np.testing.assert_array_equal(t1, t2)
     np.testing.assert_array_equal(s1, s2)
+
+
+def test_grid_sample_matches_full_image():
+    # The strided-grid candidate enumeration (used for bounded CPU samples)
+    # reproduces the full-image result on the sampled rays.
+    sc = _random_scene(13, 120)
+    full = raster.render(sc, SMALL_CAM, raster.make_opts())
+    sub = raster.render(sc, SMALL_CAM, raster.make_opts(), rays=("grid", 3))
+    ids = raster.grid_rays(SMALL_CAM, 3)
+    for ch in ("rgb", "depth", "alpha"):
+        f = full[ch].reshape(full[ch].shape[:-2] + (-1,))
+        np.testing.assert_array_equal(f[..., ids], sub[ch])
