@@ -36,11 +36,27 @@ struct PairEval {
   bool lp_used, clamped;
 };
 
+// Does the surfel's conservative rectangle (packed 16-bit bounds) miss this
+// wave's 8x8 block of rays?  Pairs outside the rectangle are never in the
+// support, so skipping them leaves every result unchanged.
+__device__ __forceinline__ bool misses_block(uint32_t cols, uint32_t rows, int bx, int by) {
+  const int c_lo = cols & 0xFFFF, c_hi = cols >> 16, r_lo = rows & 0xFFFF, r_hi = rows >> 16;
+  return c_hi < bx || c_lo > bx + 7 || r_hi < by || r_lo > by + 7;
+}
+
+// LiDAR columns may wrap (c_lo > c_hi means [c_lo, W) u [0, c_hi]).
+__device__ __forceinline__ bool misses_block_wrap(uint32_t cols, uint32_t rows, int bx, int by) {
+  const int c_lo = cols & 0xFFFF, c_hi = cols >> 16, r_lo = rows & 0xFFFF, r_hi = rows >> 16;
+  if (r_hi < by || r_lo > by + 7) return true;
+  if (c_lo <= c_hi) return c_hi < bx || c_lo > bx + 7;
+  return c_hi < bx && c_lo > bx + 7;
+}
+
 // ----------------------------- camera -----------------------------------
 // LDS record (5 x float4):
 //  [0] pcx_rel, pcy_rel, P00, P01   [1] P10, P11, P20, P21
 //  [2] mu_z, log2 o, c0, c1          [3] c2, n0, n1, n2
-//  [4] flags, o, -, -
+//  [4] flags, o, pixel columns lo|hi<<16, pixel rows lo|hi<<16
 __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint32_t s, float plx, float ply, int ox,
                                              int oy, const TileArgs& a, PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
@@ -107,11 +123,12 @@ __device__ __forceinline__ void stage_pinhole(const TileArgs& a, uint32_t s, int
   const double* r64 = a.rec64 + kRec64 * (size_t)s;
   const float pcx = (float)(r64[0] - (double)ox);
   const float pcy = (float)(r64[1] - (double)oy);
+  const uint2 rect = *reinterpret_cast<const uint2*>(r64 + 3);
   dst[0] = make_float4(pcx, pcy, r0.x, r0.y);
   dst[1] = make_float4(r0.z, r0.w, r1.x, r1.y);
   dst[2] = make_float4(r1.z, r1.w, r2.x, r2.y);
   dst[3] = make_float4(r2.z, r2.w, r3.x, r3.y);
-  dst[4] = make_float4(r3.z, r3.w, 0.0f, 0.0f);
+  dst[4] = make_float4(r3.z, r3.w, __uint_as_float(rect.x), __uint_as_float(rect.y));
 }
 
 template <int NT>
@@ -122,6 +139,7 @@ __device__ void fwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
   const int ox = tx * TW, oy = ty * TH;
+  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
   const int px = ox + lx, py = oy + ly;
   const bool inside = px < a.S.W && py < a.S.H;
   const float plx = (float)lx + 0.5f, ply = (float)ly + 0.5f;
@@ -144,6 +162,7 @@ __device__ void fwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5]
     const int cnt = (int)min((uint32_t)NT, rg.y - base);
     for (int j = 0; j < cnt; ++j) {
       if (__ballot(!done) == 0) break;
+      if (misses_block(__float_as_uint(s_rec[j][4].z), __float_as_uint(s_rec[j][4].w), bx, by)) continue;
       if (done) continue;
       PairEval e;
       ++n_eval;
@@ -198,6 +217,7 @@ __device__ void bwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
   const int ox = tx * TW, oy = ty * TH;
+  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
   const int px = ox + lx, py = oy + ly;
   const bool inside = px < a.S.W && py < a.S.H;
   const float plx = (float)lx + 0.5f, ply = (float)ly + 0.5f;
@@ -238,6 +258,7 @@ __device__ void bwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5]
     const int cnt = (int)min((uint32_t)NT, end - base);
     for (int j = 0; j < cnt; ++j) {
       if (base + j >= wlast) break;
+      if (misses_block(__float_as_uint(s_rec[j][4].z), __float_as_uint(s_rec[j][4].w), bx, by)) continue;
       const bool active = base + j < last;
       PairEval e;
       const bool hit = active && eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e, n64);
@@ -299,7 +320,7 @@ __device__ void bwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5]
 // LDS record (5 x float4):
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
 //  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, intensity, flags
-//  [4] o, -, -, -
+//  [4] o, columns lo|hi<<16 (may wrap), beams lo|hi<<16, -
 __device__ __forceinline__ void stage_lidar(const TileArgs& a, uint32_t s, const double* dtile, float4* dst) {
   const float4* r = a.rec + 4 * (size_t)s;
   const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
@@ -311,7 +332,7 @@ __device__ __forceinline__ void stage_lidar(const TileArgs& a, uint32_t s, const
   dst[1] = make_float4(r0.y, r0.z, r0.w, r1.x);
   dst[2] = make_float4(r1.y, r1.z, r1.w, r2.x);
   dst[3] = make_float4(r2.y, r2.z, r2.w, r3.x);
-  dst[4] = make_float4(r3.y, 0.0f, 0.0f, 0.0f);
+  dst[4] = make_float4(r3.y, r3.z, r3.w, 0.0f);
 }
 
 __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix,
@@ -391,6 +412,7 @@ __device__ void fwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
   const int ox = tx * TW, oy = ty * TH;
+  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
   const int pc = ox + lx, pb = oy + ly;
   const bool inside = pc < a.S.W && pb < a.S.H;
   double dt[3], d64[3];
@@ -413,6 +435,7 @@ __device__ void fwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], 
     const int cnt = (int)min((uint32_t)NT, rg.y - base);
     for (int j = 0; j < cnt; ++j) {
       if (__ballot(!done) == 0) break;
+      if (misses_block_wrap(__float_as_uint(s_rec[j][4].y), __float_as_uint(s_rec[j][4].z), bx, by)) continue;
       if (done) continue;
       PairEval e;
       ++n_eval;
@@ -451,6 +474,7 @@ __device__ void bwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
   const int ox = tx * TW, oy = ty * TH;
+  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
   const int pc = ox + lx, pb = oy + ly;
   const bool inside = pc < a.S.W && pb < a.S.H;
   double dt[3], d64[3];
@@ -490,6 +514,7 @@ __device__ void bwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], 
     const int cnt = (int)min((uint32_t)NT, end - base);
     for (int j = 0; j < cnt; ++j) {
       if (base + j >= wlast) break;
+      if (misses_block_wrap(__float_as_uint(s_rec[j][4].y), __float_as_uint(s_rec[j][4].z), bx, by)) continue;
       const bool active = base + j < last;
       PairEval e;
       const bool hit = active && eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e, n64);
@@ -548,7 +573,7 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_blend_fwd(TileArgs a, int n_tiles) {
   __shared__ float4 s_rec[TW * TH][5];
   __shared__ uint32_t s_id[TW * TH];
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const int tile = blockIdx.x;
   if (a.S.kind == GS_SENSOR_PINHOLE)
     fwd_tile_pinhole<TW * TH>(a, tile, s_rec, s_id);
   else
@@ -560,7 +585,7 @@ __global__ __launch_bounds__(TW* TH) void k_blend_bwd(TileArgs a, int n_tiles) {
   __shared__ float4 s_rec[TW * TH][5];
   __shared__ uint32_t s_id[TW * TH];
   __shared__ uint32_t s_maxlast;
-  const int tile = xcd_remap(blockIdx.x, n_tiles);
+  const int tile = blockIdx.x;
   if (a.S.kind == GS_SENSOR_PINHOLE)
     bwd_tile_pinhole<TW * TH>(a, tile, s_rec, s_id, s_maxlast);
   else

@@ -158,7 +158,10 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   r64[0] = pcx;
   r64[1] = pcy;
   r64[2] = muz;
-  r64[3] = 0.0;
+  // conservative pixel rectangle (columns, rows), 16 bits per bound
+  uint32_t* rr = reinterpret_cast<uint32_t*>(r64 + 3);
+  rr[0] = (uint32_t)b.i_lo | ((uint32_t)b.i_hi << 16);
+  rr[1] = (uint32_t)b.j_lo | ((uint32_t)b.j_hi << 16);
   if (graze) {
     double* gz = a.ws.grz + kGrz * (size_t)i;
     for (int k = 0; k < 6; ++k) gz[k] = Pm[k];
@@ -215,7 +218,9 @@ __global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
   r[0] = make_float4((float)Q[0], (float)Q[1], (float)Q[2], (float)Q[3]);
   r[1] = make_float4((float)Q[4], (float)Q[5], (float)Q[6], (float)Q[7]);
   r[2] = make_float4((float)Q[8], (float)rn, log2o, inten);
-  r[3] = make_float4(__uint_as_float(flags), o, 0.0f, 0.0f);
+  // conservative beam/column rectangle (columns may wrap), 16 bits per bound
+  r[3] = make_float4(__uint_as_float(flags), o, __uint_as_float((uint32_t)b.i_lo | ((uint32_t)b.i_hi << 16)),
+                     __uint_as_float((uint32_t)b.j_lo | ((uint32_t)b.j_hi << 16)));
   double* r64 = a.ws.rec64 + kRec64 * (size_t)i;
   r64[0] = mh[0];
   r64[1] = mh[1];
