@@ -148,9 +148,16 @@ typedef struct gs_plan_desc {
   int32_t batched;               /* 1: all sensors of the plan form one step:
                                     one record space, one depth sort, one pair
                                     list over a global tile space and one
-                                    persistent compositing launch over a
-                                    heaviest-first (sensor, tile) queue; every
-                                    tile shape must then hold 256 rays         */
+                                    persistent compositing launch for all of
+                                    them; every tile shape must then hold 256
+                                    rays                                       */
+  int32_t segment_pairs;         /* compositing work-item size L: a tile whose
+                                    depth-ordered list holds more than L pairs
+                                    is composited as ceil(len/L) segments in
+                                    parallel and merged front to back (same
+                                    results up to FP32 rounding order).
+                                    0 = default (1024), < 0 = never split,
+                                    else 32..32768                             */
 } gs_plan_desc;
 
 typedef struct gs_plan gs_plan; /* opaque, owned by the library */
@@ -167,8 +174,12 @@ typedef struct gs_run_status {
   int32_t overflow;               /* 1 if any sensor exceeded pair_capacity  */
   int32_t n_visible[GS_MAX_SENSORS];
   int64_t fp64_pairs;             /* pairs re-solved in FP64 (grazing rays)  */
-  int64_t evaluated;              /* ray-surfel pairs evaluated by the forward blend */
+  int64_t evaluated;              /* ray-surfel pairs the forward must evaluate: per
+                                     ray, the pairs of its tile list whose pixel
+                                     rectangle holds the ray, up to its stop      */
   int64_t composited;             /* ray-surfel pairs that contributed             */
+  int64_t work_items;             /* compositing work items (tiles + extra segments) */
+  int64_t segments;               /* segments of split tiles                       */
 } gs_run_status;
 
 /* Pipeline stages, for per-stage timing. */

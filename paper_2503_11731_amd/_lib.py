@@ -49,12 +49,13 @@ class SceneGrads(ctypes.Structure):
 class PlanDesc(ctypes.Structure):
     _fields_ = [("n_scenes", c_int32), ("scenes", POINTER(SceneDesc)), ("n_sensors", c_int32),
                 ("sensors", POINTER(SensorDesc)), ("opts", RenderOpts), ("pair_capacity", c_int64),
-                ("batched", c_int32)]
+                ("batched", c_int32), ("segment_pairs", c_int32)]
 
 
 class RunStatus(ctypes.Structure):
     _fields_ = [("pairs", c_int64 * GS_MAX_SENSORS), ("overflow", c_int32), ("n_visible", c_int32 * GS_MAX_SENSORS),
-                ("fp64_pairs", c_int64), ("evaluated", c_int64), ("composited", c_int64)]
+                ("fp64_pairs", c_int64), ("evaluated", c_int64), ("composited", c_int64),
+                ("work_items", c_int64), ("segments", c_int64)]
 
 
 STAGES = ("preprocess", "depth_sort", "emit", "tile_sort", "ranges", "blend", "blend_bwd", "splat_bwd")

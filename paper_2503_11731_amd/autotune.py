@@ -1,0 +1,162 @@
+"""Tile-shape and segment-length autotuner for the compositing queue.
+
+The best tile shape depends on the sensor: a 1080p camera looking down a road
+corridor has a few horizon tiles with 100x the median list, a 128 x 1800
+LiDAR range image has long thin features along the azimuth.  The segment
+length L trades the critical path of the heaviest tile (long L) against the
+extra partial-state traffic and re-evaluation of split tiles (short L).
+
+`autotune` times the forward render of every candidate (tile shape x L) on a
+calibration scene, one sensor at a time, and picks per sensor the fastest
+tile shape and per plan the L with the smallest summed time.  Results are
+cached by (GPU architecture, sensor kind, W x H, surfel-count bucket) in a
+JSON file, so that later plans for the same class of sensor skip the timing.
+Batched plans need 256-ray tiles, so only those shapes are tried for them.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+from . import render as R
+
+TILES_ANY = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (8, 32)]
+TILES_256 = [(16, 16), (32, 8), (8, 32)]
+SEGMENTS = [256, 512, 1024, 2048]
+
+
+def default_cache_path() -> str:
+    return os.environ.get("GS2D_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "gs2d", "autotune.json"))
+
+
+def n_bucket(n: int) -> int:
+    """Power of two nearest to n (in log scale)."""
+    return 1 << max(0, int(round(math.log2(max(n, 1)))))
+
+
+def cache_key(arch: str, kind: str, width: int, height: int, n: int, batched: bool) -> str:
+    return f"{arch}|{kind}|{width}x{height}|n{n_bucket(n)}|{'b' if batched else 's'}"
+
+
+@dataclass
+class TuneResult:
+    tiles: list                       # per sensor (tw, th)
+    segment_pairs: int
+    timings: dict = field(default_factory=dict)  # key -> {"tile,seg": ms}
+    from_cache: list = field(default_factory=list)
+
+
+class TuneCache:
+    """JSON map cache_key -> {"ms": {"tw x th / L": ms}} (all candidates kept)."""
+
+    def __init__(self, path: str | None):
+        self.path = path
+        self.data = {}
+        if path and os.path.exists(path):
+            try:
+                with open(path) as f:
+                    self.data = json.load(f)
+            except (OSError, ValueError):
+                self.data = {}
+
+    def get(self, key):
+        return self.data.get(key)
+
+    def put(self, key, value):
+        self.data[key] = value
+
+    def save(self):
+        if not self.path:
+            return
+        os.makedirs(os.path.dirname(self.path) or ".", exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def _fmt(tile, seg):
+    return f"{tile[0]}x{tile[1]}/{seg}"
+
+
+def _parse(s):
+    t, seg = s.split("/")
+    tw, th = t.split("x")
+    return (int(tw), int(th)), int(seg)
+
+
+def _time_forward(shape, scene, sensor, pose, group_poses, tile, seg, opts, pair_capacity, steps, warmup, device):
+    s = dict(sensor)
+    s["scene"] = 0
+    s["tile"] = tile
+    r = R.Renderer([shape], [s], opts=opts, pair_capacity=pair_capacity, device=device, segment_pairs=seg)
+    outs = r.new_outputs()
+    sp = pose.reshape(1, 12).contiguous()
+    for _ in range(warmup):
+        r.forward([scene], sp, group_poses, outputs=outs)
+    if r.status()["overflow"]:
+        raise RuntimeError("pair capacity overflow while autotuning")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        r.forward([scene], sp, group_poses, outputs=outs)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def autotune(shapes, scenes, sensors, sensor_poses, group_poses_per_sensor, *, batched=False, opts=None,
+             tiles=None, segments=None, pair_capacity=0, steps=5, warmup=2, cache_path="default",
+             device="cuda") -> TuneResult:
+    """Choose tile shapes (per sensor) and the segment length (per plan).
+
+    shapes / scenes: per sensor, the SceneShape and the scene tensors it renders;
+    sensor_poses: [S, 12] tensor; group_poses_per_sensor: list of [G, 12]
+    tensors (the groups of each sensor's scene).  Timing runs use one
+    single-sensor plan per candidate on the caller's current stream.
+    """
+    cands = tiles or (TILES_256 if batched else TILES_ANY)
+    if batched:
+        cands = [t for t in cands if t[0] * t[1] == 256]
+    segs = segments or SEGMENTS
+    path = default_cache_path() if cache_path == "default" else cache_path
+    cache = TuneCache(path)
+    arch = torch.cuda.get_device_properties(torch.device(device)).gcnArchName.split(":")[0]
+    per_sensor = []
+    from_cache = []
+    timings = {}
+    for i, s in enumerate(sensors):
+        key = cache_key(arch, s["kind"], s["width"], s["height"], shapes[i].n_splats, batched)
+        hit = cache.get(key)
+        wanted = {_fmt(t, g) for t in cands for g in segs}
+        if hit and wanted.issubset(hit["ms"].keys()):
+            ms = {k: v for k, v in hit["ms"].items() if k in wanted}
+            from_cache.append(True)
+        else:
+            ms = {}
+            for t in cands:
+                for g in segs:
+                    ms[_fmt(t, g)] = _time_forward(shapes[i], scenes[i], s, sensor_poses[i], group_poses_per_sensor[i],
+                                                   t, g, opts, pair_capacity, steps, warmup, device)
+            merged = dict(hit["ms"]) if hit else {}
+            merged.update(ms)
+            cache.put(key, {"ms": merged})
+            from_cache.append(False)
+        timings[key] = ms
+        per_sensor.append(ms)
+    cache.save()
+    # plan-wide segment length: smallest sum over sensors of each sensor's best tile at that L
+    best_seg, best_total = None, math.inf
+    for g in segs:
+        total = sum(min(ms[_fmt(t, g)] for t in cands) for ms in per_sensor)
+        if total < best_total:
+            best_seg, best_total = g, total
+    chosen = []
+    for ms in per_sensor:
+        chosen.append(min(cands, key=lambda t: ms[_fmt(t, best_seg)]))
+    return TuneResult(tiles=chosen, segment_pairs=best_seg, timings=timings, from_cache=from_cache)

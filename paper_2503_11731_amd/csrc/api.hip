@@ -9,8 +9,11 @@
 //    record space (record id = sensor's record base + surfel index), one depth
 //    sort orders all of them, one emission and one stable tile sort build the
 //    pair list over a global tile-id space (sensor tile offset + tile), and
-//    one persistent compositing launch drains a heaviest-first work queue of
-//    (sensor, tile) items.  A whole step can be captured into one HIP graph.
+//    one persistent compositing launch serves every sensor.  A whole step can
+//    be captured into one HIP graph.
+// Either way compositing drains a heaviest-first queue of (tile, segment)
+// work items: tile lists longer than the segment length are split and merged
+// (see blend.hip).
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,10 +24,6 @@
 #include "kernels.h"
 
 using namespace gs;
-
-namespace gs {
-int persistent_blocks_per_cu(bool backward);
-}
 
 namespace {
 
@@ -62,14 +61,28 @@ struct RecordArrays {
   size_t o_rec = 0, o_rec64 = 0, o_grz = 0, o_rect = 0, o_ntiles = 0, o_visible = 0, o_key0 = 0, o_key1 = 0,
          o_val0 = 0, o_val1 = 0, o_offs = 0, o_bsum = 0, o_hist = 0, o_ptile0 = 0, o_ptile1 = 0, o_pval0 = 0,
          o_pval1 = 0, o_ranges = 0, o_status = 0, o_gacc = 0;
+  // compositing work queue
+  size_t o_pslot = 0, o_arrive = 0, o_qhdr = 0, o_sbsum = 0, o_qkey0 = 0, o_qkey1 = 0, o_qval0 = 0, o_qval1 = 0,
+         o_items = 0, o_part = 0, part_stride = 0, o_flag = 0, o_walk = 0;
   uint32_t n_rec = 0, cap = 0;
-  int n_tiles = 0, tile_bits = 0;
-  int pair_buf = 0;  // buffer holding the sorted pairs
+  uint32_t seg_len = 0, cap_items = 0, pslot_cap = 0;
+  int n_tiles = 0, tile_bits = 0, rays = 256, key_bits = 16;
+  int pair_buf = 0;   // buffer holding the sorted pairs
+  int queue_buf = 0;  // buffer holding the sorted work items
+  int grid_fwd = 0, grid_bwd = 0;
+  int kinds = 0;  // sensor kinds served (bit 0 camera, bit 1 LiDAR)
 
-  void layout(Layout& L, uint32_t n, uint32_t cap_, int tiles) {
+  void layout(Layout& L, uint32_t n, uint32_t cap_, int tiles, int rays_, uint32_t seg) {
     n_rec = n;
     cap = cap_;
     n_tiles = tiles;
+    rays = rays_;
+    seg_len = seg;
+    const bool split = seg != 0xFFFFFFFFu;
+    cap_items = (uint32_t)tiles + (split ? cap_ / seg : 0u) + 1u;
+    pslot_cap = split ? 2u * (cap_ / seg) + 2u : 0u;
+    key_bits = seg <= 0xFFFFu ? 16 : 24;
+    queue_buf = (key_bits / 8) % 2;
     tile_bits = 0;
     while ((1 << tile_bits) < tiles) ++tile_bits;
     pair_buf = ((tile_bits + 7) / 8) % 2;
@@ -90,8 +103,10 @@ struct RecordArrays {
     size_t hw = radix_hist_words(cap);
     const size_t hw2 = radix_hist_words(n);
     const size_t hw3 = radix_hist_words((uint32_t)tiles);
+    const size_t hw4 = radix_hist_words(cap_items);
     hw = hw > hw2 ? hw : hw2;
     hw = hw > hw3 ? hw : hw3;
+    hw = hw > hw4 ? hw : hw4;
     o_hist = L.take(hw * 4);
     o_ptile0 = L.take((size_t)cap * 4);
     o_ptile1 = L.take((size_t)cap * 4);
@@ -99,6 +114,19 @@ struct RecordArrays {
     o_pval1 = L.take((size_t)cap * 4);
     o_ranges = L.take((size_t)tiles * 8);
     o_gacc = L.take(N * 4 * kGradFields);
+    o_pslot = L.take((size_t)tiles * 4);
+    o_arrive = L.take((size_t)tiles * 4);
+    o_qhdr = L.take(256);
+    o_sbsum = L.take(seg_bsum_words(tiles) * 4);
+    o_qkey0 = L.take((size_t)cap_items * 4);
+    o_qkey1 = L.take((size_t)cap_items * 4);
+    o_qval0 = L.take((size_t)cap_items * 4);
+    o_qval1 = L.take((size_t)cap_items * 4);
+    o_items = L.take((size_t)cap_items * 8);
+    part_stride = (size_t)pslot_cap * (size_t)rays;
+    o_part = L.take(11 * part_stride * 4);
+    o_flag = L.take((size_t)pslot_cap * 4);
+    o_walk = L.take((size_t)pslot_cap * 8);
   }
 };
 
@@ -133,10 +161,8 @@ struct gs_plan {
   // batched record space
   size_t gbase = 0;
   RecordArrays G;
-  size_t o_qkey0 = 0, o_qkey1 = 0, o_qval0 = 0, o_qval1 = 0, o_tiles = 0, o_counter = 0;
-  int queue_buf = 0;
-  int persistent_grid = 0;
   int tile_off[GS_MAX_SENSORS + 1] = {0};
+  float T_accept = 0.0f;
   // stage timing
   struct Interval {
     int stage;
@@ -330,16 +356,64 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
   stage_end(p, st, GS_STAGE_RANGES, ev);
 }
 
-BatchArgs batch_args(gs_plan* p, void* workspace) {
-  BatchArgs b;
-  memset(&b, 0, sizeof(b));
-  b.tiles = at<TileArgs>(workspace, p->o_tiles);
-  b.n_sensors = (int)p->sensors.size();
-  for (int i = 0; i <= b.n_sensors; ++i) b.tile_off[i] = p->tile_off[i];
-  b.queue = at<uint32_t>(workspace, p->queue_buf ? p->o_qval1 : p->o_qval0);
-  b.n_items = p->G.n_tiles;
-  b.counter = at<uint32_t>(workspace, p->o_counter);
-  return b;
+// Work items of one record space: segment counts, scans, keys, sort.
+void build_queue(gs_plan* p, RecordArrays& R, size_t rbase, void* workspace, hipStream_t st) {
+  char* b = static_cast<char*>(workspace) + rbase;
+  SegScanArgs a;
+  memset(&a, 0, sizeof(a));
+  a.ranges = reinterpret_cast<const uint2*>(b + R.o_ranges);
+  a.n_tiles = R.n_tiles;
+  a.seg_len = R.seg_len;
+  a.key_bits = R.key_bits;
+  a.bsum = reinterpret_cast<uint2*>(b + R.o_sbsum);
+  a.hdr = reinterpret_cast<uint32_t*>(b + R.o_qhdr);
+  a.pslot_base = reinterpret_cast<uint32_t*>(b + R.o_pslot);
+  a.arrive = reinterpret_cast<uint32_t*>(b + R.o_arrive);
+  a.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);
+  a.key = reinterpret_cast<uint32_t*>(b + R.o_qkey0);
+  a.val = reinterpret_cast<uint32_t*>(b + R.o_qval0);
+  a.items = reinterpret_cast<uint2*>(b + R.o_items);
+  a.cap_items = R.cap_items;
+  a.pslot_cap = R.pslot_cap;
+  a.status = reinterpret_cast<uint32_t*>(b + R.o_status);
+  launch_build_items(a, st);
+  uint32_t* qk[2] = {reinterpret_cast<uint32_t*>(b + R.o_qkey0), reinterpret_cast<uint32_t*>(b + R.o_qkey1)};
+  uint32_t* qv[2] = {reinterpret_cast<uint32_t*>(b + R.o_qval0), reinterpret_cast<uint32_t*>(b + R.o_qval1)};
+  (void)radix_sort(qk, qv, a.hdr, 0, R.cap_items, R.key_bits, reinterpret_cast<uint32_t*>(b + R.o_hist), st);
+}
+
+// Queue view over sensors [s0, s1) sharing record space R at byte rbase;
+// out / out_fwd / gout hold the per-sensor output pointers of this call.
+QueueArgs queue_args(const gs_plan* p, const RecordArrays& R, size_t rbase, int s0, int s1, void* workspace,
+                     float* const* out, const float* const* out_fwd, const float* const* gout) {
+  char* b = static_cast<char*>(workspace) + rbase;
+  QueueArgs q;
+  memset(&q, 0, sizeof(q));
+  for (int i = s0; i < s1; ++i) {
+    TileArgs t = tile_args(p, p->sensors[i], workspace);
+    if (out) t.out = out[i];
+    if (out_fwd) t.out_fwd = out_fwd[i];
+    if (gout) t.gout = gout[i];
+    q.tiles[i - s0] = t;
+  }
+  q.n_sensors = s1 - s0;
+  for (int i = 0; i <= q.n_sensors; ++i) q.tile_off[i] = p->batched ? p->tile_off[s0 + i] : (i ? R.n_tiles : 0);
+  q.queue = reinterpret_cast<const uint32_t*>(b + (R.queue_buf ? R.o_qval1 : R.o_qval0));
+  q.items = reinterpret_cast<const uint2*>(b + R.o_items);
+  q.n_items = reinterpret_cast<const uint32_t*>(b + R.o_qhdr);
+  q.hdr = reinterpret_cast<uint32_t*>(b + R.o_qhdr);
+  q.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);
+  q.walk = reinterpret_cast<uint2*>(b + R.o_walk);
+  q.cap_items = R.cap_items;
+  q.counter = reinterpret_cast<uint32_t*>(b + R.o_qhdr) + 2;
+  q.arrive = reinterpret_cast<uint32_t*>(b + R.o_arrive);
+  q.pslot_base = reinterpret_cast<const uint32_t*>(b + R.o_pslot);
+  q.part = reinterpret_cast<float*>(b + R.o_part);
+  q.part_stride = R.part_stride;
+  q.pslot_cap = R.pslot_cap;
+  q.seg_len = R.seg_len;
+  q.T_accept = p->T_accept;
+  return q;
 }
 
 void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_poses, const float* group_poses,
@@ -356,10 +430,11 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, st);
       stage_end(p, st, GS_STAGE_PREPROCESS, ev);
       sort_and_bin(p, s.R, s.base, std::vector<int>{(int)si}, workspace, st);
-      TileArgs t = tile_args(p, s, workspace);
-      t.out = outputs[si];
       ev = stage_begin(p, st);
-      launch_blend_forward(t, s.n_tiles, st);
+      build_queue(p, s.R, s.base, workspace, st);
+      QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, outputs, nullptr, nullptr);
+      launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, st);
+      if (s.R.pslot_cap) launch_blend_finish(q, s.R.rays, s.R.kinds, s.R.grid_fwd, st);
       stage_end(p, st, GS_STAGE_BLEND, ev);
     }
     return;
@@ -382,20 +457,12 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   std::vector<int> all(p->sensors.size());
   for (size_t i = 0; i < all.size(); ++i) all[i] = (int)i;
   sort_and_bin(p, p->G, p->gbase, all, workspace, st);
+  (void)g;
   ev = stage_begin(p, st);
-  uint32_t* qk[2] = {at<uint32_t>(workspace, p->o_qkey0), at<uint32_t>(workspace, p->o_qkey1)};
-  uint32_t* qv[2] = {at<uint32_t>(workspace, p->o_qval0), at<uint32_t>(workspace, p->o_qval1)};
-  launch_queue_keys(g.ranges, p->G.n_tiles, qk[0], qv[0], st);
-  p->queue_buf = radix_sort(qk, qv, nullptr, (uint32_t)p->G.n_tiles, (uint32_t)p->G.n_tiles, 24, g.hist, st);
-  TileArgs* table = at<TileArgs>(workspace, p->o_tiles);
-  for (size_t si = 0; si < p->sensors.size(); ++si) {
-    TileArgs t = tile_args(p, p->sensors[si], workspace);
-    t.out = outputs[si];
-    launch_store_tile_args(t, table + si, st);
-  }
-  BatchArgs b = batch_args(p, workspace);
-  launch_fill_u32(b.counter, 0u, 1, st);
-  launch_blend_persistent(b, p->persistent_grid, false, st);
+  build_queue(p, p->G, p->gbase, workspace, st);
+  QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, outputs, nullptr, nullptr);
+  launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, st);
+  if (p->G.pslot_cap) launch_blend_finish(q, p->G.rays, p->G.kinds, p->G.grid_fwd, st);
   stage_end(p, st, GS_STAGE_BLEND, ev);
 }
 
@@ -411,7 +478,7 @@ gs_status set_error(gs_status s, const std::string& msg) {
 
 extern "C" {
 
-const char* gs_version(void) { return "gs2d 0.2 (gfx950)"; }
+const char* gs_version(void) { return "gs2d 0.3 (gfx950)"; }
 
 const char* gs_status_string(gs_status s) {
   switch (s) {
@@ -467,6 +534,28 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
   p->O.bg0 = o.bg[0];
   p->O.bg1 = o.bg[1];
   p->O.bg2 = o.bg[2];
+  // segment length of the compositing queue: 0 = default, < 0 = never split
+  uint32_t seg_len = 1024u;
+  if (desc->segment_pairs < 0) {
+    seg_len = 0xFFFFFFFFu;
+  } else if (desc->segment_pairs > 0) {
+    if (desc->segment_pairs < 32 || desc->segment_pairs > 32768) {
+      delete p;
+      return fail(GS_ERR_INVALID_ARG, "segment_pairs must be 0, negative, or in [32, 32768]");
+    }
+    seg_len = (uint32_t)desc->segment_pairs;
+  }
+  // A split segment is accepted whole by the merge while T * T_seg >= T_accept;
+  // the margin covers the relative rounding of products of up to L factors.
+  p->T_accept = o.T_min * (1.0f + (float)(seg_len > 65536u ? 65536u : seg_len) * 0x1p-22f);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus <= 0)
+    cus = 256;
+  auto grid_for = [&](int rays, int kinds, bool bwd) {
+    const int per = blend_blocks_per_cu(rays, kinds, bwd);
+    return cus * (per > 0 ? per : 2);
+  };
+  int all_kinds = 0;
   int pose_base = 0;
   for (int i = 0; i < desc->n_scenes; ++i) {
     const gs_scene_desc& d = desc->scenes[i];
@@ -560,11 +649,7 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
         gs_plan_destroy(p);
         return fail(GS_ERR_HIP, std::string("LiDAR tables: ") + hipGetErrorString(e));
       }
-      K.el = s.d_tabs;
-      K.cos_el = s.d_tabs + d.height;
-      K.sin_el = s.d_tabs + 2 * d.height;
-      K.cos_az = s.d_tabs + 3 * d.height;
-      K.sin_az = s.d_tabs + 3 * d.height + d.width;
+      K.tab = s.d_tabs;
     } else {
       gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": unknown kind");
@@ -579,7 +664,7 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     K.n_ty = (K.H + K.th - 1) / K.th;
     s.n_tiles = K.n_tx * K.n_ty;
     int64_t cap = desc->pair_capacity > 0 ? desc->pair_capacity : 16ll * N + 4096;
-    if (cap > 0x7FFFFFFFll) cap = 0x7FFFFFFFll;
+    if (cap > 0x7FFFFFFEll) cap = 0x7FFFFFFEll;
     // per-sensor region
     Layout R;
     const size_t HW = (size_t)K.W * K.H;
@@ -593,8 +678,12 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
       p->tile_off[si] = total_tiles;
     } else {
       K.tile_offset = 0;
-      s.R.layout(R, (uint32_t)N, (uint32_t)cap, s.n_tiles);
+      s.R.layout(R, (uint32_t)N, (uint32_t)cap, s.n_tiles, K.tw * K.th, seg_len);
+      s.R.kinds = K.kind == GS_SENSOR_PINHOLE ? 1 : 2;
+      s.R.grid_fwd = grid_for(K.tw * K.th, s.R.kinds, false);
+      s.R.grid_bwd = grid_for(K.tw * K.th, s.R.kinds, true);
     }
+    all_kinds |= K.kind == GS_SENSOR_PINHOLE ? 1 : 2;
     total_rec += (uint64_t)N;
     total_cap += (uint64_t)cap;
     total_tiles += s.n_tiles;
@@ -606,28 +695,14 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
       gs_plan_destroy(p);
       return fail(GS_ERR_UNSUPPORTED, "batched plan exceeds 2^31 surfel records");
     }
-    if (total_cap > 0x7FFFFFFFull) total_cap = 0x7FFFFFFFull;
+    if (total_cap > 0x7FFFFFFEull) total_cap = 0x7FFFFFFEull;
     p->tile_off[desc->n_sensors] = total_tiles;
     Layout R;
-    p->G.layout(R, (uint32_t)total_rec, (uint32_t)total_cap, total_tiles);
-    p->o_qkey0 = R.take((size_t)total_tiles * 4);
-    p->o_qkey1 = R.take((size_t)total_tiles * 4);
-    p->o_qval0 = R.take((size_t)total_tiles * 4);
-    p->o_qval1 = R.take((size_t)total_tiles * 4);
-    p->o_tiles = R.take(sizeof(TileArgs) * GS_MAX_SENSORS);
-    p->o_counter = R.take(256);
+    p->G.layout(R, (uint32_t)total_rec, (uint32_t)total_cap, total_tiles, 256, seg_len);
+    p->G.kinds = all_kinds;
+    p->G.grid_fwd = grid_for(256, all_kinds, false);
+    p->G.grid_bwd = grid_for(256, all_kinds, true);
     p->gbase = L.take(R.off);
-    p->o_qkey0 += p->gbase;
-    p->o_qkey1 += p->gbase;
-    p->o_qval0 += p->gbase;
-    p->o_qval1 += p->gbase;
-    p->o_tiles += p->gbase;
-    p->o_counter += p->gbase;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus <= 0)
-      cus = 256;
-    const int per = persistent_blocks_per_cu(false);
-    p->persistent_grid = cus * (per > 0 ? per : 4);
   }
   p->ws_bytes = L.off;
   *out = p;
@@ -753,16 +828,10 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
     SensorWS g = record_ws(p->G, workspace, p->gbase, 0);
     hipEvent_t ev = stage_begin(p, st);
     launch_fill_f32(g.gacc, 0.0f, (size_t)p->G.n_rec * kGradFields, st);
-    TileArgs* table = at<TileArgs>(workspace, p->o_tiles);
-    for (size_t si = 0; si < p->sensors.size(); ++si) {
-      TileArgs t = tile_args(p, p->sensors[si], workspace);
-      t.out_fwd = outputs[si];
-      t.gout = grad_outputs[si];
-      launch_store_tile_args(t, table + si, st);
-    }
-    BatchArgs b = batch_args(p, workspace);
-    launch_fill_u32(b.counter, 0u, 1, st);
-    launch_blend_persistent(b, p->persistent_grid, true, st);
+    QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, nullptr, outputs,
+                             grad_outputs);
+    launch_fill_u32(q.counter, 0u, 1, st);
+    launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_bwd, true, st);
     stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
   }
   for (size_t si = 0; si < p->sensors.size(); ++si) {
@@ -772,10 +841,9 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
       const int N = p->scenes[s.scene].desc.n_splats;
       hipEvent_t ev = stage_begin(p, st);
       launch_fill_f32(ws.gacc, 0.0f, (size_t)N * kGradFields, st);
-      TileArgs t = tile_args(p, s, workspace);
-      t.out_fwd = outputs[si];
-      t.gout = grad_outputs[si];
-      launch_blend_backward(t, s.n_tiles, st);
+      QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, nullptr, outputs, grad_outputs);
+      launch_fill_u32(q.counter, 0u, 1, st);
+      launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_bwd, true, st);
       stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
     }
     SplatBwdArgs sb;
@@ -805,6 +873,15 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   auto read = [&](size_t off, uint32_t* w) {
     return hipMemcpy(w, static_cast<const char*>(workspace) + off, 16 * 4, hipMemcpyDeviceToHost);
   };
+  auto read_queue = [&](const RecordArrays& R, size_t base) -> hipError_t {
+    uint32_t h[16];
+    hipError_t e = read(base + R.o_qhdr, h);
+    if (e == hipSuccess) {
+      out->work_items += h[0];
+      out->segments += h[1];
+    }
+    return e;
+  };
   if (p->batched) {
     uint32_t w[16];
     GS_HIP_TRY(read(p->gbase + p->G.o_status, w));
@@ -813,6 +890,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
     out->evaluated = (int64_t)w[kStEvals] | ((int64_t)w[kStEvals + 1] << 32);
     out->composited = (int64_t)w[kStContrib] | ((int64_t)w[kStContrib + 1] << 32);
     over = w[kStOverflow] != 0;
+    GS_HIP_TRY(read_queue(p->G, p->gbase));
     for (size_t si = 0; si < p->sensors.size(); ++si) {
       uint32_t ws[16];
       GS_HIP_TRY(read(p->sensors[si].base + p->sensors[si].o_status, ws));
@@ -829,6 +907,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
       out->evaluated += (int64_t)w[kStEvals] | ((int64_t)w[kStEvals + 1] << 32);
       out->composited += (int64_t)w[kStContrib] | ((int64_t)w[kStContrib + 1] << 32);
       over = over || w[kStOverflow] != 0;
+      GS_HIP_TRY(read_queue(s.R, s.base));
     }
   }
   out->overflow = over ? 1 : 0;

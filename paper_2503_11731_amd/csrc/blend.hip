@@ -1,27 +1,39 @@
-// a6 / a8: per-tile forward compositing and its adjoint.
+// a6 / a8: front-to-back compositing (Sec. III-A, Eq. 1 with the ray-splat
+// solve of Eq. 2-3 / Eq. 5) and its adjoint, as one persistent work queue.
 //
-// One workgroup per screen tile, one lane per ray; each wave64 owns an 8x8
-// block of rays so that its lanes see nearly the same surfels.  The tile's
-// depth-ordered surfel records are staged through LDS in batches of one
-// record per thread; every lane then walks the batch with broadcast LDS reads.
-// A wave leaves a batch as soon as a ballot shows all its rays saturated; the
-// workgroup stops when a block-wide count reaches zero.
+// Work items are (tile, segment) pairs.  A tile whose depth-ordered pair list
+// is at most L pairs long is one item and is composited exactly as the
+// definition reads.  A longer list is split into segments of L pairs so that
+// no single workgroup walks tens of thousands of pairs while the rest of the
+// chip idles (horizon tiles of a driving scene hold 100x the median list):
+//  1. every segment composites its pairs for each ray starting from T = 1,
+//     with the usual skip and stop rules, and stores its partial state
+//     (accumulators, transmittance, last composited pair, counters);
+//  2. the workgroup that finishes a tile's last segment (one atomic arrival
+//     counter per tile) merges the partials front to back:
+//         C <- C + T * C_seg,   T <- T * T_seg,
+//     accepting a segment whole while T * T_seg stays clear of T_min; a ray
+//     whose stop can fall inside segment s gets its incoming state stored in
+//     slot s, the slot is marked, and (tile, s) joins a walk list;
+//  3. a second persistent pass walks every listed segment cooperatively for
+//     its marked rays from their true incoming state, so the stop rule keeps
+//     its sequential meaning (a ray that then does not stop, which needs its
+//     FP32 product within rounding of T_min, finishes the merge on its own);
+//  4. each reached segment keeps its incoming (T, prefix accumulators), so the
+//     adjoint processes every segment independently.
 //
-// Per pair (camera, Sec. III-A Eq. 2-3):  h' = e3 + P (dx, dy),
-//   u = h'0/h'2, v = h'1/h'2, z = mu_z/h'2, rho = u^2 + v^2,
-//   rho_lp = lp (dx^2 + dy^2), rho_hat = min(rho, rho_lp),
-//   alpha = min(alpha_max, exp2(log2 o - rho_hat / (2 ln 2))).
-// Per pair (LiDAR, Eq. 5): delta = d - mu_hat, h' = e3 + Q delta,
-//   range = |mu| / h'2, rho_lp = lp / step^2 |delta|^2.
-// Near-degenerate (grazing) pairs of flagged surfels (|h'2| < 1/8) are
-// re-solved in FP64 from the FP64 record.
+// Inside an item: one lane per ray, each wave64 owns an 8x8 block of rays.
+// Records are staged through LDS one per thread; lanes walk the batch with
+// broadcast LDS reads; a wave skips pairs whose pixel rectangle misses its
+// block and leaves as soon as a ballot shows all its rays saturated.
+// Grazing pairs of flagged surfels (|h'2| < 1/8) are re-solved in FP64.
 //
-// The backward pass replays each ray front to back up to the forward's last
-// contributing pair (n_last), recomputing transmittance instead of storing
-// per-ray lists, and uses the forward outputs O for the suffix sums
-// S_i = O - (prefix through i):  dO/dalpha_i = T_i f_i - S_i / (1 - alpha_i).
-// Per-pair gradients are summed over the wave with DPP and added to per-surfel
-// accumulators with one atomic per wave and field.
+// The adjoint replays each ray front to back up to the forward's last
+// contributing pair (n_last), recomputing transmittance, and uses the forward
+// outputs O for the suffix sums S_i = O - (prefix through i):
+// dO/dalpha_i = T_i f_i - S_i / (1 - alpha_i).  Per-pair gradients are summed
+// over the wave with DPP and added to per-record accumulators with one atomic
+// per wave and field.
 #include "gs_internal.h"
 #include "kernels.h"
 
@@ -30,6 +42,15 @@ namespace gs {
 namespace {
 
 constexpr float kInv2Ln2 = 0.7213475204444817f;  // 1 / (2 ln 2)
+
+// Partial-state planes of one segment slot (one value per ray of the tile).
+// After the merge, planes [0, C) and kPartT hold the segment's incoming state;
+// a slot marked kWalk in kPartLast holds the ray's last pair so far in
+// kPartCount.
+enum { kPartT = 8, kPartLast = 9, kPartCount = 10 };
+constexpr uint32_t kWalk = 0xFFFFFFFFu;  // never a (last | stop bit) value: pair ids < 2^31 - 1
+
+enum FwdMode { kWhole, kPartial, kFinish };
 
 struct PairEval {
   float alpha, u, v, z, r, dx, dy, dz3;  // dz3: LiDAR third delta component
@@ -52,8 +73,18 @@ __device__ __forceinline__ bool misses_block_wrap(uint32_t cols, uint32_t rows, 
   return c_hi < bx && c_lo > bx + 7;
 }
 
+__device__ __forceinline__ bool covers(uint32_t cols, uint32_t rows, int x, int y) {
+  return (int)(cols & 0xFFFF) <= x && x <= (int)(cols >> 16) && (int)(rows & 0xFFFF) <= y && y <= (int)(rows >> 16);
+}
+
+__device__ __forceinline__ bool covers_wrap(uint32_t cols, uint32_t rows, int x, int y) {
+  const int c_lo = cols & 0xFFFF, c_hi = cols >> 16;
+  if (!((int)(rows & 0xFFFF) <= y && y <= (int)(rows >> 16))) return false;
+  return c_lo <= c_hi ? (c_lo <= x && x <= c_hi) : (x >= c_lo || x <= c_hi);
+}
+
 // ----------------------------- camera -----------------------------------
-// LDS record (5 x float4):
+// Staged record (5 x float4):
 //  [0] pcx_rel, pcy_rel, P00, P01   [1] P10, P11, P20, P21
 //  [2] mu_z, log2 o, c0, c1          [3] c2, n0, n1, n2
 //  [4] flags, o, pixel columns lo|hi<<16, pixel rows lo|hi<<16
@@ -131,66 +162,53 @@ __device__ __forceinline__ void stage_pinhole(const TileArgs& a, uint32_t s, int
   dst[4] = make_float4(r3.z, r3.w, __uint_as_float(rect.x), __uint_as_float(rect.y));
 }
 
-template <int NT>
-__device__ void fwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id) {
-#pragma clang fp contract(off)
-  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
-  const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
-  const int ox = tx * TW, oy = ty * TH;
-  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
-  const int px = ox + lx, py = oy + ly;
-  const bool inside = px < a.S.W && py < a.S.H;
-  const float plx = (float)lx + 0.5f, ply = (float)ly + 0.5f;
-  const uint2 rg = a.ranges[a.S.tile_offset + tile];
-  float T = 1.0f;
-  float acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
-  bool done = !inside;
-  uint32_t last = rg.x, n_eval = 0, n_contrib = 0, n64 = 0;
-  for (uint32_t base = rg.x; base < rg.y; base += NT) {
-    if (__syncthreads_count(!done) == 0) break;
-    const uint32_t k = base + t;
-    if (k < rg.y) {
-      const uint32_t s = a.pval[k];
-      stage_pinhole(a, s, ox, oy, s_rec[t]);
-      s_id[t] = s;
-    }
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, rg.y - base);
-    for (int j = 0; j < cnt; ++j) {
-      if (__ballot(!done) == 0) break;
-      if (misses_block(__float_as_uint(s_rec[j][4].z), __float_as_uint(s_rec[j][4].w), bx, by)) continue;
-      if (done) continue;
-      PairEval e;
-      ++n_eval;
-      if (!eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e, n64)) continue;
-      const float Tn = T * (1.0f - e.alpha);
-      if (Tn < a.O.T_min) {
-        done = true;
-        continue;
-      }
-      ++n_contrib;
-      const float wgt = e.alpha * T;
-      const float4 q2 = s_rec[j][2], q3 = s_rec[j][3];
-      acc[0] = fmaf(wgt, q2.z, acc[0]);
-      acc[1] = fmaf(wgt, q2.w, acc[1]);
-      acc[2] = fmaf(wgt, q3.x, acc[2]);
-      acc[3] = fmaf(wgt, e.z, acc[3]);
-      acc[4] = fmaf(wgt, q3.y, acc[4]);
-      acc[5] = fmaf(wgt, q3.z, acc[5]);
-      acc[6] = fmaf(wgt, q3.w, acc[6]);
-      acc[7] = acc[7] + wgt;
-      T = Tn;
-      last = base + j + 1;
-    }
+// One camera ray of a tile: lane geometry and the per-sensor pieces of the
+// compositing loop (staging, skip test, solve, features, output, adjoint).
+struct CamRay {
+  static constexpr int C = 8;  // rgb, depth, normal xyz, alpha
+  int px, py, ox, oy, bx, by;
+  float plx, ply;
+  bool inside;
+
+  __device__ CamRay(const TileArgs& a, int tile) {
+    const int WX = a.S.tw >> 3;
+    const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
+    ox = tx * a.S.tw;
+    oy = ty * a.S.th;
+    bx = ox + (w % WX) * 8;
+    by = oy + (w / WX) * 8;
+    px = ox + lx;
+    py = oy + ly;
+    inside = px < a.S.W && py < a.S.H;
+    plx = (float)lx + 0.5f;
+    ply = (float)ly + 0.5f;
   }
-  count_pairs(a.status, n_eval, n_contrib, n64);
-  if (inside) {
-    const size_t HW = (size_t)a.S.W * a.S.H;
-    const size_t p = (size_t)py * a.S.W + px;
+  __device__ size_t pix(const TileArgs& a) const { return (size_t)py * a.S.W + px; }
+  __device__ void stage(const TileArgs& a, uint32_t s, float4* dst) const { stage_pinhole(a, s, ox, oy, dst); }
+  __device__ bool miss(const float4* R) const {
+    return misses_block(__float_as_uint(R[4].z), __float_as_uint(R[4].w), bx, by);
+  }
+  __device__ bool covered(const float4* R) const {
+    return covers(__float_as_uint(R[4].z), __float_as_uint(R[4].w), px, py);
+  }
+  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, PairEval& e, uint32_t& n64) const {
+    return eval_pinhole(R, s, plx, ply, ox, oy, a, e, n64);
+  }
+  __device__ void feat(const float4* R, const PairEval& e, float* f) const {
+    f[0] = R[2].z;
+    f[1] = R[2].w;
+    f[2] = R[3].x;
+    f[3] = e.z;
+    f[4] = R[3].y;
+    f[5] = R[3].z;
+    f[6] = R[3].w;
+    f[7] = 1.0f;
+  }
+  __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
+#pragma clang fp contract(off)
+    const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
     a.out[p] = fmaf(T, a.O.bg0, acc[0]);
     a.out[HW + p] = fmaf(T, a.O.bg1, acc[1]);
     a.out[2 * HW + p] = fmaf(T, a.O.bg2, acc[2]);
@@ -199,125 +217,49 @@ __device__ void fwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5]
     a.T_final[p] = T;
     a.n_last[p] = last;
   }
-}
-
-__device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* gacc, int N, int lane) {
-#pragma unroll
-  for (int f = 0; f < kGradFields; ++f) {
-    const float v = wave_sum_last(g[f]);
-    if (lane == 63 && v != 0.0f) atomicAdd(gacc + (size_t)f * N + s, v);
-  }
-}
-
-template <int NT>
-__device__ void bwd_tile_pinhole(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id, uint32_t& s_maxlast) {
+  // Per-record gradient fields of one pair given dL/dalpha (dal) and the
+  // pair's weight wgt = alpha T: [0..5] dP, [6..7] d(projected centre),
+  // [8] d mu_z, [9] d opacity, [10..12] d colour, [13..15] d normal.
+  __device__ void grads(const TileArgs& a, const float4* R, const PairEval& e, float dal, float wgt, const float* g,
+                        float* gr) const {
 #pragma clang fp contract(off)
-  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
-  const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
-  const int ox = tx * TW, oy = ty * TH;
-  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
-  const int px = ox + lx, py = oy + ly;
-  const bool inside = px < a.S.W && py < a.S.H;
-  const float plx = (float)lx + 0.5f, ply = (float)ly + 0.5f;
-  const uint2 rg = a.ranges[a.S.tile_offset + tile];
-  const size_t HW = (size_t)a.S.W * a.S.H;
-  const size_t p = inside ? (size_t)py * a.S.W + px : 0;
-  float g[8], O[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    g[c] = inside ? a.gout[c * HW + p] : 0.0f;
-    O[c] = inside ? a.out_fwd[c * HW + p] : 0.0f;
-  }
-  const uint32_t last = inside ? a.n_last[p] : rg.x;
-  __syncthreads();
-  if (t == 0) s_maxlast = rg.x;
-  __syncthreads();
-  atomicMax(&s_maxlast, last);
-  __syncthreads();
-  const uint32_t end = s_maxlast;
-  // wave-uniform end
-  uint32_t wlast = last;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
-  uint32_t n64 = 0;
-  float T = 1.0f;
-  float A[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) A[c] = 0.0f;
-  for (uint32_t base = rg.x; base < end; base += NT) {
-    __syncthreads();
-    const uint32_t k = base + t;
-    if (k < end) {
-      const uint32_t s = a.pval[k];
-      stage_pinhole(a, s, ox, oy, s_rec[t]);
-      s_id[t] = s;
+    const float4 q0 = R[0], q1 = R[1];
+    const float o = R[4].y;
+    const float al = e.alpha;
+    gr[10] = g[0] * wgt;
+    gr[11] = g[1] * wgt;
+    gr[12] = g[2] * wgt;
+    gr[13] = g[4] * wgt;
+    gr[14] = g[5] * wgt;
+    gr[15] = g[6] * wgt;
+    const float gz = g[3] * wgt;
+    float g_rhohat = 0.0f;
+    if (!e.clamped) {
+      gr[9] = o > 0.0f ? dal * al / o : 0.0f;
+      g_rhohat = -0.5f * dal * al;
     }
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, end - base);
-    for (int j = 0; j < cnt; ++j) {
-      if (base + j >= wlast) break;
-      if (misses_block(__float_as_uint(s_rec[j][4].z), __float_as_uint(s_rec[j][4].w), bx, by)) continue;
-      const bool active = base + j < last;
-      PairEval e;
-      const bool hit = active && eval_pinhole(s_rec[j], s_id[j], plx, ply, ox, oy, a, e, n64);
-      float gr[kGradFields];
-#pragma unroll
-      for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
-      if (hit) {
-        const float4 q0 = s_rec[j][0], q1 = s_rec[j][1], q2 = s_rec[j][2], q3 = s_rec[j][3];
-        const float o = s_rec[j][4].y;
-        const float al = e.alpha;
-        const float wgt = al * T;
-        const float f[8] = {q2.z, q2.w, q3.x, e.z, q3.y, q3.z, q3.w, 1.0f};
-        const float inv1m = 1.0f / (1.0f - al);
-        float dal = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          A[c] = fmaf(wgt, f[c], A[c]);
-          const float S = O[c] - A[c];
-          dal += g[c] * (T * f[c] - S * inv1m);
-        }
-        // colour and normal
-        gr[10] = g[0] * wgt;
-        gr[11] = g[1] * wgt;
-        gr[12] = g[2] * wgt;
-        gr[13] = g[4] * wgt;
-        gr[14] = g[5] * wgt;
-        gr[15] = g[6] * wgt;
-        const float gz = g[3] * wgt;
-        float g_rhohat = 0.0f;
-        if (!e.clamped) {
-          gr[9] = o > 0.0f ? dal * al / o : 0.0f;
-          g_rhohat = -0.5f * dal * al;
-        }
-        const float g_rho = e.lp_used ? 0.0f : g_rhohat;
-        const float g_lp = e.lp_used ? g_rhohat : 0.0f;
-        const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
-        const float gh0 = gu * e.r, gh1 = gv * e.r;
-        const float gh2 = -(gu * e.u + gv * e.v + gz * e.z) * e.r;
-        gr[8] = gz * e.r;
-        gr[0] = gh0 * e.dx;
-        gr[1] = gh0 * e.dy;
-        gr[2] = gh1 * e.dx;
-        gr[3] = gh1 * e.dy;
-        gr[4] = gh2 * e.dx;
-        gr[5] = gh2 * e.dy;
-        const float two_lp = 2.0f * a.O.lp * g_lp;
-        const float gdx = q0.z * gh0 + q1.x * gh1 + q1.z * gh2 + two_lp * e.dx;
-        const float gdy = q0.w * gh0 + q1.y * gh1 + q1.w * gh2 + two_lp * e.dy;
-        gr[6] = -gdx;
-        gr[7] = -gdy;
-        T = T * (1.0f - al);
-      }
-      if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.gacc, a.gacc_stride, lane);
-    }
+    const float g_rho = e.lp_used ? 0.0f : g_rhohat;
+    const float g_lp = e.lp_used ? g_rhohat : 0.0f;
+    const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
+    const float gh0 = gu * e.r, gh1 = gv * e.r;
+    const float gh2 = -(gu * e.u + gv * e.v + gz * e.z) * e.r;
+    gr[8] = gz * e.r;
+    gr[0] = gh0 * e.dx;
+    gr[1] = gh0 * e.dy;
+    gr[2] = gh1 * e.dx;
+    gr[3] = gh1 * e.dy;
+    gr[4] = gh2 * e.dx;
+    gr[5] = gh2 * e.dy;
+    const float two_lp = 2.0f * a.O.lp * g_lp;
+    const float gdx = q0.z * gh0 + q1.x * gh1 + q1.z * gh2 + two_lp * e.dx;
+    const float gdy = q0.w * gh0 + q1.y * gh1 + q1.w * gh2 + two_lp * e.dy;
+    gr[6] = -gdx;
+    gr[7] = -gdy;
   }
-}
+};
 
 // ----------------------------- LiDAR -------------------------------------
-// LDS record (5 x float4):
+// Staged record (5 x float4):
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
 //  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, intensity, flags
 //  [4] o, columns lo|hi<<16 (may wrap), beams lo|hi<<16, -
@@ -398,48 +340,160 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
 
 // Unit ray direction of LiDAR column c, beam j from the FP32 tables, in FP64.
 __device__ inline void lidar_dir(const SensorK& S, int c, int j, double* d) {
-  const double ce = S.cos_el[j], se = S.sin_el[j], ca = S.cos_az[c], sa = S.sin_az[c];
+  const float* t = S.tab;
+  const double ce = t[S.H + j], se = t[2 * S.H + j], ca = t[3 * S.H + c], sa = t[3 * S.H + S.W + c];
   d[0] = ce * ca;
   d[1] = ce * sa;
   d[2] = se;
 }
 
-template <int NT>
-__device__ void fwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id) {
-#pragma clang fp contract(off)
-  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
-  const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
-  const int ox = tx * TW, oy = ty * TH;
-  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
-  const int pc = ox + lx, pb = oy + ly;
-  const bool inside = pc < a.S.W && pb < a.S.H;
+struct LidarRay {
+  static constexpr int C = 3;  // range, intensity, alpha
+  int pc, pb, bx, by;
+  bool inside;
   double dt[3], d64[3];
-  lidar_dir(a.S, ox, oy, dt);
-  lidar_dir(a.S, inside ? pc : ox, inside ? pb : oy, d64);
-  const float dpix[3] = {(float)(d64[0] - dt[0]), (float)(d64[1] - dt[1]), (float)(d64[2] - dt[2])};
-  const uint2 rg = a.ranges[a.S.tile_offset + tile];
-  float T = 1.0f, acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
-  bool done = !inside;
-  uint32_t last = rg.x, n_eval = 0, n_contrib = 0, n64 = 0;
-  for (uint32_t base = rg.x; base < rg.y; base += NT) {
+  float dpix[3];
+
+  __device__ LidarRay(const TileArgs& a, int tile) {
+    const int WX = a.S.tw >> 3;
+    const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
+    const int ox = tx * a.S.tw, oy = ty * a.S.th;
+    bx = ox + (w % WX) * 8;
+    by = oy + (w / WX) * 8;
+    pc = ox + lx;
+    pb = oy + ly;
+    inside = pc < a.S.W && pb < a.S.H;
+    lidar_dir(a.S, ox, oy, dt);
+    lidar_dir(a.S, inside ? pc : ox, inside ? pb : oy, d64);
+    dpix[0] = (float)(d64[0] - dt[0]);
+    dpix[1] = (float)(d64[1] - dt[1]);
+    dpix[2] = (float)(d64[2] - dt[2]);
+  }
+  __device__ size_t pix(const TileArgs& a) const { return (size_t)pb * a.S.W + pc; }
+  __device__ void stage(const TileArgs& a, uint32_t s, float4* dst) const { stage_lidar(a, s, dt, dst); }
+  __device__ bool miss(const float4* R) const {
+    return misses_block_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), bx, by);
+  }
+  __device__ bool covered(const float4* R) const {
+    return covers_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), pc, pb);
+  }
+  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, PairEval& e, uint32_t& n64) const {
+    return eval_lidar(R, s, dpix, d64, a, e, n64);
+  }
+  __device__ void feat(const float4* R, const PairEval& e, float* f) const {
+    f[0] = e.z;
+    f[1] = R[3].z;
+    f[2] = 1.0f;
+  }
+  __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
+    const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
+    a.out[p] = acc[0];
+    a.out[HW + p] = acc[1];
+    a.out[2 * HW + p] = acc[2];
+    a.T_final[p] = T;
+    a.n_last[p] = last;
+  }
+  // [0..8] dQ (row-major), [9..11] d mu_hat, [12] d|mu|, [13] d opacity,
+  // [14] d intensity.
+  __device__ void grads(const TileArgs& a, const float4* R, const PairEval& e, float dal, float wgt, const float* g,
+                        float* gr) const {
+#pragma clang fp contract(off)
+    const float4 q0 = R[0], q1 = R[1], q2 = R[2];
+    const float o = R[4].x;
+    const float al = e.alpha;
+    const float grange = g[0] * wgt;
+    gr[14] = g[1] * wgt;
+    float g_rhohat = 0.0f;
+    if (!e.clamped) {
+      gr[13] = o > 0.0f ? dal * al / o : 0.0f;
+      g_rhohat = -0.5f * dal * al;
+    }
+    const float g_rho = e.lp_used ? 0.0f : g_rhohat;
+    const float g_lp = e.lp_used ? g_rhohat : 0.0f;
+    const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
+    const float gh0 = gu * e.r, gh1 = gv * e.r;
+    const float gh2 = -(gu * e.u + gv * e.v + grange * e.z) * e.r;
+    gr[12] = grange * e.r;
+    const float dd[3] = {e.dx, e.dy, e.dz3};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      gr[c] = gh0 * dd[c];
+      gr[3 + c] = gh1 * dd[c];
+      gr[6 + c] = gh2 * dd[c];
+    }
+    const float two_lp = 2.0f * a.S.lp_ang * g_lp;
+    const float Q[9] = {q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float gd = Q[c] * gh0 + Q[3 + c] * gh1 + Q[6 + c] * gh2 + two_lp * dd[c];
+      gr[9 + c] = -gd;
+    }
+  }
+};
+
+// ------------------------- generic compositing ---------------------------
+
+__device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* gacc, size_t stride, int lane) {
+#pragma unroll
+  for (int f = 0; f < kGradFields; ++f) {
+    const float v = wave_sum_last(g[f]);
+    if (lane == 63 && v != 0.0f) atomicAdd(gacc + (size_t)f * stride + s, v);
+  }
+}
+
+template <int NT, class Ray, bool MARK>
+__device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t L, uint32_t n_seg, uint32_t pbase,
+                           uint32_t sg0, float* part, size_t ps, float T_accept, float& T, float* acc, uint32_t& last,
+                           uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64, uint32_t& marked);
+
+// Composites pairs [b0, b1) of the tile for every ray (or, kFinish, for the
+// rays marked in slot element `pe`, from their stored incoming state).
+//  kWhole:   from T = 1, writes the outputs;
+//  kPartial: from T = 1, writes the segment's partial state to `pe`;
+//  kFinish:  writes the outputs of the marked rays.
+template <int NT, class Ray, FwdMode M>
+__device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, float4 (*s_rec)[5],
+                          uint32_t* s_id, float* part, size_t ps, size_t pe, const QueueArgs* q = nullptr,
+                          uint2 rg = make_uint2(0u, 0u), uint32_t n_seg = 0, uint32_t pbase = 0, uint32_t sg = 0) {
+#pragma clang fp contract(off)
+  constexpr int C = Ray::C;
+  const int t = threadIdx.x;
+  float T = 1.0f;
+  float acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+  bool done = !ray.inside;
+  uint32_t last = M == kPartial ? 0u : b0, n_eval = 0, n_contrib = 0, n64 = 0;
+  const uint32_t* pu = reinterpret_cast<const uint32_t*>(part);
+  if (M == kFinish) {
+    const bool marked = ray.inside && pu[kPartLast * ps + pe] == kWalk;
+    done = !marked;
+    if (marked) {
+      T = part[kPartT * ps + pe];
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = part[c * ps + pe];
+      last = pu[kPartCount * ps + pe];
+    }
+  }
+  for (uint32_t base = b0; base < b1; base += NT) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t k = base + t;
-    if (k < rg.y) {
+    if (k < b1) {
       const uint32_t s = a.pval[k];
-      stage_lidar(a, s, dt, s_rec[t]);
+      ray.stage(a, s, s_rec[t]);
       s_id[t] = s;
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, rg.y - base);
+    const int cnt = (int)min((uint32_t)NT, b1 - base);
     for (int j = 0; j < cnt; ++j) {
       if (__ballot(!done) == 0) break;
-      if (misses_block_wrap(__float_as_uint(s_rec[j][4].y), __float_as_uint(s_rec[j][4].z), bx, by)) continue;
+      if (ray.miss(s_rec[j])) continue;
       if (done) continue;
+      n_eval += ray.covered(s_rec[j]) ? 1u : 0u;
       PairEval e;
-      ++n_eval;
-      if (!eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e, n64)) continue;
+      if (!ray.eval(a, s_rec[j], s_id[j], e, n64)) continue;
       const float Tn = T * (1.0f - e.alpha);
       if (Tn < a.O.T_min) {
         done = true;
@@ -447,121 +501,212 @@ __device__ void fwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], 
       }
       ++n_contrib;
       const float wgt = e.alpha * T;
-      acc0 = fmaf(wgt, e.z, acc0);
-      acc1 = fmaf(wgt, s_rec[j][3].z, acc1);
-      acc2 = acc2 + wgt;
+      float f[C];
+      ray.feat(s_rec[j], e, f);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = fmaf(wgt, f[c], acc[c]);
       T = Tn;
       last = base + j + 1;
     }
   }
-  count_pairs(a.status, n_eval, n_contrib, n64);
-  if (inside) {
-    const size_t HW = (size_t)a.S.W * a.S.H;
-    const size_t p = (size_t)pb * a.S.W + pc;
-    a.out[p] = acc0;
-    a.out[HW + p] = acc1;
-    a.out[2 * HW + p] = acc2;
-    a.T_final[p] = T;
-    a.n_last[p] = last;
+  if (M == kPartial) {
+    count_pairs(a.status, 0u, 0u, n64);
+    if (ray.inside) {
+      uint32_t* pw = reinterpret_cast<uint32_t*>(part);
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[c * ps + pe] = acc[c];
+      part[kPartT * ps + pe] = T;
+      pw[kPartLast * ps + pe] = last | (done ? 0x80000000u : 0u);
+      pw[kPartCount * ps + pe] = n_eval | (n_contrib << 16);
+    }
+  } else if (M == kWhole) {
+    count_pairs(a.status, n_eval, n_contrib, n64);
+    if (ray.inside) ray.write(a, T, acc, last);
+  } else {
+    // a marked ray that did not stop in this segment continues on its own
+    const bool marked = ray.inside && pu[kPartLast * ps + pe] == kWalk;
+    if (marked) {
+      uint32_t unused = 0;
+      if (!done)
+        (void)merge_from<NT, Ray, false>(a, ray, rg, q->seg_len, n_seg, pbase, sg + 1, part, ps, q->T_accept, T, acc,
+                                     last, n_eval, n_contrib, n64, unused);
+      ray.write(a, T, acc, last);
+    }
+    count_pairs(a.status, n_eval, n_contrib, n64);
   }
 }
 
-template <int NT>
-__device__ void bwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], uint32_t* s_id, uint32_t& s_maxlast) {
+// One ray walks pairs [b0, b1) on its own from the state (T, acc), reading
+// records from global memory.  Returns true where the stop rule fires.
+template <class Ray>
+__device__ bool rewalk(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, float& T, float* acc,
+                       uint32_t& last, uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64) {
 #pragma clang fp contract(off)
-  const int TW = a.S.tw, TH = a.S.th, WX = TW >> 3;
-  const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
-  const int ox = tx * TW, oy = ty * TH;
-  const int bx = ox + (w % WX) * 8, by = oy + (w / WX) * 8;
-  const int pc = ox + lx, pb = oy + ly;
-  const bool inside = pc < a.S.W && pb < a.S.H;
-  double dt[3], d64[3];
-  lidar_dir(a.S, ox, oy, dt);
-  lidar_dir(a.S, inside ? pc : ox, inside ? pb : oy, d64);
-  const float dpix[3] = {(float)(d64[0] - dt[0]), (float)(d64[1] - dt[1]), (float)(d64[2] - dt[2])};
-  const uint2 rg = a.ranges[a.S.tile_offset + tile];
-  const size_t HW = (size_t)a.S.W * a.S.H;
-  const size_t p = inside ? (size_t)pb * a.S.W + pc : 0;
-  float g[3], O[3];
+  constexpr int C = Ray::C;
+  for (uint32_t k = b0; k < b1; ++k) {
+    const uint32_t s = a.pval[k];
+    float4 R[5];
+    ray.stage(a, s, R);
+    if (ray.miss(R)) continue;
+    n_eval += ray.covered(R) ? 1u : 0u;
+    PairEval e;
+    if (!ray.eval(a, R, s, e, n64)) continue;
+    const float Tn = T * (1.0f - e.alpha);
+    if (Tn < a.O.T_min) return true;
+    ++n_contrib;
+    const float wgt = e.alpha * T;
+    float f[C];
+    ray.feat(R, e, f);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    g[c] = inside ? a.gout[c * HW + p] : 0.0f;
-    O[c] = inside ? a.out_fwd[c * HW + p] : 0.0f;
+    for (int c = 0; c < C; ++c) acc[c] = fmaf(wgt, f[c], acc[c]);
+    T = Tn;
+    last = k + 1;
   }
-  const uint32_t last = inside ? a.n_last[p] : rg.x;
+  return false;
+}
+
+// Front-to-back merge of a split tile's segment partials from slot sg0 with
+// the ray's running state (see the header).  Every reached slot keeps the
+// segment's incoming (T, prefix) for the adjoint.  At a segment where the
+// stop can happen: mark = true stores the state there, marks the slot and
+// returns with `marked` = slot + 1; MARK = false re-walks the segment on the
+// ray's own.  Returns true when the ray's result is final.
+template <int NT, class Ray, bool MARK>
+__device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t L, uint32_t n_seg, uint32_t pbase,
+                           uint32_t sg0, float* part, size_t ps, float T_accept, float& T, float* acc, uint32_t& last,
+                           uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64, uint32_t& marked) {
+#pragma clang fp contract(off)
+  constexpr int C = Ray::C;
+  uint32_t* pu = reinterpret_cast<uint32_t*>(part);
+  for (uint32_t sg = sg0; sg < n_seg; ++sg) {
+    const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
+    const float Ts = part[kPartT * ps + pe];
+    const uint32_t ls = pu[kPartLast * ps + pe];
+    const uint32_t cnt = pu[kPartCount * ps + pe];
+    float as[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      as[c] = part[c * ps + pe];
+      part[c * ps + pe] = acc[c];
+    }
+    part[kPartT * ps + pe] = T;
+    if (!(ls >> 31) && T * Ts >= T_accept) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = fmaf(T, as[c], acc[c]);
+      T = T * Ts;
+      if (ls) last = ls;
+      n_eval += cnt & 0xFFFFu;
+      n_contrib += cnt >> 16;
+    } else if (MARK) {
+      pu[kPartLast * ps + pe] = kWalk;
+      pu[kPartCount * ps + pe] = last;
+      marked = sg + 1;
+      return false;
+    } else {
+      const uint32_t b0 = rg.x + sg * L;
+      const uint32_t b1 = min(b0 + L, rg.y);
+      if (rewalk(a, ray, b0, b1, T, acc, last, n_eval, n_contrib, n64)) return true;
+    }
+  }
+  return true;
+}
+
+// Merge run by the workgroup that completes a split tile; queues the
+// segments that hold some ray's stop for the cooperative walk.
+template <int NT, class Ray>
+__device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray, uint32_t gt, uint2 rg,
+                           uint32_t n_seg, uint32_t pbase) {
+#pragma clang fp contract(off)
+  constexpr int C = Ray::C;
+  uint32_t n_eval = 0, n_contrib = 0, n64 = 0;
+  if (ray.inside) {
+    float T = 1.0f;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+    uint32_t last = rg.x, marked = 0;
+    (void)merge_from<NT, Ray, true>(a, ray, rg, q.seg_len, n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc,
+                                last, n_eval, n_contrib, n64, marked);
+    if (marked == 0) {
+      ray.write(a, T, acc, last);
+    } else {
+      const uint32_t slot = pbase + marked - 1;
+      if (atomicCAS(q.slot_flag + slot, 0u, 1u) == 0u) {
+        const uint32_t w = atomicAdd(q.hdr + 3, 1u);
+        if (w < q.pslot_cap) q.walk[w] = make_uint2(gt, marked - 1);
+      }
+    }
+  }
+  count_pairs(a.status, n_eval, n_contrib, n64);
+}
+
+// Adjoint over pairs [b0, b1); the incoming state is (1, 0) for a whole tile
+// or the merge's (T_in, prefix) for a segment.
+template <int NT, class Ray>
+__device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, const float* part, size_t ps,
+                          size_t pe, float4 (*s_rec)[5], uint32_t* s_id, uint32_t& s_max) {
+#pragma clang fp contract(off)
+  constexpr int C = Ray::C;
+  const int t = threadIdx.x, lane = t & 63;
+  const size_t HW = (size_t)a.S.W * a.S.H;
+  const size_t p = ray.inside ? ray.pix(a) : 0;
+  float g[C], O[C], A[C];
+  float T = 1.0f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    g[c] = ray.inside ? a.gout[c * HW + p] : 0.0f;
+    O[c] = ray.inside ? a.out_fwd[c * HW + p] : 0.0f;
+    A[c] = 0.0f;
+  }
+  if (part && ray.inside) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) A[c] = part[c * ps + pe];
+    T = part[kPartT * ps + pe];
+  }
+  const uint32_t last = ray.inside ? a.n_last[p] : b0;
   __syncthreads();
-  if (t == 0) s_maxlast = rg.x;
+  if (t == 0) s_max = b0;
   __syncthreads();
-  atomicMax(&s_maxlast, last);
+  atomicMax(&s_max, last);
   __syncthreads();
-  const uint32_t end = s_maxlast;
+  const uint32_t end = min(s_max, b1);
   uint32_t wlast = last;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
   uint32_t n64 = 0;
-  float T = 1.0f, A0 = 0.0f, A1 = 0.0f, A2 = 0.0f;
-  for (uint32_t base = rg.x; base < end; base += NT) {
+  for (uint32_t base = b0; base < end; base += NT) {
     __syncthreads();
     const uint32_t k = base + t;
     if (k < end) {
       const uint32_t s = a.pval[k];
-      stage_lidar(a, s, dt, s_rec[t]);
+      ray.stage(a, s, s_rec[t]);
       s_id[t] = s;
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)NT, end - base);
     for (int j = 0; j < cnt; ++j) {
       if (base + j >= wlast) break;
-      if (misses_block_wrap(__float_as_uint(s_rec[j][4].y), __float_as_uint(s_rec[j][4].z), bx, by)) continue;
+      if (ray.miss(s_rec[j])) continue;
       const bool active = base + j < last;
       PairEval e;
-      const bool hit = active && eval_lidar(s_rec[j], s_id[j], dpix, d64, a, e, n64);
+      const bool hit = active && ray.eval(a, s_rec[j], s_id[j], e, n64);
       float gr[kGradFields];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
       if (hit) {
-        const float4 q0 = s_rec[j][0], q1 = s_rec[j][1], q2 = s_rec[j][2], q3 = s_rec[j][3];
-        const float o = s_rec[j][4].x;
         const float al = e.alpha;
         const float wgt = al * T;
-        const float inten = q3.z;
+        float f[C];
+        ray.feat(s_rec[j], e, f);
         const float inv1m = 1.0f / (1.0f - al);
-        A0 = fmaf(wgt, e.z, A0);
-        A1 = fmaf(wgt, inten, A1);
-        A2 = A2 + wgt;
-        float dal = g[0] * (T * e.z - (O[0] - A0) * inv1m);
-        dal += g[1] * (T * inten - (O[1] - A1) * inv1m);
-        dal += g[2] * (T - (O[2] - A2) * inv1m);
-        const float grange = g[0] * wgt;
-        gr[14] = g[1] * wgt;  // intensity
-        float g_rhohat = 0.0f;
-        if (!e.clamped) {
-          gr[13] = o > 0.0f ? dal * al / o : 0.0f;
-          g_rhohat = -0.5f * dal * al;
-        }
-        const float g_rho = e.lp_used ? 0.0f : g_rhohat;
-        const float g_lp = e.lp_used ? g_rhohat : 0.0f;
-        const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
-        const float gh0 = gu * e.r, gh1 = gv * e.r;
-        const float gh2 = -(gu * e.u + gv * e.v + grange * e.z) * e.r;
-        gr[12] = grange * e.r;  // |mu|
-        const float dd[3] = {e.dx, e.dy, e.dz3};
+        float dal = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          gr[c] = gh0 * dd[c];
-          gr[3 + c] = gh1 * dd[c];
-          gr[6 + c] = gh2 * dd[c];
+        for (int c = 0; c < C; ++c) {
+          A[c] = fmaf(wgt, f[c], A[c]);
+          const float S = O[c] - A[c];
+          dal += g[c] * (T * f[c] - S * inv1m);
         }
-        const float two_lp = 2.0f * a.S.lp_ang * g_lp;
-        const float Q[9] = {q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
-        // d(delta) -> mu_hat enters with a minus sign; stored in fields 9..11
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float gd = Q[c] * gh0 + Q[3 + c] * gh1 + Q[6 + c] * gh2 + two_lp * dd[c];
-          gr[9 + c] = -gd;
-        }
+        ray.grads(a, s_rec[j], e, dal, wgt, g, gr);
         T = T * (1.0f - al);
       }
       if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.gacc, a.gacc_stride, lane);
@@ -569,116 +714,166 @@ __device__ void bwd_tile_lidar(const TileArgs& a, int tile, float4 (*s_rec)[5], 
   }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_blend_fwd(TileArgs a, int n_tiles) {
-  __shared__ float4 s_rec[TW * TH][5];
-  __shared__ uint32_t s_id[TW * TH];
-  const int tile = blockIdx.x;
-  if (a.S.kind == GS_SENSOR_PINHOLE)
-    fwd_tile_pinhole<TW * TH>(a, tile, s_rec, s_id);
-  else
-    fwd_tile_lidar<TW * TH>(a, tile, s_rec, s_id);
-}
-
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_blend_bwd(TileArgs a, int n_tiles) {
-  __shared__ float4 s_rec[TW * TH][5];
-  __shared__ uint32_t s_id[TW * TH];
-  __shared__ uint32_t s_maxlast;
-  const int tile = blockIdx.x;
-  if (a.S.kind == GS_SENSOR_PINHOLE)
-    bwd_tile_pinhole<TW * TH>(a, tile, s_rec, s_id, s_maxlast);
-  else
-    bwd_tile_lidar<TW * TH>(a, tile, s_rec, s_id, s_maxlast);
-}
-
-// Persistent compositing over every (sensor, tile) of a batched step: each
-// workgroup pops work items (global tile ids, heaviest first) from a queue
-// with one atomic per item until the queue is empty.  256 threads; every
-// sensor's tile shape has 256 rays.
-__device__ inline int sensor_of_tile(const BatchArgs& b, uint32_t gt) {
+__device__ inline int sensor_of_tile(const QueueArgs& q, uint32_t gt) {
   int s = 0;
-  while (s + 1 < b.n_sensors && b.tile_off[s + 1] <= (int)gt) ++s;
+  while (s + 1 < q.n_sensors && q.tile_off[s + 1] <= (int)gt) ++s;
   return s;
 }
 
-template <bool BWD>
-__global__ __launch_bounds__(256) void k_blend_persistent(BatchArgs b) {
-  __shared__ float4 s_rec[256][5];
-  __shared__ uint32_t s_id[256];
-  __shared__ uint32_t s_maxlast;
-  __shared__ int s_item;
+template <int NT, bool BWD, class Ray>
+__device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, float4 (*s_rec)[5],
+                         uint32_t* s_id, uint32_t* s_u) {
+  const Ray ray(a, tile);
+  const uint2 rg = a.ranges[gt];
+  const uint32_t len = rg.y - rg.x;
+  const uint32_t L = q.seg_len;
+  const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
+  if (n_seg == 1) {
+    if (BWD)
+      bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, s_rec, s_id, s_u[1]);
+    else
+      fwd_range<NT, Ray, kWhole>(a, ray, rg.x, rg.y, s_rec, s_id, nullptr, 0, 0);
+    return;
+  }
+  const uint32_t pbase = q.pslot_base[gt];
+  if (pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
+  const uint32_t b0 = rg.x + sg * L;
+  const uint32_t b1 = min(b0 + L, rg.y);
+  const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
+  if (BWD) {
+    bwd_range<NT>(a, ray, b0, b1, q.part, q.part_stride, pe, s_rec, s_id, s_u[1]);
+    return;
+  }
+  fwd_range<NT, Ray, kPartial>(a, ray, b0, b1, s_rec, s_id, q.part, q.part_stride, pe);
+  // publish this segment (device-scope release: every XCD's L2 sees it),
+  // then let the tile's last arrival merge after a device-scope acquire
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) s_u[1] = (atomicAdd(q.arrive + gt, 1u) + 1u == n_seg) ? 1u : 0u;
+  __syncthreads();
+  if (s_u[1]) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    merge_tile<NT>(q, a, ray, gt, rg, n_seg, pbase);
+  }
+}
+
+// Sensor kinds a launch may meet (bit 0 camera, bit 1 LiDAR): single-kind
+// launches leave the other kind's code and registers out.
+constexpr int kKindCam = 1, kKindLidar = 2, kKindBoth = 3;
+
+// Persistent compositing: each workgroup pops items (heaviest first) with one
+// atomic per item until the queue is drained.
+template <int NT, bool BWD, int KINDS>
+__global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
+  __shared__ float4 s_rec[NT][5];
+  __shared__ uint32_t s_id[NT];
+  __shared__ uint32_t s_u[2];
+  const uint32_t n_items = min(*q.n_items, q.cap_items);
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(b.counter, 1u);
+    if (threadIdx.x == 0) s_u[0] = atomicAdd(q.counter, 1u);
     __syncthreads();
-    const int it = s_item;
-    if (it >= b.n_items) break;
-    const uint32_t gt = b.queue[it];
-    const int s = sensor_of_tile(b, gt);
-    const TileArgs a = b.tiles[s];
-    const int tile = (int)gt - b.tile_off[s];
-    if (a.S.kind == GS_SENSOR_PINHOLE) {
-      if (BWD) bwd_tile_pinhole<256>(a, tile, s_rec, s_id, s_maxlast);
-      else fwd_tile_pinhole<256>(a, tile, s_rec, s_id);
-    } else {
-      if (BWD) bwd_tile_lidar<256>(a, tile, s_rec, s_id, s_maxlast);
-      else fwd_tile_lidar<256>(a, tile, s_rec, s_id);
-    }
+    const uint32_t it = s_u[0];
+    if (it >= n_items) break;
+    const uint2 ts = q.items[q.queue[it]];
+    const int si = sensor_of_tile(q, ts.x);
+    const TileArgs& a = q.tiles[si];
+    const int tile = (int)ts.x - q.tile_off[si];
+    if ((KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE))
+      run_item<NT, BWD, CamRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_u);
+    else if (KINDS & kKindLidar)
+      run_item<NT, BWD, LidarRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_u);
+  }
+}
+
+// Cooperative walk of the listed segments for their marked rays.
+template <int NT, class Ray>
+__device__ void finish_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
+                            float4 (*s_rec)[5], uint32_t* s_id) {
+  const Ray ray(a, tile);
+  const uint2 rg = a.ranges[gt];
+  const uint32_t L = q.seg_len;
+  const uint32_t n_seg = (rg.y - rg.x - 1) / L + 1;
+  const uint32_t pbase = q.pslot_base[gt];
+  const uint32_t b0 = rg.x + sg * L;
+  const uint32_t b1 = min(b0 + L, rg.y);
+  const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
+  fwd_range<NT, Ray, kFinish>(a, ray, b0, b1, s_rec, s_id, q.part, q.part_stride, pe, &q, rg, n_seg, pbase, sg);
+}
+
+template <int NT, int KINDS>
+__global__ __launch_bounds__(NT) void k_blend_finish(QueueArgs q) {
+  __shared__ float4 s_rec[NT][5];
+  __shared__ uint32_t s_id[NT];
+  __shared__ uint32_t s_it;
+  const uint32_t n = min(q.hdr[3], q.pslot_cap);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_it = atomicAdd(q.hdr + 4, 1u);
+    __syncthreads();
+    const uint32_t it = s_it;
+    if (it >= n) break;
+    const uint2 w = q.walk[it];
+    const int si = sensor_of_tile(q, w.x);
+    const TileArgs& a = q.tiles[si];
+    const int tile = (int)w.x - q.tile_off[si];
+    if ((KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE))
+      finish_item<NT, CamRay>(q, a, tile, w.x, w.y, s_rec, s_id);
+    else if (KINDS & kKindLidar)
+      finish_item<NT, LidarRay>(q, a, tile, w.x, w.y, s_rec, s_id);
   }
 }
 
 }  // namespace
 
-#define GS_TILE_CASES(X) X(16, 16) X(32, 8) X(8, 32) X(16, 8) X(8, 16) X(8, 8) X(32, 16) X(16, 32)
+#define GS_TILE_RAYS(X) X(64) X(128) X(256) X(512)
+#define GS_KINDS(X, NT) X(NT, 1) X(NT, 2) X(NT, 3)
 
-void launch_blend_forward(const TileArgs& a, int n_tiles, hipStream_t st) {
-  if (n_tiles == 0) return;
-  const int tw = a.S.tw, th = a.S.th;
-  const dim3 grid(n_tiles);
-#define CASE(W, H)                                                                 \
-  if (tw == W && th == H) {                                                        \
-    hipLaunchKernelGGL((k_blend_fwd<W, H>), grid, dim3(W * H), 0, st, a, n_tiles); \
-    return;                                                                        \
+void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, hipStream_t st) {
+#define KCASE(NT, K)                                                                       \
+  if (rays == NT && kinds == K) {                                                          \
+    if (backward)                                                                          \
+      hipLaunchKernelGGL((k_blend_queue<NT, true, K>), dim3(grid), dim3(NT), 0, st, q);    \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_blend_queue<NT, false, K>), dim3(grid), dim3(NT), 0, st, q);   \
+    return;                                                                                \
   }
-  GS_TILE_CASES(CASE)
+#define CASE(NT) GS_KINDS(KCASE, NT)
+  GS_TILE_RAYS(CASE)
 #undef CASE
+#undef KCASE
 }
 
-void launch_blend_backward(const TileArgs& a, int n_tiles, hipStream_t st) {
-  if (n_tiles == 0) return;
-  const int tw = a.S.tw, th = a.S.th;
-  const dim3 grid(n_tiles);
-#define CASE(W, H)                                                                 \
-  if (tw == W && th == H) {                                                        \
-    hipLaunchKernelGGL((k_blend_bwd<W, H>), grid, dim3(W * H), 0, st, a, n_tiles); \
-    return;                                                                        \
+void launch_blend_finish(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st) {
+#define KCASE(NT, K)                                                                  \
+  if (rays == NT && kinds == K) {                                                     \
+    hipLaunchKernelGGL((k_blend_finish<NT, K>), dim3(grid), dim3(NT), 0, st, q);      \
+    return;                                                                           \
   }
-  GS_TILE_CASES(CASE)
+#define CASE(NT) GS_KINDS(KCASE, NT)
+  GS_TILE_RAYS(CASE)
 #undef CASE
+#undef KCASE
 }
 
-void launch_blend_persistent(const BatchArgs& b, int grid, bool backward, hipStream_t st) {
-  if (b.n_items == 0) return;
-  if (backward)
-    hipLaunchKernelGGL((k_blend_persistent<true>), dim3(grid), dim3(256), 0, st, b);
-  else
-    hipLaunchKernelGGL((k_blend_persistent<false>), dim3(grid), dim3(256), 0, st, b);
-}
-
-int persistent_blocks_per_cu(bool backward) {
+int blend_blocks_per_cu(int rays, int kinds, bool backward) {
   int n = 0;
-  hipError_t e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<true>, 256, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_persistent<false>, 256, 0);
+  hipError_t e = hipErrorInvalidValue;
+#define KCASE(NT, K)                                                                                         \
+  if (rays == NT && kinds == K)                                                                              \
+    e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, true, K>, NT, 0)      \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, false, K>, NT, 0);
+#define CASE(NT) GS_KINDS(KCASE, NT)
+  GS_TILE_RAYS(CASE)
+#undef CASE
+#undef KCASE
   return e == hipSuccess ? n : 0;
 }
 
 bool tile_shape_supported(int tw, int th) {
-#define CASE(W, H) \
-  if (tw == W && th == H) return true;
-  GS_TILE_CASES(CASE)
-#undef CASE
-  return false;
+  if (tw % 8 != 0 || th % 8 != 0 || tw <= 0 || th <= 0) return false;
+  const int rays = tw * th;
+  return rays == 64 || rays == 128 || rays == 256 || rays == 512;
 }
 
 }  // namespace gs

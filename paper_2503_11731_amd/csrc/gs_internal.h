@@ -47,11 +47,9 @@ struct SensorK {
   float inv_step, step;      // azimuth steps per radian and its inverse (FP32 spec)
   float c_lp;                // sqrt(cutoff2 / lp) * step: low-pass chord radius
   float lp_ang;              // lp / step^2 (FP32) for the per-ray low-pass
-  const float* el;           // [H] elevations (FP32 of the FP64 input)
-  const float* cos_el;
-  const float* sin_el;
-  const float* cos_az;       // [W]
-  const float* sin_az;
+  // FP32 tables, one array: elevations [H], cos and sin of elevation [H]
+  // each, cos and sin of azimuth [W] each
+  const float* tab;
 };
 
 // Per-sensor workspace pointers.
@@ -307,8 +305,8 @@ __device__ inline void spec_lidar_bins(const Frame32& f, float su, float sv, con
   float daz = spec_asin(sa);
   float az_lo = (az_c - daz) * S.inv_step;
   float az_hi = (az_c + daz) * S.inv_step;
-  int j_lo = lower_bound_f(S.el, S.H, el_lo) - 1;
-  int j_hi = upper_bound_f(S.el, S.H, el_hi);
+  int j_lo = lower_bound_f(S.tab, S.H, el_lo) - 1;
+  int j_hi = upper_bound_f(S.tab, S.H, el_hi);
   j_lo = max(j_lo, 0);
   j_hi = min(j_hi, S.H - 1);
   if (full_az) { az_lo = 0.0f; az_hi = 0.0f; }

@@ -50,13 +50,32 @@ struct TileArgs {
   size_t gacc_stride;
 };
 
-struct BatchArgs {
-  const TileArgs* tiles;  // device table [n_sensors]
+// Persistent compositing queue over (tile, segment) work items of one record
+// space (one sensor, or every sensor of a batched step).
+//
+// The TileArgs table travels by value in the kernel arguments: pointers read
+// from there are known to be global, so every access compiles to global_*
+// instructions (pointers read from a table in device memory would be generic
+// and compile to flat ones, which also wait on LDS traffic).
+struct QueueArgs {
+  TileArgs tiles[GS_MAX_SENSORS];
   int n_sensors;
   int tile_off[GS_MAX_SENSORS + 1];
-  const uint32_t* queue;  // global tile ids, heaviest first
-  int n_items;
-  uint32_t* counter;      // zeroed before the launch
+  const uint32_t* queue;     // item ids, heaviest first
+  const uint2* items;        // item id -> (record-space tile id, segment)
+  const uint32_t* n_items;   // device count (hdr[0])
+  uint32_t* hdr;             // [0] items [1] slots [2] queue counter [3] walk count [4] walk counter
+  uint32_t cap_items;
+  uint32_t* counter;         // zeroed before each launch
+  uint32_t* arrive;          // per tile: segments finished (forward)
+  const uint32_t* pslot_base;  // per tile: first partial-state slot
+  float* part;               // [11][pslot_cap * rays per tile]
+  uint32_t* slot_flag;       // per slot: listed for the cooperative walk
+  uint2* walk;               // walk list: (record-space tile id, segment)
+  size_t part_stride;        // elements per plane
+  uint32_t pslot_cap;
+  uint32_t seg_len;          // segment length L (pairs)
+  float T_accept;            // T_min scaled by the product-rounding margin
 };
 
 struct SplatBwdArgs {
@@ -91,17 +110,38 @@ void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uin
 size_t scan_bsum_words(int n);
 void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
                  const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st);
-// work queue keys: heaviest tiles first
-void launch_queue_keys(const uint2* ranges, int n_tiles, uint32_t* key, uint32_t* val, hipStream_t st);
-void launch_store_tile_args(const TileArgs& a, TileArgs* dst, hipStream_t st);
+// Work items of a record space: per tile n_seg = ceil(len / L) (1 when
+// len <= L); item_base / pslot_base by exclusive scans; items written with
+// keys (cost, heaviest first) and ids for the radix sort; arrival counters and
+// the queue counter cleared.  hdr[0] = items, hdr[1] = partial slots,
+// hdr[2] = queue counter.
+struct SegScanArgs {
+  const uint2* ranges;
+  int n_tiles;
+  uint32_t seg_len;
+  int key_bits;
+  uint2* bsum;
+  uint32_t* hdr;
+  uint32_t* pslot_base;
+  uint32_t* arrive;
+  uint32_t* slot_flag;
+  uint32_t* key;
+  uint32_t* val;
+  uint2* items;
+  uint32_t cap_items, pslot_cap;
+  uint32_t* status;
+};
+void launch_build_items(const SegScanArgs& a, hipStream_t st);
+size_t seg_bsum_words(int n_tiles);
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st);
 void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipStream_t st);
 
 // blend.hip
-void launch_blend_forward(const TileArgs& a, int n_tiles, hipStream_t st);
-void launch_blend_backward(const TileArgs& a, int n_tiles, hipStream_t st);
-void launch_blend_persistent(const BatchArgs& b, int grid, bool backward, hipStream_t st);
+// kinds: bit 0 camera, bit 1 LiDAR (the sensor kinds the launch serves)
+void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, hipStream_t st);
+void launch_blend_finish(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st);
+int blend_blocks_per_cu(int rays, int kinds, bool backward);
 bool tile_shape_supported(int tw, int th);
 
 // splat_backward.hip

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
   const float inten = a.intensity ? a.intensity[i] : 0.0f;
 
   // grazing: bound the angle between any ray of the rectangle and the centre
-  float el_lo = a.S.el[b.j_lo], el_hi = a.S.el[b.j_hi];
+  float el_lo = a.S.tab[b.j_lo], el_hi = a.S.tab[b.j_hi];
   double ang_el = fmax(fabs((double)el_lo - b.el_c), fabs((double)el_hi - b.el_c));
   double ang_az;
   if (b.full_cols) {

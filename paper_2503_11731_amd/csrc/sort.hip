@@ -282,17 +282,103 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_queue_keys(const uint2* __restrict__ ranges, int n_tiles,
-                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_tiles) return;
-  const uint2 r = ranges[t];
-  const uint32_t cost = r.y - r.x;
-  key[t] = 0xFFFFFFu - (cost < 0xFFFFFFu ? cost : 0xFFFFFFu);
-  val[t] = (uint32_t)t;
+// ---------------- compositing work items ----------------
+
+// (items, partial slots) of one tile: a list longer than L splits into
+// ceil(len / L) segments, each with its own partial-state slot.
+__device__ inline uint2 seg_counts(uint2 rg, uint32_t L) {
+  const uint32_t len = rg.y - rg.x;
+  const uint32_t n = len > L ? (len - 1) / L + 1 : 1u;
+  return make_uint2(n, n > 1 ? n : 0u);
 }
 
-__global__ void k_store_tile_args(TileArgs a, TileArgs* dst) { *dst = a; }
+__global__ __launch_bounds__(256) void k_seg_reduce(SegScanArgs a) {
+  __shared__ uint32_t s_w[4];
+  const int base = blockIdx.x * kScanItems;
+  uint32_t sx = 0, sy = 0;
+  for (int r = 0; r < kScanItems / 256; ++r) {
+    const int t = base + r * 256 + threadIdx.x;
+    if (t < a.n_tiles) {
+      const uint2 c = seg_counts(a.ranges[t], a.seg_len);
+      sx += c.x;
+      sy += c.y;
+    }
+  }
+  uint32_t tx, ty;
+  block_excl_scan<256>(sx, s_w, &tx);
+  block_excl_scan<256>(sy, s_w, &ty);
+  if (threadIdx.x == 0) a.bsum[blockIdx.x] = make_uint2(tx, ty);
+}
+
+__global__ __launch_bounds__(1024) void k_seg_top(SegScanArgs a, int nblk) {
+  __shared__ uint32_t s_w[16];
+  const int per = (nblk + 1023) / 1024;
+  const int beg = threadIdx.x * per;
+  const int end = min(beg + per, nblk);
+  uint32_t sx = 0, sy = 0;
+  for (int i = beg; i < end; ++i) {
+    sx += a.bsum[i].x;
+    sy += a.bsum[i].y;
+  }
+  uint32_t tx, ty;
+  uint32_t ox = block_excl_scan<1024>(sx, s_w, &tx);
+  uint32_t oy = block_excl_scan<1024>(sy, s_w, &ty);
+  for (int i = beg; i < end; ++i) {
+    const uint2 b = a.bsum[i];
+    a.bsum[i] = make_uint2(ox, oy);
+    ox += b.x;
+    oy += b.y;
+  }
+  if (threadIdx.x == 0) {
+    a.hdr[0] = tx;
+    a.hdr[1] = ty;
+    a.hdr[2] = 0u;
+    a.hdr[3] = 0u;
+    a.hdr[4] = 0u;
+    if (tx > a.cap_items || ty > a.pslot_cap) a.status[kStOverflow] = 1u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
+  __shared__ uint32_t s_w[4];
+  constexpr int PER = kScanItems / 256;
+  const int t0 = blockIdx.x * kScanItems + threadIdx.x * PER;
+  uint2 c[PER];
+  uint32_t sx = 0, sy = 0;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int t = t0 + r;
+    c[r] = t < a.n_tiles ? seg_counts(a.ranges[t], a.seg_len) : make_uint2(0u, 0u);
+    sx += c[r].x;
+    sy += c[r].y;
+  }
+  uint32_t tx, ty;
+  uint32_t ix = block_excl_scan<256>(sx, s_w, &tx) + a.bsum[blockIdx.x].x;
+  uint32_t iy = block_excl_scan<256>(sy, s_w, &ty) + a.bsum[blockIdx.x].y;
+  const uint32_t kmax = a.key_bits >= 32 ? 0xFFFFFFFFu : ((1u << a.key_bits) - 1u);
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int t = t0 + r;
+    if (t < a.n_tiles) {
+      a.pslot_base[t] = iy;
+      a.arrive[t] = 0u;
+      if (c[r].y)
+        for (uint32_t k = 0; k < c[r].y && iy + k < a.pslot_cap; ++k) a.slot_flag[iy + k] = 0u;
+      const uint2 rg = a.ranges[t];
+      const uint32_t len = rg.y - rg.x;
+      for (uint32_t sg = 0; sg < c[r].x; ++sg) {
+        const uint32_t item = ix + sg;
+        if (item >= a.cap_items) break;
+        const uint32_t cost = c[r].x == 1 ? len : min(a.seg_len, len - sg * a.seg_len);
+        a.key[item] = kmax - (cost < kmax ? cost : kmax);
+        a.val[item] = item;
+        a.items[item] = make_uint2((uint32_t)t, sg);
+      }
+    }
+    ix += c[r].x;
+    iy += c[r].y;
+  }
+}
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ ptile, const uint32_t* __restrict__ count,
                                                 uint32_t cap, uint2* __restrict__ ranges) {
@@ -371,14 +457,15 @@ void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, 
   hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, E, cap, ptile, pval);
 }
 
-void launch_queue_keys(const uint2* ranges, int n_tiles, uint32_t* key, uint32_t* val, hipStream_t st) {
-  if (n_tiles == 0) return;
-  hipLaunchKernelGGL(k_queue_keys, dim3((n_tiles + 255) / 256), dim3(256), 0, st, ranges, n_tiles, key, val);
+size_t seg_bsum_words(int n_tiles) { return 2 * ((size_t)((n_tiles + kScanItems - 1) / kScanItems) + 1); }
+
+void launch_build_items(const SegScanArgs& a, hipStream_t st) {
+  const int nblk = (a.n_tiles + kScanItems - 1) / kScanItems;
+  if (nblk > 0) hipLaunchKernelGGL(k_seg_reduce, dim3(nblk), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_seg_top, dim3(1), dim3(1024), 0, st, a, nblk);
+  if (nblk > 0) hipLaunchKernelGGL(k_seg_down, dim3(nblk), dim3(256), 0, st, a);
 }
 
-void launch_store_tile_args(const TileArgs& a, TileArgs* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_store_tile_args, dim3(1), dim3(1), 0, st, a, dst);
-}
 
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st) {

@@ -56,7 +56,8 @@ class Renderer:
     opts:    compositing options (PRODUCTION / STRICT or overrides)
     """
 
-    def __init__(self, scenes, sensors, opts=None, pair_capacity: int = 0, device="cuda", batched=False):
+    def __init__(self, scenes, sensors, opts=None, pair_capacity: int = 0, device="cuda", batched=False,
+                 segment_pairs: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
         self.scenes = [s if isinstance(s, SceneShape) else SceneShape(**s) for s in scenes]
@@ -84,7 +85,8 @@ class Renderer:
                                        s.get("scene", 0), tw, th)
         ro = L.RenderOpts(o["alpha_min"], o["alpha_max"], o["T_min"], o["cutoff2"], o["lp_inv_sigma2"],
                           int(bool(o["lowpass"])), (ctypes.c_float * 3)(*o["bg"]))
-        desc = L.PlanDesc(len(self.scenes), sd, len(self.sensors), sens, ro, int(pair_capacity), int(batched))
+        desc = L.PlanDesc(len(self.scenes), sd, len(self.sensors), sens, ro, int(pair_capacity), int(batched),
+                          int(segment_pairs))
         plan = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             L.check(self.lib.gs_plan_create(ctypes.byref(desc), ctypes.byref(plan)))
@@ -170,7 +172,8 @@ class Renderer:
         rc = self.lib.gs_query_status(self.plan, self.workspace.data_ptr(), _stream(), ctypes.byref(st))
         n = len(self.sensors)
         out = dict(pairs=list(st.pairs[:n]), overflow=bool(st.overflow), n_visible=list(st.n_visible[:n]),
-                   fp64_pairs=int(st.fp64_pairs), evaluated=int(st.evaluated), composited=int(st.composited), rc=rc)
+                   fp64_pairs=int(st.fp64_pairs), evaluated=int(st.evaluated), composited=int(st.composited),
+                   work_items=int(st.work_items), segments=int(st.segments), rc=rc)
         return out
 
     def set_timing(self, max_records: int):

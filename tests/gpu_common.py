@@ -11,7 +11,7 @@ TOL = 1e-4           # absolute, colour / alpha / normal / intensity
 TOL_DEPTH = 1e-4     # relative to max(1, |reference|), depth / range
 
 
-def gpu_render(scene, sensors, opts, tiles=None, pair_capacity=0):
+def gpu_render(scene, sensors, opts, tiles=None, pair_capacity=0, segment_pairs=0):
     shapes = [gs.SceneShape(int(scene["mean"].shape[1]), int(scene.get("sh_degree", -1) if scene.get("sh") is not None else -1),
                             scene.get("intensity") is not None,
                             tuple(int(x) for x in scene["group_offsets"]))]
@@ -21,7 +21,7 @@ def gpu_render(scene, sensors, opts, tiles=None, pair_capacity=0):
         if tiles is not None:
             s["tile"] = tiles[i] if isinstance(tiles, list) else tiles
         sens.append(s)
-    r = gs.Renderer(shapes, sens, opts=opts, pair_capacity=pair_capacity, device=DEV)
+    r = gs.Renderer(shapes, sens, opts=opts, pair_capacity=pair_capacity, device=DEV, segment_pairs=segment_pairs)
     st = gs.scene_tensors(scene, DEV)
     sp = gs.poses_tensor([s["pose"] for s in sensors], DEV)
     gp = gs.poses_tensor(scene["group_poses"], DEV)

@@ -83,6 +83,59 @@ def test_lidar_forward_parity(mode):
         assert excluded <= 0.02 * mask.size
 
 
+@pytest.mark.parametrize("mode,tile", [("production", (16, 16)), ("strict", (16, 16)), ("production", (8, 8))])
+def test_split_tiles_forward_parity(mode, tile):
+    """Tile lists split into 32-pair segments and merged: same oracle bar, and
+    the same result as the unsplit path up to FP32 rounding order."""
+    _say(f"config1 split forward {mode} tile {tile}")
+    scene, sens = _cfg1()
+    opts = gs.PRODUCTION if mode == "production" else gs.STRICT
+    r, st, sp, gp, outs = gpu_render(scene, sens, opts, tiles=tile, segment_pairs=32)
+    status = r.status()
+    assert status["segments"] > 0 and status["work_items"] > status["segments"] // 2
+    o = oracle_opts(opts, tile)
+    check_integer_parity(r, scene, sens[0], o)
+    ref = raster.render(scene, sens[0], o, margins=True)
+    got = outs[0].cpu().numpy()
+    mask = ref["margin"] >= MARGIN if mode == "production" else None
+    errs = camera_errors(got, ref, mask)
+    bad = camera_bad_pixels(got, ref)
+    _say(f"  items {status['work_items']} segments {status['segments']} out-of-tol {int(bad.sum())} errs {errs}")
+    assert within(errs), errs
+    if mask is not None:
+        assert not (bad & mask).any()
+    # the merge is deterministic
+    again = r.forward([st], sp, gp)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], again[0])
+    # unsplit vs split: identical up to rounding order away from thresholds
+    _, _, _, _, whole = gpu_render(scene, sens, opts, tiles=tile, segment_pairs=-1)
+    diff = (whole[0] - outs[0]).abs().cpu().numpy()
+    m = np.ones(diff.shape[1:], bool) if mask is None else mask
+    assert diff[:, m].max() <= 2e-5, diff[:, m].max()
+
+
+@pytest.mark.parametrize("mode", ["production", "strict"])
+def test_split_lidar_forward_parity(mode):
+    _say(f"lidar split forward {mode}")
+    L = S.lidar_spinning(n_beams=32, n_az=360)
+    L["pose"] = S.lidar_rig_pose()
+    sc = S.corridor_surfels(seed=7, n=20000, sh_degree=-1, z_lo=-30, z_hi=30, with_intensity=True)
+    scene = from_gen(sc)
+    opts = gs.PRODUCTION if mode == "production" else gs.STRICT
+    tile = (32, 8)
+    r, st, sp, gp, outs = gpu_render(scene, [L], opts, tiles=tile, segment_pairs=32)
+    assert r.status()["segments"] > 0
+    o = oracle_opts(opts, tile)
+    check_integer_parity(r, scene, L, o)
+    ref = raster.render(scene, L, o, margins=True)
+    got = outs[0].cpu().numpy()
+    mask = ref["margin"] >= MARGIN if mode == "production" else None
+    errs = lidar_errors(got, ref, mask)
+    _say(f"  errs {errs}")
+    assert within(errs), errs
+
+
 def test_forward_is_deterministic_and_order_invariant():
     _say("determinism / permutation")
     scene, sens = _cfg1()
@@ -101,8 +154,10 @@ def test_forward_is_deterministic_and_order_invariant():
     assert torch.equal(a, outs3[0])
 
 
-def _grad_check(scene, sensor, opts, tile, keys, channels_seed=0):
-    r, st, sp, gp, outs = gpu_render(scene, [sensor], opts, tiles=tile)
+def _grad_check(scene, sensor, opts, tile, keys, channels_seed=0, segment_pairs=0):
+    r, st, sp, gp, outs = gpu_render(scene, [sensor], opts, tiles=tile, segment_pairs=segment_pairs)
+    if segment_pairs > 0:
+        assert r.status()["segments"] > 0
     rng = np.random.default_rng(channels_seed)
     go = rng.standard_normal(tuple(outs[0].shape)).astype(np.float32)
     grads = r.backward([st], sp, gp, outs, [torch.from_numpy(go).to(outs[0].device)])[0]
@@ -125,9 +180,9 @@ def _grad_check(scene, sensor, opts, tile, keys, channels_seed=0):
     return res
 
 
-@pytest.mark.parametrize("kind", ["rgb", "sh"])
-def test_camera_backward_parity(kind):
-    _say(f"camera backward {kind}")
+@pytest.mark.parametrize("kind,seg", [("rgb", 0), ("sh", 0), ("rgb", 32)])
+def test_camera_backward_parity(kind, seg):
+    _say(f"camera backward {kind} segment_pairs {seg}")
     rng = np.random.default_rng(3)
     n = 300
     sc = S.random_cloud(seed=11, n=n, lo=(-1, -1, 3), hi=(1, 1, 6), log_scale=(-2.6, 0.4))
@@ -138,14 +193,15 @@ def test_camera_backward_parity(kind):
         scene["sh_degree"] = 3
     cam = S.pinhole(96, 80, 96.0)
     keys = ["mean", "quat", "scale", "opacity", "rgb" if kind == "rgb" else "sh"]
-    res = _grad_check(scene, cam, gs.PRODUCTION, (16, 16), keys)
+    res = _grad_check(scene, cam, gs.PRODUCTION, (16, 16), keys, segment_pairs=seg)
     _say(f"  {res}")
     for k, (err, scale) in res.items():
         assert err <= 1e-3 * scale + 1e-6, (k, err, scale)
 
 
-def test_lidar_backward_parity():
-    _say("lidar backward")
+@pytest.mark.parametrize("seg", [0, 32])
+def test_lidar_backward_parity(seg):
+    _say(f"lidar backward segment_pairs {seg}")
     L = S.lidar_spinning(n_beams=16, n_az=180, pose=np.concatenate([np.eye(3), np.zeros((3, 1))], 1))
     rng = np.random.default_rng(5)
     n = 300
@@ -157,7 +213,8 @@ def test_lidar_backward_parity():
     scene = dict(mean=mean, quat=q, scale=np.exp(rng.normal(-1.6, 0.3, (2, n))).astype(np.float32),
                  opacity=rng.uniform(0.2, 0.95, n).astype(np.float32), intensity=rng.uniform(0, 1, n).astype(np.float32),
                  group_offsets=np.array([0, n], np.int32), group_poses=S._identity_poses(1))
-    res = _grad_check(scene, L, gs.PRODUCTION, (32, 8), ["mean", "quat", "scale", "opacity", "intensity"])
+    res = _grad_check(scene, L, gs.PRODUCTION, (32, 8), ["mean", "quat", "scale", "opacity", "intensity"],
+                      segment_pairs=seg)
     _say(f"  {res}")
     for k, (err, scale) in res.items():
         assert err <= 1e-3 * scale + 1e-6, (k, err, scale)
