@@ -352,6 +352,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (HBM counter calibration under rocprofv3) and exit")
     ap.add_argument("--workloads", default="train720p,lidar,rig",
                     help="extra workloads to time (comma list of train720p, lidar, rig; empty for none)")
     args = ap.parse_args()
@@ -362,6 +364,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe > 0:
+        # reads and writes exactly BYTES each: the reference for FETCH_SIZE / WRITE_SIZE scaling
+        src = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "dispatches": 4}), flush=True)
+        return
 
     import paper_2503_11731_amd as gs
     from gen import scenes as S

@@ -98,44 +98,36 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   const float h0 = fmaf(q0.z, dx, q0.w * dy);
   const float h1 = fmaf(q1.x, dx, q1.y * dy);
   const float h2 = fmaf(q1.z, dx, fmaf(q1.w, dy, 1.0f));
-  float u, v, r, z;
-  if ((flags & kFlagGrazing) && fabsf(h2) < 0.125f) {
-    ++n64;
-    const double* G = a.grz + kGrz * (size_t)s;
-    const double* r64 = a.rec64 + kRec64 * (size_t)s;
-    const double ddx = ((double)ox + (double)plx) - r64[0];
-    const double ddy = ((double)oy + (double)ply) - r64[1];
-    const double H0 = G[0] * ddx + G[1] * ddy;
-    const double H1 = G[2] * ddx + G[3] * ddy;
-    const double H2 = 1.0 + G[4] * ddx + G[5] * ddy;
-    if (H2 == 0.0) return false;
-    const double rd = 1.0 / H2;
-    u = (float)(H0 * rd);
-    v = (float)(H1 * rd);
-    r = (float)rd;
-    z = (float)(G[6] * rd);
-  } else {
-    if (h2 == 0.0f) return false;
-    r = __builtin_amdgcn_rcpf(h2);
-    u = h0 * r;
-    v = h1 * r;
-    z = q2.x * r;
-  }
-  const float rho = fmaf(u, u, v * v);
-  float rho_hat = rho;
-  bool lp_used = false;
-  if (a.O.lowpass) {
-    const float rl = a.O.lp * fmaf(dx, dx, dy * dy);
-    if (!(rho <= rl)) {
-      rho_hat = rl;
-      lp_used = true;
+  float r = __builtin_amdgcn_rcpf(h2);
+  float u = h0 * r, v = h1 * r, z = q2.x * r;
+  bool ok = h2 != 0.0f;
+  if (flags & kFlagGrazing) {  // the same record for the whole wave
+    if (fabsf(h2) < 0.125f) {
+      ++n64;
+      const double* G = a.grz + kGrz * (size_t)s;
+      const double* r64 = a.rec64 + kRec64 * (size_t)s;
+      const double ddx = ((double)ox + (double)plx) - r64[0];
+      const double ddy = ((double)oy + (double)ply) - r64[1];
+      const double H0 = G[0] * ddx + G[1] * ddy;
+      const double H1 = G[2] * ddx + G[3] * ddy;
+      const double H2 = 1.0 + G[4] * ddx + G[5] * ddy;
+      ok = H2 != 0.0;
+      const double rd = 1.0 / H2;
+      u = (float)(H0 * rd);
+      v = (float)(H1 * rd);
+      r = (float)rd;
+      z = (float)(G[6] * rd);
     }
   }
-  if (!(rho_hat <= a.O.cutoff2) || !(z > a.S.z_near)) return false;
+  const float rho = fmaf(u, u, v * v);
+  const float rl = a.O.lp * fmaf(dx, dx, dy * dy);
+  const bool lp_used = a.O.lowpass && !(rho <= rl);
+  const float rho_hat = lp_used ? rl : rho;
+  ok = ok && (rho_hat <= a.O.cutoff2) && (z > a.S.z_near);
   float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q2.y));
   const bool clamped = alpha > a.O.alpha_max;
   if (clamped) alpha = a.O.alpha_max;
-  if (alpha < a.O.alpha_min) return false;
+  ok = ok && !(alpha < a.O.alpha_min);
   e.alpha = alpha;
   e.u = u;
   e.v = v;
@@ -145,10 +137,10 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   e.dy = dy;
   e.lp_used = lp_used;
   e.clamped = clamped;
-  return true;
+  return ok;
 }
 
-__device__ __forceinline__ void stage_pinhole(const TileArgs& a, uint32_t s, int ox, int oy, float4* dst) {
+__device__ __forceinline__ uint2 stage_pinhole(const TileArgs& a, uint32_t s, int ox, int oy, float4* dst) {
   const float4* r = a.rec + 4 * (size_t)s;
   const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
   const double* r64 = a.rec64 + kRec64 * (size_t)s;
@@ -160,18 +152,20 @@ __device__ __forceinline__ void stage_pinhole(const TileArgs& a, uint32_t s, int
   dst[2] = make_float4(r1.z, r1.w, r2.x, r2.y);
   dst[3] = make_float4(r2.z, r2.w, r3.x, r3.y);
   dst[4] = make_float4(r3.z, r3.w, __uint_as_float(rect.x), __uint_as_float(rect.y));
+  return rect;
 }
 
 // One camera ray of a tile: lane geometry and the per-sensor pieces of the
 // compositing loop (staging, skip test, solve, features, output, adjoint).
 struct CamRay {
   static constexpr int C = 8;  // rgb, depth, normal xyz, alpha
-  int px, py, ox, oy, bx, by;
+  int px, py, ox, oy, bx, by, wx;
   float plx, ply;
   bool inside;
 
   __device__ CamRay(const TileArgs& a, int tile) {
     const int WX = a.S.tw >> 3;
+    wx = WX;
     const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
@@ -186,9 +180,13 @@ struct CamRay {
     ply = (float)ly + 0.5f;
   }
   __device__ size_t pix(const TileArgs& a) const { return (size_t)py * a.S.W + px; }
-  __device__ void stage(const TileArgs& a, uint32_t s, float4* dst) const { stage_pinhole(a, s, ox, oy, dst); }
+  __device__ uint2 stage(const TileArgs& a, uint32_t s, float4* dst) const { return stage_pinhole(a, s, ox, oy, dst); }
   __device__ bool miss(const float4* R) const {
     return misses_block(__float_as_uint(R[4].z), __float_as_uint(R[4].w), bx, by);
+  }
+  // does rectangle `rect` touch the 8x8 block of wave w?
+  __device__ bool touches(uint2 rect, int w) const {
+    return !misses_block(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
   __device__ bool covered(const float4* R) const {
     return covers(__float_as_uint(R[4].z), __float_as_uint(R[4].w), px, py);
@@ -263,7 +261,7 @@ struct CamRay {
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
 //  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, intensity, flags
 //  [4] o, columns lo|hi<<16 (may wrap), beams lo|hi<<16, -
-__device__ __forceinline__ void stage_lidar(const TileArgs& a, uint32_t s, const double* dtile, float4* dst) {
+__device__ __forceinline__ uint2 stage_lidar(const TileArgs& a, uint32_t s, const double* dtile, float4* dst) {
   const float4* r = a.rec + 4 * (size_t)s;
   const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
   const double* r64 = a.rec64 + kRec64 * (size_t)s;
@@ -275,6 +273,7 @@ __device__ __forceinline__ void stage_lidar(const TileArgs& a, uint32_t s, const
   dst[2] = make_float4(r1.y, r1.z, r1.w, r2.x);
   dst[3] = make_float4(r2.y, r2.z, r2.w, r3.x);
   dst[4] = make_float4(r3.y, r3.z, r3.w, 0.0f);
+  return make_uint2(__float_as_uint(r3.z), __float_as_uint(r3.w));
 }
 
 __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix,
@@ -288,43 +287,35 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   const float h0 = fmaf(q0.w, d0, fmaf(q1.x, d1, q1.y * d2));
   const float h1 = fmaf(q1.z, d0, fmaf(q1.w, d1, q2.x * d2));
   const float h2 = fmaf(q2.y, d0, fmaf(q2.z, d1, fmaf(q2.w, d2, 1.0f)));
-  float u, v, r, z;
-  if ((flags & kFlagGrazing) && fabsf(h2) < 0.125f) {
-    ++n64;
-    const double* G = a.grz + kGrz * (size_t)s;
-    const double* r64 = a.rec64 + kRec64 * (size_t)s;
-    const double e0 = d64[0] - r64[0], e1 = d64[1] - r64[1], e2 = d64[2] - r64[2];
-    const double H0 = G[0] * e0 + G[1] * e1 + G[2] * e2;
-    const double H1 = G[3] * e0 + G[4] * e1 + G[5] * e2;
-    const double H2 = 1.0 + G[6] * e0 + G[7] * e1 + G[8] * e2;
-    if (H2 == 0.0) return false;
-    const double rd = 1.0 / H2;
-    u = (float)(H0 * rd);
-    v = (float)(H1 * rd);
-    r = (float)rd;
-    z = (float)(G[9] * rd);
-  } else {
-    if (h2 == 0.0f) return false;
-    r = __builtin_amdgcn_rcpf(h2);
-    u = h0 * r;
-    v = h1 * r;
-    z = q3.x * r;
-  }
-  const float rho = fmaf(u, u, v * v);
-  float rho_hat = rho;
-  bool lp_used = false;
-  if (a.O.lowpass) {
-    const float rl = a.S.lp_ang * fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-    if (!(rho <= rl)) {
-      rho_hat = rl;
-      lp_used = true;
+  float r = __builtin_amdgcn_rcpf(h2);
+  float u = h0 * r, v = h1 * r, z = q3.x * r;
+  bool ok = h2 != 0.0f;
+  if (flags & kFlagGrazing) {  // the same record for the whole wave
+    if (fabsf(h2) < 0.125f) {
+      ++n64;
+      const double* G = a.grz + kGrz * (size_t)s;
+      const double* r64 = a.rec64 + kRec64 * (size_t)s;
+      const double e0 = d64[0] - r64[0], e1 = d64[1] - r64[1], e2 = d64[2] - r64[2];
+      const double H0 = G[0] * e0 + G[1] * e1 + G[2] * e2;
+      const double H1 = G[3] * e0 + G[4] * e1 + G[5] * e2;
+      const double H2 = 1.0 + G[6] * e0 + G[7] * e1 + G[8] * e2;
+      ok = H2 != 0.0;
+      const double rd = 1.0 / H2;
+      u = (float)(H0 * rd);
+      v = (float)(H1 * rd);
+      r = (float)rd;
+      z = (float)(G[9] * rd);
     }
   }
-  if (!(rho_hat <= a.O.cutoff2) || !(z > a.S.z_near)) return false;
+  const float rho = fmaf(u, u, v * v);
+  const float rl = a.S.lp_ang * fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+  const bool lp_used = a.O.lowpass && !(rho <= rl);
+  const float rho_hat = lp_used ? rl : rho;
+  ok = ok && (rho_hat <= a.O.cutoff2) && (z > a.S.z_near);
   float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q3.y));
   const bool clamped = alpha > a.O.alpha_max;
   if (clamped) alpha = a.O.alpha_max;
-  if (alpha < a.O.alpha_min) return false;
+  ok = ok && !(alpha < a.O.alpha_min);
   e.alpha = alpha;
   e.u = u;
   e.v = v;
@@ -335,7 +326,7 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   e.dz3 = d2;
   e.lp_used = lp_used;
   e.clamped = clamped;
-  return true;
+  return ok;
 }
 
 // Unit ray direction of LiDAR column c, beam j from the FP32 tables, in FP64.
@@ -349,7 +340,7 @@ __device__ inline void lidar_dir(const SensorK& S, int c, int j, double* d) {
 
 struct LidarRay {
   static constexpr int C = 3;  // range, intensity, alpha
-  int pc, pb, bx, by;
+  int pc, pb, bx, by, ox, oy, wx;
   bool inside;
   double dt[3], d64[3];
   float dpix[3];
@@ -359,7 +350,9 @@ struct LidarRay {
     const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
-    const int ox = tx * a.S.tw, oy = ty * a.S.th;
+    ox = tx * a.S.tw;
+    oy = ty * a.S.th;
+    wx = WX;
     bx = ox + (w % WX) * 8;
     by = oy + (w / WX) * 8;
     pc = ox + lx;
@@ -372,9 +365,12 @@ struct LidarRay {
     dpix[2] = (float)(d64[2] - dt[2]);
   }
   __device__ size_t pix(const TileArgs& a) const { return (size_t)pb * a.S.W + pc; }
-  __device__ void stage(const TileArgs& a, uint32_t s, float4* dst) const { stage_lidar(a, s, dt, dst); }
+  __device__ uint2 stage(const TileArgs& a, uint32_t s, float4* dst) const { return stage_lidar(a, s, dt, dst); }
   __device__ bool miss(const float4* R) const {
     return misses_block_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), bx, by);
+  }
+  __device__ bool touches(uint2 rect, int w) const {
+    return !misses_block_wrap(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
   __device__ bool covered(const float4* R) const {
     return covers_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), pc, pb);
@@ -435,18 +431,77 @@ struct LidarRay {
 
 // ------------------------- generic compositing ---------------------------
 
+__device__ __forceinline__ float dpp_xor1(float v) {  // quad_perm [1,0,3,2]
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_xor2(float v) {  // quad_perm [2,3,0,1]
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+// ds_swizzle bit-mask mode inside 32-lane halves: lane -> lane ^ X
+template <int X>
+__device__ __forceinline__ float swz_xor(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (X << 10)));
+}
+
+// Sums the 16 per-lane gradient fields over the wave and adds each total to
+// the record's accumulator, as a butterfly transpose-reduction: every
+// exchange step halves the fields a lane holds and doubles the lanes each of
+// them is summed over (xor 1, 2 by DPP; xor 4, 8, 16 by swizzle; xor 32 by a
+// permute), leaving lane l < 16 with the wave total of field
+// 8 b0 + 4 b1 + 2 b2 + b3 (b_i = bit i of l), which it adds with one atomic.
+// All lanes must be active.
 __device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* gacc, size_t stride, int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+  float x8[8], x4[4], x2[2];
 #pragma unroll
-  for (int f = 0; f < kGradFields; ++f) {
-    const float v = wave_sum_last(g[f]);
-    if (lane == 63 && v != 0.0f) atomicAdd(gacc + (size_t)f * stride + s, v);
-  }
+  for (int i = 0; i < 8; ++i) x8[i] = (b0 ? g[i + 8] : g[i]) + dpp_xor1(b0 ? g[i] : g[i + 8]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x4[i] = (b1 ? x8[i + 4] : x8[i]) + dpp_xor2(b1 ? x8[i] : x8[i + 4]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) x2[i] = (b2 ? x4[i + 2] : x4[i]) + swz_xor<4>(b2 ? x4[i] : x4[i + 2]);
+  float x = (b3 ? x2[1] : x2[0]) + swz_xor<8>(b3 ? x2[0] : x2[1]);
+  x += swz_xor<16>(x);
+  x += __shfl_xor(x, 32, 64);
+  const int f = (b0 ? 8 : 0) + (b1 ? 4 : 0) + (b2 ? 2 : 0) + (b3 ? 1 : 0);
+  if (lane < 16 && x != 0.0f) atomicAdd(gacc + (size_t)f * stride + s, x);
 }
 
 template <int NT, class Ray, bool MARK>
 __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t L, uint32_t n_seg, uint32_t pbase,
                            uint32_t sg0, float* part, size_t ps, float T_accept, float& T, float* acc, uint32_t& last,
                            uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64, uint32_t& marked);
+
+// Stages pair records [base, min(base + NT, b1)) through LDS, one per thread,
+// and for every 64-record chunk c and wave w stores in s_mask[c][w] the bit
+// mask of the chunk's records whose rectangle touches wave w's 8x8 block.
+// A wave then walks only the set bits, in order.
+template <int NT, class Ray>
+__device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, uint32_t base, uint32_t b1,
+                                            float4 (*s_rec)[5], uint32_t* s_id, uint64_t (*s_mask)[NT / 64]) {
+  const int t = threadIdx.x, lane = t & 63;
+  const uint32_t k = base + t;
+  const bool valid = k < b1;
+  uint2 rect = make_uint2(0u, 0u);
+  if (valid) {
+    const uint32_t s = a.pval[k];
+    rect = ray.stage(a, s, s_rec[t]);
+    s_id[t] = s;
+  }
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    const uint64_t m = __ballot(valid && ray.touches(rect, w));
+    if (lane == 0) s_mask[t >> 6][w] = m;
+  }
+  __syncthreads();
+}
+
+// Wave-uniform copy of a mask word from LDS.
+__device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
+  const uint64_t m = *p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)m);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(m >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // Composites pairs [b0, b1) of the tile for every ray (or, kFinish, for the
 // rays marked in slot element `pe`, from their stored incoming state).
@@ -455,8 +510,9 @@ __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t
 //  kFinish:  writes the outputs of the marked rays.
 template <int NT, class Ray, FwdMode M>
 __device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, float4 (*s_rec)[5],
-                          uint32_t* s_id, float* part, size_t ps, size_t pe, const QueueArgs* q = nullptr,
-                          uint2 rg = make_uint2(0u, 0u), uint32_t n_seg = 0, uint32_t pbase = 0, uint32_t sg = 0) {
+                          uint32_t* s_id, uint64_t (*s_mask)[NT / 64], float* part, size_t ps, size_t pe,
+                          const QueueArgs* q = nullptr, uint2 rg = make_uint2(0u, 0u), uint32_t n_seg = 0,
+                          uint32_t pbase = 0, uint32_t sg = 0) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
@@ -477,36 +533,38 @@ __device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
       last = pu[kPartCount * ps + pe];
     }
   }
+  const int w = t >> 6;
   for (uint32_t base = b0; base < b1; base += NT) {
     if (__syncthreads_count(!done) == 0) break;
-    const uint32_t k = base + t;
-    if (k < b1) {
-      const uint32_t s = a.pval[k];
-      ray.stage(a, s, s_rec[t]);
-      s_id[t] = s;
-    }
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, b1 - base);
-    for (int j = 0; j < cnt; ++j) {
-      if (__ballot(!done) == 0) break;
-      if (ray.miss(s_rec[j])) continue;
-      if (done) continue;
-      n_eval += ray.covered(s_rec[j]) ? 1u : 0u;
-      PairEval e;
-      if (!ray.eval(a, s_rec[j], s_id[j], e, n64)) continue;
-      const float Tn = T * (1.0f - e.alpha);
-      if (Tn < a.O.T_min) {
-        done = true;
-        continue;
-      }
-      ++n_contrib;
-      const float wgt = e.alpha * T;
-      float f[C];
-      ray.feat(s_rec[j], e, f);
+    stage_batch<NT>(a, ray, base, b1, s_rec, s_id, s_mask);
+    const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
+    for (int c = 0; c < nch; ++c) {
+      uint64_t m = uniform_mask(&s_mask[c][w]);
+      while (m) {
+        if (__ballot(!done) == 0) {
+          c = nch;
+          break;
+        }
+        const int j = c * 64 + __builtin_ctzll(m);
+        m &= m - 1;
+        const float4* R = s_rec[j];
+        n_eval += (!done && ray.covered(R)) ? 1u : 0u;
+        PairEval e;
+        const bool hit = ray.eval(a, R, s_id[j], e, n64) && !done;
+        const float Tn = T * (1.0f - e.alpha);
+        const bool stop = hit && Tn < a.O.T_min;
+        done = done || stop;
+        if (hit && !stop) {
+          ++n_contrib;
+          const float wgt = e.alpha * T;
+          float f[C];
+          ray.feat(R, e, f);
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = fmaf(wgt, f[c], acc[c]);
-      T = Tn;
-      last = base + j + 1;
+          for (int c2 = 0; c2 < C; ++c2) acc[c2] = fmaf(wgt, f[c2], acc[c2]);
+          T = Tn;
+          last = base + j + 1;
+        }
+      }
     }
   }
   if (M == kPartial) {
@@ -644,7 +702,8 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
 // or the merge's (T_in, prefix) for a segment.
 template <int NT, class Ray>
 __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, const float* part, size_t ps,
-                          size_t pe, float4 (*s_rec)[5], uint32_t* s_id, uint32_t& s_max) {
+                          size_t pe, float4 (*s_rec)[5], uint32_t* s_id, uint64_t (*s_mask)[NT / 64],
+                          uint32_t& s_max) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x, lane = t & 63;
@@ -674,22 +733,23 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
   uint32_t n64 = 0;
+  const int w = t >> 6;
   for (uint32_t base = b0; base < end; base += NT) {
     __syncthreads();
-    const uint32_t k = base + t;
-    if (k < end) {
-      const uint32_t s = a.pval[k];
-      ray.stage(a, s, s_rec[t]);
-      s_id[t] = s;
-    }
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, end - base);
-    for (int j = 0; j < cnt; ++j) {
-      if (base + j >= wlast) break;
-      if (ray.miss(s_rec[j])) continue;
+    stage_batch<NT>(a, ray, base, end, s_rec, s_id, s_mask);
+    const int nch = (int)((min((uint32_t)NT, end - base) + 63) / 64);
+    for (int c = 0; c < nch; ++c) {
+      uint64_t m = uniform_mask(&s_mask[c][w]);
+      while (m) {
+      const int j = c * 64 + __builtin_ctzll(m);
+      m &= m - 1;
+      if (base + j >= wlast) {
+        c = nch;
+        break;
+      }
       const bool active = base + j < last;
       PairEval e;
-      const bool hit = active && ray.eval(a, s_rec[j], s_id[j], e, n64);
+      const bool hit = ray.eval(a, s_rec[j], s_id[j], e, n64) && active;
       float gr[kGradFields];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
@@ -710,6 +770,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         T = T * (1.0f - al);
       }
       if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.gacc, a.gacc_stride, lane);
+      }
     }
   }
 }
@@ -722,7 +783,7 @@ __device__ inline int sensor_of_tile(const QueueArgs& q, uint32_t gt) {
 
 template <int NT, bool BWD, class Ray>
 __device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, float4 (*s_rec)[5],
-                         uint32_t* s_id, uint32_t* s_u) {
+                         uint32_t* s_id, uint64_t (*s_mask)[NT / 64], uint32_t* s_u) {
   const Ray ray(a, tile);
   const uint2 rg = a.ranges[gt];
   const uint32_t len = rg.y - rg.x;
@@ -730,9 +791,9 @@ __device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
   if (n_seg == 1) {
     if (BWD)
-      bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, s_rec, s_id, s_u[1]);
+      bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, s_rec, s_id, s_mask, s_u[1]);
     else
-      fwd_range<NT, Ray, kWhole>(a, ray, rg.x, rg.y, s_rec, s_id, nullptr, 0, 0);
+      fwd_range<NT, Ray, kWhole>(a, ray, rg.x, rg.y, s_rec, s_id, s_mask, nullptr, 0, 0);
     return;
   }
   const uint32_t pbase = q.pslot_base[gt];
@@ -741,10 +802,10 @@ __device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32
   const uint32_t b1 = min(b0 + L, rg.y);
   const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
   if (BWD) {
-    bwd_range<NT>(a, ray, b0, b1, q.part, q.part_stride, pe, s_rec, s_id, s_u[1]);
+    bwd_range<NT>(a, ray, b0, b1, q.part, q.part_stride, pe, s_rec, s_id, s_mask, s_u[1]);
     return;
   }
-  fwd_range<NT, Ray, kPartial>(a, ray, b0, b1, s_rec, s_id, q.part, q.part_stride, pe);
+  fwd_range<NT, Ray, kPartial>(a, ray, b0, b1, s_rec, s_id, s_mask, q.part, q.part_stride, pe);
   // publish this segment (device-scope release: every XCD's L2 sees it),
   // then let the tile's last arrival merge after a device-scope acquire
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -767,6 +828,7 @@ template <int NT, bool BWD, int KINDS>
 __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
   __shared__ float4 s_rec[NT][5];
   __shared__ uint32_t s_id[NT];
+  __shared__ uint64_t s_mask[NT / 64][NT / 64];
   __shared__ uint32_t s_u[2];
   const uint32_t n_items = min(*q.n_items, q.cap_items);
   for (;;) {
@@ -780,16 +842,16 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
     const TileArgs& a = q.tiles[si];
     const int tile = (int)ts.x - q.tile_off[si];
     if ((KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE))
-      run_item<NT, BWD, CamRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_u);
+      run_item<NT, BWD, CamRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_mask, s_u);
     else if (KINDS & kKindLidar)
-      run_item<NT, BWD, LidarRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_u);
+      run_item<NT, BWD, LidarRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_mask, s_u);
   }
 }
 
 // Cooperative walk of the listed segments for their marked rays.
 template <int NT, class Ray>
 __device__ void finish_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
-                            float4 (*s_rec)[5], uint32_t* s_id) {
+                            float4 (*s_rec)[5], uint32_t* s_id, uint64_t (*s_mask)[NT / 64]) {
   const Ray ray(a, tile);
   const uint2 rg = a.ranges[gt];
   const uint32_t L = q.seg_len;
@@ -798,13 +860,15 @@ __device__ void finish_item(const QueueArgs& q, const TileArgs& a, int tile, uin
   const uint32_t b0 = rg.x + sg * L;
   const uint32_t b1 = min(b0 + L, rg.y);
   const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
-  fwd_range<NT, Ray, kFinish>(a, ray, b0, b1, s_rec, s_id, q.part, q.part_stride, pe, &q, rg, n_seg, pbase, sg);
+  fwd_range<NT, Ray, kFinish>(a, ray, b0, b1, s_rec, s_id, s_mask, q.part, q.part_stride, pe, &q, rg, n_seg, pbase,
+                              sg);
 }
 
 template <int NT, int KINDS>
 __global__ __launch_bounds__(NT) void k_blend_finish(QueueArgs q) {
   __shared__ float4 s_rec[NT][5];
   __shared__ uint32_t s_id[NT];
+  __shared__ uint64_t s_mask[NT / 64][NT / 64];
   __shared__ uint32_t s_it;
   const uint32_t n = min(q.hdr[3], q.pslot_cap);
   for (;;) {
@@ -818,9 +882,9 @@ __global__ __launch_bounds__(NT) void k_blend_finish(QueueArgs q) {
     const TileArgs& a = q.tiles[si];
     const int tile = (int)w.x - q.tile_off[si];
     if ((KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE))
-      finish_item<NT, CamRay>(q, a, tile, w.x, w.y, s_rec, s_id);
+      finish_item<NT, CamRay>(q, a, tile, w.x, w.y, s_rec, s_id, s_mask);
     else if (KINDS & kKindLidar)
-      finish_item<NT, LidarRay>(q, a, tile, w.x, w.y, s_rec, s_id);
+      finish_item<NT, LidarRay>(q, a, tile, w.x, w.y, s_rec, s_id, s_mask);
   }
 }
 

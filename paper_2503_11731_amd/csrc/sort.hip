@@ -58,7 +58,8 @@ struct RadixArgs {
   uint32_t count_const;
   uint32_t cap;
   int shift;
-  uint32_t* hist;
+  uint32_t* hist;   // [256][nb] digit counts, digit-major; scanned in place
+  uint32_t* hbsum;  // block sums of the digit-count scan
 };
 
 __device__ inline uint32_t radix_n(const RadixArgs& a) {
@@ -87,22 +88,66 @@ __global__ __launch_bounds__(256) void k_rs_hist(RadixArgs a) {
   }
 }
 
-__global__ __launch_bounds__(1024) void k_rs_scan(RadixArgs a) {
+// Exclusive scan of the 256 * nb digit counts (digit-major, so that every
+// block's digits land after all smaller digits of all blocks): coalesced
+// block reductions, one small top-level scan, then an in-order down-sweep.
+constexpr int kHScanItems = 4096;
+
+__global__ __launch_bounds__(256) void k_rs_hscan_reduce(RadixArgs a) {
+  __shared__ uint32_t s_w[4];
   const uint32_t n = radix_n(a);
-  const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
-  const uint32_t E = 256u * nb;
+  const uint32_t E = 256u * ((n + kRadixItems - 1) / kRadixItems);
+  const uint32_t base = blockIdx.x * kHScanItems;
+  uint32_t s = 0;
+  if (base < E) {
+#pragma unroll 4
+    for (int r = 0; r < kHScanItems / 256; ++r) {
+      const uint32_t i = base + r * 256 + threadIdx.x;
+      if (i < E) s += a.hist[i];
+    }
+  }
+  uint32_t tot;
+  block_excl_scan<256>(s, s_w, &tot);
+  if (threadIdx.x == 0) a.hbsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_rs_hscan_top(RadixArgs a, int nblk) {
   __shared__ uint32_t s_w[16];
-  const uint32_t per = (E + 1023) / 1024;
-  const uint32_t beg = threadIdx.x * per;
-  const uint32_t end = min(beg + per, E);
+  const int per = (nblk + 1023) / 1024;
+  const int beg = threadIdx.x * per;
+  const int end = min(beg + per, nblk);
   uint32_t sum = 0;
-  for (uint32_t i = beg; i < end; ++i) sum += a.hist[i];
+  for (int i = beg; i < end; ++i) sum += a.hbsum[i];
   uint32_t tot;
   uint32_t off = block_excl_scan<1024>(sum, s_w, &tot);
-  for (uint32_t i = beg; i < end; ++i) {
-    uint32_t x = a.hist[i];
-    a.hist[i] = off;
+  for (int i = beg; i < end; ++i) {
+    const uint32_t x = a.hbsum[i];
+    a.hbsum[i] = off;
     off += x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rs_hscan_down(RadixArgs a) {
+  __shared__ uint32_t s_w[4];
+  const uint32_t n = radix_n(a);
+  const uint32_t E = 256u * ((n + kRadixItems - 1) / kRadixItems);
+  const uint32_t base = blockIdx.x * kHScanItems;
+  if (base >= E) return;
+  constexpr int PER = kHScanItems / 256;
+  const uint32_t i0 = base + threadIdx.x * PER;
+  uint32_t v[PER];
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    v[r] = i0 + r < E ? a.hist[i0 + r] : 0u;
+    s += v[r];
+  }
+  uint32_t tot;
+  uint32_t off = block_excl_scan<256>(s, s_w, &tot) + a.hbsum[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    if (i0 + r < E) a.hist[i0 + r] = off;
+    off += v[r];
   }
 }
 
@@ -424,17 +469,26 @@ void launch_fill_f32(float* p, float v, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, v, n);
 }
 
-size_t radix_hist_words(uint32_t cap) { return 256ull * ((cap + kRadixItems - 1) / kRadixItems) + 256; }
+static size_t radix_nb(uint32_t cap) { return (cap + kRadixItems - 1) / kRadixItems; }
+static size_t radix_hscan_blocks(uint32_t cap) { return (256 * radix_nb(cap) + kHScanItems - 1) / kHScanItems; }
+
+size_t radix_hist_words(uint32_t cap) { return 256 * radix_nb(cap) + radix_hscan_blocks(cap) + 256; }
 
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32_t count_const, uint32_t cap,
                int bits, uint32_t* hist, hipStream_t st) {
   int cur = 0;
-  const unsigned nb_max = (cap + kRadixItems - 1) / kRadixItems;
+  const unsigned nb_max = (unsigned)radix_nb(cap);
   const unsigned grid = nb_max < 1 ? 1 : (nb_max < 2048 ? nb_max : 2048);
+  const int nhb = (int)radix_hscan_blocks(cap);
+  uint32_t* hbsum = hist + 256 * (size_t)nb_max;
   for (int shift = 0; shift < bits; shift += 8) {
-    RadixArgs a{key[cur], val[cur], key[cur ^ 1], val[cur ^ 1], count, count_const, cap, shift, hist};
+    RadixArgs a{key[cur], val[cur], key[cur ^ 1], val[cur ^ 1], count, count_const, cap, shift, hist, hbsum};
     hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, a);
+    if (nhb > 0) {
+      hipLaunchKernelGGL(k_rs_hscan_reduce, dim3(nhb), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(k_rs_hscan_top, dim3(1), dim3(1024), 0, st, a, nhb);
+      hipLaunchKernelGGL(k_rs_hscan_down, dim3(nhb), dim3(256), 0, st, a);
+    }
     hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(256), 0, st, a);
     cur ^= 1;
   }
