@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import render as R
+from .render import Renderer
 
 TILES_ANY = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (8, 32)]
 TILES_256 = [(16, 16), (32, 8), (8, 32)]
@@ -94,7 +94,7 @@ def _time_forward(shape, scene, sensor, pose, group_poses, tile, seg, opts, pair
     s = dict(sensor)
     s["scene"] = 0
     s["tile"] = tile
-    r = R.Renderer([shape], [s], opts=opts, pair_capacity=pair_capacity, device=device, segment_pairs=seg)
+    r = Renderer([shape], [s], opts=opts, pair_capacity=pair_capacity, device=device, segment_pairs=seg)
     outs = r.new_outputs()
     sp = pose.reshape(1, 12).contiguous()
     for _ in range(warmup):

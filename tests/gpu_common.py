@@ -68,6 +68,15 @@ def lidar_errors(got, ref, mask=None):
     return e
 
 
+def lidar_bad_rays(got, ref):
+    """Rays where any LiDAR channel is outside tolerance."""
+    g = got.astype(np.float64)
+    bad = np.abs(g[0] - ref["range"]) > TOL_DEPTH * np.maximum(1.0, np.abs(ref["range"]))
+    bad |= np.abs(g[1] - ref["intensity"]) > TOL
+    bad |= np.abs(g[2] - ref["alpha"]) > TOL
+    return bad
+
+
 def within(errs):
     return all(v <= (TOL_DEPTH if k in ("depth", "range") else TOL) for k, v in errs.items())
 
