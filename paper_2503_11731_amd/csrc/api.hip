@@ -370,6 +370,7 @@ void build_queue(gs_plan* p, RecordArrays& R, size_t rbase, void* workspace, hip
   a.pslot_base = reinterpret_cast<uint32_t*>(b + R.o_pslot);
   a.arrive = reinterpret_cast<uint32_t*>(b + R.o_arrive);
   a.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);
+  a.walk = reinterpret_cast<unsigned long long*>(b + R.o_walk);
   a.key = reinterpret_cast<uint32_t*>(b + R.o_qkey0);
   a.val = reinterpret_cast<uint32_t*>(b + R.o_qval0);
   a.items = reinterpret_cast<uint2*>(b + R.o_items);
@@ -403,7 +404,7 @@ QueueArgs queue_args(const gs_plan* p, const RecordArrays& R, size_t rbase, int 
   q.n_items = reinterpret_cast<const uint32_t*>(b + R.o_qhdr);
   q.hdr = reinterpret_cast<uint32_t*>(b + R.o_qhdr);
   q.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);
-  q.walk = reinterpret_cast<uint2*>(b + R.o_walk);
+  q.walk = reinterpret_cast<unsigned long long*>(b + R.o_walk);
   q.cap_items = R.cap_items;
   q.counter = reinterpret_cast<uint32_t*>(b + R.o_qhdr) + 2;
   q.arrive = reinterpret_cast<uint32_t*>(b + R.o_arrive);
@@ -434,7 +435,6 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       build_queue(p, s.R, s.base, workspace, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, outputs, nullptr, nullptr);
       launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, st);
-      if (s.R.pslot_cap) launch_blend_finish(q, s.R.rays, s.R.kinds, s.R.grid_fwd, st);
       stage_end(p, st, GS_STAGE_BLEND, ev);
     }
     return;
@@ -462,7 +462,6 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   build_queue(p, p->G, p->gbase, workspace, st);
   QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, outputs, nullptr, nullptr);
   launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, st);
-  if (p->G.pslot_cap) launch_blend_finish(q, p->G.rays, p->G.kinds, p->G.grid_fwd, st);
   stage_end(p, st, GS_STAGE_BLEND, ev);
 }
 
@@ -869,7 +868,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   if (!p || !workspace || !out) return fail(GS_ERR_INVALID_ARG, "null argument to gs_query_status");
   GS_HIP_TRY(hipStreamSynchronize(st));
   memset(out, 0, sizeof(*out));
-  bool over = false;
+  bool over = false, stalled = false;
   auto read = [&](size_t off, uint32_t* w) {
     return hipMemcpy(w, static_cast<const char*>(workspace) + off, 16 * 4, hipMemcpyDeviceToHost);
   };
@@ -879,6 +878,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
     if (e == hipSuccess) {
       out->work_items += h[0];
       out->segments += h[1];
+      stalled = stalled || h[6] != 0;
     }
     return e;
   };
@@ -912,6 +912,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   }
   out->overflow = over ? 1 : 0;
   if (over) return fail(GS_ERR_CAPACITY, "pair capacity exceeded; re-plan with a larger pair_capacity");
+  if (stalled) return fail(GS_ERR_HIP, "compositing work queue stalled (walk list inconsistent)");
   return ok();
 }
 

@@ -15,10 +15,12 @@
 //     accepting a segment whole while T * T_seg stays clear of T_min; a ray
 //     whose stop can fall inside segment s gets its incoming state stored in
 //     slot s, the slot is marked, and (tile, s) joins a walk list;
-//  3. a second persistent pass walks every listed segment cooperatively for
-//     its marked rays from their true incoming state, so the stop rule keeps
-//     its sequential meaning (a ray that then does not stop, which needs its
-//     FP32 product within rounding of T_min, finishes the merge on its own);
+//  3. once the main queue is drained, the same persistent workgroups walk
+//     every listed segment cooperatively for its marked rays from their true
+//     incoming state, so the stop rule keeps its sequential meaning (a ray
+//     that then does not stop, which needs its FP32 product within rounding
+//     of T_min, finishes the merge on its own); walks of tiles merged early
+//     overlap the rest of the queue;
 //  4. each reached segment keeps its incoming (T, prefix accumulators), so the
 //     adjoint processes every segment independently.
 //
@@ -52,6 +54,45 @@ constexpr uint32_t kWalk = 0xFFFFFFFFu;  // never a (last | stop bit) value: pai
 
 enum FwdMode { kWhole, kPartial, kFinish };
 
+// Device-coherent loads of partial state published by other workgroups
+// (possibly on other XCDs, after their device-scope release): these bypass
+// the reader's non-coherent L2 copy, so no acquire fence (which would
+// invalidate the whole L2 of the reader's XCD) is needed.
+__device__ __forceinline__ float ld_coh(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_coh(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// FP64 re-solve data of grazing-flagged records staged next to the batch:
+// up to kF64Slots records per batch (more fall back to global loads); a
+// staged record carries its slot + 1 in bits 8..15 of its flag word.
+constexpr int kF64Slots = 64;
+constexpr int kF64Doubles = kGrz + 3;  // grazing record + centre (pixel or unit direction)
+typedef double F64Slot[kF64Doubles];
+
+// Per-item constants of the per-pair test, loaded once per work item (read
+// from the TileArgs in the loop they would be re-fetched from the kernel
+// arguments at every pair).
+struct EvalK {
+  float lp;         // low-pass scale (camera: 1/sigma^2 per pixel^2; LiDAR: per rad^2)
+  float cutoff2, z_near, alpha_max, alpha_min, T_min;
+  bool lowpass;
+};
+
+__device__ __forceinline__ EvalK eval_consts(const TileArgs& a, float lp) {
+  EvalK k;
+  k.lp = lp;
+  k.cutoff2 = a.O.cutoff2;
+  k.z_near = a.S.z_near;
+  k.alpha_max = a.O.alpha_max;
+  k.alpha_min = a.O.alpha_min;
+  k.T_min = a.O.T_min;
+  k.lowpass = a.O.lowpass != 0;
+  return k;
+}
+
 struct PairEval {
   float alpha, u, v, z, r, dx, dy, dz3;  // dz3: LiDAR third delta component
   bool lp_used, clamped;
@@ -83,13 +124,47 @@ __device__ __forceinline__ bool covers_wrap(uint32_t cols, uint32_t rows, int x,
   return c_lo <= c_hi ? (c_lo <= x && x <= c_hi) : (x >= c_lo || x <= c_hi);
 }
 
+// Grazing re-solve in FP64 (the pair's h'2 is near zero, where the FP32
+// solve loses accuracy): G holds the record's FP64 plane rows and depth
+// numerator, c its FP64 centre.  Camera: G = P (2 x 3 rows as 6) + mu_z,
+// c = projected centre; LiDAR: G = Q (9) + |mu|, c = unit centre direction.
+__device__ __forceinline__ bool solve64_pinhole(const double* G, const double* c, double px, double py, float& u,
+                                                float& v, float& r, float& z) {
+  const double ddx = px - c[0];
+  const double ddy = py - c[1];
+  const double H0 = G[0] * ddx + G[1] * ddy;
+  const double H1 = G[2] * ddx + G[3] * ddy;
+  const double H2 = 1.0 + G[4] * ddx + G[5] * ddy;
+  const double rd = 1.0 / H2;
+  u = (float)(H0 * rd);
+  v = (float)(H1 * rd);
+  r = (float)rd;
+  z = (float)(G[6] * rd);
+  return H2 != 0.0;
+}
+
+__device__ __forceinline__ bool solve64_lidar(const double* G, const double* c, const double* d64, float& u, float& v,
+                                              float& r, float& z) {
+  const double e0 = d64[0] - c[0], e1 = d64[1] - c[1], e2 = d64[2] - c[2];
+  const double H0 = G[0] * e0 + G[1] * e1 + G[2] * e2;
+  const double H1 = G[3] * e0 + G[4] * e1 + G[5] * e2;
+  const double H2 = 1.0 + G[6] * e0 + G[7] * e1 + G[8] * e2;
+  const double rd = 1.0 / H2;
+  u = (float)(H0 * rd);
+  v = (float)(H1 * rd);
+  r = (float)rd;
+  z = (float)(G[9] * rd);
+  return H2 != 0.0;
+}
+
 // ----------------------------- camera -----------------------------------
 // Staged record (5 x float4):
 //  [0] pcx_rel, pcy_rel, P00, P01   [1] P10, P11, P20, P21
 //  [2] mu_z, log2 o, c0, c1          [3] c2, n0, n1, n2
 //  [4] flags, o, pixel columns lo|hi<<16, pixel rows lo|hi<<16
 __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint32_t s, float plx, float ply, int ox,
-                                             int oy, const TileArgs& a, PairEval& e, uint32_t& n64) {
+                                             int oy, const TileArgs& a, const EvalK& K, const F64Slot* f64,
+                                             PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2];
   const uint32_t flags = __float_as_uint(R[4].x);
@@ -104,30 +179,24 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   if (flags & kFlagGrazing) {  // the same record for the whole wave
     if (fabsf(h2) < 0.125f) {
       ++n64;
-      const double* G = a.grz + kGrz * (size_t)s;
-      const double* r64 = a.rec64 + kRec64 * (size_t)s;
-      const double ddx = ((double)ox + (double)plx) - r64[0];
-      const double ddy = ((double)oy + (double)ply) - r64[1];
-      const double H0 = G[0] * ddx + G[1] * ddy;
-      const double H1 = G[2] * ddx + G[3] * ddy;
-      const double H2 = 1.0 + G[4] * ddx + G[5] * ddy;
-      ok = H2 != 0.0;
-      const double rd = 1.0 / H2;
-      u = (float)(H0 * rd);
-      v = (float)(H1 * rd);
-      r = (float)rd;
-      z = (float)(G[6] * rd);
+      // from the record's LDS slot when it was staged there, else from global memory
+      const uint32_t slot = (flags >> 8) & 0xFFu;
+      const double px = (double)ox + (double)plx, py = (double)oy + (double)ply;
+      if (slot && f64)
+        ok = solve64_pinhole(f64[slot - 1], f64[slot - 1] + kGrz, px, py, u, v, r, z);
+      else
+        ok = solve64_pinhole(a.grz + kGrz * (size_t)s, a.rec64 + kRec64 * (size_t)s, px, py, u, v, r, z);
     }
   }
   const float rho = fmaf(u, u, v * v);
-  const float rl = a.O.lp * fmaf(dx, dx, dy * dy);
-  const bool lp_used = a.O.lowpass && !(rho <= rl);
+  const float rl = K.lp * fmaf(dx, dx, dy * dy);
+  const bool lp_used = K.lowpass && !(rho <= rl);
   const float rho_hat = lp_used ? rl : rho;
-  ok = ok && (rho_hat <= a.O.cutoff2) && (z > a.S.z_near);
+  ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
   float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q2.y));
-  const bool clamped = alpha > a.O.alpha_max;
-  if (clamped) alpha = a.O.alpha_max;
-  ok = ok && !(alpha < a.O.alpha_min);
+  const bool clamped = alpha > K.alpha_max;
+  if (clamped) alpha = K.alpha_max;
+  ok = ok && !(alpha < K.alpha_min);
   e.alpha = alpha;
   e.u = u;
   e.v = v;
@@ -162,8 +231,9 @@ struct CamRay {
   int px, py, ox, oy, bx, by, wx;
   float plx, ply;
   bool inside;
+  EvalK K;
 
-  __device__ CamRay(const TileArgs& a, int tile) {
+  __device__ CamRay(const TileArgs& a, int tile) : K(eval_consts(a, a.O.lp)) {
     const int WX = a.S.tw >> 3;
     wx = WX;
     const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
@@ -191,9 +261,11 @@ struct CamRay {
   __device__ bool covered(const float4* R) const {
     return covers(__float_as_uint(R[4].z), __float_as_uint(R[4].w), px, py);
   }
-  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, PairEval& e, uint32_t& n64) const {
-    return eval_pinhole(R, s, plx, ply, ox, oy, a, e, n64);
+  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
+                       uint32_t& n64) const {
+    return eval_pinhole(R, s, plx, ply, ox, oy, a, K, f64, e, n64);
   }
+  static __device__ float& flag_word(float4* R) { return R[4].x; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
     f[0] = R[2].z;
     f[1] = R[2].w;
@@ -277,7 +349,8 @@ __device__ __forceinline__ uint2 stage_lidar(const TileArgs& a, uint32_t s, cons
 }
 
 __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix,
-                                           const double* d64, const TileArgs& a, PairEval& e, uint32_t& n64) {
+                                           const double* d64, const TileArgs& a, const EvalK& K, const F64Slot* f64,
+                                           PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2], q3 = R[3];
   const uint32_t flags = __float_as_uint(q3.w);
@@ -293,29 +366,22 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   if (flags & kFlagGrazing) {  // the same record for the whole wave
     if (fabsf(h2) < 0.125f) {
       ++n64;
-      const double* G = a.grz + kGrz * (size_t)s;
-      const double* r64 = a.rec64 + kRec64 * (size_t)s;
-      const double e0 = d64[0] - r64[0], e1 = d64[1] - r64[1], e2 = d64[2] - r64[2];
-      const double H0 = G[0] * e0 + G[1] * e1 + G[2] * e2;
-      const double H1 = G[3] * e0 + G[4] * e1 + G[5] * e2;
-      const double H2 = 1.0 + G[6] * e0 + G[7] * e1 + G[8] * e2;
-      ok = H2 != 0.0;
-      const double rd = 1.0 / H2;
-      u = (float)(H0 * rd);
-      v = (float)(H1 * rd);
-      r = (float)rd;
-      z = (float)(G[9] * rd);
+      const uint32_t slot = (flags >> 8) & 0xFFu;
+      if (slot && f64)
+        ok = solve64_lidar(f64[slot - 1], f64[slot - 1] + kGrz, d64, u, v, r, z);
+      else
+        ok = solve64_lidar(a.grz + kGrz * (size_t)s, a.rec64 + kRec64 * (size_t)s, d64, u, v, r, z);
     }
   }
   const float rho = fmaf(u, u, v * v);
-  const float rl = a.S.lp_ang * fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-  const bool lp_used = a.O.lowpass && !(rho <= rl);
+  const float rl = K.lp * fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+  const bool lp_used = K.lowpass && !(rho <= rl);
   const float rho_hat = lp_used ? rl : rho;
-  ok = ok && (rho_hat <= a.O.cutoff2) && (z > a.S.z_near);
+  ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
   float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q3.y));
-  const bool clamped = alpha > a.O.alpha_max;
-  if (clamped) alpha = a.O.alpha_max;
-  ok = ok && !(alpha < a.O.alpha_min);
+  const bool clamped = alpha > K.alpha_max;
+  if (clamped) alpha = K.alpha_max;
+  ok = ok && !(alpha < K.alpha_min);
   e.alpha = alpha;
   e.u = u;
   e.v = v;
@@ -342,10 +408,11 @@ struct LidarRay {
   static constexpr int C = 3;  // range, intensity, alpha
   int pc, pb, bx, by, ox, oy, wx;
   bool inside;
+  EvalK K;
   double dt[3], d64[3];
   float dpix[3];
 
-  __device__ LidarRay(const TileArgs& a, int tile) {
+  __device__ LidarRay(const TileArgs& a, int tile) : K(eval_consts(a, a.S.lp_ang)) {
     const int WX = a.S.tw >> 3;
     const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -375,9 +442,11 @@ struct LidarRay {
   __device__ bool covered(const float4* R) const {
     return covers_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), pc, pb);
   }
-  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, PairEval& e, uint32_t& n64) const {
-    return eval_lidar(R, s, dpix, d64, a, e, n64);
+  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
+                       uint32_t& n64) const {
+    return eval_lidar(R, s, dpix, d64, a, K, f64, e, n64);
   }
+  static __device__ float& flag_word(float4* R) { return R[3].w; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
     f[0] = e.z;
     f[1] = R[3].z;
@@ -475,9 +544,23 @@ __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t
 // and for every 64-record chunk c and wave w stores in s_mask[c][w] the bit
 // mask of the chunk's records whose rectangle touches wave w's 8x8 block.
 // A wave then walks only the set bits, in order.
+// Shared-memory state of one compositing workgroup.
+template <int NT>
+struct BlendShared {
+  float4 rec[NT][5];
+  uint32_t id[NT];
+  uint64_t mask[NT / 64][NT / 64];
+  F64Slot f64[kF64Slots];
+  uint32_t u[6];  // [0] item, [1] flag / max last, [2] FP64 slot counter, [3] action, [4..5] walk entry
+};
+
 template <int NT, class Ray>
 __device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, uint32_t base, uint32_t b1,
-                                            float4 (*s_rec)[5], uint32_t* s_id, uint64_t (*s_mask)[NT / 64]) {
+                                            BlendShared<NT>& sh) {
+  float4 (*s_rec)[5] = sh.rec;
+  uint32_t* s_id = sh.id;
+  F64Slot* s_f64 = sh.f64;
+  uint32_t* s_fcount = &sh.u[2];
   const int t = threadIdx.x, lane = t & 63;
   const uint32_t k = base + t;
   const bool valid = k < b1;
@@ -486,11 +569,33 @@ __device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, u
     const uint32_t s = a.pval[k];
     rect = ray.stage(a, s, s_rec[t]);
     s_id[t] = s;
+    float& fw = Ray::flag_word(s_rec[t]);
+    const uint32_t flags = __float_as_uint(fw);
+    if (flags & kFlagGrazing) {
+      const uint32_t slot = atomicAdd(s_fcount, 1u);
+      if (slot < (uint32_t)kF64Slots) {
+        // 16-byte pieces, one at a time: flagged records are few, registers are not
+        const double2* G = reinterpret_cast<const double2*>(a.grz + kGrz * (size_t)s);
+        const double2* r64 = reinterpret_cast<const double2*>(a.rec64 + kRec64 * (size_t)s);
+        double* d = s_f64[slot];
+#pragma unroll 1
+        for (int i = 0; i < kGrz / 2; ++i) {
+          const double2 x = G[i];
+          d[2 * i] = x.x;
+          d[2 * i + 1] = x.y;
+        }
+        const double2 c01 = r64[0];
+        d[kGrz] = c01.x;
+        d[kGrz + 1] = c01.y;
+        d[kGrz + 2] = a.rec64[kRec64 * (size_t)s + 2];
+        fw = __uint_as_float(flags | ((slot + 1u) << 8));
+      }
+    }
   }
 #pragma unroll
   for (int w = 0; w < NT / 64; ++w) {
     const uint64_t m = __ballot(valid && ray.touches(rect, w));
-    if (lane == 0) s_mask[t >> 6][w] = m;
+    if (lane == 0) sh.mask[t >> 6][w] = m;
   }
   __syncthreads();
 }
@@ -509,10 +614,9 @@ __device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
 //  kPartial: from T = 1, writes the segment's partial state to `pe`;
 //  kFinish:  writes the outputs of the marked rays.
 template <int NT, class Ray, FwdMode M>
-__device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, float4 (*s_rec)[5],
-                          uint32_t* s_id, uint64_t (*s_mask)[NT / 64], float* part, size_t ps, size_t pe,
-                          const QueueArgs* q = nullptr, uint2 rg = make_uint2(0u, 0u), uint32_t n_seg = 0,
-                          uint32_t pbase = 0, uint32_t sg = 0) {
+__device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, BlendShared<NT>& sh,
+                          float* part, size_t ps, size_t pe, const QueueArgs* q = nullptr,
+                          uint2 rg = make_uint2(0u, 0u), uint32_t n_seg = 0, uint32_t pbase = 0, uint32_t sg = 0) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
@@ -524,22 +628,23 @@ __device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
   uint32_t last = M == kPartial ? 0u : b0, n_eval = 0, n_contrib = 0, n64 = 0;
   const uint32_t* pu = reinterpret_cast<const uint32_t*>(part);
   if (M == kFinish) {
-    const bool marked = ray.inside && pu[kPartLast * ps + pe] == kWalk;
+    const bool marked = ray.inside && ld_coh(pu + kPartLast * ps + pe) == kWalk;
     done = !marked;
     if (marked) {
-      T = part[kPartT * ps + pe];
+      T = ld_coh(part + kPartT * ps + pe);
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = part[c * ps + pe];
-      last = pu[kPartCount * ps + pe];
+      for (int c = 0; c < C; ++c) acc[c] = ld_coh(part + c * ps + pe);
+      last = ld_coh(pu + kPartCount * ps + pe);
     }
   }
   const int w = t >> 6;
   for (uint32_t base = b0; base < b1; base += NT) {
+    if (t == 0) sh.u[2] = 0u;
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<NT>(a, ray, base, b1, s_rec, s_id, s_mask);
+    stage_batch<NT>(a, ray, base, b1, sh);
     const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
     for (int c = 0; c < nch; ++c) {
-      uint64_t m = uniform_mask(&s_mask[c][w]);
+      uint64_t m = uniform_mask(&sh.mask[c][w]);
       while (m) {
         if (__ballot(!done) == 0) {
           c = nch;
@@ -547,12 +652,15 @@ __device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         }
         const int j = c * 64 + __builtin_ctzll(m);
         m &= m - 1;
-        const float4* R = s_rec[j];
-        n_eval += (!done && ray.covered(R)) ? 1u : 0u;
+        float4 R[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) R[i] = sh.rec[j][i];
+        const bool cov = ray.covered(R);  // evaluated whatever `done` is, so its LDS read joins the burst
+        n_eval += (cov && !done) ? 1u : 0u;
         PairEval e;
-        const bool hit = ray.eval(a, R, s_id[j], e, n64) && !done;
+        const bool hit = ray.eval(a, R, sh.id[j], sh.f64, e, n64) && !done;
         const float Tn = T * (1.0f - e.alpha);
-        const bool stop = hit && Tn < a.O.T_min;
+        const bool stop = hit && Tn < ray.K.T_min;
         done = done || stop;
         if (hit && !stop) {
           ++n_contrib;
@@ -582,7 +690,7 @@ __device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
     if (ray.inside) ray.write(a, T, acc, last);
   } else {
     // a marked ray that did not stop in this segment continues on its own
-    const bool marked = ray.inside && pu[kPartLast * ps + pe] == kWalk;
+    const bool marked = ray.inside && ld_coh(pu + kPartLast * ps + pe) == kWalk;
     if (marked) {
       uint32_t unused = 0;
       if (!done)
@@ -608,9 +716,9 @@ __device__ bool rewalk(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t 
     if (ray.miss(R)) continue;
     n_eval += ray.covered(R) ? 1u : 0u;
     PairEval e;
-    if (!ray.eval(a, R, s, e, n64)) continue;
+    if (!ray.eval(a, R, s, nullptr, e, n64)) continue;
     const float Tn = T * (1.0f - e.alpha);
-    if (Tn < a.O.T_min) return true;
+    if (Tn < ray.K.T_min) return true;
     ++n_contrib;
     const float wgt = e.alpha * T;
     float f[C];
@@ -638,17 +746,19 @@ __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t
   uint32_t* pu = reinterpret_cast<uint32_t*>(part);
   for (uint32_t sg = sg0; sg < n_seg; ++sg) {
     const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
-    const float Ts = part[kPartT * ps + pe];
-    const uint32_t ls = pu[kPartLast * ps + pe];
-    const uint32_t cnt = pu[kPartCount * ps + pe];
+    const float Ts = ld_coh(part + kPartT * ps + pe);
+    const uint32_t ls = ld_coh(pu + kPartLast * ps + pe);
+    const uint32_t cnt = ld_coh(pu + kPartCount * ps + pe);
     float as[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      as[c] = part[c * ps + pe];
+      as[c] = ld_coh(part + c * ps + pe);
       part[c * ps + pe] = acc[c];
     }
     part[kPartT * ps + pe] = T;
-    if (!(ls >> 31) && T * Ts >= T_accept) {
+    // whole segment: no local stop and either nothing composited (every pair
+    // skipped, so none can stop the ray) or T * T_seg clear of T_min
+    if (!(ls >> 31) && (Ts == 1.0f || T * Ts >= T_accept)) {
 #pragma unroll
       for (int c = 0; c < C; ++c) acc[c] = fmaf(T, as[c], acc[c]);
       T = T * Ts;
@@ -671,40 +781,52 @@ __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t
 
 // Merge run by the workgroup that completes a split tile; queues the
 // segments that hold some ray's stop for the cooperative walk.
+//
+// Walk-list protocol: the merged state is published (device-scope release)
+// before any walk entry of the tile is listed; an entry is listed by
+// reserving an index (hdr[3]) and then storing the packed (tile, segment)
+// over the cleared sentinel; the tile then leaves the pending-merge count
+// (hdr[5], release).  Consumers pop indices below hdr[3] and wait for the
+// entry to appear.
 template <int NT, class Ray>
 __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray, uint32_t gt, uint2 rg,
                            uint32_t n_seg, uint32_t pbase) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
-  uint32_t n_eval = 0, n_contrib = 0, n64 = 0;
+  uint32_t n_eval = 0, n_contrib = 0, n64 = 0, marked = 0;
   if (ray.inside) {
     float T = 1.0f;
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    uint32_t last = rg.x, marked = 0;
+    uint32_t last = rg.x;
     (void)merge_from<NT, Ray, true>(a, ray, rg, q.seg_len, n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc,
                                 last, n_eval, n_contrib, n64, marked);
-    if (marked == 0) {
-      ray.write(a, T, acc, last);
-    } else {
-      const uint32_t slot = pbase + marked - 1;
-      if (atomicCAS(q.slot_flag + slot, 0u, 1u) == 0u) {
-        const uint32_t w = atomicAdd(q.hdr + 3, 1u);
-        if (w < q.pslot_cap) q.walk[w] = make_uint2(gt, marked - 1);
-      }
-    }
+    if (marked == 0) ray.write(a, T, acc, last);
   }
   count_pairs(a.status, n_eval, n_contrib, n64);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (marked) {
+    const uint32_t slot = pbase + marked - 1;
+    if (atomicCAS(q.slot_flag + slot, 0u, 1u) == 0u) {
+      const uint32_t w = atomicAdd(q.hdr + 3, 1u);
+      if (w < q.pslot_cap)
+        __hip_atomic_store(q.walk + w, ((unsigned long long)gt << 32) | (marked - 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(q.hdr + 5, 0xFFFFFFFFu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Adjoint over pairs [b0, b1); the incoming state is (1, 0) for a whole tile
 // or the merge's (T_in, prefix) for a segment.
 template <int NT, class Ray>
 __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, const float* part, size_t ps,
-                          size_t pe, float4 (*s_rec)[5], uint32_t* s_id, uint64_t (*s_mask)[NT / 64],
-                          uint32_t& s_max) {
+                          size_t pe, BlendShared<NT>& sh) {
 #pragma clang fp contract(off)
+  uint32_t& s_max = sh.u[1];
   constexpr int C = Ray::C;
   const int t = threadIdx.x, lane = t & 63;
   const size_t HW = (size_t)a.S.W * a.S.H;
@@ -735,11 +857,12 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
   uint32_t n64 = 0;
   const int w = t >> 6;
   for (uint32_t base = b0; base < end; base += NT) {
+    if (t == 0) sh.u[2] = 0u;
     __syncthreads();
-    stage_batch<NT>(a, ray, base, end, s_rec, s_id, s_mask);
+    stage_batch<NT>(a, ray, base, end, sh);
     const int nch = (int)((min((uint32_t)NT, end - base) + 63) / 64);
     for (int c = 0; c < nch; ++c) {
-      uint64_t m = uniform_mask(&s_mask[c][w]);
+      uint64_t m = uniform_mask(&sh.mask[c][w]);
       while (m) {
       const int j = c * 64 + __builtin_ctzll(m);
       m &= m - 1;
@@ -749,7 +872,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
       }
       const bool active = base + j < last;
       PairEval e;
-      const bool hit = ray.eval(a, s_rec[j], s_id[j], e, n64) && active;
+      const bool hit = ray.eval(a, sh.rec[j], sh.id[j], sh.f64, e, n64) && active;
       float gr[kGradFields];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
@@ -757,7 +880,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         const float al = e.alpha;
         const float wgt = al * T;
         float f[C];
-        ray.feat(s_rec[j], e, f);
+        ray.feat(sh.rec[j], e, f);
         const float inv1m = 1.0f / (1.0f - al);
         float dal = 0.0f;
 #pragma unroll
@@ -766,10 +889,10 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           const float S = O[c] - A[c];
           dal += g[c] * (T * f[c] - S * inv1m);
         }
-        ray.grads(a, s_rec[j], e, dal, wgt, g, gr);
+        ray.grads(a, sh.rec[j], e, dal, wgt, g, gr);
         T = T * (1.0f - al);
       }
-      if (__ballot(hit) != 0) flush_grads(gr, s_id[j], a.gacc, a.gacc_stride, lane);
+      if (__ballot(hit) != 0) flush_grads(gr, sh.id[j], a.gacc, a.gacc_stride, lane);
       }
     }
   }
@@ -782,8 +905,9 @@ __device__ inline int sensor_of_tile(const QueueArgs& q, uint32_t gt) {
 }
 
 template <int NT, bool BWD, class Ray>
-__device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, float4 (*s_rec)[5],
-                         uint32_t* s_id, uint64_t (*s_mask)[NT / 64], uint32_t* s_u) {
+__device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
+                         BlendShared<NT>& sh) {
+  uint32_t* s_u = sh.u;
   const Ray ray(a, tile);
   const uint2 rg = a.ranges[gt];
   const uint32_t len = rg.y - rg.x;
@@ -791,9 +915,9 @@ __device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
   if (n_seg == 1) {
     if (BWD)
-      bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, s_rec, s_id, s_mask, s_u[1]);
+      bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, sh);
     else
-      fwd_range<NT, Ray, kWhole>(a, ray, rg.x, rg.y, s_rec, s_id, s_mask, nullptr, 0, 0);
+      fwd_range<NT, Ray, kWhole>(a, ray, rg.x, rg.y, sh, nullptr, 0, 0);
     return;
   }
   const uint32_t pbase = q.pslot_base[gt];
@@ -802,56 +926,27 @@ __device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32
   const uint32_t b1 = min(b0 + L, rg.y);
   const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
   if (BWD) {
-    bwd_range<NT>(a, ray, b0, b1, q.part, q.part_stride, pe, s_rec, s_id, s_mask, s_u[1]);
+    bwd_range<NT>(a, ray, b0, b1, q.part, q.part_stride, pe, sh);
     return;
   }
-  fwd_range<NT, Ray, kPartial>(a, ray, b0, b1, s_rec, s_id, s_mask, q.part, q.part_stride, pe);
-  // publish this segment (device-scope release: every XCD's L2 sees it),
-  // then let the tile's last arrival merge after a device-scope acquire
+  fwd_range<NT, Ray, kPartial>(a, ray, b0, b1, sh, q.part, q.part_stride, pe);
+  // publish this segment (device-scope release: written back from this XCD's
+  // L2), then let the tile's last arrival merge
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) s_u[1] = (atomicAdd(q.arrive + gt, 1u) + 1u == n_seg) ? 1u : 0u;
   __syncthreads();
-  if (s_u[1]) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    merge_tile<NT>(q, a, ray, gt, rg, n_seg, pbase);
-  }
+  if (s_u[1]) merge_tile<NT>(q, a, ray, gt, rg, n_seg, pbase);  // partials are read device-coherently
 }
 
 // Sensor kinds a launch may meet (bit 0 camera, bit 1 LiDAR): single-kind
 // launches leave the other kind's code and registers out.
 constexpr int kKindCam = 1, kKindLidar = 2, kKindBoth = 3;
 
-// Persistent compositing: each workgroup pops items (heaviest first) with one
-// atomic per item until the queue is drained.
-template <int NT, bool BWD, int KINDS>
-__global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
-  __shared__ float4 s_rec[NT][5];
-  __shared__ uint32_t s_id[NT];
-  __shared__ uint64_t s_mask[NT / 64][NT / 64];
-  __shared__ uint32_t s_u[2];
-  const uint32_t n_items = min(*q.n_items, q.cap_items);
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_u[0] = atomicAdd(q.counter, 1u);
-    __syncthreads();
-    const uint32_t it = s_u[0];
-    if (it >= n_items) break;
-    const uint2 ts = q.items[q.queue[it]];
-    const int si = sensor_of_tile(q, ts.x);
-    const TileArgs& a = q.tiles[si];
-    const int tile = (int)ts.x - q.tile_off[si];
-    if ((KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE))
-      run_item<NT, BWD, CamRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_mask, s_u);
-    else if (KINDS & kKindLidar)
-      run_item<NT, BWD, LidarRay>(q, a, tile, ts.x, ts.y, s_rec, s_id, s_mask, s_u);
-  }
-}
-
-// Cooperative walk of the listed segments for their marked rays.
+// Cooperative walk of a listed segment for its marked rays.
 template <int NT, class Ray>
 __device__ void finish_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
-                            float4 (*s_rec)[5], uint32_t* s_id, uint64_t (*s_mask)[NT / 64]) {
+                            BlendShared<NT>& sh) {
   const Ray ray(a, tile);
   const uint2 rg = a.ranges[gt];
   const uint32_t L = q.seg_len;
@@ -860,31 +955,117 @@ __device__ void finish_item(const QueueArgs& q, const TileArgs& a, int tile, uin
   const uint32_t b0 = rg.x + sg * L;
   const uint32_t b1 = min(b0 + L, rg.y);
   const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
-  fwd_range<NT, Ray, kFinish>(a, ray, b0, b1, s_rec, s_id, s_mask, q.part, q.part_stride, pe, &q, rg, n_seg, pbase,
-                              sg);
+  fwd_range<NT, Ray, kFinish>(a, ray, b0, b1, sh, q.part, q.part_stride, pe, &q, rg, n_seg, pbase, sg);
 }
 
-template <int NT, int KINDS>
-__global__ __launch_bounds__(NT) void k_blend_finish(QueueArgs q) {
-  __shared__ float4 s_rec[NT][5];
-  __shared__ uint32_t s_id[NT];
-  __shared__ uint64_t s_mask[NT / 64][NT / 64];
-  __shared__ uint32_t s_it;
-  const uint32_t n = min(q.hdr[3], q.pslot_cap);
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bound on every wait of the walk queue (polls of ~128 cycles): far above
+// any drain time, so a stall can only come from a broken invariant; it is
+// then reported (hdr[6]) instead of hanging.
+constexpr uint32_t kSpinLimit = 1u << 21;
+constexpr uint64_t kNoWalk = ~0ull;
+
+enum { kActExit = 0, kActItem = 1, kActWalk = 2 };
+
+// Waits (bounded) for walk entry `idx` to be stored after its reservation.
+__device__ bool take_walk(const QueueArgs& q, uint32_t idx, uint32_t* u) {
+  for (uint32_t w = 0; w < kSpinLimit; ++w) {
+    const uint64_t e = __hip_atomic_load(q.walk + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (e != kNoWalk) {
+      u[4] = (uint32_t)(e >> 32);
+      u[5] = (uint32_t)e;
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+// Thread 0 picks the workgroup's next action.  Listed walks come first (each
+// completes a split tile): one compare-and-swap attempt on the walk counter,
+// which on failure simply falls through.  Then a main-queue item (heaviest
+// first, one atomic per item).  With the main queue drained, the workgroup
+// takes a walk ticket (one atomic) and waits until that index is listed, or
+// leaves once no split tile is left to merge and the ticket lies past the
+// list (forward pass only; the adjoint has no walks).
+__device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t n_items, bool walks, uint32_t* u) {
+  if (walks) {
+    const uint32_t cnt = min(load_agent(q.hdr + 3), q.pslot_cap);
+    const uint32_t pop = load_agent(q.hdr + 4);
+    if (pop < cnt && atomicCAS(q.hdr + 4, pop, pop + 1) == pop) {
+      if (take_walk(q, pop, u)) return kActWalk;
+      atomicOr(q.hdr + 6, 1u);
+      return kActExit;
+    }
+  }
+  if (main_left) {
+    const uint32_t it = atomicAdd(q.counter, 1u);
+    if (it < n_items) {
+      u[0] = it;
+      return kActItem;
+    }
+    main_left = false;
+  }
+  if (!walks) return kActExit;
+  const uint32_t ticket = atomicAdd(q.hdr + 4, 1u);
+  for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
+    if (ticket < min(load_agent(q.hdr + 3), q.pslot_cap)) {
+      if (take_walk(q, ticket, u)) return kActWalk;
+      break;
+    }
+    // no split tile left to merge (confirmed with an acquire, so every walk
+    // its merge listed is counted) and the ticket is past the list: done
+    if (load_agent(q.hdr + 5) == 0 &&
+        __hip_atomic_load(q.hdr + 5, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+        ticket >= min(load_agent(q.hdr + 3), q.pslot_cap))
+      return kActExit;
+    __builtin_amdgcn_s_sleep(8);
+  }
+  atomicOr(q.hdr + 6, 1u);
+  return kActExit;
+}
+
+// Persistent compositing over (tile, segment) items and, in the forward pass,
+// the walk entries the merges list.
+template <int NT, bool BWD, int KINDS>
+__global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
+  __shared__ BlendShared<NT> sh;
+  uint32_t* s_u = sh.u;
+  const uint32_t n_items = min(*q.n_items, q.cap_items);
+  bool main_left = true;  // thread 0 only
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_it = atomicAdd(q.hdr + 4, 1u);
+    if (threadIdx.x == 0) s_u[3] = next_action(q, main_left, n_items, !BWD && q.pslot_cap > 0, s_u);
     __syncthreads();
-    const uint32_t it = s_it;
-    if (it >= n) break;
-    const uint2 w = q.walk[it];
-    const int si = sensor_of_tile(q, w.x);
+    const uint32_t act = s_u[3];
+    if (act == kActExit) break;
+    uint32_t gt, sg;
+    if (act == kActItem) {
+      const uint2 ts = q.items[q.queue[s_u[0]]];
+      gt = ts.x;
+      sg = ts.y;
+    } else {
+      gt = s_u[4];  // its slot state is read device-coherently
+      sg = s_u[5];
+    }
+    const int si = sensor_of_tile(q, gt);
     const TileArgs& a = q.tiles[si];
-    const int tile = (int)w.x - q.tile_off[si];
-    if ((KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE))
-      finish_item<NT, CamRay>(q, a, tile, w.x, w.y, s_rec, s_id, s_mask);
-    else if (KINDS & kKindLidar)
-      finish_item<NT, LidarRay>(q, a, tile, w.x, w.y, s_rec, s_id, s_mask);
+    const int tile = (int)gt - q.tile_off[si];
+    const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
+    if (act == kActItem) {
+      if (cam)
+        run_item<NT, BWD, CamRay>(q, a, tile, gt, sg, sh);
+      else if (KINDS & kKindLidar)
+        run_item<NT, BWD, LidarRay>(q, a, tile, gt, sg, sh);
+    } else if (!BWD) {
+      if (cam)
+        finish_item<NT, CamRay>(q, a, tile, gt, sg, sh);
+      else if (KINDS & kKindLidar)
+        finish_item<NT, LidarRay>(q, a, tile, gt, sg, sh);
+    }
   }
 }
 
@@ -901,18 +1082,6 @@ void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool 
     else                                                                                   \
       hipLaunchKernelGGL((k_blend_queue<NT, false, K>), dim3(grid), dim3(NT), 0, st, q);   \
     return;                                                                                \
-  }
-#define CASE(NT) GS_KINDS(KCASE, NT)
-  GS_TILE_RAYS(CASE)
-#undef CASE
-#undef KCASE
-}
-
-void launch_blend_finish(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st) {
-#define KCASE(NT, K)                                                                  \
-  if (rays == NT && kinds == K) {                                                     \
-    hipLaunchKernelGGL((k_blend_finish<NT, K>), dim3(grid), dim3(NT), 0, st, q);      \
-    return;                                                                           \
   }
 #define CASE(NT) GS_KINDS(KCASE, NT)
   GS_TILE_RAYS(CASE)

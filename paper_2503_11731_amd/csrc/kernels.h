@@ -64,14 +64,15 @@ struct QueueArgs {
   const uint32_t* queue;     // item ids, heaviest first
   const uint2* items;        // item id -> (record-space tile id, segment)
   const uint32_t* n_items;   // device count (hdr[0])
-  uint32_t* hdr;             // [0] items [1] slots [2] queue counter [3] walk count [4] walk counter
+  uint32_t* hdr;             // [0] items [1] slots [2] queue counter [3] walks listed [4] walks taken
+                             // [5] split tiles left to merge [6] queue stalled
   uint32_t cap_items;
   uint32_t* counter;         // zeroed before each launch
   uint32_t* arrive;          // per tile: segments finished (forward)
   const uint32_t* pslot_base;  // per tile: first partial-state slot
   float* part;               // [11][pslot_cap * rays per tile]
   uint32_t* slot_flag;       // per slot: listed for the cooperative walk
-  uint2* walk;               // walk list: (record-space tile id, segment)
+  unsigned long long* walk;  // walk list: tile << 32 | segment; cleared to ~0 per forward
   size_t part_stride;        // elements per plane
   uint32_t pslot_cap;
   uint32_t seg_len;          // segment length L (pairs)
@@ -125,6 +126,7 @@ struct SegScanArgs {
   uint32_t* pslot_base;
   uint32_t* arrive;
   uint32_t* slot_flag;
+  unsigned long long* walk;
   uint32_t* key;
   uint32_t* val;
   uint2* items;
@@ -140,7 +142,6 @@ void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipS
 // blend.hip
 // kinds: bit 0 camera, bit 1 LiDAR (the sensor kinds the launch serves)
 void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, hipStream_t st);
-void launch_blend_finish(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st);
 int blend_blocks_per_cu(int rays, int kinds, bool backward);
 bool tile_shape_supported(int tw, int th);
 

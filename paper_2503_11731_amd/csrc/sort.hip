@@ -380,6 +380,8 @@ __global__ __launch_bounds__(1024) void k_seg_top(SegScanArgs a, int nblk) {
     a.hdr[2] = 0u;
     a.hdr[3] = 0u;
     a.hdr[4] = 0u;
+    a.hdr[5] = 0u;
+    a.hdr[6] = 0u;
     if (tx > a.cap_items || ty > a.pslot_cap) a.status[kStOverflow] = 1u;
   }
 }
@@ -407,8 +409,15 @@ __global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
     if (t < a.n_tiles) {
       a.pslot_base[t] = iy;
       a.arrive[t] = 0u;
-      if (c[r].y)
-        for (uint32_t k = 0; k < c[r].y && iy + k < a.pslot_cap; ++k) a.slot_flag[iy + k] = 0u;
+      if (c[r].y && iy + c[r].y <= a.pslot_cap) {
+        // a split tile: clear its slots' walk flags and as many walk-list
+        // entries, and count it among the tiles left to merge
+        for (uint32_t k = 0; k < c[r].y; ++k) {
+          a.slot_flag[iy + k] = 0u;
+          a.walk[iy + k] = ~0ull;
+        }
+        atomicAdd(a.hdr + 5, 1u);
+      }
       const uint2 rg = a.ranges[t];
       const uint32_t len = rg.y - rg.x;
       for (uint32_t sg = 0; sg < c[r].x; ++sg) {
