@@ -437,7 +437,7 @@ def main():
                    "rays": rays, "surfels": sc.n, "frames_per_step": 1},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_blend_pinhole<16,16>", "avg_launch_ms": blend_s * 1e3},
+                     "kernel": "k_blend_queue<256, false, 1> (forward compositing, camera)", "avg_launch_ms": blend_s * 1e3},
     }
     extra = {"wall_s_timed": wall, "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
              "pairs": status["pairs"][0], "evaluated_pairs": status["evaluated"],

@@ -188,8 +188,9 @@ enum gs_stage {
   GS_STAGE_DEPTH_SORT,     /* radix sort of surfels by depth key             */
   GS_STAGE_EMIT,           /* tile-count scan and pair emission              */
   GS_STAGE_TILE_SORT,      /* stable radix sort of pairs by tile             */
-  GS_STAGE_RANGES,         /* per-tile ranges                                */
-  GS_STAGE_BLEND,          /* forward compositing (one kernel per sensor)    */
+  GS_STAGE_RANGES,         /* per-tile ranges and compositing work items     */
+  GS_STAGE_BLEND,          /* forward compositing (one persistent launch per
+                              record space)                                  */
   GS_STAGE_BLEND_BWD,      /* adjoint compositing                            */
   GS_STAGE_SPLAT_BWD,      /* per-surfel adjoint                             */
   GS_N_STAGES

@@ -433,6 +433,8 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       sort_and_bin(p, s.R, s.base, std::vector<int>{(int)si}, workspace, st);
       ev = stage_begin(p, st);
       build_queue(p, s.R, s.base, workspace, st);
+      stage_end(p, st, GS_STAGE_RANGES, ev);
+      ev = stage_begin(p, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, outputs, nullptr, nullptr);
       launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, st);
       stage_end(p, st, GS_STAGE_BLEND, ev);
@@ -460,6 +462,8 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   (void)g;
   ev = stage_begin(p, st);
   build_queue(p, p->G, p->gbase, workspace, st);
+  stage_end(p, st, GS_STAGE_RANGES, ev);
+  ev = stage_begin(p, st);
   QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, outputs, nullptr, nullptr);
   launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, st);
   stage_end(p, st, GS_STAGE_BLEND, ev);
