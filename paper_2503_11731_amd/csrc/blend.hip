@@ -52,7 +52,6 @@ constexpr float kInv2Ln2 = 0.7213475204444817f;  // 1 / (2 ln 2)
 enum { kPartT = 8, kPartLast = 9, kPartCount = 10 };
 constexpr uint32_t kWalk = 0xFFFFFFFFu;  // never a (last | stop bit) value: pair ids < 2^31 - 1
 
-enum FwdMode { kWhole, kPartial, kFinish };
 
 // Device-coherent loads of partial state published by other workgroups
 // (possibly on other XCDs, after their device-scope release): these bypass
@@ -72,9 +71,17 @@ constexpr int kF64Slots = 64;
 constexpr int kF64Doubles = kGrz + 3;  // grazing record + centre (pixel or unit direction)
 typedef double F64Slot[kF64Doubles];
 
-// Per-item constants of the per-pair test, loaded once per work item (read
-// from the TileArgs in the loop they would be re-fetched from the kernel
-// arguments at every pair).
+// Copy of a uniform value held in a vector register: the pair loop runs
+// short of scalar registers, and a constant kept there would be re-fetched
+// from the kernel arguments at every pair.
+__device__ __forceinline__ float in_vgpr(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+
+// Per-item constants of the per-pair test, loaded once per work item and
+// kept in vector registers.
 struct EvalK {
   float lp;         // low-pass scale (camera: 1/sigma^2 per pixel^2; LiDAR: per rad^2)
   float cutoff2, z_near, alpha_max, alpha_min, T_min;
@@ -83,12 +90,12 @@ struct EvalK {
 
 __device__ __forceinline__ EvalK eval_consts(const TileArgs& a, float lp) {
   EvalK k;
-  k.lp = lp;
-  k.cutoff2 = a.O.cutoff2;
-  k.z_near = a.S.z_near;
-  k.alpha_max = a.O.alpha_max;
-  k.alpha_min = a.O.alpha_min;
-  k.T_min = a.O.T_min;
+  k.lp = in_vgpr(lp);
+  k.cutoff2 = in_vgpr(a.O.cutoff2);
+  k.z_near = in_vgpr(a.S.z_near);
+  k.alpha_max = in_vgpr(a.O.alpha_max);
+  k.alpha_min = in_vgpr(a.O.alpha_min);
+  k.T_min = in_vgpr(a.O.T_min);
   k.lowpass = a.O.lowpass != 0;
   return k;
 }
@@ -124,6 +131,36 @@ __device__ __forceinline__ bool covers_wrap(uint32_t cols, uint32_t rows, int x,
   return c_lo <= c_hi ? (c_lo <= x && x <= c_hi) : (x >= c_lo || x <= c_hi);
 }
 
+// Lanes (lane = 8 y + x) of the 8x8 block at (bx, by) inside the inclusive
+// column range [c0, c1] and row range [r0, r1]; wave-uniform (scalar) work.
+__device__ __forceinline__ uint64_t block_lanes(int c0, int c1, int r0, int r1, int bx, int by) {
+  const int x0 = max(c0 - bx, 0), x1 = min(c1 - bx, 7), y0 = max(r0 - by, 0), y1 = min(r1 - by, 7);
+  if (x0 > x1 || y0 > y1) return 0ull;
+  const uint64_t cols = (uint64_t)((0xFFu >> (7 - x1)) & (0xFFu << x0)) * 0x0101010101010101ull;
+  const uint64_t rows = (~0ull >> (8 * (7 - y1))) & (~0ull << (8 * y0));
+  return cols & rows;
+}
+
+__device__ __forceinline__ uint64_t cover_lanes_rect(uint32_t cols, uint32_t rows, int bx, int by) {
+  return block_lanes((int)(cols & 0xFFFF), (int)(cols >> 16), (int)(rows & 0xFFFF), (int)(rows >> 16), bx, by);
+}
+
+// Columns may wrap (c_lo > c_hi means [c_lo, W) u [0, c_hi]).
+__device__ __forceinline__ uint64_t cover_lanes_wrap(uint32_t cols, uint32_t rows, int bx, int by) {
+  const int c_lo = (int)(cols & 0xFFFF), c_hi = (int)(cols >> 16), r_lo = (int)(rows & 0xFFFF),
+            r_hi = (int)(rows >> 16);
+  if (c_lo <= c_hi) return block_lanes(c_lo, c_hi, r_lo, r_hi, bx, by);
+  return block_lanes(c_lo, 0x7FFF, r_lo, r_hi, bx, by) | block_lanes(0, c_hi, r_lo, r_hi, bx, by);
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// Reads a wave-uniform 32-bit word (the same LDS record for every lane) into
+// a scalar register.
+__device__ __forceinline__ uint32_t uniform_u32(float v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(v));
+}
+
 // Grazing re-solve in FP64 (the pair's h'2 is near zero, where the FP32
 // solve loses accuracy): G holds the record's FP64 plane rows and depth
 // numerator, c its FP64 centre.  Camera: G = P (2 x 3 rows as 6) + mu_z,
@@ -157,6 +194,23 @@ __device__ __forceinline__ bool solve64_lidar(const double* G, const double* c, 
   return H2 != 0.0;
 }
 
+// A surfel's record as read from global memory: 16 floats and its 4 doubles
+// (camera: projected centre, -, packed pixel rectangle; LiDAR: unit centre
+// direction, -), turned into the staged form per tile by the ray kind.
+struct RawRec {
+  float4 r[4];
+  double2 d[2];
+};
+
+__device__ __forceinline__ void load_rec(const TileArgs& a, uint32_t s, RawRec& x) {
+  const float4* r = a.rec + 4 * (size_t)s;
+  const double2* r64 = reinterpret_cast<const double2*>(a.rec64 + kRec64 * (size_t)s);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x.r[i] = r[i];
+  x.d[0] = r64[0];
+  x.d[1] = r64[1];
+}
+
 // ----------------------------- camera -----------------------------------
 // Staged record (5 x float4):
 //  [0] pcx_rel, pcy_rel, P00, P01   [1] P10, P11, P20, P21
@@ -167,7 +221,7 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
                                              PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2];
-  const uint32_t flags = __float_as_uint(R[4].x);
+  const uint32_t flags = uniform_u32(R[4].x);
   const float dx = plx - q0.x;
   const float dy = ply - q0.y;
   const float h0 = fmaf(q0.z, dx, q0.w * dy);
@@ -209,13 +263,12 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   return ok;
 }
 
-__device__ __forceinline__ uint2 stage_pinhole(const TileArgs& a, uint32_t s, int ox, int oy, float4* dst) {
-  const float4* r = a.rec + 4 * (size_t)s;
-  const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-  const double* r64 = a.rec64 + kRec64 * (size_t)s;
-  const float pcx = (float)(r64[0] - (double)ox);
-  const float pcy = (float)(r64[1] - (double)oy);
-  const uint2 rect = *reinterpret_cast<const uint2*>(r64 + 3);
+__device__ __forceinline__ uint2 stage_pinhole(const RawRec& x, int ox, int oy, float4* dst) {
+  const float4 r0 = x.r[0], r1 = x.r[1], r2 = x.r[2], r3 = x.r[3];
+  const float pcx = (float)(x.d[0].x - (double)ox);
+  const float pcy = (float)(x.d[0].y - (double)oy);
+  const uint2 rect = make_uint2((uint32_t)__double_as_longlong(x.d[1].y),
+                                (uint32_t)((unsigned long long)__double_as_longlong(x.d[1].y) >> 32));
   dst[0] = make_float4(pcx, pcy, r0.x, r0.y);
   dst[1] = make_float4(r0.z, r0.w, r1.x, r1.y);
   dst[2] = make_float4(r1.z, r1.w, r2.x, r2.y);
@@ -241,8 +294,8 @@ struct CamRay {
     const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
     ox = tx * a.S.tw;
     oy = ty * a.S.th;
-    bx = ox + (w % WX) * 8;
-    by = oy + (w / WX) * 8;
+    bx = __builtin_amdgcn_readfirstlane(ox + (w % WX) * 8);
+    by = __builtin_amdgcn_readfirstlane(oy + (w / WX) * 8);
     px = ox + lx;
     py = oy + ly;
     inside = px < a.S.W && py < a.S.H;
@@ -250,16 +303,16 @@ struct CamRay {
     ply = (float)ly + 0.5f;
   }
   __device__ size_t pix(const TileArgs& a) const { return (size_t)py * a.S.W + px; }
-  __device__ uint2 stage(const TileArgs& a, uint32_t s, float4* dst) const { return stage_pinhole(a, s, ox, oy, dst); }
-  __device__ bool miss(const float4* R) const {
-    return misses_block(__float_as_uint(R[4].z), __float_as_uint(R[4].w), bx, by);
-  }
+  __device__ uint2 stage(const RawRec& x, float4* dst) const { return stage_pinhole(x, ox, oy, dst); }
   // does rectangle `rect` touch the 8x8 block of wave w?
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
   __device__ bool covered(const float4* R) const {
     return covers(__float_as_uint(R[4].z), __float_as_uint(R[4].w), px, py);
+  }
+  __device__ uint64_t cover_lanes(const float4* R) const {
+    return cover_lanes_rect(uniform_u32(R[4].z), uniform_u32(R[4].w), bx, by);
   }
   __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
@@ -333,13 +386,11 @@ struct CamRay {
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
 //  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, intensity, flags
 //  [4] o, columns lo|hi<<16 (may wrap), beams lo|hi<<16, -
-__device__ __forceinline__ uint2 stage_lidar(const TileArgs& a, uint32_t s, const double* dtile, float4* dst) {
-  const float4* r = a.rec + 4 * (size_t)s;
-  const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-  const double* r64 = a.rec64 + kRec64 * (size_t)s;
-  const float c0 = (float)(dtile[0] - r64[0]);
-  const float c1 = (float)(dtile[1] - r64[1]);
-  const float c2 = (float)(dtile[2] - r64[2]);
+__device__ __forceinline__ uint2 stage_lidar(const RawRec& x, const double* dtile, float4* dst) {
+  const float4 r0 = x.r[0], r1 = x.r[1], r2 = x.r[2], r3 = x.r[3];
+  const float c0 = (float)(dtile[0] - x.d[0].x);
+  const float c1 = (float)(dtile[1] - x.d[0].y);
+  const float c2 = (float)(dtile[2] - x.d[1].x);
   dst[0] = make_float4(c0, c1, c2, r0.x);
   dst[1] = make_float4(r0.y, r0.z, r0.w, r1.x);
   dst[2] = make_float4(r1.y, r1.z, r1.w, r2.x);
@@ -353,7 +404,7 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
                                            PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2], q3 = R[3];
-  const uint32_t flags = __float_as_uint(q3.w);
+  const uint32_t flags = uniform_u32(q3.w);
   const float d0 = dpix[0] + q0.x;
   const float d1 = dpix[1] + q0.y;
   const float d2 = dpix[2] + q0.z;
@@ -420,8 +471,8 @@ struct LidarRay {
     ox = tx * a.S.tw;
     oy = ty * a.S.th;
     wx = WX;
-    bx = ox + (w % WX) * 8;
-    by = oy + (w / WX) * 8;
+    bx = __builtin_amdgcn_readfirstlane(ox + (w % WX) * 8);
+    by = __builtin_amdgcn_readfirstlane(oy + (w / WX) * 8);
     pc = ox + lx;
     pb = oy + ly;
     inside = pc < a.S.W && pb < a.S.H;
@@ -432,15 +483,15 @@ struct LidarRay {
     dpix[2] = (float)(d64[2] - dt[2]);
   }
   __device__ size_t pix(const TileArgs& a) const { return (size_t)pb * a.S.W + pc; }
-  __device__ uint2 stage(const TileArgs& a, uint32_t s, float4* dst) const { return stage_lidar(a, s, dt, dst); }
-  __device__ bool miss(const float4* R) const {
-    return misses_block_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), bx, by);
-  }
+  __device__ uint2 stage(const RawRec& x, float4* dst) const { return stage_lidar(x, dt, dst); }
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block_wrap(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
   __device__ bool covered(const float4* R) const {
     return covers_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), pc, pb);
+  }
+  __device__ uint64_t cover_lanes(const float4* R) const {
+    return cover_lanes_wrap(uniform_u32(R[4].y), uniform_u32(R[4].z), bx, by);
   }
   __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
@@ -535,15 +586,6 @@ __device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* g
   if (lane < 16 && x != 0.0f) atomicAdd(gacc + (size_t)f * stride + s, x);
 }
 
-template <int NT, class Ray, bool MARK>
-__device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t L, uint32_t n_seg, uint32_t pbase,
-                           uint32_t sg0, float* part, size_t ps, float T_accept, float& T, float* acc, uint32_t& last,
-                           uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64, uint32_t& marked);
-
-// Stages pair records [base, min(base + NT, b1)) through LDS, one per thread,
-// and for every 64-record chunk c and wave w stores in s_mask[c][w] the bit
-// mask of the chunk's records whose rectangle touches wave w's 8x8 block.
-// A wave then walks only the set bits, in order.
 // Shared-memory state of one compositing workgroup.
 template <int NT>
 struct BlendShared {
@@ -551,43 +593,45 @@ struct BlendShared {
   uint32_t id[NT];
   uint64_t mask[NT / 64][NT / 64];
   F64Slot f64[kF64Slots];
-  uint32_t u[6];  // [0] item, [1] flag / max last, [2] FP64 slot counter, [3] action, [4..5] walk entry
+  uint32_t u[8];  // [0] item, [1] flag / max last, [2] FP64 slot counter, [3] action, [4..5] walk entry,
+                  // [6] next segment to walk
+  // per-sensor pair counts (evaluated, composited, FP64 re-solves) of this
+  // workgroup, added to the status words once at exit: per-item global
+  // atomics on the same few words serialise across the whole device
+  unsigned long long cnt[GS_MAX_SENSORS][3];
 };
 
+// Writes this thread's record (pair `valid`, surfel s, raw record x) into
+// batch slot threadIdx.x, staging a grazing record's FP64 re-solve data in an
+// LDS slot when one is free, and stores the per-wave rectangle masks.
 template <int NT, class Ray>
-__device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, uint32_t base, uint32_t b1,
-                                            BlendShared<NT>& sh) {
-  float4 (*s_rec)[5] = sh.rec;
-  uint32_t* s_id = sh.id;
-  F64Slot* s_f64 = sh.f64;
-  uint32_t* s_fcount = &sh.u[2];
+__device__ __forceinline__ void commit_batch(const TileArgs& a, const Ray& ray, bool valid, uint32_t s,
+                                             const RawRec& x, BlendShared<NT>& sh) {
   const int t = threadIdx.x, lane = t & 63;
-  const uint32_t k = base + t;
-  const bool valid = k < b1;
   uint2 rect = make_uint2(0u, 0u);
   if (valid) {
-    const uint32_t s = a.pval[k];
-    rect = ray.stage(a, s, s_rec[t]);
-    s_id[t] = s;
-    float& fw = Ray::flag_word(s_rec[t]);
+    float4* dst = sh.rec[t];
+    rect = ray.stage(x, dst);
+    sh.id[t] = s;
+    float& fw = Ray::flag_word(dst);
     const uint32_t flags = __float_as_uint(fw);
     if (flags & kFlagGrazing) {
-      const uint32_t slot = atomicAdd(s_fcount, 1u);
+      const uint32_t slot = atomicAdd(&sh.u[2], 1u);
       if (slot < (uint32_t)kF64Slots) {
-        // 16-byte pieces, one at a time: flagged records are few, registers are not
+        // all loads in flight at once: one memory round trip
         const double2* G = reinterpret_cast<const double2*>(a.grz + kGrz * (size_t)s);
-        const double2* r64 = reinterpret_cast<const double2*>(a.rec64 + kRec64 * (size_t)s);
-        double* d = s_f64[slot];
-#pragma unroll 1
+        double2 g[kGrz / 2];
+#pragma unroll
+        for (int i = 0; i < kGrz / 2; ++i) g[i] = G[i];
+        double* d = sh.f64[slot];
+#pragma unroll
         for (int i = 0; i < kGrz / 2; ++i) {
-          const double2 x = G[i];
-          d[2 * i] = x.x;
-          d[2 * i + 1] = x.y;
+          d[2 * i] = g[i].x;
+          d[2 * i + 1] = g[i].y;
         }
-        const double2 c01 = r64[0];
-        d[kGrz] = c01.x;
-        d[kGrz + 1] = c01.y;
-        d[kGrz + 2] = a.rec64[kRec64 * (size_t)s + 2];
+        d[kGrz] = x.d[0].x;
+        d[kGrz + 1] = x.d[0].y;
+        d[kGrz + 2] = x.d[1].x;
         fw = __uint_as_float(flags | ((slot + 1u) << 8));
       }
     }
@@ -600,6 +644,24 @@ __device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, u
   __syncthreads();
 }
 
+// Stages pair records [base, min(base + NT, b1)) through LDS, one per thread,
+// and for every 64-record chunk c and wave w stores in mask[c][w] the bit
+// mask of the chunk's records whose rectangle touches wave w's 8x8 block.
+// A wave then walks only the set bits, in order.
+template <int NT, class Ray>
+__device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, uint32_t base, uint32_t b1,
+                                            BlendShared<NT>& sh) {
+  const uint32_t k = base + threadIdx.x;
+  const bool valid = k < b1;
+  uint32_t s = 0;
+  RawRec x;
+  if (valid) {
+    s = a.pval[k];
+    load_rec(a, s, x);
+  }
+  commit_batch<NT>(a, ray, valid, s, x, sh);
+}
+
 // Wave-uniform copy of a mask word from LDS.
 __device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
   const uint64_t m = *p;
@@ -608,60 +670,54 @@ __device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Composites pairs [b0, b1) of the tile for every ray (or, kFinish, for the
-// rays marked in slot element `pe`, from their stored incoming state).
-//  kWhole:   from T = 1, writes the outputs;
-//  kPartial: from T = 1, writes the segment's partial state to `pe`;
-//  kFinish:  writes the outputs of the marked rays.
-template <int NT, class Ray, FwdMode M>
-__device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, BlendShared<NT>& sh,
-                          float* part, size_t ps, size_t pe, const QueueArgs* q = nullptr,
-                          uint2 rg = make_uint2(0u, 0u), uint32_t n_seg = 0, uint32_t pbase = 0, uint32_t sg = 0) {
+// Composites pairs [b0, b1) of the tile onto the running state (T, acc, last)
+// of every ray not `done`; a ray whose stop rule fires becomes done.  n_eval
+// counts the pixel-covered pairs up to the stop: per ray with lane_counts
+// (wave-uniform), else as a
+// wave total held by every lane (counted with scalar instructions from the
+// rectangle's lane mask); n_contrib and n64 per ray.
+template <int NT, class Ray>
+__device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, BlendShared<NT>& sh,
+                          bool lane_counts, bool& done, float& T, float* acc, uint32_t& last, uint32_t& n_eval, uint32_t& n_contrib,
+                          uint32_t& n64) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
-  float T = 1.0f;
-  float acc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-  bool done = !ray.inside;
-  uint32_t last = M == kPartial ? 0u : b0, n_eval = 0, n_contrib = 0, n64 = 0;
-  const uint32_t* pu = reinterpret_cast<const uint32_t*>(part);
-  if (M == kFinish) {
-    const bool marked = ray.inside && ld_coh(pu + kPartLast * ps + pe) == kWalk;
-    done = !marked;
-    if (marked) {
-      T = ld_coh(part + kPartT * ps + pe);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = ld_coh(part + c * ps + pe);
-      last = ld_coh(pu + kPartCount * ps + pe);
-    }
-  }
   const int w = t >> 6;
+  // Software pipeline over batches: this thread's record of the next batch
+  // is loaded while the current batch is composited, and the pair id of the
+  // batch after it one step earlier still (the record load depends on it).
+  uint32_t s_cur = 0, s_nxt = 0;
+  RawRec x;
+  if (b0 + t < b1) {
+    s_cur = a.pval[b0 + t];
+    load_rec(a, s_cur, x);
+  }
+  if (b0 + NT + t < b1) s_nxt = a.pval[b0 + NT + t];
   for (uint32_t base = b0; base < b1; base += NT) {
     if (t == 0) sh.u[2] = 0u;
     if (__syncthreads_count(!done) == 0) break;
-    stage_batch<NT>(a, ray, base, b1, sh);
+    commit_batch<NT>(a, ray, base + t < b1, s_cur, x, sh);
+    bool pending = base + NT < b1;
     const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
-    for (int c = 0; c < nch; ++c) {
+    uint64_t live = __ballot(!done);  // wave-uniform: rays still compositing
+    for (int c = 0; c < nch && live != 0; ++c) {
       uint64_t m = uniform_mask(&sh.mask[c][w]);
+      const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(c) << 6;
       while (m) {
-        if (__ballot(!done) == 0) {
-          c = nch;
-          break;
-        }
-        const int j = c * 64 + __builtin_ctzll(m);
+        const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
         float4 R[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) R[i] = sh.rec[j][i];
-        const bool cov = ray.covered(R);  // evaluated whatever `done` is, so its LDS read joins the burst
-        n_eval += (cov && !done) ? 1u : 0u;
+        if (lane_counts)
+          n_eval += (ray.covered(R) && !done) ? 1u : 0u;
+        else
+          n_eval += (uint32_t)__popcll(live & ray.cover_lanes(R));
         PairEval e;
         const bool hit = ray.eval(a, R, sh.id[j], sh.f64, e, n64) && !done;
         const float Tn = T * (1.0f - e.alpha);
         const bool stop = hit && Tn < ray.K.T_min;
-        done = done || stop;
         if (hit && !stop) {
           ++n_contrib;
           const float wgt = e.alpha * T;
@@ -672,75 +728,61 @@ __device__ void fwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           T = Tn;
           last = base + j + 1;
         }
+        if (__ballot(stop) != 0) {
+          done = done || stop;
+          live = __ballot(!done);
+          if (live == 0) break;
+        }
+      }
+      if (pending) {  // after the first chunk: issue the next batch's loads
+        pending = false;
+        s_cur = s_nxt;
+        if (base + NT + t < b1) load_rec(a, s_cur, x);
+        s_nxt = base + 2 * NT + t < b1 ? a.pval[base + 2 * NT + t] : 0u;
       }
     }
-  }
-  if (M == kPartial) {
-    count_pairs(a.status, 0u, 0u, n64);
-    if (ray.inside) {
-      uint32_t* pw = reinterpret_cast<uint32_t*>(part);
-#pragma unroll
-      for (int c = 0; c < C; ++c) part[c * ps + pe] = acc[c];
-      part[kPartT * ps + pe] = T;
-      pw[kPartLast * ps + pe] = last | (done ? 0x80000000u : 0u);
-      pw[kPartCount * ps + pe] = n_eval | (n_contrib << 16);
+    if (pending) {
+      s_cur = s_nxt;
+      if (base + NT + t < b1) load_rec(a, s_cur, x);
+      s_nxt = base + 2 * NT + t < b1 ? a.pval[base + 2 * NT + t] : 0u;
     }
-  } else if (M == kWhole) {
-    count_pairs(a.status, n_eval, n_contrib, n64);
-    if (ray.inside) ray.write(a, T, acc, last);
-  } else {
-    // a marked ray that did not stop in this segment continues on its own
-    const bool marked = ray.inside && ld_coh(pu + kPartLast * ps + pe) == kWalk;
-    if (marked) {
-      uint32_t unused = 0;
-      if (!done)
-        (void)merge_from<NT, Ray, false>(a, ray, rg, q->seg_len, n_seg, pbase, sg + 1, part, ps, q->T_accept, T, acc,
-                                     last, n_eval, n_contrib, n64, unused);
-      ray.write(a, T, acc, last);
-    }
-    count_pairs(a.status, n_eval, n_contrib, n64);
   }
 }
 
-// One ray walks pairs [b0, b1) on its own from the state (T, acc), reading
-// records from global memory.  Returns true where the stop rule fires.
-template <class Ray>
-__device__ bool rewalk(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, float& T, float* acc,
-                       uint32_t& last, uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64) {
-#pragma clang fp contract(off)
-  constexpr int C = Ray::C;
-  for (uint32_t k = b0; k < b1; ++k) {
-    const uint32_t s = a.pval[k];
-    float4 R[5];
-    ray.stage(a, s, R);
-    if (ray.miss(R)) continue;
-    n_eval += ray.covered(R) ? 1u : 0u;
-    PairEval e;
-    if (!ray.eval(a, R, s, nullptr, e, n64)) continue;
-    const float Tn = T * (1.0f - e.alpha);
-    if (Tn < ray.K.T_min) return true;
-    ++n_contrib;
-    const float wgt = e.alpha * T;
-    float f[C];
-    ray.feat(R, e, f);
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = fmaf(wgt, f[c], acc[c]);
-    T = Tn;
-    last = k + 1;
+// Wave total held by every lane -> held by lane 0 only (before a wave sum).
+__device__ __forceinline__ uint32_t lane0_only(uint32_t v) { return (threadIdx.x & 63) == 0 ? v : 0u; }
+
+// Adds the wave's counts to the workgroup's counters of sensor si.
+template <int NT>
+__device__ __forceinline__ void count_wg(BlendShared<NT>& sh, int si, uint32_t evals, uint32_t contribs,
+                                         uint32_t fp64) {
+  evals = wave_sum_u32(evals);
+  contribs = wave_sum_u32(contribs);
+  fp64 = wave_sum_u32(fp64);
+  if ((threadIdx.x & 63) == 0) {
+    if (evals) atomicAdd(&sh.cnt[si][0], (unsigned long long)evals);
+    if (contribs) atomicAdd(&sh.cnt[si][1], (unsigned long long)contribs);
+    if (fp64) atomicAdd(&sh.cnt[si][2], (unsigned long long)fp64);
   }
-  return false;
+}
+
+// Can a segment with local transmittance Ts and (last | stop bit) ls be
+// composited as a whole onto transmittance T?  Only with no local stop and
+// either nothing composited (every pair skipped, so none can stop the ray)
+// or T * Ts clear of T_min by the accumulated rounding (T_accept).
+__device__ __forceinline__ bool accept_segment(float T, float Ts, uint32_t ls, float T_accept) {
+  return !(ls >> 31) && (Ts == 1.0f || T * Ts >= T_accept);
 }
 
 // Front-to-back merge of a split tile's segment partials from slot sg0 with
-// the ray's running state (see the header).  Every reached slot keeps the
-// segment's incoming (T, prefix) for the adjoint.  At a segment where the
-// stop can happen: mark = true stores the state there, marks the slot and
-// returns with `marked` = slot + 1; MARK = false re-walks the segment on the
-// ray's own.  Returns true when the ray's result is final.
-template <int NT, class Ray, bool MARK>
-__device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t L, uint32_t n_seg, uint32_t pbase,
-                           uint32_t sg0, float* part, size_t ps, float T_accept, float& T, float* acc, uint32_t& last,
-                           uint32_t& n_eval, uint32_t& n_contrib, uint32_t& n64, uint32_t& marked) {
+// the ray's running state.  Every reached slot keeps the segment's incoming
+// (T, prefix) for the adjoint.  Returns the first segment that cannot be
+// taken whole (the ray's stop lies in it, or may), or n_seg when every
+// remaining segment was taken.
+template <int NT, class Ray>
+__device__ uint32_t merge_from(uint32_t n_seg, uint32_t pbase, uint32_t sg0, float* part, size_t ps,
+                               float T_accept, float& T, float* acc, uint32_t& last, uint32_t& n_eval,
+                               uint32_t& n_contrib) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   uint32_t* pu = reinterpret_cast<uint32_t*>(part);
@@ -756,27 +798,15 @@ __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t
       part[c * ps + pe] = acc[c];
     }
     part[kPartT * ps + pe] = T;
-    // whole segment: no local stop and either nothing composited (every pair
-    // skipped, so none can stop the ray) or T * T_seg clear of T_min
-    if (!(ls >> 31) && (Ts == 1.0f || T * Ts >= T_accept)) {
+    if (!accept_segment(T, Ts, ls, T_accept)) return sg;
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = fmaf(T, as[c], acc[c]);
-      T = T * Ts;
-      if (ls) last = ls;
-      n_eval += cnt & 0xFFFFu;
-      n_contrib += cnt >> 16;
-    } else if (MARK) {
-      pu[kPartLast * ps + pe] = kWalk;
-      pu[kPartCount * ps + pe] = last;
-      marked = sg + 1;
-      return false;
-    } else {
-      const uint32_t b0 = rg.x + sg * L;
-      const uint32_t b1 = min(b0 + L, rg.y);
-      if (rewalk(a, ray, b0, b1, T, acc, last, n_eval, n_contrib, n64)) return true;
-    }
+    for (int c = 0; c < C; ++c) acc[c] = fmaf(T, as[c], acc[c]);
+    T = T * Ts;
+    if (ls) last = ls;
+    n_eval += cnt & 0xFFFFu;
+    n_contrib += cnt >> 16;
   }
-  return true;
+  return n_seg;
 }
 
 // Merge run by the workgroup that completes a split tile; queues the
@@ -790,7 +820,7 @@ __device__ bool merge_from(const TileArgs& a, const Ray& ray, uint2 rg, uint32_t
 // entry to appear.
 template <int NT, class Ray>
 __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray, uint32_t gt, uint2 rg,
-                           uint32_t n_seg, uint32_t pbase) {
+                           uint32_t n_seg, uint32_t pbase, int si, BlendShared<NT>& sh) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   uint32_t n_eval = 0, n_contrib = 0, n64 = 0, marked = 0;
@@ -800,11 +830,21 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
     uint32_t last = rg.x;
-    (void)merge_from<NT, Ray, true>(a, ray, rg, q.seg_len, n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc,
-                                last, n_eval, n_contrib, n64, marked);
-    if (marked == 0) ray.write(a, T, acc, last);
+    const uint32_t sg = merge_from<NT, Ray>(n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc, last, n_eval,
+                                            n_contrib);
+    if (sg == n_seg) {
+      ray.write(a, T, acc, last);
+    } else {
+      // the stop lies in segment sg (or may): keep the incoming state there
+      // (stored by the merge), mark the slot and list a walk of it
+      const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
+      uint32_t* pu = reinterpret_cast<uint32_t*>(q.part);
+      pu[kPartLast * q.part_stride + pe] = kWalk;
+      pu[kPartCount * q.part_stride + pe] = last;
+      marked = sg + 1;
+    }
   }
-  count_pairs(a.status, n_eval, n_contrib, n64);
+  count_wg(sh, si, n_eval, n_contrib, n64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (marked) {
@@ -904,59 +944,132 @@ __device__ inline int sensor_of_tile(const QueueArgs& q, uint32_t gt) {
   return s;
 }
 
-template <int NT, bool BWD, class Ray>
-__device__ void run_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
+// Adjoint of one work item (a whole tile, or one segment of a split tile
+// from the incoming state its slot holds).
+template <int NT, class Ray>
+__device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
                          BlendShared<NT>& sh) {
-  uint32_t* s_u = sh.u;
   const Ray ray(a, tile);
   const uint2 rg = a.ranges[gt];
   const uint32_t len = rg.y - rg.x;
   const uint32_t L = q.seg_len;
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
   if (n_seg == 1) {
-    if (BWD)
-      bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, sh);
-    else
-      fwd_range<NT, Ray, kWhole>(a, ray, rg.x, rg.y, sh, nullptr, 0, 0);
+    bwd_range<NT>(a, ray, rg.x, rg.y, nullptr, 0, 0, sh);
     return;
   }
   const uint32_t pbase = q.pslot_base[gt];
   if (pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
   const uint32_t b0 = rg.x + sg * L;
-  const uint32_t b1 = min(b0 + L, rg.y);
   const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
-  if (BWD) {
-    bwd_range<NT>(a, ray, b0, b1, q.part, q.part_stride, pe, sh);
+  bwd_range<NT>(a, ray, b0, min(b0 + L, rg.y), q.part, q.part_stride, pe, sh);
+}
+
+// One forward work item, through a single compositing call site:
+//  - a whole tile (from T = 1; writes the outputs);
+//  - a segment of a split tile (from T = 1; writes the segment's partial
+//    state to its slot, and the tile's last arrival merges);
+//  - (walk) a listed stop segment, for the rays the merge marked there, from
+//    the incoming state it left in the slot.  A marked ray whose stop does
+//    not come in that segment (T * T_seg fell between T_min and T_accept)
+//    carries on: later segments are taken whole from their partials where
+//    the accept test allows, and the first one that it does not is walked by
+//    the workgroup again, for every ray that waits at it.
+template <int NT, class Ray>
+__device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile, uint32_t gt, uint32_t sg,
+                         bool walk, BlendShared<NT>& sh) {
+#pragma clang fp contract(off)
+  constexpr int C = Ray::C;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  const Ray ray(a, tile);
+  const uint2 rg = a.ranges[gt];
+  const uint32_t len = rg.y - rg.x;
+  const uint32_t L = q.seg_len;
+  const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
+  const bool split = n_seg > 1;
+  const uint32_t pbase = split ? q.pslot_base[gt] : 0u;
+  if (split && pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
+  const bool partial = split && !walk;
+  float* part = q.part;
+  const size_t ps = q.part_stride;
+  uint32_t* pu = reinterpret_cast<uint32_t*>(part);
+  const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
+  float T = 1.0f;
+  float acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+  uint32_t last = partial ? 0u : rg.x, n_eval_w = 0, n_eval = 0, n_contrib = 0, n64 = 0;
+  // the ray composites segment `need` next (kNone: nothing left for it here)
+  uint32_t need = ray.inside ? sg : kNone;
+  if (walk) {
+    if (need != kNone && ld_coh(pu + kPartLast * ps + pe) == kWalk) {
+      T = ld_coh(part + kPartT * ps + pe);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = ld_coh(part + c * ps + pe);
+      last = ld_coh(pu + kPartCount * ps + pe);
+      // complete these loads here: left in flight, they would make the pair
+      // loop wait for every outstanding load (the next batch's prefetch
+      // included) wherever it updates the running state
+      asm volatile("" ::"v"(T), "v"(last));
+#pragma unroll
+      for (int c = 0; c < C; ++c) asm volatile("" ::"v"(acc[c]));
+    } else {
+      need = kNone;
+    }
+  }
+  bool done = false;
+  for (uint32_t cur = sg;;) {
+    const bool active = need == cur;
+    done = !active;
+    const uint32_t b0 = rg.x + cur * L;
+    // a segment keeps per-ray counts: the merge takes them ray by ray
+    composite<NT>(a, ray, b0, split ? min(b0 + L, rg.y) : rg.y, sh, partial, done, T, acc, last,
+                  partial ? n_eval : n_eval_w, n_contrib, n64);
+    if (!walk) break;
+    if (active) {
+      need = done ? kNone
+                  : merge_from<NT, Ray>(n_seg, pbase, cur + 1, part, ps, q.T_accept, T, acc, last, n_eval, n_contrib);
+      if (need == n_seg) need = kNone;
+      if (need == kNone) ray.write(a, T, acc, last);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sh.u[6] = kNone;
+    __syncthreads();
+    if (need != kNone) atomicMin(&sh.u[6], need);
+    __syncthreads();
+    const uint32_t nxt = sh.u[6];
+    if (nxt == kNone) break;
+    cur = nxt;
+  }
+  if (walk) {
+    count_wg(sh, si, lane0_only(n_eval_w) + n_eval, n_contrib, n64);
     return;
   }
-  fwd_range<NT, Ray, kPartial>(a, ray, b0, b1, sh, q.part, q.part_stride, pe);
+  if (!partial) {
+    count_wg(sh, si, lane0_only(n_eval_w), n_contrib, n64);
+    if (ray.inside) ray.write(a, T, acc, last);
+    return;
+  }
+  count_wg(sh, si, 0u, 0u, n64);
+  if (ray.inside) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) part[c * ps + pe] = acc[c];
+    part[kPartT * ps + pe] = T;
+    pu[kPartLast * ps + pe] = last | (done ? 0x80000000u : 0u);
+    pu[kPartCount * ps + pe] = n_eval | (n_contrib << 16);
+  }
   // publish this segment (device-scope release: written back from this XCD's
   // L2), then let the tile's last arrival merge
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  if (threadIdx.x == 0) s_u[1] = (atomicAdd(q.arrive + gt, 1u) + 1u == n_seg) ? 1u : 0u;
+  if (threadIdx.x == 0) sh.u[1] = (atomicAdd(q.arrive + gt, 1u) + 1u == n_seg) ? 1u : 0u;
   __syncthreads();
-  if (s_u[1]) merge_tile<NT>(q, a, ray, gt, rg, n_seg, pbase);  // partials are read device-coherently
+  if (sh.u[1]) merge_tile<NT>(q, a, ray, gt, rg, n_seg, pbase, si, sh);  // partials are read device-coherently
 }
 
 // Sensor kinds a launch may meet (bit 0 camera, bit 1 LiDAR): single-kind
 // launches leave the other kind's code and registers out.
 constexpr int kKindCam = 1, kKindLidar = 2, kKindBoth = 3;
-
-// Cooperative walk of a listed segment for its marked rays.
-template <int NT, class Ray>
-__device__ void finish_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
-                            BlendShared<NT>& sh) {
-  const Ray ray(a, tile);
-  const uint2 rg = a.ranges[gt];
-  const uint32_t L = q.seg_len;
-  const uint32_t n_seg = (rg.y - rg.x - 1) / L + 1;
-  const uint32_t pbase = q.pslot_base[gt];
-  const uint32_t b0 = rg.x + sg * L;
-  const uint32_t b1 = min(b0 + L, rg.y);
-  const size_t pe = (size_t)(pbase + sg) * NT + threadIdx.x;
-  fwd_range<NT, Ray, kFinish>(a, ray, b0, b1, sh, q.part, q.part_stride, pe, &q, rg, n_seg, pbase, sg);
-}
 
 __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1036,35 +1149,50 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
   uint32_t* s_u = sh.u;
   const uint32_t n_items = min(*q.n_items, q.cap_items);
   bool main_left = true;  // thread 0 only
+  for (int i = threadIdx.x; i < GS_MAX_SENSORS * 3; i += NT) (&sh.cnt[0][0])[i] = 0ull;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_u[3] = next_action(q, main_left, n_items, !BWD && q.pslot_cap > 0, s_u);
     __syncthreads();
-    const uint32_t act = s_u[3];
+    // the action and its item are workgroup-uniform: scalar registers
+    const uint32_t act = rfl(s_u[3]);
     if (act == kActExit) break;
     uint32_t gt, sg;
     if (act == kActItem) {
-      const uint2 ts = q.items[q.queue[s_u[0]]];
-      gt = ts.x;
-      sg = ts.y;
+      const uint2 ts = q.items[q.queue[rfl(s_u[0])]];
+      gt = rfl(ts.x);
+      sg = rfl(ts.y);
     } else {
-      gt = s_u[4];  // its slot state is read device-coherently
-      sg = s_u[5];
+      gt = rfl(s_u[4]);  // its slot state is read device-coherently
+      sg = rfl(s_u[5]);
     }
     const int si = sensor_of_tile(q, gt);
     const TileArgs& a = q.tiles[si];
     const int tile = (int)gt - q.tile_off[si];
     const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
-    if (act == kActItem) {
+    if (BWD) {
       if (cam)
-        run_item<NT, BWD, CamRay>(q, a, tile, gt, sg, sh);
+        bwd_item<NT, CamRay>(q, a, tile, gt, sg, sh);
       else if (KINDS & kKindLidar)
-        run_item<NT, BWD, LidarRay>(q, a, tile, gt, sg, sh);
-    } else if (!BWD) {
+        bwd_item<NT, LidarRay>(q, a, tile, gt, sg, sh);
+    } else {
+      const bool walk = act == kActWalk;
       if (cam)
-        finish_item<NT, CamRay>(q, a, tile, gt, sg, sh);
+        fwd_item<NT, CamRay>(q, a, si, tile, gt, sg, walk, sh);
       else if (KINDS & kKindLidar)
-        finish_item<NT, LidarRay>(q, a, tile, gt, sg, sh);
+        fwd_item<NT, LidarRay>(q, a, si, tile, gt, sg, walk, sh);
+    }
+  }
+  // the workgroup's counts, once per sensor and counter
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (!BWD && i < q.n_sensors * 3) {
+    const unsigned long long v = (&sh.cnt[0][0])[i];
+    uint32_t* st = q.tiles[i / 3].status;
+    if (v) {
+      if (i % 3 == 0) atomicAdd(reinterpret_cast<unsigned long long*>(st + kStEvals), v);
+      else if (i % 3 == 1) atomicAdd(reinterpret_cast<unsigned long long*>(st + kStContrib), v);
+      else atomicAdd(st + kStFp64, (uint32_t)v);
     }
   }
 }

@@ -423,7 +423,10 @@ __global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
       for (uint32_t sg = 0; sg < c[r].x; ++sg) {
         const uint32_t item = ix + sg;
         if (item >= a.cap_items) break;
-        const uint32_t cost = c[r].x == 1 ? len : min(a.seg_len, len - sg * a.seg_len);
+        // every segment of a split tile (its short last one included) weighs
+        // two full segments: the tile's merge waits for all of them, and the
+        // stop-segment walks follow the merge on the critical path
+        const uint32_t cost = c[r].x == 1 ? len : 2u * a.seg_len;
         a.key[item] = kmax - (cost < kmax ? cost : kmax);
         a.val[item] = item;
         a.items[item] = make_uint2((uint32_t)t, sg);
