@@ -436,18 +436,6 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
-// Adds the wave's evaluation / contribution counts to the status words.
-__device__ inline void count_pairs(uint32_t* status, uint32_t evals, uint32_t contribs, uint32_t fp64) {
-  evals = wave_sum_u32(evals);
-  contribs = wave_sum_u32(contribs);
-  fp64 = wave_sum_u32(fp64);
-  if (__lane_id() == 0) {
-    if (fp64) atomicAdd(status + kStFp64, fp64);
-    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStEvals), (unsigned long long)evals);
-    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStContrib), (unsigned long long)contribs);
-  }
-}
-
 __device__ inline uint64_t lanemask_lt() {
   uint32_t lane = __lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
