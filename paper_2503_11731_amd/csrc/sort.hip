@@ -296,33 +296,65 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
   }
 }
 
+// Pair emission, one wave per 64 consecutive surfels of the depth order:
+// the wave writes the union of their pairs as consecutive 64-pair runs, each
+// lane finding its surfel with a binary search over the wave's offsets, so
+// every store instruction writes 256 contiguous bytes.  Within a surfel the
+// tiles go row by row (the order the tile sort keeps for equal tile ids).
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, const uint32_t* __restrict__ ntiles,
                                               const int4* __restrict__ rect, const uint32_t* __restrict__ offs,
                                               int n, EmitTable E, uint32_t cap, uint32_t* __restrict__ ptile,
                                               uint32_t* __restrict__ pval) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  const uint32_t s = val[j];  // record id
-  const uint32_t cnt = ntiles[s];
-  if (cnt == 0) return;
-  uint32_t o = offs[j];
-  if (o >= cap) return;
-  int se = 0;
-  while (se + 1 < E.n && E.rec_base[se + 1] <= s) ++se;
-  const int n_tx = E.n_tx[se], toff = E.tile_off[se];
-  const int4 r = rect[s];
+  const int lane = threadIdx.x & 63;
+  const int j0 = (blockIdx.x * 256 + (threadIdx.x & ~63));
+  if (j0 >= n) return;
+  const int j = j0 + lane;
+  uint32_t s = 0, cnt = 0, o = 0;
+  int4 r = make_int4(0, 0, 0, 0);
+  int n_tx = 1, toff = 0;
+  if (j < n) {
+    s = val[j];
+    cnt = ntiles[s];
+    o = offs[j];
+    if (cnt) {
+      r = rect[s];
+      int se = 0;
+      while (se + 1 < E.n && E.rec_base[se + 1] <= s) ++se;
+      n_tx = E.n_tx[se];
+      toff = E.tile_off[se];
+    }
+  }
+  const uint32_t start = (uint32_t)__shfl((int)o, 0, 64);
+  uint32_t end = j < n ? o + cnt : 0u;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, d, 64));
+  const uint32_t lo = j < n ? o - start : 0xFFFFFFFFu;  // local first pair (invalid lanes sort last)
   const bool wrap = (r.w >> 30) & 1;
-  const int ty_hi = r.w & 0x3FFFFFFF;
-  const int ncol = wrap ? (n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1);
-  for (int ty = r.z; ty <= ty_hi; ++ty) {
-    for (int c = 0; c < ncol; ++c) {
-      int tx = r.x + c;
-      if (tx >= n_tx) tx -= n_tx;
-      if (o < cap) {
-        ptile[o] = (uint32_t)(toff + ty * n_tx + tx);
-        pval[o] = s;
-      }
-      ++o;
+  const int ncol = cnt == 0 ? 1 : (wrap ? (n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1));
+  const int row0 = toff + r.z * n_tx;  // tile id of column 0 in the first row
+  for (uint32_t b = 0; start + b < end; b += 64) {
+    const uint32_t k = b + (uint32_t)lane;
+    // highest lane whose first pair is <= k (that lane has a pair at k)
+    int src = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const uint32_t l = (uint32_t)__shfl((int)lo, src + step, 64);
+      if (src + step < 64 && l <= k) src += step;
+    }
+    const uint32_t ls = (uint32_t)__shfl((int)lo, src, 64);
+    const uint32_t ss = (uint32_t)__shfl((int)s, src, 64);
+    const int nc = __shfl(ncol, src, 64);
+    const int x0 = __shfl(r.x, src, 64);
+    const int ntx = __shfl(n_tx, src, 64);
+    const int rb = __shfl(row0, src, 64);
+    const uint32_t q = start + k;
+    if (q < end && q < cap) {
+      const uint32_t loc = k - ls;
+      const uint32_t ty = loc / (uint32_t)nc;
+      int tx = x0 + (int)(loc - ty * (uint32_t)nc);
+      if (tx >= ntx) tx -= ntx;
+      ptile[q] = (uint32_t)(rb + (int)ty * ntx + tx);
+      pval[q] = ss;
     }
   }
 }
@@ -331,6 +363,9 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, 
 
 // (items, partial slots) of one tile: a list longer than L splits into
 // ceil(len / L) segments, each with its own partial-state slot.
+// tiles per block of the work-item scans (one per thread)
+constexpr int kSegItems = 256;
+
 __device__ inline uint2 seg_counts(uint2 rg, uint32_t L) {
   const uint32_t len = rg.y - rg.x;
   const uint32_t n = len > L ? (len - 1) / L + 1 : 1u;
@@ -339,15 +374,12 @@ __device__ inline uint2 seg_counts(uint2 rg, uint32_t L) {
 
 __global__ __launch_bounds__(256) void k_seg_reduce(SegScanArgs a) {
   __shared__ uint32_t s_w[4];
-  const int base = blockIdx.x * kScanItems;
+  const int t = blockIdx.x * kSegItems + threadIdx.x;
   uint32_t sx = 0, sy = 0;
-  for (int r = 0; r < kScanItems / 256; ++r) {
-    const int t = base + r * 256 + threadIdx.x;
-    if (t < a.n_tiles) {
-      const uint2 c = seg_counts(a.ranges[t], a.seg_len);
-      sx += c.x;
-      sy += c.y;
-    }
+  if (t < a.n_tiles) {
+    const uint2 c = seg_counts(a.ranges[t], a.seg_len);
+    sx = c.x;
+    sy = c.y;
   }
   uint32_t tx, ty;
   block_excl_scan<256>(sx, s_w, &tx);
@@ -388,52 +420,38 @@ __global__ __launch_bounds__(1024) void k_seg_top(SegScanArgs a, int nblk) {
 
 __global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
   __shared__ uint32_t s_w[4];
-  constexpr int PER = kScanItems / 256;
-  const int t0 = blockIdx.x * kScanItems + threadIdx.x * PER;
-  uint2 c[PER];
-  uint32_t sx = 0, sy = 0;
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int t = t0 + r;
-    c[r] = t < a.n_tiles ? seg_counts(a.ranges[t], a.seg_len) : make_uint2(0u, 0u);
-    sx += c[r].x;
-    sy += c[r].y;
-  }
-  uint32_t tx, ty;
-  uint32_t ix = block_excl_scan<256>(sx, s_w, &tx) + a.bsum[blockIdx.x].x;
-  uint32_t iy = block_excl_scan<256>(sy, s_w, &ty) + a.bsum[blockIdx.x].y;
+  const int t = blockIdx.x * kSegItems + threadIdx.x;
+  const uint2 rg = t < a.n_tiles ? a.ranges[t] : make_uint2(0u, 0u);
+  const uint2 c = t < a.n_tiles ? seg_counts(rg, a.seg_len) : make_uint2(0u, 0u);
+  uint32_t tx, ty, tsplit;
+  const uint32_t ix = block_excl_scan<256>(c.x, s_w, &tx) + a.bsum[blockIdx.x].x;
+  const uint32_t iy = block_excl_scan<256>(c.y, s_w, &ty) + a.bsum[blockIdx.x].y;
+  const bool split = t < a.n_tiles && c.y && iy + c.y <= a.pslot_cap;
+  (void)block_excl_scan<256>(split ? 1u : 0u, s_w, &tsplit);
+  // the block's split tiles join the count of tiles left to merge at once
+  if (threadIdx.x == 0 && tsplit) atomicAdd(a.hdr + 5, tsplit);
+  if (t >= a.n_tiles) return;
   const uint32_t kmax = a.key_bits >= 32 ? 0xFFFFFFFFu : ((1u << a.key_bits) - 1u);
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    const int t = t0 + r;
-    if (t < a.n_tiles) {
-      a.pslot_base[t] = iy;
-      a.arrive[t] = 0u;
-      if (c[r].y && iy + c[r].y <= a.pslot_cap) {
-        // a split tile: clear its slots' walk flags and as many walk-list
-        // entries, and count it among the tiles left to merge
-        for (uint32_t k = 0; k < c[r].y; ++k) {
-          a.slot_flag[iy + k] = 0u;
-          a.walk[iy + k] = ~0ull;
-        }
-        atomicAdd(a.hdr + 5, 1u);
-      }
-      const uint2 rg = a.ranges[t];
-      const uint32_t len = rg.y - rg.x;
-      for (uint32_t sg = 0; sg < c[r].x; ++sg) {
-        const uint32_t item = ix + sg;
-        if (item >= a.cap_items) break;
-        // every segment of a split tile (its short last one included) weighs
-        // two full segments: the tile's merge waits for all of them, and the
-        // stop-segment walks follow the merge on the critical path
-        const uint32_t cost = c[r].x == 1 ? len : 2u * a.seg_len;
-        a.key[item] = kmax - (cost < kmax ? cost : kmax);
-        a.val[item] = item;
-        a.items[item] = make_uint2((uint32_t)t, sg);
-      }
+  a.pslot_base[t] = iy;
+  a.arrive[t] = 0u;
+  if (split) {
+    // a split tile: clear its slots' walk flags and as many walk-list entries
+    for (uint32_t k = 0; k < c.y; ++k) {
+      a.slot_flag[iy + k] = 0u;
+      a.walk[iy + k] = ~0ull;
     }
-    ix += c[r].x;
-    iy += c[r].y;
+  }
+  const uint32_t len = rg.y - rg.x;
+  for (uint32_t sg = 0; sg < c.x; ++sg) {
+    const uint32_t item = ix + sg;
+    if (item >= a.cap_items) break;
+    // every segment of a split tile (its short last one included) weighs
+    // two full segments: the tile's merge waits for all of them, and the
+    // stop-segment walks follow the merge on the critical path
+    const uint32_t cost = c.x == 1 ? len : 2u * a.seg_len;
+    a.key[item] = kmax - (cost < kmax ? cost : kmax);
+    a.val[item] = item;
+    a.items[item] = make_uint2((uint32_t)t, sg);
   }
 }
 
@@ -523,10 +541,10 @@ void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, 
   hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, E, cap, ptile, pval);
 }
 
-size_t seg_bsum_words(int n_tiles) { return 2 * ((size_t)((n_tiles + kScanItems - 1) / kScanItems) + 1); }
+size_t seg_bsum_words(int n_tiles) { return 2 * ((size_t)((n_tiles + kSegItems - 1) / kSegItems) + 1); }
 
 void launch_build_items(const SegScanArgs& a, hipStream_t st) {
-  const int nblk = (a.n_tiles + kScanItems - 1) / kScanItems;
+  const int nblk = (a.n_tiles + kSegItems - 1) / kSegItems;
   if (nblk > 0) hipLaunchKernelGGL(k_seg_reduce, dim3(nblk), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_seg_top, dim3(1), dim3(1024), 0, st, a, nblk);
   if (nblk > 0) hipLaunchKernelGGL(k_seg_down, dim3(nblk), dim3(256), 0, st, a);
