@@ -151,33 +151,40 @@ __global__ __launch_bounds__(256) void k_rs_hscan_down(RadixArgs a) {
   }
 }
 
+// Stable scatter of one block of kRadixItems keys.  Each wave ranks its own
+// contiguous quarter of the block independently (match masks from 8 ballots
+// per 64 keys, per-wave digit counters in LDS that only that wave touches),
+// so the block meets only four barriers; the block's keys are then grouped
+// by digit in LDS and written out in order, contiguous runs per digit.
 __global__ __launch_bounds__(256) void k_rs_scatter(RadixArgs a) {
   const uint32_t n = radix_n(a);
   const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
   __shared__ uint32_t s_key[kRadixItems];
   __shared__ uint32_t s_val[kRadixItems];
   __shared__ uint32_t s_wcnt[4][256];
-  __shared__ uint32_t s_run[256];
   __shared__ uint32_t s_start[256];
   __shared__ uint32_t s_gbase[256];
   __shared__ uint32_t s_w[4];
-  const int t = threadIdx.x, w = t >> 6;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = lanemask_lt();
-  constexpr int R = kRadixItems / 256;
+  constexpr int R = kRadixItems / 256;  // keys per lane
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    s_run[t] = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wcnt[k][t] = 0;
     __syncthreads();
-    const uint32_t base = b * kRadixItems;
+    const uint32_t wbase = b * kRadixItems + (uint32_t)w * (kRadixItems / 4);
     uint32_t my_key[R], my_val[R], my_rank[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t idx = base + r * 256 + t;
+      const uint32_t idx = wbase + r * 64 + lane;
+      my_key[r] = idx < n ? a.kin[idx] : 0u;
+      my_val[r] = idx < n ? a.vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t idx = wbase + r * 64 + lane;
       const bool valid = idx < n;
-      const uint32_t k = valid ? a.kin[idx] : 0u;
-      const uint32_t v = valid ? a.vin[idx] : 0u;
-      const uint32_t d = (k >> a.shift) & 255u;
+      const uint32_t d = (my_key[r] >> a.shift) & 255u;
       uint64_t m = __ballot(valid);
 #pragma unroll
       for (int bit = 0; bit < 8; ++bit) {
@@ -185,39 +192,35 @@ __global__ __launch_bounds__(256) void k_rs_scatter(RadixArgs a) {
         const uint64_t bb = __ballot(on);
         m &= on ? bb : ~bb;
       }
-      const uint32_t rank_w = __popcll(m & lt);
-      if (valid && rank_w == 0) s_wcnt[w][d] = __popcll(m);
-      __syncthreads();
-      uint32_t pre = 0;
-      if (valid) {
-        pre = s_run[d];
-        for (int ww = 0; ww < w; ++ww) pre += s_wcnt[ww][d];
-      }
-      my_key[r] = k;
-      my_val[r] = v;
-      my_rank[r] = valid ? pre + rank_w : 0xFFFFFFFFu;
-      __syncthreads();
-      s_run[t] += s_wcnt[0][t] + s_wcnt[1][t] + s_wcnt[2][t] + s_wcnt[3][t];
-#pragma unroll
-      for (int k2 = 0; k2 < 4; ++k2) s_wcnt[k2][t] = 0;
-      __syncthreads();
+      const uint32_t below = (uint32_t)__popcll(m & lt);
+      // every lane of the digit reads the count before its first lane adds
+      // the digit's keys of this round (one wave, LDS in program order)
+      const uint32_t pre = valid ? s_wcnt[w][d] : 0u;
+      my_rank[r] = valid ? pre + below : 0xFFFFFFFFu;
+      if (valid && below == 0) s_wcnt[w][d] = pre + (uint32_t)__popcll(m);
     }
+    __syncthreads();
+    const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t], c3 = s_wcnt[3][t];
     uint32_t tot;
-    const uint32_t st = block_excl_scan<256>(s_run[t], s_w, &tot);
+    const uint32_t st = block_excl_scan<256>(c0 + c1 + c2 + c3, s_w, &tot);
     s_start[t] = st;
+    s_wcnt[0][t] = st;
+    s_wcnt[1][t] = st + c0;
+    s_wcnt[2][t] = st + c0 + c1;
+    s_wcnt[3][t] = st + c0 + c1 + c2;
     s_gbase[t] = a.hist[(size_t)t * nb + b];
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (my_rank[r] != 0xFFFFFFFFu) {
         const uint32_t d = (my_key[r] >> a.shift) & 255u;
-        const uint32_t pos = s_start[d] + my_rank[r];
+        const uint32_t pos = s_wcnt[w][d] + my_rank[r];
         s_key[pos] = my_key[r];
         s_val[pos] = my_val[r];
       }
     }
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kRadixItems, n - base);
+    const uint32_t cnt = min((uint32_t)kRadixItems, n - b * kRadixItems);
     for (uint32_t i = t; i < cnt; i += 256) {
       const uint32_t k = s_key[i];
       const uint32_t d = (k >> a.shift) & 255u;
