@@ -84,7 +84,7 @@ typedef struct gs_sensor_desc {
   const double* elevations;  /* LiDAR: host array of `height` ascending angles (rad) */
   float z_near;              /* camera: min hit depth; LiDAR: min hit range          */
   int32_t scene;             /* index of the scene this sensor renders              */
-  int32_t tile_w, tile_h;    /* screen tile; 0 = default (16x16 camera, 32x8 LiDAR) */
+  int32_t tile_w, tile_h;    /* screen tile; 0 = default (32x8 for both kinds) */
 } gs_sensor_desc;
 
 /* Compositing rules (front-to-back alpha blending with the 2DGS low-pass
@@ -174,9 +174,12 @@ typedef struct gs_run_status {
   int32_t overflow;               /* 1 if any sensor exceeded pair_capacity  */
   int32_t n_visible[GS_MAX_SENSORS];
   int64_t fp64_pairs;             /* pairs re-solved in FP64 (grazing rays)  */
-  int64_t evaluated;              /* ray-surfel pairs the forward must evaluate: per
-                                     ray, the pairs of its tile list whose pixel
-                                     rectangle holds the ray, up to its stop      */
+  int64_t evaluated;              /* ray-surfel pairs the forward evaluates: per ray,
+                                     the pairs of its tile list whose pixel
+                                     rectangle holds the ray, up to its stop,
+                                     except pairs proven to have no valid hit
+                                     (cutoff and alpha >= alpha_min) on any pixel
+                                     centre of the ray's 8x8 block             */
   int64_t composited;             /* ray-surfel pairs that contributed             */
   int64_t work_items;             /* compositing work items (tiles + extra segments) */
   int64_t segments;               /* segments of split tiles                       */

@@ -606,8 +606,10 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
         gs_plan_destroy(p);
         return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": focal lengths must be > 0");
       }
-      K.tw = d.tile_w ? d.tile_w : 16;
-      K.th = d.tile_h ? d.tile_h : 16;
+      // 32x8: a tile's four 8x8 ray blocks side by side (measured fastest on
+      // the driving frame, whose ground and facade footprints are wide)
+      K.tw = d.tile_w ? d.tile_w : 32;
+      K.th = d.tile_h ? d.tile_h : 8;
       K.fx = d.fx;
       K.fy = d.fy;
       K.cx = d.cx;

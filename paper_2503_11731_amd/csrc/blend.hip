@@ -308,6 +308,59 @@ struct CamRay {
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
+  // Bit w set unless the staged record d provably has no valid hit (rho_hat
+  // within the cutoff and alpha >= alpha_min) at the pixel centres of wave
+  // w's 8x8 block.  rho_hat = min(rho, low-pass) <= r2 needs either the
+  // low-pass disc to reach the block or the surfel's (u, v) disc to meet the
+  // block's image; the block maps to a projective quadrilateral whose u and v
+  // ranges are attained at its corners (u, v are linear-fractional in the
+  // pixel and h'2 > 0 on it), so the test is exact up to the (u, v) bounding
+  // box and a rounding margin.  Grazing records keep every block.
+  __device__ uint32_t hit_blocks(const float4* d, int nw) const {
+#pragma clang fp contract(off)
+    const uint32_t all = (1u << nw) - 1u;
+    const float4 q0 = d[0], q1 = d[1], q2 = d[2];
+    if (__float_as_uint(d[4].x) & kFlagGrazing) return all;
+    // largest rho_hat with alpha >= alpha_min: log2 o - rho_hat / (2 ln 2) >= log2 alpha_min
+    const float ra = (q2.y - __log2f(K.alpha_min)) * (1.0f / kInv2Ln2);
+    float r2 = fminf(K.cutoff2, ra);
+    if (!(r2 >= 0.0f)) return 0u;
+    r2 = r2 * 1.001f + 1e-3f;
+    uint32_t m = 0u;
+    for (int w = 0; w < nw; ++w) {
+      const float x0 = (float)((w % wx) * 8) + 0.5f - q0.x, x1 = x0 + 7.0f;
+      const float y0 = (float)((w / wx) * 8) + 0.5f - q0.y, y1 = y0 + 7.0f;
+      if (K.lowpass) {
+        const float ex = x0 > 0.0f ? x0 : (x1 < 0.0f ? -x1 : 0.0f);
+        const float ey = y0 > 0.0f ? y0 : (y1 < 0.0f ? -y1 : 0.0f);
+        if (K.lp * (ex * ex + ey * ey) <= r2) {
+          m |= 1u << w;
+          continue;
+        }
+      }
+      const float xs[2] = {x0, x1}, ys[2] = {y0, y1};
+      float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+      bool front = true;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float dx = xs[c & 1], dy = ys[c >> 1];
+        const float h0 = q0.z * dx + q0.w * dy;
+        const float h1 = q1.x * dx + q1.y * dy;
+        const float h2 = 1.0f + q1.z * dx + q1.w * dy;
+        front = front && h2 > 1e-6f;
+        const float r = __builtin_amdgcn_rcpf(h2);
+        const float u = h0 * r, v = h1 * r;
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+      }
+      const float eu = umin > 0.0f ? umin : (umax < 0.0f ? -umax : 0.0f);
+      const float ev = vmin > 0.0f ? vmin : (vmax < 0.0f ? -vmax : 0.0f);
+      if (!front || !(eu * eu + ev * ev > r2)) m |= 1u << w;
+    }
+    return m;
+  }
   __device__ bool covered(const float4* R) const {
     return covers(__float_as_uint(R[4].z), __float_as_uint(R[4].w), px, py);
   }
@@ -487,6 +540,7 @@ struct LidarRay {
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block_wrap(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
+  __device__ uint32_t hit_blocks(const float4*, int nw) const { return (1u << nw) - 1u; }
   __device__ bool covered(const float4* R) const {
     return covers_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), pc, pb);
   }
@@ -636,9 +690,10 @@ __device__ __forceinline__ void commit_batch(const TileArgs& a, const Ray& ray, 
       }
     }
   }
+  const uint32_t hb = valid ? ray.hit_blocks(sh.rec[t], NT / 64) : 0u;
 #pragma unroll
   for (int w = 0; w < NT / 64; ++w) {
-    const uint64_t m = __ballot(valid && ray.touches(rect, w));
+    const uint64_t m = __ballot(valid && ((hb >> w) & 1u) && ray.touches(rect, w));
     if (lane == 0) sh.mask[t >> 6][w] = m;
   }
   __syncthreads();

@@ -82,7 +82,7 @@ def test_batched_forward_matches_per_sensor_and_oracle(tiles):
     n = scene["mean"].shape[1]
     toff = 0
     for i, s in enumerate(sensors):
-        tw, th = (tiles[i] if tiles else ((16, 16) if s["kind"] == "pinhole" else (32, 8)))
+        tw, th = (tiles[i] if tiles else (32, 8))
         o = raster.make_opts(gs.PRODUCTION, tile_w=tw, tile_h=th)
         bins = raster.spec_bins(scene, s, o)
         t_ref, s_ref = spec32.tile_pairs_fast(bins)

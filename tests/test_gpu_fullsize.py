@@ -1,7 +1,7 @@
 """Full-size parity in the launch configuration bench.py times.
 
 Driving frame: 1920x1080 pinhole, 1M corridor surfels with degree-3 SH, one
-per-sensor plan with 16x16 tiles and the default segment length (the horizon
+per-sensor plan with the default 32x8 tiles and the default segment length (the horizon
 tiles are split into segments and merged).  Integer outputs (visibility,
 3.1M-entry pair list, tile ranges) are compared bit for bit with the oracle's
 FP32 specification; float outputs on a sample the FP64 oracle computes ray by
@@ -69,14 +69,15 @@ def test_driving_1080p_full_size_parity():
     status = r.status()
     assert not status["overflow"]
     assert status["segments"] > 0, "the horizon tiles should be split at this size"
-    o = oracle_opts(gs.PRODUCTION, (16, 16))
+    tw, th = 32, 8  # the default camera tile
+    o = oracle_opts(gs.PRODUCTION, (tw, th))
     _say(f"  integer parity over {status['pairs'][0]} pairs")
     n_pairs = check_integer_parity(r, scene, cam, o)
     ranges = r.inspect(0)["ranges"].cpu().numpy().astype(np.int64)
     heavy = np.argsort(ranges[:, 1] - ranges[:, 0])[-2:]
-    n_tx = (cam["width"] + 15) // 16
+    n_tx = (cam["width"] + tw - 1) // tw
     rays = np.concatenate([raster.grid_rays(cam, 24)] +
-                          [_tile_rays(int(t), n_tx, 16, 16, cam["width"], cam["height"]) for t in heavy])
+                          [_tile_rays(int(t), n_tx, tw, th, cam["width"], cam["height"]) for t in heavy])
     _say(f"  oracle on {rays.size} rays (heaviest tiles {heavy.tolist()}, "
          f"{(ranges[heavy, 1] - ranges[heavy, 0]).tolist()} pairs)")
     ref = raster.render(scene, cam, o, rays=rays, margins=True)
