@@ -122,7 +122,7 @@ struct RecordArrays {
     o_qkey1 = L.take((size_t)cap_items * 4);
     o_qval0 = L.take((size_t)cap_items * 4);
     o_qval1 = L.take((size_t)cap_items * 4);
-    o_items = L.take((size_t)cap_items * 8);
+    o_items = L.take((size_t)cap_items * 16);
     part_stride = (size_t)pslot_cap * (size_t)rays;
     o_part = L.take(11 * part_stride * 4);
     o_flag = L.take((size_t)pslot_cap * 4);
@@ -373,7 +373,7 @@ void build_queue(gs_plan* p, RecordArrays& R, size_t rbase, void* workspace, hip
   a.walk = reinterpret_cast<unsigned long long*>(b + R.o_walk);
   a.key = reinterpret_cast<uint32_t*>(b + R.o_qkey0);
   a.val = reinterpret_cast<uint32_t*>(b + R.o_qval0);
-  a.items = reinterpret_cast<uint2*>(b + R.o_items);
+  a.items = reinterpret_cast<uint4*>(b + R.o_items);
   a.cap_items = R.cap_items;
   a.pslot_cap = R.pslot_cap;
   a.status = reinterpret_cast<uint32_t*>(b + R.o_status);
@@ -400,7 +400,7 @@ QueueArgs queue_args(const gs_plan* p, const RecordArrays& R, size_t rbase, int 
   q.n_sensors = s1 - s0;
   for (int i = 0; i <= q.n_sensors; ++i) q.tile_off[i] = p->batched ? p->tile_off[s0 + i] : (i ? R.n_tiles : 0);
   q.queue = reinterpret_cast<const uint32_t*>(b + (R.queue_buf ? R.o_qval1 : R.o_qval0));
-  q.items = reinterpret_cast<const uint2*>(b + R.o_items);
+  q.items = reinterpret_cast<const uint4*>(b + R.o_items);
   q.n_items = reinterpret_cast<const uint32_t*>(b + R.o_qhdr);
   q.hdr = reinterpret_cast<uint32_t*>(b + R.o_qhdr);
   q.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);

@@ -1002,10 +1002,9 @@ __device__ inline int sensor_of_tile(const QueueArgs& q, uint32_t gt) {
 // Adjoint of one work item (a whole tile, or one segment of a split tile
 // from the incoming state its slot holds).
 template <int NT, class Ray>
-__device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg,
+__device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
                          BlendShared<NT>& sh) {
   const Ray ray(a, tile);
-  const uint2 rg = a.ranges[gt];
   const uint32_t len = rg.y - rg.x;
   const uint32_t L = q.seg_len;
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
@@ -1032,12 +1031,11 @@ __device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32
 //    the workgroup again, for every ray that waits at it.
 template <int NT, class Ray>
 __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile, uint32_t gt, uint32_t sg,
-                         bool walk, BlendShared<NT>& sh) {
+                         uint2 rg, bool walk, BlendShared<NT>& sh) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const Ray ray(a, tile);
-  const uint2 rg = a.ranges[gt];
   const uint32_t len = rg.y - rg.x;
   const uint32_t L = q.seg_len;
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
@@ -1207,16 +1205,19 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
   for (int i = threadIdx.x; i < GS_MAX_SENSORS * 3; i += NT) (&sh.cnt[0][0])[i] = 0ull;
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_u[3] = next_action(q, main_left, n_items, !BWD && q.pslot_cap > 0, s_u);
+    if (threadIdx.x == 0)
+      s_u[3] = next_action(q, main_left, n_items, !BWD && q.pslot_cap > 0, s_u);
     __syncthreads();
     // the action and its item are workgroup-uniform: scalar registers
     const uint32_t act = rfl(s_u[3]);
     if (act == kActExit) break;
     uint32_t gt, sg;
+    uint2 rg;
     if (act == kActItem) {
-      const uint2 ts = q.items[q.queue[rfl(s_u[0])]];
-      gt = rfl(ts.x);
-      sg = rfl(ts.y);
+      const uint4 e = q.items[q.queue[rfl(s_u[0])]];
+      gt = rfl(e.x);
+      sg = rfl(e.y);
+      rg = make_uint2(rfl(e.z), rfl(e.w));
     } else {
       gt = rfl(s_u[4]);  // its slot state is read device-coherently
       sg = rfl(s_u[5]);
@@ -1224,18 +1225,19 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
     const int si = sensor_of_tile(q, gt);
     const TileArgs& a = q.tiles[si];
     const int tile = (int)gt - q.tile_off[si];
+    if (act != kActItem) rg = a.ranges[gt];
     const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
     if (BWD) {
       if (cam)
-        bwd_item<NT, CamRay>(q, a, tile, gt, sg, sh);
+        bwd_item<NT, CamRay>(q, a, tile, gt, sg, rg, sh);
       else if (KINDS & kKindLidar)
-        bwd_item<NT, LidarRay>(q, a, tile, gt, sg, sh);
+        bwd_item<NT, LidarRay>(q, a, tile, gt, sg, rg, sh);
     } else {
       const bool walk = act == kActWalk;
       if (cam)
-        fwd_item<NT, CamRay>(q, a, si, tile, gt, sg, walk, sh);
+        fwd_item<NT, CamRay>(q, a, si, tile, gt, sg, rg, walk, sh);
       else if (KINDS & kKindLidar)
-        fwd_item<NT, LidarRay>(q, a, si, tile, gt, sg, walk, sh);
+        fwd_item<NT, LidarRay>(q, a, si, tile, gt, sg, rg, walk, sh);
     }
   }
   // the workgroup's counts, once per sensor and counter

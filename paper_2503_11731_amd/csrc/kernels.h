@@ -62,7 +62,7 @@ struct QueueArgs {
   int n_sensors;
   int tile_off[GS_MAX_SENSORS + 1];
   const uint32_t* queue;     // item ids, heaviest first
-  const uint2* items;        // item id -> (record-space tile id, segment)
+  const uint4* items;        // item id -> (record-space tile id, segment, tile range)
   const uint32_t* n_items;   // device count (hdr[0])
   uint32_t* hdr;             // [0] items [1] slots [2] queue counter [3] walks listed [4] walks taken
                              // [5] split tiles left to merge [6] queue stalled
@@ -129,7 +129,7 @@ struct SegScanArgs {
   unsigned long long* walk;
   uint32_t* key;
   uint32_t* val;
-  uint2* items;
+  uint4* items;
   uint32_t cap_items, pslot_cap;
   uint32_t* status;
 };

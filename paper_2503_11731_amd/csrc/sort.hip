@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
     const uint32_t cost = c.x == 1 ? len : 2u * a.seg_len;
     a.key[item] = kmax - (cost < kmax ? cost : kmax);
     a.val[item] = item;
-    a.items[item] = make_uint2((uint32_t)t, sg);
+    a.items[item] = make_uint4((uint32_t)t, sg, rg.x, rg.y);
   }
 }
 
