@@ -382,14 +382,21 @@ struct CamRay {
     f[6] = R[3].w;
     f[7] = 1.0f;
   }
-  __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
+  // output channels of a ray with final transmittance T and sums acc
+  static __device__ void out_values(const TileArgs& a, float T, const float* acc, float* v) {
 #pragma clang fp contract(off)
-    const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
-    a.out[p] = fmaf(T, a.O.bg0, acc[0]);
-    a.out[HW + p] = fmaf(T, a.O.bg1, acc[1]);
-    a.out[2 * HW + p] = fmaf(T, a.O.bg2, acc[2]);
+    v[0] = fmaf(T, a.O.bg0, acc[0]);
+    v[1] = fmaf(T, a.O.bg1, acc[1]);
+    v[2] = fmaf(T, a.O.bg2, acc[2]);
 #pragma unroll
-    for (int c = 3; c < 8; ++c) a.out[c * HW + p] = acc[c];
+    for (int c = 3; c < 8; ++c) v[c] = acc[c];
+  }
+  __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
+    const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
+    float v[C];
+    out_values(a, T, acc, v);
+#pragma unroll
+    for (int c = 0; c < C; ++c) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
   }
@@ -556,6 +563,11 @@ struct LidarRay {
     f[0] = e.z;
     f[1] = R[3].z;
     f[2] = 1.0f;
+  }
+  static __device__ void out_values(const TileArgs&, float, const float* acc, float* v) {
+    v[0] = acc[0];
+    v[1] = acc[1];
+    v[2] = acc[2];
   }
   __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
     const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
@@ -807,6 +819,40 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
 // Wave total held by every lane -> held by lane 0 only (before a wave sum).
 __device__ __forceinline__ uint32_t lane0_only(uint32_t v) { return (threadIdx.x & 63) == 0 ? v : 0u; }
 
+// Writes the outputs of the tile's rays with `wr` set, through LDS: the rays
+// of a wave form an 8x8 block, so direct stores would write 32-byte pieces of
+// each image row; staged, every store instruction writes whole tile rows.
+// All threads call it; it reuses the record staging area (no batch is live).
+template <int NT, class Ray>
+__device__ void write_tile(const TileArgs& a, const Ray& ray, bool wr, float T, const float* acc, uint32_t last,
+                           BlendShared<NT>& sh) {
+  constexpr int C = Ray::C;
+  static_assert((C + 3) * NT * 4 <= sizeof(sh.rec), "staging area too small");
+  float* st = reinterpret_cast<float*>(&sh.rec[0][0]);
+  uint32_t* su = reinterpret_cast<uint32_t*>(st);
+  const int t = threadIdx.x;
+  float v[C];
+  Ray::out_values(a, T, acc, v);
+  __syncthreads();  // every wave is past its last read of the batch records
+#pragma unroll
+  for (int c = 0; c < C; ++c) st[c * NT + t] = v[c];
+  st[C * NT + t] = T;
+  su[(C + 1) * NT + t] = last;
+  su[(C + 2) * NT + t] = wr ? 1u : 0u;
+  __syncthreads();
+  const int tw = a.S.tw, row = t / tw, col = t - row * tw;
+  const int src = ((row >> 3) * (tw >> 3) + (col >> 3)) * 64 + (row & 7) * 8 + (col & 7);
+  const int px = ray.ox + col, py = ray.oy + row;
+  if (px < a.S.W && py < a.S.H && su[(C + 2) * NT + src]) {
+    const size_t HW = (size_t)a.S.W * a.S.H, p = (size_t)py * a.S.W + px;
+#pragma unroll
+    for (int c = 0; c < C; ++c) a.out[c * HW + p] = st[c * NT + src];
+    a.T_final[p] = st[C * NT + src];
+    a.n_last[p] = su[(C + 1) * NT + src];
+  }
+  __syncthreads();  // the staging area is free again
+}
+
 // Adds the wave's counts to the workgroup's counters of sensor si.
 template <int NT>
 __device__ __forceinline__ void count_wg(BlendShared<NT>& sh, int si, uint32_t evals, uint32_t contribs,
@@ -879,16 +925,17 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   uint32_t n_eval = 0, n_contrib = 0, n64 = 0, marked = 0;
-  if (ray.inside) {
-    float T = 1.0f;
-    float acc[C];
+  float T = 1.0f;
+  float acc[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-    uint32_t last = rg.x;
+  for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+  uint32_t last = rg.x;
+  bool wr = false;
+  if (ray.inside) {
     const uint32_t sg = merge_from<NT, Ray>(n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc, last, n_eval,
                                             n_contrib);
     if (sg == n_seg) {
-      ray.write(a, T, acc, last);
+      wr = true;
     } else {
       // the stop lies in segment sg (or may): keep the incoming state there
       // (stored by the merge), mark the slot and list a walk of it
@@ -899,6 +946,7 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
       marked = sg + 1;
     }
   }
+  write_tile<NT>(a, ray, wr, T, acc, last, sh);
   count_wg(sh, si, n_eval, n_contrib, n64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
@@ -1100,7 +1148,7 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
   }
   if (!partial) {
     count_wg(sh, si, lane0_only(n_eval_w), n_contrib, n64);
-    if (ray.inside) ray.write(a, T, acc, last);
+    write_tile<NT>(a, ray, ray.inside, T, acc, last, sh);
     return;
   }
   count_wg(sh, si, 0u, 0u, n64);
