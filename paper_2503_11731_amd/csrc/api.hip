@@ -63,7 +63,7 @@ struct RecordArrays {
          o_pval1 = 0, o_ranges = 0, o_status = 0, o_gacc = 0;
   // compositing work queue
   size_t o_pslot = 0, o_arrive = 0, o_qhdr = 0, o_sbsum = 0, o_qkey0 = 0, o_qkey1 = 0, o_qval0 = 0, o_qval1 = 0,
-         o_items = 0, o_part = 0, part_stride = 0, o_flag = 0, o_walk = 0;
+         o_items = 0, o_part = 0, part_stride = 0, o_flag = 0, o_walk = 0, o_qcnt = 0;
   uint32_t n_rec = 0, cap = 0;
   uint32_t seg_len = 0, cap_items = 0, pslot_cap = 0;
   int n_tiles = 0, tile_bits = 0, rays = 256, key_bits = 16;
@@ -87,7 +87,7 @@ struct RecordArrays {
     while ((1 << tile_bits) < tiles) ++tile_bits;
     pair_buf = ((tile_bits + 7) / 8) % 2;
     const size_t N = n;
-    o_status = L.take(16 * 4);
+    o_status = L.take(kStWords * 4);
     o_rec = L.take(N * 64);
     o_rec64 = L.take(N * 8 * kRec64);
     o_grz = L.take(N * 8 * kGrz);
@@ -117,6 +117,7 @@ struct RecordArrays {
     o_pslot = L.take((size_t)tiles * 4);
     o_arrive = L.take((size_t)tiles * 4);
     o_qhdr = L.take(256);
+    o_qcnt = L.take(kQueues * kQCntStride * 4);
     o_sbsum = L.take(seg_bsum_words(tiles) * 4);
     o_qkey0 = L.take((size_t)cap_items * 4);
     o_qkey1 = L.take((size_t)cap_items * 4);
@@ -377,6 +378,7 @@ void build_queue(gs_plan* p, RecordArrays& R, size_t rbase, void* workspace, hip
   a.cap_items = R.cap_items;
   a.pslot_cap = R.pslot_cap;
   a.status = reinterpret_cast<uint32_t*>(b + R.o_status);
+  a.qcnt = reinterpret_cast<uint32_t*>(b + R.o_qcnt);
   launch_build_items(a, st);
   uint32_t* qk[2] = {reinterpret_cast<uint32_t*>(b + R.o_qkey0), reinterpret_cast<uint32_t*>(b + R.o_qkey1)};
   uint32_t* qv[2] = {reinterpret_cast<uint32_t*>(b + R.o_qval0), reinterpret_cast<uint32_t*>(b + R.o_qval1)};
@@ -406,7 +408,7 @@ QueueArgs queue_args(const gs_plan* p, const RecordArrays& R, size_t rbase, int 
   q.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);
   q.walk = reinterpret_cast<unsigned long long*>(b + R.o_walk);
   q.cap_items = R.cap_items;
-  q.counter = reinterpret_cast<uint32_t*>(b + R.o_qhdr) + 2;
+  q.counter = reinterpret_cast<uint32_t*>(b + R.o_qcnt);
   q.arrive = reinterpret_cast<uint32_t*>(b + R.o_arrive);
   q.pslot_base = reinterpret_cast<const uint32_t*>(b + R.o_pslot);
   q.part = reinterpret_cast<float*>(b + R.o_part);
@@ -425,7 +427,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       const ScenePlan& sp = p->scenes[s.scene];
       SensorWS ws = sensor_ws(p, s, workspace);
       hipEvent_t ev = stage_begin(p, st);
-      launch_fill_u32(ws.status, 0u, 16, st);
+      launch_fill_u32(ws.status, 0u, kStWords, st);
       launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
       launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
       launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, st);
@@ -444,7 +446,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   // batched step
   SensorWS g = record_ws(p->G, workspace, p->gbase, 0);
   hipEvent_t ev = stage_begin(p, st);
-  launch_fill_u32(g.status, 0u, 16, st);
+  launch_fill_u32(g.status, 0u, kStWords, st);
   for (size_t si = 0; si < p->sensors.size(); ++si) {
     SensorPlan& s = p->sensors[si];
     const ScenePlan& sp = p->scenes[s.scene];
@@ -673,7 +675,7 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     // per-sensor region
     Layout R;
     const size_t HW = (size_t)K.W * K.H;
-    s.o_status = R.take(16 * 4);
+    s.o_status = R.take(kStWords * 4);
     s.o_pose = R.take(12 * 4 * (size_t)sp.desc.n_groups);
     s.o_Tfinal = R.take(HW * 4);
     s.o_nlast = R.take(HW * 4);
@@ -835,7 +837,7 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
     launch_fill_f32(g.gacc, 0.0f, (size_t)p->G.n_rec * kGradFields, st);
     QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, nullptr, outputs,
                              grad_outputs);
-    launch_fill_u32(q.counter, 0u, 1, st);
+    launch_fill_u32(q.counter, 0u, kQueues * kQCntStride, st);
     launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_bwd, true, st);
     stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
   }
@@ -847,7 +849,7 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
       hipEvent_t ev = stage_begin(p, st);
       launch_fill_f32(ws.gacc, 0.0f, (size_t)N * kGradFields, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, nullptr, outputs, grad_outputs);
-      launch_fill_u32(q.counter, 0u, 1, st);
+      launch_fill_u32(q.counter, 0u, kQueues * kQCntStride, st);
       launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_bwd, true, st);
       stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
     }
@@ -876,7 +878,20 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   memset(out, 0, sizeof(*out));
   bool over = false, stalled = false;
   auto read = [&](size_t off, uint32_t* w) {
-    return hipMemcpy(w, static_cast<const char*>(workspace) + off, 16 * 4, hipMemcpyDeviceToHost);
+    return hipMemcpy(w, static_cast<const char*>(workspace) + off, kStWords * 4, hipMemcpyDeviceToHost);
+  };
+  // pair counts: the base words plus the per-XCD replicas
+  auto u64at = [](const uint32_t* w, int i) { return (int64_t)w[i] | ((int64_t)w[i + 1] << 32); };
+  auto add_counts = [&](const uint32_t* w) {
+    out->fp64_pairs += w[kStFp64];
+    out->evaluated += u64at(w, kStEvals);
+    out->composited += u64at(w, kStContrib);
+    for (int x = 0; x < 8; ++x) {
+      const uint32_t* r = w + kStRep + 8 * x;
+      out->evaluated += u64at(r, 0);
+      out->composited += u64at(r, 2);
+      out->fp64_pairs += r[4];
+    }
   };
   auto read_queue = [&](const RecordArrays& R, size_t base) -> hipError_t {
     uint32_t h[16];
@@ -889,29 +904,25 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
     return e;
   };
   if (p->batched) {
-    uint32_t w[16];
+    uint32_t w[kStWords];
     GS_HIP_TRY(read(p->gbase + p->G.o_status, w));
     out->pairs[0] = w[kStPairs];
-    out->fp64_pairs = w[kStFp64];
-    out->evaluated = (int64_t)w[kStEvals] | ((int64_t)w[kStEvals + 1] << 32);
-    out->composited = (int64_t)w[kStContrib] | ((int64_t)w[kStContrib + 1] << 32);
+    add_counts(w);
     over = w[kStOverflow] != 0;
     GS_HIP_TRY(read_queue(p->G, p->gbase));
     for (size_t si = 0; si < p->sensors.size(); ++si) {
-      uint32_t ws[16];
+      uint32_t ws[kStWords];
       GS_HIP_TRY(read(p->sensors[si].base + p->sensors[si].o_status, ws));
       out->n_visible[si] = (int32_t)ws[kStVisible];
     }
   } else {
     for (size_t si = 0; si < p->sensors.size(); ++si) {
       const SensorPlan& s = p->sensors[si];
-      uint32_t w[16];
+      uint32_t w[kStWords];
       GS_HIP_TRY(read(s.base + s.R.o_status, w));
       out->pairs[si] = w[kStPairs];
       out->n_visible[si] = (int32_t)w[kStVisible];
-      out->fp64_pairs += w[kStFp64];
-      out->evaluated += (int64_t)w[kStEvals] | ((int64_t)w[kStEvals + 1] << 32);
-      out->composited += (int64_t)w[kStContrib] | ((int64_t)w[kStContrib + 1] << 32);
+      add_counts(w);
       over = over || w[kStOverflow] != 0;
       GS_HIP_TRY(read_queue(s.R, s.base));
     }

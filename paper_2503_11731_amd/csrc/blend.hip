@@ -418,7 +418,7 @@ struct CamRay {
     const float gz = g[3] * wgt;
     float g_rhohat = 0.0f;
     if (!e.clamped) {
-      gr[9] = o > 0.0f ? dal * al / o : 0.0f;
+      gr[9] = o > 0.0f ? dal * al * __builtin_amdgcn_rcpf(o) : 0.0f;
       g_rhohat = -0.5f * dal * al;
     }
     const float g_rho = e.lp_used ? 0.0f : g_rhohat;
@@ -589,7 +589,7 @@ struct LidarRay {
     gr[14] = g[1] * wgt;
     float g_rhohat = 0.0f;
     if (!e.clamped) {
-      gr[13] = o > 0.0f ? dal * al / o : 0.0f;
+      gr[13] = o > 0.0f ? dal * al * __builtin_amdgcn_rcpf(o) : 0.0f;
       g_rhohat = -0.5f * dal * al;
     }
     const float g_rho = e.lp_used ? 0.0f : g_rhohat;
@@ -997,6 +997,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
   uint32_t wlast = last;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
+  wlast = rfl(wlast);
   uint32_t n64 = 0;
   const int w = t >> 6;
   for (uint32_t base = b0; base < end; base += NT) {
@@ -1004,13 +1005,15 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
     __syncthreads();
     stage_batch<NT>(a, ray, base, end, sh);
     const int nch = (int)((min((uint32_t)NT, end - base) + 63) / 64);
-    for (int c = 0; c < nch; ++c) {
+    bool past = false;  // wave-uniform: every later pair is past the wave's last contribution
+    for (int c = 0; c < nch && !past; ++c) {
       uint64_t m = uniform_mask(&sh.mask[c][w]);
+      const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(c) << 6;
       while (m) {
-      const int j = c * 64 + __builtin_ctzll(m);
+      const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
       m &= m - 1;
       if (base + j >= wlast) {
-        c = nch;
+        past = true;
         break;
       }
       const bool active = base + j < last;
@@ -1024,7 +1027,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         const float wgt = al * T;
         float f[C];
         ray.feat(sh.rec[j], e, f);
-        const float inv1m = 1.0f / (1.0f - al);
+        const float inv1m = __builtin_amdgcn_rcpf(1.0f - al);
         float dal = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -1205,7 +1208,8 @@ __device__ bool take_walk(const QueueArgs& q, uint32_t idx, uint32_t* u) {
 // takes a walk ticket (one atomic) and waits until that index is listed, or
 // leaves once no split tile is left to merge and the ticket lies past the
 // list (forward pass only; the adjoint has no walks).
-__device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t n_items, bool walks, uint32_t* u) {
+__device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& drained, uint32_t xcc,
+                                uint32_t n_items, bool walks, uint32_t* u) {
   if (walks) {
     const uint32_t cnt = min(load_agent(q.hdr + 3), q.pslot_cap);
     const uint32_t pop = load_agent(q.hdr + 4);
@@ -1216,10 +1220,17 @@ __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t n_
     }
   }
   if (main_left) {
-    const uint32_t it = atomicAdd(q.counter, 1u);
-    if (it < n_items) {
-      u[0] = it;
-      return kActItem;
+    // this XCD's sub-queue first, then the others (drained: bit per sub-queue)
+    for (uint32_t r = 0; r < (uint32_t)kQueues; ++r) {
+      const uint32_t x = (xcc + r) % kQueues;
+      if ((drained >> x) & 1u) continue;
+      const uint32_t k = atomicAdd(q.counter + kQCntStride * x, 1u);
+      const uint32_t it = k * kQueues + x;
+      if (k < n_items && it < n_items) {
+        u[0] = it;
+        return kActItem;
+      }
+      drained |= 1u << x;
     }
     main_left = false;
   }
@@ -1250,11 +1261,13 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
   uint32_t* s_u = sh.u;
   const uint32_t n_items = min(*q.n_items, q.cap_items);
   bool main_left = true;  // thread 0 only
+  uint32_t drained = 0, xcc = 0;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
   for (int i = threadIdx.x; i < GS_MAX_SENSORS * 3; i += NT) (&sh.cnt[0][0])[i] = 0ull;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0)
-      s_u[3] = next_action(q, main_left, n_items, !BWD && q.pslot_cap > 0, s_u);
+      s_u[3] = next_action(q, main_left, drained, xcc & 7u, n_items, !BWD && q.pslot_cap > 0, s_u);
     __syncthreads();
     // the action and its item are workgroup-uniform: scalar registers
     const uint32_t act = rfl(s_u[3]);
@@ -1293,11 +1306,13 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
   const int i = threadIdx.x;
   if (!BWD && i < q.n_sensors * 3) {
     const unsigned long long v = (&sh.cnt[0][0])[i];
-    uint32_t* st = q.tiles[i / 3].status;
+    uint32_t xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+    uint32_t* st = q.tiles[i / 3].status + kStRep + 8 * (xcc & 7u);
     if (v) {
-      if (i % 3 == 0) atomicAdd(reinterpret_cast<unsigned long long*>(st + kStEvals), v);
-      else if (i % 3 == 1) atomicAdd(reinterpret_cast<unsigned long long*>(st + kStContrib), v);
-      else atomicAdd(st + kStFp64, (uint32_t)v);
+      if (i % 3 == 0) atomicAdd(reinterpret_cast<unsigned long long*>(st), v);
+      else if (i % 3 == 1) atomicAdd(reinterpret_cast<unsigned long long*>(st + 2), v);
+      else atomicAdd(st + 4, (uint32_t)v);
     }
   }
 }

@@ -77,6 +77,12 @@ struct SensorWS {
 
 // status word indices
 enum { kStPairs = 0, kStOverflow = 1, kStVisible = 2, kStFp64 = 3, kStEvals = 4 /* u64 */, kStContrib = 6 /* u64 */ };
+// The compositing kernel adds its pair counts to one of 8 replicas (one per
+// XCD) of the three counters, words kStRep + 8 x: [0..1] evaluated (u64),
+// [2..3] composited (u64), [4] FP64 re-solves; the host sums them.  Atomics
+// of every workgroup on the same three words serialise across the device.
+constexpr int kStRep = 16;
+constexpr int kStWords = kStRep + 8 * 8;
 
 __device__ inline int group_of(const GroupsK& g, int i) {
   int lo = 0, hi = g.n - 1;

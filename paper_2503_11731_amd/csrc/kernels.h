@@ -50,6 +50,12 @@ struct TileArgs {
   size_t gacc_stride;
 };
 
+// The sorted work items are dealt round-robin to 8 sub-queues (one per XCD,
+// item i to sub-queue i mod 8) with one counter each, 64 bytes apart: one
+// counter popped by every workgroup of the device serialises the pops.
+constexpr int kQueues = 8;
+constexpr int kQCntStride = 16;
+
 // Persistent compositing queue over (tile, segment) work items of one record
 // space (one sensor, or every sensor of a batched step).
 //
@@ -67,7 +73,7 @@ struct QueueArgs {
   uint32_t* hdr;             // [0] items [1] slots [2] queue counter [3] walks listed [4] walks taken
                              // [5] split tiles left to merge [6] queue stalled
   uint32_t cap_items;
-  uint32_t* counter;         // zeroed before each launch
+  uint32_t* counter;         // 8 sub-queue counters, kQCntStride words apart; zeroed before each launch
   uint32_t* arrive;          // per tile: segments finished (forward)
   const uint32_t* pslot_base;  // per tile: first partial-state slot
   float* part;               // [11][pslot_cap * rays per tile]
@@ -115,7 +121,7 @@ void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, 
 // len <= L); item_base / pslot_base by exclusive scans; items written with
 // keys (cost, heaviest first) and ids for the radix sort; arrival counters and
 // the queue counter cleared.  hdr[0] = items, hdr[1] = partial slots,
-// hdr[2] = queue counter.
+// hdr[2] unused (the sub-queue counters are cleared here too).
 struct SegScanArgs {
   const uint2* ranges;
   int n_tiles;
@@ -132,6 +138,7 @@ struct SegScanArgs {
   uint4* items;
   uint32_t cap_items, pslot_cap;
   uint32_t* status;
+  uint32_t* qcnt;  // the 8 sub-queue counters (kQCntStride words apart)
 };
 void launch_build_items(const SegScanArgs& a, hipStream_t st);
 size_t seg_bsum_words(int n_tiles);
