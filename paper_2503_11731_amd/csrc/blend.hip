@@ -636,7 +636,11 @@ __device__ __forceinline__ float swz_xor(float v) {
 // permute), leaving lane l < 16 with the wave total of field
 // 8 b0 + 4 b1 + 2 b2 + b3 (b_i = bit i of l), which it adds with one atomic.
 // All lanes must be active.
-__device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* gacc, size_t stride, int lane) {
+// Wave sums of the 16 gradient fields of one pair, added to the batch's LDS
+// sums of its record j (the batch's record sums go to memory once, so a
+// record hit by several waves of the tile costs one global atomic per field).
+template <int NT>
+__device__ __forceinline__ void flush_grads(const float* g, float (*gs)[NT], uint32_t j, int lane) {
   const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
   float x8[8], x4[4], x2[2];
 #pragma unroll
@@ -649,11 +653,19 @@ __device__ __forceinline__ void flush_grads(const float* g, uint32_t s, float* g
   x += swz_xor<16>(x);
   x += __shfl_xor(x, 32, 64);
   const int f = (b0 ? 8 : 0) + (b1 ? 4 : 0) + (b2 ? 2 : 0) + (b3 ? 1 : 0);
-  if (lane < 16 && x != 0.0f) atomicAdd(gacc + (size_t)f * stride + s, x);
+  if (lane < 16 && x != 0.0f) atomicAdd(&gs[f][j], x);
 }
 
-// Shared-memory state of one compositing workgroup.
+// Per-batch gradient sums of the adjoint: [field][record of the batch].
+template <int NT, bool BWD>
+struct GradArea {
+  float g[kGradFields][NT];
+};
 template <int NT>
+struct GradArea<NT, false> {};
+
+// Shared-memory state of one compositing workgroup.
+template <int NT, bool BWD = false>
 struct BlendShared {
   float4 rec[NT][5];
   uint32_t id[NT];
@@ -665,14 +677,15 @@ struct BlendShared {
   // workgroup, added to the status words once at exit: per-item global
   // atomics on the same few words serialise across the whole device
   unsigned long long cnt[GS_MAX_SENSORS][3];
+  GradArea<NT, BWD> ga;
 };
 
 // Writes this thread's record (pair `valid`, surfel s, raw record x) into
 // batch slot threadIdx.x, staging a grazing record's FP64 re-solve data in an
 // LDS slot when one is free, and stores the per-wave rectangle masks.
-template <int NT, class Ray>
+template <int NT, class Ray, class SH>
 __device__ __forceinline__ void commit_batch(const TileArgs& a, const Ray& ray, bool valid, uint32_t s,
-                                             const RawRec& x, BlendShared<NT>& sh) {
+                                             const RawRec& x, SH& sh) {
   const int t = threadIdx.x, lane = t & 63;
   uint2 rect = make_uint2(0u, 0u);
   if (valid) {
@@ -715,9 +728,8 @@ __device__ __forceinline__ void commit_batch(const TileArgs& a, const Ray& ray, 
 // and for every 64-record chunk c and wave w stores in mask[c][w] the bit
 // mask of the chunk's records whose rectangle touches wave w's 8x8 block.
 // A wave then walks only the set bits, in order.
-template <int NT, class Ray>
-__device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, uint32_t base, uint32_t b1,
-                                            BlendShared<NT>& sh) {
+template <int NT, class Ray, class SH>
+__device__ __forceinline__ void stage_batch(const TileArgs& a, const Ray& ray, uint32_t base, uint32_t b1, SH& sh) {
   const uint32_t k = base + threadIdx.x;
   const bool valid = k < b1;
   uint32_t s = 0;
@@ -967,7 +979,7 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
 // or the merge's (T_in, prefix) for a segment.
 template <int NT, class Ray>
 __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, const float* part, size_t ps,
-                          size_t pe, BlendShared<NT>& sh) {
+                          size_t pe, BlendShared<NT, true>& sh) {
 #pragma clang fp contract(off)
   uint32_t& s_max = sh.u[1];
   constexpr int C = Ray::C;
@@ -1002,6 +1014,8 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
   const int w = t >> 6;
   for (uint32_t base = b0; base < end; base += NT) {
     if (t == 0) sh.u[2] = 0u;
+#pragma unroll
+    for (int f = 0; f < kGradFields; ++f) sh.ga.g[f][t] = 0.0f;
     __syncthreads();
     stage_batch<NT>(a, ray, base, end, sh);
     const int nch = (int)((min((uint32_t)NT, end - base) + 63) / 64);
@@ -1038,7 +1052,17 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         ray.grads(a, sh.rec[j], e, dal, wgt, g, gr);
         T = T * (1.0f - al);
       }
-      if (__ballot(hit) != 0) flush_grads(gr, sh.id[j], a.gacc, a.gacc_stride, lane);
+      if (__ballot(hit) != 0) flush_grads<NT>(gr, sh.ga.g, j, lane);
+      }
+    }
+    __syncthreads();
+    // the batch's gradient sums, thread t for record t
+    if (base + t < end) {
+      const uint32_t sid = sh.id[t];
+#pragma unroll
+      for (int f = 0; f < kGradFields; ++f) {
+        const float v = sh.ga.g[f][t];
+        if (v != 0.0f) atomicAdd(a.gacc + (size_t)f * a.gacc_stride + sid, v);
       }
     }
   }
@@ -1054,7 +1078,7 @@ __device__ inline int sensor_of_tile(const QueueArgs& q, uint32_t gt) {
 // from the incoming state its slot holds).
 template <int NT, class Ray>
 __device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
-                         BlendShared<NT>& sh) {
+                         BlendShared<NT, true>& sh) {
   const Ray ray(a, tile);
   const uint32_t len = rg.y - rg.x;
   const uint32_t L = q.seg_len;
@@ -1257,7 +1281,7 @@ __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& d
 // the walk entries the merges list.
 template <int NT, bool BWD, int KINDS>
 __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
-  __shared__ BlendShared<NT> sh;
+  __shared__ BlendShared<NT, BWD> sh;
   uint32_t* s_u = sh.u;
   const uint32_t n_items = min(*q.n_items, q.cap_items);
   bool main_left = true;  // thread 0 only
@@ -1288,7 +1312,7 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
     const int tile = (int)gt - q.tile_off[si];
     if (act != kActItem) rg = a.ranges[gt];
     const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
-    if (BWD) {
+    if constexpr (BWD) {
       if (cam)
         bwd_item<NT, CamRay>(q, a, tile, gt, sg, rg, sh);
       else if (KINDS & kKindLidar)
