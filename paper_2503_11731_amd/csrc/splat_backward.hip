@@ -29,6 +29,9 @@ __device__ inline void acc_cross(const double* a, const double* b, double* acc) 
 }
 __device__ inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+// One instantiation per sensor kind: the two chain rules share little, and
+// one kernel holding both needs twice the registers.
+template <int KIND>
 __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
   const PrepArgs& a = A.p;
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -95,18 +98,19 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
   double gcol[3] = {0, 0, 0};
   double g_int = 0.0;
 
-  if (a.S.kind == GS_SENSOR_PINHOLE) {
+  if constexpr (KIND == GS_SENSOR_PINHOLE) {
     const double fx = a.S.fx, fy = a.S.fy;
     const double muz = mus[2];
+    const double ifx = 1.0 / fx, ify = 1.0 / fy, idet = 1.0 / det, imuz = 1.0 / muz;
     const double g0[3] = {gf[0], gf[2], gf[4]};  // dL/dP[:,0]
     const double g1[3] = {gf[1], gf[3], gf[5]};  // dL/dP[:,1]
-    const double S0 = dot3(g0, c0) / fx, S1 = dot3(g1, c1) / fy;
+    const double S0 = dot3(g0, c0) * ifx, S1 = dot3(g1, c1) * ify;
     const double Ssum = S0 + S1;
-    const double gdet = -Ssum * muz / (det * det);
+    const double gdet = -Ssum * muz * idet * idet;
     double ga0[3], ga1[3];
     for (int k = 0; k < 3; ++k) {
-      ga0[k] = g0[k] * muz / (fx * det);
-      ga1[k] = g1[k] * muz / (fy * det);
+      ga0[k] = g0[k] * muz * ifx * idet;
+      ga1[k] = g1[k] * muz * ify * idet;
     }
     // adj col0 = r1 x r2 ; adj col1 = r2 x r0
     acc_cross(Mr[2], ga0, gr1);
@@ -120,9 +124,9 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
     }
     // mu_z from P's scale, from the record's mu_z, and pc
     const double gpcx = gf[6], gpcy = gf[7];
-    gmus_extra[0] += gpcx * fx / muz;
-    gmus_extra[1] += gpcy * fy / muz;
-    gmus_extra[2] += Ssum / det + (double)gf[8] - (gpcx * fx * mus[0] + gpcy * fy * mus[1]) / (muz * muz);
+    gmus_extra[0] += gpcx * fx * imuz;
+    gmus_extra[1] += gpcy * fy * imuz;
+    gmus_extra[2] += Ssum * idet + (double)gf[8] - (gpcx * fx * mus[0] + gpcy * fy * mus[1]) * imuz * imuz;
     g_op = gf[9];
     gcol[0] = gf[10];
     gcol[1] = gf[11];
@@ -136,7 +140,8 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
     gns[2] = sgn * gf[15];
   } else {
     const double rn = sqrt(dot3(mus, mus));
-    const double mh[3] = {mus[0] / rn, mus[1] / rn, mus[2] / rn};
+    const double irn = 1.0 / rn, idet = 1.0 / det;
+    const double mh[3] = {mus[0] * irn, mus[1] * irn, mus[2] * irn};
     const double* adjc[3] = {c0, c1, c2};
     // Q[r][c] = adj[r][c] rn / det, adj[r][c] = column c, entry r
     double gsum = 0.0;
@@ -144,11 +149,11 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
     for (int c = 0; c < 3; ++c)
       for (int r = 0; r < 3; ++r) {
         const double gq = gf[3 * r + c];
-        gcolv[c][r] = gq * rn / det;
+        gcolv[c][r] = gq * rn * idet;
         gsum += gq * adjc[c][r];
       }
-    const double g_rn = gsum / det + (double)gf[12];
-    const double gdet = -gsum * rn / (det * det);
+    const double g_rn = gsum * idet + (double)gf[12];
+    const double gdet = -gsum * rn * idet * idet;
     acc_cross(Mr[2], gcolv[0], gr1);
     acc_cross(gcolv[0], Mr[1], gr2);
     acc_cross(Mr[0], gcolv[1], gr2);
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
     }
     const double gmh[3] = {gf[9], gf[10], gf[11]};
     const double pr = dot3(mh, gmh);
-    for (int k = 0; k < 3; ++k) gmus_extra[k] += (gmh[k] - mh[k] * pr) / rn + g_rn * mh[k];
+    for (int k = 0; k < 3; ++k) gmus_extra[k] += (gmh[k] - mh[k] * pr) * irn + g_rn * mh[k];
     g_op = gf[13];
     g_int = gf[14];
   }
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
   }
 
   // colour from SH: view direction v = R^T mu_s (group frame), colour = max(0, sum c Y + 1/2)
-  if (a.S.kind == GS_SENSOR_PINHOLE && a.sh_degree >= 0) {
+  if (KIND == GS_SENSOR_PINHOLE && a.sh_degree >= 0) {
     double v[3];
     for (int c = 0; c < 3; ++c) v[c] = R[c] * mus[0] + R[3 + c] * mus[1] + R[6 + c] * mus[2];
     const double vn = sqrt(dot3(v, v));
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
     const double pr = dot3(dd, gd);
     // v = mu - c_group, so dL/dmu gains the projected direction gradient
     for (int c = 0; c < 3; ++c) gmu[c] += (gd[c] - dd[c] * pr) / vn;
-  } else if (a.S.kind == GS_SENSOR_PINHOLE) {
+  } else if (KIND == GS_SENSOR_PINHOLE) {
     if (A.g_rgb) {
       A.g_rgb[i] += (float)gcol[0];
       A.g_rgb[N + i] += (float)gcol[1];
@@ -256,7 +261,10 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
 
 void launch_splat_backward(const SplatBwdArgs& a, hipStream_t st) {
   if (a.p.n == 0) return;
-  hipLaunchKernelGGL(k_splat_backward, dim3((a.p.n + 255) / 256), dim3(256), 0, st, a);
+  if (a.p.S.kind == GS_SENSOR_PINHOLE)
+    hipLaunchKernelGGL(k_splat_backward<GS_SENSOR_PINHOLE>, dim3((a.p.n + 255) / 256), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_splat_backward<GS_SENSOR_LIDAR>, dim3((a.p.n + 255) / 256), dim3(256), 0, st, a);
 }
 
 }  // namespace gs
