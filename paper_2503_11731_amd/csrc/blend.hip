@@ -316,7 +316,9 @@ struct CamRay {
   // ranges are attained at its corners (u, v are linear-fractional in the
   // pixel and h'2 > 0 on it), so the test is exact up to the (u, v) bounding
   // box and a rounding margin.  Grazing records keep every block.
-  __device__ uint32_t hit_blocks(const float4* d, int nw) const {
+  template <class SH>
+  __device__ void prepare(const TileArgs&, SH&) const {}
+  __device__ uint32_t hit_blocks(const float4* d, int nw, const float (*)[6]) const {
 #pragma clang fp contract(off)
     const uint32_t all = (1u << nw) - 1u;
     const float4 q0 = d[0], q1 = d[1], q2 = d[2];
@@ -547,7 +549,103 @@ struct LidarRay {
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block_wrap(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
-  __device__ uint32_t hit_blocks(const float4*, int nw) const { return (1u << nw) - 1u; }
+  // Box of the ray directions of wave w's 8x8 block, relative to the tile's
+  // reference direction (dpix range per component), into LDS (threads
+  // w < nw).  The directions are products of the elevation and azimuth table
+  // entries, so each component's range is an interval product.
+  template <class SH>
+  __device__ void prepare(const TileArgs& a, SH& sh) const {
+    const int w = threadIdx.x;
+    if (w >= (int)(sizeof(sh.lbox) / sizeof(sh.lbox[0])) || w >= (int)(blockDim.x >> 6)) return;
+    const float* tb = a.S.tab;
+    const int c0 = ox + (w % wx) * 8, j0 = oy + (w / wx) * 8;
+    const int c1 = min(c0 + 7, a.S.W - 1), j1 = min(j0 + 7, a.S.H - 1);
+    float ce_lo = INFINITY, ce_hi = -INFINITY, se_lo = INFINITY, se_hi = -INFINITY;
+    float ca_lo = INFINITY, ca_hi = -INFINITY, sa_lo = INFINITY, sa_hi = -INFINITY;
+    for (int j = j0; j <= min(j1, j0 + 7); ++j) {
+      const float ce = tb[a.S.H + j], se = tb[2 * a.S.H + j];
+      ce_lo = fminf(ce_lo, ce);
+      ce_hi = fmaxf(ce_hi, ce);
+      se_lo = fminf(se_lo, se);
+      se_hi = fmaxf(se_hi, se);
+    }
+    for (int c = c0; c <= min(c1, c0 + 7); ++c) {
+      const float ca = tb[3 * a.S.H + c], sa = tb[3 * a.S.H + a.S.W + c];
+      ca_lo = fminf(ca_lo, ca);
+      ca_hi = fmaxf(ca_hi, ca);
+      sa_lo = fminf(sa_lo, sa);
+      sa_hi = fmaxf(sa_hi, sa);
+    }
+    float* b = sh.lbox[w];
+    if (c0 >= a.S.W || j0 >= a.S.H) {  // no ray of the image in this block
+      for (int k = 0; k < 6; ++k) b[k] = 0.0f;
+      return;
+    }
+    const float px[4] = {ce_lo * ca_lo, ce_lo * ca_hi, ce_hi * ca_lo, ce_hi * ca_hi};
+    const float py[4] = {ce_lo * sa_lo, ce_lo * sa_hi, ce_hi * sa_lo, ce_hi * sa_hi};
+    // relative to the tile direction dt, widened by a rounding margin
+    const float m = 1e-6f;
+    b[0] = fminf(fminf(px[0], px[1]), fminf(px[2], px[3])) - (float)dt[0] - m;
+    b[1] = fmaxf(fmaxf(px[0], px[1]), fmaxf(px[2], px[3])) - (float)dt[0] + m;
+    b[2] = fminf(fminf(py[0], py[1]), fminf(py[2], py[3])) - (float)dt[1] - m;
+    b[3] = fmaxf(fmaxf(py[0], py[1]), fmaxf(py[2], py[3])) - (float)dt[1] + m;
+    b[4] = se_lo - (float)dt[2] - m;
+    b[5] = se_hi - (float)dt[2] + m;
+  }
+  // As the camera's test, with the block's direction box: d = dpix + c lies
+  // in a box, h = Q d + e3 in an interval box, u = h0 / h2 and v = h1 / h2 in
+  // the interval quotients (h2 > 0 on the block).
+  __device__ uint32_t hit_blocks(const float4* d, int nw, const float (*box)[6]) const {
+#pragma clang fp contract(off)
+    const uint32_t all = (1u << nw) - 1u;
+    const float4 q0 = d[0], q1 = d[1], q2 = d[2], q3 = d[3];
+    if (__float_as_uint(q3.w) & kFlagGrazing) return all;
+    const float ra = (q3.y - __log2f(K.alpha_min)) * (1.0f / kInv2Ln2);
+    float r2 = fminf(K.cutoff2, ra);
+    if (!(r2 >= 0.0f)) return 0u;
+    r2 = r2 * 1.001f + 1e-3f;
+    const float Q[9] = {q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+    const float cc[3] = {q0.x, q0.y, q0.z};
+    uint32_t m = 0u;
+    for (int w = 0; w < nw; ++w) {
+      float mid[3], rad[3], dist2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float lo = box[w][2 * k] + cc[k], hi = box[w][2 * k + 1] + cc[k];
+        mid[k] = 0.5f * (lo + hi);
+        rad[k] = 0.5f * (hi - lo);
+        const float e = lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f);
+        dist2 += e * e;
+      }
+      if (K.lowpass && K.lp * dist2 <= r2) {
+        m |= 1u << w;
+        continue;
+      }
+      float hm[3], hr[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        hm[i] = Q[3 * i] * mid[0] + Q[3 * i + 1] * mid[1] + Q[3 * i + 2] * mid[2];
+        hr[i] = fabsf(Q[3 * i]) * rad[0] + fabsf(Q[3 * i + 1]) * rad[1] + fabsf(Q[3 * i + 2]) * rad[2];
+        hr[i] = hr[i] * 1.0001f + 1e-7f;
+      }
+      const float h2lo = 1.0f + hm[2] - hr[2], h2hi = 1.0f + hm[2] + hr[2];
+      if (!(h2lo > 1e-6f)) {
+        m |= 1u << w;
+        continue;
+      }
+      const float i_lo = __builtin_amdgcn_rcpf(h2lo), i_hi = __builtin_amdgcn_rcpf(h2hi);
+      float ev[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float a0 = hm[i] - hr[i], a1 = hm[i] + hr[i];
+        const float x0 = a0 * i_lo, x1 = a0 * i_hi, x2 = a1 * i_lo, x3 = a1 * i_hi;
+        const float lo = fminf(fminf(x0, x1), fminf(x2, x3)), hi = fmaxf(fmaxf(x0, x1), fmaxf(x2, x3));
+        ev[i] = lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f);
+      }
+      if (!(ev[0] * ev[0] + ev[1] * ev[1] > r2)) m |= 1u << w;
+    }
+    return m;
+  }
   __device__ bool covered(const float4* R) const {
     return covers_wrap(__float_as_uint(R[4].y), __float_as_uint(R[4].z), pc, pb);
   }
@@ -677,6 +775,7 @@ struct BlendShared {
   // workgroup, added to the status words once at exit: per-item global
   // atomics on the same few words serialise across the whole device
   unsigned long long cnt[GS_MAX_SENSORS][3];
+  float lbox[NT / 64][6];  // LiDAR: direction box of each wave's block
   GradArea<NT, BWD> ga;
 };
 
@@ -715,7 +814,7 @@ __device__ __forceinline__ void commit_batch(const TileArgs& a, const Ray& ray, 
       }
     }
   }
-  const uint32_t hb = valid ? ray.hit_blocks(sh.rec[t], NT / 64) : 0u;
+  const uint32_t hb = valid ? ray.hit_blocks(sh.rec[t], NT / 64, sh.lbox) : 0u;
 #pragma unroll
   for (int w = 0; w < NT / 64; ++w) {
     const uint64_t m = __ballot(valid && ((hb >> w) & 1u) && ray.touches(rect, w));
@@ -1080,6 +1179,7 @@ template <int NT, class Ray>
 __device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
                          BlendShared<NT, true>& sh) {
   const Ray ray(a, tile);
+  ray.prepare(a, sh);
   const uint32_t len = rg.y - rg.x;
   const uint32_t L = q.seg_len;
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
@@ -1111,6 +1211,7 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
   constexpr int C = Ray::C;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   const Ray ray(a, tile);
+  ray.prepare(a, sh);
   const uint32_t len = rg.y - rg.x;
   const uint32_t L = q.seg_len;
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
