@@ -10,7 +10,8 @@
 //            quantised to 8 mantissa bits.
 //   heads    opacity / colour / intensity = sigmoid, scale = l_a sigmoid,
 //            quaternion = raw, centre = x_a + l_a O_k; surfel n = a K + k.
-// Adjoint: FP32 VALU with per-block partial weight gradients added by atomics.
+// Adjoint: FP32 MFMA contractions with per-block partial weight gradients
+// added by atomics.
 #include <cstring>
 #include <string>
 
@@ -299,6 +300,54 @@ __global__ __launch_bounds__(128) void k_decode_fwd_valu(DecodeArgs a) {
   }
 }
 
+// dL/dy of one surfel's heads, written over its raw outputs y[0..J); returns
+// the surfel's share of dL/d l_a through its two scale heads.
+template <bool LIDAR>
+__device__ inline float heads_adjoint(const DecodeArgs& a, float* y, const float* bb, size_t n, size_t N, float la) {
+  constexpr int so = LIDAR ? 2 : 4;
+  float gy[so + 6];
+  const float s0 = sigmoidf(y[0] + bb[0]);
+  gy[0] = (a.gi_opacity ? a.gi_opacity[n] : 0.f) * s0 * (1.f - s0);
+  if (!LIDAR) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const float s = sigmoidf(y[1 + e] + bb[1 + e]);
+      gy[1 + e] = (a.gi_rgb ? a.gi_rgb[e * N + n] : 0.f) * s * (1.f - s);
+    }
+  } else {
+    const float s = sigmoidf(y[1] + bb[1]);
+    gy[1] = (a.gi_intensity ? a.gi_intensity[n] : 0.f) * s * (1.f - s);
+  }
+  float gla = 0.f;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float s = sigmoidf(y[so + e] + bb[so + e]);
+    const float gs = a.gi_scale ? a.gi_scale[e * N + n] : 0.f;
+    gy[so + e] = gs * la * s * (1.f - s);
+    gla += gs * s;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) gy[so + 2 + e] = a.gi_quat ? a.gi_quat[e * N + n] : 0.f;
+#pragma unroll
+  for (int j = 0; j < so + 6; ++j) y[j] = gy[j];
+  return gla;
+}
+
+__device__ inline f32x4 mfma_f32(float x, float y, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+}
+
+constexpr int kW1Cols = 48;  // W1 row in LDS: kIn columns, zero to three whole 16-column tiles
+
+// Adjoint, per block of 64 anchors of one group (4 waves x 16).  After the
+// forward layers and the heads adjoint (dL/dy in place of y), the four
+// contractions of the MLP adjoint run on FP32 MFMA (v_mfma_f32_16x16x4_f32;
+// lane l holds A[l%16][l/16], B[l/16][l%16], D[4(l/16)+r][l%16]):
+//   dH  = dY W2, ReLU-masked    per wave: 16 anchors x 32 hidden, over K*J
+//   dX  = dH W1                 per wave: 16 anchors x 35 (features, direction)
+//   dW2 = dY^T H, dW1 = dH^T X  per block: summed over its 64 anchors
+// Weights are staged in LDS as bf16 bits; each block adds its weight-gradient
+// partials to the global sums with one atomic per entry.
 __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   __shared__ float sD[4][16][4];
   __shared__ float sH[4][16][kHidden + 1];
@@ -306,11 +355,36 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   __shared__ float sGH[4][16][kHidden + 1];
   __shared__ float sGA[4][16][8];           // per anchor: dL/d scaling, dL/d xyz (3), dL/d dir (3)
   __shared__ float sCam[3];
+  __shared__ uint16_t sW1[kHidden][kW1Cols];
+  __shared__ __attribute__((aligned(16))) union {
+    uint16_t w2[kMaxKJ][kHidden + 2];  // W2 rows, for dH
+    uint16_t x[64][kFeat + 8];          // the block's features, for dW1
+  } sU;
   int g, a0;
   block_group(a, blockIdx.x, g, a0);
   const int t = threadIdx.x;
+  const int KJ = a.K * a.J;
   if (t == 0) group_camera(a, g, sCam);
   for (int q = t; q < 4 * 16 * 8; q += 256) (&sGA[0][0][0])[q] = 0.f;
+  const uint16_t* W2 = a.w2 + (size_t)g * KJ * kHidden;
+  const uint16_t* W1 = a.w1 + (size_t)g * kHidden * kIn;
+  for (int q = t; q < KJ * 4; q += 256) {
+    const int n = q >> 2, p = q & 3;
+    const uint4 v = *reinterpret_cast<const uint4*>(W2 + (size_t)n * kHidden + 8 * p);
+    uint32_t* d = reinterpret_cast<uint32_t*>(&sU.w2[n][8 * p]);
+    d[0] = v.x;
+    d[1] = v.y;
+    d[2] = v.z;
+    d[3] = v.w;
+  }
+  for (int q = t; q < kHidden * kW1Cols; q += 256) {
+    const int j = q / kW1Cols, k = q % kW1Cols;
+    sW1[j][k] = k < kIn ? W1[j * kIn + k] : (uint16_t)0;
+  }
+  // one 16-byte piece of the block's features per thread, held until the W2 area is free
+  uint4 xf = make_uint4(0, 0, 0, 0);
+  if (a0 + (t >> 2) < a.goff[g + 1])
+    xf = *reinterpret_cast<const uint4*>(a.feat + (size_t)(a0 + (t >> 2)) * kFeat + 8 * (t & 3));
   __syncthreads();
   WaveCtx c;
   c.g = g;
@@ -322,7 +396,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   c.aend = a.goff[g + 1];
   const float cam[3] = {sCam[0], sCam[1], sCam[2]};
   forward_layers(a, c, cam, sD[c.w], sH[c.w], sY[c.w]);
-  const int K = a.K, J = a.J, KJ = K * J;
+  const int K = a.K, J = a.J;
   const size_t N = (size_t)a.A * K;
   const float* B2 = a.b2 + (size_t)g * KJ;
   // heads adjoint, in place: sY <- dL/dy; per-anchor sums through LDS atomics
@@ -337,30 +411,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
     const size_t n = (size_t)ai * K + k;
     const float* bb = B2 + k * J;
     const float la = a.scaling[ai];
-    float gy[10];
-    const float s0 = sigmoidf(y[0] + bb[0]);
-    gy[0] = (a.gi_opacity ? a.gi_opacity[n] : 0.f) * s0 * (1.f - s0);
-    int so;
-    if (!a.lidar) {
-      for (int e = 0; e < 3; ++e) {
-        const float s = sigmoidf(y[1 + e] + bb[1 + e]);
-        gy[1 + e] = (a.gi_rgb ? a.gi_rgb[e * N + n] : 0.f) * s * (1.f - s);
-      }
-      so = 4;
-    } else {
-      const float s = sigmoidf(y[1] + bb[1]);
-      gy[1] = (a.gi_intensity ? a.gi_intensity[n] : 0.f) * s * (1.f - s);
-      so = 2;
-    }
-    float gla = 0.f;
-    for (int e = 0; e < 2; ++e) {
-      const float s = sigmoidf(y[so + e] + bb[so + e]);
-      const float gs = a.gi_scale ? a.gi_scale[e * N + n] : 0.f;
-      gy[so + e] = gs * la * s * (1.f - s);
-      gla += gs * s;
-    }
-    for (int e = 0; e < 4; ++e) gy[so + 2 + e] = a.gi_quat ? a.gi_quat[e * N + n] : 0.f;
-    for (int j = 0; j < J; ++j) y[j] = gy[j];
+    float gla = a.lidar ? heads_adjoint<true>(a, y, bb, n, N, la) : heads_adjoint<false>(a, y, bb, n, N, la);
     if (a.gi_mean) {
       for (int e = 0; e < 3; ++e) {
         const float gm = a.gi_mean[e * N + n];
@@ -373,28 +424,53 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
     atomicAdd(&sGA[c.w][al][0], gla);
   }
   __syncthreads();
+  const int r16 = c.lane & 15, k4 = c.lane >> 4;
   // dL/dh = dL/dy W2, masked by the ReLU
-  const uint16_t* W2 = a.w2 + (size_t)g * KJ * kHidden;
-  for (int q = c.lane; q < 16 * kHidden; q += 64) {
-    const int al = q / kHidden, j = q % kHidden;
-    float s = 0.f;
-    if (sH[c.w][al][j] > 0.f) {
-      for (int n = 0; n < KJ; ++n) s += sY[c.w][al][n] * bf2f(W2[(size_t)n * kHidden + j]);
+  {
+    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int n0 = 0; n0 < KJ; n0 += 4) {
+      const int n = n0 + k4;
+      const bool ok = n < KJ;
+      const int nc = ok ? n : 0;
+      const float av = ok ? sY[c.w][r16][nc] : 0.f;
+      const float b0 = ok ? bf2f(sU.w2[nc][r16]) : 0.f;
+      const float b1 = ok ? bf2f(sU.w2[nc][16 + r16]) : 0.f;
+      acc0 = mfma_f32(av, b0, acc0);
+      acc1 = mfma_f32(av, b1, acc1);
     }
-    sGH[c.w][al][j] = s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int al = 4 * k4 + i;
+      sGH[c.w][al][r16] = sH[c.w][al][r16] > 0.f ? acc0[i] : 0.f;
+      sGH[c.w][al][16 + r16] = sH[c.w][al][16 + r16] > 0.f ? acc1[i] : 0.f;
+    }
   }
   __syncthreads();
-  // dL/d features (written) and dL/d direction (to LDS)
-  const uint16_t* W1 = a.w1 + (size_t)g * kHidden * kIn;
-  for (int q = c.lane; q < 16 * kIn; q += 64) {
-    const int al = q / kIn, k = q % kIn;
-    const int ai = c.abase + al;
-    float s = 0.f;
-    for (int j = 0; j < kHidden; ++j) s += sGH[c.w][al][j] * bf2f(W1[j * kIn + k]);
-    if (k < kFeat) {
-      if (ai < c.aend && a.g_feat) a.g_feat[(size_t)ai * kFeat + k] += s;
-    } else {
-      sGA[c.w][al][4 + (k - kFeat)] = s;
+  *reinterpret_cast<uint4*>(&sU.x[t >> 2][8 * (t & 3)]) = xf;
+  // dL/d features (written) and dL/d direction (to LDS): dL/dh W1
+  {
+    f32x4 acc[3];
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j0 = 0; j0 < kHidden; j0 += 4) {
+      const int j = j0 + k4;
+      const float av = sGH[c.w][r16][j];
+#pragma unroll
+      for (int ct = 0; ct < 3; ++ct) acc[ct] = mfma_f32(av, bf2f(sW1[j][16 * ct + r16]), acc[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct) {
+      const int col = 16 * ct + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int al = 4 * k4 + i, ai = c.abase + al;
+        if (col < kFeat) {
+          if (ai < c.aend && a.g_feat) a.g_feat[(size_t)ai * kFeat + col] += acc[ct][i];
+        } else if (col < kIn) {
+          sGA[c.w][al][4 + (col - kFeat)] = acc[ct][i];
+        }
+      }
     }
   }
   __syncthreads();
@@ -410,41 +486,54 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
       if (a.g_scaling) a.g_scaling[ai] += sGA[c.w][al][0];
     }
   }
-  // weight gradients: partial sums over this block's anchors, one atomic per entry
-  if (a.g_w2 || a.g_b2) {
-    for (int q = t; q < KJ * (kHidden + 1); q += 256) {
-      const int n = q / (kHidden + 1), j = q % (kHidden + 1);
-      float s = 0.f;
-      for (int w = 0; w < 4; ++w)
-        for (int al = 0; al < 16; ++al) s += sY[w][al][n] * (j < kHidden ? sH[w][al][j] : 1.f);
-      if (j < kHidden) {
-        if (a.g_w2 && s != 0.f) atomicAdd(a.g_w2 + ((size_t)g * KJ + n) * kHidden + j, s);
-      } else if (a.g_b2 && s != 0.f) {
-        atomicAdd(a.g_b2 + (size_t)g * KJ + n, s);
+  // weight gradients over the block's 64 anchors (rows of invalid anchors are
+  // zero in dY and dH): 16x16 tiles of dW2 (rows n of K*J, columns j) and of
+  // dW1 (rows j, columns k of features + direction), shared out over the waves
+  const int nt2 = a.g_w2 ? 2 * ((KJ + 15) >> 4) : 0;
+  const int nt1 = a.g_w1 ? 6 : 0;
+  for (int tile = c.w; tile < nt2 + nt1; tile += 4) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (tile < nt2) {
+      const int n0 = 16 * (tile >> 1), j0 = 16 * (tile & 1);
+#pragma unroll 4
+      for (int s = 0; s < 16; ++s) {
+        const int an = 4 * s + k4;
+        acc = mfma_f32(sY[an >> 4][an & 15][n0 + r16], sH[an >> 4][an & 15][j0 + r16], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = n0 + 4 * k4 + i;
+        if (n < KJ && acc[i] != 0.f) atomicAdd(a.g_w2 + ((size_t)g * KJ + n) * kHidden + j0 + r16, acc[i]);
+      }
+    } else {
+      const int u = tile - nt2;
+      const int j0 = 16 * (u & 1), col = 16 * (u >> 1) + r16;
+#pragma unroll 4
+      for (int s = 0; s < 16; ++s) {
+        const int an = 4 * s + k4;
+        float bv = 0.f;
+        if (col < kFeat) bv = bf2f(sU.x[an][col]);
+        else if (col < kIn) bv = sD[an >> 4][an & 15][col - kFeat];
+        acc = mfma_f32(sGH[an >> 4][an & 15][j0 + r16], bv, acc);
+      }
+      if (col < kIn) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = j0 + 4 * k4 + i;
+          if (acc[i] != 0.f) atomicAdd(a.g_w1 + ((size_t)g * kHidden + j) * kIn + col, acc[i]);
+        }
       }
     }
   }
-  if (a.g_w1 || a.g_b1) {
-    for (int q = t; q < kHidden * (kIn + 1); q += 256) {
-      const int j = q / (kIn + 1), k = q % (kIn + 1);
-      float s = 0.f;
-      for (int w = 0; w < 4; ++w) {
-        for (int al = 0; al < 16; ++al) {
-          const int ai = a0 + 16 * w + al;
-          if (ai >= a.goff[g + 1]) break;
-          float x;
-          if (k < kFeat) x = bf2f(a.feat[(size_t)ai * kFeat + k]);
-          else if (k < kIn) x = sD[w][al][k - kFeat];
-          else x = 1.f;
-          s += sGH[w][al][j] * x;
-        }
-      }
-      if (k < kIn) {
-        if (a.g_w1 && s != 0.f) atomicAdd(a.g_w1 + ((size_t)g * kHidden + j) * kIn + k, s);
-      } else if (a.g_b1 && s != 0.f) {
-        atomicAdd(a.g_b1 + (size_t)g * kHidden + j, s);
-      }
-    }
+  if (a.g_b2 && t < KJ) {
+    float s = 0.f;
+    for (int an = 0; an < 64; ++an) s += sY[an >> 4][an & 15][t];
+    if (s != 0.f) atomicAdd(a.g_b2 + (size_t)g * KJ + t, s);
+  }
+  if (a.g_b1 && t >= 192 && t < 192 + kHidden) {
+    float s = 0.f;
+    for (int an = 0; an < 64; ++an) s += sGH[an >> 4][an & 15][t - 192];
+    if (s != 0.f) atomicAdd(a.g_b1 + (size_t)g * kHidden + (t - 192), s);
   }
 }
 

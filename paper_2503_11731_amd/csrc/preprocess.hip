@@ -91,6 +91,9 @@ __device__ inline void load_surfel(const PrepArgs& a, int i, float* P, float& m0
   sv = a.scale[N + i];
 }
 
+// DEG: SH degree of the colour (-1: plain RGB), fixed per instantiation so
+// that the coefficient loads unroll and issue together, ahead of the FP64 frame.
+template <int DEG>
 __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.n) return;
@@ -107,6 +110,17 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   a.ws.visible[i] = b.vis ? 1u : 0u;
   if (!b.touch) return;
   a.ws.rect[i] = make_int4(b.tx_lo, b.tx_hi, b.ty_lo, b.ty_hi);
+  constexpr int nb = DEG >= 0 ? (DEG + 1) * (DEG + 1) : 1;
+  float co[3][nb];
+  if constexpr (DEG >= 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < nb; ++k) co[c][k] = a.sh[(size_t)(k * 3 + c) * N + i];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) co[c][0] = a.rgb[(size_t)c * N + i];
+  }
   const float nsign = spec_normal_sign(f);
 
   Frame64 F;
@@ -121,24 +135,25 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
 
   // colour
   float col[3];
-  if (a.sh_degree >= 0) {
+  if constexpr (DEG >= 0) {
     // view direction in the group frame: R^T mu_s
     double dx = F.R[0] * F.mus[0] + F.R[3] * F.mus[1] + F.R[6] * F.mus[2];
     double dy = F.R[1] * F.mus[0] + F.R[4] * F.mus[1] + F.R[7] * F.mus[2];
     double dz = F.R[2] * F.mus[0] + F.R[5] * F.mus[1] + F.R[8] * F.mus[2];
     double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
     float Y[16];
-    sh_eval(a.sh_degree, (float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
-    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    sh_eval(DEG, (float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       float acc = 0.5f;
-      for (int k = 0; k < nb; ++k) acc += a.sh[(size_t)(k * 3 + c) * N + i] * Y[k];
+#pragma unroll
+      for (int k = 0; k < nb; ++k) acc += co[c][k] * Y[k];
       col[c] = acc > 0.0f ? acc : 0.0f;
     }
   } else {
-    col[0] = a.rgb[i];
-    col[1] = a.rgb[N + i];
-    col[2] = a.rgb[2 * N + i];
+    col[0] = co[0][0];
+    col[1] = co[1][0];
+    col[2] = co[2][0];
   }
   const float o = a.opacity[i];
   const float log2o = log2f(o);
@@ -241,9 +256,15 @@ void launch_compose_poses(const float* sensor_pose, const float* group_poses, in
 void launch_prep(const PrepArgs& a, hipStream_t st) {
   if (a.n == 0) return;
   dim3 grid((a.n + 255) / 256);
-  if (a.S.kind == GS_SENSOR_PINHOLE)
-    hipLaunchKernelGGL(k_prep_pinhole, grid, dim3(256), 0, st, a);
-  else
+  if (a.S.kind == GS_SENSOR_PINHOLE) {
+    switch (a.sh_degree) {
+      case 0: hipLaunchKernelGGL(k_prep_pinhole<0>, grid, dim3(256), 0, st, a); break;
+      case 1: hipLaunchKernelGGL(k_prep_pinhole<1>, grid, dim3(256), 0, st, a); break;
+      case 2: hipLaunchKernelGGL(k_prep_pinhole<2>, grid, dim3(256), 0, st, a); break;
+      case 3: hipLaunchKernelGGL(k_prep_pinhole<3>, grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL(k_prep_pinhole<-1>, grid, dim3(256), 0, st, a); break;
+    }
+  } else
     hipLaunchKernelGGL(k_prep_lidar, grid, dim3(256), 0, st, a);
 }
 

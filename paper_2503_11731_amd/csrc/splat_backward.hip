@@ -29,10 +29,12 @@ __device__ inline void acc_cross(const double* a, const double* b, double* acc) 
 }
 __device__ inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-// One instantiation per sensor kind: the two chain rules share little, and
-// one kernel holding both needs twice the registers.
-template <int KIND>
-__global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
+// One instantiation per sensor kind and SH degree (-1: plain colour or
+// intensity): the two chain rules share little, one kernel holding both needs
+// twice the registers, and a fixed degree keeps the coefficient loop unrolled
+// so that each surfel's SH loads and read-modify-writes issue together.
+template <int KIND, int DEG>
+__global__ __launch_bounds__(256, 3) void k_splat_backward(SplatBwdArgs A) {
   const PrepArgs& a = A.p;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.n) return;
@@ -192,79 +194,123 @@ __global__ __launch_bounds__(256) void k_splat_backward(SplatBwdArgs A) {
     gmu[c] = R[c] * gmus[0] + R[3 + c] * gmus[1] + R[6 + c] * gmus[2];
   }
 
-  // colour from SH: view direction v = R^T mu_s (group frame), colour = max(0, sum c Y + 1/2)
-  if (KIND == GS_SENSOR_PINHOLE && a.sh_degree >= 0) {
-    double v[3];
-    for (int c = 0; c < 3; ++c) v[c] = R[c] * mus[0] + R[3 + c] * mus[1] + R[6 + c] * mus[2];
-    const double vn = sqrt(dot3(v, v));
-    const float dxf = (float)(v[0] / vn), dyf = (float)(v[1] / vn), dzf = (float)(v[2] / vn);
-    float Y[16];
-    sh_eval(a.sh_degree, dxf, dyf, dzf, Y);
-    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
-    float gY[16];
-    for (int k = 0; k < 16; ++k) gY[k] = 0.0f;
-    for (int c = 0; c < 3; ++c) {
-      if (gcol[c] == 0.0) continue;
-      float raw = 0.5f;
-      for (int k = 0; k < nb; ++k) raw += a.sh[(size_t)(k * 3 + c) * N + i] * Y[k];
-      if (!(raw > 0.0f)) continue;
-      for (int k = 0; k < nb; ++k) {
-        if (A.g_sh) A.g_sh[(size_t)(k * 3 + c) * N + i] += (float)(gcol[c] * Y[k]);
-        gY[k] += (float)gcol[c] * a.sh[(size_t)(k * 3 + c) * N + i];
-      }
+  // quaternion: Rq = I + s B(q), s = 2/|q|^2; G = dL/dRq with columns gtu, gtv, gn
+  {
+    const double G[9] = {gtu[0], gtv[0], gn[0], gtu[1], gtv[1], gn[1], gtu[2], gtv[2], gn[2]};
+    double GB = 0.0;
+    for (int k = 0; k < 9; ++k) GB += G[k] * B[k];
+    const double gw = s * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    const double gx =
+        s * (y * G[1] + z * G[2] + y * G[3] - 2 * x * G[4] - w * G[5] + z * G[6] + w * G[7] - 2 * x * G[8]);
+    const double gy =
+        s * (-2 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] - 2 * y * G[8]);
+    const double gz =
+        s * (-2 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2 * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
+    const double ds = -s * s * GB;  // d s / d q_k = -s^2 q_k
+    if (A.g_quat) {
+      float* q = A.g_quat + i;
+      const float o0 = q[0], o1 = q[N], o2 = q[2 * N], o3 = q[3 * N];
+      q[0] = o0 + (float)(gw + ds * w);
+      q[N] = o1 + (float)(gx + ds * x);
+      q[2 * N] = o2 + (float)(gy + ds * y);
+      q[3 * N] = o3 + (float)(gz + ds * z);
     }
-    float gxf, gyf, gzf;
-    sh_grad(a.sh_degree, dxf, dyf, dzf, gY, gxf, gyf, gzf);
-    const double gd[3] = {gxf, gyf, gzf};
-    const double dd[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
-    const double pr = dot3(dd, gd);
-    // v = mu - c_group, so dL/dmu gains the projected direction gradient
-    for (int c = 0; c < 3; ++c) gmu[c] += (gd[c] - dd[c] * pr) / vn;
-  } else if (KIND == GS_SENSOR_PINHOLE) {
+  }
+  if (A.g_scale) {
+    const float o0 = A.g_scale[i], o1 = A.g_scale[N + i];
+    A.g_scale[i] = o0 + (float)gsu;
+    A.g_scale[N + i] = o1 + (float)gsv;
+  }
+  if (A.g_opacity) A.g_opacity[i] += (float)g_op;
+
+  // colour from SH: view direction v = R^T mu_s (group frame), colour = max(0, sum c Y + 1/2)
+  if constexpr (KIND == GS_SENSOR_PINHOLE && DEG >= 0) {
+    constexpr int nb = (DEG + 1) * (DEG + 1);
+    if (gcol[0] != 0.0 || gcol[1] != 0.0 || gcol[2] != 0.0) {
+      double v[3];
+      for (int c = 0; c < 3; ++c) v[c] = R[c] * mus[0] + R[3 + c] * mus[1] + R[6 + c] * mus[2];
+      const double vn = sqrt(dot3(v, v));
+      const float dxf = (float)(v[0] / vn), dyf = (float)(v[1] / vn), dzf = (float)(v[2] / vn);
+      float Y[16];
+      sh_eval(DEG, dxf, dyf, dzf, Y);
+      // every coefficient and every accumulator of the surfel, loaded before any store
+      float co[3][nb], old[3][nb];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < nb; ++k) co[c][k] = a.sh[(size_t)(k * 3 + c) * N + i];
+      if (A.g_sh) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < nb; ++k) old[c][k] = A.g_sh[(size_t)(k * 3 + c) * N + i];
+      }
+      float gY[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) gY[k] = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (gcol[c] == 0.0) continue;
+        float raw = 0.5f;
+#pragma unroll
+        for (int k = 0; k < nb; ++k) raw += co[c][k] * Y[k];
+        if (!(raw > 0.0f)) continue;
+#pragma unroll
+        for (int k = 0; k < nb; ++k) {
+          if (A.g_sh) A.g_sh[(size_t)(k * 3 + c) * N + i] = old[c][k] + (float)(gcol[c] * Y[k]);
+          gY[k] += (float)gcol[c] * co[c][k];
+        }
+      }
+      float gxf, gyf, gzf;
+      sh_grad(DEG, dxf, dyf, dzf, gY, gxf, gyf, gzf);
+      const double gd[3] = {gxf, gyf, gzf};
+      const double dd[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+      const double pr = dot3(dd, gd);
+      // v = mu - c_group, so dL/dmu gains the projected direction gradient
+      for (int c = 0; c < 3; ++c) gmu[c] += (gd[c] - dd[c] * pr) / vn;
+    }
+  } else if constexpr (KIND == GS_SENSOR_PINHOLE) {
     if (A.g_rgb) {
-      A.g_rgb[i] += (float)gcol[0];
-      A.g_rgb[N + i] += (float)gcol[1];
-      A.g_rgb[2 * N + i] += (float)gcol[2];
+      const float o0 = A.g_rgb[i], o1 = A.g_rgb[N + i], o2 = A.g_rgb[2 * N + i];
+      A.g_rgb[i] = o0 + (float)gcol[0];
+      A.g_rgb[N + i] = o1 + (float)gcol[1];
+      A.g_rgb[2 * N + i] = o2 + (float)gcol[2];
     }
   } else if (A.g_intensity) {
     A.g_intensity[i] += (float)g_int;
   }
 
-  // quaternion: Rq = I + s B(q), s = 2/|q|^2; G = dL/dRq with columns gtu, gtv, gn
-  const double G[9] = {gtu[0], gtv[0], gn[0], gtu[1], gtv[1], gn[1], gtu[2], gtv[2], gn[2]};
-  double GB = 0.0;
-  for (int k = 0; k < 9; ++k) GB += G[k] * B[k];
-  const double gw = s * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
-  const double gx = s * (y * G[1] + z * G[2] + y * G[3] - 2 * x * G[4] - w * G[5] + z * G[6] + w * G[7] - 2 * x * G[8]);
-  const double gy = s * (-2 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] - 2 * y * G[8]);
-  const double gz = s * (-2 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2 * z * G[4] + y * G[5] + x * G[6] + y * G[7]);
-  const double ds = -s * s * GB;  // d s / d q_k = -s^2 q_k
-  if (A.g_quat) {
-    A.g_quat[i] += (float)(gw + ds * w);
-    A.g_quat[N + i] += (float)(gx + ds * x);
-    A.g_quat[2 * N + i] += (float)(gy + ds * y);
-    A.g_quat[3 * N + i] += (float)(gz + ds * z);
-  }
   if (A.g_mean) {
-    A.g_mean[i] += (float)gmu[0];
-    A.g_mean[N + i] += (float)gmu[1];
-    A.g_mean[2 * N + i] += (float)gmu[2];
+    const float o0 = A.g_mean[i], o1 = A.g_mean[N + i], o2 = A.g_mean[2 * N + i];
+    A.g_mean[i] = o0 + (float)gmu[0];
+    A.g_mean[N + i] = o1 + (float)gmu[1];
+    A.g_mean[2 * N + i] = o2 + (float)gmu[2];
   }
-  if (A.g_scale) {
-    A.g_scale[i] += (float)gsu;
-    A.g_scale[N + i] += (float)gsv;
-  }
-  if (A.g_opacity) A.g_opacity[i] += (float)g_op;
 }
 
 }  // namespace
 
+template <int KIND>
+void launch_kind(const SplatBwdArgs& a, hipStream_t st) {
+  const dim3 grid((a.p.n + 255) / 256), block(256);
+  if constexpr (KIND == GS_SENSOR_PINHOLE) {
+    switch (a.p.sh_degree) {
+      case 0: hipLaunchKernelGGL((k_splat_backward<KIND, 0>), grid, block, 0, st, a); return;
+      case 1: hipLaunchKernelGGL((k_splat_backward<KIND, 1>), grid, block, 0, st, a); return;
+      case 2: hipLaunchKernelGGL((k_splat_backward<KIND, 2>), grid, block, 0, st, a); return;
+      case 3: hipLaunchKernelGGL((k_splat_backward<KIND, 3>), grid, block, 0, st, a); return;
+      default: break;
+    }
+  }
+  hipLaunchKernelGGL((k_splat_backward<KIND, -1>), grid, block, 0, st, a);
+}
+
 void launch_splat_backward(const SplatBwdArgs& a, hipStream_t st) {
   if (a.p.n == 0) return;
   if (a.p.S.kind == GS_SENSOR_PINHOLE)
-    hipLaunchKernelGGL(k_splat_backward<GS_SENSOR_PINHOLE>, dim3((a.p.n + 255) / 256), dim3(256), 0, st, a);
+    launch_kind<GS_SENSOR_PINHOLE>(a, st);
   else
-    hipLaunchKernelGGL(k_splat_backward<GS_SENSOR_LIDAR>, dim3((a.p.n + 255) / 256), dim3(256), 0, st, a);
+    launch_kind<GS_SENSOR_LIDAR>(a, st);
 }
 
 }  // namespace gs
