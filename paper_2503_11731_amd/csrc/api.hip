@@ -342,7 +342,7 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
                   hipStream_t st) {
   SensorWS w = record_ws(R, workspace, rbase, 0);
   hipEvent_t ev = stage_begin(p, st);
-  const int kb = radix_sort(w.key, w.val, nullptr, R.n_rec, R.n_rec, 32, w.hist, st);
+  const int kb = radix_sort(w.key, w.val, nullptr, R.n_rec, R.n_rec, 32, w.hist, w.status + kStSortStall, st);
   stage_end(p, st, GS_STAGE_DEPTH_SORT, ev);
   ev = stage_begin(p, st);
   launch_pair_offsets(w.val[kb], w.ntiles, (int)R.n_rec, w.offs, w.bsum, w.status, R.cap, st);
@@ -350,7 +350,7 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
               w.pval[0], st);
   stage_end(p, st, GS_STAGE_EMIT, ev);
   ev = stage_begin(p, st);
-  (void)radix_sort(w.ptile, w.pval, w.status + kStPairs, 0, R.cap, R.tile_bits, w.hist, st);
+  (void)radix_sort(w.ptile, w.pval, w.status + kStPairs, 0, R.cap, R.tile_bits, w.hist, w.status + kStSortStall, st);
   stage_end(p, st, GS_STAGE_TILE_SORT, ev);
   ev = stage_begin(p, st);
   launch_ranges(w.ptile[R.pair_buf], w.status + kStPairs, R.cap, w.ranges, R.n_tiles, st);
@@ -382,7 +382,8 @@ void build_queue(gs_plan* p, RecordArrays& R, size_t rbase, void* workspace, hip
   launch_build_items(a, st);
   uint32_t* qk[2] = {reinterpret_cast<uint32_t*>(b + R.o_qkey0), reinterpret_cast<uint32_t*>(b + R.o_qkey1)};
   uint32_t* qv[2] = {reinterpret_cast<uint32_t*>(b + R.o_qval0), reinterpret_cast<uint32_t*>(b + R.o_qval1)};
-  (void)radix_sort(qk, qv, a.hdr, 0, R.cap_items, R.key_bits, reinterpret_cast<uint32_t*>(b + R.o_hist), st);
+  (void)radix_sort(qk, qv, a.hdr, 0, R.cap_items, R.key_bits, reinterpret_cast<uint32_t*>(b + R.o_hist),
+                   a.status + kStSortStall, st);
 }
 
 // Queue view over sensors [s0, s1) sharing record space R at byte rbase;
@@ -570,6 +571,10 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
       gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "scene " + std::to_string(i) + ": bad shape");
     }
+    if ((uint32_t)d.n_splats > kMaxSortKeys) {
+      gs_plan_destroy(p);
+      return fail(GS_ERR_UNSUPPORTED, "scene " + std::to_string(i) + ": more than 2^30 - 1 surfels");
+    }
     sp.offsets.assign(d.group_offsets, d.group_offsets + d.n_groups + 1);
     bool okoff = sp.offsets[0] == 0 && sp.offsets[d.n_groups] == d.n_splats;
     for (int g = 0; g < d.n_groups; ++g) okoff = okoff && sp.offsets[g] <= sp.offsets[g + 1];
@@ -671,7 +676,7 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     K.n_ty = (K.H + K.th - 1) / K.th;
     s.n_tiles = K.n_tx * K.n_ty;
     int64_t cap = desc->pair_capacity > 0 ? desc->pair_capacity : 16ll * N + 4096;
-    if (cap > 0x7FFFFFFEll) cap = 0x7FFFFFFEll;
+    if (cap > kMaxSortKeys) cap = kMaxSortKeys;
     // per-sensor region
     Layout R;
     const size_t HW = (size_t)K.W * K.H;
@@ -698,11 +703,11 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     p->sensors.push_back(s);
   }
   if (p->batched) {
-    if (total_rec > 0x7FFFFFFFull) {
+    if (total_rec > (uint64_t)kMaxSortKeys) {
       gs_plan_destroy(p);
-      return fail(GS_ERR_UNSUPPORTED, "batched plan exceeds 2^31 surfel records");
+      return fail(GS_ERR_UNSUPPORTED, "batched plan exceeds 2^30 - 1 surfel records");
     }
-    if (total_cap > 0x7FFFFFFEull) total_cap = 0x7FFFFFFEull;
+    if (total_cap > (uint64_t)kMaxSortKeys) total_cap = kMaxSortKeys;
     p->tile_off[desc->n_sensors] = total_tiles;
     Layout R;
     p->G.layout(R, (uint32_t)total_rec, (uint32_t)total_cap, total_tiles, 256, seg_len);
@@ -876,13 +881,14 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   if (!p || !workspace || !out) return fail(GS_ERR_INVALID_ARG, "null argument to gs_query_status");
   GS_HIP_TRY(hipStreamSynchronize(st));
   memset(out, 0, sizeof(*out));
-  bool over = false, stalled = false;
+  bool over = false, stalled = false, sort_stall = false;
   auto read = [&](size_t off, uint32_t* w) {
     return hipMemcpy(w, static_cast<const char*>(workspace) + off, kStWords * 4, hipMemcpyDeviceToHost);
   };
   // pair counts: the base words plus the per-XCD replicas
   auto u64at = [](const uint32_t* w, int i) { return (int64_t)w[i] | ((int64_t)w[i + 1] << 32); };
   auto add_counts = [&](const uint32_t* w) {
+    sort_stall = sort_stall || w[kStSortStall] != 0;
     out->fp64_pairs += w[kStFp64];
     out->evaluated += u64at(w, kStEvals);
     out->composited += u64at(w, kStContrib);
@@ -930,6 +936,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   out->overflow = over ? 1 : 0;
   if (over) return fail(GS_ERR_CAPACITY, "pair capacity exceeded; re-plan with a larger pair_capacity");
   if (stalled) return fail(GS_ERR_HIP, "compositing work queue stalled (walk list inconsistent)");
+  if (sort_stall) return fail(GS_ERR_HIP, "radix sort look-back wait gave up (block statuses inconsistent)");
   return ok();
 }
 

@@ -20,6 +20,8 @@ constexpr int kRec64 = 4;       // doubles per surfel record (camera: pc; LiDAR:
 constexpr int kGrz = 10;        // doubles per grazing record
 constexpr int kGradFields = 16; // per-surfel gradient accumulators
 constexpr int kRadixItems = 4096;
+// keys per radix sort (pairs, records): the look-back counts are 30-bit
+constexpr uint32_t kMaxSortKeys = (1u << 30) - 1u;
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
 
 // record flags (stored as integer bits in float slot 14)
@@ -76,7 +78,15 @@ struct SensorWS {
 };
 
 // status word indices
-enum { kStPairs = 0, kStOverflow = 1, kStVisible = 2, kStFp64 = 3, kStEvals = 4 /* u64 */, kStContrib = 6 /* u64 */ };
+enum {
+  kStPairs = 0,
+  kStOverflow = 1,
+  kStVisible = 2,
+  kStFp64 = 3,
+  kStEvals = 4 /* u64 */,
+  kStContrib = 6 /* u64 */,
+  kStSortStall = 8 /* a radix look-back wait gave up */
+};
 // The compositing kernel adds its pair counts to one of 8 replicas (one per
 // XCD) of the three counters, words kStRep + 8 x: [0..1] evaluated (u64),
 // [2..3] composited (u64), [4] FP64 re-solves; the host sums them.  Atomics

@@ -109,7 +109,7 @@ void launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 // items.  Ping-pongs between buffers 0 and 1; returns the buffer holding the
 // result.
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32_t count_const, uint32_t cap,
-               int bits, uint32_t* hist, hipStream_t st);
+               int bits, uint32_t* hist, uint32_t* err, hipStream_t st);
 size_t radix_hist_words(uint32_t cap);
 // offs[j] = exclusive scan of ntiles[val[j]]; total -> status[kStPairs] and offs[n]
 void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uint32_t* offs, uint32_t* bsum,

@@ -8,11 +8,17 @@
 // and a stable sort on the tile id alone (ceil(log2 tiles) bits) yields
 // exactly the order of a stable sort of (tile << 32 | depth) keys.
 //
-// Radix passes use 8-bit digits over 4096-item blocks: per-block digit
-// histograms, one device-wide exclusive scan, then a stable scatter whose
-// in-block ranks come from wavefront ballots (match mask of equal digits)
-// and whose writes are staged through LDS so that each block writes
-// contiguous runs per digit.
+// Radix passes use 8-bit digits over blocks of kRadixItems keys.  One histogram kernel
+// counts every digit of every pass over all keys (totals do not depend on the
+// key order); each pass is then one scatter launch whose blocks take
+// sequential tickets, rank their keys with wavefront ballots (match mask of
+// equal digits), publish their digit counts and obtain the counts of all
+// earlier blocks by a decoupled look-back over per-block status words, then
+// write their keys through LDS in contiguous runs per digit.  A block only
+// waits on blocks holding smaller tickets, which are already running, and
+// every wait is bounded (a give-up raises a status flag instead of hanging).
+#include <cstring>
+
 #include "gs_internal.h"
 #include "kernels.h"
 
@@ -57,9 +63,13 @@ struct RadixArgs {
   const uint32_t* count;
   uint32_t count_const;
   uint32_t cap;
-  int shift;
-  uint32_t* hist;   // [256][nb] digit counts, digit-major; scanned in place
-  uint32_t* hbsum;  // block sums of the digit-count scan
+  int shift;            // first bit of this pass's digit
+  int passes;           // histogram kernel: digits counted per key
+  uint32_t* gcount;     // [pass][256] digit totals over all keys
+  uint32_t* ticket;     // this pass's block ticket counter
+  uint32_t* look;       // [block][256] status words of this pass
+  uint32_t* look_next;  // the same for the next pass, cleared here
+  uint32_t* err;        // set to 1 when a look-back wait gives up
 };
 
 __device__ inline uint32_t radix_n(const RadixArgs& a) {
@@ -67,96 +77,46 @@ __device__ inline uint32_t radix_n(const RadixArgs& a) {
   return n < a.cap ? n : a.cap;
 }
 
-__global__ __launch_bounds__(256) void k_rs_hist(RadixArgs a) {
+// status word: bits 31/30 = inclusive prefix / block aggregate available, the
+// low 30 bits the count (keys per sort < 2^30)
+constexpr uint32_t kLookInc = 1u << 31;
+constexpr uint32_t kLookAgg = 1u << 30;
+constexpr uint32_t kLookVal = kLookAgg - 1u;
+constexpr uint32_t kLookSpins = 1u << 20;
+constexpr int kLookWin = 16;  // earlier blocks read per look-back round trip
+
+__device__ inline uint32_t ld_agent(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Digit totals of every pass, one read of the keys.  Few, wide blocks: the
+// per-block totals meet in one global add per (pass, digit), and those adds
+// to the same word serialise, so their number is kept to the grid size.
+__global__ __launch_bounds__(1024) void k_rs_ghist(RadixArgs a) {
   const uint32_t n = radix_n(a);
-  const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
   __shared__ uint32_t h[4][256];
-  const int t = threadIdx.x, w = t >> 6;
-  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) h[k][t] = 0;
-    __syncthreads();
-    const uint32_t base = b * kRadixItems;
-#pragma unroll 4
-    for (int r = 0; r < kRadixItems / 256; ++r) {
-      uint32_t idx = base + r * 256 + t;
-      if (idx < n) atomicAdd(&h[w][(a.kin[idx] >> a.shift) & 255u], 1u);
-    }
-    __syncthreads();
-    a.hist[(size_t)t * nb + b] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
-    __syncthreads();
+  const int t = threadIdx.x;
+  (&h[0][0])[t] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * 1024 + t; i < n; i += gridDim.x * 1024) {
+    const uint32_t k = a.kin[i];
+    for (int p = 0; p < a.passes; ++p) atomicAdd(&h[p][(k >> (a.shift + 8 * p)) & 255u], 1u);
   }
+  __syncthreads();
+  const int p = t >> 8;
+  const uint32_t c = (&h[0][0])[t];
+  if (p < a.passes && c != 0u) atomicAdd(&a.gcount[t], c);
 }
 
-// Exclusive scan of the 256 * nb digit counts (digit-major, so that every
-// block's digits land after all smaller digits of all blocks): coalesced
-// block reductions, one small top-level scan, then an in-order down-sweep.
-constexpr int kHScanItems = 4096;
-
-__global__ __launch_bounds__(256) void k_rs_hscan_reduce(RadixArgs a) {
-  __shared__ uint32_t s_w[4];
-  const uint32_t n = radix_n(a);
-  const uint32_t E = 256u * ((n + kRadixItems - 1) / kRadixItems);
-  const uint32_t base = blockIdx.x * kHScanItems;
-  uint32_t s = 0;
-  if (base < E) {
-#pragma unroll 4
-    for (int r = 0; r < kHScanItems / 256; ++r) {
-      const uint32_t i = base + r * 256 + threadIdx.x;
-      if (i < E) s += a.hist[i];
-    }
-  }
-  uint32_t tot;
-  block_excl_scan<256>(s, s_w, &tot);
-  if (threadIdx.x == 0) a.hbsum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(1024) void k_rs_hscan_top(RadixArgs a, int nblk) {
-  __shared__ uint32_t s_w[16];
-  const int per = (nblk + 1023) / 1024;
-  const int beg = threadIdx.x * per;
-  const int end = min(beg + per, nblk);
-  uint32_t sum = 0;
-  for (int i = beg; i < end; ++i) sum += a.hbsum[i];
-  uint32_t tot;
-  uint32_t off = block_excl_scan<1024>(sum, s_w, &tot);
-  for (int i = beg; i < end; ++i) {
-    const uint32_t x = a.hbsum[i];
-    a.hbsum[i] = off;
-    off += x;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_rs_hscan_down(RadixArgs a) {
-  __shared__ uint32_t s_w[4];
-  const uint32_t n = radix_n(a);
-  const uint32_t E = 256u * ((n + kRadixItems - 1) / kRadixItems);
-  const uint32_t base = blockIdx.x * kHScanItems;
-  if (base >= E) return;
-  constexpr int PER = kHScanItems / 256;
-  const uint32_t i0 = base + threadIdx.x * PER;
-  uint32_t v[PER];
-  uint32_t s = 0;
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    v[r] = i0 + r < E ? a.hist[i0 + r] : 0u;
-    s += v[r];
-  }
-  uint32_t tot;
-  uint32_t off = block_excl_scan<256>(s, s_w, &tot) + a.hbsum[blockIdx.x];
-#pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    if (i0 + r < E) a.hist[i0 + r] = off;
-    off += v[r];
-  }
-}
-
-// Stable scatter of one block of kRadixItems keys.  Each wave ranks its own
-// contiguous quarter of the block independently (match masks from 8 ballots
-// per 64 keys, per-wave digit counters in LDS that only that wave touches),
-// so the block meets only four barriers; the block's keys are then grouped
-// by digit in LDS and written out in order, contiguous runs per digit.
-__global__ __launch_bounds__(256) void k_rs_scatter(RadixArgs a) {
+// One pass: stable scatter of kRadixItems-key blocks in ticket order.  Each wave
+// ranks its own contiguous quarter of the block (match masks from 8 ballots
+// per 64 keys, per-wave digit counters in LDS that only that wave touches);
+// the block then publishes its digit counts, looks back for the counts of all
+// earlier blocks, groups its keys by digit in LDS and writes them out in order.
+__global__ __launch_bounds__(256) void k_rs_onesweep(RadixArgs a) {
   const uint32_t n = radix_n(a);
   const uint32_t nb = (n + kRadixItems - 1) / kRadixItems;
   __shared__ uint32_t s_key[kRadixItems];
@@ -164,14 +124,24 @@ __global__ __launch_bounds__(256) void k_rs_scatter(RadixArgs a) {
   __shared__ uint32_t s_wcnt[4][256];
   __shared__ uint32_t s_start[256];
   __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_gstart[256];
   __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_ticket;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const uint64_t lt = lanemask_lt();
   constexpr int R = kRadixItems / 256;  // keys per lane
-  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+  {
+    uint32_t tot;
+    s_gstart[t] = block_excl_scan<256>(a.gcount[t], s_w, &tot);
+  }
+  for (;;) {
+    if (t == 0) s_ticket = atomicAdd(a.ticket, 1u);
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_wcnt[k][t] = 0;
     __syncthreads();
+    const uint32_t b = s_ticket;
+    if (b >= nb) break;
+    if (a.look_next) a.look_next[(size_t)b * 256 + t] = 0u;
     const uint32_t wbase = b * kRadixItems + (uint32_t)w * (kRadixItems / 4);
     uint32_t my_key[R], my_val[R], my_rank[R];
 #pragma unroll
@@ -201,14 +171,53 @@ __global__ __launch_bounds__(256) void k_rs_scatter(RadixArgs a) {
     }
     __syncthreads();
     const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t], c3 = s_wcnt[3][t];
+    const uint32_t cd = c0 + c1 + c2 + c3;
+    // digit t: publish this block's count, then add the counts of all
+    // earlier blocks (an inclusive prefix ends the walk)
+    uint32_t* mine = a.look + (size_t)b * 256 + t;
+    st_agent(mine, (b == 0 ? kLookInc : kLookAgg) | cd);
+    uint32_t excl = 0;
+    if (b > 0) {
+      // walk back kLookWin blocks per round trip, nearest first; a block that
+      // has published nothing yet stops the round and is read again
+      uint32_t spins = 0;
+      for (uint32_t k = b; k > 0;) {
+        uint32_t v[kLookWin];
+#pragma unroll
+        for (int j = 0; j < kLookWin; ++j) v[j] = (uint32_t)j < k ? ld_agent(a.look + (size_t)(k - 1 - j) * 256 + t) : kLookInc;
+        bool ended = false, inclusive = false;
+        uint32_t used = 0;
+#pragma unroll
+        for (int j = 0; j < kLookWin; ++j) {
+          if (ended || (v[j] & (kLookInc | kLookAgg)) == 0u) {
+            ended = true;
+          } else {
+            excl += v[j] & kLookVal;
+            ++used;
+            inclusive = (v[j] & kLookInc) != 0u;
+            ended = inclusive;
+          }
+        }
+        k -= used < k ? used : k;
+        if (inclusive) break;
+        if (used == 0) {
+          if (++spins > kLookSpins) {
+            if (a.err) atomicOr(a.err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      st_agent(mine, kLookInc | (excl + cd));
+    }
     uint32_t tot;
-    const uint32_t st = block_excl_scan<256>(c0 + c1 + c2 + c3, s_w, &tot);
+    const uint32_t st = block_excl_scan<256>(cd, s_w, &tot);
     s_start[t] = st;
     s_wcnt[0][t] = st;
     s_wcnt[1][t] = st + c0;
     s_wcnt[2][t] = st + c0 + c1;
     s_wcnt[3][t] = st + c0 + c1 + c2;
-    s_gbase[t] = a.hist[(size_t)t * nb + b];
+    s_gbase[t] = s_gstart[t] + excl;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -504,26 +513,42 @@ void launch_fill_f32(float* p, float v, size_t n, hipStream_t st) {
 }
 
 static size_t radix_nb(uint32_t cap) { return (cap + kRadixItems - 1) / kRadixItems; }
-static size_t radix_hscan_blocks(uint32_t cap) { return (256 * radix_nb(cap) + kHScanItems - 1) / kHScanItems; }
 
-size_t radix_hist_words(uint32_t cap) { return 256 * radix_nb(cap) + radix_hscan_blocks(cap) + 256; }
+// [4][256] digit totals | 16 tickets | two look-back areas of [blocks][256]
+size_t radix_hist_words(uint32_t cap) { return 4 * 256 + 16 + 2 * 256 * radix_nb(cap); }
 
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32_t count_const, uint32_t cap,
-               int bits, uint32_t* hist, hipStream_t st) {
+               int bits, uint32_t* hist, uint32_t* err, hipStream_t st) {
+  const int passes = (bits + 7) / 8;
+  if (passes <= 0) return 0;
+  const size_t nb_max = radix_nb(cap);
+  uint32_t* gcount = hist;
+  uint32_t* ticket = hist + 4 * 256;
+  uint32_t* area[2] = {ticket + 16, ticket + 16 + 256 * nb_max};
+  launch_fill_u32(hist, 0u, 4 * 256 + 16 + 256 * nb_max, st);
+  RadixArgs a;
+  memset(&a, 0, sizeof(a));
+  a.count = count;
+  a.count_const = count_const;
+  a.cap = cap;
+  a.err = err;
+  a.kin = key[0];
+  a.passes = passes;
+  a.gcount = gcount;
+  hipLaunchKernelGGL(k_rs_ghist, dim3(grid_for(cap, 1024 * 8, 256)), dim3(1024), 0, st, a);
+  const unsigned grid = nb_max < 1 ? 1u : (nb_max < 1024 ? (unsigned)nb_max : 1024u);
   int cur = 0;
-  const unsigned nb_max = (unsigned)radix_nb(cap);
-  const unsigned grid = nb_max < 1 ? 1 : (nb_max < 2048 ? nb_max : 2048);
-  const int nhb = (int)radix_hscan_blocks(cap);
-  uint32_t* hbsum = hist + 256 * (size_t)nb_max;
-  for (int shift = 0; shift < bits; shift += 8) {
-    RadixArgs a{key[cur], val[cur], key[cur ^ 1], val[cur ^ 1], count, count_const, cap, shift, hist, hbsum};
-    hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(256), 0, st, a);
-    if (nhb > 0) {
-      hipLaunchKernelGGL(k_rs_hscan_reduce, dim3(nhb), dim3(256), 0, st, a);
-      hipLaunchKernelGGL(k_rs_hscan_top, dim3(1), dim3(1024), 0, st, a, nhb);
-      hipLaunchKernelGGL(k_rs_hscan_down, dim3(nhb), dim3(256), 0, st, a);
-    }
-    hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(256), 0, st, a);
+  for (int p = 0; p < passes; ++p) {
+    a.kin = key[cur];
+    a.vin = val[cur];
+    a.kout = key[cur ^ 1];
+    a.vout = val[cur ^ 1];
+    a.shift = 8 * p;
+    a.gcount = gcount + 256 * p;
+    a.ticket = ticket + p;
+    a.look = area[p & 1];
+    a.look_next = p + 1 < passes ? area[(p + 1) & 1] : nullptr;
+    hipLaunchKernelGGL(k_rs_onesweep, dim3(grid), dim3(256), 0, st, a);
     cur ^= 1;
   }
   return cur;
