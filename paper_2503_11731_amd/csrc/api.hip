@@ -65,6 +65,7 @@ struct RecordArrays {
   size_t o_pslot = 0, o_arrive = 0, o_qhdr = 0, o_sbsum = 0, o_qkey0 = 0, o_qkey1 = 0, o_qval0 = 0, o_qval1 = 0,
          o_items = 0, o_part = 0, part_stride = 0, o_flag = 0, o_walk = 0, o_qcnt = 0;
   uint32_t n_rec = 0, cap = 0;
+  uint32_t status_words = kStWords;  // words cleared at the start of a frame
   uint32_t seg_len = 0, cap_items = 0, pslot_cap = 0;
   int n_tiles = 0, tile_bits = 0, rays = 256, key_bits = 16;
   int pair_buf = 0;   // buffer holding the sorted pairs
@@ -88,6 +89,10 @@ struct RecordArrays {
     pair_buf = ((tile_bits + 7) / 8) % 2;
     const size_t N = n;
     o_status = L.take(kStWords * 4);
+    // the pair-offset scan's ticket and look-back words sit right after the
+    // status words, so that the frame's one status fill clears them too
+    o_bsum = L.take(scan_bsum_words((int)N) * 4);
+    status_words = (uint32_t)((o_bsum - o_status) / 4 + scan_bsum_words((int)N));
     o_rec = L.take(N * 64);
     o_rec64 = L.take(N * 8 * kRec64);
     o_grz = L.take(N * 8 * kGrz);
@@ -99,7 +104,6 @@ struct RecordArrays {
     o_val0 = L.take(N * 4);
     o_val1 = L.take(N * 4);
     o_offs = L.take((N + 1) * 4);
-    o_bsum = L.take(scan_bsum_words((int)N) * 4);
     size_t hw = radix_hist_words(cap);
     const size_t hw2 = radix_hist_words(n);
     const size_t hw3 = radix_hist_words((uint32_t)tiles);
@@ -428,7 +432,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       const ScenePlan& sp = p->scenes[s.scene];
       SensorWS ws = sensor_ws(p, s, workspace);
       hipEvent_t ev = stage_begin(p, st);
-      launch_fill_u32(ws.status, 0u, kStWords, st);
+      launch_fill_u32(ws.status, 0u, s.R.status_words, st);
       launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
       launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
       launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, st);
@@ -447,7 +451,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   // batched step
   SensorWS g = record_ws(p->G, workspace, p->gbase, 0);
   hipEvent_t ev = stage_begin(p, st);
-  launch_fill_u32(g.status, 0u, kStWords, st);
+  launch_fill_u32(g.status, 0u, p->G.status_words, st);
   for (size_t si = 0; si < p->sensors.size(); ++si) {
     SensorPlan& s = p->sensors[si];
     const ScenePlan& sp = p->scenes[s.scene];
@@ -936,7 +940,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   out->overflow = over ? 1 : 0;
   if (over) return fail(GS_ERR_CAPACITY, "pair capacity exceeded; re-plan with a larger pair_capacity");
   if (stalled) return fail(GS_ERR_HIP, "compositing work queue stalled (walk list inconsistent)");
-  if (sort_stall) return fail(GS_ERR_HIP, "radix sort look-back wait gave up (block statuses inconsistent)");
+  if (sort_stall) return fail(GS_ERR_HIP, "sort or scan look-back wait gave up (block statuses inconsistent)");
   return ok();
 }
 

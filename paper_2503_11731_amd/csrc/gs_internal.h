@@ -85,7 +85,7 @@ enum {
   kStFp64 = 3,
   kStEvals = 4 /* u64 */,
   kStContrib = 6 /* u64 */,
-  kStSortStall = 8 /* a radix look-back wait gave up */
+  kStSortStall = 8 /* a sort or scan look-back wait gave up */
 };
 // The compositing kernel adds its pair counts to one of 8 replicas (one per
 // XCD) of the three counters, words kStRep + 8 x: [0..1] evaluated (u64),

@@ -242,67 +242,110 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(RadixArgs a) {
 }
 
 // ---------------- gathered exclusive scan of tile counts ----------------
+//
+// offs[j] = sum of ntiles[val[i]] over i < j, in one pass: 4096-item blocks in
+// ticket order, each publishing its sum and reading the sums of earlier
+// blocks by the same bounded look-back as the radix passes, with 64-bit
+// status words (high half: 1 = block sum, 2 = inclusive prefix; low half the
+// value).  The ticket and status words are cleared with the frame's status.
 
 constexpr int kScanItems = 4096;
+constexpr uint64_t kScanAgg = 1ull << 32;
+constexpr uint64_t kScanInc = 2ull << 32;
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ val,
-                                                     const uint32_t* __restrict__ ntiles, int n,
-                                                     uint32_t* __restrict__ bsum) {
+__global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict__ val,
+                                                      const uint32_t* __restrict__ ntiles, int n, uint32_t* bsum,
+                                                      uint32_t* __restrict__ offs, uint32_t* status, uint32_t cap) {
   __shared__ uint32_t s_w[4];
-  const int base = blockIdx.x * kScanItems;
-  uint32_t s = 0;
-  for (int r = 0; r < kScanItems / 256; ++r) {
-    int j = base + r * 256 + threadIdx.x;
-    if (j < n) s += ntiles[val[j]];
+  __shared__ uint32_t s_ticket, s_excl;
+  const int t = threadIdx.x;
+  const int nblk = (n + kScanItems - 1) / kScanItems;
+  if (n == 0) {
+    if (blockIdx.x == 0 && t == 0) offs[0] = 0u;
+    return;
   }
-  uint32_t tot;
-  block_excl_scan<256>(s, s_w, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, int nblk, uint32_t* offs, int n,
-                                                   uint32_t* status, uint32_t cap) {
-  __shared__ uint32_t s_w[16];
-  const int per = (nblk + 1023) / 1024;
-  const int beg = threadIdx.x * per;
-  const int end = min(beg + per, nblk);
-  uint32_t sum = 0;
-  for (int i = beg; i < end; ++i) sum += bsum[i];
-  uint32_t tot;
-  uint32_t off = block_excl_scan<1024>(sum, s_w, &tot);
-  for (int i = beg; i < end; ++i) {
-    uint32_t x = bsum[i];
-    bsum[i] = off;
-    off += x;
-  }
-  if (threadIdx.x == 0) {
-    offs[n] = tot;
-    status[kStPairs] = tot;
-    if (tot > cap) status[kStOverflow] = 1u;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ val,
-                                                   const uint32_t* __restrict__ ntiles, int n,
-                                                   const uint32_t* __restrict__ bsum, uint32_t* __restrict__ offs) {
-  __shared__ uint32_t s_w[4];
-  const int base = blockIdx.x * kScanItems;
+  uint32_t* ticket = bsum;
+  uint64_t* look = reinterpret_cast<uint64_t*>(bsum + 2);
+  if (t == 0) s_ticket = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int b = (int)s_ticket;
+  if (b >= nblk) return;
   // each thread owns 16 consecutive items so that the scan is in order
   constexpr int PER = kScanItems / 256;
   uint32_t v[PER];
-  uint32_t s = 0;
-  const int j0 = base + threadIdx.x * PER;
+  uint32_t sum = 0;
+  const int j0 = b * kScanItems + t * PER;
+  if (j0 + PER <= n) {
+    // whole run in range: all index loads, then all gathers, in flight together
+    uint32_t idx[PER];
+    const uint4* vp = reinterpret_cast<const uint4*>(val + j0);
 #pragma unroll
-  for (int r = 0; r < PER; ++r) {
-    int j = j0 + r;
-    v[r] = j < n ? ntiles[val[j]] : 0u;
-    s += v[r];
+    for (int q = 0; q < PER / 4; ++q) {
+      const uint4 x = vp[q];
+      idx[4 * q] = x.x;
+      idx[4 * q + 1] = x.y;
+      idx[4 * q + 2] = x.z;
+      idx[4 * q + 3] = x.w;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = ntiles[idx[r]];
+  } else {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) v[r] = j0 + r < n ? ntiles[val[j0 + r]] : 0u;
   }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) sum += v[r];
   uint32_t tot;
-  uint32_t off = block_excl_scan<256>(s, s_w, &tot) + bsum[blockIdx.x];
+  uint32_t off = block_excl_scan<256>(sum, s_w, &tot);
+  if (t == 0) {
+    uint64_t* mine = look + b;
+    __hip_atomic_store(mine, (b == 0 ? kScanInc : kScanAgg) | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    if (b > 0) {
+      uint32_t spins = 0;
+      for (int k = b; k > 0;) {
+        uint64_t w[kLookWin];
+#pragma unroll
+        for (int q = 0; q < kLookWin; ++q)
+          w[q] = q < k ? __hip_atomic_load(look + (k - 1 - q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanInc;
+        bool ended = false, inclusive = false;
+        int used = 0;
+#pragma unroll
+        for (int q = 0; q < kLookWin; ++q) {
+          if (ended || (w[q] >> 32) == 0u) {
+            ended = true;
+          } else {
+            excl += (uint32_t)w[q];
+            ++used;
+            inclusive = (w[q] & kScanInc) != 0u;
+            ended = inclusive;
+          }
+        }
+        k -= used < k ? used : k;
+        if (inclusive) break;
+        if (used == 0) {
+          if (++spins > kLookSpins) {
+            atomicOr(&status[kStSortStall], 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __hip_atomic_store(mine, kScanInc | (uint32_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_excl = excl;
+    if (b == nblk - 1) {
+      const uint32_t total = excl + tot;
+      offs[n] = total;
+      status[kStPairs] = total;
+      if (total > cap) status[kStOverflow] = 1u;
+    }
+  }
+  __syncthreads();
+  off += s_excl;
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
-    int j = j0 + r;
+    const int j = j0 + r;
     if (j < n) offs[j] = off;
     off += v[r];
   }
@@ -554,14 +597,15 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32
   return cur;
 }
 
-size_t scan_bsum_words(int n) { return (size_t)((n + kScanItems - 1) / kScanItems) + 1; }
+// ticket (two words, keeping the status words 8-byte aligned) + one 64-bit
+// look-back status word per 4096-item block
+size_t scan_bsum_words(int n) { return 2 + 2 * (size_t)((n + kScanItems - 1) / kScanItems); }
 
 void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uint32_t* offs, uint32_t* bsum,
                          uint32_t* status, uint32_t cap, hipStream_t st) {
   const int nblk = (n + kScanItems - 1) / kScanItems;
-  if (nblk > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nblk), dim3(256), 0, st, val, ntiles, n, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, bsum, nblk, offs, n, status, cap);
-  if (nblk > 0) hipLaunchKernelGGL(k_scan_down, dim3(nblk), dim3(256), 0, st, val, ntiles, n, bsum, offs);
+  hipLaunchKernelGGL(k_pair_offsets, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, st, val, ntiles, n, bsum, offs, status,
+                     cap);
 }
 
 void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
