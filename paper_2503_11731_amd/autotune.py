@@ -24,7 +24,7 @@ import torch
 
 from .render import Renderer
 
-TILES_ANY = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (8, 32)]
+TILES_ANY = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (8, 32), (32, 16), (16, 32), (64, 8)]
 TILES_256 = [(16, 16), (32, 8), (8, 32)]
 SEGMENTS = [256, 512, 1024, 2048]
 
