@@ -180,6 +180,22 @@ def _grad_check(scene, sensor, opts, tile, keys, channels_seed=0, segment_pairs=
     return res
 
 
+@pytest.mark.parametrize("n", [4097, 32769, 50001])
+def test_sort_block_boundaries_pair_lists(n):
+    """Pair lists and ranges bit-exact when the radix passes span several
+    4096-key blocks chained by the look-back (4097 and 32769 surfels leave a
+    single key in the depth sort's last block; the pair lists span tens of
+    blocks with ragged ends)."""
+    _say(f"sort block boundaries n={n}")
+    sc = S.random_cloud(seed=5, n=n, lo=(-3, -3, 3), hi=(3, 3, 12), log_scale=(-3.4, 0.4))
+    scene = from_gen(sc)
+    cam = S.pinhole(320, 240, 200.0)
+    r, st, sp, gp, outs = gpu_render(scene, [cam], gs.PRODUCTION, tiles=(16, 16))
+    n_pairs = check_integer_parity(r, scene, cam, oracle_opts(gs.PRODUCTION, (16, 16)))
+    _say(f"  pairs {n_pairs}")
+    assert n_pairs > 4096
+
+
 @pytest.mark.parametrize("kind,seg", [("rgb", 0), ("sh", 0), ("rgb", 32)])
 def test_camera_backward_parity(kind, seg):
     _say(f"camera backward {kind} segment_pairs {seg}")
