@@ -84,7 +84,8 @@ typedef struct gs_sensor_desc {
   const double* elevations;  /* LiDAR: host array of `height` ascending angles (rad) */
   float z_near;              /* camera: min hit depth; LiDAR: min hit range          */
   int32_t scene;             /* index of the scene this sensor renders              */
-  int32_t tile_w, tile_h;    /* screen tile; 0 = default (32x8 for both kinds) */
+  int32_t tile_w, tile_h;    /* screen tile; 0 = default: 32x8, except 16x8 for a
+                                LiDAR sensor of a per-sensor (not batched) plan */
 } gs_sensor_desc;
 
 /* Compositing rules (front-to-back alpha blending with the 2DGS low-pass

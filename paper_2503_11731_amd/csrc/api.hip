@@ -639,7 +639,9 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
         gs_plan_destroy(p);
         return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": LiDAR scene needs intensity");
       }
-      K.tw = d.tile_w ? d.tile_w : 32;
+      // 16x8 by default: two waves per workgroup balance the sparse LiDAR
+      // lists best (measured); a batched plan needs 256-ray tiles
+      K.tw = d.tile_w ? d.tile_w : (desc->batched ? 32 : 16);
       K.th = d.tile_h ? d.tile_h : 8;
       const double two_pi = 2.0 * M_PI;
       K.inv_step = (float)((double)d.width / two_pi);

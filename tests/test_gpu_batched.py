@@ -66,7 +66,9 @@ def test_batched_forward_matches_per_sensor_and_oracle(tiles):
     _say(f"batched forward tiles={tiles}")
     scene, sensors = _rig()
     scenes, sp, gp = _tensors(scene, sensors)
-    ra = _renderer(scene, sensors, False, tiles)
+    # same tile shapes on both sides: the batched defaults (32x8 for every
+    # sensor) differ from the per-sensor LiDAR default (16x8)
+    ra = _renderer(scene, sensors, False, tiles or [(32, 8)] * len(sensors))
     rb = _renderer(scene, sensors, True, tiles)
     oa = ra.forward(scenes, sp, gp)
     ob = rb.forward(scenes, sp, gp)
@@ -98,7 +100,7 @@ def test_batched_backward_matches_per_sensor():
     _say("batched backward")
     scene, sensors = _rig()
     scenes, sp, gp = _tensors(scene, sensors)
-    ra = _renderer(scene, sensors, False)
+    ra = _renderer(scene, sensors, False, [(32, 8)] * len(sensors))  # the batched default tiles
     rb = _renderer(scene, sensors, True)
     rng = np.random.default_rng(1)
     res = []

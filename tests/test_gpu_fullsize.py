@@ -7,7 +7,8 @@ tiles are split into segments and merged).  Integer outputs (visibility,
 FP32 specification; float outputs on a sample the FP64 oracle computes ray by
 ray: every 24th row and column plus every ray of the two heaviest tiles.
 
-LiDAR range image: 128 x 1800, 200k anchors x 10 = 2M surfels.  Two claims,
+LiDAR range image: 128 x 1800, 200k anchors x 10 = 2M surfels, per-sensor plan
+with the default 16x8 LiDAR tiles.  Two claims,
 checked separately: (1) render parity: the oracle's FP64 decode, rounded to
 FP32, is rendered by both sides (pair list bit-exact; floats on every 32nd
 column of every 8th beam plus the heaviest tile, which is split into hundreds
@@ -121,7 +122,7 @@ def test_lidar_full_size_render_parity():
     torch.cuda.synchronize()
     status = r.status()
     assert not status["overflow"]
-    tw, th = 32, 8
+    tw, th = 16, 8  # the default tile of a LiDAR sensor in a per-sensor plan
     o = oracle_opts(gs.PRODUCTION, (tw, th))
     _say(f"  integer parity over {status['pairs'][0]} pairs")
     check_integer_parity(r, scene, lid, o)
