@@ -242,6 +242,30 @@ def bench_lidar(steps, warmup):
             "pairs": st["pairs"][0], "segments": st["segments"], "overflow": st["overflow"]}
 
 
+def bench_affinity(steps, warmup):
+    """Inpainting affinity (Eq. 6) at the three patch levels: row softmax of X_T X_S^T, bf16 MFMA."""
+    import numpy as np
+    import torch
+
+    import paper_2503_11731_amd as gs
+    from gen import patches as P
+    dev = torch.device("cuda:0")
+    res = {}
+    for side, b, n in ((8.0, 32, 1024), (4.0, 128, 256), (2.0, 512, 64)):
+        xt, xs = P.patch_pairs(seed=int(side), batch=b, p=n, q=n, side=side, d=64)
+        t = torch.from_numpy(xt.view(np.int16).copy()).to(dev)
+        s = torch.from_numpy(xs.view(np.int16).copy()).to(dev)
+        out = torch.empty((b, n, n), dtype=torch.float32, device=dev)
+        ms = _timed(lambda: gs.affinity(t, s, out=out), steps, warmup)
+        nbytes = 4 * b * n * n + 2 * b * 2 * n * 64
+        res[f"{int(side)}m"] = {"pairs": b, "anchors_per_patch": n, "d": 64, "ms": ms,
+                               "algorithmic_bytes": nbytes, "gbs": nbytes / (ms / 1e3) / 1e9,
+                               "hbm_frac": nbytes / (ms / 1e3) / (PEAK_HBM_GBS * 1e9)}
+    return {"workload": "inpainting patch affinity, softmax over source anchors of X_T X_S^T (Eq. 6), "
+                        "synthetic bf16 anchor rows (32 features + 16 positional-encoding terms, padded to 64)",
+            "levels": res}
+
+
 def bench_rig(steps, warmup):
     """Six cameras + LiDAR per step: batched graph path vs the plain per-sensor FP32 path."""
     import numpy as np
@@ -356,8 +380,8 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration under rocprofv3) and exit")
-    ap.add_argument("--workloads", default="train720p,lidar,rig",
-                    help="extra workloads to time (comma list of train720p, lidar, rig; empty for none)")
+    ap.add_argument("--workloads", default="train720p,lidar,rig,affinity",
+                    help="extra workloads to time (comma list of train720p, lidar, rig, affinity; empty for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures a single MI355X: multi-GPU runs are not part of this build "
@@ -499,7 +523,7 @@ def main():
     if not args.no_extras:
         for w in [x for x in args.workloads.split(",") if x]:
             log(f"workload {w}")
-            fn = {"train720p": bench_train720p, "lidar": bench_lidar, "rig": bench_rig}[w]
+            fn = {"train720p": bench_train720p, "lidar": bench_lidar, "rig": bench_rig, "affinity": bench_affinity}[w]
             extra[w] = fn(args.steps, args.warmup)
 
     if not args.no_cpu_baseline:

@@ -351,6 +351,24 @@ gs_status gs_decode_backward(const gs_anchor_set* anchors, const float* sensor_p
                              const float* group_poses, const gs_decoded* grad_in,
                              const gs_anchor_grads* grads, void* scratch, hipStream_t stream);
 
+/* Inpainting patch affinity (Sec. III-B, Eq. 6).  For each of `batch` pairs
+ * of a target patch (p anchors) and a candidate source patch (q anchors):
+ *   out[b][i][j] = exp(z_ij - max_k z_ik) / sum_k exp(z_ik - max_k z_ik),
+ *   z = X_T X_S^T,
+ * the softmax over the source anchors of the product of the encoded anchor
+ * matrices (one anchor per row: its feature followed by the positional
+ * encoding of its location, built and rounded to bf16 by the caller).
+ * xt: device bf16 bits [batch][p][d] row-major; xs: device bf16 bits
+ * [batch][q][d]; both 16-byte aligned; d a multiple of 32 in [32, 256]
+ * (zero-pad the rows).  out: device FP32 [batch][p][q], written whole.
+ * Products are bf16 x bf16 on MFMA with FP32 accumulation; exponentials FP32.
+ * batch, p or q = 0: nothing is launched.  Errors (before any launch):
+ * GS_ERR_INVALID_ARG for negative sizes, batch > 65535, a bad d, null or
+ * misaligned pointers; GS_ERR_HIP if the launch fails.  Asynchronous on
+ * `stream`; no memory is allocated. */
+gs_status gs_affinity(const uint16_t* xt, const uint16_t* xs, int32_t batch, int32_t p, int32_t q, int32_t d,
+                      float* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

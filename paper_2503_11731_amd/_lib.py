@@ -112,6 +112,7 @@ SIGNATURES = [
     ("gs_decode_scratch_size", c_int32, [POINTER(AnchorSet), POINTER(c_size_t)]),
     ("gs_decode_backward", c_int32, [POINTER(AnchorSet), c_void_p, c_void_p, POINTER(Decoded),
                                      POINTER(AnchorGrads), c_void_p, c_void_p]),
+    ("gs_affinity", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
 ]
 
 _lib = None
