@@ -4,8 +4,8 @@
 //
 // One workgroup per 64 target rows of one pair, one wave per 16 rows.  The
 // wave keeps its 16 x d slice of X_T in registers as MFMA A operands and
-// walks the source anchors 16 at a time (v_mfma_f32_16x16x32_bf16, FP32
-// accumulate): a first sweep keeps a running row maximum and exponential sum
+// walks the source anchors 64 at a time (four v_mfma_f32_16x16x32_bf16
+// tiles, FP32 accumulate, all their loads issued first): a first sweep keeps a running row maximum and exponential sum
 // per lane, the 16 lanes that share a row merge theirs, and a second sweep
 // recomputes each 16 x 16 logit tile and writes exp(z - max) / sum.  The
 // output (4 bytes per entry) dominates the traffic; recomputing the logits
@@ -47,17 +47,25 @@ __global__ __launch_bounds__(256) void k_affinity(const uint16_t* __restrict__ x
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks)
     a[ks].q = ra < p ? *reinterpret_cast<const uint4*>(T + (size_t)ra * D + 32 * ks + 8 * kg) : make_uint4(0, 0, 0, 0);
-  // logits of rows row0 + 4 kg + r (r < 4) at column c0 + r16
-  auto tile = [&](int c0) {
-    const int cb = c0 + r16;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  // logits of rows row0 + 4 kg + r (r < 4) at columns c0 + 16 u + r16 (u < 4):
+  // every source load of the four tiles is issued before the first MFMA
+  auto tiles4 = [&](int c0, f32x4* z) {
+    Bf8 bv[4][KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      Bf8 bv;
-      bv.q = cb < q ? *reinterpret_cast<const uint4*>(S + (size_t)cb * D + 32 * ks + 8 * kg) : make_uint4(0, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks].v, bv.v, acc, 0, 0, 0);
+    for (int u = 0; u < 4; ++u) {
+      const int cb = c0 + 16 * u + r16;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        bv[u][ks].q =
+            cb < q ? *reinterpret_cast<const uint4*>(S + (size_t)cb * D + 32 * ks + 8 * kg) : make_uint4(0, 0, 0, 0);
     }
-    return acc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks].v, bv[u][ks].v, acc, 0, 0, 0);
+      z[u] = acc;
+    }
   };
   // sweep 1: running maximum and sum of exp(z - maximum) over this lane's columns
   float m[4], s[4];
@@ -66,16 +74,20 @@ __global__ __launch_bounds__(256) void k_affinity(const uint16_t* __restrict__ x
     m[r] = -FLT_MAX;
     s[r] = 0.f;
   }
-  for (int c0 = 0; c0 < q; c0 += 16) {
-    const f32x4 z = tile(c0);
-    if (c0 + r16 < q) {
+  for (int c0 = 0; c0 < q; c0 += 64) {
+    f32x4 z[4];
+    tiles4(c0, z);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (z[r] > m[r]) {
-          s[r] = s[r] * __expf(m[r] - z[r]) + 1.f;
-          m[r] = z[r];
-        } else {
-          s[r] += __expf(z[r] - m[r]);
+    for (int u = 0; u < 4; ++u) {
+      if (c0 + 16 * u + r16 < q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (z[u][r] > m[r]) {
+            s[r] = s[r] * __expf(m[r] - z[u][r]) + 1.f;
+            m[r] = z[u][r];
+          } else {
+            s[r] += __expf(z[u][r] - m[r]);
+          }
         }
       }
     }
@@ -97,14 +109,18 @@ __global__ __launch_bounds__(256) void k_affinity(const uint16_t* __restrict__ x
   for (int r = 0; r < 4; ++r) inv[r] = 1.f / s[r];
   // sweep 2: recompute the logits and write the normalised rows
   float* O = out + (size_t)b * p * q;
-  for (int c0 = 0; c0 < q; c0 += 16) {
-    const f32x4 z = tile(c0);
-    const int cb = c0 + r16;
-    if (cb < q) {
+  for (int c0 = 0; c0 < q; c0 += 64) {
+    f32x4 z[4];
+    tiles4(c0, z);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + 4 * kg + r;
-        if (row < p) O[(size_t)row * q + cb] = __expf(z[r] - m[r]) * inv[r];
+    for (int u = 0; u < 4; ++u) {
+      const int cb = c0 + 16 * u + r16;
+      if (cb < q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + 4 * kg + r;
+          if (row < p) O[(size_t)row * q + cb] = __expf(z[u][r] - m[r]) * inv[r];
+        }
       }
     }
   }
