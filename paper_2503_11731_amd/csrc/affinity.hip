@@ -2,7 +2,7 @@
 // patch pair, the softmax over the source anchors of X_T X_S^T, X holding one
 // encoded anchor per row (feature + positional encoding, bf16).
 //
-// One workgroup per 64 target rows of one pair, one wave per 16 rows.  The
+// One workgroup per 128 target rows of one pair (8 waves of 16 rows).  The
 // wave keeps its 16 x d slice of X_T in registers as MFMA operands and walks
 // the source anchors 64 at a time, staged in LDS once per workgroup (four
 // v_mfma_f32_16x16x32_bf16 tiles, FP32 accumulate): a first sweep keeps a running
@@ -26,13 +26,15 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+constexpr int kAffWaves = 8;  // waves (16 target rows each) per workgroup
+
 union Bf8 {
   uint4 q;
   bf16x8 v;
 };
 
-template <int KS>  // d = 32 KS
-__global__ __launch_bounds__(256) void k_affinity(const uint16_t* __restrict__ xt, const uint16_t* __restrict__ xs,
+template <int KS, int NW>  // d = 32 KS; NW waves of 16 target rows
+__global__ __launch_bounds__(64 * NW) void k_affinity(const uint16_t* __restrict__ xt, const uint16_t* __restrict__ xs,
                                                    int p, int q, float* __restrict__ out, bool vec) {
   constexpr int D = 32 * KS;
   constexpr int RS = D + 8;  // LDS row stride (bf16): rows 16 bytes apart in bank space
@@ -40,7 +42,7 @@ __global__ __launch_bounds__(256) void k_affinity(const uint16_t* __restrict__ x
   const int b = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, kg = lane >> 4;
-  const int row0 = blockIdx.x * 64 + 16 * w;
+  const int row0 = blockIdx.x * (16 * NW) + 16 * w;
   const uint16_t* T = xt + (size_t)b * p * D;
   const uint16_t* S = xs + (size_t)b * q * D;
   // Logit tiles are computed transposed, D = X_S X_T^T, so that a lane holds
@@ -59,9 +61,7 @@ __global__ __launch_bounds__(256) void k_affinity(const uint16_t* __restrict__ x
   const int ngroups = (q + 63) / 64;
   auto stage = [&](int g) {
     uint16_t* dst = s_src[g & 1];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const int e = t + 256 * ks;           // piece index in [0, 64 * 4 KS)
+    for (int e = t; e < 256 * KS; e += 64 * NW) {  // 16-byte piece index in [0, 64 * 4 KS)
       const int row = e / (4 * KS), col = 8 * (e % (4 * KS));
       const int src = 64 * g + row;
       const uint4 v = src < q ? *reinterpret_cast<const uint4*>(S + (size_t)src * D + col) : make_uint4(0, 0, 0, 0);
@@ -168,11 +168,11 @@ extern "C" gs_status gs_affinity(const uint16_t* xt, const uint16_t* xs, int32_t
   if (!xt || !xs || !out) return set_error(GS_ERR_INVALID_ARG, "null affinity argument");
   if ((reinterpret_cast<uintptr_t>(xt) | reinterpret_cast<uintptr_t>(xs)) % 16 != 0)
     return set_error(GS_ERR_INVALID_ARG, "affinity inputs must be 16-byte aligned");
-  const dim3 grid((unsigned)((p + 63) / 64), (unsigned)batch), block(256);
+  const dim3 grid((unsigned)((p + 16 * kAffWaves - 1) / (16 * kAffWaves)), (unsigned)batch), block(64 * kAffWaves);
   const bool vec = q % 4 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
   switch (d / 32) {
 #define KCASE(K) \
-  case K: hipLaunchKernelGGL(k_affinity<K>, grid, block, 0, stream, xt, xs, p, q, out, vec); break;
+  case K: hipLaunchKernelGGL((k_affinity<K, kAffWaves>), grid, block, 0, stream, xt, xs, p, q, out, vec); break;
     KCASE(1) KCASE(2) KCASE(3) KCASE(4) KCASE(5) KCASE(6) KCASE(7) KCASE(8)
 #undef KCASE
     default: return set_error(GS_ERR_INVALID_ARG, "bad affinity row width");
