@@ -245,8 +245,8 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(RadixArgs a) {
 //
 // offs[j] = sum of ntiles[val[i]] over i < j, in one pass: 4096-item blocks in
 // ticket order, each publishing its sum and reading the sums of earlier
-// blocks by the same bounded look-back as the radix passes, with 64-bit
-// status words (high half: 1 = block sum, 2 = inclusive prefix; low half the
+// blocks by a bounded look-back (64 blocks per round trip, one per lane of
+// the first wave), with 64-bit status words (high half: 1 = block sum, 2 = inclusive prefix; low half the
 // value).  The ticket and status words are cleared with the frame's status.
 
 constexpr int kScanItems = 4096;
@@ -297,48 +297,50 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
   for (int r = 0; r < PER; ++r) sum += v[r];
   uint32_t tot;
   uint32_t off = block_excl_scan<256>(sum, s_w, &tot);
-  if (t == 0) {
+  if (t < 64) {
+    // wave 0: publish this block's sum, then read 64 earlier blocks per
+    // round trip (lane i: block k - 1 - i), nearest first, up to the nearest
+    // inclusive prefix; a block with nothing published yet ends the round
+    const int lane = t;
     uint64_t* mine = look + b;
-    __hip_atomic_store(mine, (b == 0 ? kScanInc : kScanAgg) | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0)
+      __hip_atomic_store(mine, (b == 0 ? kScanInc : kScanAgg) | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t excl = 0;
     if (b > 0) {
       uint32_t spins = 0;
       for (int k = b; k > 0;) {
-        uint64_t w[kLookWin];
+        const int idx = k - 1 - lane;
+        const uint64_t v = idx >= 0 ? __hip_atomic_load(look + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanInc;
+        const uint64_t inc = __ballot((v & kScanInc) != 0u);
+        const uint64_t none = __ballot((v >> 32) == 0u);
+        const int fi = inc ? __builtin_ctzll(inc) : 64;    // nearest inclusive prefix
+        const int fn = none ? __builtin_ctzll(none) : 64;  // nearest block not yet published
+        const int used = fn <= fi ? fn : fi + 1;           // lanes [0, used) are added
+        uint32_t x = lane < used ? (uint32_t)v : 0u;
 #pragma unroll
-        for (int q = 0; q < kLookWin; ++q)
-          w[q] = q < k ? __hip_atomic_load(look + (k - 1 - q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kScanInc;
-        bool ended = false, inclusive = false;
-        int used = 0;
-#pragma unroll
-        for (int q = 0; q < kLookWin; ++q) {
-          if (ended || (w[q] >> 32) == 0u) {
-            ended = true;
-          } else {
-            excl += (uint32_t)w[q];
-            ++used;
-            inclusive = (w[q] & kScanInc) != 0u;
-            ended = inclusive;
-          }
-        }
-        k -= used < k ? used : k;
-        if (inclusive) break;
+        for (int o = 1; o < 64; o <<= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+        excl += x;
+        k -= used;
+        if (fi < fn) break;  // reached an inclusive prefix
         if (used == 0) {
           if (++spins > kLookSpins) {
-            atomicOr(&status[kStSortStall], 1u);
+            if (lane == 0) atomicOr(&status[kStSortStall], 1u);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
         }
       }
-      __hip_atomic_store(mine, kScanInc | (uint32_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(mine, kScanInc | (uint32_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_excl = excl;
-    if (b == nblk - 1) {
-      const uint32_t total = excl + tot;
-      offs[n] = total;
-      status[kStPairs] = total;
-      if (total > cap) status[kStOverflow] = 1u;
+    if (lane == 0) {
+      s_excl = excl;
+      if (b == nblk - 1) {
+        const uint32_t total = excl + tot;
+        offs[n] = total;
+        status[kStPairs] = total;
+        if (total > cap) status[kStOverflow] = 1u;
+      }
     }
   }
   __syncthreads();
