@@ -145,7 +145,8 @@ typedef struct gs_plan_desc {
   int32_t n_sensors;             /* 1..GS_MAX_SENSORS                          */
   const gs_sensor_desc* sensors; /* host array [n_sensors]                     */
   gs_render_opts opts;
-  int64_t pair_capacity;         /* (tile, surfel) pairs per sensor; 0 = 16*N+4096 */
+  int64_t pair_capacity;         /* (tile, surfel) pairs per sensor; 0 = 16*N+4096;
+                                    clamped to 2^30 - 1 (sort key limit)     */
   int32_t batched;               /* 1: all sensors of the plan form one step:
                                     one record space, one depth sort, one pair
                                     list over a global tile space and one
@@ -266,7 +267,9 @@ gs_status gs_plan_capture(gs_plan* plan, const gs_scene* scenes, const float* se
                           hipStream_t stream);
 
 /* Synchronises `stream`, then reads the workspace's status words. Returns
- * GS_ERR_CAPACITY when a sensor overflowed its pair capacity. */
+ * GS_ERR_CAPACITY when a sensor overflowed its pair capacity, and GS_ERR_HIP
+ * when a device-side bounded wait gave up (the compositing work queue, or the
+ * look-back of a sort or scan: the outputs of that run are not valid). */
 gs_status gs_query_status(const gs_plan* plan, const void* workspace, hipStream_t stream,
                           gs_run_status* out);
 
