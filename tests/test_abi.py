@@ -110,3 +110,18 @@ def test_decode_rejects_invalid_arguments():
     one = ctypes.c_float(0)
     assert lib.gs_decode_forward(ctypes.byref(an), ctypes.addressof(one), ctypes.addressof(one), None,
                                  None) == L.GS_ERR_INVALID_ARG
+
+
+@need_lib
+def test_affinity_rejects_invalid_arguments_and_launches_nothing_for_empty_sizes():
+    lib = L.load()
+    buf = (ctypes.c_uint16 * 64)()
+    p = ctypes.addressof(buf)
+    assert lib.gs_affinity(None, None, -1, 4, 4, 64, None, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_affinity(None, None, 1, 4, 4, 48, None, None) == L.GS_ERR_INVALID_ARG    # d not a multiple of 32
+    assert lib.gs_affinity(None, None, 1, 4, 4, 288, None, None) == L.GS_ERR_INVALID_ARG   # d above 256
+    assert lib.gs_affinity(None, None, 70000, 4, 4, 64, None, None) == L.GS_ERR_INVALID_ARG
+    assert lib.gs_affinity(None, None, 1, 4, 4, 64, None, None) == L.GS_ERR_INVALID_ARG    # null buffers
+    assert lib.gs_affinity(p + 2, p, 1, 4, 4, 64, p, None) == L.GS_ERR_INVALID_ARG         # misaligned rows
+    assert lib.gs_affinity(None, None, 0, 4, 4, 64, None, None) == 0                       # nothing to do
+    assert lib.gs_affinity(None, None, 3, 4, 0, 64, None, None) == 0
