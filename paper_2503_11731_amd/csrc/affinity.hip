@@ -55,17 +55,30 @@ __global__ __launch_bounds__(64 * NW) void k_affinity(const uint16_t* __restrict
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks)
     a[ks].q = row_ok ? *reinterpret_cast<const uint4*>(T + (size_t)ra * D + 32 * ks + 8 * kg) : make_uint4(0, 0, 0, 0);
-  // The workgroup stages 64 source anchors at a time in LDS (one 16-byte
-  // piece per thread and ks; double-buffered, one barrier per step), so each
-  // source row is read from L2 once per workgroup rather than once per wave.
+  // The workgroup stages 64 source anchors at a time in LDS (double-buffered,
+  // one barrier per step, the next chunk's loads in flight during a step), so
+  // each source row is read from L2 once per workgroup rather than once per wave.
   const int ngroups = (q + 63) / 64;
-  auto stage = [&](int g) {
-    uint16_t* dst = s_src[g & 1];
-    for (int e = t; e < 256 * KS; e += 64 * NW) {  // 16-byte piece index in [0, 64 * 4 KS)
+  // each thread's 16-byte pieces of a 64-anchor chunk: loaded into registers
+  // one chunk ahead, stored to LDS at the start of the chunk's step
+  constexpr int NP = (256 * KS + 64 * NW - 1) / (64 * NW);
+  uint4 pre[NP];
+  auto fetch = [&](int g) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int e = t + 64 * NW * i;  // piece index in [0, 64 * 4 KS)
       const int row = e / (4 * KS), col = 8 * (e % (4 * KS));
       const int src = 64 * g + row;
-      const uint4 v = src < q ? *reinterpret_cast<const uint4*>(S + (size_t)src * D + col) : make_uint4(0, 0, 0, 0);
-      *reinterpret_cast<uint4*>(dst + row * RS + col) = v;
+      pre[i] = e < 256 * KS && src < q ? *reinterpret_cast<const uint4*>(S + (size_t)src * D + col)
+                                       : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto stage = [&](int g) {
+    uint16_t* dst = s_src[g & 1];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int e = t + 64 * NW * i;
+      if (e < 256 * KS) *reinterpret_cast<uint4*>(dst + (e / (4 * KS)) * RS + 8 * (e % (4 * KS))) = pre[i];
     }
   };
   // four tiles of 16 staged source anchors
@@ -87,8 +100,10 @@ __global__ __launch_bounds__(64 * NW) void k_affinity(const uint16_t* __restrict
   };
   // sweep 1: running maximum and sum of exp(z - maximum) over this lane's sources
   float m = -FLT_MAX, s = 0.f;
+  fetch(0);
   for (int g = 0; g < ngroups; ++g) {
     stage(g);
+    if (g + 1 < ngroups) fetch(g + 1);
     __syncthreads();
     f32x4 z[4];
     tiles4(g, z);
@@ -125,8 +140,10 @@ __global__ __launch_bounds__(64 * NW) void k_affinity(const uint16_t* __restrict
   // the buffer that sweep 1 read last, so a barrier separates the sweeps.
   __syncthreads();
   float* O = out + (size_t)b * p * q + (size_t)ra * q;
+  fetch(0);
   for (int g = 0; g < ngroups; ++g) {
     stage(g);
+    if (g + 1 < ngroups) fetch(g + 1);
     __syncthreads();
     f32x4 z[4];
     tiles4(g, z);
