@@ -338,7 +338,9 @@ gs_status gs_decode_forward(const gs_anchor_set* anchors, const float* sensor_po
  * layout as `out`, read only); accumulates (+=) into the FP32 gradient
  * buffers (device, NULL to skip): xyz [3][A], scaling [A], offsets [3][K][A],
  * feat [A][32], w1 [G][32][35], b1 [G][32], w2 [G][K*J][32], b2 [G][K*J].
- * scratch: device, gs_decode_scratch_size bytes. */
+ * scratch: device, gs_decode_scratch_size bytes (per-block partials of the
+ * weight gradients, summed in a fixed order: weight gradients are
+ * deterministic); may be NULL only when w1, b1, w2 and b2 are all NULL. */
 typedef struct gs_anchor_grads {
   float* xyz;
   float* scaling;

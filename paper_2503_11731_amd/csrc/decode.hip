@@ -10,8 +10,8 @@
 //            quantised to 8 mantissa bits.
 //   heads    opacity / colour / intensity = sigmoid, scale = l_a sigmoid,
 //            quaternion = raw, centre = x_a + l_a O_k; surfel n = a K + k.
-// Adjoint: FP32 MFMA contractions with per-block partial weight gradients
-// added by atomics.
+// Adjoint: FP32 MFMA contractions; per-block partial weight gradients summed
+// in a fixed order by a second kernel.
 #include <cstring>
 #include <string>
 
@@ -67,6 +67,7 @@ struct DecodeArgs {
   float* g_b1;
   float* g_w2;
   float* g_b2;
+  float* part;  // per-block weight-gradient partials [blocks][w2 | b2 | w1 | b1]
 };
 
 __device__ inline uint16_t f2bf(float x) {
@@ -346,8 +347,8 @@ constexpr int kW1Cols = 48;  // W1 row in LDS: kIn columns, zero to three whole 
 //   dH  = dY W2, ReLU-masked    per wave: 16 anchors x 32 hidden, over K*J
 //   dX  = dH W1                 per wave: 16 anchors x 35 (features, direction)
 //   dW2 = dY^T H, dW1 = dH^T X  per block: summed over its 64 anchors
-// Weights are staged in LDS as bf16 bits; each block adds its weight-gradient
-// partials to the global sums with one atomic per entry.
+// Weights are staged in LDS as bf16 bits; each block writes its weight-gradient
+// partials to the scratch buffer, summed per group by k_decode_wsum.
 __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   __shared__ float sD[4][16][4];
   __shared__ float sH[4][16][kHidden + 1];
@@ -364,6 +365,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   block_group(a, blockIdx.x, g, a0);
   const int t = threadIdx.x;
   const int KJ = a.K * a.J;
+  float* part = a.part + (size_t)blockIdx.x * (KJ * (kHidden + 1) + kHidden * (kIn + 1));
   if (t == 0) group_camera(a, g, sCam);
   for (int q = t; q < 4 * 16 * 8; q += 256) (&sGA[0][0][0])[q] = 0.f;
   const uint16_t* W2 = a.w2 + (size_t)g * KJ * kHidden;
@@ -503,7 +505,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int n = n0 + 4 * k4 + i;
-        if (n < KJ && acc[i] != 0.f) atomicAdd(a.g_w2 + ((size_t)g * KJ + n) * kHidden + j0 + r16, acc[i]);
+        if (n < KJ) part[n * kHidden + j0 + r16] = acc[i];
       }
     } else {
       const int u = tile - nt2;
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int j = j0 + 4 * k4 + i;
-          if (acc[i] != 0.f) atomicAdd(a.g_w1 + ((size_t)g * kHidden + j) * kIn + col, acc[i]);
+          part[KJ * (kHidden + 1) + j * kIn + col] = acc[i];
         }
       }
     }
@@ -528,12 +530,47 @@ __global__ __launch_bounds__(256) void k_decode_bwd(DecodeArgs a) {
   if (a.g_b2 && t < KJ) {
     float s = 0.f;
     for (int an = 0; an < 64; ++an) s += sY[an >> 4][an & 15][t];
-    if (s != 0.f) atomicAdd(a.g_b2 + (size_t)g * KJ + t, s);
+    part[KJ * kHidden + t] = s;
   }
   if (a.g_b1 && t >= 192 && t < 192 + kHidden) {
     float s = 0.f;
     for (int an = 0; an < 64; ++an) s += sGH[an >> 4][an & 15][t - 192];
-    if (s != 0.f) atomicAdd(a.g_b1 + (size_t)g * kHidden + (t - 192), s);
+    part[KJ * (kHidden + 1) + kHidden * kIn + (t - 192)] = s;
+  }
+}
+
+// Weight-gradient sums: for group g and partial entry e, the sum over the
+// group's blocks of part[b][e] (16 slices of the block range per entry, then
+// an LDS sum in slice order), added once to the gradient buffer.  Fixed
+// order: the weight gradients are deterministic.
+__global__ __launch_bounds__(1024) void k_decode_wsum(DecodeArgs a) {
+  __shared__ float s_acc[16][65];
+  const int g = blockIdx.y;
+  const int KJ = a.K * a.J;
+  const int PW = KJ * (kHidden + 1) + kHidden * (kIn + 1);
+  const int le = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + le;
+  const int b0 = a.bstart[g], b1 = a.bstart[g + 1];
+  float acc = 0.f;
+  if (e < PW) {
+    int b = b0 + sl;
+#pragma unroll 4
+    for (; b < b1; b += 16) acc += a.part[(size_t)b * PW + e];
+  }
+  s_acc[sl][le] = acc;
+  __syncthreads();
+  if (sl != 0 || e >= PW) return;
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s += s_acc[k][le];
+  if (e < KJ * kHidden) {
+    if (a.g_w2) a.g_w2[(size_t)g * KJ * kHidden + e] += s;
+  } else if (e < KJ * (kHidden + 1)) {
+    if (a.g_b2) a.g_b2[(size_t)g * KJ + (e - KJ * kHidden)] += s;
+  } else if (e < KJ * (kHidden + 1) + kHidden * kIn) {
+    if (a.g_w1) a.g_w1[(size_t)g * kHidden * kIn + (e - KJ * (kHidden + 1))] += s;
+  } else {
+    if (a.g_b1) a.g_b1[(size_t)g * kHidden + (e - KJ * (kHidden + 1) - kHidden * kIn)] += s;
   }
 }
 
@@ -548,8 +585,8 @@ using namespace gs;
 namespace {
 
 gs_status fill_args(const gs_anchor_set* an, const float* sensor_pose, const float* group_poses, DecodeArgs& a,
-                    int& nblocks) {
-  if (!an || !sensor_pose || !group_poses) return set_error(GS_ERR_INVALID_ARG, "null decode argument");
+                    int& nblocks, bool need_poses = true) {
+  if (!an || (need_poses && (!sensor_pose || !group_poses))) return set_error(GS_ERR_INVALID_ARG, "null decode argument");
   if (an->n_anchors < 0 || an->k < 1 || an->k > 16 || an->n_groups < 1 || an->n_groups > kMaxGroups ||
       !an->group_offsets)
     return set_error(GS_ERR_INVALID_ARG, "bad anchor set shape");
@@ -619,14 +656,18 @@ extern "C" gs_status gs_decode_forward(const gs_anchor_set* anchors, const float
 
 extern "C" gs_status gs_decode_scratch_size(const gs_anchor_set* anchors, size_t* bytes) {
   if (!anchors || !bytes) return set_error(GS_ERR_INVALID_ARG, "null argument");
-  *bytes = 256;
+  DecodeArgs a;
+  int nb = 0;
+  const gs_status s = fill_args(anchors, nullptr, nullptr, a, nb, false);
+  if (s != GS_OK) return s;
+  const size_t pw = (size_t)a.K * a.J * (kHidden + 1) + (size_t)kHidden * (kIn + 1);
+  *bytes = nb > 0 ? (size_t)nb * pw * sizeof(float) : 256;
   return set_error(GS_OK, "");
 }
 
 extern "C" gs_status gs_decode_backward(const gs_anchor_set* anchors, const float* sensor_pose,
                                         const float* group_poses, const gs_decoded* grad_in,
                                         const gs_anchor_grads* grads, void* scratch, hipStream_t stream) {
-  (void)scratch;
   DecodeArgs a;
   int nb = 0;
   gs_status s = fill_args(anchors, sensor_pose, group_poses, a, nb);
@@ -646,7 +687,14 @@ extern "C" gs_status gs_decode_backward(const gs_anchor_set* anchors, const floa
   a.g_b1 = grads->b1;
   a.g_w2 = grads->w2;
   a.g_b2 = grads->b2;
+  if (nb > 0 && (a.g_w1 || a.g_b1 || a.g_w2 || a.g_b2) && !scratch)
+    return set_error(GS_ERR_INVALID_ARG, "decode backward needs its scratch buffer for weight gradients");
+  a.part = static_cast<float*>(scratch);
   if (nb > 0) hipLaunchKernelGGL(k_decode_bwd, dim3(nb), dim3(256), 0, stream, a);
+  if (nb > 0 && (a.g_w1 || a.g_b1 || a.g_w2 || a.g_b2)) {
+    const int pw = a.K * a.J * (kHidden + 1) + kHidden * (kIn + 1);
+    hipLaunchKernelGGL(k_decode_wsum, dim3((pw + 63) / 64, a.n_groups), dim3(1024), 0, stream, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(GS_ERR_HIP, std::string("decode backward launch: ") + hipGetErrorString(e));
   return set_error(GS_OK, "");

@@ -144,3 +144,18 @@ def test_training_step_gradient_chain():
     _say(f"  {out}")
     for k, (err, scale) in out.items():
         assert err <= 1e-3 * scale + 1e-7, (k, err, scale)
+
+
+def test_decode_weight_gradients_are_deterministic():
+    """Per-block partials summed in a fixed order: repeated adjoints agree bit for bit."""
+    _say("decode backward determinism")
+    sc, sensor, dec, sp, gp, poses_s = _setup("pinhole", n_anchors=3000, n_assets=2)
+    out = dec.forward(sp, gp)
+    rng = np.random.default_rng(8)
+    gi = {k: torch.from_numpy(rng.standard_normal(tuple(v.shape)).astype(np.float32)).to(DEV) for k, v in out.items()}
+    g1 = dec.backward(sp, gp, gi)
+    g2 = dec.backward(sp, gp, gi)
+    torch.cuda.synchronize()
+    for k in ("w1", "b1", "w2", "b2"):
+        assert torch.equal(g1[k], g2[k]), k
+        assert float(g1[k].abs().max()) > 0.0, k
