@@ -257,7 +257,7 @@ def _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride=None):
 
 
 def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None, margins=False,
-           params=None):
+           params=None, alternatives=None, max_flags=3):
     """Render one sensor in FP64.
 
     scene: dict of numpy arrays (see gen.scenes layouts; 'sh_degree' if 'sh').
@@ -267,6 +267,15 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     result also holds 'grads' (d(sum grad_out * out)/d inputs).
     params: optional dict of FP64 torch tensors to use as inputs (e.g. the
     output of the decode oracle); gradients then flow into them.
+    margins: also return per ray the smallest relative distance of any of its
+    compositing decisions to the decision's threshold ('margin').
+    alternatives: a relative tolerance tol.  Every decision of a ray that lies
+    within tol of its threshold -- a pair entering or leaving the support
+    (cutoff, z_near), the alpha_min skip, the T_min stop -- is flagged, and the
+    result also holds, for every ray with 1..max_flags flags, the outputs the
+    definition gives when any non-empty subset of those decisions goes the
+    other way ('alts': rays, values [n_alt, C] in the channel order of the
+    device layout); rays with more flags are listed in 'unverified'.
     Returns dict of numpy FP64 outputs shaped [C, H, W] (or [C, R] for rays).
     """
     opts = make_opts(**(opts or {})) if not isinstance(opts, dict) or "tile_w" not in opts else opts
@@ -292,64 +301,59 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
             params["rgb"] = _leaf(scene["rgb"], want_grad)
     sq = splat_quantities(scene, sensor, bins, params)
     rays_t = _rays(sensor, ray_ids)
+    tol = float(alternatives) if alternatives is not None else 0.0
 
     rp, sp = _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride)
-    if not full and mode == "brute":
-        pass
-    # ----- no-grad pass: support test on every candidate pair
+    # ----- no-grad pass: support test on every candidate pair; pairs within
+    # tol of the support boundary stay listed (not present) for the alternatives
     with torch.no_grad():
-        sol = _solve(sq, rays_t, rp, sp, sensor, opts, scene)
-        keep = sol["support"].numpy()
+        sol = _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol)
+        keep = (sol["support"] | sol["near"]).numpy()
     rp, sp = rp[keep], sp[keep]
     # ----- order: ray, then FP32 key bits, then surfel index
     order = np.lexsort((sp, bins["key_bits"][sp], rp))
     rp, sp = rp[order], sp[order]
-    # ----- differentiable pass on supported pairs only
-    sol = _solve(sq, rays_t, rp, sp, sensor, opts, scene)
+    # ----- differentiable pass on listed pairs only
+    sol = _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol)
     counts = np.bincount(rp, minlength=R)
     K = int(counts.max()) if counts.size and counts.max() > 0 else 1
     seg_start = np.cumsum(counts) - counts
     pos = np.arange(rp.size) - seg_start[rp]
     rp_t, pos_t = torch.as_tensor(rp), torch.as_tensor(pos)
+    sp_t = torch.as_tensor(sp)
 
-    o = sq["opacity"][torch.as_tensor(sp)]
+    def grid(v, fill=0.0):  # per pair [P] -> [R, K]
+        z = torch.full((R, K), fill, dtype=v.dtype) if v.dtype != torch.bool else torch.zeros((R, K), dtype=torch.bool)
+        return z.index_put((rp_t, pos_t), v)
+
+    o = sq["opacity"][sp_t]
     a_raw = o * torch.exp(-0.5 * sol["rho_hat"])
-    alpha_p = torch.clamp(a_raw, max=opts["alpha_max"])
-    alpha = torch.zeros((R, K), dtype=DT).index_put((rp_t, pos_t), alpha_p)
-    with torch.no_grad():
-        skip = alpha < opts["alpha_min"]
-        present = torch.zeros((R, K), dtype=torch.bool).index_put((rp_t, pos_t), torch.ones(rp.size, dtype=torch.bool))
-        skip |= ~present
-        a_eff = torch.where(skip, torch.zeros_like(alpha), alpha)
-        one_m = 1.0 - a_eff
-        T_ex = torch.cumprod(torch.cat([torch.ones((R, 1), dtype=DT), one_m[:, :-1]], 1), 1)
-        test = T_ex * one_m
-        stop_ev = (~skip) & (test < opts["T_min"])
-        stopped = torch.cumsum(stop_ev.to(torch.int64), 1) > 0
-        active = (~skip) & (~stopped)
-    a_fin = torch.where(active, alpha, torch.zeros_like(alpha))
-    om = 1.0 - a_fin
-    T = torch.cumprod(torch.cat([torch.ones((R, 1), dtype=DT), om[:, :-1]], 1), 1)
-    w = a_fin * T
-    T_final = T[:, -1] * om[:, -1]
+    alpha = grid(torch.clamp(a_raw, max=opts["alpha_max"]))
+    present = grid(sol["support"].detach())
+    listed = grid(torch.ones(rp.size, dtype=torch.bool))
+    # per-pair features in the device channel order
+    if lidar:
+        feats = [sol["depth"], sq["intensity"][sp_t], torch.ones(rp.size, dtype=DT)]
+        bg = torch.zeros(3, dtype=DT)
+    else:
+        col = sq["colour"][sp_t]
+        nrm = sq["normal"][sp_t]
+        feats = [col[:, 0], col[:, 1], col[:, 2], sol["depth"], nrm[:, 0], nrm[:, 1], nrm[:, 2],
+                 torch.ones(rp.size, dtype=DT)]
+        bg = torch.as_tensor([opts["bg"][0], opts["bg"][1], opts["bg"][2], 0, 0, 0, 0, 0], dtype=DT)
+    feat = torch.stack([grid(f) for f in feats], 2)  # [R, K, C]
 
-    def acc(feat_p):  # feat_p: [P] per pair -> [R]
-        f = torch.zeros((R, K), dtype=DT).index_put((rp_t, pos_t), feat_p)
-        return (w * f).sum(1)
+    active, T_ex, test, skip, stopped = _decide(alpha.detach(), present, opts)
+    out, w, T_final = _accumulate(active, alpha, feat, bg)
 
     outs = {}
     if lidar:
-        outs["range"] = acc(sol["depth"])
-        outs["intensity"] = acc(sq["intensity"][torch.as_tensor(sp)])
-        outs["alpha"] = w.sum(1)
+        outs["range"], outs["intensity"], outs["alpha"] = out[:, 0], out[:, 1], out[:, 2]
     else:
-        col = sq["colour"][torch.as_tensor(sp)]
-        bg = opts["bg"]
-        outs["rgb"] = torch.stack([acc(col[:, c]) + T_final * bg[c] for c in range(3)])
-        outs["depth"] = acc(sol["depth"])
-        nrm = sq["normal"][torch.as_tensor(sp)]
-        outs["normal"] = torch.stack([acc(nrm[:, c]) for c in range(3)])
-        outs["alpha"] = w.sum(1)
+        outs["rgb"] = out[:, 0:3].T
+        outs["depth"] = out[:, 3]
+        outs["normal"] = out[:, 4:7].T
+        outs["alpha"] = out[:, 7]
     outs["T_final"] = T_final
 
     result = {}
@@ -358,8 +362,14 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
         vv = v.detach().numpy()
         result[k_] = vv.reshape((vv.shape[0],) + shape) if vv.ndim == 2 else vv.reshape(shape)
     result["n_contrib"] = active.sum(1).numpy().reshape(shape)
+    first_stop = torch.where(stopped.any(1), stopped.to(torch.int64).argmax(1), torch.full((R,), K))
+    considered = listed & (torch.arange(K)[None, :] <= first_stop[:, None])
     if margins:
-        result["margin"] = _margins(sol, alpha.detach(), T_ex, skip, stopped, rp, pos, R, opts, sensor).reshape(shape)
+        result["margin"] = _margins(sol, rp, pos, R, K, alpha.detach(), test, skip, considered, opts,
+                                    sensor).reshape(shape)
+    if alternatives is not None:
+        result.update(_alternatives(sol, rp, pos, R, K, alpha.detach(), present, listed, feat.detach(), bg, test,
+                                    skip, considered, opts, tol, max_flags, sensor))
     if want_grad:
         total = 0.0
         for k_, g in grad_out.items():
@@ -376,8 +386,54 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     return result
 
 
-def _solve(sq, rays_t, rp, sp, sensor, opts, scene):
-    """Per-pair ray-splat solve (Eq. 2): (u, v), rho_hat, hit depth, support mask."""
+def _decide(alpha, present, opts, flips=None):
+    """Front-to-back skip and stop decisions on [R, K] depth-ordered pairs.
+
+    A pair is skipped when it is not in the ray's support or its alpha is
+    below alpha_min; before compositing a non-skipped pair the ray stops if
+    T (1 - alpha) < T_min (the pair and everything after it are excluded).
+    flips: optional (support, alpha_min, stop) [R, K] masks that toggle the
+    outcome of the support test, of the alpha_min test and of the stop test at
+    chosen pairs (a near-threshold decision taken the other way).
+    Returns (active, T_ex, test, skip, stopped), no gradient.
+    """
+    with torch.no_grad():
+        R = alpha.shape[0]
+        pres = present
+        low = alpha < opts["alpha_min"]
+        if flips is not None:
+            pres = pres ^ flips[0]
+            low = low ^ flips[1]
+        skip = (~pres) | low
+        a_eff = torch.where(skip, torch.zeros_like(alpha), alpha)
+        one_m = 1.0 - a_eff
+        T_ex = torch.cumprod(torch.cat([torch.ones((R, 1), dtype=DT), one_m[:, :-1]], 1), 1)
+        test = T_ex * one_m
+        stop_ev = (~skip) & (test < opts["T_min"])
+        if flips is not None:
+            stop_ev = stop_ev ^ (flips[2] & ~skip)
+        stopped = torch.cumsum(stop_ev.to(torch.int64), 1) > 0
+        active = (~skip) & (~stopped)
+    return active, T_ex, test, skip, stopped
+
+
+def _accumulate(active, alpha, feat, bg):
+    """Weights w_i = alpha_i T_i of the active pairs and the channel sums
+    O = sum_i w_i f_i + T_final bg (front-to-back compositing)."""
+    a_fin = torch.where(active, alpha, torch.zeros_like(alpha))
+    om = 1.0 - a_fin
+    R = alpha.shape[0]
+    T = torch.cumprod(torch.cat([torch.ones((R, 1), dtype=DT), om[:, :-1]], 1), 1)
+    w = a_fin * T
+    T_final = T[:, -1] * om[:, -1]
+    out = (w[:, :, None] * feat).sum(1) + T_final[:, None] * bg[None, :]
+    return out, w, T_final
+
+
+def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
+    """Per-pair ray-splat solve (Eq. 2): (u, v), rho_hat, hit depth, support
+    mask, and `near`: the support decision lies within tol (relative) of the
+    cutoff or z_near threshold."""
     rp_t = torch.as_tensor(rp)
     sp_t = torch.as_tensor(sp)
     M = sq["M"][sp_t]  # [P,3,3]
@@ -417,39 +473,67 @@ def _solve(sq, rays_t, rp, sp, sensor, opts, scene):
         rho_hat = torch.where(use_rho, rho, rho_lp)
     else:
         rho_hat = rho
-    support = ok & (rho_hat <= opts["cutoff2"]) & (depth > sensor["z_near"])
-    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support)
+    c2, zn = opts["cutoff2"], sensor["z_near"]
+    support = ok & (rho_hat <= c2) & (depth > zn)
+    with torch.no_grad():
+        near = ok & (((rho_hat - c2).abs() <= tol * c2) | ((depth - zn).abs() <= tol * zn))
+        if tol <= 0.0:
+            near = torch.zeros_like(near)
+    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support, near=near)
 
 
-def _margins(sol, alpha, T_ex, skip, stopped, rp, pos, R, opts, sensor):
-    """Per-ray smallest relative distance of any compositing decision to its threshold.
+def _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor):
+    """Per listed pair [R, K]: relative distance of its support decision
+    (cutoff, z_near), its alpha_min skip and (non-skipped pairs) its T_min
+    stop test to the threshold; inf where the rule is off."""
+    rp_t, pos_t = torch.as_tensor(rp), torch.as_tensor(pos)
+    with torch.no_grad():
+        rh = sol["rho_hat"].detach()
+        dep = sol["depth"].detach()
+        c2, zn = opts["cutoff2"], sensor["z_near"]
+        m_sup = torch.minimum((rh - c2).abs() / c2, (dep - zn).abs() / max(zn, 1e-300))
+        d_sup = torch.full((R, K), math.inf, dtype=DT).index_put((rp_t, pos_t), m_sup)
+        inf = torch.full((R, K), math.inf, dtype=DT)
+        am, tm = opts["alpha_min"], opts["T_min"]
+        d_amin = (alpha - am).abs() / am if am > 0 else inf
+        d_stop = torch.where(skip, inf, (test - tm).abs() / tm) if tm > 0 else inf
+    return d_sup, d_amin, d_stop
 
-    Considers the alpha_min skip test, the T_min stop test, the cutoff and the
-    z_near hit test of every pair up to and including the stopping surfel.
-    """
-    rh = sol["rho_hat"].detach().numpy()
-    dep = sol["depth"].detach().numpy()
-    a = alpha.numpy()[rp, pos]
-    Tx = T_ex.numpy()[rp, pos]
-    st = stopped.numpy()[rp, pos]
-    sk = skip.numpy()[rp, pos]
-    prev_stopped = np.zeros_like(st)
-    # a pair is "considered" if no earlier pair stopped the ray
-    first_stop = np.full(R, np.iinfo(np.int64).max)
-    np.minimum.at(first_stop, rp[st], pos[st])
-    considered = pos <= first_stop[rp]
-    del prev_stopped
-    m = np.full(rp.size, np.inf)
-    k = opts["cutoff2"]
-    m = np.minimum(m, np.abs(rh - k) / k)
-    m = np.minimum(m, np.abs(dep - sensor["z_near"]) / max(sensor["z_near"], 1e-12))
-    if opts["alpha_min"] > 0:
-        m = np.minimum(m, np.abs(a - opts["alpha_min"]) / opts["alpha_min"])
-    if opts["T_min"] > 0:
-        tt = Tx * (1.0 - a)
-        mt = np.where(sk, np.inf, np.abs(tt - opts["T_min"]) / opts["T_min"])
-        m = np.minimum(m, mt)
-    m = np.where(considered, m, np.inf)
-    out = np.full(R, np.inf)
-    np.minimum.at(out, rp, m)
-    return out
+
+def _margins(sol, rp, pos, R, K, alpha, test, skip, considered, opts, sensor):
+    """Per ray: the smallest relative distance of any decision of a considered
+    pair (up to and including the stopping one) to its threshold."""
+    d_sup, d_amin, d_stop = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
+    m = torch.minimum(torch.minimum(d_sup, d_amin), d_stop)
+    m = torch.where(considered, m, torch.full_like(m, math.inf))
+    return m.min(1).values.numpy() if K > 0 else np.full(R, np.inf)
+
+
+def _alternatives(sol, rp, pos, R, K, alpha, present, listed, feat, bg, test, skip, considered, opts, tol,
+                  max_flags, sensor):
+    """Outputs of every ray under each non-empty subset of its near-threshold
+    decisions taken the other way (see render's `alternatives`).  Flag kinds:
+    0 support (cutoff or z_near), 1 alpha_min, 2 stop."""
+    d_sup, d_amin, d_stop = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
+    with torch.no_grad():
+        fm = [considered & (d_sup <= tol), considered & (d_amin <= tol), considered & (d_stop <= tol)]
+        n_flags = sum(f.to(torch.int64) for f in fm).sum(1)
+    nf = n_flags.numpy()
+    rays = np.nonzero((nf >= 1) & (nf <= max_flags))[0]
+    unverified = np.nonzero(nf > max_flags)[0]
+    values, kinds = [], []
+    for r in rays:
+        r_t = torch.as_tensor([int(r)])
+        flags = [(kd, int(k)) for kd in range(3) for k in torch.nonzero(fm[kd][r]).reshape(-1).tolist()]
+        a_r, p_r, f_r = alpha[r_t], present[r_t], feat[r_t]
+        alts = []
+        for subset in range(1, 1 << len(flags)):
+            fl = [torch.zeros((1, K), dtype=torch.bool) for _ in range(3)]
+            for b, (kd, k) in enumerate(flags):
+                if (subset >> b) & 1:
+                    fl[kd][0, k] = True
+            act = _decide(a_r, p_r, opts, flips=fl)[0]
+            alts.append(_accumulate(act, a_r, f_r, bg)[0][0].numpy())
+        values.append(np.stack(alts))
+        kinds.append([kd for kd, _ in flags])
+    return dict(alts=dict(rays=rays, values=values, kinds=kinds), unverified=unverified, n_flags=nf)
