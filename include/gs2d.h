@@ -185,6 +185,8 @@ typedef struct gs_run_status {
   int64_t composited;             /* ray-surfel pairs that contributed             */
   int64_t work_items;             /* compositing work items (tiles + extra segments) */
   int64_t segments;               /* segments of split tiles                       */
+  int64_t graph_replays;          /* forward calls of this plan that replayed a
+                                     captured graph (host count, since creation) */
 } gs_run_status;
 
 /* Pipeline stages, for per-stage timing. */

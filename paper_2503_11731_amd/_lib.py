@@ -55,7 +55,7 @@ class PlanDesc(ctypes.Structure):
 class RunStatus(ctypes.Structure):
     _fields_ = [("pairs", c_int64 * GS_MAX_SENSORS), ("overflow", c_int32), ("n_visible", c_int32 * GS_MAX_SENSORS),
                 ("fp64_pairs", c_int64), ("evaluated", c_int64), ("composited", c_int64),
-                ("work_items", c_int64), ("segments", c_int64)]
+                ("work_items", c_int64), ("segments", c_int64), ("graph_replays", c_int64)]
 
 
 STAGES = ("preprocess", "depth_sort", "emit", "tile_sort", "ranges", "blend", "blend_bwd", "splat_bwd")

@@ -185,6 +185,7 @@ struct gs_plan {
   const float* g_group_poses = nullptr;
   void* g_workspace = nullptr;
   hipStream_t g_stream = nullptr;
+  int64_t replays = 0;
 };
 
 namespace {
@@ -793,6 +794,7 @@ gs_status gs_render_forward(gs_plan* p, const gs_scene* scenes, const float* sen
   for (size_t i = 0; replay && i < p->sensors.size(); ++i) replay = outputs[i] == p->g_outputs[i];
   if (replay) {
     GS_HIP_TRY(hipGraphLaunch(p->graph_exec, st));
+    ++p->replays;
     return ok();
   }
   enqueue_forward(p, scenes, sensor_poses, group_poses, outputs, workspace, st);
@@ -940,6 +942,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
     }
   }
   out->overflow = over ? 1 : 0;
+  out->graph_replays = p->replays;
   if (over) return fail(GS_ERR_CAPACITY, "pair capacity exceeded; re-plan with a larger pair_capacity");
   if (stalled) return fail(GS_ERR_HIP, "compositing work queue stalled (walk list inconsistent)");
   if (sort_stall) return fail(GS_ERR_HIP, "sort or scan look-back wait gave up (block statuses inconsistent)");

@@ -55,6 +55,31 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t* 
   return off + inc - v;
 }
 
+// 64-bit exclusive scan over 256 threads; *total receives the block sum.
+__device__ inline uint64_t block_excl_scan64(uint64_t v, uint64_t* s_w, uint64_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_w[w] = inc;
+  __syncthreads();
+  uint64_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t x = s_w[k];
+    off += (k < w) ? x : 0ull;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__device__ inline uint32_t sat32(uint64_t x) { return x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x; }
+
 struct RadixArgs {
   const uint32_t* kin;
   const uint32_t* vin;
@@ -248,6 +273,9 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(RadixArgs a) {
 // blocks by a bounded look-back (64 blocks per round trip, one per lane of
 // the first wave), with 64-bit status words (high half: 1 = block sum, 2 = inclusive prefix; low half the
 // value).  The ticket and status words are cleared with the frame's status.
+// Sums are formed in 64 bits and saturate at 2^32 - 1, so a frame whose
+// pairs exceed any capacity is always reported as an overflow (a wrapped
+// 32-bit total could pass for a small one).
 
 constexpr int kScanItems = 4096;
 constexpr uint64_t kScanAgg = 1ull << 32;
@@ -256,8 +284,9 @@ constexpr uint64_t kScanInc = 2ull << 32;
 __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict__ val,
                                                       const uint32_t* __restrict__ ntiles, int n, uint32_t* bsum,
                                                       uint32_t* __restrict__ offs, uint32_t* status, uint32_t cap) {
-  __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_ticket, s_excl;
+  __shared__ uint64_t s_w64[4];
+  __shared__ uint32_t s_ticket;
+  __shared__ uint64_t s_excl;
   const int t = threadIdx.x;
   const int nblk = (n + kScanItems - 1) / kScanItems;
   if (n == 0) {
@@ -273,7 +302,7 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
   // each thread owns 16 consecutive items so that the scan is in order
   constexpr int PER = kScanItems / 256;
   uint32_t v[PER];
-  uint32_t sum = 0;
+  uint64_t sum = 0;
   const int j0 = b * kScanItems + t * PER;
   if (j0 + PER <= n) {
     // whole run in range: all index loads, then all gathers, in flight together
@@ -295,8 +324,9 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
   }
 #pragma unroll
   for (int r = 0; r < PER; ++r) sum += v[r];
-  uint32_t tot;
-  uint32_t off = block_excl_scan<256>(sum, s_w, &tot);
+  uint64_t tot;
+  uint64_t off = block_excl_scan64(sum, s_w64, &tot);
+  const uint32_t tot32 = sat32(tot);
   if (t < 64) {
     // wave 0: publish this block's sum, then read 64 earlier blocks per
     // round trip (lane i: block k - 1 - i), nearest first, up to the nearest
@@ -304,8 +334,8 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
     const int lane = t;
     uint64_t* mine = look + b;
     if (lane == 0)
-      __hip_atomic_store(mine, (b == 0 ? kScanInc : kScanAgg) | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
+      __hip_atomic_store(mine, (b == 0 ? kScanInc : kScanAgg) | tot32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
     if (b > 0) {
       uint32_t spins = 0;
       for (int k = b; k > 0;) {
@@ -316,9 +346,9 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
         const int fi = inc ? __builtin_ctzll(inc) : 64;    // nearest inclusive prefix
         const int fn = none ? __builtin_ctzll(none) : 64;  // nearest block not yet published
         const int used = fn <= fi ? fn : fi + 1;           // lanes [0, used) are added
-        uint32_t x = lane < used ? (uint32_t)v : 0u;
+        uint64_t x = lane < used ? (uint64_t)(uint32_t)v : 0ull;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) x += (uint32_t)__shfl_xor((int)x, o, 64);
+        for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o, 64);
         excl += x;
         k -= used;
         if (fi < fn) break;  // reached an inclusive prefix
@@ -331,12 +361,12 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
         }
       }
       if (lane == 0)
-        __hip_atomic_store(mine, kScanInc | (uint32_t)(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine, kScanInc | sat32(excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lane == 0) {
       s_excl = excl;
       if (b == nblk - 1) {
-        const uint32_t total = excl + tot;
+        const uint32_t total = sat32(excl + tot);
         offs[n] = total;
         status[kStPairs] = total;
         if (total > cap) status[kStOverflow] = 1u;
@@ -348,7 +378,7 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
     const int j = j0 + r;
-    if (j < n) offs[j] = off;
+    if (j < n) offs[j] = sat32(off);
     off += v[r];
   }
 }
@@ -382,9 +412,15 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, 
     }
   }
   const uint32_t start = (uint32_t)__shfl((int)o, 0, 64);
-  uint32_t end = j < n ? o + cnt : 0u;
+  // the wave's pairs end at its last surfel's offset + count, clamped to the
+  // capacity (offsets saturate at 2^32 - 1 on overflow, so the sum is 64-bit)
+  uint64_t end64 = j < n ? (uint64_t)o + cnt : 0ull;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, d, 64));
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t y = __shfl_xor(end64, d, 64);
+    end64 = y > end64 ? y : end64;
+  }
+  const uint32_t end = (uint32_t)(end64 < cap ? end64 : cap);
   const uint32_t lo = j < n ? o - start : 0xFFFFFFFFu;  // local first pair (invalid lanes sort last)
   const bool wrap = (r.w >> 30) & 1;
   const int ncol = cnt == 0 ? 1 : (wrap ? (n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1));
@@ -405,7 +441,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, 
     const int ntx = __shfl(n_tx, src, 64);
     const int rb = __shfl(row0, src, 64);
     const uint32_t q = start + k;
-    if (q < end && q < cap) {
+    if (q < end) {
       const uint32_t loc = k - ls;
       const uint32_t ty = loc / (uint32_t)nc;
       int tx = x0 + (int)(loc - ty * (uint32_t)nc);
@@ -514,11 +550,12 @@ __global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ ptile, const uint32_t* __restrict__ count,
-                                                uint32_t cap, uint2* __restrict__ ranges) {
+                                                uint32_t cap, uint2* __restrict__ ranges, uint32_t n_tiles) {
   uint32_t n = *count;
   n = n < cap ? n : cap;
   for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const uint32_t t = ptile[i];
+    if (t >= n_tiles) continue;  // only a pair slot no emission wrote can hold such an id
     if (i == 0 || ptile[i - 1] != t) ranges[t].x = i;
     if (i + 1 == n || ptile[i + 1] != t) ranges[t].y = i + 1;
   }
@@ -629,7 +666,8 @@ void launch_build_items(const SegScanArgs& a, hipStream_t st) {
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st) {
   launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2ull * n_tiles, st);
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, st, ptile, count, cap, ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, st, ptile, count, cap, ranges,
+                     (uint32_t)n_tiles);
 }
 
 void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipStream_t st) {

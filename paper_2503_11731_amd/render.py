@@ -173,7 +173,8 @@ class Renderer:
         n = len(self.sensors)
         out = dict(pairs=list(st.pairs[:n]), overflow=bool(st.overflow), n_visible=list(st.n_visible[:n]),
                    fp64_pairs=int(st.fp64_pairs), evaluated=int(st.evaluated), composited=int(st.composited),
-                   work_items=int(st.work_items), segments=int(st.segments), rc=rc)
+                   work_items=int(st.work_items), segments=int(st.segments),
+                   graph_replays=int(st.graph_replays), rc=rc)
         return out
 
     def set_timing(self, max_records: int):

@@ -77,6 +77,67 @@ def lidar_bad_rays(got, ref):
     return bad
 
 
+ALT_TOL = 1e-4      # relative distance to a threshold below which a decision is flagged and verified both ways
+
+
+def oracle_vector(ref, kind):
+    """Oracle outputs as [C, R] in the device channel order."""
+    if kind == "pinhole":
+        v = np.concatenate([ref["rgb"].reshape(3, -1), ref["depth"].reshape(1, -1), ref["normal"].reshape(3, -1),
+                            ref["alpha"].reshape(1, -1)])
+    else:
+        v = np.stack([ref["range"].reshape(-1), ref["intensity"].reshape(-1), ref["alpha"].reshape(-1)])
+    return v
+
+
+def _tolerance(v, kind):
+    """Per-entry tolerance of output vectors v [C, ...]: 1e-4 absolute, depth/range 1e-4 relative to max(1, |v|)."""
+    t = np.full(v.shape, TOL)
+    d = 3 if kind == "pinhole" else 0
+    t[d] = TOL_DEPTH * np.maximum(1.0, np.abs(v[d]))
+    return t
+
+
+def verify(got, ref, kind):
+    """Per-ray verification of device outputs got [C, R] against the oracle run with
+    `alternatives`: a ray passes when every channel is within tolerance of the
+    oracle's nominal output or of one of the alternatives of its near-threshold
+    decisions.  Returns counts and per-channel errors against the matched candidate."""
+    g = got.astype(np.float64).reshape(got.shape[0], -1)
+    nom = oracle_vector(ref, kind)
+    err = np.abs(g - nom)
+    ok = (err <= _tolerance(nom, kind)).all(0)
+    best = err.copy()
+    alt_only = 0
+    for r, vals in zip(ref["alts"]["rays"], ref["alts"]["values"]):
+        if ok[r]:
+            continue
+        e = np.abs(g[:, r][None] - vals)
+        good = (e <= _tolerance(vals.T, kind).T).all(1)
+        if good.any():
+            ok[r] = True
+            alt_only += 1
+            best[:, r] = e[np.argmax(good)]
+    unver = np.zeros(ok.shape, bool)
+    unver[ref["unverified"]] = True
+    bad = ~ok & ~unver
+    names = (["r", "g", "b", "depth", "nx", "ny", "nz", "alpha"] if kind == "pinhole" else ["range", "intensity", "alpha"])
+    d = 3 if kind == "pinhole" else 0
+    rel = best.copy()
+    rel[d] = best[d] / np.maximum(1.0, np.abs(nom[d]))
+    m = ~unver
+    errs = {n: float(rel[c][m].max(initial=0.0)) for c, n in enumerate(names)}
+    return dict(rays=int(ok.size), flagged=int(len(ref["alts"]["rays"])), alt_only=alt_only,
+                unverified=int(unver.sum()), bad=int(bad.sum()), bad_rays=np.nonzero(bad)[0][:8].tolist(),
+                errs=errs)
+
+
+def assert_verified(v, what=""):
+    """Every verifiable ray matches; rays with too many near-threshold decisions to verify are at most 1e-4 of all."""
+    assert v["bad"] == 0, (what, v)
+    assert v["unverified"] <= 1e-4 * v["rays"], (what, v)
+
+
 def within(errs):
     return all(v <= (TOL_DEPTH if k in ("depth", "range") else TOL) for k, v in errs.items())
 

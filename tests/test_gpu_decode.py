@@ -105,35 +105,36 @@ def test_decode_backward_parity(kind):
 
 
 def test_training_step_gradient_chain():
-    """Decode -> render -> L1 loss -> adjoint render -> adjoint decode, vs the oracle's autograd chain."""
+    """Decode -> render -> L1 loss -> adjoint render -> adjoint decode, vs the oracle's autograd chain.
+
+    dL/d(rgb) is the L1 gradient sign(O - target) / n of the oracle's own forward output, given to both sides."""
     _say("training step chain")
     sc = S.corridor_anchors(seed=31, n_anchors=400, sensor_kind="pinhole", z_lo=2, z_hi=14)
     cam = S.pinhole(64, 48, 48.0)
     target = np.random.default_rng(2).uniform(0, 1, (3, 48, 64))
-    dec = gs.Decoder.from_gen(sc, DEV)
-    sp = gs.poses_tensor(cam["pose"], DEV)
-    gp = gs.poses_tensor(sc.group_poses, DEV)
     n = sc.n_anchors * sc.k
-    r = gs.Renderer([gs.SceneShape(n, -1, False, (0, n))], [cam], opts=gs.PRODUCTION, device=DEV)
-    d = dec.forward(sp[0], gp)
-    (o,) = r.forward([d], sp, gp)
-    tgt = torch.from_numpy(target.astype(np.float32)).to(DEV)
-    g_rgb = torch.sign(o[:3] - tgt) / tgt.numel()
-    go = torch.zeros_like(o)
-    go[:3] = g_rgb
-    (gsurf,) = r.backward([d], sp, gp, [o], [go])
-    ga = dec.backward(sp[0], gp, gsurf)
-    torch.cuda.synchronize()
-    # oracle chain with the same dL/d(rgb) (the sign of the GPU residual)
+    # oracle chain
     poses_s = np.stack([spec32.compose_pose(cam["pose"], g) for g in sc.group_poses])
     leaves = {k: torch.as_tensor(v).requires_grad_(True) for k, v in _anchor_dict(sc).items() if k != "group_offsets"}
     ref_dec = odec.decode(_anchor_dict(sc), sc.mlps, poses_s, "pinhole", params=leaves)
     sc32 = {k: v.detach().numpy().astype(np.float32) for k, v in ref_dec.items()}
     sc32.update(group_offsets=np.array([0, n], np.int32), group_poses=sc.group_poses)
-    res = raster.render(sc32, cam, raster.make_opts(), params=ref_dec,
-                        grad_out={"rgb": g_rgb.cpu().numpy().astype(np.float64)})
-    out_ref = res["rgb"]
-    assert np.abs(o[:3].cpu().numpy() - out_ref).max() < 1e-4
+    fwd = raster.render(sc32, cam, raster.make_opts(), params={k: v.detach() for k, v in ref_dec.items()})
+    g_rgb = np.sign(fwd["rgb"] - target) / target.size
+    res = raster.render(sc32, cam, raster.make_opts(), params=ref_dec, grad_out={"rgb": g_rgb})
+    # device chain with the same dL/d(rgb)
+    dec = gs.Decoder.from_gen(sc, DEV)
+    sp = gs.poses_tensor(cam["pose"], DEV)
+    gp = gs.poses_tensor(sc.group_poses, DEV)
+    r = gs.Renderer([gs.SceneShape(n, -1, False, (0, n))], [cam], opts=gs.PRODUCTION, device=DEV)
+    d = dec.forward(sp[0], gp)
+    (o,) = r.forward([d], sp, gp)
+    go = torch.zeros_like(o)
+    go[:3] = torch.from_numpy(g_rgb.astype(np.float32)).to(DEV)
+    (gsurf,) = r.backward([d], sp, gp, [o], [go])
+    ga = dec.backward(sp[0], gp, gsurf)
+    torch.cuda.synchronize()
+    assert np.abs(o[:3].cpu().numpy() - fwd["rgb"]).max() < 1e-4
     leaf_keys = ["xyz", "scaling", "offsets", "feat"]
     gl = torch.autograd.grad(sum((ref_dec[k] * torch.as_tensor(res["grads"][k])).sum() for k in res["grads"]),
                              [leaves[k] for k in leaf_keys])
