@@ -16,8 +16,11 @@ Plain definition of what the renderer computes, per ray (Sec. III-A):
    squared distance to the projected centre in units of sigma (pinhole:
    pixels; LiDAR: chord to the centre direction in azimuth steps).
 5. The candidate set of a ray is every visible surfel whose support contains
-   it: rho_hat <= cutoff^2, hit depth (camera z / LiDAR range) > z_near.
+   it: rho_hat <= cutoff^2, depth (camera z / LiDAR range) > z_near.
    Candidates are ordered by the FP32 depth key, ties by surfel index.
+   The depth of a pair is that of its hit point when rho itself is used and
+   that of the surfel centre when the low-pass term is smaller (the filter's
+   degenerate, edge-on case, where the hit point is not meaningful).
 6. Front-to-back alpha compositing (Sec. II, splatting): alpha =
    min(alpha_max, o exp(-rho_hat/2)); skip if alpha < alpha_min; stop before a
    surfel that would take T (1 - alpha) below T_min; w = alpha T.
@@ -271,7 +274,8 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     compositing decisions to the decision's threshold ('margin').
     alternatives: a relative tolerance tol.  Every decision of a ray that lies
     within tol of its threshold -- a pair entering or leaving the support
-    (cutoff, z_near), the alpha_min skip, the T_min stop -- is flagged, and the
+    (cutoff, z_near), the alpha_min skip, the T_min stop, the choice between
+    rho and the low-pass term (which sets the pair's depth) -- is flagged, and the
     result also holds, for every ray with 1..max_flags flags, the outputs the
     definition gives when any non-empty subset of those decisions goes the
     other way ('alts': rays, values [n_alt, C] in the channel order of the
@@ -368,8 +372,13 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
         result["margin"] = _margins(sol, rp, pos, R, K, alpha.detach(), test, skip, considered, opts,
                                     sensor).reshape(shape)
     if alternatives is not None:
+        with torch.no_grad():
+            alt = dict(alpha=grid(torch.clamp(o.detach() * torch.exp(-0.5 * sol["alt"]["rho_hat"]),
+                                              max=opts["alpha_max"])),
+                       present=grid(sol["alt"]["support"]), depth=grid(sol["alt"]["depth"]),
+                       ch=0 if lidar else 3)
         result.update(_alternatives(sol, rp, pos, R, K, alpha.detach(), present, listed, feat.detach(), bg, test,
-                                    skip, considered, opts, tol, max_flags, sensor))
+                                    skip, considered, opts, tol, max_flags, sensor, alt))
     if want_grad:
         total = 0.0
         for k_, g in grad_out.items():
@@ -431,9 +440,19 @@ def _accumulate(active, alpha, feat, bg):
 
 
 def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
-    """Per-pair ray-splat solve (Eq. 2): (u, v), rho_hat, hit depth, support
-    mask, and `near`: the support decision lies within tol (relative) of the
-    cutoff or z_near threshold."""
+    """Per-pair ray-splat solve (Eq. 2): (u, v), rho_hat, depth, support mask,
+    and `near`: the support decision, or the choice between the surfel's own
+    rho and the low-pass term, lies within tol (relative) of its threshold.
+
+    Depth (camera z, LiDAR range) is that of the hit point x = M (u, v, 1)
+    when rho itself is used.  When the low-pass term is smaller, the pair is
+    the degenerate line projection the filter stands in for (Sec. II): the
+    plane is seen (nearly) edge-on, its hit point is not meaningful and can
+    lie arbitrarily far along the ray, so the pair takes the depth of the
+    surfel centre (camera mu_z, LiDAR |mu|), as the cited 2DGS filter does.
+    The same depth decides the z_near test.  `alt` holds the pair's rho_hat,
+    depth and support under the other choice.
+    """
     rp_t = torch.as_tensor(rp)
     sp_t = torch.as_tensor(sp)
     M = sq["M"][sp_t]  # [P,3,3]
@@ -453,7 +472,8 @@ def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
     mu = sq["mu_s"][sp_t]
     lp = opts["lp_inv_sigma2"]
     if sensor["kind"] == "pinhole":
-        depth = X[:, 2]
+        depth_hit = X[:, 2]
+        depth_c = mu[:, 2]
         if opts["lowpass"]:
             pcx = sensor["fx"] * mu[:, 0] / mu[:, 2] + sensor["cx"]
             pcy = sensor["fy"] * mu[:, 1] / mu[:, 2] + sensor["cy"]
@@ -462,30 +482,49 @@ def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
             rho_lp = lp * (dx * dx + dy * dy)
     else:
         d = rays_t["d"][rp_t]
-        depth = (d * X).sum(1)
+        depth_hit = (d * X).sum(1)
+        rn = torch.linalg.norm(mu, dim=1)
+        depth_c = rn
         if opts["lowpass"]:
             step = 2.0 * math.pi / int(sensor["width"])
-            mh = mu / torch.linalg.norm(mu, dim=1, keepdim=True)
+            mh = mu / rn[:, None]
             dd = d - mh
             rho_lp = lp * (dd * dd).sum(1) / (step * step)
+    c2, zn = opts["cutoff2"], sensor["z_near"]
     if opts["lowpass"]:
         use_rho = rho <= rho_lp
         rho_hat = torch.where(use_rho, rho, rho_lp)
+        depth = torch.where(use_rho, depth_hit, depth_c)
     else:
         rho_hat = rho
-    c2, zn = opts["cutoff2"], sensor["z_near"]
+        depth = depth_hit
     support = ok & (rho_hat <= c2) & (depth > zn)
     with torch.no_grad():
         near = ok & (((rho_hat - c2).abs() <= tol * c2) | ((depth - zn).abs() <= tol * zn))
+        if opts["lowpass"]:
+            big = torch.maximum(rho, rho_lp)
+            d_lp = torch.where(big > 0, (rho - rho_lp).abs() / torch.where(big > 0, big, torch.ones_like(big)),
+                               torch.full_like(big, math.inf))
+            near_lp = ok & (d_lp <= tol)
+            rho_alt = torch.where(use_rho, rho_lp, rho).detach()
+            depth_alt = torch.where(use_rho, depth_c, depth_hit).detach()
+            support_alt = ok & (rho_alt <= c2) & (depth_alt > zn)
+            near = near | (near_lp & (support_alt | ((rho_alt - c2).abs() <= tol * c2) |
+                                      ((depth_alt - zn).abs() <= tol * zn)))
+        else:
+            d_lp = torch.full_like(rho, math.inf)
+            rho_alt, depth_alt, support_alt = rho_hat.detach(), depth.detach(), support.detach()
         if tol <= 0.0:
             near = torch.zeros_like(near)
-    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support, near=near)
+    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support, near=near, d_lp=d_lp,
+                alt=dict(rho_hat=rho_alt, depth=depth_alt, support=support_alt))
 
 
 def _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor):
     """Per listed pair [R, K]: relative distance of its support decision
-    (cutoff, z_near), its alpha_min skip and (non-skipped pairs) its T_min
-    stop test to the threshold; inf where the rule is off."""
+    (cutoff, z_near), its alpha_min skip, (non-skipped pairs) its T_min stop
+    test and its choice between rho and the low-pass term to the threshold;
+    inf where the rule is off."""
     rp_t, pos_t = torch.as_tensor(rp), torch.as_tensor(pos)
     with torch.no_grad():
         rh = sol["rho_hat"].detach()
@@ -493,30 +532,35 @@ def _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor):
         c2, zn = opts["cutoff2"], sensor["z_near"]
         m_sup = torch.minimum((rh - c2).abs() / c2, (dep - zn).abs() / max(zn, 1e-300))
         d_sup = torch.full((R, K), math.inf, dtype=DT).index_put((rp_t, pos_t), m_sup)
+        d_lp = torch.full((R, K), math.inf, dtype=DT).index_put((rp_t, pos_t), sol["d_lp"].detach())
         inf = torch.full((R, K), math.inf, dtype=DT)
         am, tm = opts["alpha_min"], opts["T_min"]
         d_amin = (alpha - am).abs() / am if am > 0 else inf
         d_stop = torch.where(skip, inf, (test - tm).abs() / tm) if tm > 0 else inf
-    return d_sup, d_amin, d_stop
+    return d_sup, d_amin, d_stop, d_lp
 
 
 def _margins(sol, rp, pos, R, K, alpha, test, skip, considered, opts, sensor):
     """Per ray: the smallest relative distance of any decision of a considered
     pair (up to and including the stopping one) to its threshold."""
-    d_sup, d_amin, d_stop = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
-    m = torch.minimum(torch.minimum(d_sup, d_amin), d_stop)
+    d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
+    m = torch.minimum(torch.minimum(d_sup, d_amin), torch.minimum(d_stop, d_lp))
     m = torch.where(considered, m, torch.full_like(m, math.inf))
     return m.min(1).values.numpy() if K > 0 else np.full(R, np.inf)
 
 
 def _alternatives(sol, rp, pos, R, K, alpha, present, listed, feat, bg, test, skip, considered, opts, tol,
-                  max_flags, sensor):
+                  max_flags, sensor, alt):
     """Outputs of every ray under each non-empty subset of its near-threshold
     decisions taken the other way (see render's `alternatives`).  Flag kinds:
-    0 support (cutoff or z_near), 1 alpha_min, 2 stop."""
-    d_sup, d_amin, d_stop = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
+    0 support (cutoff or z_near), 1 alpha_min, 2 stop, 3 the choice between
+    rho and the low-pass term (the other choice gives the pair the alpha,
+    depth and support in `alt`: [R, K] grids 'alpha', 'present', 'depth', and
+    the depth channel index 'ch')."""
+    d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
     with torch.no_grad():
-        fm = [considered & (d_sup <= tol), considered & (d_amin <= tol), considered & (d_stop <= tol)]
+        fm = [considered & (d_sup <= tol), considered & (d_amin <= tol), considered & (d_stop <= tol),
+              considered & (d_lp <= tol)]
         n_flags = sum(f.to(torch.int64) for f in fm).sum(1)
     nf = n_flags.numpy()
     rays = np.nonzero((nf >= 1) & (nf <= max_flags))[0]
@@ -524,14 +568,19 @@ def _alternatives(sol, rp, pos, R, K, alpha, present, listed, feat, bg, test, sk
     values, kinds = [], []
     for r in rays:
         r_t = torch.as_tensor([int(r)])
-        flags = [(kd, int(k)) for kd in range(3) for k in torch.nonzero(fm[kd][r]).reshape(-1).tolist()]
-        a_r, p_r, f_r = alpha[r_t], present[r_t], feat[r_t]
+        flags = [(kd, int(k)) for kd in range(4) for k in torch.nonzero(fm[kd][r]).reshape(-1).tolist()]
         alts = []
         for subset in range(1, 1 << len(flags)):
+            a_r, p_r, f_r = alpha[r_t].clone(), present[r_t].clone(), feat[r_t].clone()
             fl = [torch.zeros((1, K), dtype=torch.bool) for _ in range(3)]
             for b, (kd, k) in enumerate(flags):
                 if (subset >> b) & 1:
-                    fl[kd][0, k] = True
+                    if kd == 3:
+                        a_r[0, k] = alt["alpha"][r, k]
+                        p_r[0, k] = alt["present"][r, k]
+                        f_r[0, k, alt["ch"]] = alt["depth"][r, k]
+                    else:
+                        fl[kd][0, k] = True
             act = _decide(a_r, p_r, opts, flips=fl)[0]
             alts.append(_accumulate(act, a_r, f_r, bg)[0][0].numpy())
         values.append(np.stack(alts))

@@ -144,12 +144,13 @@ def test_alternatives_of_a_random_scene_agree_with_margins():
     np.testing.assert_array_equal(nf > 0, res["margin"] <= 1e-2)
     # one alternative per non-empty subset of flags; flipping an alpha_min or a
     # stop decision always changes the ray (a support flip may not: in
-    # production alpha at the cutoff is below alpha_min)
+    # production alpha at the cutoff is below alpha_min; nor may the low-pass
+    # choice of a pair outside the support either way)
     nom = np.concatenate([res["rgb"], res["depth"][None], res["normal"], res["alpha"][None]]).reshape(8, -1)
     n_checked = 0
     for r, vals, kinds in zip(res["alts"]["rays"], res["alts"]["values"], res["alts"]["kinds"]):
         assert vals.shape[0] == 2 ** nf.reshape(-1)[r] - 1
-        if 0 not in kinds:
+        if 0 not in kinds and 3 not in kinds:
             assert (np.abs(vals - nom[:, r][None]).max(1) > 0).all()
             n_checked += 1
     assert n_checked > 0
