@@ -91,11 +91,14 @@ typedef struct gs_sensor_desc {
 /* Compositing rules (front-to-back alpha blending with the 2DGS low-pass
  * filter): alpha = min(alpha_max, o * exp(-rho_hat / 2)) with
  * rho_hat = min(u^2 + v^2, rho_lp) when `lowpass` is set; a ray-surfel pair
- * contributes iff rho_hat <= cutoff2, the hit depth (range) > z_near and
+ * contributes iff rho_hat <= cutoff2, its depth (range) > z_near and
  * alpha >= alpha_min; a ray stops before the surfel that would take its
  * transmittance T (1 - alpha) below T_min.  rho_lp is lp_inv_sigma2 times
  * the squared distance to the projected centre in pixels (camera) or the
- * squared chord to the centre direction in azimuth steps (LiDAR). */
+ * squared chord to the centre direction in azimuth steps (LiDAR).  A pair's
+ * depth is that of the ray's hit point on the surfel plane when u^2 + v^2 is
+ * used, and that of the surfel centre (camera mu_z, LiDAR |mu|) when rho_lp
+ * is smaller (the filter's degenerate, edge-on case). */
 typedef struct gs_render_opts {
   float alpha_min;       /* e.g. 1/255; 0 disables the skip test          */
   float alpha_max;       /* e.g. 0.99                                     */

@@ -246,6 +246,9 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   const float rl = K.lp * fmaf(dx, dx, dy * dy);
   const bool lp_used = K.lowpass && !(rho <= rl);
   const float rho_hat = lp_used ? rl : rho;
+  // a pair admitted by the low-pass term (edge-on or sub-pixel surfel) takes
+  // the centre's depth: its plane hit is not meaningful there
+  if (lp_used) z = q2.x;
   ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
   float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q2.y));
   const bool clamped = alpha > K.alpha_max;
@@ -427,8 +430,10 @@ struct CamRay {
     const float g_lp = e.lp_used ? g_rhohat : 0.0f;
     const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
     const float gh0 = gu * e.r, gh1 = gv * e.r;
-    const float gh2 = -(gu * e.u + gv * e.v + gz * e.z) * e.r;
-    gr[8] = gz * e.r;
+    // depth = mu_z h'2^-1 at the plane hit, mu_z itself for a low-pass pair
+    const float gzh = e.lp_used ? 0.0f : gz;
+    const float gh2 = -(gu * e.u + gv * e.v + gzh * e.z) * e.r;
+    gr[8] = e.lp_used ? gz : gz * e.r;
     gr[0] = gh0 * e.dx;
     gr[1] = gh0 * e.dy;
     gr[2] = gh1 * e.dx;
@@ -490,6 +495,7 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   const float rl = K.lp * fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
   const bool lp_used = K.lowpass && !(rho <= rl);
   const float rho_hat = lp_used ? rl : rho;
+  if (lp_used) z = q3.x;  // the centre's range |mu| (see eval_pinhole)
   ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
   float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q3.y));
   const bool clamped = alpha > K.alpha_max;
@@ -508,13 +514,18 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   return ok;
 }
 
-// Unit ray direction of LiDAR column c, beam j from the FP32 tables, in FP64.
+// Ray direction of LiDAR column c, beam j, in FP64: the line where the two
+// planes of Eq. 5 built from the FP32 tables meet, h_u x h_v =
+// (ce ca, ce sa, se (ca^2 + sa^2)).  The rounded tables make ca^2 + sa^2
+// differ from 1 by ~1e-7; a surfel met nearly edge-on (the low-pass filter
+// admits such pairs) amplifies that into its hit range by 1/h'2, so the
+// solve must use the planes' own line, not the nominal unit beam.
 __device__ inline void lidar_dir(const SensorK& S, int c, int j, double* d) {
   const float* t = S.tab;
   const double ce = t[S.H + j], se = t[2 * S.H + j], ca = t[3 * S.H + c], sa = t[3 * S.H + S.W + c];
   d[0] = ce * ca;
   d[1] = ce * sa;
-  d[2] = se;
+  d[2] = se * (ca * ca + sa * sa);
 }
 
 struct LidarRay {
@@ -694,8 +705,9 @@ struct LidarRay {
     const float g_lp = e.lp_used ? g_rhohat : 0.0f;
     const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
     const float gh0 = gu * e.r, gh1 = gv * e.r;
-    const float gh2 = -(gu * e.u + gv * e.v + grange * e.z) * e.r;
-    gr[12] = grange * e.r;
+    const float grh = e.lp_used ? 0.0f : grange;
+    const float gh2 = -(gu * e.u + gv * e.v + grh * e.z) * e.r;
+    gr[12] = e.lp_used ? grange : grange * e.r;
     const float dd[3] = {e.dx, e.dy, e.dz3};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
