@@ -216,6 +216,42 @@ def test_decode_feature_relu_and_view_direction_routing():
         assert out["opacity"][a * K + 0].item() == pytest.approx(sig(max(d[0], 0.0)), abs=1e-14)
 
 
+def test_decode_view_direction_with_turned_sensor_and_group():
+    # Sensor at world centre c with a general rotation, group turned and moved
+    # by G = [Rg | tg]: the decoder's view direction is the unit vector from
+    # the sensor centre to the anchor in the group's frame, with the centre
+    # there at Rg^T (c - tg).  W1 routes d_x, d_y, d_z + 2 to hidden units
+    # 0-2 and W2 sends unit k to offset k's opacity, so sigmoid^-1(opacity) - 2
+    # reads the direction back.
+    an = _anchors(A=5, K=3, seed=6)
+    K, J = 3, 10
+    w1 = np.zeros((32, 35))
+    b1 = np.zeros(32)
+    for c in range(3):
+        w1[c, 32 + c] = 1.0
+        b1[c] = 2.0
+    w2 = np.zeros((K * J, 32))
+    for k in range(3):
+        w2[k * J + 0, k] = 1.0
+    mlp = dict(w1=w1, b1=b1, w2=w2, b2=np.zeros(K * J))
+    from scipy.spatial.transform import Rotation
+    from oracle import spec32
+    c_w = np.array([1.5, -0.7, 2.0])
+    Rv = Rotation.from_euler("zyx", [30, -50, 20], degrees=True).as_matrix()
+    V = np.concatenate([Rv, (-Rv @ c_w)[:, None]], 1).astype(F32)
+    Rg = Rotation.from_euler("xyz", [-15, 65, 40], degrees=True).as_matrix()
+    tg = np.array([0.4, 0.2, -1.1])
+    G = np.concatenate([Rg, tg[:, None]], 1).astype(F32)
+    P = spec32.compose_pose(V, G)[None]
+    out = odec.decode(an, [mlp], P, "pinhole")
+    op = out["opacity"].numpy().reshape(5, K)
+    d_got = np.log(op / (1 - op)) - 2.0
+    c_g = Rg.T @ (c_w - tg)
+    for a in range(5):
+        d = an["xyz"][:, a] - c_g
+        np.testing.assert_allclose(d_got[a], d / np.linalg.norm(d), atol=2e-6)
+
+
 def test_decode_groups_use_their_own_mlp_and_pose():
     an = _anchors(A=6, K=2, seed=4)
     an["group_offsets"] = np.array([0, 4, 6])

@@ -218,6 +218,70 @@ def test_rigid_invariance_group_pose_vs_sensor_pose():
         np.testing.assert_allclose(a[ch], b[ch], rtol=2e-5, atol=2e-5)
 
 
+def test_rigid_invariance_holds_for_sh_colour():
+    # The SH colour is evaluated at the view direction in the surfel group's
+    # own frame: an asset turned by G and seen by the camera equals the
+    # unturned asset seen by the camera moved by G (camera pose V G), for
+    # degree-3 coefficients.  A world-frame direction would break this.
+    rng = np.random.default_rng(21)
+    sc = _random_scene(7, 60)
+    sc.pop("rgb")
+    sc["sh"] = rng.normal(0.0, 0.3, (16 * 3, 60)).astype(F32)
+    sc["sh_degree"] = 3
+    G = np.eye(4)
+    G[:3, :3] = Rotation.from_euler("xyz", [25, -40, 70], degrees=True).as_matrix()
+    G[:3, 3] = [0.2, 0.1, -0.3]
+    V = np.eye(4)
+    V[:3, :3] = Rotation.from_euler("y", 15, degrees=True).as_matrix()
+    V[:3, 3] = [0.1, 0.0, 0.4]
+    Gi = np.linalg.inv(G)
+    # asset turned by G in a world seen through V G^-1  ==  the plain asset seen through V
+    turned = dict(sc, group_poses=G[None, :3, :].astype(F32))
+    cam_t = dict(SMALL_CAM, pose=(V @ Gi)[:3, :].astype(F32))
+    cam_p = dict(SMALL_CAM, pose=V[:3, :].astype(F32))
+    a = raster.render(sc, cam_p, raster.make_opts(raster.STRICT))
+    b = raster.render(turned, cam_t, raster.make_opts(raster.STRICT))
+    assert a["alpha"].max() > 0.5
+    for ch in ("rgb", "depth", "normal", "alpha"):
+        np.testing.assert_allclose(a[ch], b[ch], rtol=2e-5, atol=2e-5)
+    # and the colour does depend on the direction: the same scene seen through
+    # the turned camera without turning the asset differs
+    c = raster.render(sc, cam_t, raster.make_opts(raster.STRICT))
+    assert np.abs(c["rgb"] - a["rgb"]).max() > 1e-2
+
+
+def test_sh_colour_uses_the_view_direction_in_the_group_frame():
+    # Degree-1 SH with only the Y_1,0 = sqrt(3 / 4 pi) z coefficients set:
+    # colour = 0.5 + c sqrt(3 / 4 pi) d_z, with d the unit direction from the
+    # camera centre to the surfel expressed in the group's frame.  The camera
+    # (centre c_w, general rotation) sees the surfel centre on a pixel's ray,
+    # where alpha = o, so rgb / alpha is the colour.  Sensor-frame or
+    # world-frame directions give other values.
+    c_w = np.array([0.3, -0.2, -0.5])
+    Rv = Rotation.from_euler("zyx", [20, -35, 10], degrees=True).as_matrix()
+    V = np.concatenate([Rv, (-Rv @ c_w)[:, None]], 1)
+    Rg = Rotation.from_euler("xyz", [50, 30, -70], degrees=True).as_matrix()
+    tg = np.array([0.5, 0.1, 0.2])
+    G = np.concatenate([Rg, tg[:, None]], 1)
+    i, j, z = 20, 15, 4.0
+    p_s = np.array([(i + 0.5 - SMALL_CAM["cx"]) / SMALL_CAM["fx"] * z, (j + 0.5 - SMALL_CAM["cy"]) / SMALL_CAM["fy"] * z, z])
+    p_w = Rv.T @ p_s + c_w            # on the ray of pixel (i, j)
+    mu_g = Rg.T @ (p_w - tg)          # the surfel centre in its group's frame
+    coef = np.array([0.6, -0.4, 0.2])
+    sh = np.zeros((4 * 3, 1))
+    sh[2 * 3:2 * 3 + 3, 0] = coef
+    q = quat_wxyz(Rotation.from_euler("xy", [10, -20], degrees=True))
+    sc = surfels([mu_g], q, [0.05, 0.05], [0.8], sh=sh, sh_degree=1)
+    sc["group_poses"] = G[None].astype(F32)
+    out = raster.render(sc, dict(SMALL_CAM, pose=V.astype(F32)), raster.make_opts(raster.STRICT))
+    a = out["alpha"][j, i]
+    assert a == pytest.approx(float(F32(0.8)), rel=1e-5)
+    d = Rg.T @ (p_w - c_w)
+    d /= np.linalg.norm(d)
+    want = 0.5 + coef.astype(F32).astype(np.float64) * math.sqrt(3 / (4 * math.pi)) * d[2]
+    np.testing.assert_allclose(out["rgb"][:, j, i] / a, want, atol=2e-6)
+
+
 def test_lidar_planes_contain_beam_direction():
     # Eq. 5 read with azimuth/elevation roles such that both planes contain
     # the beam: h_u . d = h_v . d = h_u . h_v = 0.
