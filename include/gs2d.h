@@ -361,6 +361,26 @@ gs_status gs_decode_backward(const gs_anchor_set* anchors, const float* sensor_p
                              const float* group_poses, const gs_decoded* grad_in,
                              const gs_anchor_grads* grads, void* scratch, hipStream_t stream);
 
+/* Allocation-free variant of gs_decode_backward, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): same arguments and
+ * results, without `scratch`.  The weight-gradient partials live in a
+ * library-owned device array of GS_DECODE_NOALLOC_SCRATCH_BYTES per GPU
+ * (allocated when the library is loaded, held until the process ends; its
+ * address is looked up once per device on the first call there).  Inputs
+ * whose partials need more (gs_decode_scratch_size) are rejected with
+ * GS_ERR_INVALID_ARG before any launch: with K = 10 offsets that is about
+ * 120k camera (J = 10) or 140k LiDAR (J = 8) anchors in one group (64 per
+ * block, blocks rounded up per group) when weight gradients are requested;
+ * without them there is no limit.  Every call on a GPU shares
+ * that GPU's array: calls that may overlap on one GPU (other streams, other
+ * host threads) race and must be ordered by the caller.  Calls no allocating
+ * routine. */
+#define GS_DECODE_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+gs_status gs_decode_backward_noalloc(const gs_anchor_set* anchors, const float* sensor_pose,
+                                     const float* group_poses, const gs_decoded* grad_in,
+                                     const gs_anchor_grads* grads, hipStream_t stream);
+
 /* Inpainting patch affinity (Sec. III-B, Eq. 6).  For each of `batch` pairs
  * of a target patch (p anchors) and a candidate source patch (q anchors):
  *   out[b][i][j] = exp(z_ij - max_k z_ik) / sum_k exp(z_ik - max_k z_ik),

@@ -78,6 +78,7 @@ class AnchorSet(ctypes.Structure):
 
 
 GS_DECODE_VALU_FP32 = 1
+GS_DECODE_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class Decoded(ctypes.Structure):
@@ -112,6 +113,8 @@ SIGNATURES = [
     ("gs_decode_scratch_size", c_int32, [POINTER(AnchorSet), POINTER(c_size_t)]),
     ("gs_decode_backward", c_int32, [POINTER(AnchorSet), c_void_p, c_void_p, POINTER(Decoded),
                                      POINTER(AnchorGrads), c_void_p, c_void_p]),
+    ("gs_decode_backward_noalloc", c_int32, [POINTER(AnchorSet), c_void_p, c_void_p, POINTER(Decoded),
+                                             POINTER(AnchorGrads), c_void_p]),
     ("gs_affinity", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
 ]
 

@@ -12,7 +12,9 @@
 //            quaternion = raw, centre = x_a + l_a O_k; surfel n = a K + k.
 // Adjoint: FP32 MFMA contractions; per-block partial weight gradients summed
 // in a fixed order by a second kernel.
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "gs_internal.h"
@@ -665,9 +667,19 @@ extern "C" gs_status gs_decode_scratch_size(const gs_anchor_set* anchors, size_t
   return set_error(GS_OK, "");
 }
 
-extern "C" gs_status gs_decode_backward(const gs_anchor_set* anchors, const float* sensor_pose,
-                                        const float* group_poses, const gs_decoded* grad_in,
-                                        const gs_anchor_grads* grads, void* scratch, hipStream_t stream) {
+// Scratch of the allocation-free decode adjoint: the per-block weight-gradient
+// partials, in a file-scope device array (one copy per GPU, held until the
+// process ends).  Host code never passes `scratch` itself to a kernel -- in
+// host code the name is a stand-in, not a device address -- but the address
+// hipGetSymbolAddress returns for the current device.  Every entry the sum
+// kernel reads is written by the same call first, so nothing is cleared.
+static __device__ __align__(256) float scratch[GS_DECODE_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+
+gs_status decode_backward_impl(const gs_anchor_set* anchors, const float* sensor_pose, const float* group_poses,
+                               const gs_decoded* grad_in, const gs_anchor_grads* grads, void* scratch,
+                               size_t scratch_cap, hipStream_t stream, bool check_only = false) {
   DecodeArgs a;
   int nb = 0;
   gs_status s = fill_args(anchors, sensor_pose, group_poses, a, nb);
@@ -687,15 +699,64 @@ extern "C" gs_status gs_decode_backward(const gs_anchor_set* anchors, const floa
   a.g_b1 = grads->b1;
   a.g_w2 = grads->w2;
   a.g_b2 = grads->b2;
-  if (nb > 0 && (a.g_w1 || a.g_b1 || a.g_w2 || a.g_b2) && !scratch)
+  const bool weights = a.g_w1 || a.g_b1 || a.g_w2 || a.g_b2;
+  const int pw = a.K * a.J * (kHidden + 1) + kHidden * (kIn + 1);
+  if (nb > 0 && weights && (size_t)nb * pw * sizeof(float) > scratch_cap)
+    return set_error(GS_ERR_INVALID_ARG, "decode backward: the weight-gradient partials of " + std::to_string(nb) +
+                                             " anchor blocks need " +
+                                             std::to_string((size_t)nb * pw * sizeof(float)) +
+                                             " bytes, more than the scratch buffer's " + std::to_string(scratch_cap));
+  if (check_only) return GS_OK;
+  if (nb > 0 && weights && !scratch)
     return set_error(GS_ERR_INVALID_ARG, "decode backward needs its scratch buffer for weight gradients");
   a.part = static_cast<float*>(scratch);
   if (nb > 0) hipLaunchKernelGGL(k_decode_bwd, dim3(nb), dim3(256), 0, stream, a);
-  if (nb > 0 && (a.g_w1 || a.g_b1 || a.g_w2 || a.g_b2)) {
-    const int pw = a.K * a.J * (kHidden + 1) + kHidden * (kIn + 1);
+  if (nb > 0 && weights)
     hipLaunchKernelGGL(k_decode_wsum, dim3((pw + 63) / 64, a.n_groups), dim3(1024), 0, stream, a);
-  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(GS_ERR_HIP, std::string("decode backward launch: ") + hipGetErrorString(e));
   return set_error(GS_OK, "");
+}
+
+constexpr size_t kNoAllocScratchBytes = GS_DECODE_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gs_status noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(GS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(GS_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(GS_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" gs_status gs_decode_backward(const gs_anchor_set* anchors, const float* sensor_pose,
+                                        const float* group_poses, const gs_decoded* grad_in,
+                                        const gs_anchor_grads* grads, void* scratch, hipStream_t stream) {
+  return decode_backward_impl(anchors, sensor_pose, group_poses, grad_in, grads, scratch, SIZE_MAX, stream);
+}
+
+extern "C" gs_status gs_decode_backward_noalloc(const gs_anchor_set* anchors, const float* sensor_pose,
+                                                const float* group_poses, const gs_decoded* grad_in,
+                                                const gs_anchor_grads* grads, hipStream_t stream) {
+  // arguments and size first (host only), then the array's address on this device
+  const gs_status v = decode_backward_impl(anchors, sensor_pose, group_poses, grad_in, grads, nullptr,
+                                           kNoAllocScratchBytes, stream, /*check_only=*/true);
+  if (v != GS_OK) return v;
+  void* p = nullptr;
+  const gs_status s = noalloc_scratch(&p);
+  if (s != GS_OK) return s;
+  return decode_backward_impl(anchors, sensor_pose, group_poses, grad_in, grads, p, kNoAllocScratchBytes, stream);
 }

@@ -83,7 +83,11 @@ class Decoder:
                                            ctypes.byref(d), _stream()))
         return out
 
-    def backward(self, sensor_pose, group_poses, grad_in: dict, grads: dict | None = None) -> dict:
+    def backward(self, sensor_pose, group_poses, grad_in: dict, grads: dict | None = None,
+                 noalloc: bool = False) -> dict:
+        """Adjoint (+= into grads).  noalloc: use gs_decode_backward_noalloc, which
+        needs no scratch buffer (the library's own per-GPU array holds the
+        weight-gradient partials); nothing is allocated when grads is given."""
         dev = self.xyz.device
         if grads is None:
             z = lambda t: torch.zeros(t.shape, dtype=torch.float32, device=dev)
@@ -95,6 +99,11 @@ class Decoder:
         g = lambda k: L.ptr(grads.get(k))
         ag = L.AnchorGrads(g("xyz"), g("scaling"), g("offsets"), g("feat"), g("w1"), g("b1"), g("w2"), g("b2"))
         s = self._struct()
+        if noalloc:
+            L.check(self.lib.gs_decode_backward_noalloc(ctypes.byref(s), sensor_pose.data_ptr(),
+                                                        group_poses.data_ptr(), ctypes.byref(d), ctypes.byref(ag),
+                                                        _stream()))
+            return grads
         nb = ctypes.c_size_t()
         L.check(self.lib.gs_decode_scratch_size(ctypes.byref(s), ctypes.byref(nb)))
         scratch = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)

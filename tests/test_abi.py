@@ -113,6 +113,35 @@ def test_decode_rejects_invalid_arguments():
 
 
 @need_lib
+def test_noalloc_decode_backward_checks_arguments_and_size_before_any_device_call():
+    # Host-side checks run before the library touches the device: a bad
+    # shape, null gradients, and anchor sets whose weight-gradient partials
+    # exceed the per-GPU array (the fake device addresses are never read).
+    lib = L.load()
+    off = (ctypes.c_int32 * 2)(0, 5)
+    an = L.AnchorSet(5, 0, 0, 1, off, 0, 0, 0, 0, 0, 0, 0, 0, 0)  # k = 0
+    one = ctypes.c_float(0)
+    p1 = ctypes.addressof(one)
+    assert lib.gs_decode_backward_noalloc(ctypes.byref(an), p1, p1, None, None, None) == L.GS_ERR_INVALID_ARG
+    fake = 1 << 20
+    A = 2000 * 64
+    big = (ctypes.c_int32 * 2)(0, A)
+    an = L.AnchorSet(A, 10, 0, 1, big, fake, fake, fake, fake, fake, fake, fake, fake, 0)
+    nb = ctypes.c_size_t()
+    assert lib.gs_decode_scratch_size(ctypes.byref(an), ctypes.byref(nb)) == L.GS_OK
+    assert nb.value == 2000 * 4 * (10 * 10 * 33 + 32 * 36) > L.GS_DECODE_NOALLOC_SCRATCH_BYTES
+    d = L.Decoded(fake, fake, fake, fake, fake, None)
+    assert lib.gs_decode_backward_noalloc(ctypes.byref(an), p1, p1, ctypes.byref(d), None,
+                                          None) == L.GS_ERR_INVALID_ARG
+    g = L.AnchorGrads(None, None, None, None, None, None, fake, None)  # dW2 requested
+    assert lib.gs_decode_backward_noalloc(ctypes.byref(an), p1, p1, ctypes.byref(d), ctypes.byref(g),
+                                          None) == L.GS_ERR_INVALID_ARG
+    buf = ctypes.create_string_buffer(256)
+    lib.gs_last_error(buf, 256)
+    assert b"scratch" in buf.value
+
+
+@need_lib
 def test_affinity_rejects_invalid_arguments_and_launches_nothing_for_empty_sizes():
     lib = L.load()
     buf = (ctypes.c_uint16 * 64)()
