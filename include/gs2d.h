@@ -190,6 +190,7 @@ typedef struct gs_run_status {
   int64_t segments;               /* segments of split tiles                       */
   int64_t graph_replays;          /* forward calls of this plan that replayed a
                                      captured graph (host count, since creation) */
+  int64_t step_launches;          /* gs_plan_launch calls of this plan (host count) */
 } gs_run_status;
 
 /* Pipeline stages, for per-stage timing. */
@@ -270,6 +271,22 @@ gs_status gs_render_backward(gs_plan* plan, const gs_scene* scenes, const float*
 gs_status gs_plan_capture(gs_plan* plan, const gs_scene* scenes, const float* sensor_poses,
                           const float* group_poses, float* const* outputs, void* workspace,
                           hipStream_t stream);
+
+/* Step capture: everything enqueued on `stream` by the calling thread between
+ * gs_plan_begin_capture and gs_plan_end_capture -- this plan's forward and
+ * backward, decode calls, and the caller's own kernels on that stream (a
+ * loss gradient, gradient clears) -- becomes one HIP graph held by the plan,
+ * and gs_plan_launch replays it as one graph launch: a whole simulation or
+ * training step (decode, batched render, loss, adjoint render, adjoint decode)
+ * for the pointers used while capturing.  Inside the capture the calls only
+ * enqueue (no stage timing, no forward-graph replay); the caller must not
+ * allocate device memory or synchronise the stream in between (allocation-
+ * free calls such as gs_decode_backward_noalloc suit it), and must keep every
+ * buffer the graph uses alive while it may be launched.  `stream` must not be
+ * the legacy default stream.  A new capture replaces the previous step. */
+gs_status gs_plan_begin_capture(gs_plan* plan, hipStream_t stream);
+gs_status gs_plan_end_capture(gs_plan* plan, hipStream_t stream);
+gs_status gs_plan_launch(gs_plan* plan, hipStream_t stream);
 
 /* Synchronises `stream`, then reads the workspace's status words. Returns
  * GS_ERR_CAPACITY when a sensor overflowed its pair capacity, and GS_ERR_HIP

@@ -55,7 +55,8 @@ class PlanDesc(ctypes.Structure):
 class RunStatus(ctypes.Structure):
     _fields_ = [("pairs", c_int64 * GS_MAX_SENSORS), ("overflow", c_int32), ("n_visible", c_int32 * GS_MAX_SENSORS),
                 ("fp64_pairs", c_int64), ("evaluated", c_int64), ("composited", c_int64),
-                ("work_items", c_int64), ("segments", c_int64), ("graph_replays", c_int64)]
+                ("work_items", c_int64), ("segments", c_int64), ("graph_replays", c_int64),
+                ("step_launches", c_int64)]
 
 
 STAGES = ("preprocess", "depth_sort", "emit", "tile_sort", "ranges", "blend", "blend_bwd", "splat_bwd")
@@ -103,6 +104,9 @@ SIGNATURES = [
                                     c_void_p]),
     ("gs_render_backward", c_int32, [c_void_p, POINTER(Scene), c_void_p, c_void_p, POINTER(c_void_p),
                                      POINTER(c_void_p), c_void_p, POINTER(SceneGrads), c_void_p]),
+    ("gs_plan_begin_capture", c_int32, [c_void_p, c_void_p]),
+    ("gs_plan_end_capture", c_int32, [c_void_p, c_void_p]),
+    ("gs_plan_launch", c_int32, [c_void_p, c_void_p]),
     ("gs_plan_capture", c_int32, [c_void_p, POINTER(Scene), c_void_p, c_void_p, POINTER(c_void_p), c_void_p,
                                   c_void_p]),
     ("gs_query_status", c_int32, [c_void_p, c_void_p, c_void_p, POINTER(RunStatus)]),

@@ -186,6 +186,11 @@ struct gs_plan {
   void* g_workspace = nullptr;
   hipStream_t g_stream = nullptr;
   int64_t replays = 0;
+  // captured step (any work enqueued between begin and end capture)
+  hipGraphExec_t step_exec = nullptr;
+  hipStream_t step_stream = nullptr;
+  bool step_capturing = false;
+  int64_t step_launches = 0;
 };
 
 namespace {
@@ -514,6 +519,7 @@ gs_status gs_last_error(char* buf, size_t n) {
 void gs_plan_destroy(gs_plan* p) {
   if (!p) return;
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->step_exec) (void)hipGraphExecDestroy(p->step_exec);
   for (hipEvent_t e : p->pool) (void)hipEventDestroy(e);
   for (auto& s : p->sensors)
     if (s.d_tabs) (void)hipFree(s.d_tabs);
@@ -787,7 +793,8 @@ gs_status gs_render_forward(gs_plan* p, const gs_scene* scenes, const float* sen
   if (v != GS_OK) return v;
   for (size_t si = 0; si < p->sensors.size(); ++si)
     if (!outputs[si]) return fail(GS_ERR_INVALID_ARG, "null output for sensor " + std::to_string(si));
-  bool replay = p->graph_exec && workspace == p->g_workspace && sensor_poses == p->g_sensor_poses &&
+  bool replay = !p->step_capturing && p->graph_exec && workspace == p->g_workspace &&
+                sensor_poses == p->g_sensor_poses &&
                 group_poses == p->g_group_poses && st == p->g_stream;
   for (size_t i = 0; replay && i < p->scenes.size(); ++i)
     replay = memcmp(&scenes[i], &p->g_scenes[i], sizeof(gs_scene)) == 0;
@@ -832,6 +839,48 @@ gs_status gs_plan_capture(gs_plan* p, const gs_scene* scenes, const float* senso
   p->g_group_poses = group_poses;
   p->g_workspace = workspace;
   p->g_stream = st;
+  return ok();
+}
+
+gs_status gs_plan_begin_capture(gs_plan* p, hipStream_t st) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "null plan");
+  if (!st) return fail(GS_ERR_INVALID_ARG, "step capture needs a non-default stream");
+  if (p->step_capturing) return fail(GS_ERR_INVALID_ARG, "a step capture of this plan is already open");
+  GS_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  p->step_capturing = true;
+  p->capturing = true;
+  p->step_stream = st;
+  return ok();
+}
+
+gs_status gs_plan_end_capture(gs_plan* p, hipStream_t st) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "null plan");
+  if (!p->step_capturing || st != p->step_stream)
+    return fail(GS_ERR_INVALID_ARG, "no step capture of this plan is open on this stream");
+  p->step_capturing = false;
+  p->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (e != hipSuccess) return fail(GS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  if (p->step_exec) {
+    (void)hipGraphExecDestroy(p->step_exec);
+    p->step_exec = nullptr;
+  }
+  e = hipGraphInstantiate(&p->step_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    p->step_exec = nullptr;
+    return fail(GS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return ok();
+}
+
+gs_status gs_plan_launch(gs_plan* p, hipStream_t st) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "null plan");
+  if (!p->step_exec) return fail(GS_ERR_INVALID_ARG, "no captured step to launch");
+  if (p->step_capturing) return fail(GS_ERR_INVALID_ARG, "cannot launch while capturing");
+  GS_HIP_TRY(hipGraphLaunch(p->step_exec, st));
+  ++p->step_launches;
   return ok();
 }
 
@@ -943,6 +992,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
   }
   out->overflow = over ? 1 : 0;
   out->graph_replays = p->replays;
+  out->step_launches = p->step_launches;
   if (over) return fail(GS_ERR_CAPACITY, "pair capacity exceeded; re-plan with a larger pair_capacity");
   if (stalled) return fail(GS_ERR_HIP, "compositing work queue stalled (walk list inconsistent)");
   if (sort_stall) return fail(GS_ERR_HIP, "sort or scan look-back wait gave up (block statuses inconsistent)");

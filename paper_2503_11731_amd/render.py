@@ -146,6 +146,18 @@ class Renderer:
         L.check(self.lib.gs_plan_capture(self.plan, sc, sensor_poses.data_ptr(), group_poses.data_ptr(), optr,
                                          self.workspace.data_ptr(), _stream()))
 
+    def begin_capture(self):
+        """Start capturing everything enqueued on the current (non-default) stream
+        into this plan's step graph (see gs_plan_begin_capture)."""
+        L.check(self.lib.gs_plan_begin_capture(self.plan, _stream()))
+
+    def end_capture(self):
+        L.check(self.lib.gs_plan_end_capture(self.plan, _stream()))
+
+    def launch(self):
+        """Replay the captured step on the current stream (one graph launch)."""
+        L.check(self.lib.gs_plan_launch(self.plan, _stream()))
+
     def backward(self, scenes, sensor_poses, group_poses, outputs, grad_outputs, grads=None):
         """Adjoint of forward (uses the workspace state of the last forward).
 
@@ -174,7 +186,7 @@ class Renderer:
         out = dict(pairs=list(st.pairs[:n]), overflow=bool(st.overflow), n_visible=list(st.n_visible[:n]),
                    fp64_pairs=int(st.fp64_pairs), evaluated=int(st.evaluated), composited=int(st.composited),
                    work_items=int(st.work_items), segments=int(st.segments),
-                   graph_replays=int(st.graph_replays), rc=rc)
+                   graph_replays=int(st.graph_replays), step_launches=int(st.step_launches), rc=rc)
         return out
 
     def set_timing(self, max_records: int):

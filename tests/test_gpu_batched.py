@@ -393,6 +393,74 @@ def test_graph_replay_of_decode_and_render_matches_eager_and_oracle():
                 assert_verified(v, f"replay sensor {i}")
 
 
+def test_step_capture_through_the_abi_replays_forward_and_backward():
+    """A whole training step -- four decodes, one batched render, the adjoint render and the four decode
+    adjoints (allocation-free), gradient clears in between -- captured through gs_plan_begin_capture /
+    gs_plan_end_capture and replayed by gs_plan_launch: after each pose update the replay's outputs equal an
+    eager step and its gradients match the eager ones (atomic summation order aside)."""
+    _say("ABI step capture: forward + backward")
+    cam_sc, lid_sc, sensors = _decoded_rig()
+    rg = _GpuRig(cam_sc, lid_sc, sensors)
+    re_ = _GpuRig(cam_sc, lid_sc, sensors)
+    rng = np.random.default_rng(5)
+    gouts = [torch.from_numpy(rng.standard_normal(tuple(o.shape)).astype(np.float32)).to(DEV) for o in rg.outs]
+    gsurf = [{k: torch.zeros_like(v) for k, v in d.items()} for d in rg.ds]
+
+    def zeros(dec):
+        z = lambda t: torch.zeros(t.shape, dtype=torch.float32, device=DEV)
+        return dict(xyz=z(dec.xyz), scaling=z(dec.scaling), offsets=z(dec.offsets), feat=z(dec.feat),
+                    w1=z(dec.w1), b1=z(dec.b1), w2=z(dec.w2), b2=z(dec.b2))
+
+    agc, agl = zeros(rg.dc), zeros(rg.dl)
+
+    def step():
+        rg.forward()
+        for d in gsurf + [agc, agl]:
+            for v in d.values():
+                v.zero_()
+        rg.r.backward(rg.ds, rg.sp, rg.gp_all, rg.outs, gouts, grads=gsurf)
+        for i, s in enumerate(sensors):
+            if s["kind"] == "pinhole":
+                rg.dc.backward(rg.sp[i], rg.gp_c, gsurf[i], grads=agc, noalloc=True)
+            else:
+                rg.dl.backward(rg.sp[i], rg.gp_l, gsurf[i], grads=agl, noalloc=True)
+
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        step()  # warm (lazy module loading) before capture
+        stream.synchronize()
+        rg.r.begin_capture()
+        step()
+        rg.r.end_capture()
+    for it in range(3):
+        shift = torch.zeros_like(rg.sp)
+        shift[:, 3] = 0.06 * (it + 1)
+        new_sp = rg.sp + shift
+        rg.sp.copy_(new_sp)
+        re_.sp.copy_(new_sp)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            rg.r.launch()
+        torch.cuda.current_stream().wait_stream(stream)
+        ref = [o.clone() for o in re_.forward()]
+        rc, rl = re_.backward(gouts)
+        x = torch.randn(512, 512, device=DEV) @ torch.randn(512, 512, device=DEV)  # unrelated eager work
+        torch.cuda.synchronize()
+        del x
+        for a, b in zip(rg.outs, ref):
+            assert torch.equal(a, b), f"replay {it}: outputs differ from eager"
+        for got, want in ((agc, rc), (agl, rl)):
+            for k in want:
+                err = float((got[k] - want[k]).abs().max())
+                scale = float(want[k].abs().max())
+                assert scale > 0 and err <= 1e-4 * scale, (it, k, err, scale)
+        _say(f"  replay {it}: outputs bit-equal, gradients within 1e-4 of eager")
+    with torch.cuda.stream(stream):
+        st = rg.r.status()
+    assert st["step_launches"] == 3 and not st["overflow"]
+
+
 def test_plan_graph_replay_matches_eager_with_pose_updates():
     _say("plan graph replay")
     scene, sensors = _rig()
