@@ -205,10 +205,47 @@ def _grid_pairs(bins, sensor, stride):
     return row * nW + col, sp
 
 
+def _grid_pairs_lidar(bins, sensor, stride):
+    """Candidate pairs for the grid_rays(sensor, stride) sample of a LiDAR: the
+    beam/column rectangles, whose columns may wrap ([i_lo, W) u [0, i_hi]) or
+    span the full circle."""
+    W = int(sensor["width"])
+    nW = (W + stride - 1) // stride
+    touch = np.nonzero(bins["touch"])[0]
+    lo, hi = bins["i_lo"][touch], bins["i_hi"][touch]
+    full = bins["full_cols"][touch]
+    wrap = (lo > hi) & ~full
+    # up to two inclusive column runs per surfel
+    a1 = np.where(full, 0, lo)
+    b1 = np.where(full | wrap, W - 1, hi)
+    a2 = np.zeros_like(lo)
+    b2 = np.where(wrap, hi, -1)
+    r_lo = -(-bins["j_lo"][touch] // stride)
+    r_hi = bins["j_hi"][touch] // stride
+    nrow = np.maximum(r_hi - r_lo + 1, 0)
+    rps, sps = [], []
+    for a, b in ((a1, b1), (a2, b2)):
+        c_lo = -(-a // stride)
+        c_hi = np.where(b >= 0, b // stride, -1)
+        ncol = np.maximum(c_hi - c_lo + 1, 0)
+        cnt = ncol * nrow
+        sp = np.repeat(touch, cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        local = np.arange(int(cnt.sum())) - start
+        nc = np.repeat(np.maximum(ncol, 1), cnt)
+        col = np.repeat(c_lo, cnt) + local % nc
+        row = np.repeat(r_lo, cnt) + local // nc
+        rps.append(row * nW + col)
+        sps.append(sp)
+    return np.concatenate(rps), np.concatenate(sps)
+
+
 def _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride=None):
     """(ray position, surfel) candidate pairs before the per-pair support test."""
-    if grid_stride is not None and mode != "brute" and sensor["kind"] == "pinhole":
-        return _grid_pairs(bins, sensor, grid_stride)
+    if grid_stride is not None and mode != "brute":
+        if sensor["kind"] == "pinhole":
+            return _grid_pairs(bins, sensor, grid_stride)
+        return _grid_pairs_lidar(bins, sensor, grid_stride)
     W = int(sensor["width"])
     vis = np.nonzero(bins["visible"])[0]
     R = ray_ids.size

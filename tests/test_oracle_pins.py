@@ -420,3 +420,18 @@ def test_grid_sample_matches_full_image():
     for ch in ("rgb", "depth", "alpha"):
         f = full[ch].reshape(full[ch].shape[:-2] + (-1,))
         np.testing.assert_array_equal(f[..., ids], sub[ch])
+
+
+def test_lidar_grid_sample_matches_full_image():
+    # Same for a LiDAR, whose column ranges wrap around the circle or span it.
+    L = _small_lidar(32, 96)
+    sc = _lidar_scene(14, 300)
+    full = raster.render(sc, L, raster.make_opts(tile_w=16, tile_h=8))
+    b = full["bins"]
+    assert (b["wrap"] | b["full_cols"]).any() and b["touch"].sum() > 100
+    for stride in (2, 5):
+        sub = raster.render(sc, L, raster.make_opts(tile_w=16, tile_h=8), rays=("grid", stride))
+        ids = raster.grid_rays(L, stride)
+        for ch in ("range", "intensity", "alpha"):
+            np.testing.assert_array_equal(full[ch].reshape(-1)[ids], sub[ch])
+        assert sub["alpha"].max() > 0.1
