@@ -1,36 +1,44 @@
 #!/usr/bin/env python3
-"""Throughput of the MI355X 2D-surfel renderer.
+"""Throughput of the MI355X 2D-surfel renderer on one simulation step.
 
-Headline: forward rays/s on the driving-scene camera workload (1920x1080
-pinhole, f = 960, 1M surfels on a synthetic road corridor, degree-3 SH colour,
-FP32), one step = one complete pass of the render path (pose composition,
-projection and binning, depth sort, pair emission, tile sort, tile ranges,
-compositing) over that frame with the inputs resident in HBM.
+Headline: the six-camera + LiDAR step -- 3 pinhole cameras at 1920x1080
+(f = 960) and 3 at 1280x720 (f = 640) on a yaw rig plus a 128-beam x 1800
+spinning LiDAR, 9,216,000 rays -- over a synthetic road corridor of 300k
+anchors plus 20 posed vehicle assets of 2k anchors, 10 offsets each (3.4M
+surfels decoded per sensor).  One step is the whole hot path with the inputs
+resident in HBM: seven neural-Gaussian decodes (BF16 MFMA, FP32 accumulate),
+then one batched render of all sensors (pose composition, projection and
+binning, one depth sort, pair emission, one tile sort over the global tile
+space, tile ranges and work items, one persistent compositing launch), with
+tile shapes and the segment length chosen by the project's autotuner, the
+whole step replayed as one HIP graph captured through the library's step
+capture.  value = rays per step / forward step time; the forward+backward
+step (decode, render, L1 loss gradient, adjoint render, adjoint decode, one
+graph) is reported beside it.
 
-Also reported (in "extra"): forward+backward rays/s on the same frame (L1
-loss gradient, adjoint compositing, per-surfel adjoint), the per-stage time
-split, pair counts, and the algorithmic HBM bytes of a forward step; and, on
-the other workloads:
-  - neural-Gaussian training step (1280x720 camera, 50k anchors x 10): BF16
-    MFMA decode -> render -> L1 loss -> adjoint render -> adjoint decode, with
-    the decode's MFMA fraction;
-  - LiDAR range image (128 x 1800, 200k anchors x 10 = 2M surfels): decode +
-    render forward and forward+backward rays/s;
-  - six-camera + LiDAR step (9.2M rays, 3.4M surfels per sensor): the batched
-    path (BF16 MFMA decode, one record space, one persistent compositing
-    launch, whole step replayed as one HIP graph) against the plain
-    per-sensor FP32 path (FP32 VALU decode, one sensor at a time, no graph,
-    16x16 tiles, no list splitting), ms per step forward and forward+backward.
+roofline: the dominant kernel is the batched forward compositing launch; it
+is bound by plain FP32 ALU work.  "achieved" is its algorithmic FLOP per
+launch -- 60 FLOP per evaluated ray-surfel pair (the per-pair count of the
+solve, filter, exponent and blend), times the evaluated pairs the device
+counts -- over its average launch time, from HIP events the library records
+around that launch on its stream during an instrumented eager run of the same
+step.  The peak is the chip's 157.3 TFLOP/s FP32 vector figure; the fraction
+of the 78.6 TFLOP/s non-packed rate (this build emits no packed-FP32
+instructions) and the kernel's algorithmic HBM bytes per launch (pairs x
+(4 B index + 72 B record) + rays x outputs) as a fraction of 8 TB/s are given
+beside it.
 
-roofline: the dominant kernel is the forward compositing kernel; it is bound
-by plain FP32 ALU work, so "achieved" is its algorithmic FLOP per launch (the
-counted ray-surfel evaluations times the per-pair FLOP of the solve, plus the
-composited pairs times the per-pair FLOP of blending) over its average
-duration, timed with HIP events around each stage on the render stream during
-a second run of the same number of frames (the frame rate itself is timed
-without the per-stage events, which cost the frame a few microseconds each).
+cpu_baseline: the FP64 oracle (decode of every anchor, then render) on every
+8th row and column of the front 1080p camera, the rear 720p camera and the
+LiDAR; the same sample gives the per-channel error of the GPU step against
+the oracle.
 
-cpu_baseline: the FP64 oracle on every 8th row and column of the same frame.
+Also reported (in "extra"): the same step on the per-sensor path with list
+splitting and autotuned tiles (no batching, no graph), on the plain
+per-sensor FP32 path (FP32 VALU decode, 16x16 tiles, no splitting, no
+graph), the per-stage split, the single 1080p driving-scene frame (1M
+surfels, SH3), the 720p neural training step, the LiDAR frame and the
+inpainting affinity.
 """
 from __future__ import annotations
 
@@ -46,17 +54,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Non-packed FP32 VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz.
-PEAK_ALU_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3          # published FP32 vector peak (counts packed dual issue)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FLOP per ray-surfel pair of the forward compositing kernel:
-# evaluation (offsets, solve, rho, low-pass, exponent) and, for composited
-# pairs, transmittance update, weight and 8-channel accumulation.
-FLOP_EVAL = 33
-FLOP_COMPOSITE = 20
+PEAK_BF16_TFLOPS = 2500.0
+# Algorithmic FLOP per evaluated ray-surfel pair of the compositing kernel
+# (two-plane solve, low-pass filter, exponent, transmittance and blend).
+FLOP_PER_PAIR = 60
+REC_BYTES = 72                    # algorithmic per-surfel record gathered per pair
+CHANNELS = {"pinhole": 8, "lidar": 3}
 
 BLEND_SOURCES = ("paper_2503_11731_amd/csrc/blend.hip", "paper_2503_11731_amd/csrc/gs_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_pinhole_1080p_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_rig_step_traffic.json")
 
 
 def log(msg):
@@ -71,10 +80,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per blend launch from committed rocprofv3 counters, if they match this source."""
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per compositing launch from committed rocprofv3 counters, if they match this source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -83,50 +92,28 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
-def forward_bytes(n, n_touch, pairs, rays, sh_coeffs):
-    """Algorithmic HBM bytes of one forward step (inputs once, records, pairs, sorts, outputs)."""
-    inputs = n * (12 + 16 + 8 + 4 + 4 * sh_coeffs)
-    per_splat = n * (4 + 4 + 4 + 4 + 4) + n_touch * (64 + 32 + 16)  # keys, vals, tiles, visible + records
-    depth_sort = 4 * n * 8 * 2                                       # 4 passes, read + write 8 B
-    emit = pairs * 8
-    tile_sort = 2 * pairs * 8 * 2
-    gather = pairs * (4 + 64 + 32)                                   # surfel id + record per pair
-    outputs = rays * (8 * 4 + 8)
-    return inputs + per_splat + depth_sort + emit + tile_sort + gather + outputs
-
-
-def cpu_baseline(scene, cam, stride):
+def _timed(fn, steps, warmup, stream=None):
+    """Mean ms per call of fn over `steps` calls after `warmup`, HIP events on `stream` (default: current)."""
     import torch
-
-    from oracle import raster
-    t0 = time.perf_counter()
-    out = raster.render(scene, cam, raster.make_opts(), rays=("grid", stride))
-    dt = time.perf_counter() - t0
-    n = int(out["alpha"].size)
-    return dict(value=n / dt, unit="rays/s", cores=int(torch.get_num_threads()), kind="oracle",
-                sample=f"every {stride}th row and column of the 1920x1080 frame ({n} rays), FP64, "
-                       f"{dt:.1f} s including per-surfel setup of all 1M surfels")
-
-
-def _timed(fn, steps, warmup):
-    """Mean ms per call of fn over `steps` calls after `warmup`, HIP events on the current stream."""
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize()
+    stream = stream or torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            fn()
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        stream.synchronize()
     return e0.elapsed_time(e1) / steps
 
 
 def _zero(dicts):
     for d in dicts:
         for v in d.values():
-            v.zero_()
+            if v is not None:
+                v.zero_()
 
 
 def _decode_flops(n_anchors, n_out):
@@ -134,7 +121,198 @@ def _decode_flops(n_anchors, n_out):
     return 2.0 * n_anchors * (35 * 32 + 32 * n_out)
 
 
-PEAK_BF16_TFLOPS = 2500.0
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_logical_cpus": os.cpu_count(), "host_cpu_model": model}
+
+
+# ---------------------------------------------------------------------------
+# the six-camera + LiDAR step
+# ---------------------------------------------------------------------------
+
+class RigStep:
+    """Decoders of the camera and LiDAR anchor scenes, one plan over the seven sensors
+    (sensor i renders scene i, its own decode), and every buffer a step uses, allocated
+    once so that the step can be captured into a graph."""
+
+    def __init__(self, cam_sc, lid_sc, sensors, dev, *, batched, tiles=None, segment_pairs=0, plain=False):
+        import torch
+
+        import paper_2503_11731_amd as gs
+        self.sensors = sensors
+        self.dc = gs.Decoder.from_gen(cam_sc, dev, plain_fp32=plain)
+        self.dl = gs.Decoder.from_gen(lid_sc, dev, plain_fp32=plain)
+        self.sp = gs.poses_tensor([s["pose"] for s in sensors], dev)
+        self.gp_c = gs.poses_tensor(cam_sc.group_poses, dev)
+        self.gp_l = gs.poses_tensor(lid_sc.group_poses, dev)
+        shapes, sens = [], []
+        for i, s in enumerate(sensors):
+            an = cam_sc if s["kind"] == "pinhole" else lid_sc
+            offs = tuple(int(x) * an.k for x in an.group_offsets)
+            shapes.append(gs.SceneShape(an.n_anchors * an.k, -1, s["kind"] != "pinhole", offs))
+            s = dict(s, scene=i)
+            if tiles is not None:
+                s["tile"] = tiles[i]
+            sens.append(s)
+        self.shapes = shapes
+        n = shapes[0].n_splats
+        self.r = gs.Renderer(shapes, sens, opts=gs.PRODUCTION, device=dev, batched=batched, pair_capacity=6 * n,
+                             segment_pairs=segment_pairs)
+        self.gp_all = torch.cat([self.gp_c if s["kind"] == "pinhole" else self.gp_l for s in sensors]).contiguous()
+        self.ds = [self._dec(i).new_decoded() for i in range(len(sensors))]
+        self.outs = self.r.new_outputs()
+        self.rays = sum(s["width"] * s["height"] for s in sensors)
+        # training-step buffers
+        g = torch.Generator(device=dev).manual_seed(7)
+        self.targets = [torch.rand(o.shape, generator=g, device=dev) for o in self.outs]
+        self.gouts = [torch.zeros_like(o) for o in self.outs]
+        self.gsurf = [{k: torch.zeros_like(v) for k, v in d.items()} for d in self.ds]
+        z = lambda t: torch.zeros(t.shape, dtype=torch.float32, device=dev)
+        self.ag = [dict(xyz=z(d.xyz), scaling=z(d.scaling), offsets=z(d.offsets), feat=z(d.feat), w1=z(d.w1),
+                        b1=z(d.b1), w2=z(d.w2), b2=z(d.b2)) for d in (self.dc, self.dl)]
+        self.scratch = [torch.empty(d.scratch_bytes(), dtype=torch.uint8, device=dev) for d in (self.dc, self.dl)]
+
+    def _dec(self, i):
+        return self.dc if self.sensors[i]["kind"] == "pinhole" else self.dl
+
+    def fwd(self):
+        for i, s in enumerate(self.sensors):
+            if s["kind"] == "pinhole":
+                self.dc.forward(self.sp[i], self.gp_c, out=self.ds[i])
+            else:
+                self.dl.forward(self.sp[i], self.gp_l, out=self.ds[i])
+        self.r.forward(self.ds, self.sp, self.gp_all, outputs=self.outs)
+
+    def fwd_bwd(self):
+        """L1 loss against the targets, mean over each sensor's outputs: dL/dO = sign(O - T) / n."""
+        import torch
+        self.fwd()
+        for o, t, g in zip(self.outs, self.targets, self.gouts):
+            torch.sub(o, t, out=g)
+            torch.sign(g, out=g)
+            g.mul_(1.0 / g.numel())
+        _zero(self.gsurf + self.ag)
+        self.r.backward(self.ds, self.sp, self.gp_all, self.outs, self.gouts, grads=self.gsurf)
+        for i, s in enumerate(self.sensors):
+            j = 0 if s["kind"] == "pinhole" else 1
+            self._dec(i).backward(self.sp[i], self.gp_c if j == 0 else self.gp_l, self.gsurf[i], grads=self.ag[j],
+                                  scratch=self.scratch[j])
+
+    def capture(self, fn, stream):
+        """Capture fn (enqueue-only, allocation-free) as this plan's step graph on `stream`."""
+        import torch
+        with torch.cuda.stream(stream):
+            fn()  # warm: lazy kernel loading happens outside the capture
+            stream.synchronize()
+            self.r.begin_capture()
+            fn()
+            self.r.end_capture()
+            stream.synchronize()
+
+    def launch(self):
+        self.r.launch()
+
+
+def _rig_roofline(rig, steps):
+    """Average compositing launch time (library HIP events on its stream) and the kernel's counts."""
+    import torch
+    rig.r.set_timing(12 * (steps + 2))
+    for _ in range(steps):
+        rig.fwd()
+    torch.cuda.synchronize()
+    stages = rig.r.stage_times(reset=True)
+    rig.r.set_timing(0)
+    st = rig.r.status()
+    blend_ms, blend_n = stages["blend"]
+    t = blend_ms / max(blend_n, 1) / 1e3
+    flop = FLOP_PER_PAIR * st["evaluated"]
+    pairs = int(sum(st["pairs"]))
+    out_bytes = sum(s["width"] * s["height"] * (4 * CHANNELS[s["kind"]] + 8) for s in rig.sensors)
+    hbm = pairs * (4 + REC_BYTES) + out_bytes
+    achieved = flop / t / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+            "kernel": "k_blend_queue (batched forward compositing, all seven sensors, one persistent launch)",
+            "avg_launch_ms": t * 1e3, "launches_timed": blend_n,
+            "flop_per_launch": flop, "flop_per_evaluated_pair": FLOP_PER_PAIR,
+            "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS, "frac_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "hbm_algorithmic_bytes_per_launch": hbm, "hbm_frac": hbm / t / (PEAK_HBM_GBS * 1e9)}
+    stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
+    counts = {"pairs": pairs, "evaluated_pairs": st["evaluated"], "composited_pairs": st["composited"],
+              "fp64_pairs": st["fp64_pairs"], "work_items": st["work_items"], "segments": st["segments"],
+              "visible": [int(x) for x in st["n_visible"]]}
+    return roof, stage_ms, counts
+
+
+def rig_cpu_baseline_and_errors(cam_sc, lid_sc, sensors, outs, stride=8, which=(0, 3, 6)):
+    """The FP64 oracle (decode, then render) on every stride-th row and column of the given sensors,
+    timed; and the GPU outputs' error against it on the same rays."""
+    import numpy as np
+    import torch
+
+    from gen import scenes as S
+    from oracle import decode as odec
+    from oracle import raster, spec32
+
+    def anchor_dict(sc):
+        return dict(xyz=sc.xyz.astype(np.float64), scaling=sc.scaling.astype(np.float64),
+                    offsets=sc.offsets.astype(np.float64), feat=S.bf16_bits_to_f32(sc.feat_bf16).astype(np.float64),
+                    group_offsets=sc.group_offsets)
+
+    total_rays, total_s, errs, parts = 0, 0.0, {}, []
+    for i in which:
+        s = sensors[i]
+        an = cam_sc if s["kind"] == "pinhole" else lid_sc
+        t0 = time.perf_counter()
+        poses_s = np.stack([spec32.compose_pose(s["pose"], g) for g in an.group_poses])
+        with torch.no_grad():
+            dec = odec.decode(anchor_dict(an), an.mlps, poses_s, s["kind"])
+        sc32 = {k: np.ascontiguousarray(v.numpy().astype(np.float32)) for k, v in dec.items()}
+        sc32.update(group_offsets=np.array([int(x) * an.k for x in an.group_offsets], np.int32),
+                    group_poses=an.group_poses)
+        o = raster.make_opts(raster.PRODUCTION)
+        ref = raster.render(sc32, s, o, rays=("grid", stride), params=dict(dec))
+        dt = time.perf_counter() - t0
+        ids = raster.grid_rays(s, stride)
+        n = ids.size
+        total_rays += n
+        total_s += dt
+        parts.append(f"{s['kind']} {s['width']}x{s['height']}: {n} rays")
+        got = outs[i].reshape(outs[i].shape[0], -1)[:, torch.as_tensor(ids, device=outs[i].device)]
+        got = got.cpu().numpy().astype(np.float64)
+        if s["kind"] == "pinhole":
+            names = ("r", "g", "b", "depth", "nx", "ny", "nz", "alpha")
+            want = np.concatenate([ref["rgb"], ref["depth"][None], ref["normal"], ref["alpha"][None]])
+            dch = 3
+        else:
+            names = ("range", "intensity", "alpha")
+            want = np.stack([ref["range"], ref["intensity"], ref["alpha"]])
+            dch = 0
+        e = np.abs(got - want)
+        e[dch] /= np.maximum(1.0, np.abs(want[dch]))
+        beyond = int((e > 1e-4).any(0).sum())
+        errs[f"sensor{i}_{s['kind']}"] = {"max_err": {nm: float(e[c].max()) for c, nm in enumerate(names)},
+                                          "p9999_err": {nm: float(np.quantile(e[c], 0.9999)) for c, nm in
+                                                        enumerate(names)},
+                                          "rays": int(n), "rays_beyond_1e-4": beyond}
+    base = {"value": total_rays / total_s, "unit": "rays/s", "cores": int(torch.get_num_threads()),
+            "kind": "oracle",
+            "sample": f"every {stride}th row and column of the front 1920x1080 camera, the rear 1280x720 camera and the 128x1800 LiDAR "
+                      f"({'; '.join(parts)}), each sensor's 340k anchors decoded in FP64 and all 3.4M surfels "
+                      f"set up; {total_s:.1f} s of CPU time for {total_rays} rays", **cpu_info()}
+    errs["note"] = ("GPU step (BF16-MFMA decode, FP32 render) minus the FP64 oracle chain (decode of the same bf16 "
+                    "parameters, render) on the sampled rays; depth/range relative to max(1 m, |ref|); rays beyond "
+                    "1e-4 are rays with a decision within rounding of its threshold (the parity tests verify them "
+                    "against the oracle's alternative outcomes)")
+    return base, errs
 
 
 def bench_train720p(steps, warmup):
@@ -266,108 +444,60 @@ def bench_affinity(steps, warmup):
             "levels": res}
 
 
-def bench_rig(steps, warmup):
-    """Six cameras + LiDAR per step: batched graph path vs the plain per-sensor FP32 path."""
-    import numpy as np
+def bench_frame1080(steps, warmup):
+    """Single driving-scene camera frame: 1920x1080, 1M surfels, SH3, forward and forward+backward."""
     import torch
 
     import paper_2503_11731_amd as gs
     from gen import scenes as S
     dev = torch.device("cuda:0")
-    cam_sc, lid_sc, sensors = S.config5()
-    n_s = len(sensors)
-    rays = sum(s["width"] * s["height"] for s in sensors)
-    k = cam_sc.k
-    n = cam_sc.n_anchors * k
-    offs = tuple(int(x) * k for x in cam_sc.group_offsets)
-    sens = []
-    for i, s in enumerate(sensors):
-        s = dict(s)
-        s["scene"] = i
-        sens.append(s)
-    shapes = [gs.SceneShape(n, -1, s["kind"] != "pinhole", offs) for s in sens]
-    sp = gs.poses_tensor([s["pose"] for s in sens], dev)
-    gp_c = gs.poses_tensor(cam_sc.group_poses, dev)
-    gp_l = gs.poses_tensor(lid_sc.group_poses, dev)
-    gp_all = torch.cat([gp_c] * (n_s - 1) + [gp_l]).contiguous()
-    cap = 6 * n
-    res = {"workload": "3 pinhole 1920x1080 (f=960) + 3 pinhole 1280x720 (f=640) + 128x1800 LiDAR; 300k corridor "
-                       "anchors + 20 vehicle assets x 2k anchors, x 10 offsets = 3.4M surfels decoded per sensor",
-           "rays_per_step": rays, "surfels_per_sensor": n}
-
-    def build(batched, plain):
-        dc = gs.Decoder.from_gen(cam_sc, dev, plain_fp32=plain)
-        dl = gs.Decoder.from_gen(lid_sc, dev, plain_fp32=plain)
-        ss = [dict(s) for s in sens]
-        if plain:
-            for s in ss:
-                s["tile"] = (16, 16)
-        r = gs.Renderer(shapes, ss, opts=gs.PRODUCTION, device=dev, batched=batched, pair_capacity=cap,
-                        segment_pairs=-1 if plain else 0)
-        ds = [(dc if s["kind"] == "pinhole" else dl).new_decoded() for s in sens]
-        outs = r.new_outputs()
-
-        def fwd():
-            for i, s in enumerate(sens):
-                if s["kind"] == "pinhole":
-                    dc.forward(sp[i], gp_c, out=ds[i])
-                else:
-                    dl.forward(sp[i], gp_l, out=ds[i])
-            r.forward(ds, sp, gp_all, outputs=outs)
-        return dc, dl, r, ds, outs, fwd
-
-    for label, batched, plain in (("plain_per_sensor_fp32", False, True), ("batched", True, False)):
-        dc, dl, r, ds, outs, fwd = build(batched, plain)
+    sc, sensors = S.config2()
+    cam = sensors[0]
+    scene = dict(mean=sc.mean, quat=sc.quat, scale=sc.scale, opacity=sc.opacity, sh=sc.sh, sh_degree=3,
+                 group_offsets=sc.group_offsets, group_poses=sc.group_poses)
+    st = gs.scene_tensors(scene, dev)
+    sp = gs.poses_tensor([cam["pose"]], dev)
+    gp = gs.poses_tensor(sc.group_poses, dev)
+    r = gs.Renderer([gs.SceneShape(sc.n, 3, False, (0, sc.n))], [cam], opts=gs.PRODUCTION, device=dev)
+    rays = cam["width"] * cam["height"]
+    outs = r.new_outputs()
+    fwd = lambda: r.forward([st], sp, gp, outputs=outs)
+    ms = _timed(fwd, steps, warmup)
+    r.set_timing(8 * (steps + 2))
+    for _ in range(steps):
         fwd()
-        st = r.status()
-        if st["overflow"]:
-            raise RuntimeError(f"{label}: pair capacity overflow")
-        entry = {"fwd_ms_eager": _timed(fwd, steps, warmup), "pairs": int(sum(st["pairs"])),
-                 "segments": st["segments"]}
-        if batched:
-            stream = torch.cuda.Stream()
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.stream(stream):
-                fwd()
-                stream.synchronize()
-                with torch.cuda.graph(graph, stream=stream):
-                    fwd()
-            ref = [o.clone() for o in outs]
-            entry["fwd_ms"] = _timed(graph.replay, steps, warmup)
-            entry["graph_replay_matches_eager"] = bool(all(torch.equal(a, b) for a, b in zip(ref, outs)))
-        else:
-            entry["fwd_ms"] = entry["fwd_ms_eager"]
-        targets = [torch.rand_like(o) for o in outs]
-        gsurf = [{kk: torch.zeros_like(v) for kk, v in d.items()} for d in ds]
-        g_outs = [torch.zeros_like(o) for o in outs]
-        agc = [None]
-        agl = [None]
+    torch.cuda.synchronize()
+    stages = r.stage_times(reset=True)
+    r.set_timing(0)
+    status = r.status()
+    if status["overflow"]:
+        raise RuntimeError("pair capacity overflow")
+    blend_ms, blend_n = stages["blend"]
+    t = blend_ms / max(blend_n, 1) / 1e3
+    achieved = FLOP_PER_PAIR * status["evaluated"] / t / 1e12
+    target = torch.rand_like(outs[0])
+    grads = [{k: torch.zeros_like(v) for k, v in st.items()}]
+    g = torch.zeros_like(outs[0])
 
-        def step():
-            if batched:
-                graph.replay()
-            else:
-                fwd()
-            for o, t, g in zip(outs, targets, g_outs):
-                torch.sign(o - t, out=g)
-            _zero(gsurf)
-            r.backward(ds, sp, gp_all, outs, g_outs, grads=gsurf)
-            for i, s in enumerate(sens):
-                if s["kind"] == "pinhole":
-                    agc[0] = dc.backward(sp[i], gp_c, gsurf[i], grads=agc[0])
-                else:
-                    agl[0] = dl.backward(sp[i], gp_l, gsurf[i], grads=agl[0])
+    def fwd_bwd():
+        fwd()
+        torch.sub(outs[0], target, out=g)
+        torch.sign(g, out=g)
+        g.mul_(1.0 / g.numel())
+        _zero(grads)
+        r.backward([st], sp, gp, outs, [g], grads=grads)
 
-        entry["fwd_bwd_ms"] = _timed(step, steps, warmup)
-        entry["fwd_rays_per_s"] = rays / (entry["fwd_ms"] / 1e3)
-        entry["fwd_bwd_rays_per_s"] = rays / (entry["fwd_bwd_ms"] / 1e3)
-        res[label] = entry
-        del r, ds, outs, gsurf, g_outs, targets
-        torch.cuda.synchronize()
-        torch.cuda.empty_cache()
-    res["fwd_speedup_vs_plain"] = res["plain_per_sensor_fp32"]["fwd_ms"] / res["batched"]["fwd_ms"]
-    res["fwd_bwd_speedup_vs_plain"] = res["plain_per_sensor_fp32"]["fwd_bwd_ms"] / res["batched"]["fwd_bwd_ms"]
-    return res
+    fb_ms = _timed(fwd_bwd, steps, warmup)
+    return {"workload": "driving-scene camera: 1920x1080 pinhole f=960, 1M corridor surfels (ground 60%, facades "
+                        "30%, vehicles 10%), SH degree 3, production compositing",
+            "fwd_ms": ms, "fwd_rays_per_s": rays / (ms / 1e3), "fwd_bwd_ms": fb_ms,
+            "fwd_bwd_rays_per_s": rays / (fb_ms / 1e3),
+            "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
+            "blend_avg_launch_ms": t * 1e3, "blend_tflops": achieved,
+            "blend_frac_of_157": achieved / PEAK_FP32_TFLOPS, "pairs": status["pairs"][0],
+            "evaluated_pairs": status["evaluated"], "composited_pairs": status["composited"],
+            "fp64_pairs": status["fp64_pairs"],
+            "grad_finite": bool(all(torch.isfinite(v).all() for v in grads[0].values()))}
 
 
 def main():
@@ -377,18 +507,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="default tiles and segment length for the step")
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration under rocprofv3) and exit")
-    ap.add_argument("--workloads", default="train720p,lidar,rig,affinity",
-                    help="extra workloads to time (comma list of train720p, lidar, rig, affinity; empty for none)")
+    ap.add_argument("--workloads", default="per_sensor,plain,frame1080,train720p,lidar,affinity",
+                    help="extra workloads (comma list of per_sensor, plain, frame1080, train720p, lidar, affinity)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures a single MI355X: multi-GPU runs are not part of this build "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_probe > 0:
@@ -401,134 +531,117 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "dispatches": 4}), flush=True)
         return
 
-    import paper_2503_11731_amd as gs
     from gen import scenes as S
+    from paper_2503_11731_amd import autotune as at
 
     dev = torch.device("cuda:0")
-    log("generating the driving-scene workload (1M surfels, SH3)")
-    sc, sensors = S.config2()
-    cam = sensors[0]
-    scene = dict(mean=sc.mean, quat=sc.quat, scale=sc.scale, opacity=sc.opacity, sh=sc.sh, sh_degree=3,
-                 group_offsets=sc.group_offsets, group_poses=sc.group_poses)
-    st = gs.scene_tensors(scene, dev)
-    sp = gs.poses_tensor([cam["pose"]], dev)
-    gp = gs.poses_tensor(sc.group_poses, dev)
-    r = gs.Renderer([gs.SceneShape(sc.n, 3, False, (0, sc.n))], [cam], opts=gs.PRODUCTION, device=dev)
-    rays = cam["width"] * cam["height"]
-    outs = r.new_outputs()
+    log("generating the six-camera + LiDAR step (300k anchors + 20 assets x 2k, 10 offsets)")
+    cam_sc, lid_sc, sensors = S.config5()
+    stream = torch.cuda.Stream()
+    extra = {}
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        r.forward([st], sp, gp, outputs=outs)
-    status = r.status()
-    if status["overflow"]:
+    tiles, seg = None, 0
+    if not args.no_autotune:
+        log("autotune (tile shape per sensor, segment length per plan)")
+        probe = RigStep(cam_sc, lid_sc, sensors, dev, batched=True)
+        probe.fwd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gps = [probe.gp_c if s["kind"] == "pinhole" else probe.gp_l for s in sensors]
+        res = at.autotune(probe.shapes, probe.ds, sensors, probe.sp, gps, batched=True, segments=[512, 1024, 2048],
+                          pair_capacity=probe.shapes[0].n_splats * 6, steps=3, warmup=1)
+        tiles, seg = res.tiles, res.segment_pairs
+        extra["autotune"] = {"tiles": [list(t) for t in tiles], "segment_pairs": seg,
+                             "seconds": time.perf_counter() - t0, "from_cache": res.from_cache}
+        del probe
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    log("batched step: capture forward")
+    rig = RigStep(cam_sc, lid_sc, sensors, dev, batched=True, tiles=tiles, segment_pairs=seg)
+    rig.fwd()
+    st = rig.r.status()
+    if st["overflow"]:
         raise RuntimeError("pair capacity overflow")
-
-    # The frame rate is timed without per-stage events (each event record
-    # costs the frame a few microseconds); the same number of frames is then
-    # run again with HIP events around every stage for the stage split and
-    # the compositing kernel's average launch time.
-    log(f"timed forward x{args.steps}")
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    eager_fwd_ms = _timed(rig.fwd, args.steps, args.warmup, stream)
+    rig.capture(rig.fwd, stream)
+    log(f"timed forward step x{args.steps} (graph)")
     w0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        r.forward([st], sp, gp, outputs=outs)
-    e1.record()
-    torch.cuda.synchronize()
+    fwd_ms = _timed(rig.launch, args.steps, args.warmup, stream)
     wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1) / args.steps
-    log(f"instrumented forward x{args.steps}")
-    r.set_timing(8 * (args.steps + 2))
-    e0.record()
-    for _ in range(args.steps):
-        r.forward([st], sp, gp, outputs=outs)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_instr = e0.elapsed_time(e1) / args.steps
-    stages = r.stage_times(reset=True)
-    r.set_timing(0)
-    status = r.status()
-    blend_ms, blend_n = stages["blend"]
-    blend_s = blend_ms / max(blend_n, 1) / 1e3
-    flop = status["evaluated"] * FLOP_EVAL + status["composited"] * FLOP_COMPOSITE
-    achieved = flop / blend_s / 1e12
-    value = rays / (ms / 1e3)
-
+    fwd_outs = [o.clone() for o in rig.outs]
+    log("batched step: capture forward + backward")
+    rig.capture(rig.fwd_bwd, stream)
+    fb_ms = _timed(rig.launch, args.steps, args.warmup, stream)
+    grad_finite = bool(all(torch.isfinite(v).all() for d in rig.ag for v in d.values()))
+    log("instrumented eager forward (stage split, compositing launch time)")
+    with torch.cuda.stream(stream):
+        roof, stage_ms, counts = _rig_roofline(rig, args.steps)
+        replay_same = all(torch.equal(a, b) for a, b in zip(fwd_outs, rig.outs))
+        st = rig.r.status()
+    rays = rig.rays
     line = {
-        "metric": "rays/s fwd 2DGS raster (1920x1080 camera, 1M surfels, SH3)",
-        "value": value,
+        "metric": "rays/s fwd and fwd+bwd 2DGS raster; ms per 6-camera+LiDAR step",
+        "value": rays / (fwd_ms / 1e3),
         "unit": "rays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": fwd_ms,
+        "fwd_bwd_ms_per_step": fb_ms,
+        "fwd_bwd_rays_per_s": rays / (fb_ms / 1e3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "driving-scene camera forward: 1920x1080 pinhole f=960, 1M corridor surfels "
-                               "(ground 60%, facades 30%, vehicles 10%), SH degree 3, production compositing",
-                   "rays": rays, "surfels": sc.n, "frames_per_step": 1},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "k_blend_queue<256, false, 1> (forward compositing, camera)", "avg_launch_ms": blend_s * 1e3},
+        "config": {"workload": "6-camera + LiDAR step: 3 pinhole 1920x1080 (f=960) + 3 pinhole 1280x720 (f=640) on a "
+                               "yaw rig + 128-beam x 1800 spinning LiDAR; 300k road-corridor anchors + 20 posed vehicle "
+                               "assets x 2k anchors, 10 offsets (3.4M surfels decoded per sensor, BF16 MFMA decode with "
+                               "FP32 accumulation, FP32 compositing); decode + batched render as one HIP graph",
+                   "rays_per_step": rays, "surfels_per_sensor": rig.shapes[0].n_splats,
+                   "tiles": [list(t) for t in tiles] if tiles else "default 32x8",
+                   "segment_pairs": seg or "default 1024"},
+        "roofline": roof,
     }
-    extra = {"wall_s_timed": wall, "ms_per_step_with_stage_events": ms_instr,
-             "stage_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]},
-             "pairs": status["pairs"][0], "evaluated_pairs": status["evaluated"],
-             "composited_pairs": status["composited"], "fp64_pairs": status["fp64_pairs"],
-             "visible": status["n_visible"][0]}
-    n_touch = status["n_visible"][0]
-    fb = forward_bytes(sc.n, n_touch, status["pairs"][0], rays, 48)
-    extra["forward_algorithmic_bytes"] = fb
-    extra["forward_hbm_frac"] = fb / (ms / 1e3) / (PEAK_HBM_GBS * 1e9)
-
-    if not args.no_extras:
-        log("timed forward+backward")
-        target = torch.rand_like(outs[0])
-        grads = [{k: torch.zeros_like(v) for k, v in st.items()}]
-        for _ in range(2):
-            o = r.forward([st], sp, gp, outputs=outs)
-            g = torch.sign(o[0] - target) / o[0].numel()
-            r.backward([st], sp, gp, o, [g], grads=grads)
-        def fwd_bwd():
-            o = r.forward([st], sp, gp, outputs=outs)
-            g = torch.sign(o[0] - target) / o[0].numel()
-            for d in grads:
-                for v in d.values():
-                    v.zero_()
-            r.backward([st], sp, gp, o, [g], grads=grads)
-
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            fwd_bwd()
-        e1.record()
-        torch.cuda.synchronize()
-        fb_ms = e0.elapsed_time(e1) / args.steps
-        r.set_timing(10 * (args.steps + 2))
-        for _ in range(args.steps):
-            fwd_bwd()
-        torch.cuda.synchronize()
-        st2 = r.stage_times(reset=True)
-        r.set_timing(0)
-        extra["fwd_bwd_rays_per_s"] = rays / (fb_ms / 1e3)
-        extra["fwd_bwd_ms_per_step"] = fb_ms
-        extra["fwd_bwd_stage_ms"] = {k: v[0] / max(v[1], 1) for k, v in st2.items() if v[1]}
-        extra["grad_finite"] = bool(all(torch.isfinite(v).all() for v in grads[0].values()))
+    extra.update({"wall_s_timed_forward": wall, "eager_fwd_ms": eager_fwd_ms, "stage_ms": stage_ms, **counts,
+                  "graph_replay_matches_eager": bool(replay_same), "grad_finite": grad_finite,
+                  "step_launches": st["step_launches"]})
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline (oracle, stride {args.cpu_stride}) and GPU error against it")
+        base, errs = rig_cpu_baseline_and_errors(cam_sc, lid_sc, sensors, fwd_outs, stride=args.cpu_stride)
+        line["cpu_baseline"] = base
+        extra["error_vs_oracle"] = errs
+    del rig, fwd_outs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
     if not args.no_extras:
         for w in [x for x in args.workloads.split(",") if x]:
             log(f"workload {w}")
-            fn = {"train720p": bench_train720p, "lidar": bench_lidar, "rig": bench_rig, "affinity": bench_affinity}[w]
-            extra[w] = fn(args.steps, args.warmup)
-
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline (oracle, stride {args.cpu_stride})")
-        line["cpu_baseline"] = cpu_baseline(scene, cam, args.cpu_stride)
+            if w in ("per_sensor", "plain"):
+                plain = w == "plain"
+                rr = RigStep(cam_sc, lid_sc, sensors, dev, batched=False, plain=plain,
+                             tiles=[(16, 16)] * len(sensors) if plain else tiles,
+                             segment_pairs=-1 if plain else seg)
+                rr.fwd()
+                s2 = rr.r.status()
+                e = {"fwd_ms": _timed(rr.fwd, args.steps, args.warmup, stream),
+                     "fwd_bwd_ms": _timed(rr.fwd_bwd, args.steps, args.warmup, stream),
+                     "pairs": int(sum(s2["pairs"])), "overflow": s2["overflow"],
+                     "what": ("FP32 VALU decode, one sensor at a time, 16x16 tiles, no list splitting, no graph"
+                              if plain else "BF16 MFMA decode, one sensor at a time with list splitting and the "
+                                            "autotuned tiles, no batching, no graph")}
+                e["fwd_speedup_of_batched_graph"] = e["fwd_ms"] / fwd_ms
+                e["fwd_bwd_speedup_of_batched_graph"] = e["fwd_bwd_ms"] / fb_ms
+                extra[w] = e
+                del rr
+            else:
+                fn = {"frame1080": bench_frame1080, "train720p": bench_train720p, "lidar": bench_lidar,
+                      "affinity": bench_affinity}[w]
+                extra[w] = fn(args.steps, args.warmup)
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
     line["extra"] = extra
     print(json.dumps(line), flush=True)
 

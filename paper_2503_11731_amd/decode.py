@@ -83,11 +83,20 @@ class Decoder:
                                            ctypes.byref(d), _stream()))
         return out
 
+    def scratch_bytes(self) -> int:
+        """Bytes of the scratch buffer gs_decode_backward needs (weight-gradient partials)."""
+        s = self._struct()
+        nb = ctypes.c_size_t()
+        L.check(self.lib.gs_decode_scratch_size(ctypes.byref(s), ctypes.byref(nb)))
+        return max(int(nb.value), 256)
+
     def backward(self, sensor_pose, group_poses, grad_in: dict, grads: dict | None = None,
-                 noalloc: bool = False) -> dict:
+                 noalloc: bool = False, scratch: torch.Tensor | None = None) -> dict:
         """Adjoint (+= into grads).  noalloc: use gs_decode_backward_noalloc, which
         needs no scratch buffer (the library's own per-GPU array holds the
-        weight-gradient partials); nothing is allocated when grads is given."""
+        weight-gradient partials); scratch: a caller buffer of scratch_bytes()
+        for gs_decode_backward.  Either way nothing is allocated when grads is
+        given."""
         dev = self.xyz.device
         if grads is None:
             z = lambda t: torch.zeros(t.shape, dtype=torch.float32, device=dev)
@@ -104,9 +113,10 @@ class Decoder:
                                                         group_poses.data_ptr(), ctypes.byref(d), ctypes.byref(ag),
                                                         _stream()))
             return grads
-        nb = ctypes.c_size_t()
-        L.check(self.lib.gs_decode_scratch_size(ctypes.byref(s), ctypes.byref(nb)))
-        scratch = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
+        if scratch is None:
+            scratch = torch.empty(self.scratch_bytes(), dtype=torch.uint8, device=dev)
+        elif scratch.numel() * scratch.element_size() < self.scratch_bytes():
+            raise ValueError("decode scratch buffer too small")
         L.check(self.lib.gs_decode_backward(ctypes.byref(s), sensor_pose.data_ptr(), group_poses.data_ptr(),
                                             ctypes.byref(d), ctypes.byref(ag), scratch.data_ptr(), _stream()))
         return grads
