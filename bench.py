@@ -222,15 +222,19 @@ class RigStep:
 
 
 def _rig_roofline(rig, steps):
-    """Average compositing launch time (library HIP events on its stream) and the kernel's counts."""
+    """Average compositing launch time (library HIP events on its stream, pair counters off, as in
+    the timed step) and the kernel's pair counts (from a calibration forward with the counters on)."""
     import torch
+    rig.r.set_counters(True)
+    rig.fwd()
+    st = rig.r.status()
+    rig.r.set_counters(False)
     rig.r.set_timing(12 * (steps + 2))
     for _ in range(steps):
         rig.fwd()
     torch.cuda.synchronize()
     stages = rig.r.stage_times(reset=True)
     rig.r.set_timing(0)
-    st = rig.r.status()
     blend_ms, blend_n = stages["blend"]
     t = blend_ms / max(blend_n, 1) / 1e3
     flop = FLOP_PER_PAIR * st["evaluated"]
@@ -247,6 +251,8 @@ def _rig_roofline(rig, steps):
             "hbm_algorithmic_bytes_per_launch": hbm, "hbm_frac": hbm / t / (PEAK_HBM_GBS * 1e9)}
     stage_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
     counts = {"pairs": pairs, "evaluated_pairs": st["evaluated"], "composited_pairs": st["composited"],
+              "wave_pair_iterations": st["wave_pairs"],
+              "lane_utilisation": st["evaluated"] / max(64 * st["wave_pairs"], 1),
               "fp64_pairs": st["fp64_pairs"], "work_items": st["work_items"], "segments": st["segments"],
               "visible": [int(x) for x in st["n_visible"]]}
     return roof, stage_ms, counts
@@ -463,13 +469,16 @@ def bench_frame1080(steps, warmup):
     outs = r.new_outputs()
     fwd = lambda: r.forward([st], sp, gp, outputs=outs)
     ms = _timed(fwd, steps, warmup)
+    r.set_counters(True)
+    fwd()
+    status = r.status()
+    r.set_counters(False)
     r.set_timing(8 * (steps + 2))
     for _ in range(steps):
         fwd()
     torch.cuda.synchronize()
     stages = r.stage_times(reset=True)
     r.set_timing(0)
-    status = r.status()
     if status["overflow"]:
         raise RuntimeError("pair capacity overflow")
     blend_ms, blend_n = stages["blend"]
@@ -496,7 +505,8 @@ def bench_frame1080(steps, warmup):
             "blend_avg_launch_ms": t * 1e3, "blend_tflops": achieved,
             "blend_frac_of_157": achieved / PEAK_FP32_TFLOPS, "pairs": status["pairs"][0],
             "evaluated_pairs": status["evaluated"], "composited_pairs": status["composited"],
-            "fp64_pairs": status["fp64_pairs"],
+            "fp64_pairs": status["fp64_pairs"], "wave_pair_iterations": status["wave_pairs"],
+            "lane_utilisation": status["evaluated"] / max(64 * status["wave_pairs"], 1),
             "grad_finite": bool(all(torch.isfinite(v).all() for v in grads[0].values()))}
 
 
@@ -508,6 +518,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="default tiles and segment length for the step")
+    ap.add_argument("--tiles", default="", help="tile shapes of the step's sensors instead of the autotuner's, "
+                                                "e.g. 32x8,32x8,32x8,16x16,16x16,16x16,32x8")
+    ap.add_argument("--segment-pairs", type=int, default=0, help="segment length with --tiles (0: default)")
+    ap.add_argument("--eager-only", action="store_true",
+                    help="time only eager forward steps of the batched plan, then exit (for profilers)")
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration under rocprofv3) and exit")
@@ -541,7 +556,10 @@ def main():
     extra = {}
 
     tiles, seg = None, 0
-    if not args.no_autotune:
+    if args.tiles:
+        tiles = [tuple(int(v) for v in t.split("x")) for t in args.tiles.split(",")]
+        seg = args.segment_pairs
+    elif not args.no_autotune:
         log("autotune (tile shape per sensor, segment length per plan)")
         probe = RigStep(cam_sc, lid_sc, sensors, dev, batched=True)
         probe.fwd()
@@ -564,6 +582,9 @@ def main():
     if st["overflow"]:
         raise RuntimeError("pair capacity overflow")
     eager_fwd_ms = _timed(rig.fwd, args.steps, args.warmup, stream)
+    if args.eager_only:
+        print(json.dumps({"eager_fwd_ms": eager_fwd_ms, "tiles": tiles, "segment_pairs": seg}), flush=True)
+        return
     rig.capture(rig.fwd, stream)
     log(f"timed forward step x{args.steps} (graph)")
     w0 = time.perf_counter()

@@ -179,18 +179,25 @@ typedef struct gs_run_status {
   int32_t overflow;               /* 1 if any sensor exceeded pair_capacity  */
   int32_t n_visible[GS_MAX_SENSORS];
   int64_t fp64_pairs;             /* pairs re-solved in FP64 (grazing rays)  */
-  int64_t evaluated;              /* ray-surfel pairs the forward evaluates: per ray,
+  int64_t evaluated;              /* (with gs_plan_set_counters) ray-surfel pairs the
+                                     forward evaluates: per ray,
                                      the pairs of its tile list whose pixel
                                      rectangle holds the ray, up to its stop,
                                      except pairs proven to have no valid hit
                                      (cutoff and alpha >= alpha_min) on any pixel
                                      centre of the ray's 8x8 block             */
-  int64_t composited;             /* ray-surfel pairs that contributed             */
+  int64_t composited;             /* (with gs_plan_set_counters) ray-surfel pairs
+                                     that contributed                              */
   int64_t work_items;             /* compositing work items (tiles + extra segments) */
   int64_t segments;               /* segments of split tiles                       */
   int64_t graph_replays;          /* forward calls of this plan that replayed a
                                      captured graph (host count, since creation) */
   int64_t step_launches;          /* gs_plan_launch calls of this plan (host count) */
+  int64_t wave_pairs;             /* (with gs_plan_set_counters) forward pair-loop
+                                     iterations of all wavefronts:
+                                     each evaluates one pair for the wave's 64 rays,
+                                     so evaluated / (64 wave_pairs) is the lane
+                                     utilisation of the compositing kernel     */
 } gs_run_status;
 
 /* Pipeline stages, for per-stage timing. */
@@ -220,6 +227,13 @@ gs_status gs_plan_set_timing(gs_plan* plan, int32_t max_records);
 /* Synchronises `stream` and sums the recorded intervals per stage; clears
  * them when `reset` is non-zero. */
 gs_status gs_plan_stage_times(gs_plan* plan, hipStream_t stream, int32_t reset, gs_stage_times* out);
+
+/* Enables (on != 0) or disables (0, the default) the pair counters of later
+ * forward calls: evaluated and composited ray-surfel pairs and wavefront
+ * pair-loop iterations (gs_run_status).  Counting costs the compositing loop
+ * scalar work, so it is meant for calibration runs; FP64 re-solves are always
+ * counted. */
+gs_status gs_plan_set_counters(gs_plan* plan, int32_t on);
 
 /* Library version string and status text. */
 const char* gs_version(void);

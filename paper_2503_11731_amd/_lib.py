@@ -56,7 +56,7 @@ class RunStatus(ctypes.Structure):
     _fields_ = [("pairs", c_int64 * GS_MAX_SENSORS), ("overflow", c_int32), ("n_visible", c_int32 * GS_MAX_SENSORS),
                 ("fp64_pairs", c_int64), ("evaluated", c_int64), ("composited", c_int64),
                 ("work_items", c_int64), ("segments", c_int64), ("graph_replays", c_int64),
-                ("step_launches", c_int64)]
+                ("step_launches", c_int64), ("wave_pairs", c_int64)]
 
 
 STAGES = ("preprocess", "depth_sort", "emit", "tile_sort", "ranges", "blend", "blend_bwd", "splat_bwd")
@@ -104,6 +104,7 @@ SIGNATURES = [
                                     c_void_p]),
     ("gs_render_backward", c_int32, [c_void_p, POINTER(Scene), c_void_p, c_void_p, POINTER(c_void_p),
                                      POINTER(c_void_p), c_void_p, POINTER(SceneGrads), c_void_p]),
+    ("gs_plan_set_counters", c_int32, [c_void_p, c_int32]),
     ("gs_plan_begin_capture", c_int32, [c_void_p, c_void_p]),
     ("gs_plan_end_capture", c_int32, [c_void_p, c_void_p]),
     ("gs_plan_launch", c_int32, [c_void_p, c_void_p]),

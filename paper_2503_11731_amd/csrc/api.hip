@@ -191,6 +191,7 @@ struct gs_plan {
   hipStream_t step_stream = nullptr;
   bool step_capturing = false;
   int64_t step_launches = 0;
+  bool count_pairs = false;  // forward compositing counts pairs (calibration)
 };
 
 namespace {
@@ -449,7 +450,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       stage_end(p, st, GS_STAGE_RANGES, ev);
       ev = stage_begin(p, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, outputs, nullptr, nullptr);
-      launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, st);
+      launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, p->count_pairs, st);
       stage_end(p, st, GS_STAGE_BLEND, ev);
     }
     return;
@@ -478,7 +479,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   stage_end(p, st, GS_STAGE_RANGES, ev);
   ev = stage_begin(p, st);
   QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, outputs, nullptr, nullptr);
-  launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, st);
+  launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, p->count_pairs, st);
   stage_end(p, st, GS_STAGE_BLEND, ev);
 }
 
@@ -766,6 +767,12 @@ gs_status gs_plan_stage_times(gs_plan* p, hipStream_t st, int32_t reset, gs_stag
   return ok();
 }
 
+gs_status gs_plan_set_counters(gs_plan* p, int32_t on) {
+  if (!p) return fail(GS_ERR_INVALID_ARG, "null plan");
+  p->count_pairs = on != 0;
+  return ok();
+}
+
 gs_status gs_plan_workspace_size(const gs_plan* p, size_t* bytes) {
   if (!p || !bytes) return fail(GS_ERR_INVALID_ARG, "null plan or output");
   *bytes = p->ws_bytes;
@@ -900,7 +907,7 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
     QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, nullptr, outputs,
                              grad_outputs);
     launch_fill_u32(q.counter, 0u, kQueues * kQCntStride, st);
-    launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_bwd, true, st);
+    launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_bwd, true, false, st);
     stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
   }
   for (size_t si = 0; si < p->sensors.size(); ++si) {
@@ -912,7 +919,7 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
       launch_fill_f32(ws.gacc, 0.0f, (size_t)N * kGradFields, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, nullptr, outputs, grad_outputs);
       launch_fill_u32(q.counter, 0u, kQueues * kQCntStride, st);
-      launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_bwd, true, st);
+      launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_bwd, true, false, st);
       stage_end(p, st, GS_STAGE_BLEND_BWD, ev);
     }
     SplatBwdArgs sb;
@@ -954,6 +961,7 @@ gs_status gs_query_status(const gs_plan* p, const void* workspace, hipStream_t s
       out->evaluated += u64at(r, 0);
       out->composited += u64at(r, 2);
       out->fp64_pairs += r[4];
+      out->wave_pairs += u64at(r, 6);
     }
   };
   auto read_queue = [&](const RecordArrays& R, size_t base) -> hipError_t {

@@ -786,7 +786,7 @@ struct BlendShared {
   // per-sensor pair counts (evaluated, composited, FP64 re-solves) of this
   // workgroup, added to the status words once at exit: per-item global
   // atomics on the same few words serialise across the whole device
-  unsigned long long cnt[GS_MAX_SENSORS][3];
+  unsigned long long cnt[GS_MAX_SENSORS][4];
   float lbox[NT / 64][6];  // LiDAR: direction box of each wave's block
   GradArea<NT, BWD> ga;
 };
@@ -861,15 +861,17 @@ __device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
 }
 
 // Composites pairs [b0, b1) of the tile onto the running state (T, acc, last)
-// of every ray not `done`; a ray whose stop rule fires becomes done.  n_eval
-// counts the pixel-covered pairs up to the stop: per ray with lane_counts
-// (wave-uniform), else as a
-// wave total held by every lane (counted with scalar instructions from the
-// rectangle's lane mask); n_contrib and n64 per ray.
-template <int NT, class Ray>
+// of every ray not `done`; a ray whose stop rule fires becomes done.  With
+// COUNT (calibration runs): n_eval counts the pixel-covered pairs up to the
+// stop -- per ray with lane_counts (wave-uniform), else as a wave total held
+// by every lane (counted with scalar instructions from the rectangle's lane
+// mask) -- n_contrib the composited pairs per ray and n_iter the wave's pair
+// iterations; without it they are left alone (the counting is a sizeable
+// part of the pair loop's scalar work).  n64 always counts FP64 re-solves.
+template <int NT, bool COUNT, class Ray>
 __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, BlendShared<NT>& sh,
                           bool lane_counts, bool& done, float& T, float* acc, uint32_t& last, uint32_t& n_eval, uint32_t& n_contrib,
-                          uint32_t& n64) {
+                          uint32_t& n64, uint32_t& n_iter) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
@@ -900,16 +902,19 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         float4 R[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) R[i] = sh.rec[j][i];
-        if (lane_counts)
-          n_eval += (ray.covered(R) && !done) ? 1u : 0u;
-        else
-          n_eval += (uint32_t)__popcll(live & ray.cover_lanes(R));
+        if constexpr (COUNT) {
+          ++n_iter;
+          if (lane_counts)
+            n_eval += (ray.covered(R) && !done) ? 1u : 0u;
+          else
+            n_eval += (uint32_t)__popcll(live & ray.cover_lanes(R));
+        }
         PairEval e;
         const bool hit = ray.eval(a, R, sh.id[j], sh.f64, e, n64) && !done;
         const float Tn = T * (1.0f - e.alpha);
         const bool stop = hit && Tn < ray.K.T_min;
         if (hit && !stop) {
-          ++n_contrib;
+          if constexpr (COUNT) ++n_contrib;
           const float wgt = e.alpha * T;
           float f[C];
           ray.feat(R, e, f);
@@ -976,10 +981,11 @@ __device__ void write_tile(const TileArgs& a, const Ray& ray, bool wr, float T, 
   __syncthreads();  // the staging area is free again
 }
 
-// Adds the wave's counts to the workgroup's counters of sensor si.
+// Adds the wave's counts to the workgroup's counters of sensor si;
+// `iters`: the wave's pair-loop iterations (wave-uniform).
 template <int NT>
 __device__ __forceinline__ void count_wg(BlendShared<NT>& sh, int si, uint32_t evals, uint32_t contribs,
-                                         uint32_t fp64) {
+                                         uint32_t fp64, uint32_t iters = 0u) {
   evals = wave_sum_u32(evals);
   contribs = wave_sum_u32(contribs);
   fp64 = wave_sum_u32(fp64);
@@ -987,6 +993,7 @@ __device__ __forceinline__ void count_wg(BlendShared<NT>& sh, int si, uint32_t e
     if (evals) atomicAdd(&sh.cnt[si][0], (unsigned long long)evals);
     if (contribs) atomicAdd(&sh.cnt[si][1], (unsigned long long)contribs);
     if (fp64) atomicAdd(&sh.cnt[si][2], (unsigned long long)fp64);
+    if (iters) atomicAdd(&sh.cnt[si][3], (unsigned long long)iters);
   }
 }
 
@@ -1216,7 +1223,7 @@ __device__ void bwd_item(const QueueArgs& q, const TileArgs& a, int tile, uint32
 //    carries on: later segments are taken whole from their partials where
 //    the accept test allows, and the first one that it does not is walked by
 //    the workgroup again, for every ray that waits at it.
-template <int NT, class Ray>
+template <int NT, bool COUNT, class Ray>
 __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile, uint32_t gt, uint32_t sg,
                          uint2 rg, bool walk, BlendShared<NT>& sh) {
 #pragma clang fp contract(off)
@@ -1239,7 +1246,7 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
   float acc[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-  uint32_t last = partial ? 0u : rg.x, n_eval_w = 0, n_eval = 0, n_contrib = 0, n64 = 0;
+  uint32_t last = partial ? 0u : rg.x, n_eval_w = 0, n_eval = 0, n_contrib = 0, n64 = 0, n_iter = 0;
   // the ray composites segment `need` next (kNone: nothing left for it here)
   uint32_t need = ray.inside ? sg : kNone;
   if (walk) {
@@ -1264,8 +1271,8 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
     done = !active;
     const uint32_t b0 = rg.x + cur * L;
     // a segment keeps per-ray counts: the merge takes them ray by ray
-    composite<NT>(a, ray, b0, split ? min(b0 + L, rg.y) : rg.y, sh, partial, done, T, acc, last,
-                  partial ? n_eval : n_eval_w, n_contrib, n64);
+    composite<NT, COUNT>(a, ray, b0, split ? min(b0 + L, rg.y) : rg.y, sh, partial, done, T, acc, last,
+                  partial ? n_eval : n_eval_w, n_contrib, n64, n_iter);
     if (!walk) break;
     if (active) {
       need = done ? kNone
@@ -1283,15 +1290,15 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
     cur = nxt;
   }
   if (walk) {
-    count_wg(sh, si, lane0_only(n_eval_w) + n_eval, n_contrib, n64);
+    count_wg(sh, si, lane0_only(n_eval_w) + n_eval, n_contrib, n64, n_iter);
     return;
   }
   if (!partial) {
-    count_wg(sh, si, lane0_only(n_eval_w), n_contrib, n64);
+    count_wg(sh, si, lane0_only(n_eval_w), n_contrib, n64, n_iter);
     write_tile<NT>(a, ray, ray.inside, T, acc, last, sh);
     return;
   }
-  count_wg(sh, si, 0u, 0u, n64);
+  count_wg(sh, si, 0u, 0u, n64, n_iter);
   if (ray.inside) {
 #pragma unroll
     for (int c = 0; c < C; ++c) part[c * ps + pe] = acc[c];
@@ -1392,15 +1399,15 @@ __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& d
 
 // Persistent compositing over (tile, segment) items and, in the forward pass,
 // the walk entries the merges list.
-template <int NT, bool BWD, int KINDS>
-__global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
+template <int NT, bool BWD, int KINDS, bool COUNT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT ? 1 : 4))) void k_blend_queue(QueueArgs q) {
   __shared__ BlendShared<NT, BWD> sh;
   uint32_t* s_u = sh.u;
   const uint32_t n_items = min(*q.n_items, q.cap_items);
   bool main_left = true;  // thread 0 only
   uint32_t drained = 0, xcc = 0;
   asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-  for (int i = threadIdx.x; i < GS_MAX_SENSORS * 3; i += NT) (&sh.cnt[0][0])[i] = 0ull;
+  for (int i = threadIdx.x; i < GS_MAX_SENSORS * 4; i += NT) (&sh.cnt[0][0])[i] = 0ull;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0)
@@ -1433,23 +1440,24 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
     } else {
       const bool walk = act == kActWalk;
       if (cam)
-        fwd_item<NT, CamRay>(q, a, si, tile, gt, sg, rg, walk, sh);
+        fwd_item<NT, COUNT, CamRay>(q, a, si, tile, gt, sg, rg, walk, sh);
       else if (KINDS & kKindLidar)
-        fwd_item<NT, LidarRay>(q, a, si, tile, gt, sg, rg, walk, sh);
+        fwd_item<NT, COUNT, LidarRay>(q, a, si, tile, gt, sg, rg, walk, sh);
     }
   }
   // the workgroup's counts, once per sensor and counter
   __syncthreads();
   const int i = threadIdx.x;
-  if (!BWD && i < q.n_sensors * 3) {
+  if (!BWD && i < q.n_sensors * 4) {
     const unsigned long long v = (&sh.cnt[0][0])[i];
     uint32_t xcc;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-    uint32_t* st = q.tiles[i / 3].status + kStRep + 8 * (xcc & 7u);
+    uint32_t* st = q.tiles[i / 4].status + kStRep + 8 * (xcc & 7u);
     if (v) {
-      if (i % 3 == 0) atomicAdd(reinterpret_cast<unsigned long long*>(st), v);
-      else if (i % 3 == 1) atomicAdd(reinterpret_cast<unsigned long long*>(st + 2), v);
-      else atomicAdd(st + 4, (uint32_t)v);
+      if (i % 4 == 0) atomicAdd(reinterpret_cast<unsigned long long*>(st), v);
+      else if (i % 4 == 1) atomicAdd(reinterpret_cast<unsigned long long*>(st + 2), v);
+      else if (i % 4 == 2) atomicAdd(st + 4, (uint32_t)v);
+      else atomicAdd(reinterpret_cast<unsigned long long*>(st + 6), v);
     }
   }
 }
@@ -1459,14 +1467,17 @@ __global__ __launch_bounds__(NT) void k_blend_queue(QueueArgs q) {
 #define GS_TILE_RAYS(X) X(64) X(128) X(256) X(512)
 #define GS_KINDS(X, NT) X(NT, 1) X(NT, 2) X(NT, 3)
 
-void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, hipStream_t st) {
-#define KCASE(NT, K)                                                                       \
-  if (rays == NT && kinds == K) {                                                          \
-    if (backward)                                                                          \
-      hipLaunchKernelGGL((k_blend_queue<NT, true, K>), dim3(grid), dim3(NT), 0, st, q);    \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_blend_queue<NT, false, K>), dim3(grid), dim3(NT), 0, st, q);   \
-    return;                                                                                \
+void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, bool count,
+                        hipStream_t st) {
+#define KCASE(NT, K)                                                                              \
+  if (rays == NT && kinds == K) {                                                                 \
+    if (backward)                                                                                 \
+      hipLaunchKernelGGL((k_blend_queue<NT, true, K, false>), dim3(grid), dim3(NT), 0, st, q);    \
+    else if (count)                                                                               \
+      hipLaunchKernelGGL((k_blend_queue<NT, false, K, true>), dim3(grid), dim3(NT), 0, st, q);    \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_blend_queue<NT, false, K, false>), dim3(grid), dim3(NT), 0, st, q);   \
+    return;                                                                                       \
   }
 #define CASE(NT) GS_KINDS(KCASE, NT)
   GS_TILE_RAYS(CASE)
@@ -1479,8 +1490,8 @@ int blend_blocks_per_cu(int rays, int kinds, bool backward) {
   hipError_t e = hipErrorInvalidValue;
 #define KCASE(NT, K)                                                                                         \
   if (rays == NT && kinds == K)                                                                              \
-    e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, true, K>, NT, 0)      \
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, false, K>, NT, 0);
+    e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, true, K, false>, NT, 0) \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, false, K, false>, NT, 0);
 #define CASE(NT) GS_KINDS(KCASE, NT)
   GS_TILE_RAYS(CASE)
 #undef CASE

@@ -88,9 +88,10 @@ enum {
   kStSortStall = 8 /* a sort or scan look-back wait gave up */
 };
 // The compositing kernel adds its pair counts to one of 8 replicas (one per
-// XCD) of the three counters, words kStRep + 8 x: [0..1] evaluated (u64),
-// [2..3] composited (u64), [4] FP64 re-solves; the host sums them.  Atomics
-// of every workgroup on the same three words serialise across the device.
+// XCD) of the four counters, words kStRep + 8 x: [0..1] evaluated (u64),
+// [2..3] composited (u64), [4] FP64 re-solves, [6..7] wave pair-loop
+// iterations (u64); the host sums them.  Atomics of every workgroup on the
+// same words serialise across the device.
 constexpr int kStRep = 16;
 constexpr int kStWords = kStRep + 8 * 8;
 

@@ -148,7 +148,10 @@ void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipS
 
 // blend.hip
 // kinds: bit 0 camera, bit 1 LiDAR (the sensor kinds the launch serves)
-void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, hipStream_t st);
+// count: the forward also counts evaluated / composited pairs and pair-loop
+// iterations into the status words (calibration runs).
+void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, bool count,
+                        hipStream_t st);
 int blend_blocks_per_cu(int rays, int kinds, bool backward);
 bool tile_shape_supported(int tw, int th);
 

@@ -186,8 +186,12 @@ class Renderer:
         out = dict(pairs=list(st.pairs[:n]), overflow=bool(st.overflow), n_visible=list(st.n_visible[:n]),
                    fp64_pairs=int(st.fp64_pairs), evaluated=int(st.evaluated), composited=int(st.composited),
                    work_items=int(st.work_items), segments=int(st.segments),
-                   graph_replays=int(st.graph_replays), step_launches=int(st.step_launches), rc=rc)
+                   graph_replays=int(st.graph_replays), step_launches=int(st.step_launches), wave_pairs=int(st.wave_pairs), rc=rc)
         return out
+
+    def set_counters(self, on: bool):
+        """Count evaluated / composited pairs and pair-loop iterations in later forwards (calibration)."""
+        L.check(self.lib.gs_plan_set_counters(self.plan, int(bool(on))))
 
     def set_timing(self, max_records: int):
         """Record HIP events around every stage of the next calls (0 disables)."""

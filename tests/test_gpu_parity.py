@@ -165,6 +165,17 @@ def test_forward_is_deterministic_and_order_invariant():
     _, _, _, _, outs3 = gpu_render(sp_scene, sens, gs.PRODUCTION)
     # keys are tie-free, so the composited order and every float op are the same
     assert torch.equal(a, outs3[0])
+    # the pair counters of calibration runs change no output
+    r.set_counters(True)
+    outs4 = r.forward([st], sp, gp)
+    st4 = r.status()
+    torch.cuda.synchronize()
+    assert torch.equal(a, outs4[0])
+    assert st4["evaluated"] >= st4["composited"] > 0 and st4["wave_pairs"] > 0
+    assert st4["evaluated"] <= 64 * st4["wave_pairs"]
+    r.set_counters(False)
+    r.forward([st], sp, gp)
+    assert r.status()["evaluated"] == 0
 
 
 def grad_check(scene, sensor, opts, tile, keys, channels_seed=0, segment_pairs=0):
