@@ -95,10 +95,17 @@ def spec_frames(scene, sensor):
     return fr, np.stack(poses)
 
 
+def is_lidar(sensor) -> bool:
+    """LiDAR (range, intensity, alpha) rather than a camera (pinhole or cylindrical; 8 channels)."""
+    return sensor["kind"] == "lidar"
+
+
 def spec_bins(scene, sensor, opts):
     fr, poses = spec_frames(scene, sensor)
     if sensor["kind"] == "pinhole":
         b = spec32.pinhole_bins(fr, sensor, opts)
+    elif sensor["kind"] == "cylindrical":
+        b = spec32.cylindrical_bins(fr, scene["scale"], sensor, opts)
     else:
         b = spec32.lidar_bins(fr, scene["scale"], sensor, opts)
     b["normal_sign"] = spec32.normal_sign(fr["n_s"], fr["mu_s"])
@@ -130,6 +137,19 @@ def _rays(sensor, ray_ids: np.ndarray):
         hv = np.stack([np.zeros_like(yn), -np.ones_like(yn), yn], 1)
         return dict(hu=torch.as_tensor(hu), hv=torch.as_tensor(hv), px=torch.as_tensor(px),
                     py=torch.as_tensor(py), i=i, j=j)
+    if sensor["kind"] == "cylindrical":
+        # Eq. 4: h_u = (cos phi, 0, -sin phi); h_v is the plane through the x-axis-free
+        # line of height y_n on the unit cylinder: (y_n sin phi, -1, y_n cos phi)
+        tabs = spec32.cylindrical_tables(sensor)
+        sp = tabs["sin_phi"][i].astype(np.float64)
+        cp = tabs["cos_phi"][i].astype(np.float64)
+        yn = tabs["yn"][j].astype(np.float64)
+        hu = np.stack([cp, np.zeros_like(cp), -sp], 1)
+        hv = np.stack([yn * sp, -np.ones_like(yn), yn * cp], 1)
+        hdir = np.stack([sp, np.zeros_like(sp), cp], 1)  # the column's horizontal direction
+        return dict(hu=torch.as_tensor(hu), hv=torch.as_tensor(hv), hdir=torch.as_tensor(hdir),
+                    px=torch.as_tensor(i.astype(np.float64) + 0.5), py=torch.as_tensor(j.astype(np.float64) + 0.5),
+                    i=i, j=j)
     tabs = spec32.lidar_tables(sensor)
     ca = tabs["cos_az"][i].astype(np.float64)
     sa = tabs["sin_az"][i].astype(np.float64)
@@ -165,7 +185,7 @@ def splat_quantities(scene, sensor, bins, params):
     out = dict(M=M, mu_s=mu_s, opacity=params["opacity"])
     sign = torch.as_tensor(bins["normal_sign"].astype(np.float64))
     out["normal"] = n_s * sign[:, None]
-    if sensor["kind"] == "pinhole":
+    if not is_lidar(sensor):
         if "sh" in params and params["sh"] is not None:
             dirs = torch.einsum("nji,nj->ni", Rm, mu_s)  # R^T mu_s: object-frame ray direction
             dirs = dirs / torch.linalg.norm(dirs, dim=1, keepdim=True)
@@ -243,7 +263,7 @@ def _grid_pairs_lidar(bins, sensor, stride):
 def _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride=None):
     """(ray position, surfel) candidate pairs before the per-pair support test."""
     if grid_stride is not None and mode != "brute":
-        if sensor["kind"] == "pinhole":
+        if not is_lidar(sensor):
             return _grid_pairs(bins, sensor, grid_stride)
         return _grid_pairs_lidar(bins, sensor, grid_stride)
     W = int(sensor["width"])
@@ -255,7 +275,7 @@ def _candidate_pairs(bins, sensor, ray_ids, mode, grid_stride=None):
         return rp, sp
     touch = np.nonzero(bins["touch"])[0]
     full_image = R == int(sensor["width"]) * int(sensor["height"]) and np.array_equal(ray_ids, np.arange(R))
-    lidar = sensor["kind"] != "pinhole"
+    lidar = is_lidar(sensor)
     if full_image:
         i_lo, i_hi = bins["i_lo"][touch], bins["i_hi"][touch]
         j_lo, j_hi = bins["j_lo"][touch], bins["j_hi"][touch]
@@ -321,7 +341,7 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     """
     opts = make_opts(**(opts or {})) if not isinstance(opts, dict) or "tile_w" not in opts else opts
     W, H = int(sensor["width"]), int(sensor["height"])
-    lidar = sensor["kind"] != "pinhole"
+    lidar = is_lidar(sensor)
     full = rays is None
     grid_stride = None
     if isinstance(rays, tuple) and rays[0] == "grid":
@@ -514,6 +534,19 @@ def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
         if opts["lowpass"]:
             pcx = sensor["fx"] * mu[:, 0] / mu[:, 2] + sensor["cx"]
             pcy = sensor["fy"] * mu[:, 1] / mu[:, 2] + sensor["cy"]
+            dx = rays_t["px"][rp_t] - pcx
+            dy = rays_t["py"][rp_t] - pcy
+            rho_lp = lp * (dx * dx + dy * dy)
+    elif sensor["kind"] == "cylindrical":
+        # cylindrical depth: distance from the camera's vertical axis, signed
+        # along the column's horizontal direction (negative behind the camera)
+        hd = rays_t["hdir"][rp_t]
+        depth_hit = (hd * X).sum(1) / torch.linalg.norm(hd, dim=1)
+        r_c = torch.sqrt(mu[:, 0] * mu[:, 0] + mu[:, 2] * mu[:, 2])
+        depth_c = r_c
+        if opts["lowpass"]:
+            pcx = sensor["fx"] * torch.atan2(mu[:, 0], mu[:, 2]) + sensor["cx"]
+            pcy = sensor["fy"] * mu[:, 1] / r_c + sensor["cy"]
             dx = rays_t["px"][rp_t] - pcx
             dy = rays_t["py"][rp_t] - pcy
             rho_lp = lp * (dx * dx + dy * dy)

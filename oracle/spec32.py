@@ -322,6 +322,109 @@ def lidar_bins(fr: dict, scale, sensor: dict, opts: dict):
                 wrap=wrap, full_cols=full | all_tx)
 
 
+# ----------------------------------------------------------------------------
+# cylindrical (fisheye) camera binning
+# ----------------------------------------------------------------------------
+
+def cylindrical_tables(sensor: dict):
+    """The cylindrical camera as FP32 tables (FP64 values rounded to nearest).
+
+    Column i looks at the horizontal angle phi_i = (i + 1/2 - c_x) / f_x about
+    the camera's y axis (Eq. 4), row j at height y_n = (j + 1/2 - c_y) / f_y on
+    the unit cylinder: the ray direction is (sin phi, y_n, cos phi).  Both sides
+    use these rounded values as the definition of the rays.
+    """
+    W, H = int(sensor["width"]), int(sensor["height"])
+    fx, fy = float(sensor["fx"]), float(sensor["fy"])
+    cx, cy = float(sensor["cx"]), float(sensor["cy"])
+    phi = [(i + 0.5 - cx) / fx for i in range(W)]
+    sin_phi = np.array([math.sin(t) for t in phi], np.float64).astype(F32)
+    cos_phi = np.array([math.cos(t) for t in phi], np.float64).astype(F32)
+    yn = np.array([(j + 0.5 - cy) / fy for j in range(H)], np.float64).astype(F32)
+    return dict(sin_phi=sin_phi, cos_phi=cos_phi, yn=yn)
+
+
+def cylindrical_bins(fr: dict, scale, sensor: dict, opts: dict):
+    """Visibility, pixel rectangle, tile rectangle and depth key for a cylindrical camera.
+
+    Pixel (x, y) = (c_x + f_x phi, c_y + f_y y_n) for the ray of direction
+    (sin phi, y_n, cos phi).  The support lies inside the ball of radius
+    R = sqrt(k) max(s_u, s_v) around mu: its rays have |phi - phi_c| <=
+    asin(R / r) with r = sqrt(mu_x^2 + mu_z^2) (the ball's shadow on the
+    horizontal plane), and y_n = y / r' over the box y in [mu_y - R, mu_y + R],
+    r' in [r - R, r + R].  The low-pass disc has radius sqrt(k / lp) pixels
+    around the projected centre (c_x + f_x phi_c, c_y + f_y mu_y / r).  Angles
+    come from the A&S arctangent (error <= 1e-5 rad, inside the one-pixel pad).
+    Visible iff r^2 > (R + z_near)^2 (the ball is wholly outside the near
+    cylinder).  A range that crosses the back of the camera (phi = +-pi) takes
+    every column.  Key = r^2 (monotone in the cylindrical depth).
+    """
+    mu = _f(fr["mu_s"])
+    scale = _f(scale)
+    W, H = int(sensor["width"]), int(sensor["height"])
+    fx, fy = F32(sensor["fx"]), F32(sensor["fy"])
+    cx, cy = F32(sensor["cx"]), F32(sensor["cy"])
+    z_near = F32(sensor["z_near"])
+    k = F32(opts["cutoff2"])
+    lp = F32(opts["lp_inv_sigma2"])
+    use_lp = bool(opts["lowpass"])
+    tw, th = int(opts["tile_w"]), int(opts["tile_h"])
+    with np.errstate(all="ignore"):
+        r2 = mu[0] * mu[0] + mu[2] * mu[2]
+        r = np.sqrt(r2)
+        R = np.sqrt(k) * np.maximum(scale[0], scale[1])
+        Rn = R + z_near
+        vis = fr["valid"] & (r2 > Rn * Rn) & np.isfinite(r2) & np.isfinite(R) & np.isfinite(mu[1])
+        phi_c = atan2_spec(mu[0], mu[2])
+        q = np.where(vis, R / r, F32(0.0)).astype(F32)
+        dphi = asin_spec(np.minimum(q, F32(1.0)))
+        y_lo, y_hi = mu[1] - R, mu[1] + R
+        r_lo, r_hi = r - R, r + R
+        yn_lo = np.minimum(y_lo / r_lo, y_lo / r_hi)
+        yn_hi = np.maximum(y_hi / r_lo, y_hi / r_hi)
+        a_lo, a_hi = phi_c - dphi, phi_c + dphi
+        back = (a_lo < -PI_F) | (a_hi > PI_F)
+        xlo, xhi = fx * a_lo, fx * a_hi
+        ylo, yhi = fy * yn_lo, fy * yn_hi
+        if use_lp:
+            rl = np.sqrt(k / lp)
+            pcx = fx * phi_c
+            pcy = fy * (mu[1] / r)
+            xlo = np.minimum(xlo, pcx - rl)
+            xhi = np.maximum(xhi, pcx + rl)
+            ylo = np.minimum(ylo, pcy - rl)
+            yhi = np.maximum(yhi, pcy + rl)
+        one = F32(1.0)
+        half = F32(0.5)
+        X_lo = ((xlo - one) + cx) - half
+        X_hi = ((xhi + one) + cx) - half
+        Y_lo = ((ylo - one) + cy) - half
+        Y_hi = ((yhi + one) + cy) - half
+        vis &= np.isfinite(X_lo) & np.isfinite(X_hi) & np.isfinite(Y_lo) & np.isfinite(Y_hi)
+    X_lo = np.where(vis, X_lo, F32(0.0))
+    X_hi = np.where(vis, X_hi, F32(0.0))
+    Y_lo = np.where(vis, Y_lo, F32(0.0))
+    Y_hi = np.where(vis, Y_hi, F32(0.0))
+    X_lo = np.where(back, F32(-2.0), np.minimum(np.maximum(X_lo, F32(-2.0)), F32(W + 2)))
+    X_hi = np.where(back, F32(W + 2), np.minimum(np.maximum(X_hi, F32(-2.0)), F32(W + 2)))
+    Y_lo = np.minimum(np.maximum(Y_lo, F32(-2.0)), F32(H + 2))
+    Y_hi = np.minimum(np.maximum(Y_hi, F32(-2.0)), F32(H + 2))
+    i_lo = np.maximum(np.ceil(X_lo).astype(np.int64), 0)
+    i_hi = np.minimum(np.floor(X_hi).astype(np.int64), W - 1)
+    j_lo = np.maximum(np.ceil(Y_lo).astype(np.int64), 0)
+    j_hi = np.minimum(np.floor(Y_hi).astype(np.int64), H - 1)
+    touch = vis & (i_lo <= i_hi) & (j_lo <= j_hi)
+    n_tx = (W + tw - 1) // tw
+    tx_lo, tx_hi = i_lo // tw, i_hi // tw
+    ty_lo, ty_hi = j_lo // th, j_hi // th
+    n_tiles = np.where(touch, (tx_hi - tx_lo + 1) * (ty_hi - ty_lo + 1), 0)
+    key = np.where(vis, r2, F32(0.0)).astype(F32)
+    return dict(visible=vis, touch=touch, i_lo=i_lo, i_hi=i_hi, j_lo=j_lo, j_hi=j_hi,
+                tx_lo=tx_lo, tx_hi=tx_hi, ty_lo=ty_lo, ty_hi=ty_hi, n_tx=n_tx,
+                n_ty=(H + th - 1) // th, n_tiles=n_tiles, key=key,
+                key_bits=key.view(np.uint32).astype(np.int64), wrap=np.zeros_like(vis))
+
+
 def tile_pairs(bins: dict):
     """(tile id, splat index) pairs of every touched tile, in the FP32 spec's order.
 
