@@ -115,6 +115,18 @@ def pinhole(width: int, height: int, f: float, pose=None, cx=None, cy=None, z_ne
                 z_near=float(z_near), pose=np.asarray(pose, dtype=F32).reshape(3, 4).copy())
 
 
+def cylindrical(width: int, height: int, hfov_deg: float, pose=None, z_near=0.2) -> dict:
+    """Cylindrical (fisheye) camera: columns span hfov_deg about the camera's y
+    axis (f_x pixels per radian), rows are heights on the unit cylinder with
+    f_y = f_x; x right, y down, z forward; pose is world->camera [3,4]."""
+    if pose is None:
+        pose = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    f = float(width) / math.radians(hfov_deg)
+    return dict(kind="cylindrical", width=int(width), height=int(height), fx=f, fy=f,
+                cx=float(width / 2), cy=float(height / 2), z_near=float(z_near),
+                pose=np.asarray(pose, dtype=F32).reshape(3, 4).copy())
+
+
 def lidar_spinning(n_beams=128, n_az=1800, el_min_deg=-25.0, el_max_deg=15.0, pose=None,
                    z_near=0.5) -> dict:
     """Spinning LiDAR: x forward, y left, z up; beams uniform in elevation.

@@ -69,7 +69,12 @@ typedef enum gs_status {
   GS_ERR_UNSUPPORTED = 4    /* valid but unsupported combination of options     */
 } gs_status;
 
-enum gs_sensor_kind { GS_SENSOR_PINHOLE = 0, GS_SENSOR_LIDAR = 1 };
+/* Sensor kinds: pinhole camera (Eq. 3), spinning LiDAR (Eq. 5) and
+ * cylindrical (fisheye) camera (Eq. 4: column i looks at the angle
+ * phi = (i + 1/2 - cx) / fx about the camera's y axis, row j at height
+ * y_n = (j + 1/2 - cy) / fy on the unit cylinder, ray (sin phi, y_n, cos phi);
+ * its depth channel is the distance from the camera's vertical axis). */
+enum gs_sensor_kind { GS_SENSOR_PINHOLE = 0, GS_SENSOR_LIDAR = 1, GS_SENSOR_CYLINDRICAL = 2 };
 
 /* Maximum number of surfel groups (static scene + posed objects) per scene. */
 #define GS_MAX_GROUPS 64
@@ -79,10 +84,12 @@ enum gs_sensor_kind { GS_SENSOR_PINHOLE = 0, GS_SENSOR_LIDAR = 1 };
 /* Sensor model (Eq. 3 pinhole, Eq. 5 spinning LiDAR). */
 typedef struct gs_sensor_desc {
   int32_t kind;              /* gs_sensor_kind                                     */
-  int32_t width, height;     /* pinhole: pixels; LiDAR: azimuth steps x beams        */
-  float fx, fy, cx, cy;      /* pinhole intrinsics; pixel (i,j) centre = (i+.5,j+.5) */
+  int32_t width, height;     /* cameras: pixels; LiDAR: azimuth steps x beams        */
+  float fx, fy, cx, cy;      /* camera intrinsics; pixel (i,j) centre = (i+.5,j+.5);
+                                cylindrical: fx in pixels per radian              */
   const double* elevations;  /* LiDAR: host array of `height` ascending angles (rad) */
-  float z_near;              /* camera: min hit depth; LiDAR: min hit range          */
+  float z_near;              /* camera: min depth (cylindrical: min distance from the
+                                vertical axis); LiDAR: min range                  */
   int32_t scene;             /* index of the scene this sensor renders              */
   int32_t tile_w, tile_h;    /* screen tile; 0 = default: 32x8, except 16x8 for a
                                 LiDAR sensor of a per-sensor (not batched) plan */
@@ -167,7 +174,8 @@ typedef struct gs_plan_desc {
 
 typedef struct gs_plan gs_plan; /* opaque, owned by the library */
 
-/* Output channel counts: camera [8][H][W] = rgb(3), depth, normal(3), alpha;
+/* Output channel counts: camera (pinhole or cylindrical) [8][H][W] = rgb(3),
+ * depth, normal(3), alpha;
  * LiDAR [3][H][W] = range, intensity, alpha.  Depth/range and normal are
  * unnormalised sums (divide by alpha for the expected value). */
 #define GS_CAMERA_CHANNELS 8

@@ -138,12 +138,12 @@ def _rays(sensor, ray_ids: np.ndarray):
         return dict(hu=torch.as_tensor(hu), hv=torch.as_tensor(hv), px=torch.as_tensor(px),
                     py=torch.as_tensor(py), i=i, j=j)
     if sensor["kind"] == "cylindrical":
-        # Eq. 4: h_u = (cos phi, 0, -sin phi); h_v is the plane through the x-axis-free
-        # line of height y_n on the unit cylinder: (y_n sin phi, -1, y_n cos phi)
+        # Eq. 4: h_u = (cos phi, 0, -sin phi); h_v = (y_n sin phi, -1, y_n cos phi),
+        # the plane through the camera's x-free line at height y_n on the unit cylinder
         tabs = spec32.cylindrical_tables(sensor)
-        sp = tabs["sin_phi"][i].astype(np.float64)
-        cp = tabs["cos_phi"][i].astype(np.float64)
-        yn = tabs["yn"][j].astype(np.float64)
+        sp = tabs["sin_phi"][i]
+        cp = tabs["cos_phi"][i]
+        yn = tabs["yn"][j]
         hu = np.stack([cp, np.zeros_like(cp), -sp], 1)
         hv = np.stack([yn * sp, -np.ones_like(yn), yn * cp], 1)
         hdir = np.stack([sp, np.zeros_like(sp), cp], 1)  # the column's horizontal direction
@@ -328,11 +328,14 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     params: optional dict of FP64 torch tensors to use as inputs (e.g. the
     output of the decode oracle); gradients then flow into them.
     margins: also return per ray the smallest relative distance of any of its
-    compositing decisions to the decision's threshold ('margin').
+    compositing decisions to the decision's threshold ('margin'; with
+    alternatives, in the measure that flags them, see _relative_distances).
     alternatives: a relative tolerance tol.  Every decision of a ray that lies
     within tol of its threshold -- a pair entering or leaving the support
     (cutoff, z_near), the alpha_min skip, the T_min stop, the choice between
-    rho and the low-pass term (which sets the pair's depth) -- is flagged, and the
+    rho and the low-pass term (which sets the pair's depth) -- is flagged (a
+    decision on rho also when rho lies within the first-order error bound of
+    an FP32 evaluation of the solve, _fp32_uv_error), and the
     result also holds, for every ray with 1..max_flags flags, the outputs the
     definition gives when any non-empty subset of those decisions goes the
     other way ('alts': rays, values [n_alt, C] in the channel order of the
@@ -427,7 +430,7 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     considered = listed & (torch.arange(K)[None, :] <= first_stop[:, None])
     if margins:
         result["margin"] = _margins(sol, rp, pos, R, K, alpha.detach(), test, skip, considered, opts,
-                                    sensor).reshape(shape)
+                                    sensor, tol).reshape(shape)
     if alternatives is not None:
         with torch.no_grad():
             alt = dict(alpha=grid(torch.clamp(o.detach() * torch.exp(-0.5 * sol["alt"]["rho_hat"]),
@@ -496,6 +499,73 @@ def _accumulate(active, alpha, feat, bg):
     return out, w, T_final
 
 
+def _fp32_uv_error(M, mu, u, v, rays_t, rp_t, sensor, opts):
+    """First-order bound on the (u, v) error of the ray-splat solve carried
+    out in FP32 (test infrastructure: it sizes the window within which a
+    decision on rho is verified both ways, not any output).
+
+    The FP32 solve evaluates the homography of Eq. 2 on pixel offsets from the
+    projected centre (LiDAR: on direction offsets from the centre direction),
+    h' = P d + e3 normalised so that h'_2 = 1 at the centre; a surfel seen
+    nearly edge-on makes P's rows large and the evaluation cancels.  With
+    kappa the largest absolute sum of the (u, v) rows of P plus 3.4 times that
+    of its h'_2 row, the error is bounded by
+      pinhole      (2^-22 kappa |d|_inf + 2^-20) / |h'_2|
+      cylindrical  (2^-21 kappa |(X, Y)|_inf + 2^-20) / |h'_2|, X = f tan dphi,
+                   Y = dy + (p_y - c_y)(sec dphi - 1) in the centre's column frame
+      LiDAR        (2^-23 kappa (2 |d|_inf + |d_p|_inf + |c|_inf) + 2^-20) / |h'_2|,
+                   d = ray - centre direction, c = tile reference ray - centre
+                   direction, d_p = ray - tile reference ray
+    (two roundings of the offsets' size, two in the products, the centre held
+    to twice FP32 precision in the tile's frame)."""
+    det = torch.linalg.det(M)
+    adj = torch.linalg.inv(M) * det[:, None, None]
+    kind = sensor["kind"]
+    if kind in ("pinhole", "cylindrical"):
+        if kind == "pinhole":
+            muz = mu[:, 2]
+            pcx = sensor["fx"] * mu[:, 0] / muz + sensor["cx"]
+        else:
+            muz = torch.sqrt(mu[:, 0] ** 2 + mu[:, 2] ** 2)
+            c, sn = mu[:, 2] / muz, mu[:, 0] / muz
+            adj = torch.stack([adj[:, :, 0] * c[:, None] - adj[:, :, 2] * sn[:, None], adj[:, :, 1],
+                               adj[:, :, 0] * sn[:, None] + adj[:, :, 2] * c[:, None]], 2)
+            pcx = sensor["fx"] * torch.atan2(mu[:, 0], mu[:, 2]) + sensor["cx"]
+        pcy = sensor["fy"] * mu[:, 1] / muz + sensor["cy"]
+        P = torch.stack([adj[:, :, 0] * (muz / (sensor["fx"] * det))[:, None],
+                         adj[:, :, 1] * (muz / (sensor["fy"] * det))[:, None]], 2)  # [P, 3 rows, 2]
+        dx = rays_t["px"][rp_t] - pcx
+        dy = rays_t["py"][rp_t] - pcy
+        if kind == "pinhole":
+            X, Y, w = dx, dy, 2.0 ** -22
+        else:
+            ph = dx / sensor["fx"]
+            X = sensor["fx"] * torch.tan(ph)
+            Y = dy + (rays_t["py"][rp_t] - sensor["cy"]) * (1.0 / torch.cos(ph) - 1.0)
+            w = 2.0 ** -21
+        rs = P.abs().sum(2)
+        kap = torch.maximum(rs[:, 0], rs[:, 1]) + 3.4 * rs[:, 2]
+        h2 = 1.0 + P[:, 2, 0] * X + P[:, 2, 1] * Y
+        e = (w * kap * torch.maximum(X.abs(), Y.abs()) + 2.0 ** -20) / h2.abs()
+    else:
+        rn = torch.linalg.norm(mu, dim=1)
+        Q = adj * (rn / det)[:, None, None]
+        mh = mu / rn[:, None]
+        d = rays_t["d"][rp_t] - mh
+        tw, th = int(opts["tile_w"]), int(opts["tile_h"])
+        i, j = rays_t["i"][rp_t.numpy()], rays_t["j"][rp_t.numpy()]
+        ref = (j // th) * th * int(sensor["width"]) + (i // tw) * tw
+        dt = _rays(sensor, ref)["d"]
+        c = dt - mh
+        dp = rays_t["d"][rp_t] - dt
+        rs = Q.abs().sum(2)
+        kap = torch.maximum(rs[:, 0], rs[:, 1]) + 3.4 * rs[:, 2]
+        h2 = 1.0 + (Q[:, 2, :] * d).sum(1)
+        e = (2.0 ** -23 * kap * (2.0 * d.abs().amax(1) + dp.abs().amax(1) + c.abs().amax(1)) + 2.0 ** -20) / h2.abs()
+    # rho's error: 2 |(u, v)|_1 e + 2 e^2, taken with a 20% margin
+    return 2.4 * (u.abs() + v.abs()) * e + 2.0 * e * e
+
+
 def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
     """Per-pair ray-splat solve (Eq. 2): (u, v), rho_hat, depth, support mask,
     and `near`: the support decision, or the choice between the surfel's own
@@ -561,6 +631,8 @@ def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
             dd = d - mh
             rho_lp = lp * (dd * dd).sum(1) / (step * step)
     c2, zn = opts["cutoff2"], sensor["z_near"]
+    with torch.no_grad():
+        drho = _fp32_uv_error(M.detach(), mu.detach(), u.detach(), v.detach(), rays_t, rp_t, sensor, opts)
     if opts["lowpass"]:
         use_rho = rho <= rho_lp
         rho_hat = torch.where(use_rho, rho, rho_lp)
@@ -570,50 +642,66 @@ def _solve(sq, rays_t, rp, sp, sensor, opts, scene, tol=0.0):
         depth = depth_hit
     support = ok & (rho_hat <= c2) & (depth > zn)
     with torch.no_grad():
-        near = ok & (((rho_hat - c2).abs() <= tol * c2) | ((depth - zn).abs() <= tol * zn))
+        # a window of tol relative, widened to rho's FP32 error bound where
+        # rho itself is compared (not the low-pass term, which has no such error)
+        wr = drho if tol > 0.0 else torch.zeros_like(drho)
+        wt = torch.full_like(wr, tol * c2)
+        rho_dec = use_rho if opts["lowpass"] else torch.ones_like(ok)
+        wc = torch.where(rho_dec, torch.maximum(wt, wr), wt)
+        near = ok & (((rho_hat - c2).abs() <= wc) | ((depth - zn).abs() <= tol * zn))
         if opts["lowpass"]:
             big = torch.maximum(rho, rho_lp)
-            d_lp = torch.where(big > 0, (rho - rho_lp).abs() / torch.where(big > 0, big, torch.ones_like(big)),
+            scale = torch.maximum(big, wr / tol) if tol > 0.0 else big
+            d_lp = torch.where(big > 0, (rho - rho_lp).abs() / torch.where(big > 0, scale, torch.ones_like(scale)),
                                torch.full_like(big, math.inf))
             near_lp = ok & (d_lp <= tol)
             rho_alt = torch.where(use_rho, rho_lp, rho).detach()
             depth_alt = torch.where(use_rho, depth_c, depth_hit).detach()
             support_alt = ok & (rho_alt <= c2) & (depth_alt > zn)
-            near = near | (near_lp & (support_alt | ((rho_alt - c2).abs() <= tol * c2) |
+            wc_alt = torch.where(use_rho, wt, torch.maximum(wt, wr))
+            near = near | (near_lp & (support_alt | ((rho_alt - c2).abs() <= wc_alt) |
                                       ((depth_alt - zn).abs() <= tol * zn)))
         else:
             d_lp = torch.full_like(rho, math.inf)
             rho_alt, depth_alt, support_alt = rho_hat.detach(), depth.detach(), support.detach()
         if tol <= 0.0:
             near = torch.zeros_like(near)
-    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support, near=near, d_lp=d_lp,
+    # the support and alpha_min decisions see rho's error only where rho decides
+    drho_dec = torch.where(use_rho, drho, torch.zeros_like(drho)) if opts["lowpass"] else drho
+    return dict(u=u, v=v, rho_hat=rho_hat, depth=depth, support=support, near=near, d_lp=d_lp, drho=drho_dec,
                 alt=dict(rho_hat=rho_alt, depth=depth_alt, support=support_alt))
 
 
-def _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor):
+def _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor, tol=0.0):
     """Per listed pair [R, K]: relative distance of its support decision
     (cutoff, z_near), its alpha_min skip, (non-skipped pairs) its T_min stop
     test and its choice between rho and the low-pass term to the threshold;
-    inf where the rule is off."""
+    inf where the rule is off.  With tol > 0 the distances of the decisions
+    on rho are scaled so that a pair whose rho lies within its FP32 error
+    bound of the threshold (sol['drho']) also comes out at most tol."""
     rp_t, pos_t = torch.as_tensor(rp), torch.as_tensor(pos)
     with torch.no_grad():
         rh = sol["rho_hat"].detach()
         dep = sol["depth"].detach()
         c2, zn = opts["cutoff2"], sensor["z_near"]
-        m_sup = torch.minimum((rh - c2).abs() / c2, (dep - zn).abs() / max(zn, 1e-300))
+        wr = sol["drho"].detach() / tol if tol > 0.0 else torch.zeros_like(rh)
+        m_sup = torch.minimum((rh - c2).abs() / torch.clamp(wr, min=c2), (dep - zn).abs() / max(zn, 1e-300))
         d_sup = torch.full((R, K), math.inf, dtype=DT).index_put((rp_t, pos_t), m_sup)
         d_lp = torch.full((R, K), math.inf, dtype=DT).index_put((rp_t, pos_t), sol["d_lp"].detach())
         inf = torch.full((R, K), math.inf, dtype=DT)
         am, tm = opts["alpha_min"], opts["T_min"]
-        d_amin = (alpha - am).abs() / am if am > 0 else inf
+        # alpha moves by about alpha drho / 2 (0.6 with margin) when rho does by drho
+        wa = torch.zeros((R, K), dtype=DT).index_put((rp_t, pos_t), wr) * alpha * 0.6
+        d_amin = (alpha - am).abs() / torch.clamp(wa, min=am) if am > 0 else inf
         d_stop = torch.where(skip, inf, (test - tm).abs() / tm) if tm > 0 else inf
     return d_sup, d_amin, d_stop, d_lp
 
 
-def _margins(sol, rp, pos, R, K, alpha, test, skip, considered, opts, sensor):
+def _margins(sol, rp, pos, R, K, alpha, test, skip, considered, opts, sensor, tol=0.0):
     """Per ray: the smallest relative distance of any decision of a considered
-    pair (up to and including the stopping one) to its threshold."""
-    d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
+    pair (up to and including the stopping one) to its threshold (with
+    tol > 0, in the scaled measure of _relative_distances)."""
+    d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor, tol)
     m = torch.minimum(torch.minimum(d_sup, d_amin), torch.minimum(d_stop, d_lp))
     m = torch.where(considered, m, torch.full_like(m, math.inf))
     return m.min(1).values.numpy() if K > 0 else np.full(R, np.inf)
@@ -627,7 +715,7 @@ def _alternatives(sol, rp, pos, R, K, alpha, present, listed, feat, bg, test, sk
     rho and the low-pass term (the other choice gives the pair the alpha,
     depth and support in `alt`: [R, K] grids 'alpha', 'present', 'depth', and
     the depth channel index 'ch')."""
-    d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor)
+    d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor, tol)
     with torch.no_grad():
         fm = [considered & (d_sup <= tol), considered & (d_amin <= tol), considered & (d_stop <= tol),
               considered & (d_lp <= tol)]

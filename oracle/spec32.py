@@ -327,21 +327,20 @@ def lidar_bins(fr: dict, scale, sensor: dict, opts: dict):
 # ----------------------------------------------------------------------------
 
 def cylindrical_tables(sensor: dict):
-    """The cylindrical camera as FP32 tables (FP64 values rounded to nearest).
+    """The cylindrical camera's ray definition (FP64).
 
     Column i looks at the horizontal angle phi_i = (i + 1/2 - c_x) / f_x about
     the camera's y axis (Eq. 4), row j at height y_n = (j + 1/2 - c_y) / f_y on
-    the unit cylinder: the ray direction is (sin phi, y_n, cos phi).  Both sides
-    use these rounded values as the definition of the rays.
+    the unit cylinder: the ray direction is (sin phi, y_n, cos phi).  These are
+    exact functions of the pixel centre (no table rounding), like the pinhole's
+    normalised coordinates.
     """
     W, H = int(sensor["width"]), int(sensor["height"])
     fx, fy = float(sensor["fx"]), float(sensor["fy"])
     cx, cy = float(sensor["cx"]), float(sensor["cy"])
-    phi = [(i + 0.5 - cx) / fx for i in range(W)]
-    sin_phi = np.array([math.sin(t) for t in phi], np.float64).astype(F32)
-    cos_phi = np.array([math.cos(t) for t in phi], np.float64).astype(F32)
-    yn = np.array([(j + 0.5 - cy) / fy for j in range(H)], np.float64).astype(F32)
-    return dict(sin_phi=sin_phi, cos_phi=cos_phi, yn=yn)
+    phi = (np.arange(W, dtype=np.float64) + 0.5 - cx) / fx
+    yn = (np.arange(H, dtype=np.float64) + 0.5 - cy) / fy
+    return dict(sin_phi=np.sin(phi), cos_phi=np.cos(phi), yn=yn, phi=phi)
 
 
 def cylindrical_bins(fr: dict, scale, sensor: dict, opts: dict):

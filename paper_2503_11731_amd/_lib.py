@@ -13,7 +13,7 @@ PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG_DIR, "libgs2d.so")
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = range(5)
-GS_SENSOR_PINHOLE, GS_SENSOR_LIDAR = 0, 1
+GS_SENSOR_PINHOLE, GS_SENSOR_LIDAR, GS_SENSOR_CYLINDRICAL = 0, 1, 2
 GS_MAX_GROUPS = 64
 GS_MAX_SENSORS = 16
 GS_CAMERA_CHANNELS = 8

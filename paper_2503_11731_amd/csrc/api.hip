@@ -71,7 +71,7 @@ struct RecordArrays {
   int pair_buf = 0;   // buffer holding the sorted pairs
   int queue_buf = 0;  // buffer holding the sorted work items
   int grid_fwd = 0, grid_bwd = 0;
-  int kinds = 0;  // sensor kinds served (bit 0 camera, bit 1 LiDAR)
+  int kinds = 0;  // sensor kinds served (bit 0 pinhole, bit 1 LiDAR, bit 2 cylindrical)
 
   void layout(Layout& L, uint32_t n, uint32_t cap_, int tiles, int rays_, uint32_t seg) {
     n_rec = n;
@@ -144,7 +144,7 @@ struct SensorPlan {
   size_t o_pose = 0, o_Tfinal = 0, o_nlast = 0, o_status = 0;
   RecordArrays R;          // per-sensor layout only
   uint32_t rec_base = 0;   // batched layout: first record id
-  float* d_tabs = nullptr; // LiDAR tables (device, owned by the plan)
+  float* d_tabs = nullptr; // LiDAR / cylindrical tables (device, owned by the plan)
 };
 
 struct ScenePlan {
@@ -305,6 +305,9 @@ EmitTable emit_table(const gs_plan* p, const std::vector<int>& sensors) {
   return E;
 }
 
+// Kind bit of a sensor for the compositing kernels' variants.
+int kind_bit(int kind) { return kind == GS_SENSOR_PINHOLE ? 1 : kind == GS_SENSOR_LIDAR ? 2 : 4; }
+
 gs_status check_scene(const gs_plan* p, int si, const gs_scene& sc, bool need_colour, bool need_intensity) {
   const gs_scene_desc& d = p->scenes[si].desc;
   if (d.n_splats == 0) return GS_OK;
@@ -342,7 +345,7 @@ gs_status validate_call(const gs_plan* p, const gs_scene* scenes, const float* s
     return fail(GS_ERR_INVALID_ARG, "workspace must be 256-B aligned");
   for (size_t si = 0; si < p->sensors.size(); ++si) {
     const SensorPlan& s = p->sensors[si];
-    gs_status cs = check_scene(p, s.scene, scenes[s.scene], s.K.kind == GS_SENSOR_PINHOLE, s.K.kind == GS_SENSOR_LIDAR);
+    gs_status cs = check_scene(p, s.scene, scenes[s.scene], s.K.kind != GS_SENSOR_LIDAR, s.K.kind == GS_SENSOR_LIDAR);
     if (cs != GS_OK) return cs;
   }
   return GS_OK;
@@ -676,11 +679,24 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
         return fail(GS_ERR_HIP, std::string("LiDAR tables: ") + hipGetErrorString(e));
       }
       K.tab = s.d_tabs;
+    } else if (d.kind == GS_SENSOR_CYLINDRICAL) {
+      if (!(d.fx > 0.0f && d.fy > 0.0f)) {
+        gs_plan_destroy(p);
+        return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": focal lengths must be > 0");
+      }
+      K.tw = d.tile_w ? d.tile_w : 32;
+      K.th = d.tile_h ? d.tile_h : 8;
+      K.fx = d.fx;
+      K.fy = d.fy;
+      K.cx = d.cx;
+      K.cy = d.cy;
     } else {
       gs_plan_destroy(p);
       return fail(GS_ERR_INVALID_ARG, "sensor " + std::to_string(si) + ": unknown kind");
     }
-    const bool shape_ok = tile_shape_supported(K.tw, K.th) && (!p->batched || K.tw * K.th == 256);
+    // batched plans and cylindrical cameras composite 256-ray tiles
+    const bool shape_ok = tile_shape_supported(K.tw, K.th) &&
+                          ((!p->batched && K.kind != GS_SENSOR_CYLINDRICAL) || K.tw * K.th == 256);
     if (!shape_ok) {
       p->sensors.push_back(s);
       gs_plan_destroy(p);
@@ -705,11 +721,11 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     } else {
       K.tile_offset = 0;
       s.R.layout(R, (uint32_t)N, (uint32_t)cap, s.n_tiles, K.tw * K.th, seg_len);
-      s.R.kinds = K.kind == GS_SENSOR_PINHOLE ? 1 : 2;
+      s.R.kinds = kind_bit(K.kind);
       s.R.grid_fwd = grid_for(K.tw * K.th, s.R.kinds, false);
       s.R.grid_bwd = grid_for(K.tw * K.th, s.R.kinds, true);
     }
-    all_kinds |= K.kind == GS_SENSOR_PINHOLE ? 1 : 2;
+    all_kinds |= kind_bit(K.kind);
     total_rec += (uint64_t)N;
     total_cap += (uint64_t)cap;
     total_tiles += s.n_tiles;

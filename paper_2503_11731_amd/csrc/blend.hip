@@ -105,6 +105,69 @@ struct PairEval {
   bool lp_used, clamped;
 };
 
+// The rest of a pair's evaluation from its solve (u, v, 1/h'_2, depth): the
+// low-pass choice, the support and alpha tests and alpha itself.  rl is the
+// low-pass term, zc the centre's depth (taken by pairs the low-pass term admits).
+__device__ __forceinline__ bool finish_pair(float u, float v, float r, float z, bool ok, float rl, float zc,
+                                            float log2o, const EvalK& K, PairEval& e) {
+#pragma clang fp contract(off)
+  const float rho = fmaf(u, u, v * v);
+  const bool lp_used = K.lowpass && !(rho <= rl);
+  const float rho_hat = lp_used ? rl : rho;
+  // a pair admitted by the low-pass term (edge-on or sub-pixel surfel) takes
+  // the centre's depth: its plane hit is not meaningful there
+  if (lp_used) z = zc;
+  ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
+  float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, log2o));
+  const bool clamped = alpha > K.alpha_max;
+  if (clamped) alpha = K.alpha_max;
+  ok = ok && !(alpha < K.alpha_min);
+  e.alpha = alpha;
+  e.u = u;
+  e.v = v;
+  e.z = z;
+  e.r = r;
+  e.lp_used = lp_used;
+  e.clamped = clamped;
+  return ok;
+}
+
+// Per-tile FP32 error bound of a staged record: Et bounds the (u, v) error of
+// any of the tile's pairs to first order (see the record flags).  The edge
+// bit stays only where Et still allows an alpha error above the budget, and
+// the wild bit is set where Et is too large to trust the FP32 rho; Et itself
+// goes to a spare slot for the block test's rounding slack.
+__device__ __forceinline__ void set_tile_bound(float& flag_word, float& slot, float Et, float log2o) {
+  uint32_t f = __float_as_uint(flag_word);
+  if (f & kFlagEdge) {
+    if (!(2.87f * __builtin_amdgcn_exp2f(log2o) * Et > kEdgeTau)) f &= ~kFlagEdge;
+    if (!(Et <= kWildErr)) f |= kFlagWild;
+  }
+  flag_word = __uint_as_float(f);
+  slot = Et;
+}
+
+// Does an edge-flagged pair need the FP64 re-solve?  err |1/h'_2| bounds its
+// (u, v) error to first order, so its alpha error is at most alpha
+// |(u, v)|_1 err |1/h'_2| (taken with a 30% margin) where rho decides alpha;
+// a pair whose alpha comes from the low-pass term does not depend on (u, v)
+// (a choice between the two that the error could flip is a near-threshold
+// decision).  Where the bound exceeds kWildErr (only in wild tiles) the FP32
+// rho is not trusted: the pair re-solves if rho could be inside
+// min(cutoff, low-pass term) with that error.
+__device__ __forceinline__ bool edge_needs_f64(const PairEval& e, float err, float rl, uint32_t flags,
+                                               const EvalK& K) {
+#pragma clang fp contract(off)
+  const float eu = err * fabsf(e.r);
+  bool r = !e.lp_used & (e.alpha * ((fabsf(e.u) + fabsf(e.v)) * eu) > kEdgeTau * (1.0f / 1.3f));
+  if (flags & kFlagWild) {  // the same record for the whole wave
+    const float rho = fmaf(e.u, e.u, e.v * e.v);
+    const float m = K.lowpass ? fminf(K.cutoff2, rl) : K.cutoff2;
+    r = r | ((eu > kWildErr) & !(rho > fmaf(eu, fmaf(2.0f, eu, 9.5f), m)));
+  }
+  return r;
+}
+
 // Does the surfel's conservative rectangle (packed 16-bit bounds) miss this
 // wave's 8x8 block of rays?  Pairs outside the rectangle are never in the
 // support, so skipping them leaves every result unchanged.
@@ -211,73 +274,99 @@ __device__ __forceinline__ void load_rec(const TileArgs& a, uint32_t s, RawRec& 
   x.d[1] = r64[1];
 }
 
+// The FP64 re-solve data of record s into registers: G (NG doubles: the
+// solve's rows and the centre depth or range) and its FP64 centre (NC
+// doubles), from the record's LDS slot when it was staged there, else from
+// global memory -- every load issued before any is used.
+template <int NG, int NC>
+__device__ __forceinline__ void fetch64(const TileArgs& a, const F64Slot* f64, uint32_t slot, uint32_t s, double* g,
+                                        double* c) {
+  if (slot && f64) {
+    const double* d = f64[slot - 1];
+#pragma unroll
+    for (int k = 0; k < NG; ++k) g[k] = d[k];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) c[k] = d[kGrz + k];
+  } else {
+    const double* G = a.grz + kGrz * (size_t)s;
+    const double* C = a.rec64 + kRec64 * (size_t)s;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) g[k] = G[k];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) c[k] = C[k];
+  }
+}
+
 // ----------------------------- camera -----------------------------------
-// Staged record (5 x float4):
-//  [0] pcx_rel, pcy_rel, P00, P01   [1] P10, P11, P20, P21
-//  [2] mu_z, log2 o, c0, c1          [3] c2, n0, n1, n2
-//  [4] flags, o, pixel columns lo|hi<<16, pixel rows lo|hi<<16
+// Staged record (6 x float4), the fields every pair reads first:
+//  [0] pcx_rel, pcy_rel, P00, P01
+//  [1] P10, P11, P20, P21
+//  [2] mu_z, log2 o, the rounding residuals of pcx_rel, pcy_rel
+//  [3] flags, 2^-22 kappa (2^-21 for the cylindrical map: the pairs' FP32
+//      error bound factor), c0, c1
+//  [4] c2, n0, n1, n2
+//  [5] pixel columns lo|hi<<16, pixel rows lo|hi<<16, the tile's error bound Et, -
+// The centre in the tile frame is held as an FP32 pair (value + residual),
+// so that the offset dx = (p_x - pcx_rel) - residual carries only its own
+// rounding, not that of a centre up to a tile away.
 __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint32_t s, float plx, float ply, int ox,
                                              int oy, const TileArgs& a, const EvalK& K, const F64Slot* f64,
                                              PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
   const float4 q0 = R[0], q1 = R[1], q2 = R[2];
-  const uint32_t flags = uniform_u32(R[4].x);
-  const float dx = plx - q0.x;
-  const float dy = ply - q0.y;
+  const uint32_t flags = uniform_u32(R[3].x);
+  const float dx = (plx - q0.x) - q2.z;
+  const float dy = (ply - q0.y) - q2.w;
   const float h0 = fmaf(q0.z, dx, q0.w * dy);
   const float h1 = fmaf(q1.x, dx, q1.y * dy);
   const float h2 = fmaf(q1.z, dx, fmaf(q1.w, dy, 1.0f));
   float r = __builtin_amdgcn_rcpf(h2);
   float u = h0 * r, v = h1 * r, z = q2.x * r;
   bool ok = h2 != 0.0f;
-  if (flags & kFlagGrazing) {  // the same record for the whole wave
-    if (fabsf(h2) < 0.125f) {
-      ++n64;
-      // from the record's LDS slot when it was staged there, else from global memory
-      const uint32_t slot = (flags >> 8) & 0xFFu;
-      const double px = (double)ox + (double)plx, py = (double)oy + (double)ply;
-      if (slot && f64)
-        ok = solve64_pinhole(f64[slot - 1], f64[slot - 1] + kGrz, px, py, u, v, r, z);
-      else
-        ok = solve64_pinhole(a.grz + kGrz * (size_t)s, a.rec64 + kRec64 * (size_t)s, px, py, u, v, r, z);
-    }
-  }
-  const float rho = fmaf(u, u, v * v);
   const float rl = K.lp * fmaf(dx, dx, dy * dy);
-  const bool lp_used = K.lowpass && !(rho <= rl);
-  const float rho_hat = lp_used ? rl : rho;
-  // a pair admitted by the low-pass term (edge-on or sub-pixel surfel) takes
-  // the centre's depth: its plane hit is not meaningful there
-  if (lp_used) z = q2.x;
-  ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
-  float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q2.y));
-  const bool clamped = alpha > K.alpha_max;
-  if (clamped) alpha = K.alpha_max;
-  ok = ok && !(alpha < K.alpha_min);
-  e.alpha = alpha;
-  e.u = u;
-  e.v = v;
-  e.z = z;
-  e.r = r;
   e.dx = dx;
   e.dy = dy;
-  e.lp_used = lp_used;
-  e.clamped = clamped;
-  return ok;
+  bool hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
+  // FP64 re-solve: grazing pairs (|h'_2| < 1/8) and an edge record's pairs
+  // whose error bound could matter
+  const uint32_t slot = (flags >> 8) & 0xFFu;
+  bool redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
+  // the offsets carry two roundings of their size, the products two more
+  // (the record holds 2^-22 kappa)
+  if (flags & kFlagEdge)  // the same record for the whole wave
+    redo = redo | edge_needs_f64(e, fmaf(R[3].y, fmaxf(fabsf(dx), fabsf(dy)), 0x1p-20f), rl, flags, K);
+  if (redo) {
+    ++n64;
+    double g[7], c[2];
+    fetch64<7, 2>(a, f64, slot, s, g, c);
+    ok = solve64_pinhole(g, c, (double)ox + (double)plx, (double)oy + (double)ply, u, v, r, z);
+    hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
+  }
+  return hit;
 }
 
 __device__ __forceinline__ uint2 stage_pinhole(const RawRec& x, int ox, int oy, float4* dst) {
   const float4 r0 = x.r[0], r1 = x.r[1], r2 = x.r[2], r3 = x.r[3];
-  const float pcx = (float)(x.d[0].x - (double)ox);
-  const float pcy = (float)(x.d[0].y - (double)oy);
+  const double cx = x.d[0].x - (double)ox, cy = x.d[0].y - (double)oy;
+  const float pcx = (float)cx, pcy = (float)cy;
   const uint2 rect = make_uint2((uint32_t)__double_as_longlong(x.d[1].y),
                                 (uint32_t)((unsigned long long)__double_as_longlong(x.d[1].y) >> 32));
+  // global record: P (6), mu_z, log2 o, c0..c2, n0..n2, flags, 2^-23 kappa
   dst[0] = make_float4(pcx, pcy, r0.x, r0.y);
   dst[1] = make_float4(r0.z, r0.w, r1.x, r1.y);
-  dst[2] = make_float4(r1.z, r1.w, r2.x, r2.y);
-  dst[3] = make_float4(r2.z, r2.w, r3.x, r3.y);
-  dst[4] = make_float4(r3.z, r3.w, __uint_as_float(rect.x), __uint_as_float(rect.y));
+  dst[2] = make_float4(r1.z, r1.w, (float)(cx - (double)pcx), (float)(cy - (double)pcy));
+  dst[3] = make_float4(r3.z, r3.w, r2.x, r2.y);
+  dst[4] = make_float4(r2.z, r2.w, r3.x, r3.y);
+  dst[5] = make_float4(__uint_as_float(rect.x), __uint_as_float(rect.y), 0.0f, 0.0f);
   return rect;
+}
+
+// Largest |offset| from the centre (at c, tile frame) over the pixel centres
+// of [lo - 7, hi + 7] (an image-axis range of the surfel's rectangle, widened
+// to the 8-pixel blocks that evaluate it) within the tile's [0, n).
+__device__ __forceinline__ float max_offset(int lo, int hi, int o, int n, float c) {
+  const float a = (float)max(lo - o - 7, 0) + 0.5f, b = (float)min(hi - o + 7, n - 1) + 0.5f;
+  return fmaxf(fabsf(a - c), fabsf(b - c));
 }
 
 // One camera ray of a tile: lane geometry and the per-sensor pieces of the
@@ -286,6 +375,7 @@ struct CamRay {
   static constexpr int C = 8;  // rgb, depth, normal xyz, alpha
   int px, py, ox, oy, bx, by, wx;
   float plx, ply;
+  int tw, th;
   bool inside;
   EvalK K;
 
@@ -304,9 +394,25 @@ struct CamRay {
     inside = px < a.S.W && py < a.S.H;
     plx = (float)lx + 0.5f;
     ply = (float)ly + 0.5f;
+    tw = a.S.tw;
+    th = a.S.th;
   }
   __device__ size_t pix(const TileArgs& a) const { return (size_t)py * a.S.W + px; }
-  __device__ uint2 stage(const RawRec& x, float4* dst) const { return stage_pinhole(x, ox, oy, dst); }
+  // the staged record, with its FP32 error bound over this tile: the offsets
+  // carry about two roundings of their own size and the products two more,
+  // so s = 2 |offset|_inf at the farthest pixel of the tile that evaluates
+  // the record (plus slack for the roundings relative to u, v themselves),
+  // over the smallest h'_2 there
+  __device__ uint2 stage(const RawRec& x, float4* dst, const float (*)[6], int) const {
+    const uint2 rect = stage_pinhole(x, ox, oy, dst);
+    const float cx = dst[0].x, cy = dst[0].y;
+    const float mdx = max_offset(rect.x & 0xFFFF, rect.x >> 16, ox, tw, cx);
+    const float mdy = max_offset(rect.y & 0xFFFF, rect.y >> 16, oy, th, cy);
+    const float h2m = 1.0f - (fabsf(dst[1].z) * mdx + fabsf(dst[1].w) * mdy);
+    const float Et = fmaf(dst[3].y, fmaxf(mdx, mdy), 0x1p-20f) / fmaxf(h2m, 0.125f);
+    set_tile_bound(dst[3].x, dst[5].z, Et, dst[2].y);
+    return rect;
+  }
   // does rectangle `rect` touch the 8x8 block of wave w?
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
@@ -325,12 +431,14 @@ struct CamRay {
 #pragma clang fp contract(off)
     const uint32_t all = (1u << nw) - 1u;
     const float4 q0 = d[0], q1 = d[1], q2 = d[2];
-    if (__float_as_uint(d[4].x) & kFlagGrazing) return all;
+    if (__float_as_uint(d[3].x) & kFlagGrazing) return all;
     // largest rho_hat with alpha >= alpha_min: log2 o - rho_hat / (2 ln 2) >= log2 alpha_min
     const float ra = (q2.y - __log2f(K.alpha_min)) * (1.0f / kInv2Ln2);
     float r2 = fminf(K.cutoff2, ra);
     if (!(r2 >= 0.0f)) return 0u;
     r2 = r2 * 1.001f + 1e-3f;
+    // slack for the corners' own FP32 error: twice the tile's bound
+    const float sl = 2.0f * d[5].z;
     uint32_t m = 0u;
     for (int w = 0; w < nw; ++w) {
       const float x0 = (float)((w % wx) * 8) + 0.5f - q0.x, x1 = x0 + 7.0f;
@@ -360,31 +468,31 @@ struct CamRay {
         vmin = fminf(vmin, v);
         vmax = fmaxf(vmax, v);
       }
-      const float eu = umin > 0.0f ? umin : (umax < 0.0f ? -umax : 0.0f);
-      const float ev = vmin > 0.0f ? vmin : (vmax < 0.0f ? -vmax : 0.0f);
+      const float eu = fmaxf((umin > 0.0f ? umin : (umax < 0.0f ? -umax : 0.0f)) - sl, 0.0f);
+      const float ev = fmaxf((vmin > 0.0f ? vmin : (vmax < 0.0f ? -vmax : 0.0f)) - sl, 0.0f);
       if (!front || !(eu * eu + ev * ev > r2)) m |= 1u << w;
     }
     return m;
   }
   __device__ bool covered(const float4* R) const {
-    return covers(__float_as_uint(R[4].z), __float_as_uint(R[4].w), px, py);
+    return covers(__float_as_uint(R[5].x), __float_as_uint(R[5].y), px, py);
   }
   __device__ uint64_t cover_lanes(const float4* R) const {
-    return cover_lanes_rect(uniform_u32(R[4].z), uniform_u32(R[4].w), bx, by);
+    return cover_lanes_rect(uniform_u32(R[5].x), uniform_u32(R[5].y), bx, by);
   }
   __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
     return eval_pinhole(R, s, plx, ply, ox, oy, a, K, f64, e, n64);
   }
-  static __device__ float& flag_word(float4* R) { return R[4].x; }
+  static __device__ float& flag_word(float4* R) { return R[3].x; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
-    f[0] = R[2].z;
-    f[1] = R[2].w;
-    f[2] = R[3].x;
+    f[0] = R[3].z;
+    f[1] = R[3].w;
+    f[2] = R[4].x;
     f[3] = e.z;
-    f[4] = R[3].y;
-    f[5] = R[3].z;
-    f[6] = R[3].w;
+    f[4] = R[4].y;
+    f[5] = R[4].z;
+    f[6] = R[4].w;
     f[7] = 1.0f;
   }
   // output channels of a ray with final transmittance T and sums acc
@@ -412,7 +520,7 @@ struct CamRay {
                         float* gr) const {
 #pragma clang fp contract(off)
     const float4 q0 = R[0], q1 = R[1];
-    const float o = R[4].y;
+    const float o = __builtin_amdgcn_exp2f(R[2].y);
     const float al = e.alpha;
     gr[10] = g[0] * wgt;
     gr[11] = g[1] * wgt;
@@ -448,12 +556,400 @@ struct CamRay {
   }
 };
 
+// ------------------------- cylindrical camera ---------------------------
+// A surfel's record is the camera record in its own column frame (the sensor
+// frame turned about y by the centre's angle): the ray of a pixel at angle
+// offset dphi = dx / f_x from the centre's column is the pinhole ray
+// (tan dphi, y_n sec dphi, 1) there, so the per-pair solve is the camera's on
+//   X = f_x tan dphi,   Y = dy + (p_y - c_y)(sec dphi - 1)
+// (Y = f_y (y_n sec dphi - y_n,centre)), and the depth -- the distance from
+// the vertical axis -- is r sec dphi / h'_2 (r = the centre's distance).
+
+// sin and cos for the angle offsets of a cylindrical camera (|x| < 16, far
+// beyond the 3 pi a full-circle camera can produce): Cody-Waite reduction by
+// pi/2 in two parts, then the Taylor series of sin and cos on |r| <= pi/4
+// (truncation below 2e-9 relative in FP32, 1e-19 in FP64).  Written out so
+// that the pair loop carries no large-argument reduction.
+__device__ __forceinline__ bool sincos_small(float x, float& s, float& c) {
+#pragma clang fp contract(off)
+  if (!(fabsf(x) < 16.0f)) return false;
+  const float k = rintf(x * 0.63661977236758134f);
+  const float r = fmaf(-k, -4.37113900018624283e-8f, fmaf(-k, 1.57079637050628662f, x));  // x - k pi/2
+  const float r2 = r * r;
+  float ps = fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  ps = fmaf(r2, ps, 1.0f / 120.0f);
+  ps = fmaf(r2, ps, -1.0f / 6.0f);
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  pc = fmaf(r2, pc, -1.0f / 720.0f);
+  pc = fmaf(r2, pc, 1.0f / 24.0f);
+  pc = fmaf(r2, pc, -0.5f);
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = (int)k & 3;
+  s = (q & 1) ? cr : sr;
+  c = (q & 1) ? sr : cr;
+  if (q == 1 || q == 2) c = -c;
+  if (q >= 2) s = -s;
+  return true;
+}
+
+__device__ __forceinline__ bool sincos_small(double x, double& s, double& c) {
+  if (!(fabs(x) < 16.0)) return false;
+  const double k = rint(x * 0.63661977236758134308);
+  const double r = fma(-k, 6.123233995736766036e-17, fma(-k, 1.5707963267948965580, x));  // x - k pi/2
+  const double r2 = r * r;
+  // sin: 1/(2n+1)! through r^17; cos: 1/(2n)! through r^18
+  double ps = fma(r2, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);
+  ps = fma(r2, ps, 1.0 / 6227020800.0);
+  ps = fma(r2, ps, -1.0 / 39916800.0);
+  ps = fma(r2, ps, 1.0 / 362880.0);
+  ps = fma(r2, ps, -1.0 / 5040.0);
+  ps = fma(r2, ps, 1.0 / 120.0);
+  ps = fma(r2, ps, -1.0 / 6.0);
+  const double sr = fma(r * r2, ps, r);
+  double pc = fma(r2, -1.0 / 6402373705728000.0, 1.0 / 20922789888000.0);
+  pc = fma(r2, pc, -1.0 / 87178291200.0);
+  pc = fma(r2, pc, 1.0 / 479001600.0);
+  pc = fma(r2, pc, -1.0 / 3628800.0);
+  pc = fma(r2, pc, 1.0 / 40320.0);
+  pc = fma(r2, pc, -1.0 / 720.0);
+  pc = fma(r2, pc, 1.0 / 24.0);
+  pc = fma(r2, pc, -0.5);
+  const double cr = fma(r2, pc, 1.0);
+  const int q = (int)k & 3;
+  s = (q & 1) ? cr : sr;
+  c = (q & 1) ? sr : cr;
+  if (q == 1 || q == 2) c = -c;
+  if (q >= 2) s = -s;
+  return true;
+}
+
+// tan x and sec x - 1.  |x| <= 1/4: their Taylor series through x^11 and x^10
+// (relative error < 1e-8 there); beyond, from sin and cos.  Returns false
+// where cos x <= 0: such a ray looks away from the surfel's column by more
+// than 90 degrees, so it cannot meet a visible surfel's support (the rays
+// that do are within asin(R / r) < 90 degrees of it).
+__device__ __forceinline__ bool tan_secm1(float x, float& t, float& sm1) {
+#pragma clang fp contract(off)
+  if (fabsf(x) <= 0.25f) {
+    const float x2 = x * x;
+    // tan: 1, 1/3, 2/15, 17/315, 62/2835, 1382/155925
+    float p = fmaf(x2, 1382.0f / 155925.0f, 62.0f / 2835.0f);
+    p = fmaf(x2, p, 17.0f / 315.0f);
+    p = fmaf(x2, p, 2.0f / 15.0f);
+    p = fmaf(x2, p, 1.0f / 3.0f);
+    t = fmaf(x * x2, p, x);
+    // sec - 1: 1/2, 5/24, 61/720, 277/8064, 50521/3628800
+    float q = fmaf(x2, 50521.0f / 3628800.0f, 277.0f / 8064.0f);
+    q = fmaf(x2, q, 61.0f / 720.0f);
+    q = fmaf(x2, q, 5.0f / 24.0f);
+    q = fmaf(x2, q, 0.5f);
+    sm1 = x2 * q;
+    return true;
+  }
+  float sn = 0.0f, cs = 0.0f;
+  if (!sincos_small(x, sn, cs) || !(cs > 0.0f)) {
+    t = 0.0f;
+    sm1 = 0.0f;
+    return false;
+  }
+  const float rc = 1.0f / cs;
+  t = sn * rc;
+  sm1 = (sn * sn) * rc / (1.0f + cs);
+  return true;
+}
+
+// Per-sensor constants of the cylindrical mapping, in vector registers.
+struct CylK {
+  float fx, ifx;  // f_x and 1 / f_x
+};
+
+// Grazing re-solve in FP64: the pixel's ray turned into the record's column
+// frame is (tan dphi, y_n sec dphi, 1), dphi = (p_x - pc_x) / f_x exactly.
+// G = P (6) + r, c = projected centre.
+__device__ __forceinline__ bool solve64_cyl(const double* G, const double* c, const SensorK& S, int col, int row,
+                                            float& u, float& v, float& r, float& z) {
+  const double dphi = ((double)col + 0.5 - c[0]) / (double)S.fx;
+  double sn, cs;
+  if (!sincos_small(dphi, sn, cs) || !(cs > 0.0)) return false;
+  const double sec = 1.0 / cs;
+  const double X = (double)S.fx * (sn * sec);
+  const double Y = ((double)row + 0.5 - (double)S.cy) * sec - (c[1] - (double)S.cy);
+  const double H0 = G[0] * X + G[1] * Y;
+  const double H1 = G[2] * X + G[3] * Y;
+  const double H2 = 1.0 + G[4] * X + G[5] * Y;
+  const double rd = 1.0 / H2;
+  u = (float)(H0 * rd);
+  v = (float)(H1 * rd);
+  r = (float)rd;
+  z = (float)(G[6] * rd * sec);
+  return H2 != 0.0;
+}
+
+__device__ __forceinline__ bool eval_cyl(const float4* __restrict__ R, uint32_t s, float plx, float ply, float Ay,
+                                         int px, int py, const TileArgs& a, const EvalK& K, const CylK& Y0,
+                                         const F64Slot* f64, PairEval& e, uint32_t& n64) {
+#pragma clang fp contract(off)
+  const float4 q0 = R[0], q1 = R[1], q2 = R[2];
+  const uint32_t flags = uniform_u32(R[3].x);
+  const float dx = (plx - q0.x) - q2.z;
+  const float dy = (ply - q0.y) - q2.w;
+  float tn, sm1;
+  bool ok = tan_secm1(dx * Y0.ifx, tn, sm1);
+  const float X = Y0.fx * tn;
+  const float Y = fmaf(Ay, sm1, dy);
+  const float h0 = fmaf(q0.z, X, q0.w * Y);
+  const float h1 = fmaf(q1.x, X, q1.y * Y);
+  const float h2 = fmaf(q1.z, X, fmaf(q1.w, Y, 1.0f));
+  float r = __builtin_amdgcn_rcpf(h2);
+  float u = h0 * r, v = h1 * r, z = (q2.x * r) * (1.0f + sm1);
+  ok = ok && h2 != 0.0f;
+  const float rl = K.lp * fmaf(dx, dx, dy * dy);
+  e.dx = dx;
+  e.dy = dy;
+  bool hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
+  // FP64 re-solve as for the pinhole camera
+  const uint32_t slot = (flags >> 8) & 0xFFu;
+  bool redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
+  // X = f tan and Y = dy + A (sec - 1) take about twice the pinhole's
+  // roundings (the record holds 2^-21 kappa)
+  if (flags & kFlagEdge)
+    redo = redo | edge_needs_f64(e, fmaf(R[3].y, fmaxf(fabsf(X), fabsf(Y)), 0x1p-20f), rl, flags, K);
+  if (redo) {
+    ++n64;
+    double g[7], c[2];
+    fetch64<7, 2>(a, f64, slot, s, g, c);
+    ok = solve64_cyl(g, c, a.S, px, py, u, v, r, z);
+    hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
+  }
+  return hit;
+}
+
+// One cylindrical-camera ray of a tile: the camera ray with the column-frame
+// mapping (see above); records, features and outputs are the camera's.
+struct CylRay {
+  static constexpr int C = 8;  // rgb, depth, normal xyz, alpha
+  int px, py, ox, oy, bx, by, wx;
+  int tc, tr;               // pixel column and row of the ray (inside the image for every lane)
+  float plx, ply, Ay, ay0;  // Ay: p_y - c_y of this ray; ay0: of the tile's first row
+  int tw, th;
+  bool inside;
+  EvalK K;
+  CylK Y0;
+
+  __device__ CylRay(const TileArgs& a, int tile) : K(eval_consts(a, a.O.lp)) {
+    const int WX = a.S.tw >> 3;
+    wx = WX;
+    const int tx = tile % a.S.n_tx, ty = tile / a.S.n_tx;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int lx = (w % WX) * 8 + (lane & 7), ly = (w / WX) * 8 + (lane >> 3);
+    ox = tx * a.S.tw;
+    oy = ty * a.S.th;
+    bx = __builtin_amdgcn_readfirstlane(ox + (w % WX) * 8);
+    by = __builtin_amdgcn_readfirstlane(oy + (w / WX) * 8);
+    px = ox + lx;
+    py = oy + ly;
+    inside = px < a.S.W && py < a.S.H;
+    tc = px < a.S.W ? px : ox;
+    tr = py < a.S.H ? py : oy;
+    plx = (float)lx + 0.5f;
+    ply = (float)ly + 0.5f;
+    Ay = ((float)py + 0.5f) - a.S.cy;
+    ay0 = ((float)oy + 0.5f) - a.S.cy;
+    Y0.fx = in_vgpr(a.S.fx);
+    Y0.ifx = in_vgpr(1.0f / a.S.fx);
+    tw = a.S.tw;
+    th = a.S.th;
+  }
+  __device__ size_t pix(const TileArgs& a) const { return (size_t)py * a.S.W + px; }
+  // the staged record, with its FP32 error bound over this tile: as the
+  // pinhole camera's on the (X, Y) box of the tile's pixels (columns up to 80
+  // degrees from the centre's; a tile reaching beyond is wild), doubled for
+  // the extra rounding steps of X = f tan and Y = dy + A (sec - 1)
+  __device__ uint2 stage(const RawRec& x, float4* dst, const float (*)[6], int) const {
+#pragma clang fp contract(off)
+    const uint2 rect = stage_pinhole(x, ox, oy, dst);
+    const float cx = dst[0].x, cy = dst[0].y;
+    const float mdx = max_offset(rect.x & 0xFFFF, rect.x >> 16, ox, tw, cx);
+    const float mdy = max_offset(rect.y & 0xFFFF, rect.y >> 16, oy, th, cy);
+    const float ang = mdx * Y0.ifx;
+    float Et = INFINITY;
+    float tn, sm1;
+    if (ang <= 1.39f && tan_secm1(ang, tn, sm1)) {
+      const float Aym = fmaxf(fabsf(ay0), fabsf(ay0 + (float)(th - 1)));
+      const float Xm = Y0.fx * tn, Ym = mdy + Aym * sm1;
+      const float h2m = 1.0f - (fabsf(dst[1].z) * Xm + fabsf(dst[1].w) * Ym);
+      Et = fmaf(dst[3].y, fmaxf(Xm, Ym), 0x1p-20f) / fmaxf(h2m, 0.125f);
+    }
+    set_tile_bound(dst[3].x, dst[5].z, Et, dst[2].y);
+    return rect;
+  }
+  __device__ bool touches(uint2 rect, int w) const {
+    return !misses_block(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
+  }
+  template <class SH>
+  __device__ void prepare(const TileArgs&, SH&) const {}
+  // The camera's block test on the box of (X, Y) over the block: X = f tan
+  // is monotone in the pixel offset, sec - 1 is even and grows with |dphi|,
+  // and Y = dy + (p_y - c_y)(sec - 1) is bounded by the interval products;
+  // u and v, linear-fractional in (X, Y), take their ranges at the box's
+  // corners.  Blocks that reach 90 degrees from the centre's column are kept.
+  __device__ uint32_t hit_blocks(const float4* d, int nw, const float (*)[6]) const {
+#pragma clang fp contract(off)
+    const uint32_t all = (1u << nw) - 1u;
+    const float4 q0 = d[0], q1 = d[1], q2 = d[2];
+    if (__float_as_uint(d[3].x) & kFlagGrazing) return all;
+    const float ra = (q2.y - __log2f(K.alpha_min)) * (1.0f / kInv2Ln2);
+    float r2 = fminf(K.cutoff2, ra);
+    if (!(r2 >= 0.0f)) return 0u;
+    r2 = r2 * 1.001f + 1e-3f;
+    // slack for the corners' own FP32 error: twice the tile's bound
+    const float sl = 2.0f * d[5].z;
+    uint32_t m = 0u;
+    for (int w = 0; w < nw; ++w) {
+      const float x0 = (float)((w % wx) * 8) + 0.5f - q0.x, x1 = x0 + 7.0f;
+      const float y0 = (float)((w / wx) * 8) + 0.5f - q0.y, y1 = y0 + 7.0f;
+      if (K.lowpass) {
+        const float ex = x0 > 0.0f ? x0 : (x1 < 0.0f ? -x1 : 0.0f);
+        const float ey = y0 > 0.0f ? y0 : (y1 < 0.0f ? -y1 : 0.0f);
+        if (K.lp * (ex * ex + ey * ey) <= r2) {
+          m |= 1u << w;
+          continue;
+        }
+      }
+      float t0, s0, t1, s1;
+      if (!tan_secm1(x0 * Y0.ifx, t0, s0) || !tan_secm1(x1 * Y0.ifx, t1, s1)) {
+        m |= 1u << w;
+        continue;
+      }
+      const float smin = (x0 <= 0.0f && x1 >= 0.0f) ? 0.0f : fminf(s0, s1), smax = fmaxf(s0, s1);
+      const float A0 = ay0 + (float)((w / wx) * 8), A1 = A0 + 7.0f;
+      const float pa = A0 * smin, pb = A0 * smax, pc = A1 * smin, pd = A1 * smax;
+      float Xlo = Y0.fx * t0, Xhi = Y0.fx * t1;
+      float Ylo = y0 + fminf(fminf(pa, pb), fminf(pc, pd)), Yhi = y1 + fmaxf(fmaxf(pa, pb), fmaxf(pc, pd));
+      // rounding margins: the per-pair X, Y are FP32 values of the same maps
+      const float mX = 1e-5f * fmaxf(fabsf(Xlo), fabsf(Xhi)) + 1e-4f;
+      const float mY = 1e-5f * (fmaxf(fabsf(Ylo), fabsf(Yhi)) + fmaxf(fabsf(A0), fabsf(A1))) + 1e-4f;
+      Xlo -= mX;
+      Xhi += mX;
+      Ylo -= mY;
+      Yhi += mY;
+      const float xs[2] = {Xlo, Xhi}, ys[2] = {Ylo, Yhi};
+      float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+      bool front = true;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float X = xs[c & 1], Y = ys[c >> 1];
+        const float h0 = q0.z * X + q0.w * Y;
+        const float h1 = q1.x * X + q1.y * Y;
+        const float h2 = 1.0f + q1.z * X + q1.w * Y;
+        front = front && h2 > 1e-6f;
+        const float r = __builtin_amdgcn_rcpf(h2);
+        const float u = h0 * r, v = h1 * r;
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+      }
+      const float eu = fmaxf((umin > 0.0f ? umin : (umax < 0.0f ? -umax : 0.0f)) - sl, 0.0f);
+      const float ev = fmaxf((vmin > 0.0f ? vmin : (vmax < 0.0f ? -vmax : 0.0f)) - sl, 0.0f);
+      if (!front || !(eu * eu + ev * ev > r2)) m |= 1u << w;
+    }
+    return m;
+  }
+  __device__ bool covered(const float4* R) const {
+    return covers(__float_as_uint(R[5].x), __float_as_uint(R[5].y), px, py);
+  }
+  __device__ uint64_t cover_lanes(const float4* R) const {
+    return cover_lanes_rect(uniform_u32(R[5].x), uniform_u32(R[5].y), bx, by);
+  }
+  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
+                       uint32_t& n64) const {
+    return eval_cyl(R, s, plx, ply, Ay, tc, tr, a, K, Y0, f64, e, n64);
+  }
+  static __device__ float& flag_word(float4* R) { return R[3].x; }
+  __device__ void feat(const float4* R, const PairEval& e, float* f) const {
+    f[0] = R[3].z;
+    f[1] = R[3].w;
+    f[2] = R[4].x;
+    f[3] = e.z;
+    f[4] = R[4].y;
+    f[5] = R[4].z;
+    f[6] = R[4].w;
+    f[7] = 1.0f;
+  }
+  static __device__ void out_values(const TileArgs& a, float T, const float* acc, float* v) {
+    CamRay::out_values(a, T, acc, v);
+  }
+  __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
+    const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
+    float v[C];
+    out_values(a, T, acc, v);
+#pragma unroll
+    for (int c = 0; c < C; ++c) a.out[c * HW + p] = v[c];
+    a.T_final[p] = T;
+    a.n_last[p] = last;
+  }
+  // The camera's fields: [0..5] dP, [6..7] d(projected centre), [8] d r (the
+  // record's centre distance), [9] d opacity, [10..12] d colour, [13..15]
+  // d normal; the offsets enter through X, Y and the depth's sec factor.
+  __device__ void grads(const TileArgs& a, const float4* R, const PairEval& e, float dal, float wgt, const float* g,
+                        float* gr) const {
+#pragma clang fp contract(off)
+    const float4 q0 = R[0], q1 = R[1], q2 = R[2];
+    const float o = __builtin_amdgcn_exp2f(q2.y);
+    const float al = e.alpha;
+    gr[10] = g[0] * wgt;
+    gr[11] = g[1] * wgt;
+    gr[12] = g[2] * wgt;
+    gr[13] = g[4] * wgt;
+    gr[14] = g[5] * wgt;
+    gr[15] = g[6] * wgt;
+    const float gz = g[3] * wgt;
+    float g_rhohat = 0.0f;
+    if (!e.clamped) {
+      gr[9] = o > 0.0f ? dal * al * __builtin_amdgcn_rcpf(o) : 0.0f;
+      g_rhohat = -0.5f * dal * al;
+    }
+    const float g_rho = e.lp_used ? 0.0f : g_rhohat;
+    const float g_lp = e.lp_used ? g_rhohat : 0.0f;
+    float tn, sm1;
+    (void)tan_secm1(e.dx * Y0.ifx, tn, sm1);
+    const float sec = 1.0f + sm1;
+    const float X = Y0.fx * tn;
+    const float Y = fmaf(Ay, sm1, e.dy);
+    const float gu = 2.0f * e.u * g_rho, gv = 2.0f * e.v * g_rho;
+    const float gh0 = gu * e.r, gh1 = gv * e.r;
+    // depth = r sec / h'_2 at the plane hit, r itself for a low-pass pair
+    const float gzh = e.lp_used ? 0.0f : gz;
+    const float gh2 = -(gu * e.u + gv * e.v + gzh * e.z) * e.r;
+    gr[8] = e.lp_used ? gz : gz * e.r * sec;
+    gr[0] = gh0 * X;
+    gr[1] = gh0 * Y;
+    gr[2] = gh1 * X;
+    gr[3] = gh1 * Y;
+    gr[4] = gh2 * X;
+    gr[5] = gh2 * Y;
+    const float gX = q0.z * gh0 + q1.x * gh1 + q1.z * gh2;
+    const float gY = q0.w * gh0 + q1.y * gh1 + q1.w * gh2;
+    // d/d dx: X' = sec^2, Y' = (p_y - c_y) sec tan / f_x, depth' = depth tan / f_x
+    const float st = sec * tn * Y0.ifx;
+    const float two_lp = 2.0f * a.O.lp * g_lp;
+    const float gdx = gX * (sec * sec) + gY * (Ay * st) + gzh * e.z * tn * Y0.ifx + two_lp * e.dx;
+    const float gdy = gY + two_lp * e.dy;
+    gr[6] = -gdx;
+    gr[7] = -gdy;
+    (void)q2;
+  }
+};
+
 // ----------------------------- LiDAR -------------------------------------
-// Staged record (5 x float4):
+// Staged record (5 x float4), the fields every pair reads first:
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
-//  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, intensity, flags
-//  [4] o, columns lo|hi<<16 (may wrap), beams lo|hi<<16, -
+//  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, 2^-23 kappa, flags
+//  [4] intensity, columns lo|hi<<16 (may wrap), beams lo|hi<<16, the tile's error bound Et
 __device__ __forceinline__ uint2 stage_lidar(const RawRec& x, const double* dtile, float4* dst) {
+  // global record: Q (9), |mu|, log2 o, intensity, flags, 2^-23 kappa, columns, beams
   const float4 r0 = x.r[0], r1 = x.r[1], r2 = x.r[2], r3 = x.r[3];
   const float c0 = (float)(dtile[0] - x.d[0].x);
   const float c1 = (float)(dtile[1] - x.d[0].y);
@@ -461,12 +957,12 @@ __device__ __forceinline__ uint2 stage_lidar(const RawRec& x, const double* dtil
   dst[0] = make_float4(c0, c1, c2, r0.x);
   dst[1] = make_float4(r0.y, r0.z, r0.w, r1.x);
   dst[2] = make_float4(r1.y, r1.z, r1.w, r2.x);
-  dst[3] = make_float4(r2.y, r2.z, r2.w, r3.x);
-  dst[4] = make_float4(r3.y, r3.z, r3.w, 0.0f);
+  dst[3] = make_float4(r2.y, r2.z, r3.y, r3.x);
+  dst[4] = make_float4(r2.w, r3.z, r3.w, 0.0f);
   return make_uint2(__float_as_uint(r3.z), __float_as_uint(r3.w));
 }
 
-__device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix,
+__device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix, float dpm,
                                            const double* d64, const TileArgs& a, const EvalK& K, const F64Slot* f64,
                                            PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
@@ -481,37 +977,30 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   float r = __builtin_amdgcn_rcpf(h2);
   float u = h0 * r, v = h1 * r, z = q3.x * r;
   bool ok = h2 != 0.0f;
-  if (flags & kFlagGrazing) {  // the same record for the whole wave
-    if (fabsf(h2) < 0.125f) {
-      ++n64;
-      const uint32_t slot = (flags >> 8) & 0xFFu;
-      if (slot && f64)
-        ok = solve64_lidar(f64[slot - 1], f64[slot - 1] + kGrz, d64, u, v, r, z);
-      else
-        ok = solve64_lidar(a.grz + kGrz * (size_t)s, a.rec64 + kRec64 * (size_t)s, d64, u, v, r, z);
-    }
-  }
-  const float rho = fmaf(u, u, v * v);
   const float rl = K.lp * fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-  const bool lp_used = K.lowpass && !(rho <= rl);
-  const float rho_hat = lp_used ? rl : rho;
-  if (lp_used) z = q3.x;  // the centre's range |mu| (see eval_pinhole)
-  ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
-  float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, q3.y));
-  const bool clamped = alpha > K.alpha_max;
-  if (clamped) alpha = K.alpha_max;
-  ok = ok && !(alpha < K.alpha_min);
-  e.alpha = alpha;
-  e.u = u;
-  e.v = v;
-  e.z = z;
-  e.r = r;
   e.dx = d0;
   e.dy = d1;
   e.dz3 = d2;
-  e.lp_used = lp_used;
-  e.clamped = clamped;
-  return ok;
+  // the centre's range |mu| for low-pass pairs (see eval_pinhole)
+  bool hit = finish_pair(u, v, r, z, ok, rl, q3.x, q3.y, K, e);
+  // FP64 re-solve as for the pinhole camera
+  const uint32_t slot = (flags >> 8) & 0xFFu;
+  bool redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
+  if (flags & kFlagEdge) {
+    // the roundings of dpix and of c, then two of d's size and two in the
+    // products (the record holds 2^-23 kappa)
+    const float dm = fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fabsf(d2));
+    const float cm = fmaxf(fmaxf(fabsf(q0.x), fabsf(q0.y)), fabsf(q0.z));
+    redo = redo | edge_needs_f64(e, fmaf(q3.z, fmaf(2.0f, dm, dpm + cm), 0x1p-20f), rl, flags, K);
+  }
+  if (redo) {
+    ++n64;
+    double g[10], c[3];
+    fetch64<10, 3>(a, f64, slot, s, g, c);
+    ok = solve64_lidar(g, c, d64, u, v, r, z);
+    hit = finish_pair(u, v, r, z, ok, rl, q3.x, q3.y, K, e);
+  }
+  return hit;
 }
 
 // Ray direction of LiDAR column c, beam j, in FP64: the line where the two
@@ -534,7 +1023,7 @@ struct LidarRay {
   bool inside;
   EvalK K;
   double dt[3], d64[3];
-  float dpix[3];
+  float dpix[3], dpm;  // dpm: max |dpix|
 
   __device__ LidarRay(const TileArgs& a, int tile) : K(eval_consts(a, a.S.lp_ang)) {
     const int WX = a.S.tw >> 3;
@@ -554,9 +1043,30 @@ struct LidarRay {
     dpix[0] = (float)(d64[0] - dt[0]);
     dpix[1] = (float)(d64[1] - dt[1]);
     dpix[2] = (float)(d64[2] - dt[2]);
+    dpm = fmaxf(fmaxf(fabsf(dpix[0]), fabsf(dpix[1])), fabsf(dpix[2]));
   }
   __device__ size_t pix(const TileArgs& a) const { return (size_t)pb * a.S.W + pc; }
-  __device__ uint2 stage(const RawRec& x, float4* dst) const { return stage_lidar(x, dt, dst); }
+  // the staged record, with its FP32 error bound over this tile: as the
+  // camera's, with the offset d = dpix + c bounded by |c| plus the largest
+  // |dpix| of the blocks that evaluate the record (their direction boxes),
+  // |dpix| and |c| counted once more for their own roundings
+  __device__ uint2 stage(const RawRec& x, float4* dst, const float (*box)[6], int nw) const {
+#pragma clang fp contract(off)
+    const uint2 rect = stage_lidar(x, dt, dst);
+    float m[3] = {0.0f, 0.0f, 0.0f};
+    for (int w = 0; w < nw; ++w) {
+      if (!touches(rect, w)) continue;  // no pair of this block is evaluated
+#pragma unroll
+      for (int k = 0; k < 3; ++k) m[k] = fmaxf(m[k], fmaxf(fabsf(box[w][2 * k]), fabsf(box[w][2 * k + 1])));
+    }
+    const float c0 = fabsf(dst[0].x), c1 = fabsf(dst[0].y), c2 = fabsf(dst[0].z);
+    const float h2m = 1.0f - (fabsf(dst[2].y) * (c0 + m[0]) + fabsf(dst[2].z) * (c1 + m[1]) + fabsf(dst[2].w) * (c2 + m[2]));
+    const float mi = fmaxf(fmaxf(c0 + m[0], c1 + m[1]), c2 + m[2]), mp = fmaxf(fmaxf(m[0], m[1]), m[2]);
+    const float mc = fmaxf(fmaxf(c0, c1), c2);
+    const float Et = fmaf(dst[3].z, 2.0f * mi + mp + mc, 0x1p-20f) / fmaxf(h2m, 0.125f);
+    set_tile_bound(dst[3].w, dst[4].w, Et, dst[3].y);
+    return rect;
+  }
   __device__ bool touches(uint2 rect, int w) const {
     return !misses_block_wrap(rect.x, rect.y, ox + (w % wx) * 8, oy + (w / wx) * 8);
   }
@@ -617,6 +1127,7 @@ struct LidarRay {
     r2 = r2 * 1.001f + 1e-3f;
     const float Q[9] = {q0.w, q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
     const float cc[3] = {q0.x, q0.y, q0.z};
+    const float sl = 2.0f * d[4].w;  // slack: twice the tile's FP32 error bound
     uint32_t m = 0u;
     for (int w = 0; w < nw; ++w) {
       float mid[3], rad[3], dist2 = 0.0f;
@@ -651,7 +1162,7 @@ struct LidarRay {
         const float a0 = hm[i] - hr[i], a1 = hm[i] + hr[i];
         const float x0 = a0 * i_lo, x1 = a0 * i_hi, x2 = a1 * i_lo, x3 = a1 * i_hi;
         const float lo = fminf(fminf(x0, x1), fminf(x2, x3)), hi = fmaxf(fmaxf(x0, x1), fmaxf(x2, x3));
-        ev[i] = lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f);
+        ev[i] = fmaxf((lo > 0.0f ? lo : (hi < 0.0f ? -hi : 0.0f)) - sl, 0.0f);
       }
       if (!(ev[0] * ev[0] + ev[1] * ev[1] > r2)) m |= 1u << w;
     }
@@ -665,12 +1176,12 @@ struct LidarRay {
   }
   __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
-    return eval_lidar(R, s, dpix, d64, a, K, f64, e, n64);
+    return eval_lidar(R, s, dpix, dpm, d64, a, K, f64, e, n64);
   }
   static __device__ float& flag_word(float4* R) { return R[3].w; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
     f[0] = e.z;
-    f[1] = R[3].z;
+    f[1] = R[4].x;
     f[2] = 1.0f;
   }
   static __device__ void out_values(const TileArgs&, float, const float* acc, float* v) {
@@ -692,7 +1203,7 @@ struct LidarRay {
                         float* gr) const {
 #pragma clang fp contract(off)
     const float4 q0 = R[0], q1 = R[1], q2 = R[2];
-    const float o = R[4].x;
+    const float o = __builtin_amdgcn_exp2f(R[3].y);
     const float al = e.alpha;
     const float grange = g[0] * wgt;
     gr[14] = g[1] * wgt;
@@ -777,7 +1288,7 @@ struct GradArea<NT, false> {};
 // Shared-memory state of one compositing workgroup.
 template <int NT, bool BWD = false>
 struct BlendShared {
-  float4 rec[NT][5];
+  float4 rec[NT][6];
   uint32_t id[NT];
   uint64_t mask[NT / 64][NT / 64];
   F64Slot f64[kF64Slots];
@@ -801,7 +1312,7 @@ __device__ __forceinline__ void commit_batch(const TileArgs& a, const Ray& ray, 
   uint2 rect = make_uint2(0u, 0u);
   if (valid) {
     float4* dst = sh.rec[t];
-    rect = ray.stage(x, dst);
+    rect = ray.stage(x, dst, sh.lbox, NT / 64);
     sh.id[t] = s;
     float& fw = Ray::flag_word(dst);
     const uint32_t flags = __float_as_uint(fw);
@@ -899,15 +1410,18 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
       while (m) {
         const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
-        float4 R[5];
+        // the solve's fields (the first four) into registers; the rest
+        // (features, rectangle) is read where needed
+        const float4* Rl = sh.rec[j];
+        float4 R[4];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) R[i] = sh.rec[j][i];
+        for (int i = 0; i < 4; ++i) R[i] = Rl[i];
         if constexpr (COUNT) {
           ++n_iter;
           if (lane_counts)
-            n_eval += (ray.covered(R) && !done) ? 1u : 0u;
+            n_eval += (ray.covered(Rl) && !done) ? 1u : 0u;
           else
-            n_eval += (uint32_t)__popcll(live & ray.cover_lanes(R));
+            n_eval += (uint32_t)__popcll(live & ray.cover_lanes(Rl));
         }
         PairEval e;
         const bool hit = ray.eval(a, R, sh.id[j], sh.f64, e, n64) && !done;
@@ -917,7 +1431,7 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           if constexpr (COUNT) ++n_contrib;
           const float wgt = e.alpha * T;
           float f[C];
-          ray.feat(R, e, f);
+          ray.feat(Rl, e, f);
 #pragma unroll
           for (int c2 = 0; c2 < C; ++c2) acc[c2] = fmaf(wgt, f[c2], acc[c2]);
           T = Tn;
@@ -1317,7 +1831,7 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
 
 // Sensor kinds a launch may meet (bit 0 camera, bit 1 LiDAR): single-kind
 // launches leave the other kind's code and registers out.
-constexpr int kKindCam = 1, kKindLidar = 2, kKindBoth = 3;
+constexpr int kKindCam = 1, kKindLidar = 2, kKindBoth = 3, kKindCyl = 4;
 
 __device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1400,7 +1914,7 @@ __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& d
 // Persistent compositing over (tile, segment) items and, in the forward pass,
 // the walk entries the merges list.
 template <int NT, bool BWD, int KINDS, bool COUNT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT ? 1 : 4))) void k_blend_queue(QueueArgs q) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT || (KINDS & kKindCyl) ? 1 : 4))) void k_blend_queue(QueueArgs q) {
   __shared__ BlendShared<NT, BWD> sh;
   uint32_t* s_u = sh.u;
   const uint32_t n_items = min(*q.n_items, q.cap_items);
@@ -1431,16 +1945,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT
     const TileArgs& a = q.tiles[si];
     const int tile = (int)gt - q.tile_off[si];
     if (act != kActItem) rg = a.ranges[gt];
+    // the sensor's kind, decided statically where the launch serves one kind
     const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
+    const bool cyl = (KINDS & kKindCyl) && (KINDS == kKindCyl || a.S.kind == GS_SENSOR_CYLINDRICAL);
     if constexpr (BWD) {
       if (cam)
         bwd_item<NT, CamRay>(q, a, tile, gt, sg, rg, sh);
+      else if (cyl)
+        bwd_item<NT, CylRay>(q, a, tile, gt, sg, rg, sh);
       else if (KINDS & kKindLidar)
         bwd_item<NT, LidarRay>(q, a, tile, gt, sg, rg, sh);
     } else {
       const bool walk = act == kActWalk;
       if (cam)
         fwd_item<NT, COUNT, CamRay>(q, a, si, tile, gt, sg, rg, walk, sh);
+      else if (cyl)
+        fwd_item<NT, COUNT, CylRay>(q, a, si, tile, gt, sg, rg, walk, sh);
       else if (KINDS & kKindLidar)
         fwd_item<NT, COUNT, LidarRay>(q, a, si, tile, gt, sg, rg, walk, sh);
     }
@@ -1464,8 +1984,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT
 
 }  // namespace
 
-#define GS_TILE_RAYS(X) X(64) X(128) X(256) X(512)
-#define GS_KINDS(X, NT) X(NT, 1) X(NT, 2) X(NT, 3)
+// Launch variants: every tile size for pinhole / LiDAR mixes; kinds with the
+// cylindrical camera (bit 2) at 256-ray tiles only (plans enforce it).
+#define GS_VARIANTS(X) \
+  X(64, 1) X(64, 2) X(64, 3) X(128, 1) X(128, 2) X(128, 3) X(256, 1) X(256, 2) X(256, 3) X(512, 1) X(512, 2) \
+  X(512, 3) X(256, 4) X(256, 5) X(256, 6) X(256, 7)
 
 void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, bool count,
                         hipStream_t st) {
@@ -1479,9 +2002,7 @@ void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool 
       hipLaunchKernelGGL((k_blend_queue<NT, false, K, false>), dim3(grid), dim3(NT), 0, st, q);   \
     return;                                                                                       \
   }
-#define CASE(NT) GS_KINDS(KCASE, NT)
-  GS_TILE_RAYS(CASE)
-#undef CASE
+  GS_VARIANTS(KCASE)
 #undef KCASE
 }
 
@@ -1492,9 +2013,7 @@ int blend_blocks_per_cu(int rays, int kinds, bool backward) {
   if (rays == NT && kinds == K)                                                                              \
     e = backward ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, true, K, false>, NT, 0) \
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_blend_queue<NT, false, K, false>, NT, 0);
-#define CASE(NT) GS_KINDS(KCASE, NT)
-  GS_TILE_RAYS(CASE)
-#undef CASE
+  GS_VARIANTS(KCASE)
 #undef KCASE
   return e == hipSuccess ? n : 0;
 }

@@ -17,7 +17,7 @@ namespace gs {
 constexpr int kMaxGroups = GS_MAX_GROUPS;
 constexpr int kRecF32 = 16;     // floats per surfel record
 constexpr int kRec64 = 4;       // doubles per surfel record (camera: pc; LiDAR: unit centre)
-constexpr int kGrz = 10;        // doubles per grazing record
+constexpr int kGrz = 10;        // doubles per record with FP64 re-solve data
 constexpr int kGradFields = 16; // per-surfel gradient accumulators
 constexpr int kRadixItems = 4096;
 // keys per radix sort (pairs, records): the look-back counts are 30-bit
@@ -25,7 +25,35 @@ constexpr uint32_t kMaxSortKeys = (1u << 30) - 1u;
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
 
 // record flags (stored as integer bits in float slot 14)
+//  grazing: h'_2 may fall below 1/8 in the rectangle; pairs with |h'_2| < 1/8
+//    are solved in FP64.
+//  edge: the surfel is seen nearly edge-on, so its 2 x 2 solve is
+//    ill-conditioned: the FP32 (u, v) may be off by enough to move alpha by
+//    more than kEdgeTau.  The record carries FP64 re-solve data; per tile the
+//    staged copy keeps the bit only where the tile's own bound still allows
+//    that, and then each pair re-solves in FP64 where its alpha error could.
+//  wild (staged copies only): the tile's (u, v) error bound exceeds
+//    kWildErr, too large to trust the FP32 rho at all: every pair that could
+//    be inside the support with that error re-solves in FP64.
 constexpr uint32_t kFlagGrazing = 1u;
+constexpr uint32_t kFlagEdge = 2u;
+constexpr uint32_t kFlagWild = 4u;
+constexpr uint32_t kFlagF64 = kFlagGrazing | kFlagEdge;  // records that carry FP64 re-solve data
+// Error budget of one pair's FP32 solve: the first-order bound of its alpha
+// error must stay below kEdgeTau, a tenth of the 1e-4 output bar.
+constexpr float kEdgeTau = 1e-5f;
+constexpr float kWildErr = 0.05f;
+// The FP32 (u, v) error of a pair is bounded, to first order, by
+// err = (2^-23 kappa s + 2^-20) / |h'_2|: kappa the largest absolute row sum
+// of the solve's (u, v) rows plus 3.4 times that of its h'_2 row, s = 2
+// |offset from the centre|_inf (the offset's own rounding and the products';
+// the centre itself is held to twice FP32 precision in the tile frame).  A
+// record is edge-flagged when its bound E over the pixels of the tiles its
+// rectangle touches allows an alpha error above the budget (|(u, v)|_1 <= 4.7
+// inside the cutoff, alpha <= 0.61 o there).
+__device__ inline uint32_t conditioning_flags(double E, float o) {
+  return 2.87 * (double)o * E > (double)kEdgeTau ? kFlagEdge : 0u;
+}
 
 struct GroupsK {
   int n;                     // groups in the scene
@@ -49,8 +77,8 @@ struct SensorK {
   float inv_step, step;      // azimuth steps per radian and its inverse (FP32 spec)
   float c_lp;                // sqrt(cutoff2 / lp) * step: low-pass chord radius
   float lp_ang;              // lp / step^2 (FP32) for the per-ray low-pass
-  // FP32 tables, one array: elevations [H], cos and sin of elevation [H]
-  // each, cos and sin of azimuth [W] each
+  // LiDAR: FP32 tables, one array: elevations [H], cos and sin of elevation
+  // [H] each, cos and sin of azimuth [W] each
   const float* tab;
 };
 
@@ -282,6 +310,76 @@ __device__ inline int upper_bound_f(const float* el, int n, float x) {
     if (el[mid] <= x) lo = mid + 1; else hi = mid;
   }
   return lo;
+}
+
+// Cylindrical camera (Eq. 4): pixel (c_x + f_x phi, c_y + f_y y_n) for the
+// ray (sin phi, y_n, cos phi).  The support lies in the ball of radius
+// R = sqrt(k) max(s_u, s_v) around mu: |phi - phi_c| <= asin(R / r),
+// r = sqrt(mu_x^2 + mu_z^2), and y_n = y / r' over y in [mu_y - R, mu_y + R],
+// r' in [r - R, r + R]; united with the low-pass disc around the projected
+// centre (c_x + f_x phi_c, c_y + f_y mu_y / r) and padded by one pixel.  A
+// range across the back of the camera (phi = +-pi) takes every column.
+// Visible iff r^2 > (R + z_near)^2; key = r^2.
+__device__ inline void spec_cyl_bins(const Frame32& f, float su, float sv, const SensorK& S, const OptsK& O,
+                                     Bins& b) {
+#pragma clang fp contract(off)
+  const float k = O.cutoff2;
+  const float kPi = (float)3.141592653589793;
+  float r2 = f.mu[0] * f.mu[0] + f.mu[2] * f.mu[2];
+  float r = sqrtf(r2);
+  float R = sqrtf(k) * (su < sv ? sv : su);
+  float Rn = R + S.z_near;
+  bool vis = f.valid && (r2 > Rn * Rn) && finite_f(r2) && finite_f(R) && finite_f(f.mu[1]);
+  float phi_c = spec_atan2(f.mu[0], f.mu[2]);
+  float q = vis ? R / r : 0.0f;
+  float dphi = spec_asin(q < 1.0f ? q : 1.0f);
+  float y_lo = f.mu[1] - R, y_hi = f.mu[1] + R, r_lo = r - R, r_hi = r + R;
+  float a1 = y_lo / r_lo, a2 = y_lo / r_hi, b1 = y_hi / r_lo, b2 = y_hi / r_hi;
+  float yn_lo = a1 < a2 ? a1 : a2;
+  float yn_hi = b1 < b2 ? b2 : b1;
+  float a_lo = phi_c - dphi, a_hi = phi_c + dphi;
+  bool back = (a_lo < -kPi) || (a_hi > kPi);
+  float xlo = S.fx * a_lo, xhi = S.fx * a_hi, ylo = S.fy * yn_lo, yhi = S.fy * yn_hi;
+  if (O.lowpass) {
+    float rl = O.rl;
+    float pcx = S.fx * phi_c;
+    float pcy = S.fy * (f.mu[1] / r);
+    float a = pcx - rl, c = pcx + rl, e = pcy - rl, g = pcy + rl;
+    xlo = a < xlo ? a : xlo;
+    xhi = c > xhi ? c : xhi;
+    ylo = e < ylo ? e : ylo;
+    yhi = g > yhi ? g : yhi;
+  }
+  float X_lo = ((xlo - 1.0f) + S.cx) - 0.5f;
+  float X_hi = ((xhi + 1.0f) + S.cx) - 0.5f;
+  float Y_lo = ((ylo - 1.0f) + S.cy) - 0.5f;
+  float Y_hi = ((yhi + 1.0f) + S.cy) - 0.5f;
+  vis = vis && finite_f(X_lo) && finite_f(X_hi) && finite_f(Y_lo) && finite_f(Y_hi);
+  b.vis = vis;
+  b.wrap = false;
+  b.full_cols = false;
+  b.el_c = b.az_c = b.beta = 0.0f;
+  if (!vis) {
+    b.touch = false;
+    b.n_tiles = 0;
+    b.key = 0.0f;
+    b.tx_lo = b.tx_hi = b.ty_lo = b.ty_hi = b.i_lo = b.i_hi = b.j_lo = b.j_hi = 0;
+    return;
+  }
+  X_lo = back ? -2.0f : fclamp_spec(X_lo, -2.0f, (float)(S.W + 2));
+  X_hi = back ? (float)(S.W + 2) : fclamp_spec(X_hi, -2.0f, (float)(S.W + 2));
+  Y_lo = fclamp_spec(Y_lo, -2.0f, (float)(S.H + 2));
+  Y_hi = fclamp_spec(Y_hi, -2.0f, (float)(S.H + 2));
+  int i_lo = max((int)ceilf(X_lo), 0);
+  int i_hi = min((int)floorf(X_hi), S.W - 1);
+  int j_lo = max((int)ceilf(Y_lo), 0);
+  int j_hi = min((int)floorf(Y_hi), S.H - 1);
+  b.i_lo = i_lo; b.i_hi = i_hi; b.j_lo = j_lo; b.j_hi = j_hi;
+  b.touch = (i_lo <= i_hi) && (j_lo <= j_hi);
+  b.tx_lo = i_lo / S.tw; b.tx_hi = i_hi / S.tw;
+  b.ty_lo = j_lo / S.th; b.ty_hi = j_hi / S.th;
+  b.n_tiles = b.touch ? (uint32_t)((b.tx_hi - b.tx_lo + 1) * (b.ty_hi - b.ty_lo + 1)) : 0u;
+  b.key = r2;
 }
 
 __device__ inline void spec_lidar_bins(const Frame32& f, float su, float sv, const SensorK& S, const OptsK& O,

@@ -1,4 +1,5 @@
-// a0 + a2: pose composition and per-surfel preprocessing (pinhole and LiDAR).
+// a0 + a2: pose composition and per-surfel preprocessing (pinhole, cylindrical
+// camera and LiDAR).
 //
 // One thread per surfel.  Integer decisions (visibility, tile rectangle,
 // depth key, normal orientation) follow the FP32 binning specification in
@@ -7,6 +8,12 @@
 //   camera: h' = e3 + P (dx, dy) with (dx, dy) the pixel offset from the
 //           projected centre, u = h'_0/h'_2, v = h'_1/h'_2, z = mu_z / h'_2
 //   LiDAR : h' = e3 + Q (d - mu_hat), u, v as above, range = |mu| / h'_2
+//   cylindrical: the camera form in the surfel's own column frame (the
+//           sensor frame turned about y by the centre's angle phi_c, where
+//           mu = (0, mu_y, r)): a ray at angle phi is the pinhole ray
+//           (tan dphi, y_n sec dphi, 1), dphi = phi - phi_c, so with
+//           X = f_x tan dphi, Y = f_y (y_n sec dphi - mu_y / r),
+//           h' = e3 + P (X, Y) and the depth is r sec dphi / h'_2
 // (h' is adj(M) d scaled so that its third entry is 1 at the surfel centre).
 #include "gs_internal.h"
 #include "kernels.h"
@@ -93,8 +100,8 @@ __device__ inline void load_surfel(const PrepArgs& a, int i, float* P, float& m0
 
 // DEG: SH degree of the colour (-1: plain RGB), fixed per instantiation so
 // that the coefficient loads unroll and issue together, ahead of the FP64 frame.
-template <int DEG>
-__global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
+template <int DEG, bool CYL>
+__global__ __launch_bounds__(256) void k_prep_camera(PrepArgs a) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= a.n) return;
   const int N = a.n;
@@ -103,7 +110,10 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   Frame32 f;
   spec_frame(P, m0, m1, m2, qw, qx, qy, qz, su, sv, f);
   Bins b;
-  spec_pinhole_bins(f, a.S, a.O, b);
+  if constexpr (CYL)
+    spec_cyl_bins(f, su, sv, a.S, a.O, b);
+  else
+    spec_pinhole_bins(f, a.S, a.O, b);
   a.ws.key[0][i] = b.vis ? __float_as_uint(b.key) : kInvalidKey;
   a.ws.val[0][i] = a.rec_base + (uint32_t)i;
   a.ws.ntiles[i] = b.n_tiles;
@@ -125,13 +135,32 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
 
   Frame64 F;
   frame64(P, m0, m1, m2, qw, qx, qy, qz, su, sv, F);
-  const double muz = F.mus[2];
+  double muz, pcx, pcy;
+  double adj[3][3];
+  if constexpr (CYL) {
+    // the centre's column frame: x' = c x - s z, z' = s x + c z (mu' = (0, mu_y, r));
+    // adj(Ry M) = adj(M) Ry^T, det unchanged
+    const double r = sqrt(F.mus[0] * F.mus[0] + F.mus[2] * F.mus[2]);
+    const double phi_c = atan2(F.mus[0], F.mus[2]);
+    const double c = F.mus[2] / r, sn = F.mus[0] / r;
+    for (int k = 0; k < 3; ++k) {
+      adj[k][0] = F.adj[k][0] * c - F.adj[k][2] * sn;
+      adj[k][1] = F.adj[k][1];
+      adj[k][2] = F.adj[k][0] * sn + F.adj[k][2] * c;
+    }
+    muz = r;
+    pcx = (double)a.S.fx * phi_c + (double)a.S.cx;
+    pcy = (double)a.S.fy * F.mus[1] / r + (double)a.S.cy;
+  } else {
+    for (int k = 0; k < 3; ++k)
+      for (int c = 0; c < 3; ++c) adj[k][c] = F.adj[k][c];
+    muz = F.mus[2];
+    pcx = (double)a.S.fx * F.mus[0] / muz + (double)a.S.cx;
+    pcy = (double)a.S.fy * F.mus[1] / muz + (double)a.S.cy;
+  }
   const double k0 = muz / ((double)a.S.fx * F.det);
   const double k1 = muz / ((double)a.S.fy * F.det);
-  double Pm[6] = {F.adj[0][0] * k0, F.adj[0][1] * k1, F.adj[1][0] * k0,
-                  F.adj[1][1] * k1, F.adj[2][0] * k0, F.adj[2][1] * k1};
-  const double pcx = (double)a.S.fx * F.mus[0] / muz + (double)a.S.cx;
-  const double pcy = (double)a.S.fy * F.mus[1] / muz + (double)a.S.cy;
+  double Pm[6] = {adj[0][0] * k0, adj[0][1] * k1, adj[1][0] * k0, adj[1][1] * k1, adj[2][0] * k0, adj[2][1] * k1};
 
   // colour
   float col[3];
@@ -161,14 +190,42 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   // grazing: can h'_2 = 1 + P20 dx + P21 dy drop below 1/8 inside the rectangle?
   double mx = fmax(fabs(b.i_lo + 0.5 - pcx), fabs(b.i_hi + 0.5 - pcx));
   double my = fmax(fabs(b.j_lo + 0.5 - pcy), fabs(b.j_hi + 0.5 - pcy));
-  bool graze = fabs(Pm[4]) * mx + fabs(Pm[5]) * my > 0.875;
+  // grazing over the rectangle; the FP32 error bound (see the record flags)
+  // over the pixels of every tile the rectangle touches (up to a tile beyond
+  // it): s = 2 |offset|_inf there (4 |(X, Y)|_inf for the cylindrical map)
+  bool graze;
+  double h2e, s;
+  const double mxe = mx + a.S.tw, mye = my + a.S.th;
+  if constexpr (CYL) {
+    // |X| <= f tan(dphi_max), |Y| <= |dy| + |p_y - c_y| (sec dphi_max - 1); past
+    // 80 degrees (only for surfels near the camera) every pair may graze
+    const double dmax = mx / (double)a.S.fx;
+    const double ay = fmax(fabs(b.j_lo + 0.5 - (double)a.S.cy), fabs(b.j_hi + 0.5 - (double)a.S.cy));
+    const double Xm = (double)a.S.fx * tan(fmin(dmax, 1.39)), Ym = my + ay * (1.0 / cos(fmin(dmax, 1.39)) - 1.0);
+    graze = dmax > 1.39 || 1.0 - (fabs(Pm[4]) * Xm + fabs(Pm[5]) * Ym) < 0.125;
+    const double de = fmin(mxe / (double)a.S.fx, 1.39), aye = ay + a.S.th;
+    const double Xe = (double)a.S.fx * tan(de), Ye = mye + aye * (1.0 / cos(de) - 1.0);
+    h2e = 1.0 - (fabs(Pm[4]) * Xe + fabs(Pm[5]) * Ye);
+    s = 4.0 * fmax(Xe, Ye);
+  } else {
+    graze = 1.0 - (fabs(Pm[4]) * mx + fabs(Pm[5]) * my) < 0.125;
+    h2e = 1.0 - (fabs(Pm[4]) * mxe + fabs(Pm[5]) * mye);
+    s = 2.0 * fmax(mxe, mye);
+  }
   uint32_t flags = graze ? kFlagGrazing : 0u;
+  // kappa: the (u, v) rows' largest absolute sum, plus the h'_2 row's times
+  // the largest |u|, |v| inside the cutoff (its error enters as u dh'_2)
+  const double kap = fmax(fabs(Pm[0]) + fabs(Pm[1]), fabs(Pm[2]) + fabs(Pm[3])) + 3.4 * (fabs(Pm[4]) + fabs(Pm[5]));
+  flags |= conditioning_flags((0x1p-23 * kap * s + 0x1p-20) / fmax(h2e, 0.125), o);
 
   float4* r = a.ws.rec + 4 * (size_t)i;
   r[0] = make_float4((float)Pm[0], (float)Pm[1], (float)Pm[2], (float)Pm[3]);
   r[1] = make_float4((float)Pm[4], (float)Pm[5], (float)muz, log2o);
   r[2] = make_float4(col[0], col[1], col[2], (float)(nsign * F.ns[0]));
-  r[3] = make_float4((float)(nsign * F.ns[1]), (float)(nsign * F.ns[2]), __uint_as_float(flags), o);
+  // slot 15: the per-record factor of the pairs' FP32 error bound, 2^-23 kappa
+  // times the offsets' weight in it (2, or 4 for the cylindrical map)
+  r[3] = make_float4((float)(nsign * F.ns[1]), (float)(nsign * F.ns[2]), __uint_as_float(flags),
+                     (float)((CYL ? 0x1p-21 : 0x1p-22) * kap));
   double* r64 = a.ws.rec64 + kRec64 * (size_t)i;
   r64[0] = pcx;
   r64[1] = pcy;
@@ -177,7 +234,7 @@ __global__ __launch_bounds__(256) void k_prep_pinhole(PrepArgs a) {
   uint32_t* rr = reinterpret_cast<uint32_t*>(r64 + 3);
   rr[0] = (uint32_t)b.i_lo | ((uint32_t)b.i_hi << 16);
   rr[1] = (uint32_t)b.j_lo | ((uint32_t)b.j_hi << 16);
-  if (graze) {
+  if (flags & kFlagF64) {
     double* gz = a.ws.grz + kGrz * (size_t)i;
     for (int k = 0; k < 6; ++k) gz[k] = Pm[k];
     gz[6] = muz;
@@ -226,22 +283,34 @@ __global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
     ang_az = fmax(d1, d2) + step * (double)a.S.tw;
   }
   double bound = ang_el + ang_az + 0.01;
-  bool graze = (fabs(Q[6]) + fabs(Q[7]) + fabs(Q[8])) * bound > 0.875;
+  const double h2m = 1.0 - (fabs(Q[6]) + fabs(Q[7]) + fabs(Q[8])) * bound;
+  bool graze = h2m < 0.125;
   uint32_t flags = graze ? kFlagGrazing : 0u;
+  // FP32 error bound (see the record flags) over the rays of every tile the
+  // rectangle touches: offsets from the centre direction and from a tile's
+  // reference direction are chords of at most `bound` plus a tile's angular
+  // extent (its columns' azimuth span, 0.1 rad of elevation at most)
+  const double kap = fmax(fabs(Q[0]) + fabs(Q[1]) + fabs(Q[2]), fabs(Q[3]) + fabs(Q[4]) + fabs(Q[5])) +
+                     3.4 * (fabs(Q[6]) + fabs(Q[7]) + fabs(Q[8]));
+  const double ext = bound + 6.283185307179586 * a.S.tw / a.S.W + 0.1;
+  const double h2e = 1.0 - (fabs(Q[6]) + fabs(Q[7]) + fabs(Q[8])) * ext;
+  flags |= conditioning_flags((0x1p-23 * kap * 3.0 * ext + 0x1p-20) / fmax(h2e, 0.125), o);
 
   float4* r = a.ws.rec + 4 * (size_t)i;
   r[0] = make_float4((float)Q[0], (float)Q[1], (float)Q[2], (float)Q[3]);
   r[1] = make_float4((float)Q[4], (float)Q[5], (float)Q[6], (float)Q[7]);
   r[2] = make_float4((float)Q[8], (float)rn, log2o, inten);
-  // conservative beam/column rectangle (columns may wrap), 16 bits per bound
-  r[3] = make_float4(__uint_as_float(flags), o, __uint_as_float((uint32_t)b.i_lo | ((uint32_t)b.i_hi << 16)),
+  // flags; 2^-23 kappa, the per-record factor of the pairs' FP32 error bound;
+  // the conservative column/beam rectangle (columns may wrap), 16 bits per bound
+  r[3] = make_float4(__uint_as_float(flags), (float)(0x1p-23 * kap),
+                     __uint_as_float((uint32_t)b.i_lo | ((uint32_t)b.i_hi << 16)),
                      __uint_as_float((uint32_t)b.j_lo | ((uint32_t)b.j_hi << 16)));
   double* r64 = a.ws.rec64 + kRec64 * (size_t)i;
   r64[0] = mh[0];
   r64[1] = mh[1];
   r64[2] = mh[2];
   r64[3] = rn;
-  if (graze) {
+  if (flags & kFlagF64) {
     double* gz = a.ws.grz + kGrz * (size_t)i;
     for (int k = 0; k < 9; ++k) gz[k] = Q[k];
     gz[9] = rn;
@@ -258,11 +327,19 @@ void launch_prep(const PrepArgs& a, hipStream_t st) {
   dim3 grid((a.n + 255) / 256);
   if (a.S.kind == GS_SENSOR_PINHOLE) {
     switch (a.sh_degree) {
-      case 0: hipLaunchKernelGGL(k_prep_pinhole<0>, grid, dim3(256), 0, st, a); break;
-      case 1: hipLaunchKernelGGL(k_prep_pinhole<1>, grid, dim3(256), 0, st, a); break;
-      case 2: hipLaunchKernelGGL(k_prep_pinhole<2>, grid, dim3(256), 0, st, a); break;
-      case 3: hipLaunchKernelGGL(k_prep_pinhole<3>, grid, dim3(256), 0, st, a); break;
-      default: hipLaunchKernelGGL(k_prep_pinhole<-1>, grid, dim3(256), 0, st, a); break;
+      case 0: hipLaunchKernelGGL((k_prep_camera<0, false>), grid, dim3(256), 0, st, a); break;
+      case 1: hipLaunchKernelGGL((k_prep_camera<1, false>), grid, dim3(256), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((k_prep_camera<2, false>), grid, dim3(256), 0, st, a); break;
+      case 3: hipLaunchKernelGGL((k_prep_camera<3, false>), grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_prep_camera<-1, false>), grid, dim3(256), 0, st, a); break;
+    }
+  } else if (a.S.kind == GS_SENSOR_CYLINDRICAL) {
+    switch (a.sh_degree) {
+      case 0: hipLaunchKernelGGL((k_prep_camera<0, true>), grid, dim3(256), 0, st, a); break;
+      case 1: hipLaunchKernelGGL((k_prep_camera<1, true>), grid, dim3(256), 0, st, a); break;
+      case 2: hipLaunchKernelGGL((k_prep_camera<2, true>), grid, dim3(256), 0, st, a); break;
+      case 3: hipLaunchKernelGGL((k_prep_camera<3, true>), grid, dim3(256), 0, st, a); break;
+      default: hipLaunchKernelGGL((k_prep_camera<-1, true>), grid, dim3(256), 0, st, a); break;
     }
   } else
     hipLaunchKernelGGL(k_prep_lidar, grid, dim3(256), 0, st, a);

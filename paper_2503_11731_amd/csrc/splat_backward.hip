@@ -5,6 +5,9 @@
 // Camera record: P[:,j] = adj(M)[:,j] mu_z / (f_j det M) (j = 0, 1),
 //   pc = (fx mu_x / mu_z, fy mu_y / mu_z), mu_z, o, colour, normal.
 // LiDAR record: Q = |mu| adj(M) / det M, mu_hat = mu / |mu|, |mu|, o, intensity.
+// Cylindrical record: the camera record of M' = Ry M, the sensor frame turned
+// about y by the centre's angle phi_c = atan2(mu_x, mu_z) (mu' = (0, mu_y, r)),
+// with pc = (c_x + fx phi_c, c_y + fy mu_y / r) and r in place of mu_z.
 // adj(M) columns are r1 x r2, r2 x r0, r0 x r1 (rows r_i of M), det = r0 . (r1 x r2),
 // M = [s_u R t_u, s_v R t_v, R mu + t], (t_u, t_v, n) the columns of the
 // rotation of q scaled by s = 2/|q|^2.
@@ -140,6 +143,70 @@ __global__ __launch_bounds__(256, 3) void k_splat_backward(SplatBwdArgs A) {
     gns[0] = sgn * gf[13];
     gns[1] = sgn * gf[14];
     gns[2] = sgn * gf[15];
+  } else if constexpr (KIND == GS_SENSOR_CYLINDRICAL) {
+    const double fx = a.S.fx, fy = a.S.fy;
+    const double r = sqrt(mus[0] * mus[0] + mus[2] * mus[2]);
+    const double cc = mus[2] / r, sc = mus[0] / r;
+    // rows of M' = Ry M and its adjugate columns (det unchanged)
+    double Mp[3][3];
+    for (int k = 0; k < 3; ++k) {
+      Mp[0][k] = cc * Mr[0][k] - sc * Mr[2][k];
+      Mp[1][k] = Mr[1][k];
+      Mp[2][k] = sc * Mr[0][k] + cc * Mr[2][k];
+    }
+    double e0[3], e1[3], e2[3];
+    cross3(Mp[1], Mp[2], e0);
+    cross3(Mp[2], Mp[0], e1);
+    cross3(Mp[0], Mp[1], e2);
+    const double detp = dot3(Mp[0], e0);
+    const double ifx = 1.0 / fx, ify = 1.0 / fy, idet = 1.0 / detp, ir = 1.0 / r;
+    const double g0[3] = {gf[0], gf[2], gf[4]};  // dL/dP[:,0]
+    const double g1[3] = {gf[1], gf[3], gf[5]};  // dL/dP[:,1]
+    const double S0 = dot3(g0, e0) * ifx, S1 = dot3(g1, e1) * ify;
+    const double Ssum = S0 + S1;
+    const double gdet = -Ssum * r * idet * idet;
+    double ga0[3], ga1[3];
+    for (int k = 0; k < 3; ++k) {
+      ga0[k] = g0[k] * r * ifx * idet;
+      ga1[k] = g1[k] * r * ify * idet;
+    }
+    double hr0[3] = {0, 0, 0}, hr1[3] = {0, 0, 0}, hr2[3] = {0, 0, 0};  // dL/d rows of M'
+    acc_cross(Mp[2], ga0, hr1);
+    acc_cross(ga0, Mp[1], hr2);
+    acc_cross(Mp[0], ga1, hr2);
+    acc_cross(ga1, Mp[2], hr0);
+    for (int k = 0; k < 3; ++k) {
+      hr0[k] += gdet * e0[k];
+      hr1[k] += gdet * e1[k];
+      hr2[k] += gdet * e2[k];
+    }
+    // direct dependencies on mu' = (0, mu_y, r): P's scale r, the record's r, pc_y
+    const double gpcx = gf[6], gpcy = gf[7];
+    const double gmp[3] = {0.0, gpcy * fy * ir, Ssum * idet + (double)gf[8] - gpcy * fy * mus[1] * ir * ir};
+    // phi_c: through pc_x and the turn of M' and mu'; dRy/dphi rows (-s, 0, -c), (0, 0, 0), (c, 0, -s)
+    double gphi = gpcx * fx;
+    for (int k = 0; k < 3; ++k)
+      gphi += hr0[k] * (-sc * Mr[0][k] - cc * Mr[2][k]) + hr2[k] * (cc * Mr[0][k] - sc * Mr[2][k]);
+    gphi += gmp[0] * (-sc * mus[0] - cc * mus[2]) + gmp[2] * (cc * mus[0] - sc * mus[2]);
+    // back to the sensor frame (Ry^T), and phi_c = atan2(mu_x, mu_z)
+    for (int k = 0; k < 3; ++k) {
+      gr0[k] = cc * hr0[k] + sc * hr2[k];
+      gr1[k] = hr1[k];
+      gr2[k] = -sc * hr0[k] + cc * hr2[k];
+    }
+    gmus_extra[0] += cc * gmp[0] + sc * gmp[2] + gphi * mus[2] * ir * ir;
+    gmus_extra[1] += gmp[1];
+    gmus_extra[2] += -sc * gmp[0] + cc * gmp[2] - gphi * mus[0] * ir * ir;
+    g_op = gf[9];
+    gcol[0] = gf[10];
+    gcol[1] = gf[11];
+    gcol[2] = gf[12];
+    Frame32 f32;
+    spec_frame(P, m0, m1, m2, qwf, qxf, qyf, qzf, su, sv, f32);
+    const double sgn = spec_normal_sign(f32);
+    gns[0] = sgn * gf[13];
+    gns[1] = sgn * gf[14];
+    gns[2] = sgn * gf[15];
   } else {
     const double rn = sqrt(dot3(mus, mus));
     const double irn = 1.0 / rn, idet = 1.0 / det;
@@ -224,7 +291,7 @@ __global__ __launch_bounds__(256, 3) void k_splat_backward(SplatBwdArgs A) {
   if (A.g_opacity) A.g_opacity[i] += (float)g_op;
 
   // colour from SH: view direction v = R^T mu_s (group frame), colour = max(0, sum c Y + 1/2)
-  if constexpr (KIND == GS_SENSOR_PINHOLE && DEG >= 0) {
+  if constexpr (KIND != GS_SENSOR_LIDAR && DEG >= 0) {
     constexpr int nb = (DEG + 1) * (DEG + 1);
     if (gcol[0] != 0.0 || gcol[1] != 0.0 || gcol[2] != 0.0) {
       double v[3];
@@ -269,7 +336,7 @@ __global__ __launch_bounds__(256, 3) void k_splat_backward(SplatBwdArgs A) {
       // v = mu - c_group, so dL/dmu gains the projected direction gradient
       for (int c = 0; c < 3; ++c) gmu[c] += (gd[c] - dd[c] * pr) / vn;
     }
-  } else if constexpr (KIND == GS_SENSOR_PINHOLE) {
+  } else if constexpr (KIND != GS_SENSOR_LIDAR) {
     if (A.g_rgb) {
       const float o0 = A.g_rgb[i], o1 = A.g_rgb[N + i], o2 = A.g_rgb[2 * N + i];
       A.g_rgb[i] = o0 + (float)gcol[0];
@@ -293,7 +360,7 @@ __global__ __launch_bounds__(256, 3) void k_splat_backward(SplatBwdArgs A) {
 template <int KIND>
 void launch_kind(const SplatBwdArgs& a, hipStream_t st) {
   const dim3 grid((a.p.n + 255) / 256), block(256);
-  if constexpr (KIND == GS_SENSOR_PINHOLE) {
+  if constexpr (KIND != GS_SENSOR_LIDAR) {
     switch (a.p.sh_degree) {
       case 0: hipLaunchKernelGGL((k_splat_backward<KIND, 0>), grid, block, 0, st, a); return;
       case 1: hipLaunchKernelGGL((k_splat_backward<KIND, 1>), grid, block, 0, st, a); return;
@@ -309,6 +376,8 @@ void launch_splat_backward(const SplatBwdArgs& a, hipStream_t st) {
   if (a.p.n == 0) return;
   if (a.p.S.kind == GS_SENSOR_PINHOLE)
     launch_kind<GS_SENSOR_PINHOLE>(a, st);
+  else if (a.p.S.kind == GS_SENSOR_CYLINDRICAL)
+    launch_kind<GS_SENSOR_CYLINDRICAL>(a, st);
   else
     launch_kind<GS_SENSOR_LIDAR>(a, st);
 }

@@ -74,8 +74,9 @@ class Renderer:
         sens = (L.SensorDesc * len(self.sensors))()
         for i, s in enumerate(self.sensors):
             tw, th = s.get("tile", (0, 0))
-            if s["kind"] == "pinhole":
-                sens[i] = L.SensorDesc(L.GS_SENSOR_PINHOLE, s["width"], s["height"], s["fx"], s["fy"], s["cx"],
+            if s["kind"] in ("pinhole", "cylindrical"):
+                kind = L.GS_SENSOR_PINHOLE if s["kind"] == "pinhole" else L.GS_SENSOR_CYLINDRICAL
+                sens[i] = L.SensorDesc(kind, s["width"], s["height"], s["fx"], s["fy"], s["cx"],
                                        s["cy"], None, s["z_near"], s.get("scene", 0), tw, th)
             else:
                 el = np.ascontiguousarray(s["elevations"], np.float64)
@@ -109,7 +110,7 @@ class Renderer:
 
     # ------------------------------------------------------------------
     def channels(self, i: int) -> int:
-        return L.GS_CAMERA_CHANNELS if self.sensors[i]["kind"] == "pinhole" else L.GS_LIDAR_CHANNELS
+        return L.GS_LIDAR_CHANNELS if self.sensors[i]["kind"] == "lidar" else L.GS_CAMERA_CHANNELS
 
     def _scene_structs(self, scenes):
         arr = (L.Scene * len(self.scenes))()

@@ -82,7 +82,7 @@ ALT_TOL = 1e-4      # relative distance to a threshold below which a decision is
 
 def oracle_vector(ref, kind):
     """Oracle outputs as [C, R] in the device channel order."""
-    if kind == "pinhole":
+    if kind != "lidar":
         v = np.concatenate([ref["rgb"].reshape(3, -1), ref["depth"].reshape(1, -1), ref["normal"].reshape(3, -1),
                             ref["alpha"].reshape(1, -1)])
     else:
@@ -93,7 +93,7 @@ def oracle_vector(ref, kind):
 def _tolerance(v, kind):
     """Per-entry tolerance of output vectors v [C, ...]: 1e-4 absolute, depth/range 1e-4 relative to max(1, |v|)."""
     t = np.full(v.shape, TOL)
-    d = 3 if kind == "pinhole" else 0
+    d = 3 if kind != "lidar" else 0
     t[d] = TOL_DEPTH * np.maximum(1.0, np.abs(v[d]))
     return t
 
@@ -121,8 +121,8 @@ def verify(got, ref, kind):
     unver = np.zeros(ok.shape, bool)
     unver[ref["unverified"]] = True
     bad = ~ok & ~unver
-    names = (["r", "g", "b", "depth", "nx", "ny", "nz", "alpha"] if kind == "pinhole" else ["range", "intensity", "alpha"])
-    d = 3 if kind == "pinhole" else 0
+    names = (["r", "g", "b", "depth", "nx", "ny", "nz", "alpha"] if kind != "lidar" else ["range", "intensity", "alpha"])
+    d = 3 if kind != "lidar" else 0
     rel = best.copy()
     rel[d] = best[d] / np.maximum(1.0, np.abs(nom[d]))
     m = ~unver

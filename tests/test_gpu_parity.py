@@ -189,7 +189,7 @@ def grad_check(scene, sensor, opts, tile, keys, channels_seed=0, segment_pairs=0
     grads = r.backward([st], sp, gp, outs, [torch.from_numpy(go).to(outs[0].device)])[0]
     torch.cuda.synchronize()
     o = oracle_opts(opts, tile)
-    if sensor["kind"] == "pinhole":
+    if sensor["kind"] != "lidar":
         gmap = {"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]}
     else:
         gmap = {"range": go[0], "intensity": go[1], "alpha": go[2]}

@@ -53,13 +53,14 @@ def test_planes_contain_the_ray_and_are_orthogonal():
     tabs = spec32.cylindrical_tables(C)
     i = np.arange(C["width"] * C["height"]) % C["width"]
     j = np.arange(C["width"] * C["height"]) // C["width"]
-    d = np.stack([tabs["sin_phi"][i], tabs["yn"][j], tabs["cos_phi"][i]], 1).astype(np.float64)
+    phi = (i + 0.5 - C["cx"]) / C["fx"]
+    yn = (j + 0.5 - C["cy"]) / C["fy"]
+    d = np.stack([np.sin(phi), yn, np.cos(phi)], 1)
     hu, hv = rays["hu"].numpy(), rays["hv"].numpy()
     for a, b in ((hu, d), (hv, d), (hu, hv)):
-        assert np.abs((a * b).sum(1)).max() < 1e-6
-    # the angle of column i is (i + 1/2 - c_x) / f_x
+        assert np.abs((a * b).sum(1)).max() < 1e-13
     np.testing.assert_allclose(np.arctan2(tabs["sin_phi"], tabs["cos_phi"]),
-                               (np.arange(C["width"]) + 0.5 - C["cx"]) / C["fx"], atol=1e-6)
+                               (np.arange(C["width"]) + 0.5 - C["cx"]) / C["fx"], atol=1e-13)
 
 
 def test_centre_column_equals_the_pinhole_column():
@@ -73,7 +74,6 @@ def test_centre_column_equals_the_pinhole_column():
     q = quat_wxyz(Rotation.random(n, random_state=3))
     sc = surfels(mean, q, np.exp(rng.normal(-2.0, 0.3, (n, 2))), rng.uniform(0.2, 0.8, n),
                  rgb=rng.uniform(0, 1, (n, 3)))
-    # f = 32 keeps every y_n = (j + 1/2 - 15) / 32 exact in FP32, as the pinhole's FP64 value
     C = cyl(width=24, height=30, fx=32.0, fy=32.0, cx=i0 + 0.5, cy=15.0)
     P = dict(kind="pinhole", width=24, height=30, fx=32.0, fy=32.0, cx=i0 + 0.5, cy=15.0, z_near=0.2, pose=IDPOSE)
     opts = raster.make_opts(raster.STRICT, lowpass=False, tile_w=8, tile_h=8)
@@ -90,7 +90,7 @@ def test_centre_column_equals_the_pinhole_column():
 def test_facing_surfel_on_a_pixel_ray(i, j, r):
     C = cyl()
     tabs = spec32.cylindrical_tables(C)
-    d = np.array([tabs["sin_phi"][i], tabs["yn"][j], tabs["cos_phi"][i]], np.float64)
+    d = np.array([tabs["sin_phi"][i], tabs["yn"][j], tabs["cos_phi"][i]])
     nrm = d / np.linalg.norm(d)
     tu = np.cross([0, 1.0, 0], nrm)
     tu /= np.linalg.norm(tu)
