@@ -305,6 +305,7 @@ class SurfelScene:
     sh: np.ndarray | None = None
     sh_degree: int = -1
     intensity: np.ndarray | None = None
+    drop: np.ndarray | None = None      # LiDAR ray-drop probability per surfel
     group_offsets: np.ndarray = field(default_factory=lambda: np.zeros(2, np.int32))
     group_poses: np.ndarray = field(default_factory=lambda: np.zeros((1, 3, 4), F32))
 
@@ -335,6 +336,8 @@ def random_cloud(seed=1, n=4096, lo=(-2, -2, 3), hi=(2, 2, 8), log_scale=(-3.0, 
                      group_poses=_identity_poses(1))
     if with_intensity:
         sc.intensity = rng.uniform(0, 1, size=n).astype(F32)
+        # ray drop: most surfels return, a few (dark, specular, far) mostly do not
+        sc.drop = (rng.uniform(0, 1, size=n) ** 3).astype(F32)
     return sc
 
 
@@ -359,6 +362,8 @@ def corridor_surfels(seed=2, n=1_000_000, sh_degree=3, z_lo=0.0, z_hi=120.0,
         sc.rgb = rng.uniform(0, 1, size=(3, n)).astype(F32)
     if with_intensity:
         sc.intensity = rng.uniform(0, 1, size=n).astype(F32)
+        # ray drop: most surfels return, a few (dark, specular, far) mostly do not
+        sc.drop = (rng.uniform(0, 1, size=n) ** 3).astype(F32)
     return sc
 
 
@@ -386,7 +391,7 @@ FEAT_DIM = 32
 HIDDEN = 32
 K_OFFSETS = 10
 ATTRS_CAMERA = 10   # opacity, r, g, b, s_u, s_v, qw, qx, qy, qz
-ATTRS_LIDAR = 8     # opacity, intensity, s_u, s_v, qw, qx, qy, qz
+ATTRS_LIDAR = 9     # opacity, intensity, s_u, s_v, qw, qx, qy, qz, ray-drop
 
 
 def mlp_params(rng, n_out, n_in=FEAT_DIM + 3, hidden=HIDDEN) -> dict:

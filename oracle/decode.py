@@ -8,7 +8,7 @@ direction from the sensor centre to the anchor, in the anchor group's frame
 (3)], hidden 32 with ReLU, output K offsets x J attributes:
 
   camera  J = 10: opacity, r, g, b, s_u, s_v, q_w, q_x, q_y, q_z
-  LiDAR   J = 8 : opacity, intensity, s_u, s_v, q_w, q_x, q_y, q_z
+  LiDAR   J = 9 : opacity, intensity, s_u, s_v, q_w, q_x, q_y, q_z, ray-drop
 
 Heads: opacity, colour, intensity = sigmoid(y); scale = l_a * sigmoid(y);
 rotation = the raw 4-vector (the renderer normalises quaternions); centre
@@ -49,7 +49,7 @@ def decode(anchors: dict, mlps: list, group_poses_s: np.ndarray, kind: str, para
     feat = p.get("feat", _t(anchors["feat"]))
     go = np.asarray(anchors["group_offsets"], np.int64)
     K = offsets.shape[1]
-    J = 10 if kind == "pinhole" else 8
+    J = 10 if kind == "pinhole" else 9
     ys = []
     for g in range(len(go) - 1):
         sl = slice(int(go[g]), int(go[g + 1]))
@@ -82,6 +82,8 @@ def decode(anchors: dict, mlps: list, group_poses_s: np.ndarray, kind: str, para
         so = 2
     out["scale"] = torch.stack([per_surfel(scaling[None, :] * sig(y[:, so + c])) for c in range(2)])
     out["quat"] = torch.stack([per_surfel(y[:, so + 2 + c]) for c in range(4)])
+    if kind != "pinhole":
+        out["drop"] = per_surfel(sig(y[:, 8]))  # ray-drop probability
     mean = xyz[:, None, :] + scaling[None, None, :] * offsets  # [3, K, A]
     out["mean"] = mean.permute(0, 2, 1).reshape(3, A * K)
     return out

@@ -194,6 +194,8 @@ def splat_quantities(scene, sensor, bins, params):
             out["colour"] = params["rgb"].T
     else:
         out["intensity"] = params["intensity"]
+        if params.get("drop") is not None:
+            out["drop"] = params["drop"]
     return out
 
 
@@ -340,7 +342,11 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     definition gives when any non-empty subset of those decisions goes the
     other way ('alts': rays, values [n_alt, C] in the channel order of the
     device layout); rays with more flags are listed in 'unverified'.
-    Returns dict of numpy FP64 outputs shaped [C, H, W] (or [C, R] for rays).
+    Returns dict of numpy FP64 outputs shaped [C, H, W] (or [C, R] for rays):
+    camera rgb, depth, normal, alpha, median (depth); LiDAR range, intensity,
+    alpha, drop (ray-drop probability), drop_mask, median (range); and
+    T_final.  The alternatives' value vectors hold every channel in the
+    device order (camera 9, LiDAR 6).
     """
     opts = make_opts(**(opts or {})) if not isinstance(opts, dict) or "tile_w" not in opts else opts
     W, H = int(sensor["width"]), int(sensor["height"])
@@ -359,6 +365,8 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
                       scale=_leaf(scene["scale"], want_grad), opacity=_leaf(scene["opacity"], want_grad))
         if lidar:
             params["intensity"] = _leaf(scene["intensity"], want_grad)
+            if scene.get("drop") is not None:
+                params["drop"] = _leaf(scene["drop"], want_grad)
         elif scene.get("sh") is not None:
             params["sh"] = _leaf(scene["sh"], want_grad)
         else:
@@ -397,8 +405,10 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     listed = grid(torch.ones(rp.size, dtype=torch.bool))
     # per-pair features in the device channel order
     if lidar:
-        feats = [sol["depth"], sq["intensity"][sp_t], torch.ones(rp.size, dtype=DT)]
-        bg = torch.zeros(3, dtype=DT)
+        # ray-drop probability: a ray that meets nothing returns nothing (background 1)
+        drop = sq["drop"][sp_t] if sq.get("drop") is not None else torch.zeros(rp.size, dtype=DT)
+        feats = [sol["depth"], sq["intensity"][sp_t], torch.ones(rp.size, dtype=DT), drop]
+        bg = torch.as_tensor([0.0, 0.0, 0.0, 1.0], dtype=DT)
     else:
         col = sq["colour"][sp_t]
         nrm = sq["normal"][sp_t]
@@ -408,16 +418,19 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     feat = torch.stack([grid(f) for f in feats], 2)  # [R, K, C]
 
     active, T_ex, test, skip, stopped = _decide(alpha.detach(), present, opts)
-    out, w, T_final = _accumulate(active, alpha, feat, bg)
+    dch = 0 if lidar else 3
+    full_out, T_final = _compose(active, alpha, feat, bg, dch, lidar)
 
     outs = {}
     if lidar:
-        outs["range"], outs["intensity"], outs["alpha"] = out[:, 0], out[:, 1], out[:, 2]
+        outs["range"], outs["intensity"], outs["alpha"] = full_out[:, 0], full_out[:, 1], full_out[:, 2]
+        outs["drop"], outs["drop_mask"], outs["median"] = full_out[:, 3], full_out[:, 4], full_out[:, 5]
     else:
-        outs["rgb"] = out[:, 0:3].T
-        outs["depth"] = out[:, 3]
-        outs["normal"] = out[:, 4:7].T
-        outs["alpha"] = out[:, 7]
+        outs["rgb"] = full_out[:, 0:3].T
+        outs["depth"] = full_out[:, 3]
+        outs["normal"] = full_out[:, 4:7].T
+        outs["alpha"] = full_out[:, 7]
+        outs["median"] = full_out[:, 8]
     outs["T_final"] = T_final
 
     result = {}
@@ -428,9 +441,10 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
     result["n_contrib"] = active.sum(1).numpy().reshape(shape)
     first_stop = torch.where(stopped.any(1), stopped.to(torch.int64).argmax(1), torch.full((R,), K))
     considered = listed & (torch.arange(K)[None, :] <= first_stop[:, None])
+    derived = _derived_distances(active, alpha.detach(), full_out.detach(), lidar)
     if margins:
         result["margin"] = _margins(sol, rp, pos, R, K, alpha.detach(), test, skip, considered, opts,
-                                    sensor, tol).reshape(shape)
+                                    sensor, derived, tol).reshape(shape)
     if alternatives is not None:
         with torch.no_grad():
             alt = dict(alpha=grid(torch.clamp(o.detach() * torch.exp(-0.5 * sol["alt"]["rho_hat"]),
@@ -438,7 +452,7 @@ def render(scene, sensor, opts=None, *, mode="culled", rays=None, grad_out=None,
                        present=grid(sol["alt"]["support"]), depth=grid(sol["alt"]["depth"]),
                        ch=0 if lidar else 3)
         result.update(_alternatives(sol, rp, pos, R, K, alpha.detach(), present, listed, feat.detach(), bg, test,
-                                    skip, considered, opts, tol, max_flags, sensor, alt))
+                                    skip, considered, opts, tol, max_flags, sensor, alt, derived))
     if want_grad:
         total = 0.0
         for k_, g in grad_out.items():
@@ -497,6 +511,44 @@ def _accumulate(active, alpha, feat, bg):
     T_final = T[:, -1] * om[:, -1]
     out = (w[:, :, None] * feat).sum(1) + T_final[:, None] * bg[None, :]
     return out, w, T_final
+
+
+def _median_and_mask(active, alpha, feat, out, dch, lidar, med_flip=None, mask_flip=None):
+    """The derived channels.  Median depth (2DGS): the depth feature of the
+    first composited pair after which the transmittance is below 1/2, 0 where
+    it never falls that low.  LiDAR ray drop: the composited drop probability
+    P (background 1) and the drop mask P > 1/2.  med_flip [R, K] toggles the
+    test T_after < 1/2 at chosen pairs, mask_flip [R] the mask (near-threshold
+    decisions taken the other way).  Returns the extra channels [R, E]."""
+    with torch.no_grad():
+        a_fin = torch.where(active, alpha, torch.zeros_like(alpha))
+        T_after = torch.cumprod(1.0 - a_fin, 1)
+        b = active & (T_after < 0.5)
+        if med_flip is not None:
+            b = b ^ med_flip
+        has = b.any(1)
+        first = torch.where(has, b.to(torch.int64).argmax(1), torch.zeros_like(has, dtype=torch.int64))
+    R = alpha.shape[0]
+    med = torch.where(has, feat[torch.arange(R), first, dch], torch.zeros(R, dtype=DT))
+    if not lidar:
+        return med[:, None]
+    P = out[:, 3]
+    with torch.no_grad():
+        mask = P > 0.5
+        if mask_flip is not None:
+            mask = mask ^ mask_flip
+    return torch.stack([P, mask.to(DT), med], 1)
+
+
+def _compose(active, alpha, feat, bg, dch, lidar, med_flip=None, mask_flip=None):
+    """Every output channel in the device order ([R, C]: the camera's 8
+    sums and its median depth; the LiDAR's range, intensity and alpha sums,
+    drop probability, drop mask and median range) and T_final."""
+    out, w, T_final = _accumulate(active, alpha, feat, bg)
+    ext = _median_and_mask(active, alpha, feat, out, dch, lidar, med_flip, mask_flip)
+    if lidar:
+        return torch.cat([out[:, 0:3], ext], 1), T_final
+    return torch.cat([out, ext], 1), T_final
 
 
 def _fp32_uv_error(M, mu, u, v, rays_t, rp_t, sensor, opts):
@@ -697,28 +749,52 @@ def _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor, tol
     return d_sup, d_amin, d_stop, d_lp
 
 
-def _margins(sol, rp, pos, R, K, alpha, test, skip, considered, opts, sensor, tol=0.0):
+def _derived_distances(active, alpha, out_full, lidar):
+    """Relative distances of the derived channels' decisions to their
+    thresholds: per pair [R, K] the median crossing test T_after < 1/2 (active
+    pairs), per ray [R] the LiDAR drop mask P > 1/2 (inf for cameras)."""
+    with torch.no_grad():
+        a_fin = torch.where(active, alpha, torch.zeros_like(alpha))
+        T_after = torch.cumprod(1.0 - a_fin, 1)
+        d_med = torch.where(active, (T_after - 0.5).abs() / 0.5, torch.full_like(alpha, math.inf))
+        if lidar:
+            d_mask = (out_full[:, 3] - 0.5).abs() / 0.5
+        else:
+            d_mask = torch.full((alpha.shape[0],), math.inf, dtype=DT)
+    return d_med, d_mask
+
+
+def _margins(sol, rp, pos, R, K, alpha, test, skip, considered, opts, sensor, derived, tol=0.0):
     """Per ray: the smallest relative distance of any decision of a considered
     pair (up to and including the stopping one) to its threshold (with
-    tol > 0, in the scaled measure of _relative_distances)."""
+    tol > 0, in the scaled measure of _relative_distances), the derived
+    channels' decisions (median crossing, drop mask) included."""
     d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor, tol)
+    d_med, d_mask = derived
     m = torch.minimum(torch.minimum(d_sup, d_amin), torch.minimum(d_stop, d_lp))
+    m = torch.minimum(m, d_med)
     m = torch.where(considered, m, torch.full_like(m, math.inf))
-    return m.min(1).values.numpy() if K > 0 else np.full(R, np.inf)
+    mr = m.min(1).values if K > 0 else torch.full((R,), math.inf, dtype=DT)
+    return torch.minimum(mr, d_mask).numpy()
 
 
 def _alternatives(sol, rp, pos, R, K, alpha, present, listed, feat, bg, test, skip, considered, opts, tol,
-                  max_flags, sensor, alt):
+                  max_flags, sensor, alt, derived):
     """Outputs of every ray under each non-empty subset of its near-threshold
     decisions taken the other way (see render's `alternatives`).  Flag kinds:
     0 support (cutoff or z_near), 1 alpha_min, 2 stop, 3 the choice between
     rho and the low-pass term (the other choice gives the pair the alpha,
     depth and support in `alt`: [R, K] grids 'alpha', 'present', 'depth', and
-    the depth channel index 'ch')."""
+    the depth channel index 'ch'), 4 the median crossing test T < 1/2 at a
+    pair, 5 the LiDAR drop mask P > 1/2 (listed at pair 0)."""
     d_sup, d_amin, d_stop, d_lp = _relative_distances(sol, rp, pos, R, K, alpha, test, skip, opts, sensor, tol)
+    d_med, d_mask = derived
+    lidar = is_lidar(sensor)
     with torch.no_grad():
+        mask_col = torch.zeros((R, K), dtype=torch.bool)
+        mask_col[:, 0] = d_mask <= tol
         fm = [considered & (d_sup <= tol), considered & (d_amin <= tol), considered & (d_stop <= tol),
-              considered & (d_lp <= tol)]
+              considered & (d_lp <= tol), considered & (d_med <= tol), mask_col]
         n_flags = sum(f.to(torch.int64) for f in fm).sum(1)
     nf = n_flags.numpy()
     rays = np.nonzero((nf >= 1) & (nf <= max_flags))[0]
@@ -726,21 +802,27 @@ def _alternatives(sol, rp, pos, R, K, alpha, present, listed, feat, bg, test, sk
     values, kinds = [], []
     for r in rays:
         r_t = torch.as_tensor([int(r)])
-        flags = [(kd, int(k)) for kd in range(4) for k in torch.nonzero(fm[kd][r]).reshape(-1).tolist()]
+        flags = [(kd, int(k)) for kd in range(6) for k in torch.nonzero(fm[kd][r]).reshape(-1).tolist()]
         alts = []
         for subset in range(1, 1 << len(flags)):
             a_r, p_r, f_r = alpha[r_t].clone(), present[r_t].clone(), feat[r_t].clone()
             fl = [torch.zeros((1, K), dtype=torch.bool) for _ in range(3)]
+            med_flip = torch.zeros((1, K), dtype=torch.bool)
+            mask_flip = torch.zeros((1,), dtype=torch.bool)
             for b, (kd, k) in enumerate(flags):
                 if (subset >> b) & 1:
                     if kd == 3:
                         a_r[0, k] = alt["alpha"][r, k]
                         p_r[0, k] = alt["present"][r, k]
                         f_r[0, k, alt["ch"]] = alt["depth"][r, k]
+                    elif kd == 4:
+                        med_flip[0, k] = True
+                    elif kd == 5:
+                        mask_flip[0] = True
                     else:
                         fl[kd][0, k] = True
             act = _decide(a_r, p_r, opts, flips=fl)[0]
-            alts.append(_accumulate(act, a_r, f_r, bg)[0][0].numpy())
+            alts.append(_compose(act, a_r, f_r, bg, alt["ch"], lidar, med_flip, mask_flip)[0][0].numpy())
         values.append(np.stack(alts))
         kinds.append([kd for kd, _ in flags])
     return dict(alts=dict(rays=rays, values=values, kinds=kinds), unverified=unverified, n_flags=nf)

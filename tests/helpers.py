@@ -10,7 +10,7 @@ def quat_wxyz(rot: Rotation) -> np.ndarray:
     return np.stack([w, x, y, z]).astype(F32).reshape(4, -1)
 
 
-def surfels(mean, quat, scale, opacity, rgb=None, intensity=None, sh=None, sh_degree=-1):
+def surfels(mean, quat, scale, opacity, rgb=None, intensity=None, sh=None, sh_degree=-1, drop=None):
     mean = np.asarray(mean, F32).reshape(-1, 3).T.copy()
     n = mean.shape[1]
     sc = dict(mean=mean, quat=np.asarray(quat, F32).reshape(4, n).copy(),
@@ -21,6 +21,8 @@ def surfels(mean, quat, scale, opacity, rgb=None, intensity=None, sh=None, sh_de
         sc["rgb"] = np.asarray(rgb, F32).reshape(-1, 3).T.copy()
     if intensity is not None:
         sc["intensity"] = np.asarray(intensity, F32).reshape(n).copy()
+    if drop is not None:
+        sc["drop"] = np.asarray(drop, F32).reshape(n).copy()
     if sh is not None:
         sc["sh"] = np.asarray(sh, F32).copy()
         sc["sh_degree"] = sh_degree
@@ -44,6 +46,8 @@ def from_gen(sc):
         d["rgb"] = sc.rgb
     if sc.intensity is not None:
         d["intensity"] = sc.intensity
+    if getattr(sc, "drop", None) is not None:
+        d["drop"] = sc.drop
     return d
 
 
@@ -53,7 +57,7 @@ def subset(scene, idx):
     for k in ("mean", "quat", "scale", "rgb", "sh"):
         if k in scene and scene[k] is not None:
             out[k] = np.ascontiguousarray(scene[k][:, idx])
-    for k in ("opacity", "intensity"):
+    for k in ("opacity", "intensity", "drop"):
         if k in scene and scene[k] is not None:
             out[k] = np.ascontiguousarray(scene[k][idx])
     out["group_offsets"] = np.array([0, idx.size], np.int32)

@@ -165,7 +165,7 @@ IDPOSE = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)[None].astype(F32)
 def test_decode_zero_second_layer_gives_bias_heads(kind):
     an = _anchors()
     K = 3
-    J = 10 if kind == "pinhole" else 8
+    J = 10 if kind == "pinhole" else 9
     rng = np.random.default_rng(2)
     b2 = rng.standard_normal(K * J)
     mlp = dict(w1=rng.standard_normal((32, 35)), b1=rng.standard_normal(32), w2=np.zeros((K * J, 32)), b2=b2)
@@ -185,6 +185,8 @@ def test_decode_zero_second_layer_gives_bias_heads(kind):
                 so = 2
             np.testing.assert_allclose(out["scale"][:, n].numpy(), an["scaling"][a] * sig(y[k, so:so + 2]), atol=1e-14)
             np.testing.assert_allclose(out["quat"][:, n].numpy(), y[k, so + 2:so + 6], atol=1e-14)
+            if kind != "pinhole":  # the ray-drop head
+                assert out["drop"][n].item() == pytest.approx(sig(y[k, 8]), abs=1e-14)
             np.testing.assert_allclose(out["mean"][:, n].numpy(),
                                        an["xyz"][:, a] + an["scaling"][a] * an["offsets"][:, k, a], atol=1e-14)
 
@@ -255,7 +257,7 @@ def test_decode_view_direction_with_turned_sensor_and_group():
 def test_decode_groups_use_their_own_mlp_and_pose():
     an = _anchors(A=6, K=2, seed=4)
     an["group_offsets"] = np.array([0, 4, 6])
-    K, J = 2, 8
+    K, J = 2, 9
     m0 = dict(w1=np.zeros((32, 35)), b1=np.zeros(32), w2=np.zeros((K * J, 32)), b2=np.full(K * J, 0.3))
     m1 = dict(w1=np.zeros((32, 35)), b1=np.zeros(32), w2=np.zeros((K * J, 32)), b2=np.full(K * J, -0.7))
     poses = np.concatenate([IDPOSE, IDPOSE])

@@ -118,7 +118,7 @@ def test_lowpass_choice_near_a_tie_is_flagged_with_the_hit_depth_alternative():
     assert r in rays
     assert res["alts"]["kinds"][rays.index(r)] == [3]
     alt = res["alts"]["values"][rays.index(r)]
-    assert alt.shape == (1, 8)
+    assert alt.shape == (1, 9)  # the 8 sums and the median depth
     assert alt[0][7] == pytest.approx(o * math.exp(-0.5 * rho), rel=1e-12)
     assert alt[0][3] / alt[0][7] == pytest.approx(x[2], rel=1e-9)
 

@@ -57,7 +57,7 @@ def test_alpha_min_flag_and_skip_alternative():
     assert res["n_flags"][r] == 1
     assert res["margin"][10, 20] == pytest.approx(rel, rel=1e-9)
     alt = _alts(res, r)
-    assert alt is not None and alt.shape == (1, 8)
+    assert alt is not None and alt.shape == (1, 9)
     np.testing.assert_allclose(alt[0], 0.0, atol=1e-15)  # the surfel skipped: nothing composited
 
 
@@ -89,8 +89,10 @@ def test_stop_flag_and_stopped_alternative():
     np.testing.assert_allclose(got, nominal, atol=1e-12)
     assert res["n_flags"][r] == 1
     alt = _alts(res, r)
-    assert alt is not None and alt.shape == (1, 8)
-    np.testing.assert_allclose(alt[0], stopped, atol=1e-12)
+    assert alt is not None and alt.shape == (1, 9)
+    np.testing.assert_allclose(alt[0][:8], stopped, atol=1e-12)
+    # the median depth is the first surfel's (T = 0.1 after it) either way
+    assert res["median"][20, 30] == pytest.approx(zs[0], rel=1e-6) and alt[0][8] == res["median"][20, 30]
 
 
 def test_support_cutoff_flag_and_included_alternative():
@@ -146,7 +148,8 @@ def test_alternatives_of_a_random_scene_agree_with_margins():
     # stop decision always changes the ray (a support flip may not: in
     # production alpha at the cutoff is below alpha_min; nor may the low-pass
     # choice of a pair outside the support either way)
-    nom = np.concatenate([res["rgb"], res["depth"][None], res["normal"], res["alpha"][None]]).reshape(8, -1)
+    nom = np.concatenate([res["rgb"], res["depth"][None], res["normal"], res["alpha"][None],
+                          res["median"][None]]).reshape(9, -1)
     n_checked = 0
     for r, vals, kinds in zip(res["alts"]["rays"], res["alts"]["values"], res["alts"]["kinds"]):
         assert vals.shape[0] == 2 ** nf.reshape(-1)[r] - 1
