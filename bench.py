@@ -530,8 +530,8 @@ def main():
                     help="extra workloads (comma list of per_sensor, plain, frame1080, train720p, lidar, affinity)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures a single MI355X: multi-GPU runs are not part of this build "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one MI355X only: the renderer runs one process per GPU and "
+              "has no multi-GPU path; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -566,7 +566,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         gps = [probe.gp_c if s["kind"] == "pinhole" else probe.gp_l for s in sensors]
-        res = at.autotune(probe.shapes, probe.ds, sensors, probe.sp, gps, batched=True, segments=[512, 1024, 2048],
+        res = at.autotune(probe.shapes, probe.ds, sensors, probe.sp, gps, batched=True, segments=[1024, 2048, 4096],
                           pair_capacity=probe.shapes[0].n_splats * 6, steps=3, warmup=1)
         tiles, seg = res.tiles, res.segment_pairs
         extra["autotune"] = {"tiles": [list(t) for t in tiles], "segment_pairs": seg,

@@ -134,6 +134,9 @@ typedef struct gs_scene {
   const float* rgb;        /* [3][N] when sh_degree < 0                            */
   const float* sh;         /* [(deg+1)^2*3][N], row k*3+channel, when sh_degree>=0 */
   const float* intensity;  /* [N] when has_intensity                              */
+  const float* drop;       /* [N] LiDAR ray-drop probability in [0,1] (Sec. III-A's
+                              attribute rho, read as the probability that a beam
+                              meeting the surfel returns nothing); NULL = 0     */
 } gs_scene;
 
 /* Gradient buffers (device pointers), same layouts as gs_scene.  The adjoint
@@ -146,6 +149,7 @@ typedef struct gs_scene_grads {
   float* rgb;
   float* sh;
   float* intensity;
+  float* drop;
 } gs_scene_grads;
 
 typedef struct gs_plan_desc {
@@ -174,12 +178,19 @@ typedef struct gs_plan_desc {
 
 typedef struct gs_plan gs_plan; /* opaque, owned by the library */
 
-/* Output channel counts: camera (pinhole or cylindrical) [8][H][W] = rgb(3),
- * depth, normal(3), alpha;
- * LiDAR [3][H][W] = range, intensity, alpha.  Depth/range and normal are
- * unnormalised sums (divide by alpha for the expected value). */
-#define GS_CAMERA_CHANNELS 8
-#define GS_LIDAR_CHANNELS 3
+/* Output channel counts: camera (pinhole or cylindrical) [9][H][W] = rgb(3),
+ * depth, normal(3), alpha, median depth;
+ * LiDAR [6][H][W] = range, intensity, alpha, ray-drop probability, drop
+ * mask, median range.  Depth/range and normal are unnormalised sums (divide
+ * by alpha for the expected value).  The median depth (range) is the depth
+ * of the first composited surfel after which the transmittance is below 1/2
+ * (the 2DGS median), 0 where it never falls that low.  The drop probability
+ * is P = sum_i w_i rho_i + T_final (a beam that meets nothing returns
+ * nothing) and the mask is 1 where P > 1/2, else 0.  The adjoint takes
+ * gradients of every channel but the mask; the median's goes to the depth
+ * of its surfel. */
+#define GS_CAMERA_CHANNELS 9
+#define GS_LIDAR_CHANNELS 6
 
 /* Status of the last run on a workspace (filled by gs_query_status). */
 typedef struct gs_run_status {
@@ -333,8 +344,8 @@ gs_status gs_plan_inspect(const gs_plan* plan, int32_t sensor, gs_workspace_view
  * x = [f_a (F, bf16); unit(x_a - sensor centre) in the group frame (3)],
  * h = ReLU(W1 x + b1) (H wide), y = W2 h + b2 with K offsets x J attributes:
  *   camera J = 10: opacity, r, g, b, s_u, s_v, q (4)
- *   LiDAR  J = 8 : opacity, intensity, s_u, s_v, q (4)
- * Heads: opacity/colour/intensity = sigmoid, scale = l_a * sigmoid,
+ *   LiDAR  J = 9 : opacity, intensity, s_u, s_v, q (4), ray drop
+ * Heads: opacity/colour/intensity/ray drop = sigmoid, scale = l_a * sigmoid,
  * rotation = raw 4-vector, centre = x_a + l_a * O_k.  Surfel n = a*K + k.
  * The contractions run on MFMA with bf16 weights and features and FP32
  * accumulation; activations keep ~16 mantissa bits (hi+lo bf16 split).
@@ -342,7 +353,7 @@ gs_status gs_plan_inspect(const gs_plan* plan, int32_t sensor, gs_workspace_view
 typedef struct gs_anchor_set {
   int32_t n_anchors;            /* A                                       */
   int32_t k;                    /* offsets per anchor (K <= 16)            */
-  int32_t lidar;                /* 0: camera heads (J=10), 1: LiDAR (J=8)  */
+  int32_t lidar;                /* 0: camera heads (J=10), 1: LiDAR (J=9)  */
   int32_t n_groups;             /* groups, each with its own MLP           */
   const int32_t* group_offsets; /* host [n_groups+1] over anchors          */
   const float* xyz;             /* device [3][A]                           */
@@ -361,8 +372,8 @@ typedef struct gs_anchor_set {
  * decode the MFMA path is compared against. */
 #define GS_DECODE_VALU_FP32 1
 
-/* Decoded surfel buffers (device, [C][A*K]).  rgb for camera, intensity for
- * LiDAR. */
+/* Decoded surfel buffers (device, [C][A*K]).  rgb for camera, intensity and
+ * drop (ray-drop probability) for LiDAR. */
 typedef struct gs_decoded {
   float* mean;
   float* quat;
@@ -370,6 +381,7 @@ typedef struct gs_decoded {
   float* opacity;
   float* rgb;
   float* intensity;
+  float* drop;
 } gs_decoded;
 
 /* Decodes every anchor for one sensor pose.  sensor_pose: device [12]

@@ -16,8 +16,8 @@ GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_UNSUPPORTED = ran
 GS_SENSOR_PINHOLE, GS_SENSOR_LIDAR, GS_SENSOR_CYLINDRICAL = 0, 1, 2
 GS_MAX_GROUPS = 64
 GS_MAX_SENSORS = 16
-GS_CAMERA_CHANNELS = 8
-GS_LIDAR_CHANNELS = 3
+GS_CAMERA_CHANNELS = 9
+GS_LIDAR_CHANNELS = 6
 
 
 class SensorDesc(ctypes.Structure):
@@ -38,12 +38,12 @@ class SceneDesc(ctypes.Structure):
 
 class Scene(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("opacity", c_void_p),
-                ("rgb", c_void_p), ("sh", c_void_p), ("intensity", c_void_p)]
+                ("rgb", c_void_p), ("sh", c_void_p), ("intensity", c_void_p), ("drop", c_void_p)]
 
 
 class SceneGrads(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("opacity", c_void_p),
-                ("rgb", c_void_p), ("sh", c_void_p), ("intensity", c_void_p)]
+                ("rgb", c_void_p), ("sh", c_void_p), ("intensity", c_void_p), ("drop", c_void_p)]
 
 
 class PlanDesc(ctypes.Structure):
@@ -84,7 +84,7 @@ GS_DECODE_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 class Decoded(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("quat", c_void_p), ("scale", c_void_p), ("opacity", c_void_p),
-                ("rgb", c_void_p), ("intensity", c_void_p)]
+                ("rgb", c_void_p), ("intensity", c_void_p), ("drop", c_void_p)]
 
 
 class AnchorGrads(ctypes.Structure):

@@ -26,7 +26,7 @@ from .render import Renderer
 
 TILES_ANY = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (8, 32), (32, 16), (16, 32), (64, 8)]
 TILES_256 = [(16, 16), (32, 8), (8, 32)]
-SEGMENTS = [256, 512, 1024, 2048]
+SEGMENTS = [256, 512, 1024, 2048, 4096]
 
 
 def default_cache_path() -> str:

@@ -141,7 +141,7 @@ struct SensorPlan {
   int scene = 0;
   int n_tiles = 0;
   size_t base = 0;  // workspace byte offset of this sensor's region
-  size_t o_pose = 0, o_Tfinal = 0, o_nlast = 0, o_status = 0;
+  size_t o_pose = 0, o_Tfinal = 0, o_nlast = 0, o_mpair = 0, o_status = 0;
   RecordArrays R;          // per-sensor layout only
   uint32_t rec_base = 0;   // batched layout: first record id
   float* d_tabs = nullptr; // LiDAR / cylindrical tables (device, owned by the plan)
@@ -246,6 +246,7 @@ SensorWS sensor_ws(const gs_plan* p, const SensorPlan& s, void* ws) {
   w.pose = at<float>(ws, s.base + s.o_pose);
   w.T_final = at<float>(ws, s.base + s.o_Tfinal);
   w.n_last = at<uint32_t>(ws, s.base + s.o_nlast);
+  w.mpair = at<uint32_t>(ws, s.base + s.o_mpair);
   return w;
 }
 
@@ -261,6 +262,7 @@ PrepArgs prep_args(const gs_plan* p, const SensorPlan& s, const gs_scene& sc, co
   a.rgb = sc.rgb;
   a.sh = sc.sh;
   a.intensity = sc.intensity;
+  a.drop = sc.drop;
   a.sh_degree = sp.desc.sh_degree;
   a.groups = groups_of(sp);
   a.S = s.K;
@@ -285,6 +287,7 @@ TileArgs tile_args(const gs_plan* p, const SensorPlan& s, void* ws) {
   t.pval = full.pval[R.pair_buf];
   t.T_final = at<float>(ws, s.base + s.o_Tfinal);
   t.n_last = at<uint32_t>(ws, s.base + s.o_nlast);
+  t.mpair = at<uint32_t>(ws, s.base + s.o_mpair);
   t.status = full.status;
   t.gacc = full.gacc;
   t.gacc_stride = R.n_rec;
@@ -454,6 +457,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       ev = stage_begin(p, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, outputs, nullptr, nullptr);
       launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, p->count_pairs, st);
+      launch_median(q, s.R.rays, s.R.kinds, s.R.grid_fwd, st);
       stage_end(p, st, GS_STAGE_BLEND, ev);
     }
     return;
@@ -483,6 +487,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   ev = stage_begin(p, st);
   QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, outputs, nullptr, nullptr);
   launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, p->count_pairs, st);
+  launch_median(q, p->G.rays, p->G.kinds, p->G.grid_fwd, st);
   stage_end(p, st, GS_STAGE_BLEND, ev);
 }
 
@@ -714,6 +719,7 @@ gs_status gs_plan_create(const gs_plan_desc* desc, gs_plan** out) {
     s.o_pose = R.take(12 * 4 * (size_t)sp.desc.n_groups);
     s.o_Tfinal = R.take(HW * 4);
     s.o_nlast = R.take(HW * 4);
+    s.o_mpair = R.take(HW * 4);
     if (p->batched) {
       K.tile_offset = total_tiles;
       s.rec_base = (uint32_t)total_rec;
@@ -949,6 +955,7 @@ gs_status gs_render_backward(gs_plan* p, const gs_scene* scenes, const float* se
     sb.g_rgb = g.rgb;
     sb.g_sh = g.sh;
     sb.g_intensity = g.intensity;
+    sb.g_drop = g.drop;
     hipEvent_t ev = stage_begin(p, st);
     launch_splat_backward(sb, st);
     stage_end(p, st, GS_STAGE_SPLAT_BWD, ev);

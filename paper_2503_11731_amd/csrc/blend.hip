@@ -372,7 +372,8 @@ __device__ __forceinline__ float max_offset(int lo, int hi, int o, int n, float 
 // One camera ray of a tile: lane geometry and the per-sensor pieces of the
 // compositing loop (staging, skip test, solve, features, output, adjoint).
 struct CamRay {
-  static constexpr int C = 8;  // rgb, depth, normal xyz, alpha
+  static constexpr int C = 8;   // accumulated: rgb, depth, normal xyz, alpha
+  static constexpr int CO = 9;  // output channels: the 8 sums and the median depth
   int px, py, ox, oy, bx, by, wx;
   float plx, ply;
   int tw, th;
@@ -495,7 +496,9 @@ struct CamRay {
     f[6] = R[4].w;
     f[7] = 1.0f;
   }
-  // output channels of a ray with final transmittance T and sums acc
+  // output channels of a ray with final transmittance T and sums acc (the
+  // median depth is written by the median pass; 0 until then, and for rays
+  // whose transmittance never falls below 1/2)
   static __device__ void out_values(const TileArgs& a, float T, const float* acc, float* v) {
 #pragma clang fp contract(off)
     v[0] = fmaf(T, a.O.bg0, acc[0]);
@@ -503,21 +506,25 @@ struct CamRay {
     v[2] = fmaf(T, a.O.bg2, acc[2]);
 #pragma unroll
     for (int c = 3; c < 8; ++c) v[c] = acc[c];
+    v[8] = 0.0f;
   }
+  static constexpr int kMedian = 8;  // output channel of the median depth
   __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
     const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
-    float v[C];
+    float v[CO];
     out_values(a, T, acc, v);
 #pragma unroll
-    for (int c = 0; c < C; ++c) a.out[c * HW + p] = v[c];
+    for (int c = 0; c < CO; ++c) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
+    a.mpair[p] = kNoPair;
   }
   // Per-record gradient fields of one pair given dL/dalpha (dal) and the
   // pair's weight wgt = alpha T: [0..5] dP, [6..7] d(projected centre),
   // [8] d mu_z, [9] d opacity, [10..12] d colour, [13..15] d normal.
+  // gzx: a further dL/d(depth) of this pair (the median depth's, at its pair)
   __device__ void grads(const TileArgs& a, const float4* R, const PairEval& e, float dal, float wgt, const float* g,
-                        float* gr) const {
+                        float gzx, float* gr) const {
 #pragma clang fp contract(off)
     const float4 q0 = R[0], q1 = R[1];
     const float o = __builtin_amdgcn_exp2f(R[2].y);
@@ -528,7 +535,7 @@ struct CamRay {
     gr[13] = g[4] * wgt;
     gr[14] = g[5] * wgt;
     gr[15] = g[6] * wgt;
-    const float gz = g[3] * wgt;
+    const float gz = fmaf(g[3], wgt, gzx);
     float g_rhohat = 0.0f;
     if (!e.clamped) {
       gr[9] = o > 0.0f ? dal * al * __builtin_amdgcn_rcpf(o) : 0.0f;
@@ -728,7 +735,9 @@ __device__ __forceinline__ bool eval_cyl(const float4* __restrict__ R, uint32_t 
 // One cylindrical-camera ray of a tile: the camera ray with the column-frame
 // mapping (see above); records, features and outputs are the camera's.
 struct CylRay {
-  static constexpr int C = 8;  // rgb, depth, normal xyz, alpha
+  static constexpr int C = 8;   // accumulated: rgb, depth, normal xyz, alpha
+  static constexpr int CO = 9;  // output channels: the 8 sums and the median depth
+  static constexpr int kMedian = 8;
   int px, py, ox, oy, bx, by, wx;
   int tc, tr;               // pixel column and row of the ray (inside the image for every lane)
   float plx, ply, Ay, ay0;  // Ay: p_y - c_y of this ray; ay0: of the tile's first row
@@ -883,18 +892,19 @@ struct CylRay {
   }
   __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
     const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
-    float v[C];
+    float v[CO];
     out_values(a, T, acc, v);
 #pragma unroll
-    for (int c = 0; c < C; ++c) a.out[c * HW + p] = v[c];
+    for (int c = 0; c < CO; ++c) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
+    a.mpair[p] = kNoPair;
   }
   // The camera's fields: [0..5] dP, [6..7] d(projected centre), [8] d r (the
   // record's centre distance), [9] d opacity, [10..12] d colour, [13..15]
   // d normal; the offsets enter through X, Y and the depth's sec factor.
   __device__ void grads(const TileArgs& a, const float4* R, const PairEval& e, float dal, float wgt, const float* g,
-                        float* gr) const {
+                        float gzx, float* gr) const {
 #pragma clang fp contract(off)
     const float4 q0 = R[0], q1 = R[1], q2 = R[2];
     const float o = __builtin_amdgcn_exp2f(q2.y);
@@ -905,7 +915,7 @@ struct CylRay {
     gr[13] = g[4] * wgt;
     gr[14] = g[5] * wgt;
     gr[15] = g[6] * wgt;
-    const float gz = g[3] * wgt;
+    const float gz = fmaf(g[3], wgt, gzx);
     float g_rhohat = 0.0f;
     if (!e.clamped) {
       gr[9] = o > 0.0f ? dal * al * __builtin_amdgcn_rcpf(o) : 0.0f;
@@ -944,12 +954,14 @@ struct CylRay {
 };
 
 // ----------------------------- LiDAR -------------------------------------
-// Staged record (5 x float4), the fields every pair reads first:
+// Staged record (6 x float4), the fields every pair reads first:
 //  [0] c0, c1, c2 (= d_tile - mu_hat), Q00   [1] Q01, Q02, Q10, Q11
 //  [2] Q12, Q20, Q21, Q22                    [3] |mu|, log2 o, 2^-23 kappa, flags
 //  [4] intensity, columns lo|hi<<16 (may wrap), beams lo|hi<<16, the tile's error bound Et
+//  [5] ray-drop probability, -, -, -
 __device__ __forceinline__ uint2 stage_lidar(const RawRec& x, const double* dtile, float4* dst) {
-  // global record: Q (9), |mu|, log2 o, intensity, flags, 2^-23 kappa, columns, beams
+  // global record: Q (9), |mu|, log2 o, intensity, flags, 2^-23 kappa, columns,
+  // beams; FP64 record: unit centre direction, ray-drop probability
   const float4 r0 = x.r[0], r1 = x.r[1], r2 = x.r[2], r3 = x.r[3];
   const float c0 = (float)(dtile[0] - x.d[0].x);
   const float c1 = (float)(dtile[1] - x.d[0].y);
@@ -959,6 +971,7 @@ __device__ __forceinline__ uint2 stage_lidar(const RawRec& x, const double* dtil
   dst[2] = make_float4(r1.y, r1.z, r1.w, r2.x);
   dst[3] = make_float4(r2.y, r2.z, r3.y, r3.x);
   dst[4] = make_float4(r2.w, r3.z, r3.w, 0.0f);
+  dst[5] = make_float4((float)x.d[1].y, 0.0f, 0.0f, 0.0f);
   return make_uint2(__float_as_uint(r3.z), __float_as_uint(r3.w));
 }
 
@@ -1018,7 +1031,10 @@ __device__ inline void lidar_dir(const SensorK& S, int c, int j, double* d) {
 }
 
 struct LidarRay {
-  static constexpr int C = 3;  // range, intensity, alpha
+  static constexpr int C = 4;   // accumulated: range, intensity, alpha, ray drop
+  static constexpr int CO = 6;  // output channels: range, intensity, alpha, drop probability,
+                                // drop mask, median range
+  static constexpr int kMedian = 5;
   int pc, pb, bx, by, ox, oy, wx;
   bool inside;
   EvalK K;
@@ -1183,30 +1199,40 @@ struct LidarRay {
     f[0] = e.z;
     f[1] = R[4].x;
     f[2] = 1.0f;
+    f[3] = R[5].x;  // the surfel's ray-drop probability
   }
-  static __device__ void out_values(const TileArgs&, float, const float* acc, float* v) {
+  // drop probability P = sum w rho + T (a ray that meets nothing returns
+  // nothing), the drop mask P > 1/2; the median range comes from the median pass
+  static __device__ void out_values(const TileArgs&, float T, const float* acc, float* v) {
+#pragma clang fp contract(off)
     v[0] = acc[0];
     v[1] = acc[1];
     v[2] = acc[2];
+    v[3] = acc[3] + T;
+    v[4] = v[3] > 0.5f ? 1.0f : 0.0f;
+    v[5] = 0.0f;
   }
   __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
     const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
-    a.out[p] = acc[0];
-    a.out[HW + p] = acc[1];
-    a.out[2 * HW + p] = acc[2];
+    float v[CO];
+    out_values(a, T, acc, v);
+#pragma unroll
+    for (int c = 0; c < CO; ++c) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
+    a.mpair[p] = kNoPair;
   }
   // [0..8] dQ (row-major), [9..11] d mu_hat, [12] d|mu|, [13] d opacity,
-  // [14] d intensity.
+  // [14] d intensity, [15] d ray drop.
   __device__ void grads(const TileArgs& a, const float4* R, const PairEval& e, float dal, float wgt, const float* g,
-                        float* gr) const {
+                        float gzx, float* gr) const {
 #pragma clang fp contract(off)
     const float4 q0 = R[0], q1 = R[1], q2 = R[2];
     const float o = __builtin_amdgcn_exp2f(R[3].y);
     const float al = e.alpha;
-    const float grange = g[0] * wgt;
+    const float grange = fmaf(g[0], wgt, gzx);
     gr[14] = g[1] * wgt;
+    gr[15] = g[3] * wgt;
     float g_rhohat = 0.0f;
     if (!e.clamped) {
       gr[13] = o > 0.0f ? dal * al * __builtin_amdgcn_rcpf(o) : 0.0f;
@@ -1468,7 +1494,7 @@ __device__ __forceinline__ uint32_t lane0_only(uint32_t v) { return (threadIdx.x
 template <int NT, class Ray>
 __device__ void write_tile(const TileArgs& a, const Ray& ray, bool wr, float T, const float* acc, uint32_t last,
                            BlendShared<NT>& sh) {
-  constexpr int C = Ray::C;
+  constexpr int C = Ray::CO;
   static_assert((C + 3) * NT * 4 <= sizeof(sh.rec), "staging area too small");
   float* st = reinterpret_cast<float*>(&sh.rec[0][0]);
   uint32_t* su = reinterpret_cast<uint32_t*>(st);
@@ -1491,6 +1517,7 @@ __device__ void write_tile(const TileArgs& a, const Ray& ray, bool wr, float T, 
     for (int c = 0; c < C; ++c) a.out[c * HW + p] = st[c * NT + src];
     a.T_final[p] = st[C * NT + src];
     a.n_last[p] = su[(C + 1) * NT + src];
+    a.mpair[p] = kNoPair;
   }
   __syncthreads();  // the staging area is free again
 }
@@ -1631,6 +1658,9 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
     for (int c = 0; c < C; ++c) A[c] = part[c * ps + pe];
     T = part[kPartT * ps + pe];
   }
+  // the median depth's gradient goes to the depth of its crossing pair
+  const float gmed = ray.inside ? a.gout[Ray::kMedian * HW + p] : 0.0f;
+  const uint32_t mp = ray.inside ? a.mpair[p] : kNoPair;
   const uint32_t last = ray.inside ? a.n_last[p] : b0;
   __syncthreads();
   if (t == 0) s_max = b0;
@@ -1681,7 +1711,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           const float S = O[c] - A[c];
           dal += g[c] * (T * f[c] - S * inv1m);
         }
-        ray.grads(a, sh.rec[j], e, dal, wgt, g, gr);
+        ray.grads(a, sh.rec[j], e, dal, wgt, g, base + j == mp ? gmed : 0.0f, gr);
         T = T * (1.0f - al);
       }
       if (__ballot(hit) != 0) flush_grads<NT>(gr, sh.ga.g, j, lane);
@@ -1986,6 +2016,106 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT
 
 // Launch variants: every tile size for pinhole / LiDAR mixes; kinds with the
 // cylindrical camera (bit 2) at 256-ray tiles only (plans enforce it).
+// Median depth (2DGS: the depth where the accumulated opacity reaches 1/2)
+// of the rays whose transmittance crosses 1/2 inside this item: they replay
+// the item's pairs from its incoming transmittance (the forward leaves it in
+// the segment's slot; 1 for a whole tile) and take the depth of the pair
+// after which it falls below 1/2.  Which item holds a ray's crossing follows
+// from the forward's own transmittances (incoming >= 1/2 > outgoing, for a
+// ray still compositing there), so exactly one item writes it; should the
+// replay's rounding not cross inside
+// the item, the item's last composited pair stands for it.  The crossing
+// comes before any stop (T_min < 1/2), so the replay needs no stop rule.
+template <int NT, class Ray>
+__device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
+                            BlendShared<NT>& sh) {
+#pragma clang fp contract(off)
+  const Ray ray(a, tile);
+  ray.prepare(a, sh);
+  const uint32_t len = rg.y - rg.x, L = q.seg_len;
+  const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
+  const bool split = n_seg > 1;
+  const uint32_t pbase = split ? q.pslot_base[gt] : 0u;
+  if (split && pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
+  const uint32_t b0 = split ? rg.x + sg * L : rg.x;
+  const uint32_t b1 = split ? min(b0 + L, rg.y) : rg.y;
+  const int t = threadIdx.x;
+  const size_t HW = (size_t)a.S.W * a.S.H, p = ray.inside ? ray.pix(a) : 0;
+  // incoming and outgoing transmittance: a segment's slot holds its incoming
+  // state only while the ray is still compositing there (its last composited
+  // pair, n_last - 1, at or after the segment's start); past its last pair
+  // the outgoing value is T_final
+  float T = 1.0f, Tout = 1.0f;
+  const uint32_t nl = ray.inside ? a.n_last[p] : 0u;
+  if (ray.inside) {
+    Tout = a.T_final[p];
+    if (split) {
+      const size_t ps = q.part_stride;
+      T = q.part[kPartT * ps + (size_t)(pbase + sg) * NT + t];
+      if (sg + 1 < n_seg && nl > b1) Tout = q.part[kPartT * ps + (size_t)(pbase + sg + 1) * NT + t];
+    }
+  }
+  const bool mine = ray.inside && nl > b0 && T >= 0.5f && Tout < 0.5f;
+  bool active = mine;
+  float med = 0.0f, zl = 0.0f;
+  uint32_t mp = kNoPair, pl = kNoPair, n64 = 0;
+  const int w = t >> 6;
+  for (uint32_t base = b0; base < b1; base += NT) {
+    if (t == 0) sh.u[2] = 0u;
+    if (__syncthreads_count(active) == 0) break;
+    stage_batch<NT>(a, ray, base, b1, sh);
+    const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
+    for (int c = 0; c < nch; ++c) {
+      uint64_t m = uniform_mask(&sh.mask[c][w]);
+      const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(c) << 6;
+      while (m && __ballot(active) != 0) {
+        const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        PairEval e;
+        const bool hit = ray.eval(a, sh.rec[j], sh.id[j], sh.f64, e, n64) && active;
+        if (hit) {
+          const float Tn = T * (1.0f - e.alpha);
+          zl = e.z;
+          pl = base + j;
+          if (Tn < 0.5f) {
+            med = e.z;
+            mp = base + j;
+            active = false;
+          }
+          T = Tn;
+        }
+      }
+    }
+  }
+  if (mine) {
+    a.out[Ray::kMedian * HW + p] = mp != kNoPair ? med : zl;
+    a.mpair[p] = mp != kNoPair ? mp : pl;
+  }
+}
+
+template <int NT, int KINDS>
+__global__ __launch_bounds__(NT) void k_median(QueueArgs q) {
+  __shared__ BlendShared<NT> sh;
+  const uint32_t n_items = min(*q.n_items, q.cap_items);
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const uint4 e = q.items[it];
+    const uint32_t gt = rfl(e.x), sg = rfl(e.y);
+    const uint2 rg = make_uint2(rfl(e.z), rfl(e.w));
+    const int si = sensor_of_tile(q, gt);
+    const TileArgs& a = q.tiles[si];
+    const int tile = (int)gt - q.tile_off[si];
+    const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
+    const bool cyl = (KINDS & kKindCyl) && (KINDS == kKindCyl || a.S.kind == GS_SENSOR_CYLINDRICAL);
+    if (cam)
+      median_item<NT, CamRay>(q, a, tile, gt, sg, rg, sh);
+    else if (cyl)
+      median_item<NT, CylRay>(q, a, tile, gt, sg, rg, sh);
+    else if (KINDS & kKindLidar)
+      median_item<NT, LidarRay>(q, a, tile, gt, sg, rg, sh);
+    __syncthreads();  // the shared state is free for the next item
+  }
+}
+
 #define GS_VARIANTS(X) \
   X(64, 1) X(64, 2) X(64, 3) X(128, 1) X(128, 2) X(128, 3) X(256, 1) X(256, 2) X(256, 3) X(512, 1) X(512, 2) \
   X(512, 3) X(256, 4) X(256, 5) X(256, 6) X(256, 7)
@@ -2001,6 +2131,16 @@ void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool 
     else                                                                                          \
       hipLaunchKernelGGL((k_blend_queue<NT, false, K, false>), dim3(grid), dim3(NT), 0, st, q);   \
     return;                                                                                       \
+  }
+  GS_VARIANTS(KCASE)
+#undef KCASE
+}
+
+void launch_median(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st) {
+#define KCASE(NT, K)                                                             \
+  if (rays == NT && kinds == K) {                                                \
+    hipLaunchKernelGGL((k_median<NT, K>), dim3(grid), dim3(NT), 0, st, q);      \
+    return;                                                                      \
   }
   GS_VARIANTS(KCASE)
 #undef KCASE

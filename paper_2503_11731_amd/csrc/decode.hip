@@ -8,7 +8,7 @@
 //   layer 2  Y = H W2^T + b2 on MFMA; H enters as a bf16 hi + lo pair
 //            (H ~ hi + lo to ~2^-17 relative) so that no activation is
 //            quantised to 8 mantissa bits.
-//   heads    opacity / colour / intensity = sigmoid, scale = l_a sigmoid,
+//   heads    opacity / colour / intensity / ray drop = sigmoid, scale = l_a sigmoid,
 //            quaternion = raw, centre = x_a + l_a O_k; surfel n = a K + k.
 // Adjoint: FP32 MFMA contractions; per-block partial weight gradients summed
 // in a fixed order by a second kernel.
@@ -54,6 +54,7 @@ struct DecodeArgs {
   float* opacity;
   float* rgb;
   float* intensity;
+  float* drop;  // LiDAR ray-drop probability
   // adjoint inputs / outputs
   const float* gi_mean;
   const float* gi_quat;
@@ -61,6 +62,7 @@ struct DecodeArgs {
   const float* gi_opacity;
   const float* gi_rgb;
   const float* gi_intensity;
+  const float* gi_drop;
   float* g_xyz;
   float* g_scaling;
   float* g_offsets;
@@ -237,6 +239,7 @@ __global__ __launch_bounds__(256) void k_decode_fwd(DecodeArgs a) {
     a.scale[N + n] = la * sigmoidf(y[so + 1] + bb[so + 1]);
 #pragma unroll
     for (int e = 0; e < 4; ++e) a.quat[e * N + n] = y[so + 2 + e] + bb[so + 2 + e];
+    if (a.lidar) a.drop[n] = sigmoidf(y[8] + bb[8]);
 #pragma unroll
     for (int e = 0; e < 3; ++e)
       a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
@@ -298,6 +301,7 @@ __global__ __launch_bounds__(128) void k_decode_fwd_valu(DecodeArgs a) {
     a.scale[n] = la * sigmoidf(y[so]);
     a.scale[N + n] = la * sigmoidf(y[so + 1]);
     for (int e = 0; e < 4; ++e) a.quat[e * N + n] = y[so + 2 + e];
+    if (a.lidar) a.drop[n] = sigmoidf(y[8]);
     for (int e = 0; e < 3; ++e)
       a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
   }
@@ -308,7 +312,8 @@ __global__ __launch_bounds__(128) void k_decode_fwd_valu(DecodeArgs a) {
 template <bool LIDAR>
 __device__ inline float heads_adjoint(const DecodeArgs& a, float* y, const float* bb, size_t n, size_t N, float la) {
   constexpr int so = LIDAR ? 2 : 4;
-  float gy[so + 6];
+  constexpr int J = LIDAR ? 9 : 10;
+  float gy[J];
   const float s0 = sigmoidf(y[0] + bb[0]);
   gy[0] = (a.gi_opacity ? a.gi_opacity[n] : 0.f) * s0 * (1.f - s0);
   if (!LIDAR) {
@@ -331,8 +336,12 @@ __device__ inline float heads_adjoint(const DecodeArgs& a, float* y, const float
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) gy[so + 2 + e] = a.gi_quat ? a.gi_quat[e * N + n] : 0.f;
+  if (LIDAR) {  // ray-drop head
+    const float s = sigmoidf(y[8] + bb[8]);
+    gy[J - 1] = (a.gi_drop ? a.gi_drop[n] : 0.f) * s * (1.f - s);
+  }
 #pragma unroll
-  for (int j = 0; j < so + 6; ++j) y[j] = gy[j];
+  for (int j = 0; j < J; ++j) y[j] = gy[j];
   return gla;
 }
 
@@ -601,7 +610,7 @@ gs_status fill_args(const gs_anchor_set* an, const float* sensor_pose, const flo
   a.A = an->n_anchors;
   a.K = an->k;
   a.lidar = an->lidar ? 1 : 0;
-  a.J = a.lidar ? 8 : 10;
+  a.J = a.lidar ? 9 : 10;
   a.n_groups = an->n_groups;
   int nb = 0;
   for (int g = 0; g <= an->n_groups; ++g) {
@@ -638,7 +647,7 @@ extern "C" gs_status gs_decode_forward(const gs_anchor_set* anchors, const float
   gs_status s = fill_args(anchors, sensor_pose, group_poses, a, nb);
   if (s != GS_OK) return s;
   if (!out || !out->mean || !out->quat || !out->scale || !out->opacity || (!a.lidar && !out->rgb) ||
-      (a.lidar && !out->intensity))
+      (a.lidar && (!out->intensity || !out->drop)))
     return set_error(GS_ERR_INVALID_ARG, "null decode output");
   a.mean = out->mean;
   a.quat = out->quat;
@@ -646,6 +655,7 @@ extern "C" gs_status gs_decode_forward(const gs_anchor_set* anchors, const float
   a.opacity = out->opacity;
   a.rgb = out->rgb;
   a.intensity = out->intensity;
+  a.drop = out->drop;
   if (anchors->flags & GS_DECODE_VALU_FP32) {
     if (a.A > 0) hipLaunchKernelGGL(k_decode_fwd_valu, dim3((a.A + 127) / 128), dim3(128), 0, stream, a);
   } else if (nb > 0) {
@@ -691,6 +701,7 @@ gs_status decode_backward_impl(const gs_anchor_set* anchors, const float* sensor
   a.gi_opacity = grad_in->opacity;
   a.gi_rgb = grad_in->rgb;
   a.gi_intensity = grad_in->intensity;
+  a.gi_drop = grad_in->drop;
   a.g_xyz = grads->xyz;
   a.g_scaling = grads->scaling;
   a.g_offsets = grads->offsets;

@@ -23,6 +23,7 @@ constexpr int kRadixItems = 4096;
 // keys per radix sort (pairs, records): the look-back counts are 30-bit
 constexpr uint32_t kMaxSortKeys = (1u << 30) - 1u;
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
+constexpr uint32_t kNoPair = 0xFFFFFFFFu;  // a ray whose transmittance never falls below 1/2
 
 // record flags (stored as integer bits in float slot 14)
 //  grazing: h'_2 may fall below 1/8 in the rectangle; pairs with |h'_2| < 1/8
@@ -100,6 +101,7 @@ struct SensorWS {
   uint2* ranges;     // [n_tiles]
   float* T_final;    // [H*W]
   uint32_t* n_last;  // [H*W]
+  uint32_t* mpair;   // [H*W] pair index of the median crossing (kNoPair: none)
   uint32_t* status;  // [16]
   float* gacc;       // [kGradFields][N]
   uint32_t* visible; // [N]

@@ -14,6 +14,7 @@ struct PrepArgs {
   const float* rgb;
   const float* sh;
   const float* intensity;
+  const float* drop;      // LiDAR ray-drop probability [N] (nullptr: 0)
   int sh_degree;
   GroupsK groups;
   SensorK S;
@@ -45,6 +46,7 @@ struct TileArgs {
   const float* gout;      // backward: dL/d outputs
   float* T_final;         // [H*W]
   uint32_t* n_last;       // [H*W]
+  uint32_t* mpair;        // [H*W] pair index of the median crossing (kNoPair: none)
   uint32_t* status;       // counters
   float* gacc;            // [kGradFields][gacc_stride]
   size_t gacc_stride;
@@ -94,6 +96,7 @@ struct SplatBwdArgs {
   float* g_rgb;
   float* g_sh;
   float* g_intensity;
+  float* g_drop;
 };
 
 // preprocess.hip
@@ -152,6 +155,10 @@ void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipS
 // iterations into the status words (calibration runs).
 void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, bool count,
                         hipStream_t st);
+// Median pass after a forward: for every (tile, segment) item, the rays whose
+// transmittance crosses 1/2 inside it replay it from its incoming state and
+// write the median depth / range and the crossing's pair index.
+void launch_median(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st);
 int blend_blocks_per_cu(int rays, int kinds, bool backward);
 bool tile_shape_supported(int tw, int th);
 

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
   r64[0] = mh[0];
   r64[1] = mh[1];
   r64[2] = mh[2];
-  r64[3] = rn;
+  r64[3] = a.drop ? (double)a.drop[i] : 0.0;  // ray-drop probability
   if (flags & kFlagF64) {
     double* gz = a.ws.grz + kGrz * (size_t)i;
     for (int k = 0; k < 9; ++k) gz[k] = Q[k];

@@ -343,8 +343,9 @@ __global__ __launch_bounds__(256, 3) void k_splat_backward(SplatBwdArgs A) {
       A.g_rgb[N + i] = o1 + (float)gcol[1];
       A.g_rgb[2 * N + i] = o2 + (float)gcol[2];
     }
-  } else if (A.g_intensity) {
-    A.g_intensity[i] += (float)g_int;
+  } else {
+    if (A.g_intensity) A.g_intensity[i] += (float)g_int;
+    if (A.g_drop) A.g_drop[i] += gf[15];  // the drop probability enters linearly
   }
 
   if (A.g_mean) {

@@ -34,7 +34,7 @@ class Decoder:
         self.lidar = bool(lidar)
         self.K = int(offsets.shape[1])
         self.A = int(xyz.shape[1])
-        self.J = 8 if lidar else 10
+        self.J = 9 if lidar else 10
         self._off = (ctypes.c_int32 * len(self.group_offsets))(*self.group_offsets)
         self.flags = L.GS_DECODE_VALU_FP32 if plain_fp32 else 0
 
@@ -70,6 +70,7 @@ class Decoder:
         out = dict(mean=e(3), quat=e(4), scale=e(2), opacity=torch.empty(n, dtype=torch.float32, device=dev))
         if self.lidar:
             out["intensity"] = torch.empty(n, dtype=torch.float32, device=dev)
+            out["drop"] = torch.empty(n, dtype=torch.float32, device=dev)
         else:
             out["rgb"] = e(3)
         return out
@@ -77,7 +78,7 @@ class Decoder:
     def forward(self, sensor_pose: torch.Tensor, group_poses: torch.Tensor, out=None) -> dict:
         out = out or self.new_decoded()
         p = lambda k: L.ptr(out.get(k))
-        d = L.Decoded(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("intensity"))
+        d = L.Decoded(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("intensity"), p("drop"))
         s = self._struct()
         L.check(self.lib.gs_decode_forward(ctypes.byref(s), sensor_pose.data_ptr(), group_poses.data_ptr(),
                                            ctypes.byref(d), _stream()))
@@ -104,7 +105,7 @@ class Decoder:
                          w1=z(self.w1), b1=z(self.b1), w2=z(self.w2), b2=z(self.b2))
         gi = {k: (v.contiguous() if v is not None else None) for k, v in grad_in.items()}
         p = lambda k: L.ptr(gi.get(k))
-        d = L.Decoded(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("intensity"))
+        d = L.Decoded(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("intensity"), p("drop"))
         g = lambda k: L.ptr(grads.get(k))
         ag = L.AnchorGrads(g("xyz"), g("scaling"), g("offsets"), g("feat"), g("w1"), g("b1"), g("w2"), g("b2"))
         s = self._struct()

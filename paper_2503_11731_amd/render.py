@@ -20,8 +20,8 @@ PRODUCTION = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, cutoff2=2.0
                   lowpass=True, lp_inv_sigma2=2.0, bg=(0.0, 0.0, 0.0))
 STRICT = dict(PRODUCTION, alpha_min=0.0, T_min=0.0, cutoff2=25.0)
 
-CAMERA_CHANNELS = ("r", "g", "b", "depth", "nx", "ny", "nz", "alpha")
-LIDAR_CHANNELS = ("range", "intensity", "alpha")
+CAMERA_CHANNELS = ("r", "g", "b", "depth", "nx", "ny", "nz", "alpha", "median")
+LIDAR_CHANNELS = ("range", "intensity", "alpha", "drop", "drop_mask", "median")
 
 
 def _stream() -> int:
@@ -118,7 +118,8 @@ class Renderer:
             p = lambda k: L.ptr(_f32(sc.get(k), k))
             if sc["mean"].shape[-1] != shape.n_splats:
                 raise ValueError(f"scene {i}: expected {shape.n_splats} surfels, got {sc['mean'].shape[-1]}")
-            arr[i] = L.Scene(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("sh"), p("intensity"))
+            arr[i] = L.Scene(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("sh"), p("intensity"),
+                             p("drop"))
         return arr
 
     def new_outputs(self):
@@ -171,7 +172,8 @@ class Renderer:
         gptr = (L.SceneGrads * len(self.scenes))()
         for i, g in enumerate(grads):
             p = lambda k: L.ptr(g.get(k))
-            gptr[i] = L.SceneGrads(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("sh"), p("intensity"))
+            gptr[i] = L.SceneGrads(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("sh"), p("intensity"),
+                                   p("drop"))
         grad_outputs = [g.contiguous() for g in grad_outputs]
         optr = (ctypes.c_void_p * len(outputs))(*[o.data_ptr() for o in outputs])
         gop = (ctypes.c_void_p * len(grad_outputs))(*[g.data_ptr() for g in grad_outputs])
@@ -230,7 +232,7 @@ def poses_tensor(poses, device="cuda") -> torch.Tensor:
 def scene_tensors(scene: dict, device="cuda") -> dict:
     """numpy scene dict (gen / tests layout) -> dict of CUDA float32 tensors."""
     out = {}
-    for k in ("mean", "quat", "scale", "opacity", "rgb", "sh", "intensity"):
+    for k in ("mean", "quat", "scale", "opacity", "rgb", "sh", "intensity", "drop"):
         v = scene.get(k)
         if v is not None:
             out[k] = torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(device)

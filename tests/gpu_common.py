@@ -84,17 +84,48 @@ def oracle_vector(ref, kind):
     """Oracle outputs as [C, R] in the device channel order."""
     if kind != "lidar":
         v = np.concatenate([ref["rgb"].reshape(3, -1), ref["depth"].reshape(1, -1), ref["normal"].reshape(3, -1),
-                            ref["alpha"].reshape(1, -1)])
+                            ref["alpha"].reshape(1, -1), ref["median"].reshape(1, -1)])
     else:
-        v = np.stack([ref["range"].reshape(-1), ref["intensity"].reshape(-1), ref["alpha"].reshape(-1)])
+        v = np.stack([ref["range"].reshape(-1), ref["intensity"].reshape(-1), ref["alpha"].reshape(-1),
+                      ref["drop"].reshape(-1), ref["drop_mask"].reshape(-1), ref["median"].reshape(-1)])
     return v
 
 
+CAMERA_NAMES = ["r", "g", "b", "depth", "nx", "ny", "nz", "alpha", "median"]
+LIDAR_NAMES = ["range", "intensity", "alpha", "drop", "drop_mask", "median"]
+
+
+def depth_like(kind):
+    """Channels compared relative to max(1 m, |value|): depth / range and the median."""
+    return (3, 8) if kind != "lidar" else (0, 5)
+
+
+def gmap_of(go, kind):
+    """dL/d(outputs) [C, ...] as the oracle's grad_out dict (the drop mask has no gradient)."""
+    if kind != "lidar":
+        return {"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7], "median": go[8]}
+    return {"range": go[0], "intensity": go[1], "alpha": go[2], "drop": go[3], "median": go[5]}
+
+
+def median_channel(kind):
+    return 8 if kind != "lidar" else 5
+
+
+def quiet_median(go, scene, sensor, o, rays=None):
+    """Zero dL/d(median) (in place) on rays with a decision within ALT_TOL of its
+    threshold: the median's surfel is itself a decision (transmittance against
+    1/2), which the FP32 kernel and the FP64 oracle may then take differently."""
+    m = raster.render(scene, sensor, o, margins=True, rays=rays)["margin"]
+    go[median_channel(sensor["kind"])][m <= ALT_TOL] = 0.0
+    return go
+
+
 def _tolerance(v, kind):
-    """Per-entry tolerance of output vectors v [C, ...]: 1e-4 absolute, depth/range 1e-4 relative to max(1, |v|)."""
+    """Per-entry tolerance of output vectors v [C, ...]: 1e-4 absolute, depth/range and median 1e-4 relative
+    to max(1, |v|)."""
     t = np.full(v.shape, TOL)
-    d = 3 if kind != "lidar" else 0
-    t[d] = TOL_DEPTH * np.maximum(1.0, np.abs(v[d]))
+    for d in depth_like(kind):
+        t[d] = TOL_DEPTH * np.maximum(1.0, np.abs(v[d]))
     return t
 
 
@@ -121,10 +152,10 @@ def verify(got, ref, kind):
     unver = np.zeros(ok.shape, bool)
     unver[ref["unverified"]] = True
     bad = ~ok & ~unver
-    names = (["r", "g", "b", "depth", "nx", "ny", "nz", "alpha"] if kind != "lidar" else ["range", "intensity", "alpha"])
-    d = 3 if kind != "lidar" else 0
+    names = CAMERA_NAMES if kind != "lidar" else LIDAR_NAMES
     rel = best.copy()
-    rel[d] = best[d] / np.maximum(1.0, np.abs(nom[d]))
+    for d in depth_like(kind):
+        rel[d] = best[d] / np.maximum(1.0, np.abs(nom[d]))
     m = ~unver
     errs = {n: float(rel[c][m].max(initial=0.0)) for c, n in enumerate(names)}
     return dict(rays=int(ok.size), flagged=int(len(ref["alts"]["rays"])), alt_only=alt_only,

@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 from gen import scenes as S  # noqa: E402
 from oracle import decode as odec  # noqa: E402
 from oracle import raster, spec32  # noqa: E402
-from tests.gpu_common import ALT_TOL, DEV, assert_verified, verify  # noqa: E402
+from tests.gpu_common import ALT_TOL, DEV, assert_verified, gmap_of, median_channel, verify  # noqa: E402
 
 import paper_2503_11731_amd as gs  # noqa: E402
 
@@ -125,8 +125,7 @@ def _oracle_scene_grads(scene, sensors, outs_grad, scene_of):
     acc = {}
     for i, s in enumerate(sensors):
         go = outs_grad[i]
-        gmap = ({"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]} if s["kind"] == "pinhole"
-                else {"range": go[0], "intensity": go[1], "alpha": go[2]})
+        gmap = gmap_of(go, s["kind"])
         sc = dict(scene)
         if s["kind"] == "pinhole":
             sc.pop("intensity", None)
@@ -152,6 +151,8 @@ def test_batched_backward_matches_per_sensor_and_oracle():
         outs = r.forward(scenes, sp, gp)
         rng = np.random.default_rng(1)
         gos = [rng.standard_normal(tuple(o.shape)).astype(np.float32) for o in outs]
+        for g, s in zip(gos, sensors):
+            g[median_channel(s["kind"])] = 0.0  # the median's gradient is tested per sensor
         res.append(r.backward(scenes, sp, gp, outs, [torch.from_numpy(g).to(DEV) for g in gos]))
     torch.cuda.synchronize()
     for si in range(2):
@@ -321,6 +322,8 @@ def test_decoded_posed_rig_backward_matches_oracle_chain():
     outs = rig.forward()
     rng = np.random.default_rng(12)
     gos = [rng.standard_normal(tuple(o.shape)).astype(np.float32) for o in outs]
+    for g, s in zip(gos, sensors):
+        g[median_channel(s["kind"])] = 0.0  # the median's gradient is tested per sensor
     agc, agl = rig.backward([torch.from_numpy(g).to(DEV) for g in gos])
     torch.cuda.synchronize()
     for kind, an, ag in (("pinhole", cam_sc, agc), ("lidar", lid_sc, agl)):
@@ -336,8 +339,7 @@ def test_decoded_posed_rig_backward_matches_oracle_chain():
                 continue
             dec, sc32 = _oracle_decoded(an, s, kind, leaves=leaves)
             go = gos[i]
-            gmap = ({"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]} if kind == "pinhole"
-                    else {"range": go[0], "intensity": go[1], "alpha": go[2]})
+            gmap = gmap_of(go, kind)
             res = raster.render(sc32, s, raster.make_opts(gs.PRODUCTION, tile_w=32, tile_h=8),
                                 params={k: v.detach().requires_grad_(True) for k, v in dec.items()},
                                 grad_out={k: v.astype(np.float64) for k, v in gmap.items()})

@@ -23,7 +23,8 @@ pytestmark = pytest.mark.gpu
 
 from gen import scenes as S  # noqa: E402
 from oracle import raster  # noqa: E402
-from tests.gpu_common import (ALT_TOL, DEV, assert_verified, check_integer_parity, gpu_render, oracle_opts,  # noqa: E402
+from tests.gpu_common import (ALT_TOL, DEV, assert_verified, check_integer_parity, gmap_of, gpu_render, oracle_opts,  # noqa: E402
+                              quiet_median,
                               verify)
 from tests.helpers import from_gen, surfels  # noqa: E402
 
@@ -117,9 +118,10 @@ def test_cylindrical_backward_parity(kind):
     cam = S.cylindrical(128, 64, 170.0)
     r, st, sp, gp, outs = gpu_render(scene, [cam], gs.PRODUCTION, tiles=(16, 16))
     go = rng.standard_normal(tuple(outs[0].shape)).astype(np.float32)
+    quiet_median(go, scene, cam, oracle_opts(gs.PRODUCTION, (16, 16)))
     grads = r.backward([st], sp, gp, outs, [torch.from_numpy(go).to(DEV)])[0]
     torch.cuda.synchronize()
-    gmap = {"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]}
+    gmap = gmap_of(go, "cylindrical")
     ref = raster.render(scene, cam, oracle_opts(gs.PRODUCTION, (16, 16)),
                         grad_out={k: v.astype(np.float64) for k, v in gmap.items()})
     for k in ("mean", "quat", "scale", "opacity", "rgb" if kind == "rgb" else "sh"):
@@ -197,16 +199,18 @@ def test_cylindrical_1080p_full_size_adjoint_on_a_crop():
     gp = gs.poses_tensor(sc.group_poses, DEV)
     (out,) = r.forward([st], sp, gp)
     rng = np.random.default_rng(8)
-    g_crop = rng.standard_normal((8, rays.size))
+    C = out.shape[0]
+    g_crop = rng.standard_normal((C, rays.size))
+    g_crop[8] = 0.0  # the median's gradient is tested on the small cases
     go = torch.zeros_like(out)
-    go.view(8, -1)[:, torch.from_numpy(rays).to(DEV)] = torch.from_numpy(g_crop.astype(np.float32)).to(DEV)
+    go.view(C, -1)[:, torch.from_numpy(rays).to(DEV)] = torch.from_numpy(g_crop.astype(np.float32)).to(DEV)
     (grads,) = r.backward([st], sp, gp, [out], [go])
     torch.cuda.synchronize()
     o = oracle_opts(gs.PRODUCTION, (32, 8))
-    gmap = {"rgb": g_crop[0:3], "depth": g_crop[3], "normal": g_crop[4:7], "alpha": g_crop[7]}
+    gmap = gmap_of(g_crop, "cylindrical")
     _say("  oracle adjoint over the crop")
     ref = raster.render(scene, cam, o, rays=rays, grad_out=gmap)
-    crop = out.view(8, -1)[:, torch.from_numpy(rays).to(DEV)].cpu().numpy()
+    crop = out.view(C, -1)[:, torch.from_numpy(rays).to(DEV)].cpu().numpy()
     assert np.abs(crop[7] - ref["alpha"]).max() < 1e-3 and ref["alpha"].max() > 0.5
     for k in ("mean", "quat", "scale", "opacity", "sh"):
         g = grads[k].cpu().numpy().astype(np.float64)

@@ -65,7 +65,7 @@ def test_decode_forward_parity(kind, plain):
     torch.cuda.synchronize()
     ref = odec.decode(_anchor_dict(sc), sc.mlps, poses_s, kind)
     errs = {}
-    for k in ("opacity", "scale") + (("rgb",) if kind == "pinhole" else ("intensity",)):
+    for k in ("opacity", "scale") + (("rgb",) if kind == "pinhole" else ("intensity", "drop")):
         errs[k] = _cmp(k, out[k], ref[k].numpy())
     errs["quat"] = _cmp("quat", out["quat"], ref["quat"].numpy(), rel=True)
     errs["mean"] = _cmp("mean", out["mean"], ref["mean"].numpy(), rel=True)

@@ -148,7 +148,7 @@ def test_lidar_full_size_decode_parity():
     d = dec.forward(sp[0], gp)
     torch.cuda.synchronize()
     errs = {}
-    for k in ("opacity", "scale", "intensity"):
+    for k in ("opacity", "scale", "intensity", "drop"):
         errs[k] = float(np.abs(d[k].cpu().numpy().astype(np.float64) - ref_dec[k].numpy()).max())
     for k in ("quat", "mean"):
         ref = ref_dec[k].numpy()
@@ -192,12 +192,12 @@ def test_training_720p_full_size_adjoint_on_a_crop():
     d = dcd.forward(sp[0], gp)
     (out,) = r.forward([d], sp, gp)
     go = torch.zeros_like(out)
-    gflat = go.view(8, -1)
+    gflat = go.view(go.shape[0], -1)
     gflat[:3, torch.from_numpy(rays).to(DEV)] = torch.from_numpy(g_rgb.astype(np.float32)).to(DEV)
     (gsurf,) = r.backward([d], sp, gp, [out], [go])
     ga = dcd.backward(sp[0], gp, gsurf)
     torch.cuda.synchronize()
-    crop = out.view(8, -1)[:, torch.from_numpy(rays).to(DEV)].cpu().numpy()
+    crop = out.view(out.shape[0], -1)[:, torch.from_numpy(rays).to(DEV)].cpu().numpy()
     assert np.abs(crop[:3] - fwd["rgb"]).max() < 1e-3
     _say("  oracle adjoint")
     res = raster.render(sc32, cam, o, rays=rays, params={k: v.detach().requires_grad_(True) for k, v in dec.items()},

@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 
 from gen import scenes as S  # noqa: E402
 from oracle import raster  # noqa: E402
-from tests.gpu_common import (ALT_TOL, assert_verified, check_integer_parity, gpu_render, oracle_opts,  # noqa: E402
+from tests.gpu_common import (ALT_TOL, assert_verified, check_integer_parity, gmap_of, gpu_render, oracle_opts,  # noqa: E402
+                              quiet_median,
                               verify)
 from tests.helpers import from_gen  # noqa: E402
 
@@ -101,7 +102,7 @@ def test_split_tiles_forward_parity(mode, tile):
     # unsplit vs split: identical up to rounding order away from near-threshold decisions
     _, _, _, _, whole = gpu_render(scene, sens, opts, tiles=tile, segment_pairs=-1)
     ref = raster.render(scene, sens[0], oracle_opts(opts, tile), alternatives=ALT_TOL)
-    diff = (whole[0] - outs[0]).abs().cpu().numpy().reshape(8, -1)
+    diff = (whole[0] - outs[0]).abs().cpu().numpy().reshape(outs[0].shape[0], -1)
     m = ref["n_flags"] == 0
     assert diff[:, m].max() <= 2e-5, diff[:, m].max()
 
@@ -186,13 +187,11 @@ def grad_check(scene, sensor, opts, tile, keys, channels_seed=0, segment_pairs=0
         assert r.status()["segments"] > 0
     rng = np.random.default_rng(channels_seed)
     go = rng.standard_normal(tuple(outs[0].shape)).astype(np.float32)
+    o = oracle_opts(opts, tile)
+    quiet_median(go, scene, sensor, o)
     grads = r.backward([st], sp, gp, outs, [torch.from_numpy(go).to(outs[0].device)])[0]
     torch.cuda.synchronize()
-    o = oracle_opts(opts, tile)
-    if sensor["kind"] != "lidar":
-        gmap = {"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]}
-    else:
-        gmap = {"range": go[0], "intensity": go[1], "alpha": go[2]}
+    gmap = gmap_of(go, sensor["kind"])
     ref = raster.render(scene, sensor, o, grad_out={k: v.astype(np.float64) for k, v in gmap.items()})
     res = {}
     for k in keys:

@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 
 from gen import scenes as S  # noqa: E402
 from oracle import raster  # noqa: E402
-from tests.gpu_common import (ALT_TOL, assert_verified, check_integer_parity, gpu_render, oracle_opts,  # noqa: E402
+from tests.gpu_common import (ALT_TOL, assert_verified, check_integer_parity, gmap_of, gpu_render, oracle_opts,  # noqa: E402
+                              quiet_median,
                               verify)
 from tests.helpers import F32  # noqa: E402
 
@@ -116,9 +117,10 @@ def test_posed_groups_backward_parity(sh_degree):
     r, st, sp, gp, outs = gpu_render(scene, [cam], gs.PRODUCTION, tiles=tile)
     rng = np.random.default_rng(9)
     go = rng.standard_normal(tuple(outs[0].shape)).astype(np.float32)
+    quiet_median(go, scene, cam, oracle_opts(gs.PRODUCTION, tile))
     grads = r.backward([st], sp, gp, outs, [torch.from_numpy(go).to(outs[0].device)])[0]
     torch.cuda.synchronize()
-    gmap = {"rgb": go[0:3], "depth": go[3], "normal": go[4:7], "alpha": go[7]}
+    gmap = gmap_of(go, "pinhole")
     ref = raster.render(scene, cam, oracle_opts(gs.PRODUCTION, tile),
                         grad_out={k: v.astype(np.float64) for k, v in gmap.items()})
     keys = ["mean", "quat", "scale", "opacity", "sh" if sh_degree >= 0 else "rgb"]
