@@ -496,9 +496,9 @@ struct CamRay {
     f[6] = R[4].w;
     f[7] = 1.0f;
   }
-  // output channels of a ray with final transmittance T and sums acc (the
-  // median depth is written by the median pass; 0 until then, and for rays
-  // whose transmittance never falls below 1/2)
+  // output channels of a ray with final transmittance T and sums acc; the
+  // median channel is left 0 here (the compositing pass that knows the ray's
+  // incoming transmittance, or the median pass, writes it)
   static __device__ void out_values(const TileArgs& a, float T, const float* acc, float* v) {
 #pragma clang fp contract(off)
     v[0] = fmaf(T, a.O.bg0, acc[0]);
@@ -509,15 +509,17 @@ struct CamRay {
     v[8] = 0.0f;
   }
   static constexpr int kMedian = 8;  // output channel of the median depth
+  // outputs of a split tile's ray that finishes after a walk (the median
+  // channel and pair were written by its segment passes)
   __device__ void write(const TileArgs& a, float T, const float* acc, uint32_t last) const {
     const size_t HW = (size_t)a.S.W * a.S.H, p = pix(a);
     float v[CO];
     out_values(a, T, acc, v);
 #pragma unroll
-    for (int c = 0; c < CO; ++c) a.out[c * HW + p] = v[c];
+    for (int c = 0; c < CO; ++c)
+      if (c != kMedian) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
-    a.mpair[p] = kNoPair;
   }
   // Per-record gradient fields of one pair given dL/dalpha (dal) and the
   // pair's weight wgt = alpha T: [0..5] dP, [6..7] d(projected centre),
@@ -895,10 +897,10 @@ struct CylRay {
     float v[CO];
     out_values(a, T, acc, v);
 #pragma unroll
-    for (int c = 0; c < CO; ++c) a.out[c * HW + p] = v[c];
+    for (int c = 0; c < CO; ++c)
+      if (c != kMedian) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
-    a.mpair[p] = kNoPair;
   }
   // The camera's fields: [0..5] dP, [6..7] d(projected centre), [8] d r (the
   // record's centre distance), [9] d opacity, [10..12] d colour, [13..15]
@@ -1217,10 +1219,10 @@ struct LidarRay {
     float v[CO];
     out_values(a, T, acc, v);
 #pragma unroll
-    for (int c = 0; c < CO; ++c) a.out[c * HW + p] = v[c];
+    for (int c = 0; c < CO; ++c)
+      if (c != kMedian) a.out[c * HW + p] = v[c];
     a.T_final[p] = T;
     a.n_last[p] = last;
-    a.mpair[p] = kNoPair;
   }
   // [0..8] dQ (row-major), [9..11] d mu_hat, [12] d|mu|, [13] d opacity,
   // [14] d intensity, [15] d ray drop.
@@ -1405,10 +1407,15 @@ __device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
 // mask) -- n_contrib the composited pairs per ray and n_iter the wave's pair
 // iterations; without it they are left alone (the counting is a sizeable
 // part of the pair loop's scalar work).  n64 always counts FP64 re-solves.
+//
+// With `track` (the caller's T is the ray's true transmittance: a whole tile,
+// or the first segment of a split one), the first composited pair that takes
+// T below 1/2 is recorded: its depth in med and its pair index in mp (which
+// the caller starts at kNoPair).
 template <int NT, bool COUNT, class Ray>
 __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, BlendShared<NT>& sh,
                           bool lane_counts, bool& done, float& T, float* acc, uint32_t& last, uint32_t& n_eval, uint32_t& n_contrib,
-                          uint32_t& n64, uint32_t& n_iter) {
+                          uint32_t& n64, uint32_t& n_iter, bool track, float& med, uint32_t& mp) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
@@ -1460,6 +1467,10 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           ray.feat(Rl, e, f);
 #pragma unroll
           for (int c2 = 0; c2 < C; ++c2) acc[c2] = fmaf(wgt, f[c2], acc[c2]);
+          if (track && Tn < 0.5f && mp == kNoPair) {
+            med = e.z;
+            mp = base + j;
+          }
           T = Tn;
           last = base + j + 1;
         }
@@ -1491,22 +1502,27 @@ __device__ __forceinline__ uint32_t lane0_only(uint32_t v) { return (threadIdx.x
 // of a wave form an 8x8 block, so direct stores would write 32-byte pieces of
 // each image row; staged, every store instruction writes whole tile rows.
 // All threads call it; it reuses the record staging area (no batch is live).
+// with_median: the median channel and pair index are written too (from med
+// and mp of a whole tile's pass); else they are left to the segment passes.
 template <int NT, class Ray>
 __device__ void write_tile(const TileArgs& a, const Ray& ray, bool wr, float T, const float* acc, uint32_t last,
-                           BlendShared<NT>& sh) {
+                           bool with_median, float med, uint32_t mp, BlendShared<NT>& sh) {
   constexpr int C = Ray::CO;
-  static_assert((C + 3) * NT * 4 <= sizeof(sh.rec), "staging area too small");
+  constexpr int M = Ray::kMedian;
+  static_assert((C + 4) * NT * 4 <= sizeof(sh.rec), "staging area too small");
   float* st = reinterpret_cast<float*>(&sh.rec[0][0]);
   uint32_t* su = reinterpret_cast<uint32_t*>(st);
   const int t = threadIdx.x;
   float v[C];
   Ray::out_values(a, T, acc, v);
+  v[M] = mp != kNoPair ? med : 0.0f;
   __syncthreads();  // every wave is past its last read of the batch records
 #pragma unroll
   for (int c = 0; c < C; ++c) st[c * NT + t] = v[c];
   st[C * NT + t] = T;
   su[(C + 1) * NT + t] = last;
   su[(C + 2) * NT + t] = wr ? 1u : 0u;
+  su[(C + 3) * NT + t] = mp;
   __syncthreads();
   const int tw = a.S.tw, row = t / tw, col = t - row * tw;
   const int src = ((row >> 3) * (tw >> 3) + (col >> 3)) * 64 + (row & 7) * 8 + (col & 7);
@@ -1514,10 +1530,11 @@ __device__ void write_tile(const TileArgs& a, const Ray& ray, bool wr, float T, 
   if (px < a.S.W && py < a.S.H && su[(C + 2) * NT + src]) {
     const size_t HW = (size_t)a.S.W * a.S.H, p = (size_t)py * a.S.W + px;
 #pragma unroll
-    for (int c = 0; c < C; ++c) a.out[c * HW + p] = st[c * NT + src];
+    for (int c = 0; c < C; ++c)
+      if (c != M || with_median) a.out[c * HW + p] = st[c * NT + src];
     a.T_final[p] = st[C * NT + src];
     a.n_last[p] = su[(C + 1) * NT + src];
-    a.mpair[p] = kNoPair;
+    if (with_median) a.mpair[p] = su[(C + 3) * NT + src];
   }
   __syncthreads();  // the staging area is free again
 }
@@ -1617,7 +1634,7 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
       marked = sg + 1;
     }
   }
-  write_tile<NT>(a, ray, wr, T, acc, last, sh);
+  write_tile<NT>(a, ray, wr, T, acc, last, false, 0.0f, kNoPair, sh);
   count_wg(sh, si, n_eval, n_contrib, n64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
@@ -1810,13 +1827,19 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
     }
   }
   bool done = false;
+  // the median crossing is found here where the incoming transmittance is
+  // the ray's true one (1): a whole tile, or the first segment of a split
+  // tile; a crossing in a later segment is left to the median pass
+  const bool track = !walk && sg == 0;
+  float med = 0.0f;
+  uint32_t mp = kNoPair;
   for (uint32_t cur = sg;;) {
     const bool active = need == cur;
     done = !active;
     const uint32_t b0 = rg.x + cur * L;
     // a segment keeps per-ray counts: the merge takes them ray by ray
     composite<NT, COUNT>(a, ray, b0, split ? min(b0 + L, rg.y) : rg.y, sh, partial, done, T, acc, last,
-                  partial ? n_eval : n_eval_w, n_contrib, n64, n_iter);
+                  partial ? n_eval : n_eval_w, n_contrib, n64, n_iter, track, med, mp);
     if (!walk) break;
     if (active) {
       need = done ? kNone
@@ -1839,10 +1862,15 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
   }
   if (!partial) {
     count_wg(sh, si, lane0_only(n_eval_w), n_contrib, n64, n_iter);
-    write_tile<NT>(a, ray, ray.inside, T, acc, last, sh);
+    write_tile<NT>(a, ray, ray.inside, T, acc, last, true, med, mp, sh);
     return;
   }
   count_wg(sh, si, 0u, 0u, n64, n_iter);
+  if (ray.inside && sg == 0) {
+    const size_t HW = (size_t)a.S.W * a.S.H, p = ray.pix(a);
+    a.out[Ray::kMedian * HW + p] = mp != kNoPair ? med : 0.0f;
+    a.mpair[p] = mp;
+  }
   if (ray.inside) {
 #pragma unroll
     for (int c = 0; c < C; ++c) part[c * ps + pe] = acc[c];
@@ -2017,28 +2045,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT
 // Launch variants: every tile size for pinhole / LiDAR mixes; kinds with the
 // cylindrical camera (bit 2) at 256-ray tiles only (plans enforce it).
 // Median depth (2DGS: the depth where the accumulated opacity reaches 1/2)
-// of the rays whose transmittance crosses 1/2 inside this item: they replay
-// the item's pairs from its incoming transmittance (the forward leaves it in
-// the segment's slot; 1 for a whole tile) and take the depth of the pair
-// after which it falls below 1/2.  Which item holds a ray's crossing follows
-// from the forward's own transmittances (incoming >= 1/2 > outgoing, for a
-// ray still compositing there), so exactly one item writes it; should the
-// replay's rounding not cross inside
-// the item, the item's last composited pair stands for it.  The crossing
-// comes before any stop (T_min < 1/2), so the replay needs no stop rule.
+// of the rays whose transmittance crosses 1/2 in a later segment (s >= 1) of
+// a split tile; whole tiles and first segments, composited from the ray's
+// true incoming transmittance, had their crossing recorded by the forward.
+// Such rays replay the segment's pairs from its incoming transmittance (the
+// merge leaves it in the segment's slot) and take the depth of the pair
+// after which it falls below 1/2.  Which segment holds a ray's crossing
+// follows from the forward's own transmittances (incoming >= 1/2 > outgoing,
+// for a ray still compositing there), so exactly one item writes it; should
+// the replay's rounding not cross inside the segment, its last composited
+// pair stands for it.  The crossing comes before any stop (T_min < 1/2), so
+// the replay needs no stop rule.
 template <int NT, class Ray>
 __device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
                             BlendShared<NT>& sh) {
 #pragma clang fp contract(off)
-  const Ray ray(a, tile);
-  ray.prepare(a, sh);
   const uint32_t len = rg.y - rg.x, L = q.seg_len;
   const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
-  const bool split = n_seg > 1;
-  const uint32_t pbase = split ? q.pslot_base[gt] : 0u;
-  if (split && pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
-  const uint32_t b0 = split ? rg.x + sg * L : rg.x;
-  const uint32_t b1 = split ? min(b0 + L, rg.y) : rg.y;
+  if (n_seg == 1 || sg == 0) return;  // uniform over the workgroup
+  const Ray ray(a, tile);
+  ray.prepare(a, sh);
+  const uint32_t pbase = q.pslot_base[gt];
+  if (pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
+  const uint32_t b0 = rg.x + sg * L;
+  const uint32_t b1 = min(b0 + L, rg.y);
   const int t = threadIdx.x;
   const size_t HW = (size_t)a.S.W * a.S.H, p = ray.inside ? ray.pix(a) : 0;
   // incoming and outgoing transmittance: a segment's slot holds its incoming
@@ -2049,11 +2079,9 @@ __device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uin
   const uint32_t nl = ray.inside ? a.n_last[p] : 0u;
   if (ray.inside) {
     Tout = a.T_final[p];
-    if (split) {
-      const size_t ps = q.part_stride;
-      T = q.part[kPartT * ps + (size_t)(pbase + sg) * NT + t];
-      if (sg + 1 < n_seg && nl > b1) Tout = q.part[kPartT * ps + (size_t)(pbase + sg + 1) * NT + t];
-    }
+    const size_t ps = q.part_stride;
+    T = q.part[kPartT * ps + (size_t)(pbase + sg) * NT + t];
+    if (sg + 1 < n_seg && nl > b1) Tout = q.part[kPartT * ps + (size_t)(pbase + sg + 1) * NT + t];
   }
   const bool mine = ray.inside && nl > b0 && T >= 0.5f && Tout < 0.5f;
   bool active = mine;

@@ -155,9 +155,10 @@ void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipS
 // iterations into the status words (calibration runs).
 void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, bool count,
                         hipStream_t st);
-// Median pass after a forward: for every (tile, segment) item, the rays whose
-// transmittance crosses 1/2 inside it replay it from its incoming state and
-// write the median depth / range and the crossing's pair index.
+// Median pass after a forward: the rays whose transmittance crosses 1/2 in
+// a later segment (s >= 1) of a split tile replay that segment from its
+// incoming state and write the median depth / range and the crossing's pair
+// index (the forward writes both for every other ray).
 void launch_median(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st);
 int blend_blocks_per_cu(int rays, int kinds, bool backward);
 bool tile_shape_supported(int tw, int th);
