@@ -1327,6 +1327,11 @@ struct BlendShared {
   // atomics on the same few words serialise across the whole device
   unsigned long long cnt[GS_MAX_SENSORS][4];
   float lbox[NT / 64][6];  // LiDAR: direction box of each wave's block
+  // forward: each ray's median crossing (depth, pair index; kNoPair: none
+  // yet), kept here rather than in registers (it is written once per ray)
+  float med[NT];
+  uint32_t mp[NT];
+  uint32_t mbits[9];  // merge: segments holding some ray's median crossing ([8]: any from 256 on)
   GradArea<NT, BWD> ga;
 };
 
@@ -1409,13 +1414,13 @@ __device__ __forceinline__ uint64_t uniform_mask(const uint64_t* p) {
 // part of the pair loop's scalar work).  n64 always counts FP64 re-solves.
 //
 // With `track` (the caller's T is the ray's true transmittance: a whole tile,
-// or the first segment of a split one), the first composited pair that takes
-// T below 1/2 is recorded: its depth in med and its pair index in mp (which
-// the caller starts at kNoPair).
+// the first segment of a split one, or a walk from the merged state), the
+// composited pair that takes T from at least 1/2 to below it is recorded: its
+// depth in sh.med and its pair index in sh.mp (the ray's own entries).
 template <int NT, bool COUNT, class Ray>
 __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32_t b1, BlendShared<NT>& sh,
                           bool lane_counts, bool& done, float& T, float* acc, uint32_t& last, uint32_t& n_eval, uint32_t& n_contrib,
-                          uint32_t& n64, uint32_t& n_iter, bool track, float& med, uint32_t& mp) {
+                          uint32_t& n64, uint32_t& n_iter, bool track) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
@@ -1467,9 +1472,9 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           ray.feat(Rl, e, f);
 #pragma unroll
           for (int c2 = 0; c2 < C; ++c2) acc[c2] = fmaf(wgt, f[c2], acc[c2]);
-          if (track && Tn < 0.5f && mp == kNoPair) {
-            med = e.z;
-            mp = base + j;
+          if (track && T >= 0.5f && Tn < 0.5f) {
+            sh.med[t] = e.z;
+            sh.mp[t] = base + j;
           }
           T = Tn;
           last = base + j + 1;
@@ -1563,15 +1568,25 @@ __device__ __forceinline__ bool accept_segment(float T, float Ts, uint32_t ls, f
   return !(ls >> 31) && (Ts == 1.0f || T * Ts >= T_accept);
 }
 
+// Appends (tile gt, segment sg) to the median pass's list.
+__device__ __forceinline__ void list_median(const QueueArgs& q, uint32_t gt, uint32_t sg) {
+  const uint32_t w = atomicAdd(q.hdr + 7, 1u);
+  if (w < q.pslot_cap) q.mlist[w] = ((unsigned long long)gt << 32) | sg;
+}
+
 // Front-to-back merge of a split tile's segment partials from slot sg0 with
 // the ray's running state.  Every reached slot keeps the segment's incoming
 // (T, prefix) for the adjoint.  Returns the first segment that cannot be
 // taken whole (the ray's stop lies in it, or may), or n_seg when every
-// remaining segment was taken.
+// remaining segment was taken.  With mbits (the tile's merge), a later
+// segment (s >= 1) taken whole in which T falls from at least 1/2 to below
+// it is marked for the median pass, which finds the crossing: bit s of the
+// LDS mask mbits[0..8) when s < 256, else mbits[8] (every segment from 256 on
+// is then listed; the pass itself tests which rays cross where).
 template <int NT, class Ray>
 __device__ uint32_t merge_from(uint32_t n_seg, uint32_t pbase, uint32_t sg0, float* part, size_t ps,
                                float T_accept, float& T, float* acc, uint32_t& last, uint32_t& n_eval,
-                               uint32_t& n_contrib) {
+                               uint32_t& n_contrib, uint32_t* mbits) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   uint32_t* pu = reinterpret_cast<uint32_t*>(part);
@@ -1590,7 +1605,10 @@ __device__ uint32_t merge_from(uint32_t n_seg, uint32_t pbase, uint32_t sg0, flo
     if (!accept_segment(T, Ts, ls, T_accept)) return sg;
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = fmaf(T, as[c], acc[c]);
-    T = T * Ts;
+    const float Tn = T * Ts;
+    if (mbits && sg > 0 && T >= 0.5f && Tn < 0.5f)
+      atomicOr(&mbits[min(sg >> 5, 8u)], sg < 256u ? 1u << (sg & 31u) : 1u);
+    T = Tn;
     if (ls) last = ls;
     n_eval += cnt & 0xFFFFu;
     n_contrib += cnt >> 16;
@@ -1619,9 +1637,11 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
   for (int c = 0; c < C; ++c) acc[c] = 0.0f;
   uint32_t last = rg.x;
   bool wr = false;
+  if (threadIdx.x < 9) sh.mbits[threadIdx.x] = 0u;
+  __syncthreads();
   if (ray.inside) {
     const uint32_t sg = merge_from<NT, Ray>(n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc, last, n_eval,
-                                            n_contrib);
+                                            n_contrib, sh.mbits);
     if (sg == n_seg) {
       wr = true;
     } else {
@@ -1634,6 +1654,10 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
       marked = sg + 1;
     }
   }
+  __syncthreads();
+  const uint32_t n_list = sh.mbits[8] ? n_seg : min(n_seg, 256u);
+  for (uint32_t k = threadIdx.x; k < n_list; k += NT)
+    if (k < 256u ? (sh.mbits[k >> 5] >> (k & 31u)) & 1u : 1u) list_median(q, gt, k);
   write_tile<NT>(a, ray, wr, T, acc, last, false, 0.0f, kNoPair, sh);
   count_wg(sh, si, n_eval, n_contrib, n64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1828,22 +1852,25 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
   }
   bool done = false;
   // the median crossing is found here where the incoming transmittance is
-  // the ray's true one (1): a whole tile, or the first segment of a split
-  // tile; a crossing in a later segment is left to the median pass
-  const bool track = !walk && sg == 0;
-  float med = 0.0f;
-  uint32_t mp = kNoPair;
+  // the ray's true one: a whole tile, the first segment of a split tile (1),
+  // a walk (the merged state); a crossing in a later segment taken whole by a
+  // merge is left to the median pass
+  const bool track = walk || sg == 0;
+  sh.mp[threadIdx.x] = kNoPair;  // this thread's own entry: no barrier needed
   for (uint32_t cur = sg;;) {
     const bool active = need == cur;
     done = !active;
     const uint32_t b0 = rg.x + cur * L;
     // a segment keeps per-ray counts: the merge takes them ray by ray
     composite<NT, COUNT>(a, ray, b0, split ? min(b0 + L, rg.y) : rg.y, sh, partial, done, T, acc, last,
-                  partial ? n_eval : n_eval_w, n_contrib, n64, n_iter, track, med, mp);
+                  partial ? n_eval : n_eval_w, n_contrib, n64, n_iter, track);
     if (!walk) break;
     if (active) {
+      // a walked ray's transmittance is near T_min: no later segment can hold
+      // its median crossing (nothing to mark)
       need = done ? kNone
-                  : merge_from<NT, Ray>(n_seg, pbase, cur + 1, part, ps, q.T_accept, T, acc, last, n_eval, n_contrib);
+                  : merge_from<NT, Ray>(n_seg, pbase, cur + 1, part, ps, q.T_accept, T, acc, last, n_eval, n_contrib,
+                                        nullptr);
       if (need == n_seg) need = kNone;
       if (need == kNone) ray.write(a, T, acc, last);
     }
@@ -1856,19 +1883,25 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
     if (nxt == kNone) break;
     cur = nxt;
   }
+  const uint32_t mp = sh.mp[threadIdx.x];
   if (walk) {
+    if (ray.inside && mp != kNoPair) {  // a crossing inside a walked segment
+      const size_t HW = (size_t)a.S.W * a.S.H, p = ray.pix(a);
+      a.out[Ray::kMedian * HW + p] = sh.med[threadIdx.x];
+      a.mpair[p] = mp;
+    }
     count_wg(sh, si, lane0_only(n_eval_w) + n_eval, n_contrib, n64, n_iter);
     return;
   }
   if (!partial) {
     count_wg(sh, si, lane0_only(n_eval_w), n_contrib, n64, n_iter);
-    write_tile<NT>(a, ray, ray.inside, T, acc, last, true, med, mp, sh);
+    write_tile<NT>(a, ray, ray.inside, T, acc, last, true, sh.med[threadIdx.x], mp, sh);
     return;
   }
   count_wg(sh, si, 0u, 0u, n64, n_iter);
   if (ray.inside && sg == 0) {
     const size_t HW = (size_t)a.S.W * a.S.H, p = ray.pix(a);
-    a.out[Ray::kMedian * HW + p] = mp != kNoPair ? med : 0.0f;
+    a.out[Ray::kMedian * HW + p] = mp != kNoPair ? sh.med[threadIdx.x] : 0.0f;
     a.mpair[p] = mp;
   }
   if (ray.inside) {
@@ -2124,13 +2157,13 @@ __device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uin
 template <int NT, int KINDS>
 __global__ __launch_bounds__(NT) void k_median(QueueArgs q) {
   __shared__ BlendShared<NT> sh;
-  const uint32_t n_items = min(*q.n_items, q.cap_items);
-  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const uint4 e = q.items[it];
-    const uint32_t gt = rfl(e.x), sg = rfl(e.y);
-    const uint2 rg = make_uint2(rfl(e.z), rfl(e.w));
+  const uint32_t n = min(q.hdr[7], q.pslot_cap);
+  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const unsigned long long e = q.mlist[it];
+    const uint32_t gt = rfl((uint32_t)(e >> 32)), sg = rfl((uint32_t)e);
     const int si = sensor_of_tile(q, gt);
     const TileArgs& a = q.tiles[si];
+    const uint2 rg = a.ranges[gt];
     const int tile = (int)gt - q.tile_off[si];
     const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
     const bool cyl = (KINDS & kKindCyl) && (KINDS == kKindCyl || a.S.kind == GS_SENSOR_CYLINDRICAL);

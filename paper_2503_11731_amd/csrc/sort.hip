@@ -507,6 +507,7 @@ __global__ __launch_bounds__(1024) void k_seg_top(SegScanArgs a, int nblk) {
     a.hdr[4] = 0u;
     a.hdr[5] = 0u;
     a.hdr[6] = 0u;
+    a.hdr[7] = 0u;
     if (tx > a.cap_items || ty > a.pslot_cap) a.status[kStOverflow] = 1u;
   }
   if (threadIdx.x < kQueues) a.qcnt[kQCntStride * threadIdx.x] = 0u;
