@@ -62,7 +62,7 @@ PEAK_BF16_TFLOPS = 2500.0
 # (two-plane solve, low-pass filter, exponent, transmittance and blend).
 FLOP_PER_PAIR = 60
 REC_BYTES = 72                    # algorithmic per-surfel record gathered per pair
-CHANNELS = {"pinhole": 8, "lidar": 3}
+CHANNELS = {"pinhole": 9, "lidar": 6}
 
 BLEND_SOURCES = ("paper_2503_11731_amd/csrc/blend.hip", "paper_2503_11731_amd/csrc/gs_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blend_rig_step_traffic.json")
@@ -143,21 +143,25 @@ class RigStep:
     (sensor i renders scene i, its own decode), and every buffer a step uses, allocated
     once so that the step can be captured into a graph."""
 
-    def __init__(self, cam_sc, lid_sc, sensors, dev, *, batched, tiles=None, segment_pairs=0, plain=False):
+    def __init__(self, cam_sc, lid_sc, sensors, dev, *, batched, tiles=None, segment_pairs=0, plain=False,
+                 decoders=None, train=True):
         import torch
 
         import paper_2503_11731_amd as gs
         self.sensors = sensors
-        self.dc = gs.Decoder.from_gen(cam_sc, dev, plain_fp32=plain)
-        self.dl = gs.Decoder.from_gen(lid_sc, dev, plain_fp32=plain)
+        if decoders is None:
+            self.dc = gs.Decoder.from_gen(cam_sc, dev, plain_fp32=plain)
+            self.dl = gs.Decoder.from_gen(lid_sc, dev, plain_fp32=plain)
+        else:
+            self.dc, self.dl = decoders
         self.sp = gs.poses_tensor([s["pose"] for s in sensors], dev)
         self.gp_c = gs.poses_tensor(cam_sc.group_poses, dev)
         self.gp_l = gs.poses_tensor(lid_sc.group_poses, dev)
         shapes, sens = [], []
         for i, s in enumerate(sensors):
-            an = cam_sc if s["kind"] == "pinhole" else lid_sc
-            offs = tuple(int(x) * an.k for x in an.group_offsets)
-            shapes.append(gs.SceneShape(an.n_anchors * an.k, -1, s["kind"] != "pinhole", offs))
+            d = self.dc if s["kind"] == "pinhole" else self.dl
+            offs = tuple(int(x) * d.K for x in d.group_offsets)
+            shapes.append(gs.SceneShape(d.A * d.K, -1, s["kind"] != "pinhole", offs))
             s = dict(s, scene=i)
             if tiles is not None:
                 s["tile"] = tiles[i]
@@ -170,6 +174,8 @@ class RigStep:
         self.ds = [self._dec(i).new_decoded() for i in range(len(sensors))]
         self.outs = self.r.new_outputs()
         self.rays = sum(s["width"] * s["height"] for s in sensors)
+        if not train:
+            return
         # training-step buffers
         g = torch.Generator(device=dev).manual_seed(7)
         self.targets = [torch.rand(o.shape, generator=g, device=dev) for o in self.outs]
@@ -295,15 +301,18 @@ def rig_cpu_baseline_and_errors(cam_sc, lid_sc, sensors, outs, stride=8, which=(
         got = outs[i].reshape(outs[i].shape[0], -1)[:, torch.as_tensor(ids, device=outs[i].device)]
         got = got.cpu().numpy().astype(np.float64)
         if s["kind"] == "pinhole":
-            names = ("r", "g", "b", "depth", "nx", "ny", "nz", "alpha")
-            want = np.concatenate([ref["rgb"], ref["depth"][None], ref["normal"], ref["alpha"][None]])
-            dch = 3
+            names = ("r", "g", "b", "depth", "nx", "ny", "nz", "alpha", "median")
+            want = np.concatenate([ref["rgb"], ref["depth"][None], ref["normal"], ref["alpha"][None],
+                                   ref["median"][None]])
+            dch = (3, 8)
         else:
-            names = ("range", "intensity", "alpha")
-            want = np.stack([ref["range"], ref["intensity"], ref["alpha"]])
-            dch = 0
+            names = ("range", "intensity", "alpha", "drop", "drop_mask", "median")
+            want = np.stack([ref["range"], ref["intensity"], ref["alpha"], ref["drop"], ref["drop_mask"],
+                             ref["median"]])
+            dch = (0, 5)
         e = np.abs(got - want)
-        e[dch] /= np.maximum(1.0, np.abs(want[dch]))
+        for c in dch:
+            e[c] /= np.maximum(1.0, np.abs(want[c]))
         beyond = int((e > 1e-4).any(0).sum())
         errs[f"sensor{i}_{s['kind']}"] = {"max_err": {nm: float(e[c].max()) for c, nm in enumerate(names)},
                                           "p9999_err": {nm: float(np.quantile(e[c], 0.9999)) for c, nm in
@@ -315,10 +324,164 @@ def rig_cpu_baseline_and_errors(cam_sc, lid_sc, sensors, outs, stride=8, which=(
                       f"({'; '.join(parts)}), each sensor's 340k anchors decoded in FP64 and all 3.4M surfels "
                       f"set up; {total_s:.1f} s of CPU time for {total_rays} rays", **cpu_info()}
     errs["note"] = ("GPU step (BF16-MFMA decode, FP32 render) minus the FP64 oracle chain (decode of the same bf16 "
-                    "parameters, render) on the sampled rays; depth/range relative to max(1 m, |ref|); rays beyond "
+                    "parameters, render) on the sampled rays; depth/range/median relative to max(1 m, |ref|); rays beyond "
                     "1e-4 are rays with a decision within rounding of its threshold (the parity tests verify them "
                     "against the oracle's alternative outcomes)")
     return base, errs
+
+
+def bench_chunk_stream(stream, tiles=None, seg=0, step_m=1.5, length_m=150.0, warmup=3):
+    """Step latency of the six-camera + LiDAR rig driving along a 200 m corridor cut into
+    40 m zones (25 % padding, Sec. III-A large-scale scenes), frame by frame:
+      whole     every anchor resident, one plan (the scene without zones);
+      prefetch  two zone buffers per sensor kind; the next zone is gathered and copied by the
+                library's swap-in thread once the vehicle is within the padding (10 m) of the
+                boundary, overlapping the renders, and the buffers swap at the crossing;
+      sync      the same buffers, with the zone loaded only at the crossing (the step waits
+                for the gather and the copy).
+    Each step: sensor poses to the device, decode of both kinds + batched render of the seven
+    sensors as one HIP graph (per buffer), synchronised; host wall time per step."""
+    import numpy as np
+    import torch
+
+    import paper_2503_11731_amd as gs
+    from gen import scenes as S
+    from paper_2503_11731_amd import zones as gz
+    dev = torch.device("cuda:0")
+    z_lo, z_hi, n_anchors = -20.0, 180.0, 333_000
+    cam = S.corridor_anchors(seed=6, n_anchors=n_anchors, sensor_kind="pinhole", z_lo=z_lo, z_hi=z_hi,
+                             n_assets=20, asset_anchors=2_000)
+    lid = S.corridor_anchors(seed=6, n_anchors=n_anchors, sensor_kind="lidar", z_lo=z_lo, z_hi=z_hi,
+                             n_assets=20, asset_anchors=2_000)
+    grid = gz.ZoneGrid(axis=(0, 2), origin=(-20.0, z_lo), size=40.0, pad=0.25, nx=1, ny=5)
+    base = [S.pinhole(w, h, f, pose=S.camera_yaw_pose(yaw)) for _, yaw, w, h, f in S.CAMERA_RIG]
+    base.append(S.lidar_spinning())
+    path = np.arange(0.0, length_m + 1e-9, step_m)
+    allp = torch.from_numpy(np.stack([np.stack([S.translate_pose(s["pose"], (0.0, 0.0, zv)).reshape(12)
+                                                for s in base]) for zv in path]).astype(np.float32)).pin_memory()
+    zone_of = [grid.zone_of(0.0, zv) for zv in path]
+
+    def drive(rig_of, before=None):
+        lat = []
+        with torch.cuda.stream(stream):
+            for k in list(range(warmup)) + list(range(len(path))):
+                t0 = time.perf_counter()
+                rig = before(k) if before else rig_of
+                rig.sp.copy_(allp[k], non_blocking=True)
+                rig.launch()
+                stream.synchronize()
+                lat.append((time.perf_counter() - t0) * 1e3)
+        return lat[warmup:]
+
+    def summary(lat, crossing=None):
+        a = np.asarray(lat)
+        d = {"p50_ms": float(np.median(a)), "p99_ms": float(np.quantile(a, 0.99)), "max_ms": float(a.max()),
+             "mean_ms": float(a.mean())}
+        if crossing is not None:
+            c = a[crossing]
+            d.update(crossing_steps_ms=[round(float(x), 3) for x in c], crossing_max_ms=float(c.max()),
+                     steady_p50_ms=float(np.median(np.delete(a, crossing))))
+        return d
+
+    out = {"workload": "six-camera + LiDAR rig (3 x 1920x1080 + 3 x 1280x720 pinhole, 128 x 1800 LiDAR) driving "
+                       f"{length_m:.0f} m along a 200 m corridor at {step_m} m per frame; 333k corridor anchors + 20 "
+                       "vehicle assets x 2k (10 offsets), 40 m zones with 25 % padding (60 m squares), each zone with "
+                       "its own MLP; decode + batched render per frame as one HIP graph",
+           "zones": grid.n_zones, "frames": int(len(path))}
+    # the whole corridor resident
+    whole = RigStep(cam, lid, base, dev, batched=True, tiles=tiles, segment_pairs=seg, train=False)
+    whole.fwd()
+    whole.capture(whole.fwd, stream)
+    out["whole"] = summary(drive(whole))
+    out["surfels_per_sensor_whole"] = whole.shapes[0].n_splats
+    del whole
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # zone buffers
+    sc_c, ac_c = S.static_and_actors(cam)
+    sc_l, ac_l = S.static_and_actors(lid)
+    t0 = time.perf_counter()
+    za = [gz.ZonedAnchors(sc_c, S.zone_mlps(61, grid.n_zones, "pinhole"), grid, lidar=False, device=dev,
+                          actors=ac_c, threads=4),
+          gz.ZonedAnchors(sc_l, S.zone_mlps(62, grid.n_zones, "lidar"), grid, lidar=True, device=dev,
+                          actors=ac_l, threads=4)]
+    out["partition_and_setup_s"] = time.perf_counter() - t0
+    out["zone_anchors"] = [int(c) for c in za[0].counts]
+    out["zone_capacity"] = za[0].capacity
+    out["surfels_per_sensor_zone_buffer"] = za[0].n_surfels
+
+    def each(fn):
+        for z in za:
+            fn(z.stream)
+
+    with torch.cuda.stream(stream):
+        for b in (0, 1):
+            each(lambda s: s.prefetch(b, b))
+            each(lambda s: s.acquire(b))
+    rigs = [RigStep(cam, lid, base, dev, batched=True, tiles=tiles, segment_pairs=seg, train=False,
+                    decoders=(za[0].decoders[b], za[1].decoders[b])) for b in (0, 1)]
+    for r in rigs:
+        r.fwd()
+        r.capture(r.fwd, stream)
+    crossing = [k for k in range(1, len(path)) if zone_of[k] != zone_of[k - 1]]
+    lookahead = grid.pad * grid.size
+
+    def policy(prefetch):
+        st = {"cur": 0, "held": {0: 0, 1: 1 if prefetch else -1}, "queued": {}}
+
+        def before(k):
+            kk = max(k, 0)
+            zone = zone_of[kk]
+            cur = st["cur"]
+            nb = 1 - cur
+            if st["held"][cur] != zone:
+                if st["queued"].get(nb) != zone and st["held"][nb] != zone:
+                    each(lambda s: s.release(nb))
+                    each(lambda s: s.prefetch(zone, nb))
+                each(lambda s: s.acquire(nb))
+                each(lambda s: s.release(cur))
+                st["held"][nb] = zone
+                st["queued"].pop(nb, None)
+                st["cur"] = cur = nb
+                nb = 1 - cur
+            if prefetch:
+                ahead = grid.zone_of(0.0, path[kk] + lookahead)
+                if ahead not in (-1, zone) and st["queued"].get(nb) != ahead and st["held"][nb] != ahead:
+                    each(lambda s: s.prefetch(ahead, nb))
+                    st["queued"][nb] = ahead
+            return rigs[st["cur"]]
+        return before
+
+    # buffers back to zones 0 (current) and 1 before each drive
+    def reset(second):
+        with torch.cuda.stream(stream):
+            each(lambda s: s.release(0))
+            each(lambda s: s.prefetch(0, 0))
+            each(lambda s: s.acquire(0))
+            each(lambda s: s.release(1))
+            each(lambda s: s.prefetch(second, 1))
+            each(lambda s: s.acquire(1))
+        stream.synchronize()
+
+    reset(1)
+    lat = drive(None, policy(True))
+    out["prefetch"] = summary(lat, crossing)
+    swaps = []
+    for z in za:
+        for b in (0, 1):
+            swaps.append(z.stream.stats(b))
+    out["swap_last_uploads"] = swaps
+    reset(0)
+    lat = drive(None, policy(False))
+    out["sync"] = summary(lat, crossing)
+    out["crossings"] = len(crossing)
+    out["zone_bytes_both_kinds"] = int(swaps[0]["bytes"] + swaps[2]["bytes"])
+    out["h2d_GBps"] = float(np.mean([x["bytes"] / (x["upload_ms"] * 1e6) for x in swaps if x["upload_ms"] > 0]))
+    out["gather_ms"] = float(np.mean([x["gather_ms"] for x in swaps]))
+    for z in za:
+        z.close()
+    del rigs, za
+    return out
 
 
 def bench_train720p(steps, warmup):
@@ -526,8 +689,9 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration under rocprofv3) and exit")
-    ap.add_argument("--workloads", default="per_sensor,plain,frame1080,train720p,lidar,affinity",
-                    help="extra workloads (comma list of per_sensor, plain, frame1080, train720p, lidar, affinity)")
+    ap.add_argument("--workloads", default="per_sensor,plain,frame1080,train720p,lidar,affinity,chunk_stream",
+                    help="extra workloads (comma list of per_sensor, plain, frame1080, train720p, lidar, affinity, "
+                         "chunk_stream)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one MI355X only: the renderer runs one process per GPU and "
@@ -658,9 +822,12 @@ def main():
                 extra[w] = e
                 del rr
             else:
-                fn = {"frame1080": bench_frame1080, "train720p": bench_train720p, "lidar": bench_lidar,
-                      "affinity": bench_affinity}[w]
-                extra[w] = fn(args.steps, args.warmup)
+                if w == "chunk_stream":
+                    extra[w] = bench_chunk_stream(stream, tiles=tiles, seg=seg)
+                else:
+                    fn = {"frame1080": bench_frame1080, "train720p": bench_train720p, "lidar": bench_lidar,
+                          "affinity": bench_affinity}[w]
+                    extra[w] = fn(args.steps, args.warmup)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
     line["extra"] = extra

@@ -499,6 +499,54 @@ def config5(n_anchors=300_000, n_assets=20, asset_anchors=2_000):
     return cam, lid, sensors
 
 
+def translate_pose(pose: np.ndarray, c) -> np.ndarray:
+    """world->sensor pose of a sensor carried by a vehicle moved by c (world)."""
+    p = np.asarray(pose, np.float64).reshape(3, 4)
+    t = p[:, 3] - p[:, :3] @ np.asarray(c, np.float64)
+    return np.concatenate([p[:, :3], t[:, None]], axis=1).astype(F32)
+
+
+def zone_mlps(seed: int, n_zones: int, sensor_kind="pinhole", k=K_OFFSETS) -> list:
+    """One MLP per zone (every zone of a large scene is reconstructed on its own)."""
+    rng = _rng(seed)
+    n_attr = ATTRS_CAMERA if sensor_kind == "pinhole" else ATTRS_LIDAR
+    return [mlp_params(rng, k * n_attr) for _ in range(n_zones)]
+
+
+def static_and_actors(sc: AnchorScene):
+    """Split an anchor scene into its static group (group 0) and its actor groups.
+
+    Returns (static dict(xyz, scaling, offsets, feat), actors dict or None), the
+    arrays as stored in the scene (feat as bf16 bits).
+    """
+    s = int(sc.group_offsets[1])
+    static = dict(xyz=np.ascontiguousarray(sc.xyz[:, :s]), scaling=np.ascontiguousarray(sc.scaling[:s]),
+                  offsets=np.ascontiguousarray(sc.offsets[:, :, :s]), feat=np.ascontiguousarray(sc.feat_bf16[:s]))
+    if len(sc.group_offsets) <= 2:
+        return static, None
+    actors = dict(xyz=np.ascontiguousarray(sc.xyz[:, s:]), scaling=np.ascontiguousarray(sc.scaling[s:]),
+                  offsets=np.ascontiguousarray(sc.offsets[:, :, s:]), feat=np.ascontiguousarray(sc.feat_bf16[s:]),
+                  group_offsets=np.asarray(sc.group_offsets[1:], np.int64) - s, mlps=list(sc.mlps[1:]),
+                  group_poses=sc.group_poses[1:])
+    return static, actors
+
+
+def zone_scene(sc: AnchorScene, anchors, mlp: dict) -> AnchorScene:
+    """The anchor scene a zone renders: the zone's static anchors (ascending ids)
+    with the zone's own MLP, followed by every actor group of `sc`."""
+    a = np.asarray(anchors, np.int64)
+    s = int(sc.group_offsets[1])
+    xyz = np.concatenate([sc.xyz[:, a], sc.xyz[:, s:]], 1)
+    scaling = np.concatenate([sc.scaling[a], sc.scaling[s:]])
+    offsets = np.concatenate([sc.offsets[:, :, a], sc.offsets[:, :, s:]], 2)
+    feat = np.concatenate([sc.feat_bf16[a], sc.feat_bf16[s:]], 0)
+    goff = np.concatenate([[0], a.size + np.asarray(sc.group_offsets[1:], np.int64) - s]).astype(np.int32)
+    return AnchorScene(xyz=np.ascontiguousarray(xyz), scaling=np.ascontiguousarray(scaling),
+                       offsets=np.ascontiguousarray(offsets), feat_bf16=np.ascontiguousarray(feat),
+                       group_offsets=goff, group_poses=sc.group_poses.copy(), mlps=[mlp] + list(sc.mlps[1:]),
+                       sensor_kind=sc.sensor_kind)
+
+
 def target_features(scene: AnchorScene, seed: int, std=0.1) -> np.ndarray:
     """Perturbed anchor features (bf16 bits) for the training-step target render."""
     rng = _rng(seed)

@@ -450,6 +450,131 @@ gs_status gs_decode_backward_noalloc(const gs_anchor_set* anchors, const float* 
 gs_status gs_affinity(const uint16_t* xt, const uint16_t* xs, int32_t batch, int32_t p, int32_t q, int32_t d,
                       float* out, hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Scene zones and double-buffered swap-in (Sec. III-A, large-scale scenes:
+ * the scene is cut by ground-plane position into square zones, 40 m on a
+ * side in the paper, each widened on every side by a fixed fraction of its
+ * side, 25 % in the paper; at render time two buffers are used, and the
+ * Gaussians of the zone the vehicle is about to enter are brought into one
+ * while the other is rendered).
+ *
+ * Zone (i, j) of a grid covers, in ground coordinates (a, b) =
+ * (x[axis[0]], x[axis[1]]) converted to double,
+ *   origin[0] + (i - pad) * size <= a < origin[0] + ((i + 1) + pad) * size
+ *   origin[1] + (j - pad) * size <= b < origin[1] + ((j + 1) + pad) * size,
+ * each bound evaluated in IEEE double exactly as written (i, j converted to
+ * double).  Zone id = j * nx + i.  With pad > 0 neighbouring zones overlap,
+ * so a point belongs to up to four zones; points outside every zone (or
+ * with a NaN coordinate) belong to none.
+ * ------------------------------------------------------------------- */
+typedef struct gs_zone_grid {
+  int32_t axis[2];   /* world axes spanning the ground plane (0 x, 1 y, 2 z), distinct */
+  double origin[2];  /* ground coordinates of the low corner of zone (0, 0)            */
+  double size;       /* zone side, finite and > 0 (metres)                              */
+  double pad;        /* padding on each side as a fraction of `size`, finite, in [0, 1] */
+  int32_t nx, ny;    /* zones along axis[0] and axis[1], >= 1, nx * ny <= 2^20          */
+} gs_zone_grid;
+
+/* Lists the anchors (points) of every zone.  xyz: host [3][n] FP32.
+ * zone_offsets: host [nx*ny + 1], always written (CSR offsets).  index: host
+ * [cap]; the anchors of zone z are index[zone_offsets[z] ..
+ * zone_offsets[z+1]) in ascending order.  *total: number of (zone, anchor)
+ * memberships, always written.  index may be NULL with cap = 0 to query
+ * *total.  Errors: GS_ERR_INVALID_ARG (bad grid, n outside [0, 2^32 - 1],
+ * null pointers); GS_ERR_CAPACITY when *total > cap (index is then left
+ * unspecified).  Host only: no HIP call is made. */
+gs_status gs_zone_partition(const gs_zone_grid* grid, const float* xyz, int64_t n, uint32_t* zone_offsets,
+                            uint32_t* index, int64_t cap, int64_t* total);
+
+/* One array that moves with a zone.
+ *   per_zone = 0: an anchor attribute.  host is [rows][host_stride]
+ *     elements of elem_bytes bytes over every anchor of the scene; an upload
+ *     of zone z into buffer b writes, for every row r and k < capacity,
+ *       device[b][r * device_stride + k] = host[r * host_stride + L[k]]
+ *     for the zone's anchor list L (k < |L|), and `fill` (elem_bytes bytes;
+ *     NULL: zero bytes) for |L| <= k < capacity.  Elements of a device row
+ *     at or beyond `capacity` (e.g. resident actors) are not touched.
+ *   per_zone = 1: a per-zone block (e.g. the zone's MLP weights).  host is
+ *     [n_zones][elem_bytes] bytes; an upload writes the zone's block to
+ *     device[b] (rows must be 1; strides and fill unused).
+ * host is read by the swap-in thread while the stream exists and must not
+ * change meanwhile; device[0] and device[1] are device memory of the
+ * stream's device. */
+typedef struct gs_zone_field {
+  const void* host;
+  int64_t host_stride;     /* elements per host row (per_zone = 0)          */
+  void* device[2];         /* destination in buffer 0 and buffer 1          */
+  int64_t device_stride;   /* elements per device row, >= capacity           */
+  int32_t rows;            /* >= 1                                           */
+  int32_t elem_bytes;      /* 1..65536                                        */
+  int32_t per_zone;        /* 0 or 1                                         */
+  const void* fill;        /* host, elem_bytes bytes, or NULL                 */
+} gs_zone_field;
+
+typedef struct gs_zone_stream_desc {
+  int32_t n_zones;               /* >= 1                                         */
+  const uint32_t* zone_offsets;  /* host [n_zones + 1] (gs_zone_partition)       */
+  const uint32_t* index;         /* host [zone_offsets[n_zones]]                 */
+  int64_t capacity;              /* anchors per buffer, >= the largest zone       */
+  int64_t n_anchors;             /* anchors of the scene (every index below it)  */
+  int32_t n_fields;              /* 1..64                                        */
+  const gs_zone_field* fields;   /* host [n_fields]                              */
+  int32_t threads;               /* host threads that gather one zone, 1..64      */
+} gs_zone_stream_desc;
+
+typedef struct gs_zone_stream gs_zone_stream; /* opaque, owned by the library */
+
+/* The calls on one zone stream are made from one host thread (the swap-in
+ * thread is the library's own). */
+
+/* Creates a swap-in stream on the current device: pinned host staging for
+ * both buffers (the bytes of one zone at full capacity, per buffer), a copy
+ * stream of its own, and one swap-in thread.  The descriptor's arrays are
+ * copied; `host` arrays are not.  Errors: GS_ERR_INVALID_ARG (bad sizes or
+ * pointers, an index at or beyond n_anchors, capacity below a zone's
+ * count), GS_ERR_HIP. */
+gs_status gs_zone_stream_create(const gs_zone_stream_desc* desc, gs_zone_stream** out);
+
+/* Queues an upload of `zone` into `buffer` (0 or 1) and returns at once.  The
+ * swap-in thread waits until the previous upload from that buffer's staging
+ * has finished, gathers the zone into the staging, and enqueues the copies
+ * on the copy stream behind the last gs_zone_stream_release of the buffer.
+ * Uploads are processed in the order they are queued. */
+gs_status gs_zone_stream_prefetch(gs_zone_stream* zs, int32_t zone, int32_t buffer);
+
+/* Waits on the host until every upload queued into `buffer` has been
+ * enqueued, then makes `stream` wait on the device for the last of them:
+ * work enqueued on `stream` afterwards sees the buffer's new contents.
+ * Writes the zone the buffer holds and its anchor count (NULL to skip).
+ * GS_ERR_INVALID_ARG if nothing was ever queued into the buffer; GS_ERR_HIP
+ * if the swap-in thread met a HIP error (sticky). */
+gs_status gs_zone_stream_acquire(gs_zone_stream* zs, int32_t buffer, hipStream_t stream, int32_t* zone,
+                                 int64_t* count);
+
+/* Marks the end of the reads of `buffer` by the work enqueued on `stream` so
+ * far: the next upload into the buffer starts on the device only after that
+ * work.  Call it after enqueuing the last use of the buffer's contents and
+ * before queueing an upload into it.  GS_ERR_INVALID_ARG if an upload was
+ * queued into the buffer since its last acquire (that upload could
+ * otherwise be ordered behind work that waits for a later upload). */
+gs_status gs_zone_stream_release(gs_zone_stream* zs, int32_t buffer, hipStream_t stream);
+
+typedef struct gs_zone_swap_stats {
+  int32_t zone;       /* zone of the last upload into the buffer (-1: none)   */
+  int64_t count;      /* its anchors                                          */
+  int64_t bytes;      /* bytes copied host to device                          */
+  double gather_ms;   /* host time of the gather into pinned staging          */
+  double upload_ms;   /* device time of the copies on the copy stream         */
+} gs_zone_swap_stats;
+
+/* Statistics of the last upload into `buffer`; waits for that upload to
+ * complete. */
+gs_status gs_zone_stream_stats(gs_zone_stream* zs, int32_t buffer, gs_zone_swap_stats* out);
+
+/* Waits for queued uploads, stops the swap-in thread and frees the staging,
+ * stream and events.  NULL is a no-op. */
+void gs_zone_stream_destroy(gs_zone_stream* zs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,26 @@ class AnchorGrads(ctypes.Structure):
                 ("w1", c_void_p), ("b1", c_void_p), ("w2", c_void_p), ("b2", c_void_p)]
 
 
+class ZoneGrid(ctypes.Structure):
+    _fields_ = [("axis", c_int32 * 2), ("origin", c_double * 2), ("size", c_double), ("pad", c_double),
+                ("nx", c_int32), ("ny", c_int32)]
+
+
+class ZoneField(ctypes.Structure):
+    _fields_ = [("host", c_void_p), ("host_stride", c_int64), ("device", c_void_p * 2), ("device_stride", c_int64),
+                ("rows", c_int32), ("elem_bytes", c_int32), ("per_zone", c_int32), ("fill", c_void_p)]
+
+
+class ZoneStreamDesc(ctypes.Structure):
+    _fields_ = [("n_zones", c_int32), ("zone_offsets", c_void_p), ("index", c_void_p), ("capacity", c_int64),
+                ("n_anchors", c_int64), ("n_fields", c_int32), ("fields", POINTER(ZoneField)), ("threads", c_int32)]
+
+
+class ZoneSwapStats(ctypes.Structure):
+    _fields_ = [("zone", c_int32), ("count", c_int64), ("bytes", c_int64), ("gather_ms", c_double),
+                ("upload_ms", c_double)]
+
+
 # (name, restype, argtypes) of every exported function of include/gs2d.h
 SIGNATURES = [
     ("gs_version", c_char_p, []),
@@ -121,6 +141,14 @@ SIGNATURES = [
     ("gs_decode_backward_noalloc", c_int32, [POINTER(AnchorSet), c_void_p, c_void_p, POINTER(Decoded),
                                              POINTER(AnchorGrads), c_void_p]),
     ("gs_affinity", c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    ("gs_zone_partition", c_int32, [POINTER(ZoneGrid), c_void_p, c_int64, c_void_p, c_void_p, c_int64,
+                                    POINTER(c_int64)]),
+    ("gs_zone_stream_create", c_int32, [POINTER(ZoneStreamDesc), POINTER(c_void_p)]),
+    ("gs_zone_stream_prefetch", c_int32, [c_void_p, c_int32, c_int32]),
+    ("gs_zone_stream_acquire", c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_int32), POINTER(c_int64)]),
+    ("gs_zone_stream_release", c_int32, [c_void_p, c_int32, c_void_p]),
+    ("gs_zone_stream_stats", c_int32, [c_void_p, c_int32, POINTER(ZoneSwapStats)]),
+    ("gs_zone_stream_destroy", None, [c_void_p]),
 ]
 
 _lib = None
