@@ -93,9 +93,13 @@ def measured_traffic(path=TRAFFIC_FILE):
 
 
 def _timed(fn, steps, warmup, stream=None):
-    """Mean ms per call of fn over `steps` calls after `warmup`, HIP events on `stream` (default: current)."""
+    """Mean ms per call of fn over `steps` calls after `warmup`, HIP events on `stream` (default: current).
+
+    Work queued earlier on other streams is finished first: a plan's calls must be ordered on one
+    stream (they share its workspace), and fn may use a plan last used on another stream."""
     import torch
     stream = stream or torch.cuda.current_stream()
+    torch.cuda.synchronize()
     with torch.cuda.stream(stream):
         for _ in range(warmup):
             fn()
@@ -213,8 +217,10 @@ class RigStep:
                                   scratch=self.scratch[j])
 
     def capture(self, fn, stream):
-        """Capture fn (enqueue-only, allocation-free) as this plan's step graph on `stream`."""
+        """Capture fn (enqueue-only, allocation-free) as this plan's step graph on `stream` (after the
+        work queued on every other stream: the plan's calls must be ordered on one stream)."""
         import torch
+        torch.cuda.synchronize()
         with torch.cuda.stream(stream):
             fn()  # warm: lazy kernel loading happens outside the capture
             stream.synchronize()
@@ -390,8 +396,7 @@ def bench_chunk_stream(stream, tiles=None, seg=0, step_m=1.5, length_m=150.0, wa
            "zones": grid.n_zones, "frames": int(len(path))}
     # the whole corridor resident
     whole = RigStep(cam, lid, base, dev, batched=True, tiles=tiles, segment_pairs=seg, train=False)
-    whole.fwd()
-    whole.capture(whole.fwd, stream)
+    whole.capture(whole.fwd, stream)  # (after a warm-up forward on the same stream)
     out["whole"] = summary(drive(whole))
     out["surfels_per_sensor_whole"] = whole.shapes[0].n_splats
     del whole
@@ -421,8 +426,7 @@ def bench_chunk_stream(stream, tiles=None, seg=0, step_m=1.5, length_m=150.0, wa
     rigs = [RigStep(cam, lid, base, dev, batched=True, tiles=tiles, segment_pairs=seg, train=False,
                     decoders=(za[0].decoders[b], za[1].decoders[b])) for b in (0, 1)]
     for r in rigs:
-        r.fwd()
-        r.capture(r.fwd, stream)
+        r.capture(r.fwd, stream)  # on the stream that waited for the uploads
     crossing = [k for k in range(1, len(path)) if zone_of[k] != zone_of[k - 1]]
     lookahead = grid.pad * grid.size
 
@@ -687,6 +691,9 @@ def main():
     ap.add_argument("--eager-only", action="store_true",
                     help="time only eager forward steps of the batched plan, then exit (for profilers)")
     ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--profile-workload", default="", metavar="NAME",
+                    help="run only the extra workload NAME (frame1080, train720p, lidar, affinity) and print its "
+                         "JSON (for profilers)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (HBM counter calibration under rocprofv3) and exit")
     ap.add_argument("--workloads", default="per_sensor,plain,frame1080,train720p,lidar,affinity,chunk_stream",
@@ -708,6 +715,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "dispatches": 4}), flush=True)
+        return
+
+    if args.profile_workload:
+        fn = {"frame1080": bench_frame1080, "train720p": bench_train720p, "lidar": bench_lidar,
+              "affinity": bench_affinity}[args.profile_workload]
+        print(json.dumps({args.profile_workload: fn(args.steps, args.warmup)}), flush=True)
         return
 
     from gen import scenes as S
@@ -733,11 +746,34 @@ def main():
         res = at.autotune(probe.shapes, probe.ds, sensors, probe.sp, gps, batched=True, segments=[1024, 2048, 4096],
                           pair_capacity=probe.shapes[0].n_splats * 6, steps=3, warmup=1)
         tiles, seg = res.tiles, res.segment_pairs
-        extra["autotune"] = {"tiles": [list(t) for t in tiles], "segment_pairs": seg,
-                             "seconds": time.perf_counter() - t0, "from_cache": res.from_cache}
         del probe
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+        # the segment length again, on the batched step itself (the per-sensor sums above miss
+        # how the sensors share the queue), cached next to the per-sensor timings
+        cache = at.TuneCache(at.default_cache_path())
+        arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
+        key = "|".join([arch, "rig-batched"] + [f"{s['kind']}{s['width']}x{s['height']}@{t[0]}x{t[1]}"
+                                                for s, t in zip(sensors, tiles)] + [f"n{at.n_bucket(cam_sc.n_anchors)}"])
+        segs = [1024, 2048, 4096]
+        hit = cache.get(key)
+        if hit and all(str(g) in hit["ms"] for g in segs):
+            seg_ms = {g: hit["ms"][str(g)] for g in segs}
+        else:
+            seg_ms = {}
+            for g in segs:
+                rr = RigStep(cam_sc, lid_sc, sensors, dev, batched=True, tiles=tiles, segment_pairs=g, train=False)
+                rr.fwd()
+                seg_ms[g] = _timed(rr.fwd, 5, 2, stream)
+                del rr
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+            cache.put(key, {"ms": {str(g): v for g, v in seg_ms.items()}})
+            cache.save()
+        seg = at.pick(seg_ms, at.PREFER_SEG)
+        extra["autotune"] = {"tiles": [list(t) for t in tiles], "segment_pairs": seg,
+                             "batched_segment_ms": {str(g): v for g, v in seg_ms.items()},
+                             "seconds": time.perf_counter() - t0, "from_cache": res.from_cache}
 
     log("batched step: capture forward")
     rig = RigStep(cam_sc, lid_sc, sensors, dev, batched=True, tiles=tiles, segment_pairs=seg)

@@ -12,6 +12,12 @@ tile shape and per plan the L with the smallest summed time.  Results are
 cached by (GPU architecture, sensor kind, W x H, surfel-count bucket) in a
 JSON file, so that later plans for the same class of sensor skip the timing.
 Batched plans need 256-ray tiles, so only those shapes are tried for them.
+
+Choices keep a preferred candidate (the kind's usual tile shape, L = 2048)
+unless another is faster by more than a margin (3 %): candidates within
+timing noise of each other would otherwise flip from run to run, and a
+plan's counters and profiles would describe a different configuration than
+its timed run.
 """
 from __future__ import annotations
 
@@ -27,6 +33,20 @@ from .render import Renderer
 TILES_ANY = [(8, 8), (16, 8), (8, 16), (16, 16), (32, 8), (8, 32), (32, 16), (16, 32), (64, 8)]
 TILES_256 = [(16, 16), (32, 8), (8, 32)]
 SEGMENTS = [256, 512, 1024, 2048, 4096]
+# preferred candidates (kept unless another is faster by more than MARGIN)
+PREFER_TILE = {"pinhole": (32, 8), "cylindrical": (32, 8), "lidar": (16, 16)}
+PREFER_TILE_SINGLE = {"pinhole": (32, 8), "cylindrical": (32, 8), "lidar": (16, 8)}
+PREFER_SEG = 2048
+MARGIN = 0.03
+
+
+def pick(ms: dict, prefer, margin: float = MARGIN):
+    """The key of the smallest value of ms, except that `prefer` (a key of ms)
+    is kept unless the smallest is below it by more than `margin`."""
+    best = min(ms, key=lambda k: ms[k])
+    if prefer is not None and prefer in ms and ms[prefer] <= (1.0 + margin) * ms[best]:
+        return prefer
+    return best
 
 
 def default_cache_path() -> str:
@@ -112,7 +132,7 @@ def _time_forward(shape, scene, sensor, pose, group_poses, tile, seg, opts, pair
 
 def autotune(shapes, scenes, sensors, sensor_poses, group_poses_per_sensor, *, batched=False, opts=None,
              tiles=None, segments=None, pair_capacity=0, steps=5, warmup=2, cache_path="default",
-             device="cuda") -> TuneResult:
+             device="cuda", margin=MARGIN) -> TuneResult:
     """Choose tile shapes (per sensor) and the segment length (per plan).
 
     shapes / scenes: per sensor, the SceneShape and the scene tensors it renders;
@@ -151,12 +171,11 @@ def autotune(shapes, scenes, sensors, sensor_poses, group_poses_per_sensor, *, b
         per_sensor.append(ms)
     cache.save()
     # plan-wide segment length: smallest sum over sensors of each sensor's best tile at that L
-    best_seg, best_total = None, math.inf
-    for g in segs:
-        total = sum(min(ms[_fmt(t, g)] for t in cands) for ms in per_sensor)
-        if total < best_total:
-            best_seg, best_total = g, total
+    totals = {g: sum(min(ms[_fmt(t, g)] for t in cands) for ms in per_sensor) for g in segs}
+    best_seg = pick(totals, PREFER_SEG, margin)
+    prefer = PREFER_TILE if batched else PREFER_TILE_SINGLE
     chosen = []
-    for ms in per_sensor:
-        chosen.append(min(cands, key=lambda t: ms[_fmt(t, best_seg)]))
+    for s, ms in zip(sensors, per_sensor):
+        at_seg = {t: ms[_fmt(t, best_seg)] for t in cands}
+        chosen.append(pick(at_seg, prefer.get(s["kind"]), margin))
     return TuneResult(tiles=chosen, segment_pairs=best_seg, timings=timings, from_cache=from_cache)

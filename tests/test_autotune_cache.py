@@ -27,3 +27,12 @@ def test_corrupt_cache_is_ignored(tmp_path):
     p = tmp_path / "c.json"
     p.write_text("{not json")
     assert at.TuneCache(str(p)).data == {}
+
+
+def test_pick_keeps_the_preferred_candidate_within_the_margin():
+    ms = {"a": 1.00, "b": 1.02, "c": 1.10}
+    assert at.pick(ms, "b", 0.03) == "b"      # within 3 % of the best: kept
+    assert at.pick(ms, "c", 0.03) == "a"      # 10 % slower: the best wins
+    assert at.pick(ms, None, 0.03) == "a"
+    assert at.pick(ms, "zz", 0.03) == "a"     # not a candidate
+    assert at.pick({2048: 5.0, 1024: 4.99}, 2048) == 2048
