@@ -63,7 +63,7 @@ struct RecordArrays {
          o_pval1 = 0, o_ranges = 0, o_status = 0, o_gacc = 0;
   // compositing work queue
   size_t o_pslot = 0, o_arrive = 0, o_qhdr = 0, o_sbsum = 0, o_qkey0 = 0, o_qkey1 = 0, o_qval0 = 0, o_qval1 = 0,
-         o_items = 0, o_part = 0, part_stride = 0, o_flag = 0, o_walk = 0, o_qcnt = 0, o_mlist = 0;
+         o_items = 0, o_part = 0, part_stride = 0, o_flag = 0, o_walk = 0, o_qcnt = 0;
   uint32_t n_rec = 0, cap = 0;
   uint32_t status_words = kStWords;  // words cleared at the start of a frame
   uint32_t seg_len = 0, cap_items = 0, pslot_cap = 0;
@@ -131,8 +131,7 @@ struct RecordArrays {
     part_stride = (size_t)pslot_cap * (size_t)rays;
     o_part = L.take(11 * part_stride * 4);
     o_flag = L.take((size_t)pslot_cap * 4);
-    o_walk = L.take((size_t)pslot_cap * 8);
-    o_mlist = L.take((size_t)pslot_cap * 8);
+    o_walk = L.take((size_t)pslot_cap * 2 * 8);
   }
 };
 
@@ -426,7 +425,7 @@ QueueArgs queue_args(const gs_plan* p, const RecordArrays& R, size_t rbase, int 
   q.hdr = reinterpret_cast<uint32_t*>(b + R.o_qhdr);
   q.slot_flag = reinterpret_cast<uint32_t*>(b + R.o_flag);
   q.walk = reinterpret_cast<unsigned long long*>(b + R.o_walk);
-  q.mlist = reinterpret_cast<unsigned long long*>(b + R.o_mlist);
+  q.walk_cap = 2 * R.pslot_cap;
   q.cap_items = R.cap_items;
   q.counter = reinterpret_cast<uint32_t*>(b + R.o_qcnt);
   q.arrive = reinterpret_cast<uint32_t*>(b + R.o_arrive);
@@ -459,7 +458,6 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       ev = stage_begin(p, st);
       QueueArgs q = queue_args(p, s.R, s.base, (int)si, (int)si + 1, workspace, outputs, nullptr, nullptr);
       launch_blend_queue(q, s.R.rays, s.R.kinds, s.R.grid_fwd, false, p->count_pairs, st);
-      launch_median(q, s.R.rays, s.R.kinds, s.R.grid_fwd, st);
       stage_end(p, st, GS_STAGE_BLEND, ev);
     }
     return;
@@ -489,7 +487,6 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   ev = stage_begin(p, st);
   QueueArgs q = queue_args(p, p->G, p->gbase, 0, (int)p->sensors.size(), workspace, outputs, nullptr, nullptr);
   launch_blend_queue(q, p->G.rays, p->G.kinds, p->G.grid_fwd, false, p->count_pairs, st);
-  launch_median(q, p->G.rays, p->G.kinds, p->G.grid_fwd, st);
   stage_end(p, st, GS_STAGE_BLEND, ev);
 }
 

@@ -50,6 +50,11 @@ constexpr float kInv2Ln2 = 0.7213475204444817f;  // 1 / (2 ln 2)
 // a slot marked kWalk in kPartLast holds the ray's last pair so far in
 // kPartCount.
 enum { kPartT = 8, kPartLast = 9, kPartCount = 10 };
+// A merge marks a ray whose transmittance falls below 1/2 inside a later
+// segment s it takes whole with mpair = kCross | s, and lists (tile, s |
+// kMedianEntry) on the walk list; the entry's replay finds the crossing pair.
+constexpr uint32_t kCross = 0x80000000u;
+constexpr uint32_t kMedianEntry = 0x80000000u;
 constexpr uint32_t kWalk = 0xFFFFFFFFu;  // never a (last | stop bit) value: pair ids < 2^31 - 1
 
 
@@ -1568,25 +1573,20 @@ __device__ __forceinline__ bool accept_segment(float T, float Ts, uint32_t ls, f
   return !(ls >> 31) && (Ts == 1.0f || T * Ts >= T_accept);
 }
 
-// Appends (tile gt, segment sg) to the median pass's list.
-__device__ __forceinline__ void list_median(const QueueArgs& q, uint32_t gt, uint32_t sg) {
-  const uint32_t w = atomicAdd(q.hdr + 7, 1u);
-  if (w < q.pslot_cap) q.mlist[w] = ((unsigned long long)gt << 32) | sg;
-}
-
 // Front-to-back merge of a split tile's segment partials from slot sg0 with
 // the ray's running state.  Every reached slot keeps the segment's incoming
 // (T, prefix) for the adjoint.  Returns the first segment that cannot be
 // taken whole (the ray's stop lies in it, or may), or n_seg when every
 // remaining segment was taken.  With mbits (the tile's merge), a later
 // segment (s >= 1) taken whole in which T falls from at least 1/2 to below
-// it is marked for the median pass, which finds the crossing: bit s of the
-// LDS mask mbits[0..8) when s < 256, else mbits[8] (every segment from 256 on
-// is then listed; the pass itself tests which rays cross where).
+// it gets the ray's median crossing: s goes to *mark (the ray's LDS entry)
+// and the segment to the LDS mask, bit s of mbits[0..8) when s < 256, else
+// mbits[8] (every segment from 256 on is then listed; the replay takes only
+// the rays marked for it).
 template <int NT, class Ray>
 __device__ uint32_t merge_from(uint32_t n_seg, uint32_t pbase, uint32_t sg0, float* part, size_t ps,
                                float T_accept, float& T, float* acc, uint32_t& last, uint32_t& n_eval,
-                               uint32_t& n_contrib, uint32_t* mbits) {
+                               uint32_t& n_contrib, uint32_t* mbits, uint32_t* mark) {
 #pragma clang fp contract(off)
   constexpr int C = Ray::C;
   uint32_t* pu = reinterpret_cast<uint32_t*>(part);
@@ -1606,8 +1606,10 @@ __device__ uint32_t merge_from(uint32_t n_seg, uint32_t pbase, uint32_t sg0, flo
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = fmaf(T, as[c], acc[c]);
     const float Tn = T * Ts;
-    if (mbits && sg > 0 && T >= 0.5f && Tn < 0.5f)
+    if (mbits && sg > 0 && T >= 0.5f && Tn < 0.5f) {
       atomicOr(&mbits[min(sg >> 5, 8u)], sg < 256u ? 1u << (sg & 31u) : 1u);
+      *mark = sg;
+    }
     T = Tn;
     if (ls) last = ls;
     n_eval += cnt & 0xFFFFu;
@@ -1638,10 +1640,13 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
   uint32_t last = rg.x;
   bool wr = false;
   if (threadIdx.x < 9) sh.mbits[threadIdx.x] = 0u;
+  sh.mp[threadIdx.x] = kNoPair;  // this ray's crossing segment, if a later one
   __syncthreads();
   if (ray.inside) {
     const uint32_t sg = merge_from<NT, Ray>(n_seg, pbase, 0, q.part, q.part_stride, q.T_accept, T, acc, last, n_eval,
-                                            n_contrib, sh.mbits);
+                                            n_contrib, sh.mbits, &sh.mp[threadIdx.x]);
+    const uint32_t ms = sh.mp[threadIdx.x];
+    if (ms != kNoPair) a.mpair[ray.pix(a)] = kCross | ms;
     if (sg == n_seg) {
       wr = true;
     } else {
@@ -1654,23 +1659,24 @@ __device__ void merge_tile(const QueueArgs& q, const TileArgs& a, const Ray& ray
       marked = sg + 1;
     }
   }
-  __syncthreads();
-  const uint32_t n_list = sh.mbits[8] ? n_seg : min(n_seg, 256u);
-  for (uint32_t k = threadIdx.x; k < n_list; k += NT)
-    if (k < 256u ? (sh.mbits[k >> 5] >> (k & 31u)) & 1u : 1u) list_median(q, gt, k);
   write_tile<NT>(a, ray, wr, T, acc, last, false, 0.0f, kNoPair, sh);
   count_wg(sh, si, n_eval, n_contrib, n64);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
+  auto list = [&](uint32_t seg) {
+    const uint32_t w = atomicAdd(q.hdr + 3, 1u);
+    if (w < q.walk_cap)
+      __hip_atomic_store(q.walk + w, ((unsigned long long)gt << 32) | seg, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  };
   if (marked) {
     const uint32_t slot = pbase + marked - 1;
-    if (atomicCAS(q.slot_flag + slot, 0u, 1u) == 0u) {
-      const uint32_t w = atomicAdd(q.hdr + 3, 1u);
-      if (w < q.pslot_cap)
-        __hip_atomic_store(q.walk + w, ((unsigned long long)gt << 32) | (marked - 1), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (atomicCAS(q.slot_flag + slot, 0u, 1u) == 0u) list(marked - 1);
   }
+  // median entries: one per segment holding some ray's crossing
+  const uint32_t n_list = sh.mbits[8] ? n_seg : min(n_seg, 256u);
+  for (uint32_t k = threadIdx.x; k < n_list; k += NT)
+    if (k < 256u ? (sh.mbits[k >> 5] >> (k & 31u)) & 1u : 1u) list(k | kMedianEntry);
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_fetch_add(q.hdr + 5, 0xFFFFFFFFu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1870,7 +1876,7 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
       // its median crossing (nothing to mark)
       need = done ? kNone
                   : merge_from<NT, Ray>(n_seg, pbase, cur + 1, part, ps, q.T_accept, T, acc, last, n_eval, n_contrib,
-                                        nullptr);
+                                        nullptr, nullptr);
       if (need == n_seg) need = kNone;
       if (need == kNone) ray.write(a, T, acc, last);
     }
@@ -1920,6 +1926,71 @@ __device__ void fwd_item(const QueueArgs& q, const TileArgs& a, int si, int tile
   if (sh.u[1]) merge_tile<NT>(q, a, ray, gt, rg, n_seg, pbase, si, sh);  // partials are read device-coherently
 }
 
+// Median depth (2DGS: the depth where the accumulated opacity reaches 1/2)
+// of the rays whose transmittance falls below 1/2 inside a later segment
+// (s >= 1) of a split tile, which the merge took whole (whole tiles, first
+// segments and walks composite from the ray's true transmittance and record
+// the crossing themselves).  The merge marked those rays (mpair = kCross | s)
+// and listed the segment; the rays replay its pairs from the incoming
+// transmittance the merge left in the slot and take the depth of the pair
+// after which it falls below 1/2.  Should the replay's rounding not cross
+// inside the segment, its last composited pair stands for it.  The crossing
+// comes before any stop (T_min < 1/2), so the replay needs no stop rule.
+// Runs as a walk-list entry: slot state and marks are read device-coherently.
+template <int NT, class Ray>
+__device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
+                            BlendShared<NT>& sh) {
+#pragma clang fp contract(off)
+  const uint32_t len = rg.y - rg.x, L = q.seg_len;
+  const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
+  if (n_seg == 1 || sg == 0 || sg >= n_seg) return;  // unreachable: merges list later segments only
+  const uint32_t pbase = q.pslot_base[gt];
+  if (pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
+  const Ray ray(a, tile);
+  ray.prepare(a, sh);
+  const uint32_t b0 = rg.x + sg * L;
+  const uint32_t b1 = min(b0 + L, rg.y);
+  const int t = threadIdx.x;
+  const size_t HW = (size_t)a.S.W * a.S.H, p = ray.inside ? ray.pix(a) : 0;
+  const bool mine = ray.inside && ld_coh(a.mpair + p) == (kCross | sg);
+  float T = mine ? ld_coh(q.part + kPartT * q.part_stride + (size_t)(pbase + sg) * NT + t) : 1.0f;
+  bool active = mine;
+  float med = 0.0f, zl = 0.0f;
+  uint32_t mp = kNoPair, pl = kNoPair, n64 = 0;
+  const int w = t >> 6;
+  for (uint32_t base = b0; base < b1; base += NT) {
+    if (t == 0) sh.u[2] = 0u;
+    if (__syncthreads_count(active) == 0) break;
+    stage_batch<NT>(a, ray, base, b1, sh);
+    const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
+    for (int c = 0; c < nch; ++c) {
+      uint64_t m = uniform_mask(&sh.mask[c][w]);
+      const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(c) << 6;
+      while (m && __ballot(active) != 0) {
+        const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        PairEval e;
+        const bool hit = ray.eval(a, sh.rec[j], sh.id[j], sh.f64, e, n64) && active;
+        if (hit) {
+          const float Tn = T * (1.0f - e.alpha);
+          zl = e.z;
+          pl = base + j;
+          if (Tn < 0.5f) {
+            med = e.z;
+            mp = base + j;
+            active = false;
+          }
+          T = Tn;
+        }
+      }
+    }
+  }
+  if (mine) {
+    a.out[Ray::kMedian * HW + p] = mp != kNoPair ? med : zl;
+    a.mpair[p] = mp != kNoPair ? mp : pl;
+  }
+}
+
 // Sensor kinds a launch may meet (bit 0 camera, bit 1 LiDAR): single-kind
 // launches leave the other kind's code and registers out.
 constexpr int kKindCam = 1, kKindLidar = 2, kKindBoth = 3, kKindCyl = 4;
@@ -1960,7 +2031,7 @@ __device__ bool take_walk(const QueueArgs& q, uint32_t idx, uint32_t* u) {
 __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& drained, uint32_t xcc,
                                 uint32_t n_items, bool walks, uint32_t* u) {
   if (walks) {
-    const uint32_t cnt = min(load_agent(q.hdr + 3), q.pslot_cap);
+    const uint32_t cnt = min(load_agent(q.hdr + 3), q.walk_cap);
     const uint32_t pop = load_agent(q.hdr + 4);
     if (pop < cnt && atomicCAS(q.hdr + 4, pop, pop + 1) == pop) {
       if (take_walk(q, pop, u)) return kActWalk;
@@ -1986,7 +2057,7 @@ __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& d
   if (!walks) return kActExit;
   const uint32_t ticket = atomicAdd(q.hdr + 4, 1u);
   for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
-    if (ticket < min(load_agent(q.hdr + 3), q.pslot_cap)) {
+    if (ticket < min(load_agent(q.hdr + 3), q.walk_cap)) {
       if (take_walk(q, ticket, u)) return kActWalk;
       break;
     }
@@ -1994,7 +2065,7 @@ __device__ uint32_t next_action(const QueueArgs& q, bool& main_left, uint32_t& d
     // its merge listed is counted) and the ticket is past the list: done
     if (load_agent(q.hdr + 5) == 0 &&
         __hip_atomic_load(q.hdr + 5, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-        ticket >= min(load_agent(q.hdr + 3), q.pslot_cap))
+        ticket >= min(load_agent(q.hdr + 3), q.walk_cap))
       return kActExit;
     __builtin_amdgcn_s_sleep(8);
   }
@@ -2048,7 +2119,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT
         bwd_item<NT, LidarRay>(q, a, tile, gt, sg, rg, sh);
     } else {
       const bool walk = act == kActWalk;
-      if (cam)
+      if (walk && (sg & kMedianEntry)) {
+        if (cam)
+          median_item<NT, CamRay>(q, a, tile, gt, sg & ~kMedianEntry, rg, sh);
+        else if (cyl)
+          median_item<NT, CylRay>(q, a, tile, gt, sg & ~kMedianEntry, rg, sh);
+        else if (KINDS & kKindLidar)
+          median_item<NT, LidarRay>(q, a, tile, gt, sg & ~kMedianEntry, rg, sh);
+      } else if (cam)
         fwd_item<NT, COUNT, CamRay>(q, a, si, tile, gt, sg, rg, walk, sh);
       else if (cyl)
         fwd_item<NT, COUNT, CylRay>(q, a, si, tile, gt, sg, rg, walk, sh);
@@ -2077,106 +2155,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BWD || COUNT
 
 // Launch variants: every tile size for pinhole / LiDAR mixes; kinds with the
 // cylindrical camera (bit 2) at 256-ray tiles only (plans enforce it).
-// Median depth (2DGS: the depth where the accumulated opacity reaches 1/2)
-// of the rays whose transmittance crosses 1/2 in a later segment (s >= 1) of
-// a split tile; whole tiles and first segments, composited from the ray's
-// true incoming transmittance, had their crossing recorded by the forward.
-// Such rays replay the segment's pairs from its incoming transmittance (the
-// merge leaves it in the segment's slot) and take the depth of the pair
-// after which it falls below 1/2.  Which segment holds a ray's crossing
-// follows from the forward's own transmittances (incoming >= 1/2 > outgoing,
-// for a ray still compositing there), so exactly one item writes it; should
-// the replay's rounding not cross inside the segment, its last composited
-// pair stands for it.  The crossing comes before any stop (T_min < 1/2), so
-// the replay needs no stop rule.
-template <int NT, class Ray>
-__device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uint32_t gt, uint32_t sg, uint2 rg,
-                            BlendShared<NT>& sh) {
-#pragma clang fp contract(off)
-  const uint32_t len = rg.y - rg.x, L = q.seg_len;
-  const uint32_t n_seg = len > L ? (len - 1) / L + 1 : 1u;
-  if (n_seg == 1 || sg == 0) return;  // uniform over the workgroup
-  const Ray ray(a, tile);
-  ray.prepare(a, sh);
-  const uint32_t pbase = q.pslot_base[gt];
-  if (pbase + n_seg > q.pslot_cap) return;  // unreachable: slots are sized for the pair capacity
-  const uint32_t b0 = rg.x + sg * L;
-  const uint32_t b1 = min(b0 + L, rg.y);
-  const int t = threadIdx.x;
-  const size_t HW = (size_t)a.S.W * a.S.H, p = ray.inside ? ray.pix(a) : 0;
-  // incoming and outgoing transmittance: a segment's slot holds its incoming
-  // state only while the ray is still compositing there (its last composited
-  // pair, n_last - 1, at or after the segment's start); past its last pair
-  // the outgoing value is T_final
-  float T = 1.0f, Tout = 1.0f;
-  const uint32_t nl = ray.inside ? a.n_last[p] : 0u;
-  if (ray.inside) {
-    Tout = a.T_final[p];
-    const size_t ps = q.part_stride;
-    T = q.part[kPartT * ps + (size_t)(pbase + sg) * NT + t];
-    if (sg + 1 < n_seg && nl > b1) Tout = q.part[kPartT * ps + (size_t)(pbase + sg + 1) * NT + t];
-  }
-  const bool mine = ray.inside && nl > b0 && T >= 0.5f && Tout < 0.5f;
-  bool active = mine;
-  float med = 0.0f, zl = 0.0f;
-  uint32_t mp = kNoPair, pl = kNoPair, n64 = 0;
-  const int w = t >> 6;
-  for (uint32_t base = b0; base < b1; base += NT) {
-    if (t == 0) sh.u[2] = 0u;
-    if (__syncthreads_count(active) == 0) break;
-    stage_batch<NT>(a, ray, base, b1, sh);
-    const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
-    for (int c = 0; c < nch; ++c) {
-      uint64_t m = uniform_mask(&sh.mask[c][w]);
-      const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(c) << 6;
-      while (m && __ballot(active) != 0) {
-        const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
-        m &= m - 1;
-        PairEval e;
-        const bool hit = ray.eval(a, sh.rec[j], sh.id[j], sh.f64, e, n64) && active;
-        if (hit) {
-          const float Tn = T * (1.0f - e.alpha);
-          zl = e.z;
-          pl = base + j;
-          if (Tn < 0.5f) {
-            med = e.z;
-            mp = base + j;
-            active = false;
-          }
-          T = Tn;
-        }
-      }
-    }
-  }
-  if (mine) {
-    a.out[Ray::kMedian * HW + p] = mp != kNoPair ? med : zl;
-    a.mpair[p] = mp != kNoPair ? mp : pl;
-  }
-}
-
-template <int NT, int KINDS>
-__global__ __launch_bounds__(NT) void k_median(QueueArgs q) {
-  __shared__ BlendShared<NT> sh;
-  const uint32_t n = min(q.hdr[7], q.pslot_cap);
-  for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
-    const unsigned long long e = q.mlist[it];
-    const uint32_t gt = rfl((uint32_t)(e >> 32)), sg = rfl((uint32_t)e);
-    const int si = sensor_of_tile(q, gt);
-    const TileArgs& a = q.tiles[si];
-    const uint2 rg = a.ranges[gt];
-    const int tile = (int)gt - q.tile_off[si];
-    const bool cam = (KINDS & kKindCam) && (KINDS == kKindCam || a.S.kind == GS_SENSOR_PINHOLE);
-    const bool cyl = (KINDS & kKindCyl) && (KINDS == kKindCyl || a.S.kind == GS_SENSOR_CYLINDRICAL);
-    if (cam)
-      median_item<NT, CamRay>(q, a, tile, gt, sg, rg, sh);
-    else if (cyl)
-      median_item<NT, CylRay>(q, a, tile, gt, sg, rg, sh);
-    else if (KINDS & kKindLidar)
-      median_item<NT, LidarRay>(q, a, tile, gt, sg, rg, sh);
-    __syncthreads();  // the shared state is free for the next item
-  }
-}
-
 #define GS_VARIANTS(X) \
   X(64, 1) X(64, 2) X(64, 3) X(128, 1) X(128, 2) X(128, 3) X(256, 1) X(256, 2) X(256, 3) X(512, 1) X(512, 2) \
   X(512, 3) X(256, 4) X(256, 5) X(256, 6) X(256, 7)
@@ -2192,16 +2170,6 @@ void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool 
     else                                                                                          \
       hipLaunchKernelGGL((k_blend_queue<NT, false, K, false>), dim3(grid), dim3(NT), 0, st, q);   \
     return;                                                                                       \
-  }
-  GS_VARIANTS(KCASE)
-#undef KCASE
-}
-
-void launch_median(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st) {
-#define KCASE(NT, K)                                                             \
-  if (rays == NT && kinds == K) {                                                \
-    hipLaunchKernelGGL((k_median<NT, K>), dim3(grid), dim3(NT), 0, st, q);      \
-    return;                                                                      \
   }
   GS_VARIANTS(KCASE)
 #undef KCASE

@@ -73,16 +73,17 @@ struct QueueArgs {
   const uint4* items;        // item id -> (record-space tile id, segment, tile range)
   const uint32_t* n_items;   // device count (hdr[0])
   uint32_t* hdr;             // [0] items [1] slots [2] queue counter [3] walks listed [4] walks taken
-                             // [5] split tiles left to merge [6] queue stalled [7] median segments listed
+                             // [5] split tiles left to merge [6] queue stalled
   uint32_t cap_items;
   uint32_t* counter;         // 8 sub-queue counters, kQCntStride words apart; zeroed before each launch
   uint32_t* arrive;          // per tile: segments finished (forward)
   const uint32_t* pslot_base;  // per tile: first partial-state slot
   float* part;               // [11][pslot_cap * rays per tile]
   uint32_t* slot_flag;       // per slot: listed for the cooperative walk
-  unsigned long long* walk;  // walk list: tile << 32 | segment; cleared to ~0 per forward
-  unsigned long long* mlist; // median list: tile << 32 | segment (hdr[7] entries; a tile's merge
-                             // lists each of its segments at most once)
+  unsigned long long* walk;  // walk list: tile << 32 | segment (| 1 << 31: a median entry); cleared to
+                             // ~0 per forward; walk_cap entries (a slot is listed at most once as a
+                             // stop walk and once as a median entry)
+  uint32_t walk_cap;
   size_t part_stride;        // elements per plane
   uint32_t pslot_cap;
   uint32_t seg_len;          // segment length L (pairs)
@@ -157,12 +158,6 @@ void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipS
 // iterations into the status words (calibration runs).
 void launch_blend_queue(const QueueArgs& q, int rays, int kinds, int grid, bool backward, bool count,
                         hipStream_t st);
-// Median pass after a forward: over the (tile, segment) entries the merges
-// listed, the rays whose transmittance crosses 1/2 in that later segment
-// (s >= 1) of a split tile replay it from its incoming state and write the
-// median depth / range and the crossing's pair index (the forward writes
-// both for every other ray).
-void launch_median(const QueueArgs& q, int rays, int kinds, int grid, hipStream_t st);
 int blend_blocks_per_cu(int rays, int kinds, bool backward);
 bool tile_shape_supported(int tw, int th);
 

@@ -507,7 +507,6 @@ __global__ __launch_bounds__(1024) void k_seg_top(SegScanArgs a, int nblk) {
     a.hdr[4] = 0u;
     a.hdr[5] = 0u;
     a.hdr[6] = 0u;
-    a.hdr[7] = 0u;
     if (tx > a.cap_items || ty > a.pslot_cap) a.status[kStOverflow] = 1u;
   }
   if (threadIdx.x < kQueues) a.qcnt[kQCntStride * threadIdx.x] = 0u;
@@ -530,10 +529,12 @@ __global__ __launch_bounds__(256) void k_seg_down(SegScanArgs a) {
   a.pslot_base[t] = iy;
   a.arrive[t] = 0u;
   if (split) {
-    // a split tile: clear its slots' walk flags and as many walk-list entries
+    // a split tile: clear its slots' walk flags and twice as many walk-list
+    // entries (a slot can be listed as a stop walk and as a median entry)
     for (uint32_t k = 0; k < c.y; ++k) {
       a.slot_flag[iy + k] = 0u;
-      a.walk[iy + k] = ~0ull;
+      a.walk[2 * (iy + k)] = ~0ull;
+      a.walk[2 * (iy + k) + 1] = ~0ull;
     }
   }
   const uint32_t len = rg.y - rg.x;
