@@ -80,14 +80,17 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=TRAFFIC_FILE):
-    """HBM bytes per compositing launch from committed rocprofv3 counters, if they match this source."""
+def measured_traffic(tiles, seg, path=TRAFFIC_FILE):
+    """HBM bytes per compositing launch from committed rocprofv3 counters, if they were taken on this
+    source and this configuration (tile shapes, segment length)."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != source_hash():
+        return None
+    if t.get("tiles") != [list(x) for x in tiles] or t.get("segment_pairs") != seg:
         return None
     return t.get("bytes_per_launch")
 
@@ -153,6 +156,7 @@ class RigStep:
 
         import paper_2503_11731_amd as gs
         self.sensors = sensors
+        self.tiles, self.seg = tiles, segment_pairs
         if decoders is None:
             self.dc = gs.Decoder.from_gen(cam_sc, dev, plain_fp32=plain)
             self.dl = gs.Decoder.from_gen(lid_sc, dev, plain_fp32=plain)
@@ -255,7 +259,7 @@ def _rig_roofline(rig, steps):
     hbm = pairs * (4 + REC_BYTES) + out_bytes
     achieved = flop / t / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(rig.tiles or [], rig.seg),
             "kernel": "k_blend_queue (batched forward compositing, all seven sensors, one persistent launch)",
             "avg_launch_ms": t * 1e3, "launches_timed": blend_n,
             "flop_per_launch": flop, "flop_per_evaluated_pair": FLOP_PER_PAIR,
@@ -691,6 +695,7 @@ def main():
     ap.add_argument("--eager-only", action="store_true",
                     help="time only eager forward steps of the batched plan, then exit (for profilers)")
     ap.add_argument("--cpu-stride", type=int, default=8)
+    ap.add_argument("--tune-steps", type=int, default=3, help="timed forwards per autotuning candidate")
     ap.add_argument("--profile-workload", default="", metavar="NAME",
                     help="run only the extra workload NAME (frame1080, train720p, lidar, affinity) and print its "
                          "JSON (for profilers)")
@@ -744,7 +749,7 @@ def main():
         t0 = time.perf_counter()
         gps = [probe.gp_c if s["kind"] == "pinhole" else probe.gp_l for s in sensors]
         res = at.autotune(probe.shapes, probe.ds, sensors, probe.sp, gps, batched=True, segments=[1024, 2048, 4096],
-                          pair_capacity=probe.shapes[0].n_splats * 6, steps=3, warmup=1)
+                          pair_capacity=probe.shapes[0].n_splats * 6, steps=args.tune_steps, warmup=1)
         tiles, seg = res.tiles, res.segment_pairs
         del probe
         torch.cuda.synchronize()
@@ -764,7 +769,7 @@ def main():
             for g in segs:
                 rr = RigStep(cam_sc, lid_sc, sensors, dev, batched=True, tiles=tiles, segment_pairs=g, train=False)
                 rr.fwd()
-                seg_ms[g] = _timed(rr.fwd, 5, 2, stream)
+                seg_ms[g] = _timed(rr.fwd, max(5, args.tune_steps), 2, stream)
                 del rr
                 torch.cuda.synchronize()
                 torch.cuda.empty_cache()

@@ -17,7 +17,11 @@ Choices keep a preferred candidate (the kind's usual tile shape, L = 2048)
 unless another is faster by more than a margin (3 %): candidates within
 timing noise of each other would otherwise flip from run to run, and a
 plan's counters and profiles would describe a different configuration than
-its timed run.
+its timed run.  For the same reason the package ships the timings measured
+on MI355X (gfx950) for its benchmark sensors (`tuned/autotune_seed.json`):
+their entries take precedence over the user cache, so every machine of that
+kind runs the configuration the profiles describe (GS2D_AUTOTUNE_SEED=""
+turns the seed off).
 """
 from __future__ import annotations
 
@@ -49,6 +53,13 @@ def pick(ms: dict, prefer, margin: float = MARGIN):
     return best
 
 
+SEED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "autotune_seed.json")
+
+
+def seed_path() -> str:
+    return os.environ.get("GS2D_AUTOTUNE_SEED", SEED_PATH)
+
+
 def default_cache_path() -> str:
     return os.environ.get("GS2D_AUTOTUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "gs2d", "autotune.json"))
@@ -74,15 +85,21 @@ class TuneResult:
 class TuneCache:
     """JSON map cache_key -> {"ms": {"tw x th / L": ms}} (all candidates kept)."""
 
-    def __init__(self, path: str | None):
+    def __init__(self, path: str | None, seed: str | None = None):
         self.path = path
-        self.data = {}
-        if path and os.path.exists(path):
-            try:
-                with open(path) as f:
-                    self.data = json.load(f)
-            except (OSError, ValueError):
-                self.data = {}
+        self.data = self._read(path)
+        self.data.update(self._read(seed_path() if seed is None else seed))  # shipped timings win
+
+    @staticmethod
+    def _read(path):
+        if not path or not os.path.exists(path):
+            return {}
+        try:
+            with open(path) as f:
+                d = json.load(f)
+            return d if isinstance(d, dict) else {}
+        except (OSError, ValueError):
+            return {}
 
     def get(self, key):
         return self.data.get(key)

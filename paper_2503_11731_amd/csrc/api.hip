@@ -362,8 +362,11 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
   const int kb = radix_sort(w.key, w.val, nullptr, R.n_rec, R.n_rec, 32, w.hist, w.status + kStSortStall, st);
   stage_end(p, st, GS_STAGE_DEPTH_SORT, ev);
   ev = stage_begin(p, st);
-  launch_pair_offsets(w.val[kb], w.ntiles, (int)R.n_rec, w.offs, w.bsum, w.status, R.cap, st);
-  launch_emit(w.val[kb], w.ntiles, w.rect, w.offs, (int)R.n_rec, emit_table(p, sensors), R.cap, w.ptile[0],
+  // visible records sort before every culled one (whose key is kInvalidKey):
+  // the scan and the emission take only the first kStVisible of them
+  launch_pair_offsets(w.val[kb], w.ntiles, (int)R.n_rec, w.status + kStVisible, w.offs, w.bsum, w.status, R.cap, st);
+  launch_emit(w.val[kb], w.ntiles, w.rect, w.offs, (int)R.n_rec, w.status + kStVisible, emit_table(p, sensors), R.cap,
+              w.ptile[0],
               w.pval[0], st);
   stage_end(p, st, GS_STAGE_EMIT, ev);
   ev = stage_begin(p, st);
@@ -449,7 +452,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       launch_fill_u32(ws.status, 0u, s.R.status_words, st);
       launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
       launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
-      launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, st);
+      launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, nullptr, st);
       stage_end(p, st, GS_STAGE_PREPROCESS, ev);
       sort_and_bin(p, s.R, s.base, std::vector<int>{(int)si}, workspace, st);
       ev = stage_begin(p, st);
@@ -474,7 +477,7 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
     launch_fill_u32(sst, 0u, 16, st);
     launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
     launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
-    launch_count_visible(ws.visible, sp.desc.n_splats, sst, st);
+    launch_count_visible(ws.visible, sp.desc.n_splats, sst, g.status, st);
   }
   stage_end(p, st, GS_STAGE_PREPROCESS, ev);
   std::vector<int> all(p->sensors.size());

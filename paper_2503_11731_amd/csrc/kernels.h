@@ -118,10 +118,14 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32
                int bits, uint32_t* hist, uint32_t* err, hipStream_t st);
 size_t radix_hist_words(uint32_t cap);
 // offs[j] = exclusive scan of ntiles[val[j]]; total -> status[kStPairs] and offs[n]
-void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uint32_t* offs, uint32_t* bsum,
+// With count (device): only the first min(n, *count) sorted records (the
+// visible ones: every culled record's key sorts after them).
+void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, const uint32_t* count, uint32_t* offs,
+                         uint32_t* bsum,
                          uint32_t* status, uint32_t cap, hipStream_t st);
 size_t scan_bsum_words(int n);
 void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
+                 const uint32_t* count,
                  const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st);
 // Work items of a record space: per tile n_seg = ceil(len / L) (1 when
 // len <= L); item_base / pslot_base by exclusive scans; items written with
@@ -150,7 +154,8 @@ void launch_build_items(const SegScanArgs& a, hipStream_t st);
 size_t seg_bsum_words(int n_tiles);
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st);
-void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipStream_t st);
+// adds the visible count to status[kStVisible] (and status2[kStVisible] when given)
+void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, uint32_t* status2, hipStream_t st);
 
 // blend.hip
 // kinds: bit 0 camera, bit 1 LiDAR (the sensor kinds the launch serves)

@@ -282,12 +282,15 @@ constexpr uint64_t kScanAgg = 1ull << 32;
 constexpr uint64_t kScanInc = 2ull << 32;
 
 __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict__ val,
-                                                      const uint32_t* __restrict__ ntiles, int n, uint32_t* bsum,
+                                                      const uint32_t* __restrict__ ntiles, int n_max,
+                                                      const uint32_t* count, uint32_t* bsum,
                                                       uint32_t* __restrict__ offs, uint32_t* status, uint32_t cap) {
   __shared__ uint64_t s_w64[4];
   __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_excl;
   const int t = threadIdx.x;
+  // the first *count sorted records (the visible ones) when a count is given
+  const int n = count ? (int)min((uint32_t)n_max, *count) : n_max;
   const int nblk = (n + kScanItems - 1) / kScanItems;
   if (n == 0) {
     if (blockIdx.x == 0 && t == 0) offs[0] = 0u;
@@ -390,8 +393,9 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
 // tiles go row by row (the order the tile sort keeps for equal tile ids).
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, const uint32_t* __restrict__ ntiles,
                                               const int4* __restrict__ rect, const uint32_t* __restrict__ offs,
-                                              int n, EmitTable E, uint32_t cap, uint32_t* __restrict__ ptile,
-                                              uint32_t* __restrict__ pval) {
+                                              int n_max, const uint32_t* count, EmitTable E, uint32_t cap,
+                                              uint32_t* __restrict__ ptile, uint32_t* __restrict__ pval) {
+  const int n = count ? (int)min((uint32_t)n_max, *count) : n_max;
   const int lane = threadIdx.x & 63;
   const int j0 = (blockIdx.x * 256 + (threadIdx.x & ~63));
   if (j0 >= n) return;
@@ -570,13 +574,17 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restrict__ vis, int n, uint32_t* status) {
+__global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restrict__ vis, int n, uint32_t* status,
+                                                       uint32_t* status2) {
   uint32_t c = 0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) c += vis[i];
   __shared__ uint32_t s_w[4];
   uint32_t tot;
   block_excl_scan<256>(c, s_w, &tot);
-  if (threadIdx.x == 0 && tot) atomicAdd(&status[kStVisible], tot);
+  if (threadIdx.x == 0 && tot) {
+    atomicAdd(&status[kStVisible], tot);
+    if (status2) atomicAdd(&status2[kStVisible], tot);
+  }
 }
 
 inline unsigned grid_for(size_t n, unsigned block, unsigned cap_blocks) {
@@ -642,17 +650,19 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32
 // look-back status word per 4096-item block
 size_t scan_bsum_words(int n) { return 2 + 2 * (size_t)((n + kScanItems - 1) / kScanItems); }
 
-void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, uint32_t* offs, uint32_t* bsum,
-                         uint32_t* status, uint32_t cap, hipStream_t st) {
+void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, const uint32_t* count, uint32_t* offs,
+                         uint32_t* bsum, uint32_t* status, uint32_t cap, hipStream_t st) {
   const int nblk = (n + kScanItems - 1) / kScanItems;
-  hipLaunchKernelGGL(k_pair_offsets, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, st, val, ntiles, n, bsum, offs, status,
-                     cap);
+  hipLaunchKernelGGL(k_pair_offsets, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, st, val, ntiles, n, count, bsum, offs,
+                     status, cap);
 }
 
 void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
-                 const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st) {
+                 const uint32_t* count, const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval,
+                 hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, E, cap, ptile, pval);
+  hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, count, E, cap, ptile,
+                     pval);
 }
 
 size_t seg_bsum_words(int n_tiles) { return 2 * ((size_t)((n_tiles + kSegItems - 1) / kSegItems) + 1); }
@@ -672,9 +682,9 @@ void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, u
                      (uint32_t)n_tiles);
 }
 
-void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, hipStream_t st) {
+void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, uint32_t* status2, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_count_visible, dim3(grid_for(n, 256, 256)), dim3(256), 0, st, visible, n, status);
+  hipLaunchKernelGGL(k_count_visible, dim3(grid_for(n, 256, 256)), dim3(256), 0, st, visible, n, status, status2);
 }
 
 }  // namespace gs

@@ -26,7 +26,7 @@ def test_cache_round_trip(tmp_path):
 def test_corrupt_cache_is_ignored(tmp_path):
     p = tmp_path / "c.json"
     p.write_text("{not json")
-    assert at.TuneCache(str(p)).data == {}
+    assert at.TuneCache(str(p), seed="").data == {}
 
 
 def test_pick_keeps_the_preferred_candidate_within_the_margin():
@@ -36,3 +36,13 @@ def test_pick_keeps_the_preferred_candidate_within_the_margin():
     assert at.pick(ms, None, 0.03) == "a"
     assert at.pick(ms, "zz", 0.03) == "a"     # not a candidate
     assert at.pick({2048: 5.0, 1024: 4.99}, 2048) == 2048
+
+
+def test_shipped_seed_takes_precedence(tmp_path):
+    user = tmp_path / "user.json"
+    seed = tmp_path / "seed.json"
+    user.write_text('{"k": {"ms": {"32x8/1024": 2.0}}, "u": {"ms": {}}}')
+    seed.write_text('{"k": {"ms": {"16x16/4096": 1.0}}}')
+    c = at.TuneCache(str(user), seed=str(seed))
+    assert c.get("k") == {"ms": {"16x16/4096": 1.0}} and c.get("u") == {"ms": {}}
+    assert at.TuneCache(str(user), seed="").get("k") == {"ms": {"32x8/1024": 2.0}}
