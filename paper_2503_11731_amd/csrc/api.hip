@@ -359,14 +359,18 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
                   hipStream_t st) {
   SensorWS w = record_ws(R, workspace, rbase, 0);
   hipEvent_t ev = stage_begin(p, st);
-  const int kb = radix_sort(w.key, w.val, nullptr, R.n_rec, R.n_rec, 32, w.hist, w.status + kStSortStall, st);
+  // only the visible records are sorted: compacted in record order into the
+  // second buffers (offs serves as the block-count scratch), then the stable
+  // depth sort over the first kStVisible of them
+  launch_compact_visible(w.key[0], w.val[0], (int)R.n_rec, w.offs, w.key[1], w.val[1], st);
+  uint32_t* ks[2] = {w.key[1], w.key[0]};
+  uint32_t* vs[2] = {w.val[1], w.val[0]};
+  const uint32_t* n_vis = w.status + kStVisible;
+  const int kb = radix_sort(ks, vs, n_vis, 0, R.n_rec, 32, w.hist, w.status + kStSortStall, st);
   stage_end(p, st, GS_STAGE_DEPTH_SORT, ev);
   ev = stage_begin(p, st);
-  // visible records sort before every culled one (whose key is kInvalidKey):
-  // the scan and the emission take only the first kStVisible of them
-  launch_pair_offsets(w.val[kb], w.ntiles, (int)R.n_rec, w.status + kStVisible, w.offs, w.bsum, w.status, R.cap, st);
-  launch_emit(w.val[kb], w.ntiles, w.rect, w.offs, (int)R.n_rec, w.status + kStVisible, emit_table(p, sensors), R.cap,
-              w.ptile[0],
+  launch_pair_offsets(vs[kb], w.ntiles, (int)R.n_rec, n_vis, w.offs, w.bsum, w.status, R.cap, st);
+  launch_emit(vs[kb], w.ntiles, w.rect, w.offs, (int)R.n_rec, n_vis, emit_table(p, sensors), R.cap, w.ptile[0],
               w.pval[0], st);
   stage_end(p, st, GS_STAGE_EMIT, ev);
   ev = stage_begin(p, st);

@@ -154,6 +154,10 @@ void launch_build_items(const SegScanArgs& a, hipStream_t st);
 size_t seg_bsum_words(int n_tiles);
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st);
+// The records whose key is not kInvalidKey, in record order, to kout / vout
+// (n records in; scratch: ceil(n / 4096) words).
+void launch_compact_visible(const uint32_t* kin, const uint32_t* vin, int n, uint32_t* scratch, uint32_t* kout,
+                            uint32_t* vout, hipStream_t st);
 // adds the visible count to status[kStVisible] (and status2[kStVisible] when given)
 void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, uint32_t* status2, hipStream_t st);
 

@@ -587,6 +587,67 @@ __global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restric
   }
 }
 
+// ---------------- compaction of the visible records ----------------
+// Order-preserving: the records whose key is not kInvalidKey (the visible
+// ones), in record order, so that the stable depth sort that follows ranks
+// equal keys exactly as a sort of every record would.  Blocks of 4096 records
+// (256 threads x 16 consecutive ones): per-block counts, one scan of those
+// counts, then each block writes its records at its offset.
+constexpr int kCompactItems = 4096;
+
+__global__ __launch_bounds__(256) void k_compact_count(const uint32_t* __restrict__ key, int n,
+                                                       uint32_t* __restrict__ bcnt) {
+  __shared__ uint32_t s_w[4];
+  const int j0 = blockIdx.x * kCompactItems + threadIdx.x * 16;
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) c += (j0 + r < n && key[j0 + r] != kInvalidKey) ? 1u : 0u;
+  uint32_t tot;
+  block_excl_scan<256>(c, s_w, &tot);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+}
+
+// exclusive scan of nblk block counts in place, one workgroup
+__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* __restrict__ bcnt, int nblk) {
+  __shared__ uint32_t s_w[16];
+  const int per = (nblk + 1023) / 1024;
+  const int beg = threadIdx.x * per, end = min(beg + per, nblk);
+  uint32_t s = 0;
+  for (int i = beg; i < end; ++i) s += bcnt[i];
+  uint32_t tot;
+  uint32_t off = block_excl_scan<1024>(s, s_w, &tot);
+  for (int i = beg; i < end; ++i) {
+    const uint32_t c = bcnt[i];
+    bcnt[i] = off;
+    off += c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin, int n,
+                                                         const uint32_t* __restrict__ boff,
+                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ uint32_t s_w[4];
+  const int j0 = blockIdx.x * kCompactItems + threadIdx.x * 16;
+  uint32_t k[16];
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    k[r] = j0 + r < n ? kin[j0 + r] : kInvalidKey;
+    c += k[r] != kInvalidKey ? 1u : 0u;
+  }
+  uint32_t tot;
+  uint32_t o = boff[blockIdx.x] + block_excl_scan<256>(c, s_w, &tot);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if (k[r] != kInvalidKey) {
+      kout[o] = k[r];
+      vout[o] = vin[j0 + r];
+      ++o;
+    }
+  }
+}
+
 inline unsigned grid_for(size_t n, unsigned block, unsigned cap_blocks) {
   size_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -680,6 +741,15 @@ void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, u
   launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2ull * n_tiles, st);
   hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, st, ptile, count, cap, ranges,
                      (uint32_t)n_tiles);
+}
+
+void launch_compact_visible(const uint32_t* kin, const uint32_t* vin, int n, uint32_t* scratch, uint32_t* kout,
+                            uint32_t* vout, hipStream_t st) {
+  if (n == 0) return;
+  const int nblk = (n + kCompactItems - 1) / kCompactItems;
+  hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(256), 0, st, kin, n, scratch);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, scratch, nblk);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(256), 0, st, kin, vin, n, scratch, kout, vout);
 }
 
 void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, uint32_t* status2, hipStream_t st) {
