@@ -180,6 +180,13 @@ class RigStep:
                              segment_pairs=segment_pairs)
         self.gp_all = torch.cat([self.gp_c if s["kind"] == "pinhole" else self.gp_l for s in sensors]).contiguous()
         self.ds = [self._dec(i).new_decoded() for i in range(len(sensors))]
+        # the surfel centres do not depend on the sensor: the first camera's decode writes them and
+        # the other cameras' scenes share that buffer (their decodes skip it)
+        cams = [i for i, s in enumerate(sensors) if s["kind"] == "pinhole"]
+        self.dout = list(self.ds)
+        for i in cams[1:]:
+            self.ds[i]["mean"] = self.ds[cams[0]]["mean"]
+            self.dout[i] = {k: (None if k == "mean" else v) for k, v in self.ds[i].items()}
         self.outs = self.r.new_outputs()
         self.rays = sum(s["width"] * s["height"] for s in sensors)
         if not train:
@@ -200,9 +207,9 @@ class RigStep:
     def fwd(self):
         for i, s in enumerate(self.sensors):
             if s["kind"] == "pinhole":
-                self.dc.forward(self.sp[i], self.gp_c, out=self.ds[i])
+                self.dc.forward(self.sp[i], self.gp_c, out=self.dout[i])
             else:
-                self.dl.forward(self.sp[i], self.gp_l, out=self.ds[i])
+                self.dl.forward(self.sp[i], self.gp_l, out=self.dout[i])
         self.r.forward(self.ds, self.sp, self.gp_all, outputs=self.outs)
 
     def fwd_bwd(self):

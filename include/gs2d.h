@@ -386,7 +386,10 @@ typedef struct gs_decoded {
 
 /* Decodes every anchor for one sensor pose.  sensor_pose: device [12]
  * world->sensor; group_poses: device [n_groups][12] group->world.  Writes
- * A*K surfels; anchors of group g become surfels [K*off[g], K*off[g+1]). */
+ * A*K surfels; anchors of group g become surfels [K*off[g], K*off[g+1]).
+ * out->mean may be NULL: the centres x_a + l_a O_k do not depend on the
+ * sensor, so a caller decoding one anchor set for several sensors writes
+ * them once (every other output is required). */
 gs_status gs_decode_forward(const gs_anchor_set* anchors, const float* sensor_pose,
                             const float* group_poses, const gs_decoded* out, hipStream_t stream);
 

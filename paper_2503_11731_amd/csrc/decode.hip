@@ -240,9 +240,11 @@ __global__ __launch_bounds__(256) void k_decode_fwd(DecodeArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) a.quat[e * N + n] = y[so + 2 + e] + bb[so + 2 + e];
     if (a.lidar) a.drop[n] = sigmoidf(y[8] + bb[8]);
+    if (a.mean) {
 #pragma unroll
-    for (int e = 0; e < 3; ++e)
-      a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
+      for (int e = 0; e < 3; ++e)
+        a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
+    }
   }
 }
 
@@ -302,8 +304,9 @@ __global__ __launch_bounds__(128) void k_decode_fwd_valu(DecodeArgs a) {
     a.scale[N + n] = la * sigmoidf(y[so + 1]);
     for (int e = 0; e < 4; ++e) a.quat[e * N + n] = y[so + 2 + e];
     if (a.lidar) a.drop[n] = sigmoidf(y[8]);
-    for (int e = 0; e < 3; ++e)
-      a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
+    if (a.mean)
+      for (int e = 0; e < 3; ++e)
+        a.mean[e * N + n] = a.xyz[(size_t)e * a.A + ai] + la * a.offsets[((size_t)e * K + k) * a.A + ai];
   }
 }
 
@@ -646,7 +649,7 @@ extern "C" gs_status gs_decode_forward(const gs_anchor_set* anchors, const float
   int nb = 0;
   gs_status s = fill_args(anchors, sensor_pose, group_poses, a, nb);
   if (s != GS_OK) return s;
-  if (!out || !out->mean || !out->quat || !out->scale || !out->opacity || (!a.lidar && !out->rgb) ||
+  if (!out || !out->quat || !out->scale || !out->opacity || (!a.lidar && !out->rgb) ||
       (a.lidar && (!out->intensity || !out->drop)))
     return set_error(GS_ERR_INVALID_ARG, "null decode output");
   a.mean = out->mean;

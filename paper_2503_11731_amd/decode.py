@@ -76,6 +76,8 @@ class Decoder:
         return out
 
     def forward(self, sensor_pose: torch.Tensor, group_poses: torch.Tensor, out=None) -> dict:
+        """Decode for one sensor pose into `out` (new buffers if None).  out["mean"] may be None: the
+        centres do not depend on the sensor, and are then not written."""
         out = out or self.new_decoded()
         p = lambda k: L.ptr(out.get(k))
         d = L.Decoded(p("mean"), p("quat"), p("scale"), p("opacity"), p("rgb"), p("intensity"), p("drop"))

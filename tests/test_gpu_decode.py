@@ -74,6 +74,23 @@ def test_decode_forward_parity(kind, plain):
         assert e <= 1e-4, (k, e)
 
 
+@pytest.mark.parametrize("plain", [False, True])
+def test_decode_without_centres_writes_the_same_other_outputs(plain):
+    """out.mean = NULL: the centres are not written (they do not depend on the sensor); every other
+    output is bit-identical to a full decode."""
+    _say(f"decode without centres plain_fp32={plain}")
+    sc, sensor, dec, sp, gp, poses_s = _setup("pinhole", plain=plain)
+    full = dec.forward(sp, gp)
+    part = dec.new_decoded()
+    part["mean"] = None
+    part = dec.forward(sp, gp, out=part)
+    torch.cuda.synchronize()
+    for k, v in full.items():
+        if k != "mean":
+            assert torch.equal(v, part[k]), k
+    assert part["mean"] is None
+
+
 @pytest.mark.parametrize("kind", ["pinhole", "lidar"])
 def test_decode_backward_parity(kind):
     _say(f"decode backward {kind}")
