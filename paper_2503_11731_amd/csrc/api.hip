@@ -360,9 +360,21 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
   SensorWS w = record_ws(R, workspace, rbase, 0);
   hipEvent_t ev = stage_begin(p, st);
   // only the visible records are sorted: compacted in record order into the
-  // second buffers (offs serves as the block-count scratch), then the stable
-  // depth sort over the first kStVisible of them
-  launch_compact_visible(w.key[0], w.val[0], (int)R.n_rec, w.offs, w.key[1], w.val[1], st);
+  // second buffers (offs serves as the block-count scratch; their number to
+  // kStVisible), then the stable depth sort over the first kStVisible of them
+  launch_compact_visible(w.key[0], w.val[0], (int)R.n_rec, w.offs, w.key[1], w.val[1], w.status + kStVisible, st);
+  if (p->batched) {
+    VisibleSplit vs;
+    memset(&vs, 0, sizeof(vs));
+    vs.n = (int)sensors.size();
+    for (int k = 0; k < vs.n; ++k) {
+      const SensorPlan& s = p->sensors[sensors[k]];
+      vs.rec_base[k] = s.rec_base;
+      vs.status[k] = at<uint32_t>(workspace, s.base + s.o_status);
+    }
+    vs.rec_base[vs.n] = (uint32_t)R.n_rec;
+    launch_visible_split(w.val[1], w.status + kStVisible, vs, st);
+  }
   uint32_t* ks[2] = {w.key[1], w.key[0]};
   uint32_t* vs[2] = {w.val[1], w.val[0]};
   const uint32_t* n_vis = w.status + kStVisible;
@@ -456,7 +468,6 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
       launch_fill_u32(ws.status, 0u, s.R.status_words, st);
       launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
       launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
-      launch_count_visible(ws.visible, sp.desc.n_splats, ws.status, nullptr, st);
       stage_end(p, st, GS_STAGE_PREPROCESS, ev);
       sort_and_bin(p, s.R, s.base, std::vector<int>{(int)si}, workspace, st);
       ev = stage_begin(p, st);
@@ -481,7 +492,6 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
     launch_fill_u32(sst, 0u, 16, st);
     launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
     launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
-    launch_count_visible(ws.visible, sp.desc.n_splats, sst, g.status, st);
   }
   stage_end(p, st, GS_STAGE_PREPROCESS, ev);
   std::vector<int> all(p->sensors.size());

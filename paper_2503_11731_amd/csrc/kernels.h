@@ -155,11 +155,18 @@ size_t seg_bsum_words(int n_tiles);
 void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, uint2* ranges, int n_tiles,
                    hipStream_t st);
 // The records whose key is not kInvalidKey, in record order, to kout / vout
-// (n records in; scratch: ceil(n / 4096) words).
+// (n records in; scratch: ceil(n / 4096) words); their number to *count.
 void launch_compact_visible(const uint32_t* kin, const uint32_t* vin, int n, uint32_t* scratch, uint32_t* kout,
-                            uint32_t* vout, hipStream_t st);
-// adds the visible count to status[kStVisible] (and status2[kStVisible] when given)
-void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, uint32_t* status2, hipStream_t st);
+                            uint32_t* vout, uint32_t* count, hipStream_t st);
+// Sensor k of a batched record space owns record ids [rec_base[k],
+// rec_base[k + 1]); its visible count goes to status[k][kStVisible].
+struct VisibleSplit {
+  int n;
+  uint32_t rec_base[GS_MAX_SENSORS + 1];
+  uint32_t* status[GS_MAX_SENSORS];
+};
+// ids: the *count compacted record ids (ascending), before the depth sort
+void launch_visible_split(const uint32_t* ids, const uint32_t* count, const VisibleSplit& s, hipStream_t st);
 
 // blend.hip
 // kinds: bit 0 camera, bit 1 LiDAR (the sensor kinds the launch serves)

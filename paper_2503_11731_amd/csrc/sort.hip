@@ -574,19 +574,6 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_count_visible(const uint32_t* __restrict__ vis, int n, uint32_t* status,
-                                                       uint32_t* status2) {
-  uint32_t c = 0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) c += vis[i];
-  __shared__ uint32_t s_w[4];
-  uint32_t tot;
-  block_excl_scan<256>(c, s_w, &tot);
-  if (threadIdx.x == 0 && tot) {
-    atomicAdd(&status[kStVisible], tot);
-    if (status2) atomicAdd(&status2[kStVisible], tot);
-  }
-}
-
 // ---------------- compaction of the visible records ----------------
 // Order-preserving: the records whose key is not kInvalidKey (the visible
 // ones), in record order, so that the stable depth sort that follows ranks
@@ -607,8 +594,9 @@ __global__ __launch_bounds__(256) void k_compact_count(const uint32_t* __restric
   if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
 }
 
-// exclusive scan of nblk block counts in place, one workgroup
-__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* __restrict__ bcnt, int nblk) {
+// exclusive scan of nblk block counts in place, one workgroup; *count = the total
+__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* __restrict__ bcnt, int nblk,
+                                                       uint32_t* __restrict__ count) {
   __shared__ uint32_t s_w[16];
   const int per = (nblk + 1023) / 1024;
   const int beg = threadIdx.x * per, end = min(beg + per, nblk);
@@ -621,6 +609,37 @@ __global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* __restrict__ bc
     bcnt[i] = off;
     off += c;
   }
+  if (threadIdx.x == 0) *count = tot;
+}
+
+// First index j < n with v[j] >= x in the ascending v[0, n) (n if none), by
+// the whole workgroup: each round samples 256 evenly spaced positions of the
+// open range and keeps the gap between the last sample below x and the next,
+// so a range of m shrinks below m / 256 per round (4 rounds for 2^32).
+__device__ uint32_t block_lower_bound(const uint32_t* __restrict__ v, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t step = (hi - lo + 255) / 256;
+    const uint32_t m = (hi - lo + step - 1) / step;  // samples lo + t * step, t < m
+    const uint32_t q = lo + threadIdx.x * step;
+    const uint32_t c = (uint32_t)__syncthreads_count(threadIdx.x < m && v[q] < x);
+    const uint32_t nlo = c ? lo + (c - 1) * step + 1 : lo;
+    hi = c < m ? lo + c * step : hi;
+    lo = nlo;
+  }
+  return lo;
+}
+
+// Per-sensor visible counts of a batched record space: the compacted record
+// ids ascend and sensor k owns ids [rec_base[k], rec_base[k + 1]), so its
+// count is the difference of two lower bounds.  One workgroup per sensor.
+__global__ __launch_bounds__(256) void k_visible_split(const uint32_t* __restrict__ ids,
+                                                       const uint32_t* __restrict__ count, VisibleSplit s) {
+  const int k = blockIdx.x;
+  const uint32_t n = *count;
+  const uint32_t a = k == 0 ? 0u : block_lower_bound(ids, n, s.rec_base[k]);
+  const uint32_t b = k + 1 == s.n ? n : block_lower_bound(ids, n, s.rec_base[k + 1]);
+  if (threadIdx.x == 0) s.status[k][kStVisible] = b - a;
 }
 
 __global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t* __restrict__ kin,
@@ -744,17 +763,17 @@ void launch_ranges(const uint32_t* ptile, const uint32_t* count, uint32_t cap, u
 }
 
 void launch_compact_visible(const uint32_t* kin, const uint32_t* vin, int n, uint32_t* scratch, uint32_t* kout,
-                            uint32_t* vout, hipStream_t st) {
-  if (n == 0) return;
+                            uint32_t* vout, uint32_t* count, hipStream_t st) {
+  if (n == 0) return;  // the caller's zeroed count stands
   const int nblk = (n + kCompactItems - 1) / kCompactItems;
   hipLaunchKernelGGL(k_compact_count, dim3(nblk), dim3(256), 0, st, kin, n, scratch);
-  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, scratch, nblk);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, st, scratch, nblk, count);
   hipLaunchKernelGGL(k_compact_scatter, dim3(nblk), dim3(256), 0, st, kin, vin, n, scratch, kout, vout);
 }
 
-void launch_count_visible(const uint32_t* visible, int n, uint32_t* status, uint32_t* status2, hipStream_t st) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_count_visible, dim3(grid_for(n, 256, 256)), dim3(256), 0, st, visible, n, status, status2);
+void launch_visible_split(const uint32_t* ids, const uint32_t* count, const VisibleSplit& s, hipStream_t st) {
+  if (s.n <= 0) return;
+  hipLaunchKernelGGL(k_visible_split, dim3(s.n), dim3(256), 0, st, ids, count, s);
 }
 
 }  // namespace gs

@@ -77,8 +77,10 @@ def _tensors(scene, sensors):
 
 
 def _check_pairs(rb, sensor_scenes, sensors, tiles, rec_bases):
-    """Integer parity of a batched plan's pair list, sensor by sensor."""
+    """Integer parity of a batched plan's pair list and per-sensor visible
+    counts, sensor by sensor."""
     v = rb.inspect(0)
+    n_vis = rb.status()["n_visible"]
     tile = v["pair_tile"].cpu().numpy().astype(np.int64)
     rec = v["pair_surfel"].cpu().numpy().astype(np.int64)
     toff = 0
@@ -91,6 +93,7 @@ def _check_pairs(rb, sensor_scenes, sensors, tiles, rec_bases):
         sel = (tile >= toff) & (tile < toff + n_t)
         np.testing.assert_array_equal(tile[sel] - toff, t_ref)
         np.testing.assert_array_equal(rec[sel] - rec_bases[i], s_ref)
+        assert n_vis[i] == int(np.count_nonzero(bins["visible"])), (i, n_vis[i])
         toff += n_t
     assert toff == v["n_tiles"]
 
@@ -110,6 +113,7 @@ def test_batched_forward_matches_per_sensor_and_oracle(tiles):
     for a, b in zip(oa, ob):
         assert torch.equal(a, b)
     assert not rb.status()["overflow"]
+    assert ra.status()["n_visible"] == rb.status()["n_visible"]
     n = scene["mean"].shape[1]
     _check_pairs(rb, [scene] * len(sensors), sensors, tiles, [i * n for i in range(len(sensors))])
     for i, s in enumerate(sensors):
@@ -118,6 +122,30 @@ def test_batched_forward_matches_per_sensor_and_oracle(tiles):
         v = verify(ob[i].cpu().numpy(), ref, s["kind"])
         _say(f"  sensor {i}: {v}")
         assert_verified(v, f"sensor {i}")
+
+
+def test_batched_sensor_with_nothing_visible():
+    """A camera turned away from the whole scene between two that see it: its
+    visible count is zero, the others' match the oracle's culling, and the
+    batched outputs equal the per-sensor plan's."""
+    _say("batched forward with an empty sensor")
+    scene, sensors = _rig()
+    away = dict(sensors[1], pose=S.translate_pose(S.camera_yaw_pose(180.0), (0.0, 0.0, -1.0e4)))
+    sensors = [sensors[0], away, sensors[2], sensors[3]]
+    scenes, sp, gp = _tensors(scene, sensors)
+    ra = _renderer(scene, sensors, False, [(32, 8)] * len(sensors))
+    rb = _renderer(scene, sensors, True)
+    oa = ra.forward(scenes, sp, gp)
+    ob = rb.forward(scenes, sp, gp)
+    torch.cuda.synchronize()
+    for a, b in zip(oa, ob):
+        assert torch.equal(a, b)
+    st = rb.status()
+    assert not st["overflow"]
+    assert st["n_visible"][1] == 0
+    assert ra.status()["n_visible"] == st["n_visible"]
+    n = scene["mean"].shape[1]
+    _check_pairs(rb, [scene] * len(sensors), sensors, None, [i * n for i in range(len(sensors))])
 
 
 def _oracle_scene_grads(scene, sensors, outs_grad, scene_of):
