@@ -302,39 +302,28 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
   __syncthreads();
   const int b = (int)s_ticket;
   if (b >= nblk) return;
-  // each thread owns 16 consecutive items so that the scan is in order
+  // wave w takes the w-th quarter of the block in rounds of 64 consecutive
+  // items (one per lane): index loads and offset stores are contiguous runs,
+  // and each round's offsets come from a wave scan
   constexpr int PER = kScanItems / 256;
-  uint32_t v[PER];
+  const int w = t >> 6, lane = t & 63;
+  const int base = b * kScanItems + w * (kScanItems / 4) + lane;
+  uint32_t v[PER], idx[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) idx[r] = base + r * 64 < n ? val[base + r * 64] : 0u;
+#pragma unroll
+  for (int r = 0; r < PER; ++r) v[r] = base + r * 64 < n ? ntiles[idx[r]] : 0u;
   uint64_t sum = 0;
-  const int j0 = b * kScanItems + t * PER;
-  if (j0 + PER <= n) {
-    // whole run in range: all index loads, then all gathers, in flight together
-    uint32_t idx[PER];
-    const uint4* vp = reinterpret_cast<const uint4*>(val + j0);
-#pragma unroll
-    for (int q = 0; q < PER / 4; ++q) {
-      const uint4 x = vp[q];
-      idx[4 * q] = x.x;
-      idx[4 * q + 1] = x.y;
-      idx[4 * q + 2] = x.z;
-      idx[4 * q + 3] = x.w;
-    }
-#pragma unroll
-    for (int r = 0; r < PER; ++r) v[r] = ntiles[idx[r]];
-  } else {
-#pragma unroll
-    for (int r = 0; r < PER; ++r) v[r] = j0 + r < n ? ntiles[val[j0 + r]] : 0u;
-  }
 #pragma unroll
   for (int r = 0; r < PER; ++r) sum += v[r];
   uint64_t tot;
-  uint64_t off = block_excl_scan64(sum, s_w64, &tot);
+  // lane 0's exclusive prefix is the sum over the earlier waves' quarters
+  const uint64_t wave_off = __shfl(block_excl_scan64(sum, s_w64, &tot), 0, 64);
   const uint32_t tot32 = sat32(tot);
   if (t < 64) {
     // wave 0: publish this block's sum, then read 64 earlier blocks per
     // round trip (lane i: block k - 1 - i), nearest first, up to the nearest
     // inclusive prefix; a block with nothing published yet ends the round
-    const int lane = t;
     uint64_t* mine = look + b;
     if (lane == 0)
       __hip_atomic_store(mine, (b == 0 ? kScanInc : kScanAgg) | tot32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -377,12 +366,17 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
     }
   }
   __syncthreads();
-  off += s_excl;
+  uint64_t off = s_excl + wave_off;
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
-    const int j = j0 + r;
-    if (j < n) offs[j] = sat32(off);
-    off += v[r];
+    uint64_t inc = v[r];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (base + r * 64 < n) offs[base + r * 64] = sat32(off + inc - v[r]);
+    off += __shfl(inc, 63, 64);
   }
 }
 
@@ -577,21 +571,29 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 // ---------------- compaction of the visible records ----------------
 // Order-preserving: the records whose key is not kInvalidKey (the visible
 // ones), in record order, so that the stable depth sort that follows ranks
-// equal keys exactly as a sort of every record would.  Blocks of 4096 records
-// (256 threads x 16 consecutive ones): per-block counts, one scan of those
-// counts, then each block writes its records at its offset.
+// equal keys exactly as a sort of every record would.  Blocks of 4096
+// records: per-block counts, one scan of those counts, then each block writes
+// its records at its offset.  Inside a block wave w takes the w-th quarter in
+// 16 rounds of 64 consecutive records (one per lane), so every load reads and
+// every store writes one contiguous run; a round's visible records are ranked
+// by a ballot.
 constexpr int kCompactItems = 4096;
+constexpr int kCompactRounds = kCompactItems / 256;
 
 __global__ __launch_bounds__(256) void k_compact_count(const uint32_t* __restrict__ key, int n,
                                                        uint32_t* __restrict__ bcnt) {
-  __shared__ uint32_t s_w[4];
-  const int j0 = blockIdx.x * kCompactItems + threadIdx.x * 16;
+  __shared__ uint32_t s_c[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t base = (uint32_t)blockIdx.x * kCompactItems + (uint32_t)w * (kCompactItems / 4) + (uint32_t)lane;
+  uint32_t k[kCompactRounds];
+#pragma unroll
+  for (int r = 0; r < kCompactRounds; ++r) k[r] = base + r * 64 < (uint32_t)n ? key[base + r * 64] : kInvalidKey;
   uint32_t c = 0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) c += (j0 + r < n && key[j0 + r] != kInvalidKey) ? 1u : 0u;
-  uint32_t tot;
-  block_excl_scan<256>(c, s_w, &tot);
-  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+  for (int r = 0; r < kCompactRounds; ++r) c += (uint32_t)__popcll(__ballot(k[r] != kInvalidKey));
+  if (lane == 0) s_c[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
 }
 
 // exclusive scan of nblk block counts in place, one workgroup; *count = the total
@@ -646,24 +648,36 @@ __global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t* __restr
                                                          const uint32_t* __restrict__ vin, int n,
                                                          const uint32_t* __restrict__ boff,
                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ uint32_t s_w[4];
-  const int j0 = blockIdx.x * kCompactItems + threadIdx.x * 16;
-  uint32_t k[16];
+  __shared__ uint32_t s_c[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t base = (uint32_t)blockIdx.x * kCompactItems + (uint32_t)w * (kCompactItems / 4) + (uint32_t)lane;
+  const uint64_t lt = lanemask_lt();
+  uint32_t k[kCompactRounds], v[kCompactRounds];
+  uint64_t m[kCompactRounds];
+#pragma unroll
+  for (int r = 0; r < kCompactRounds; ++r) {
+    const uint32_t i = base + r * 64;
+    k[r] = i < (uint32_t)n ? kin[i] : kInvalidKey;
+    v[r] = i < (uint32_t)n ? vin[i] : 0u;
+  }
   uint32_t c = 0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    k[r] = j0 + r < n ? kin[j0 + r] : kInvalidKey;
-    c += k[r] != kInvalidKey ? 1u : 0u;
+  for (int r = 0; r < kCompactRounds; ++r) {
+    m[r] = __ballot(k[r] != kInvalidKey);
+    c += (uint32_t)__popcll(m[r]);
   }
-  uint32_t tot;
-  uint32_t o = boff[blockIdx.x] + block_excl_scan<256>(c, s_w, &tot);
+  if (lane == 0) s_c[w] = c;
+  __syncthreads();
+  uint32_t o = boff[blockIdx.x];
+  for (int q = 0; q < w; ++q) o += s_c[q];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < kCompactRounds; ++r) {
     if (k[r] != kInvalidKey) {
-      kout[o] = k[r];
-      vout[o] = vin[j0 + r];
-      ++o;
+      const uint32_t pos = o + (uint32_t)__popcll(m[r] & lt);
+      kout[pos] = k[r];
+      vout[pos] = v[r];
     }
+    o += (uint32_t)__popcll(m[r]);
   }
 }
 
