@@ -484,14 +484,22 @@ void enqueue_forward(gs_plan* p, const gs_scene* scenes, const float* sensor_pos
   SensorWS g = record_ws(p->G, workspace, p->gbase, 0);
   hipEvent_t ev = stage_begin(p, st);
   launch_fill_u32(g.status, 0u, p->G.status_words, st);
+  SensorSetup setup;
+  memset(&setup, 0, sizeof(setup));
+  setup.n = (int)p->sensors.size();
+  for (size_t si = 0; si < p->sensors.size(); ++si) {
+    const SensorPlan& s = p->sensors[si];
+    const ScenePlan& sp = p->scenes[s.scene];
+    setup.sensor_pose[si] = sensor_poses + 12 * si;
+    setup.pose_base[si] = sp.pose_base;
+    setup.n_groups[si] = sp.desc.n_groups;
+    setup.pose_out[si] = sensor_ws(p, s, workspace).pose;
+    setup.status[si] = at<uint32_t>(workspace, s.base + s.o_status);
+  }
+  launch_sensor_setup(group_poses, setup, st);
   for (size_t si = 0; si < p->sensors.size(); ++si) {
     SensorPlan& s = p->sensors[si];
-    const ScenePlan& sp = p->scenes[s.scene];
-    SensorWS ws = sensor_ws(p, s, workspace);
-    uint32_t* sst = at<uint32_t>(workspace, s.base + s.o_status);
-    launch_fill_u32(sst, 0u, 16, st);
-    launch_compose_poses(sensor_poses + 12 * si, group_poses, sp.pose_base, sp.desc.n_groups, ws.pose, st);
-    launch_prep(prep_args(p, s, scenes[s.scene], ws), st);
+    launch_prep(prep_args(p, s, scenes[s.scene], sensor_ws(p, s, workspace)), st);
   }
   stage_end(p, st, GS_STAGE_PREPROCESS, ev);
   std::vector<int> all(p->sensors.size());

@@ -284,7 +284,7 @@ __device__ __forceinline__ void load_rec(const TileArgs& a, uint32_t s, RawRec& 
 // doubles), from the record's LDS slot when it was staged there, else from
 // global memory -- every load issued before any is used.
 template <int NG, int NC>
-__device__ __forceinline__ void fetch64(const TileArgs& a, const F64Slot* f64, uint32_t slot, uint32_t s, double* g,
+__device__ __forceinline__ void fetch64(const TileArgs& a, const F64Slot* f64, uint32_t slot, const uint32_t* sid, double* g,
                                         double* c) {
   if (slot && f64) {
     const double* d = f64[slot - 1];
@@ -293,6 +293,9 @@ __device__ __forceinline__ void fetch64(const TileArgs& a, const F64Slot* f64, u
 #pragma unroll
     for (int k = 0; k < NC; ++k) c[k] = d[kGrz + k];
   } else {
+    // the surfel id (the batch slot's word, the same for every lane) is read
+    // only here: the staged FP64 data cover nearly every re-solve
+    const uint32_t s = rfl(*sid);
     const double* G = a.grz + kGrz * (size_t)s;
     const double* C = a.rec64 + kRec64 * (size_t)s;
 #pragma unroll
@@ -314,7 +317,7 @@ __device__ __forceinline__ void fetch64(const TileArgs& a, const F64Slot* f64, u
 // The centre in the tile frame is held as an FP32 pair (value + residual),
 // so that the offset dx = (p_x - pcx_rel) - residual carries only its own
 // rounding, not that of a centre up to a tile away.
-__device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint32_t s, float plx, float ply, int ox,
+__device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, const uint32_t* sid, float plx, float ply, int ox,
                                              int oy, const TileArgs& a, const EvalK& K, const F64Slot* f64,
                                              PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
@@ -343,7 +346,7 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, uint3
   if (redo) {
     ++n64;
     double g[7], c[2];
-    fetch64<7, 2>(a, f64, slot, s, g, c);
+    fetch64<7, 2>(a, f64, slot, sid, g, c);
     ok = solve64_pinhole(g, c, (double)ox + (double)plx, (double)oy + (double)ply, u, v, r, z);
     hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
   }
@@ -486,9 +489,9 @@ struct CamRay {
   __device__ uint64_t cover_lanes(const float4* R) const {
     return cover_lanes_rect(uniform_u32(R[5].x), uniform_u32(R[5].y), bx, by);
   }
-  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
+  __device__ bool eval(const TileArgs& a, const float4* R, const uint32_t* sid, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
-    return eval_pinhole(R, s, plx, ply, ox, oy, a, K, f64, e, n64);
+    return eval_pinhole(R, sid, plx, ply, ox, oy, a, K, f64, e, n64);
   }
   static __device__ float& flag_word(float4* R) { return R[3].x; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
@@ -700,7 +703,7 @@ __device__ __forceinline__ bool solve64_cyl(const double* G, const double* c, co
   return H2 != 0.0;
 }
 
-__device__ __forceinline__ bool eval_cyl(const float4* __restrict__ R, uint32_t s, float plx, float ply, float Ay,
+__device__ __forceinline__ bool eval_cyl(const float4* __restrict__ R, const uint32_t* sid, float plx, float ply, float Ay,
                                          int px, int py, const TileArgs& a, const EvalK& K, const CylK& Y0,
                                          const F64Slot* f64, PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
@@ -732,7 +735,7 @@ __device__ __forceinline__ bool eval_cyl(const float4* __restrict__ R, uint32_t 
   if (redo) {
     ++n64;
     double g[7], c[2];
-    fetch64<7, 2>(a, f64, slot, s, g, c);
+    fetch64<7, 2>(a, f64, slot, sid, g, c);
     ok = solve64_cyl(g, c, a.S, px, py, u, v, r, z);
     hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
   }
@@ -879,9 +882,9 @@ struct CylRay {
   __device__ uint64_t cover_lanes(const float4* R) const {
     return cover_lanes_rect(uniform_u32(R[5].x), uniform_u32(R[5].y), bx, by);
   }
-  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
+  __device__ bool eval(const TileArgs& a, const float4* R, const uint32_t* sid, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
-    return eval_cyl(R, s, plx, ply, Ay, tc, tr, a, K, Y0, f64, e, n64);
+    return eval_cyl(R, sid, plx, ply, Ay, tc, tr, a, K, Y0, f64, e, n64);
   }
   static __device__ float& flag_word(float4* R) { return R[3].x; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
@@ -982,7 +985,7 @@ __device__ __forceinline__ uint2 stage_lidar(const RawRec& x, const double* dtil
   return make_uint2(__float_as_uint(r3.z), __float_as_uint(r3.w));
 }
 
-__device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_t s, const float* dpix, float dpm,
+__device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, const uint32_t* sid, const float* dpix, float dpm,
                                            const double* d64, const TileArgs& a, const EvalK& K, const F64Slot* f64,
                                            PairEval& e, uint32_t& n64) {
 #pragma clang fp contract(off)
@@ -1016,7 +1019,7 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, uint32_
   if (redo) {
     ++n64;
     double g[10], c[3];
-    fetch64<10, 3>(a, f64, slot, s, g, c);
+    fetch64<10, 3>(a, f64, slot, sid, g, c);
     ok = solve64_lidar(g, c, d64, u, v, r, z);
     hit = finish_pair(u, v, r, z, ok, rl, q3.x, q3.y, K, e);
   }
@@ -1197,9 +1200,9 @@ struct LidarRay {
   __device__ uint64_t cover_lanes(const float4* R) const {
     return cover_lanes_wrap(uniform_u32(R[4].y), uniform_u32(R[4].z), bx, by);
   }
-  __device__ bool eval(const TileArgs& a, const float4* R, uint32_t s, const F64Slot* f64, PairEval& e,
+  __device__ bool eval(const TileArgs& a, const float4* R, const uint32_t* sid, const F64Slot* f64, PairEval& e,
                        uint32_t& n64) const {
-    return eval_lidar(R, s, dpix, dpm, d64, a, K, f64, e, n64);
+    return eval_lidar(R, sid, dpix, dpm, d64, a, K, f64, e, n64);
   }
   static __device__ float& flag_word(float4* R) { return R[3].w; }
   __device__ void feat(const float4* R, const PairEval& e, float* f) const {
@@ -1467,7 +1470,7 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
             n_eval += (uint32_t)__popcll(live & ray.cover_lanes(Rl));
         }
         PairEval e;
-        const bool hit = ray.eval(a, R, sh.id[j], sh.f64, e, n64) && !done;
+        const bool hit = ray.eval(a, R, &sh.id[j], sh.f64, e, n64) && !done;
         const float Tn = T * (1.0f - e.alpha);
         const bool stop = hit && Tn < ray.K.T_min;
         if (hit && !stop) {
@@ -1741,7 +1744,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
       }
       const bool active = base + j < last;
       PairEval e;
-      const bool hit = ray.eval(a, sh.rec[j], sh.id[j], sh.f64, e, n64) && active;
+      const bool hit = ray.eval(a, sh.rec[j], &sh.id[j], sh.f64, e, n64) && active;
       float gr[kGradFields];
 #pragma unroll
       for (int f = 0; f < kGradFields; ++f) gr[f] = 0.0f;
@@ -1970,7 +1973,7 @@ __device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uin
         const uint32_t j = cb + (uint32_t)__builtin_ctzll(m);
         m &= m - 1;
         PairEval e;
-        const bool hit = ray.eval(a, sh.rec[j], sh.id[j], sh.f64, e, n64) && active;
+        const bool hit = ray.eval(a, sh.rec[j], &sh.id[j], sh.f64, e, n64) && active;
         if (hit) {
           const float Tn = T * (1.0f - e.alpha);
           zl = e.z;

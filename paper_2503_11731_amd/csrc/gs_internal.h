@@ -19,7 +19,9 @@ constexpr int kRecF32 = 16;     // floats per surfel record
 constexpr int kRec64 = 4;       // doubles per surfel record (camera: pc; LiDAR: unit centre)
 constexpr int kGrz = 10;        // doubles per record with FP64 re-solve data
 constexpr int kGradFields = 16; // per-surfel gradient accumulators
-constexpr int kRadixItems = 4096;
+// keys per radix-sort block (256 threads x 32): on MI355X faster than 4096,
+// with per-digit output runs twice as long and half the look-back chain
+constexpr int kRadixItems = 8192;
 // keys per radix sort (pairs, records): the look-back counts are 30-bit
 constexpr uint32_t kMaxSortKeys = (1u << 30) - 1u;
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;

@@ -105,6 +105,18 @@ struct SplatBwdArgs {
 // preprocess.hip
 void launch_compose_poses(const float* sensor_pose, const float* group_poses, int pose_base, int n_groups, float* out,
                           hipStream_t st);
+// Batched step: for every sensor k, status[k][0..16) = 0 and its n_groups[k]
+// (<= 64) composed poses (sensor_pose[k] o group pose pose_base[k] + g) to
+// pose_out[k], in one launch.
+struct SensorSetup {
+  int n;
+  const float* sensor_pose[GS_MAX_SENSORS];
+  int pose_base[GS_MAX_SENSORS];
+  int n_groups[GS_MAX_SENSORS];
+  float* pose_out[GS_MAX_SENSORS];
+  uint32_t* status[GS_MAX_SENSORS];
+};
+void launch_sensor_setup(const float* group_poses, const SensorSetup& s, hipStream_t st);
 void launch_prep(const PrepArgs& a, hipStream_t st);
 
 // sort.hip

@@ -34,6 +34,22 @@ __global__ void k_compose_poses(const float* __restrict__ sensor_pose, const flo
   }
 }
 
+// The batched step's per-sensor set-up in one launch, one workgroup per
+// sensor: its 16 status words cleared and its group poses composed.
+__global__ void k_sensor_setup(const float* __restrict__ group_poses, SensorSetup s) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x, g = threadIdx.x;
+  if (g < 16) s.status[k][g] = 0u;
+  if (g >= s.n_groups[k]) return;
+  const float* a = s.sensor_pose[k];
+  const float* b = group_poses + 12 * (s.pose_base[k] + g);
+  float* o = s.pose_out[k] + 12 * g;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) o[4 * i + j] = (a[4 * i] * b[j] + a[4 * i + 1] * b[4 + j]) + a[4 * i + 2] * b[8 + j];
+    o[4 * i + 3] = ((a[4 * i] * b[3] + a[4 * i + 1] * b[7]) + a[4 * i + 2] * b[11]) + a[4 * i + 3];
+  }
+}
+
 struct Frame64 {
   double R[9], t[3];
   double tus[3], tvs[3], ns[3], mus[3];
@@ -320,6 +336,11 @@ __global__ __launch_bounds__(256) void k_prep_lidar(PrepArgs a) {
 void launch_compose_poses(const float* sensor_pose, const float* group_poses, int pose_base, int n_groups, float* out,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_compose_poses, dim3(1), dim3(64), 0, st, sensor_pose, group_poses, pose_base, n_groups, out);
+}
+
+void launch_sensor_setup(const float* group_poses, const SensorSetup& s, hipStream_t st) {
+  if (s.n <= 0) return;
+  hipLaunchKernelGGL(k_sensor_setup, dim3(s.n), dim3(64), 0, st, group_poses, s);
 }
 
 void launch_prep(const PrepArgs& a, hipStream_t st) {
