@@ -123,9 +123,11 @@ __device__ __forceinline__ bool finish_pair(float u, float v, float r, float z, 
   // the centre's depth: its plane hit is not meaningful there
   if (lp_used) z = zc;
   ok = ok && (rho_hat <= K.cutoff2) && (z > K.z_near);
-  float alpha = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, log2o));
-  const bool clamped = alpha > K.alpha_max;
-  if (clamped) alpha = K.alpha_max;
+  const float alpha_raw = __builtin_amdgcn_exp2f(fmaf(-kInv2Ln2, rho_hat, log2o));
+  // min(alpha_raw, alpha_max) as one median-of-three (alpha_raw >= 0); the
+  // clamp flag serves the adjoint only
+  const bool clamped = alpha_raw > K.alpha_max;
+  const float alpha = __builtin_amdgcn_fmed3f(alpha_raw, 0.0f, K.alpha_max);
   ok = ok && !(alpha < K.alpha_min);
   e.alpha = alpha;
   e.u = u;
@@ -338,11 +340,14 @@ __device__ __forceinline__ bool eval_pinhole(const float4* __restrict__ R, const
   // FP64 re-solve: grazing pairs (|h'_2| < 1/8) and an edge record's pairs
   // whose error bound could matter
   const uint32_t slot = (flags >> 8) & 0xFFu;
-  bool redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
-  // the offsets carry two roundings of their size, the products two more
-  // (the record holds 2^-22 kappa)
-  if (flags & kFlagEdge)  // the same record for the whole wave
-    redo = redo | edge_needs_f64(e, fmaf(R[3].y, fmaxf(fabsf(dx), fabsf(dy)), 0x1p-20f), rl, flags, K);
+  bool redo = false;
+  if (flags & (kFlagGrazing | kFlagEdge)) {  // the same record for the whole wave
+    redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
+    // the offsets carry two roundings of their size, the products two more
+    // (the record holds 2^-22 kappa)
+    if (flags & kFlagEdge)
+      redo = redo | edge_needs_f64(e, fmaf(R[3].y, fmaxf(fabsf(dx), fabsf(dy)), 0x1p-20f), rl, flags, K);
+  }
   if (redo) {
     ++n64;
     double g[7], c[2];
@@ -727,11 +732,14 @@ __device__ __forceinline__ bool eval_cyl(const float4* __restrict__ R, const uin
   bool hit = finish_pair(u, v, r, z, ok, rl, q2.x, q2.y, K, e);
   // FP64 re-solve as for the pinhole camera
   const uint32_t slot = (flags >> 8) & 0xFFu;
-  bool redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
-  // X = f tan and Y = dy + A (sec - 1) take about twice the pinhole's
-  // roundings (the record holds 2^-21 kappa)
-  if (flags & kFlagEdge)
-    redo = redo | edge_needs_f64(e, fmaf(R[3].y, fmaxf(fabsf(X), fabsf(Y)), 0x1p-20f), rl, flags, K);
+  bool redo = false;
+  if (flags & (kFlagGrazing | kFlagEdge)) {
+    redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
+    // X = f tan and Y = dy + A (sec - 1) take about twice the pinhole's
+    // roundings (the record holds 2^-21 kappa)
+    if (flags & kFlagEdge)
+      redo = redo | edge_needs_f64(e, fmaf(R[3].y, fmaxf(fabsf(X), fabsf(Y)), 0x1p-20f), rl, flags, K);
+  }
   if (redo) {
     ++n64;
     double g[7], c[2];
@@ -1008,13 +1016,16 @@ __device__ __forceinline__ bool eval_lidar(const float4* __restrict__ R, const u
   bool hit = finish_pair(u, v, r, z, ok, rl, q3.x, q3.y, K, e);
   // FP64 re-solve as for the pinhole camera
   const uint32_t slot = (flags >> 8) & 0xFFu;
-  bool redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
-  if (flags & kFlagEdge) {
-    // the roundings of dpix and of c, then two of d's size and two in the
-    // products (the record holds 2^-23 kappa)
-    const float dm = fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fabsf(d2));
-    const float cm = fmaxf(fmaxf(fabsf(q0.x), fabsf(q0.y)), fabsf(q0.z));
-    redo = redo | edge_needs_f64(e, fmaf(q3.z, fmaf(2.0f, dm, dpm + cm), 0x1p-20f), rl, flags, K);
+  bool redo = false;
+  if (flags & (kFlagGrazing | kFlagEdge)) {
+    redo = (flags & kFlagGrazing) && fabsf(h2) < 0.125f;
+    if (flags & kFlagEdge) {
+      // the roundings of dpix and of c, then two of d's size and two in the
+      // products (the record holds 2^-23 kappa)
+      const float dm = fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fabsf(d2));
+      const float cm = fmaxf(fmaxf(fabsf(q0.x), fabsf(q0.y)), fabsf(q0.z));
+      redo = redo | edge_needs_f64(e, fmaf(q3.z, fmaf(2.0f, dm, dpm + cm), 0x1p-20f), rl, flags, K);
+    }
   }
   if (redo) {
     ++n64;
@@ -1433,6 +1444,10 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
   constexpr int C = Ray::C;
   const int t = threadIdx.x;
   const int w = t >> 6;
+  // Inside the loop a stopped ray is marked by the sign bit of its
+  // transmittance (never negative itself, and +0 only in strict mode), one
+  // compare per pair instead of a flag turned into a lane mask.
+  float Ts = done ? -T : T;
   // Software pipeline over batches: this thread's record of the next batch
   // is loaded while the current batch is composited, and the pair id of the
   // batch after it one step earlier still (the record load depends on it).
@@ -1445,11 +1460,11 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
   if (b0 + NT + t < b1) s_nxt = a.pval[b0 + NT + t];
   for (uint32_t base = b0; base < b1; base += NT) {
     if (t == 0) sh.u[2] = 0u;
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(__float_as_int(Ts) >= 0) == 0) break;
     commit_batch<NT>(a, ray, base + t < b1, s_cur, x, sh);
     bool pending = base + NT < b1;
     const int nch = (int)((min((uint32_t)NT, b1 - base) + 63) / 64);
-    uint64_t live = __ballot(!done);  // wave-uniform: rays still compositing
+    uint64_t live = __ballot(__float_as_int(Ts) >= 0);  // wave-uniform: rays still compositing
     for (int c = 0; c < nch && live != 0; ++c) {
       uint64_t m = uniform_mask(&sh.mask[c][w]);
       const uint32_t cb = (uint32_t)__builtin_amdgcn_readfirstlane(c) << 6;
@@ -1465,31 +1480,31 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         if constexpr (COUNT) {
           ++n_iter;
           if (lane_counts)
-            n_eval += (ray.covered(Rl) && !done) ? 1u : 0u;
+            n_eval += (ray.covered(Rl) && __float_as_int(Ts) >= 0) ? 1u : 0u;
           else
             n_eval += (uint32_t)__popcll(live & ray.cover_lanes(Rl));
         }
         PairEval e;
-        const bool hit = ray.eval(a, R, &sh.id[j], sh.f64, e, n64) && !done;
-        const float Tn = T * (1.0f - e.alpha);
+        const bool hit = ray.eval(a, R, &sh.id[j], sh.f64, e, n64) && __float_as_int(Ts) >= 0;
+        const float Tn = Ts * (1.0f - e.alpha);
         const bool stop = hit && Tn < ray.K.T_min;
         if (hit && !stop) {
           if constexpr (COUNT) ++n_contrib;
-          const float wgt = e.alpha * T;
+          const float wgt = e.alpha * Ts;
           float f[C];
           ray.feat(Rl, e, f);
 #pragma unroll
           for (int c2 = 0; c2 < C; ++c2) acc[c2] = fmaf(wgt, f[c2], acc[c2]);
-          if (track && T >= 0.5f && Tn < 0.5f) {
+          if (track && Ts >= 0.5f && Tn < 0.5f) {
             sh.med[t] = e.z;
             sh.mp[t] = base + j;
           }
-          T = Tn;
+          Ts = Tn;
           last = base + j + 1;
         }
         if (__ballot(stop) != 0) {
-          done = done || stop;
-          live = __ballot(!done);
+          if (stop) Ts = -Ts;
+          live = __ballot(__float_as_int(Ts) >= 0);
           if (live == 0) break;
         }
       }
@@ -1506,6 +1521,8 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
       s_nxt = base + 2 * NT + t < b1 ? a.pval[base + 2 * NT + t] : 0u;
     }
   }
+  done = __float_as_int(Ts) < 0;
+  T = fabsf(Ts);
 }
 
 // Wave total held by every lane -> held by lane 0 only (before a wave sum).
