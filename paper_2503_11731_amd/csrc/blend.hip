@@ -1486,7 +1486,7 @@ __device__ void composite(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
         }
         PairEval e;
         const bool hit = ray.eval(a, R, &sh.id[j], sh.f64, e, n64) && __float_as_int(Ts) >= 0;
-        const float Tn = Ts * (1.0f - e.alpha);
+        const float Tn = fmaf(-e.alpha, Ts, Ts);  // T (1 - alpha), one rounding
         const bool stop = hit && Tn < ray.K.T_min;
         if (hit && !stop) {
           if constexpr (COUNT) ++n_contrib;
@@ -1779,7 +1779,7 @@ __device__ void bwd_range(const TileArgs& a, const Ray& ray, uint32_t b0, uint32
           dal += g[c] * (T * f[c] - S * inv1m);
         }
         ray.grads(a, sh.rec[j], e, dal, wgt, g, base + j == mp ? gmed : 0.0f, gr);
-        T = T * (1.0f - al);
+        T = fmaf(-al, T, T);  // as the forward pass
       }
       if (__ballot(hit) != 0) flush_grads<NT>(gr, sh.ga.g, j, lane);
       }
@@ -1992,7 +1992,7 @@ __device__ void median_item(const QueueArgs& q, const TileArgs& a, int tile, uin
         PairEval e;
         const bool hit = ray.eval(a, sh.rec[j], &sh.id[j], sh.f64, e, n64) && active;
         if (hit) {
-          const float Tn = T * (1.0f - e.alpha);
+          const float Tn = fmaf(-e.alpha, T, T);  // as the compositing pass
           zl = e.z;
           pl = base + j;
           if (Tn < 0.5f) {
