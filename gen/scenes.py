@@ -486,9 +486,11 @@ CAMERA_RIG = [("front", 0.0, 1920, 1080, 960.0), ("front_left", 55.0, 1920, 1080
 def config5(n_anchors=300_000, n_assets=20, asset_anchors=2_000):
     """Six cameras + LiDAR; corridor anchors plus 20 posed vehicle assets.
 
-    Returns (camera anchor scene, lidar anchor scene, sensors): the camera and
-    LiDAR scenes share geometry but carry separate MLPs (Sec. III-A keeps a
-    camera scene and a LiDAR scene).
+    Returns (camera anchor scene, lidar anchor scene, sensors): separate camera
+    and LiDAR scenes with separate MLPs (Sec. III-A keeps a camera scene and a
+    LiDAR scene).  Their static corridor anchors are the same; the vehicle
+    assets and their poses are drawn after each scene's MLPs, so the two
+    scenes' assets differ.
     """
     cam = corridor_anchors(seed=5, n_anchors=n_anchors, sensor_kind="pinhole", z_lo=-60.0, z_hi=120.0,
                            n_assets=n_assets, asset_anchors=asset_anchors)

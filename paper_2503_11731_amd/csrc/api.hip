@@ -381,9 +381,8 @@ void sort_and_bin(gs_plan* p, const RecordArrays& R, size_t rbase, const std::ve
   const int kb = radix_sort(ks, vs, n_vis, 0, R.n_rec, 32, w.hist, w.status + kStSortStall, st);
   stage_end(p, st, GS_STAGE_DEPTH_SORT, ev);
   ev = stage_begin(p, st);
-  launch_pair_offsets(vs[kb], w.ntiles, (int)R.n_rec, n_vis, w.offs, w.bsum, w.status, R.cap, st);
-  launch_emit(vs[kb], w.ntiles, w.rect, w.offs, (int)R.n_rec, n_vis, emit_table(p, sensors), R.cap, w.ptile[0],
-              w.pval[0], st);
+  launch_offsets_emit(vs[kb], w.ntiles, w.rect, (int)R.n_rec, n_vis, emit_table(p, sensors), w.bsum, w.status, R.cap,
+                      w.ptile[0], w.pval[0], st);
   stage_end(p, st, GS_STAGE_EMIT, ev);
   ev = stage_begin(p, st);
   (void)radix_sort(w.ptile, w.pval, w.status + kStPairs, 0, R.cap, R.tile_bits, w.hist, w.status + kStSortStall, st);

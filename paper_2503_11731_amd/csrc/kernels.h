@@ -129,16 +129,15 @@ void launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32_t count_const, uint32_t cap,
                int bits, uint32_t* hist, uint32_t* err, hipStream_t st);
 size_t radix_hist_words(uint32_t cap);
-// offs[j] = exclusive scan of ntiles[val[j]]; total -> status[kStPairs] and offs[n]
-// With count (device): only the first min(n, *count) sorted records (the
-// visible ones: every culled record's key sorts after them).
-void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, const uint32_t* count, uint32_t* offs,
-                         uint32_t* bsum,
-                         uint32_t* status, uint32_t cap, hipStream_t st);
+// The (tile, surfel) pairs of the sorted records, in one pass: record j's
+// pairs start at the exclusive scan of ntiles[val[j]] (total ->
+// status[kStPairs], overflow flag when above cap) and are written in depth
+// order, each surfel's tiles row by row.  With count (device): only the first
+// min(n, *count) sorted records (the visible ones).
+void launch_offsets_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, int n, const uint32_t* count,
+                         const EmitTable& E, uint32_t* bsum, uint32_t* status, uint32_t cap, uint32_t* ptile,
+                         uint32_t* pval, hipStream_t st);
 size_t scan_bsum_words(int n);
-void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
-                 const uint32_t* count,
-                 const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval, hipStream_t st);
 // Work items of a record space: per tile n_seg = ceil(len / L) (1 when
 // len <= L); item_base / pslot_base by exclusive scans; items written with
 // keys (cost, heaviest first) and ids for the radix sort; arrival counters and

@@ -266,10 +266,10 @@ __global__ __launch_bounds__(256) void k_rs_onesweep(RadixArgs a) {
   }
 }
 
-// ---------------- gathered exclusive scan of tile counts ----------------
+// ---------------- pair offsets and emission, one pass ----------------
 //
-// offs[j] = sum of ntiles[val[i]] over i < j, in one pass: 4096-item blocks in
-// ticket order, each publishing its sum and reading the sums of earlier
+// The first pair of sorted record j is the sum of ntiles[val[i]] over i < j:
+// 4096-item blocks in ticket order, each publishing its sum and reading the sums of earlier
 // blocks by a bounded look-back (64 blocks per round trip, one per lane of
 // the first wave), with 64-bit status words (high half: 1 = block sum, 2 = inclusive prefix; low half the
 // value).  The ticket and status words are cleared with the frame's status.
@@ -281,10 +281,74 @@ constexpr int kScanItems = 4096;
 constexpr uint64_t kScanAgg = 1ull << 32;
 constexpr uint64_t kScanInc = 2ull << 32;
 
-__global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict__ val,
-                                                      const uint32_t* __restrict__ ntiles, int n_max,
-                                                      const uint32_t* count, uint32_t* bsum,
-                                                      uint32_t* __restrict__ offs, uint32_t* status, uint32_t cap) {
+// Pair emission of one wave's 64 consecutive surfels of the depth order (lane
+// l: surfel s with cnt pairs from pair o): the wave writes the union of their
+// pairs as consecutive 64-pair runs, each lane finding its surfel with a
+// binary search over the wave's first pairs, so every store instruction
+// writes 256 contiguous bytes.  Within a surfel the tiles go row by row (the
+// order the tile sort keeps for equal tile ids).  Pairs from cap on are not
+// written (the frame then reports an overflow).
+__device__ __forceinline__ void emit_wave(uint32_t s, uint32_t cnt, uint64_t o, const int4* __restrict__ rect,
+                                          const EmitTable& E, uint32_t cap, uint32_t* __restrict__ ptile,
+                                          uint32_t* __restrict__ pval) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t start64 = __shfl(o, 0, 64);
+  if (start64 >= cap) return;  // wave-uniform
+  uint64_t end64 = o + cnt;     // lanes past the list hold cnt 0
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t y = __shfl_xor(end64, d, 64);
+    end64 = y > end64 ? y : end64;
+  }
+  const uint32_t start = (uint32_t)start64;
+  const uint32_t end = (uint32_t)(end64 < cap ? end64 : cap);
+  // local first pair (a surfel's tile count is far below 2^26, so 64 of them fit)
+  const uint32_t lo = (uint32_t)(o - start64);
+  int4 r = make_int4(0, 0, 0, 0);
+  int n_tx = 1, toff = 0;
+  if (cnt) {
+    r = rect[s];
+    int se = 0;
+    while (se + 1 < E.n && E.rec_base[se + 1] <= s) ++se;
+    n_tx = E.n_tx[se];
+    toff = E.tile_off[se];
+  }
+  const bool wrap = (r.w >> 30) & 1;
+  const int ncol = cnt == 0 ? 1 : (wrap ? (n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1));
+  const int row0 = toff + r.z * n_tx;  // tile id of column 0 in the first row
+  for (uint32_t b = 0; start + b < end; b += 64) {
+    const uint32_t k = b + (uint32_t)lane;
+    // highest lane whose first pair is <= k (that lane has a pair at k: a
+    // lane without pairs shares its first pair with the next lane)
+    int src = 0;
+#pragma unroll
+    for (int step = 32; step >= 1; step >>= 1) {
+      const uint32_t l = (uint32_t)__shfl((int)lo, src + step, 64);
+      if (src + step < 64 && l <= k) src += step;
+    }
+    const uint32_t ls = (uint32_t)__shfl((int)lo, src, 64);
+    const uint32_t ss = (uint32_t)__shfl((int)s, src, 64);
+    const int nc = __shfl(ncol, src, 64);
+    const int x0 = __shfl(r.x, src, 64);
+    const int ntx = __shfl(n_tx, src, 64);
+    const int rb = __shfl(row0, src, 64);
+    const uint32_t q = start + k;
+    if (q < end) {
+      const uint32_t loc = k - ls;
+      const uint32_t ty = loc / (uint32_t)nc;
+      int tx = x0 + (int)(loc - ty * (uint32_t)nc);
+      if (tx >= ntx) tx -= ntx;
+      ptile[q] = (uint32_t)(rb + (int)ty * ntx + tx);
+      pval[q] = ss;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_offsets_emit(const uint32_t* __restrict__ val,
+                                                      const uint32_t* __restrict__ ntiles,
+                                                      const int4* __restrict__ rect, int n_max, const uint32_t* count,
+                                                      uint32_t* bsum, uint32_t* status, EmitTable E, uint32_t cap,
+                                                      uint32_t* __restrict__ ptile, uint32_t* __restrict__ pval) {
   __shared__ uint64_t s_w64[4];
   __shared__ uint32_t s_ticket;
   __shared__ uint64_t s_excl;
@@ -292,10 +356,7 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
   // the first *count sorted records (the visible ones) when a count is given
   const int n = count ? (int)min((uint32_t)n_max, *count) : n_max;
   const int nblk = (n + kScanItems - 1) / kScanItems;
-  if (n == 0) {
-    if (blockIdx.x == 0 && t == 0) offs[0] = 0u;
-    return;
-  }
+  if (n == 0) return;
   uint32_t* ticket = bsum;
   uint64_t* look = reinterpret_cast<uint64_t*>(bsum + 2);
   if (t == 0) s_ticket = atomicAdd(ticket, 1u);
@@ -359,7 +420,6 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
       s_excl = excl;
       if (b == nblk - 1) {
         const uint32_t total = sat32(excl + tot);
-        offs[n] = total;
         status[kStPairs] = total;
         if (total > cap) status[kStOverflow] = 1u;
       }
@@ -369,83 +429,15 @@ __global__ __launch_bounds__(256) void k_pair_offsets(const uint32_t* __restrict
   uint64_t off = s_excl + wave_off;
 #pragma unroll
   for (int r = 0; r < PER; ++r) {
-    uint64_t inc = v[r];
+    if (base - lane + r * 64 < n) {  // wave-uniform: the round holds part of the list
+      uint64_t inc = v[r];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint64_t y = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += y;
-    }
-    if (base + r * 64 < n) offs[base + r * 64] = sat32(off + inc - v[r]);
-    off += __shfl(inc, 63, 64);
-  }
-}
-
-// Pair emission, one wave per 64 consecutive surfels of the depth order:
-// the wave writes the union of their pairs as consecutive 64-pair runs, each
-// lane finding its surfel with a binary search over the wave's offsets, so
-// every store instruction writes 256 contiguous bytes.  Within a surfel the
-// tiles go row by row (the order the tile sort keeps for equal tile ids).
-__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ val, const uint32_t* __restrict__ ntiles,
-                                              const int4* __restrict__ rect, const uint32_t* __restrict__ offs,
-                                              int n_max, const uint32_t* count, EmitTable E, uint32_t cap,
-                                              uint32_t* __restrict__ ptile, uint32_t* __restrict__ pval) {
-  const int n = count ? (int)min((uint32_t)n_max, *count) : n_max;
-  const int lane = threadIdx.x & 63;
-  const int j0 = (blockIdx.x * 256 + (threadIdx.x & ~63));
-  if (j0 >= n) return;
-  const int j = j0 + lane;
-  uint32_t s = 0, cnt = 0, o = 0;
-  int4 r = make_int4(0, 0, 0, 0);
-  int n_tx = 1, toff = 0;
-  if (j < n) {
-    s = val[j];
-    cnt = ntiles[s];
-    o = offs[j];
-    if (cnt) {
-      r = rect[s];
-      int se = 0;
-      while (se + 1 < E.n && E.rec_base[se + 1] <= s) ++se;
-      n_tx = E.n_tx[se];
-      toff = E.tile_off[se];
-    }
-  }
-  const uint32_t start = (uint32_t)__shfl((int)o, 0, 64);
-  // the wave's pairs end at its last surfel's offset + count, clamped to the
-  // capacity (offsets saturate at 2^32 - 1 on overflow, so the sum is 64-bit)
-  uint64_t end64 = j < n ? (uint64_t)o + cnt : 0ull;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint64_t y = __shfl_xor(end64, d, 64);
-    end64 = y > end64 ? y : end64;
-  }
-  const uint32_t end = (uint32_t)(end64 < cap ? end64 : cap);
-  const uint32_t lo = j < n ? o - start : 0xFFFFFFFFu;  // local first pair (invalid lanes sort last)
-  const bool wrap = (r.w >> 30) & 1;
-  const int ncol = cnt == 0 ? 1 : (wrap ? (n_tx - r.x) + (r.y + 1) : (r.y - r.x + 1));
-  const int row0 = toff + r.z * n_tx;  // tile id of column 0 in the first row
-  for (uint32_t b = 0; start + b < end; b += 64) {
-    const uint32_t k = b + (uint32_t)lane;
-    // highest lane whose first pair is <= k (that lane has a pair at k)
-    int src = 0;
-#pragma unroll
-    for (int step = 32; step >= 1; step >>= 1) {
-      const uint32_t l = (uint32_t)__shfl((int)lo, src + step, 64);
-      if (src + step < 64 && l <= k) src += step;
-    }
-    const uint32_t ls = (uint32_t)__shfl((int)lo, src, 64);
-    const uint32_t ss = (uint32_t)__shfl((int)s, src, 64);
-    const int nc = __shfl(ncol, src, 64);
-    const int x0 = __shfl(r.x, src, 64);
-    const int ntx = __shfl(n_tx, src, 64);
-    const int rb = __shfl(row0, src, 64);
-    const uint32_t q = start + k;
-    if (q < end) {
-      const uint32_t loc = k - ls;
-      const uint32_t ty = loc / (uint32_t)nc;
-      int tx = x0 + (int)(loc - ty * (uint32_t)nc);
-      if (tx >= ntx) tx -= ntx;
-      ptile[q] = (uint32_t)(rb + (int)ty * ntx + tx);
-      pval[q] = ss;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      emit_wave(idx[r], v[r], off + inc - v[r], rect, E, cap, ptile, pval);
+      off += __shfl(inc, 63, 64);
     }
   }
 }
@@ -744,19 +736,12 @@ int radix_sort(uint32_t* key[2], uint32_t* val[2], const uint32_t* count, uint32
 // look-back status word per 4096-item block
 size_t scan_bsum_words(int n) { return 2 + 2 * (size_t)((n + kScanItems - 1) / kScanItems); }
 
-void launch_pair_offsets(const uint32_t* val, const uint32_t* ntiles, int n, const uint32_t* count, uint32_t* offs,
-                         uint32_t* bsum, uint32_t* status, uint32_t cap, hipStream_t st) {
+void launch_offsets_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, int n, const uint32_t* count,
+                         const EmitTable& E, uint32_t* bsum, uint32_t* status, uint32_t cap, uint32_t* ptile,
+                         uint32_t* pval, hipStream_t st) {
   const int nblk = (n + kScanItems - 1) / kScanItems;
-  hipLaunchKernelGGL(k_pair_offsets, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, st, val, ntiles, n, count, bsum, offs,
-                     status, cap);
-}
-
-void launch_emit(const uint32_t* val, const uint32_t* ntiles, const int4* rect, const uint32_t* offs, int n,
-                 const uint32_t* count, const EmitTable& E, uint32_t cap, uint32_t* ptile, uint32_t* pval,
-                 hipStream_t st) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, st, val, ntiles, rect, offs, n, count, E, cap, ptile,
-                     pval);
+  hipLaunchKernelGGL(k_offsets_emit, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, st, val, ntiles, rect, n, count, bsum,
+                     status, E, cap, ptile, pval);
 }
 
 size_t seg_bsum_words(int n_tiles) { return 2 * ((size_t)((n_tiles + kSegItems - 1) / kSegItems) + 1); }
